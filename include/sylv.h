@@ -1,0 +1,210 @@
+/*
+ * sylv.h — C ABI of libsylv.so, a mixed-precision Schur-based solver for
+ * the real Sylvester equation AX + XB = C and the real Lyapunov equation
+ * AX + XA^T = C on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Dmytryshyn, Fasi, Higham, Liu, "Mixed-precision algorithms for
+ * solving the Sylvester matrix equation"):
+ *   - the problem statement is eq. (1.1) (Sylvester) and eq. (1.3)
+ *     (Lyapunov, real case: A^* = A^T);
+ *   - the real Schur factorisations of A and B are computed in low precision
+ *     (Sec. 2.1, eq. (2.3): A ~ U T U^T with U orthogonal to u_low);
+ *   - Bartels-Stewart transform / quasi-triangular solve / back-transform
+ *     (Sec. 2.2.1) give the first iterate;
+ *   - the stationary iteration of Sec. 3 (Alg. 3.1) refines it: each step
+ *     solves the correction equation with the low-precision Schur factors
+ *     while the residual R = C - AX - XB is formed in binary64 against the
+ *     original coefficients (the original-basis form of eq. (3.2));
+ *   - convergence is measured by the normwise relative residual, eq. (2.1),
+ *     with Frobenius norms evaluated in binary64.
+ * With low = SYLV_PREC_FP64 the library runs the plain binary64
+ * Bartels-Stewart algorithm on the GPU (the baseline and the fallback).
+ *
+ * Conventions (all entry points):
+ *   - Matrices are column-major with explicit leading dimensions; vec()
+ *     stacks columns as in eq. (1.2).
+ *   - Matrix arguments (A, B, C, X and the stage-level T, U, Y) are DEVICE
+ *     pointers.  The caller owns them.  A, B and C are never modified; X is
+ *     fully written.  Every other pointer argument (opts, info, size
+ *     arrays, pointer arrays) is a HOST pointer.
+ *   - `stream` is a hipStream_t passed as void*.  NULL means the default
+ *     stream.  All work is enqueued on `stream`; the solve entry points make
+ *     host decisions from device results (deflation points of the QR
+ *     algorithm, residual norms), so they synchronise `stream` and return
+ *     only when X and *info are final.
+ *   - Workspace: `work`/`work_bytes` may provide device scratch of at least
+ *     the size returned by the matching *_workspace_size call; with
+ *     work == NULL the library allocates (and caches per device) what it
+ *     needs.
+ *   - Return value (synchronous errors only): 0 = success; -i = the i-th
+ *     argument is invalid (negative size, leading dimension too small, NULL
+ *     pointer with a positive size, workspace too small); SYLV_ERR_HIP - k
+ *     = HIP runtime error k; SYLV_ERR_ALLOC = device allocation failed;
+ *     SYLV_ERR_NOGPU = no usable gfx950 device.
+ *   - Numerical outcome is reported per equation in sylv_info.status.
+ */
+#ifndef SYLV_H
+#define SYLV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SYLV_PREC_FP64 = 0, /* plain binary64 Bartels-Stewart (no refinement)          */
+    SYLV_PREC_FP32 = 1, /* binary32 Schur/transforms/tri-solve + binary64 refinement */
+    SYLV_PREC_BF16 = 2, /* binary32 Schur, bfloat16-input MFMA products in the
+                           correction transforms + binary64 refinement             */
+    SYLV_PREC_AUTO = 4  /* per-equation choice by the learned selector (batched)   */
+} sylv_prec;
+
+typedef enum { SYLV_KIND_SYLV = 0, SYLV_KIND_LYAP = 1 } sylv_kind;
+
+typedef struct {
+    int    low;        /* sylv_prec: precision of the Schur factors and corrections (default FP32) */
+    double tol;        /* target relative residual, eq. (2.1), Frobenius (default 1e-14)          */
+    int    max_iter;   /* refinement cap (default 20, the cap used in the paper's experiments)    */
+    int    fallback;   /* 1: on failure escalate to the plain binary64 path (default 1)           */
+    int    orth_check; /* 0 off, 1 (default) binary64 ||U^T U - I||_F of the low-precision factors */
+} sylv_opts;
+
+typedef struct {
+    double rel_res;     /* eq. (2.1) at exit, binary64, Frobenius norms                         */
+    double orth_u;      /* ||U^T U - I||_F of the Schur vectors of A (0 if not checked)         */
+    double orth_v;      /* same for B (Lyapunov: equals orth_u)                                 */
+    double sep_est;     /* min |lambda_i + mu_j| over the computed eigenvalues (estimate of sep) */
+    double corr_ratio;  /* ||D||_F / ||X||_F of the last correction (stopping quantity of Alg. 3.1) */
+    int    iterations;  /* refinement steps taken (corrections applied)                         */
+    int    precision_used; /* sylv_prec of the path that produced X                             */
+    int    fell_back;   /* 1 if the binary64 fallback produced X                                 */
+    int    status;      /* SYLV_OK, or one of the SYLV_ST_* codes below                          */
+} sylv_info;
+
+#define SYLV_OK               0
+#define SYLV_ST_PERTURBED     1  /* a near-singular pivot of the quasi-triangular solve was perturbed */
+#define SYLV_ST_NOT_CONVERGED 2  /* tolerance not reached within max_iter and no fallback            */
+#define SYLV_ST_NAN           3  /* NaN or Inf in the iterate or residual                            */
+#define SYLV_ST_QR_FAILED     4  /* the QR algorithm hit its iteration cap                            */
+
+#define SYLV_ERR_HIP   (-100)
+#define SYLV_ERR_ALLOC (-200)
+#define SYLV_ERR_NOGPU (-300)
+
+/* Fill *opts with the defaults listed in sylv_opts. */
+void sylv_default_opts(sylv_opts *opts);
+
+/* Device workspace in bytes that sylv_solve (lyap = 0) or lyap_solve
+ * (lyap = 1, n ignored) needs for these sizes and options.  Returns 0 for
+ * invalid arguments. */
+size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts);
+
+/* Solve AX + XB = C (eq. (1.1)), A m x m, B n x n, C and X m x n.
+ * opts may be NULL (defaults).  info must be a host pointer (may be NULL). */
+int sylv_solve(int m, int n, const double *A, int lda, const double *B, int ldb,
+               const double *C, int ldc, double *X, int ldx,
+               const sylv_opts *opts, sylv_info *info,
+               void *work, size_t work_bytes, void *stream);
+
+/* Solve AX + XA^T = C (eq. (1.3), real case), A, C, X n x n, with one Schur
+ * factorisation.  Arguments as sylv_solve. */
+int lyap_solve(int n, const double *A, int lda, const double *C, int ldc,
+               double *X, int ldx, const sylv_opts *opts, sylv_info *info,
+               void *work, size_t work_bytes, void *stream);
+
+/* Solve `batch` independent equations (kind[i] = SYLV_KIND_SYLV or
+ * SYLV_KIND_LYAP; B[i] ignored for Lyapunov).  kind, m, n, lda, ldb, ldc,
+ * ldx, and the pointer arrays A, B, C, X are HOST arrays of length batch;
+ * the matrices they point to live in device memory.  infos is a host array
+ * of length batch.  Equations up to order 256 run in one persistent kernel
+ * (one workgroup per equation, longest-first work queue); larger ones go
+ * through sylv_solve one by one. */
+int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
+                       const double *const *A, const int *lda,
+                       const double *const *B, const int *ldb,
+                       const double *const *C, const int *ldc,
+                       double *const *X, const int *ldx,
+                       const sylv_opts *opts, sylv_info *infos,
+                       void *work, size_t work_bytes, void *stream);
+
+/* Text for a return value or a status code. */
+const char *sylv_status_string(int code);
+
+/* ------------------------------------------------------------------------
+ * Stage-level entry points (used for stage-by-stage parity checks).
+ * prec is SYLV_PREC_FP64 or SYLV_PREC_FP32; for FP32 the float arrays are
+ * `float*` passed as void*.
+ * ---------------------------------------------------------------------- */
+
+/* Real Schur factorisation A = U T U^T (Sec. 2.1, eq. (2.3)): blocked
+ * Householder reduction to Hessenberg form, then the multishift QR
+ * algorithm.  A (n x n, lda) is read only; T (ldt) receives the upper
+ * quasi-triangular factor (every 2x2 diagonal block holds a complex pair;
+ * all other subdiagonal entries are exact zeros), U (ldu) the orthogonal
+ * factor.  Element type per prec.  Returns 0 or a negative error; *status
+ * (host, may be NULL) receives SYLV_OK or SYLV_ST_QR_FAILED. */
+int sylv_schur(int n, const void *A, int lda, void *T, int ldt, void *U, int ldu,
+               int prec, int *status, void *stream);
+
+/* Quasi-triangular equation TA Y + Y op(TB) = C (the Bartels-Stewart
+ * substitution of Sec. 2.2.1): TA m x m and TB n x n upper quasi-triangular;
+ * op(TB) = TB (trans_b = 0) or TB^T (trans_b = 1, the Lyapunov case).  C
+ * (ldc) is overwritten by Y.  *perturbed (host, may be NULL) is set to 1 if
+ * a near-singular block pivot was perturbed. */
+int sylv_trsyl(int m, int n, const void *TA, int ldta, const void *TB, int ldtb,
+               int trans_b, void *C, int ldc, int prec, int *perturbed, void *stream);
+
+/* Binary64 residual R = C - A X - X op(B) with op(B) = B (lyap = 0) or A^T
+ * (lyap = 1), and the relative residual of eq. (2.1) (Frobenius norms)
+ * returned in *rel_res (host).  R (ldr) may be NULL. */
+int sylv_residual(int m, int n, const double *A, int lda, const double *B, int ldb,
+                  const double *C, int ldc, const double *X, int ldx,
+                  double *R, int ldr, int lyap, double *rel_res, void *stream);
+
+/* C = alpha op(A) op(B) + beta C with op = transpose when ta/tb = 1.
+ * prec FP64: double operands (FP64 MFMA); FP32: float operands (FP32 MFMA).
+ * op(A) is m x k, op(B) is k x n. */
+int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha,
+              const void *A, int lda, const void *B, int ldb, double beta,
+              void *C, int ldc, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned precision selector (MLP 16-64-64-3, FP32).  Features are the 16
+ * cheap quantities listed in sylv_selector_features; classes are
+ * 0 = BF16 + refinement, 1 = FP32 + refinement, 2 = plain FP64.
+ * ---------------------------------------------------------------------- */
+
+#define SYLV_NFEAT 16
+#define SYLV_NCLASS 3
+#define SYLV_MLP_NPARAM 5443
+
+/* Forward pass: feats (device, n x 16 row-major, already standardised),
+ * params (device, 5443 floats: W1 64x16, b1, W2 64x64, b2, W3 3x64, b3,
+ * row-major weights), probs (device, n x 3 row-major). */
+int sylv_mlp_forward(int n, const float *feats, const float *params, float *probs,
+                     void *stream);
+
+/* One training step on a mini-batch: forward, mean cross-entropy, backward
+ * and an Adam update of params in place.  labels (device, int32, n);
+ * adam_m/adam_v (device, 5443 floats each) are the moment estimates; t is
+ * the 1-based step count; grad (device, 5443, may be NULL) receives the
+ * gradient; loss (host, may be NULL) the mean loss of the batch. */
+int sylv_mlp_train_step(int n, const float *feats, const int *labels, float *params,
+                        float *adam_m, float *adam_v, int t, float lr, float *grad,
+                        float *loss, void *stream);
+
+/* Install selector weights (host: 5443 params followed by 16 feature means
+ * and 16 feature standard deviations) used by SYLV_PREC_AUTO. */
+int sylv_selector_set(const float *blob, int nvalues);
+
+/* Features of one equation from its coefficient data (device pointers):
+ * writes 16 floats to feats (host).  Sylvester: B given; Lyapunov: B NULL. */
+int sylv_selector_features(int m, int n, const double *A, int lda, const double *B,
+                           int ldb, const double *C, int ldc, float *feats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYLV_H */

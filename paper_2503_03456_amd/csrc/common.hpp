@@ -1,0 +1,70 @@
+// Shared device/host helpers for the gfx950 Sylvester solver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <cmath>
+#include <cfloat>
+
+#define SYLV_DEVINL __device__ __forceinline__
+
+// Column-major element access.
+#define CM(a, i, j, ld) ((a)[(size_t)(j) * (size_t)(ld) + (size_t)(i)])
+
+namespace sylv {
+
+template <typename T> struct num;
+template <> struct num<float> {
+    static constexpr float ulp = 5.9604644775390625e-08f;  // 2^-24, unit roundoff of binary32
+    static constexpr float safmin = 1.17549435e-38f;
+};
+template <> struct num<double> {
+    static constexpr double ulp = 1.1102230246251565e-16;  // 2^-53
+    static constexpr double safmin = 2.2250738585072014e-308;
+};
+
+// Error checking on the host: returns the negative ABI code from the caller.
+#define HIP_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return SYLV_ERR_HIP - (int)_e;  \
+    } while (0)
+
+// 2-norm of (a, b, c) without overflow for moderate ranges: scale by the
+// largest magnitude.
+template <typename T>
+SYLV_DEVINL T norm3(T a, T b, T c) {
+    T m = fmax(fabs(a), fmax(fabs(b), fabs(c)));
+    if (m == T(0)) return T(0);
+    T x = a / m, y = b / m, z = c / m;
+    return m * sqrt(x * x + y * y + z * z);
+}
+
+// Householder reflector for a vector of length 2 or 3 (z ignored when
+// len == 2): P = I - tau v v^T, v = (1, v1, v2), P x = beta e1.  Returns
+// tau = 0 when x(1:) is zero (P = I).
+template <typename T>
+SYLV_DEVINL void reflector3(int len, T x, T y, T z, T &v1, T &v2, T &tau, T &beta) {
+    if (len == 2) z = T(0);
+    T tail = fmax(fabs(y), fabs(z));
+    if (tail == T(0)) {
+        v1 = T(0); v2 = T(0); tau = T(0); beta = x;
+        return;
+    }
+    T nrm = norm3(x, y, z);
+    T b = (x >= T(0)) ? -nrm : nrm;
+    tau = (b - x) / b;
+    T s = T(1) / (x - b);
+    v1 = y * s;
+    v2 = z * s;
+    beta = b;
+}
+
+}  // namespace sylv
+
+// ABI error codes (mirrors include/sylv.h)
+#ifndef SYLV_ERR_HIP
+#define SYLV_ERR_HIP (-100)
+#define SYLV_ERR_ALLOC (-200)
+#define SYLV_ERR_NOGPU (-300)
+#endif

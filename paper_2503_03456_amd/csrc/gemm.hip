@@ -1,0 +1,159 @@
+// MFMA GEMM for gfx950: C = alpha * op(A) * op(B) + beta * C, column-major.
+//
+// One kernel template serves every precision pair the solver needs:
+//   ACC = double -> v_mfma_f64_16x16x4f64 (binary64 residual, plain FP64 path)
+//   ACC = float  -> v_mfma_f32_16x16x4f32 (binary32 Schur updates, transforms)
+// Operands may be stored in a wider type than ACC (binary64 residual read
+// straight into a binary32 product: the conversion happens on the way into
+// LDS) and C may be wider than ACC (binary64 X += binary32 product).
+//
+// Tiling: 64x64 output tile per 256-thread workgroup (4 wave64s in a 2x2
+// grid, each 32x32 = 2x2 MFMA blocks of 16x16), K staged through LDS 16 at a
+// time with a register prefetch of the next K slice.  The MFMA operands are
+// fed swapped (op(B)^T in the A slot, op(A)^T in the B slot) so that each
+// lane's accumulators run down a column of C: stores are 16 consecutive
+// elements of a column per quarter-wave.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace sylv {
+
+template <typename T> struct mfma16;
+template <> struct mfma16<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static SYLV_DEVINL v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // output row (within the 16x16 block) held by lane l in accumulator r
+    static SYLV_DEVINL int orow(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct mfma16<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static SYLV_DEVINL v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static SYLV_DEVINL int orow(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 16;
+
+template <typename TA, typename TB, typename TC, typename ACC>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
+                                                   const TA *__restrict__ A, int lda, int ta,
+                                                   const TB *__restrict__ B, int ldb, int tb,
+                                                   TC *__restrict__ C, int ldc, ACC alpha, ACC beta,
+                                                   int tiles_m, TB bscale) {
+    __shared__ ACC As[GBK][GBM + GPAD];
+    __shared__ ACC Bs[GBK][GBN + GPAD];
+    typedef typename mfma16<ACC>::v4 v4;
+
+    // XCD-aware tile order: consecutive workgroup ids go to different XCDs;
+    // give each XCD a contiguous run of tiles (shares operand panels in L2).
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+    const int tm = bid % tiles_m, tn = bid / tiles_m;
+    const int row0 = tm * GBM, col0 = tn * GBN;
+
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wm = w & 1, wn = w >> 1;
+
+    v4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+
+    ACC ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int i, k;
+            if (!ta) { i = l; k = (t >> 6) + 4 * r; } else { k = t & 15; i = (t >> 4) + 16 * r; }
+            int gi = row0 + i, gk = k0 + k;
+            ACC v = ACC(0);
+            if (gi < M && gk < K) v = (ACC)(ta ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi]);
+            ra[r] = v;
+            int j;
+            if (!tb) { k = t & 15; j = (t >> 4) + 16 * r; } else { j = l; k = (t >> 6) + 4 * r; }
+            int gj = col0 + j;
+            gk = k0 + k;
+            ACC u = ACC(0);
+            if (gj < N && gk < K) u = (ACC)(bscale * (tb ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk]));
+            rb[r] = u;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int i, k;
+            if (!ta) { i = l; k = (t >> 6) + 4 * r; } else { k = t & 15; i = (t >> 4) + 16 * r; }
+            As[k][i] = ra[r];
+            int j;
+            if (!tb) { k = t & 15; j = (t >> 4) + 16 * r; } else { j = l; k = (t >> 6) + 4 * r; }
+            Bs[k][j] = rb[r];
+        }
+    };
+
+    const int nk = (K + GBK - 1) / GBK;
+    if (nk > 0) load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        store();
+        __syncthreads();
+        if (kt + 1 < nk) load((kt + 1) * GBK);
+#pragma unroll
+        for (int kk = 0; kk < GBK / 4; ++kk) {
+            const int kr = 4 * kk + (l >> 4);
+            ACC fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) fa[a] = As[kr][32 * wm + 16 * a + (l & 15)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) fb[b] = Bs[kr][32 * wn + 16 * b + (l & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = mfma16<ACC>::op(fb[b], fa[a], acc[a][b]);
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int i = row0 + 32 * wm + 16 * a + (l & 15);
+                int j = col0 + 32 * wn + 16 * b + mfma16<ACC>::orow(l, r);
+                if (i < M && j < N) {
+                    TC *p = C + (size_t)j * ldc + i;
+                    ACC v = alpha * acc[a][b][r];
+                    if (beta != ACC(0)) *p = (TC)v + (TC)beta * (*p);
+                    else *p = (TC)v;
+                }
+            }
+}
+
+template <typename TA, typename TB, typename TC, typename ACC>
+void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const TA *A, int lda,
+          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale) {
+    if (M <= 0 || N <= 0) return;
+    int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, ACC>), dim3(tm * tn), dim3(256), 0, s, M, N, K, A,
+                       lda, ta, B, ldb, tb, C, ldc, alpha, beta, tm, bscale);
+}
+
+template void gemm<double, double, double, double>(hipStream_t, int, int, int, int, int, double,
+                                                   const double *, int, const double *, int,
+                                                   double, double *, int, double);
+template void gemm<float, float, float, float>(hipStream_t, int, int, int, int, int, float,
+                                               const float *, int, const float *, int, float,
+                                               float *, int, float);
+template void gemm<float, double, float, float>(hipStream_t, int, int, int, int, int, float,
+                                                const float *, int, const double *, int, float,
+                                                float *, int, double);
+template void gemm<float, float, double, float>(hipStream_t, int, int, int, int, int, float,
+                                                const float *, int, const float *, int, float,
+                                                double *, int, float);
+
+}  // namespace sylv

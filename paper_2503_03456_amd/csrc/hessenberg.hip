@@ -1,0 +1,259 @@
+// Blocked Householder reduction to upper Hessenberg form, H = U0^T A U0
+// (the first phase of the QR algorithm, Golub & Van Loan Sec. 7.4.3, in the
+// blocked form where a panel of nb reflectors Q = I - V T V^T is applied to
+// the trailing matrix as A <- Q^T (A - Y V^T), Y = A V T).
+//
+// Per panel column (one pair of launches):
+//   k_hess_col  (one workgroup): finish y and T of the previous column,
+//               bring the current column up to date with the panel's earlier
+//               reflectors (right: -Y V(col,:)^T; left: -V T^T V^T a), and
+//               generate its Householder vector.
+//   k_hess_gemv (many workgroups): y_raw = A(:, col+1:n) v over row blocks x
+//               column slices; partial sums are combined in a fixed order by
+//               the next k_hess_col (deterministic).
+// After the panel: trailing update with MFMA GEMMs.  U0 is formed at the end
+// by applying the stored block reflectors backwards to the identity.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace sylv {
+
+constexpr int HNT = 1024;
+
+template <typename T>
+SYLV_DEVINL T block_sum(T v, T *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    T s = T(0);
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
+// State: A (n x n, lda), V (n x n, ldv = n) reflector vectors (column c holds
+// the vector of column c's reflector, 1 at row c+1, zeros above), Tp (nb x nb,
+// ld nb) the panel's T, Y (n x nb, ld n), Ypart (S x n) partials of y_raw for
+// column `col-1`, tau (n).
+template <typename T>
+__global__ __launch_bounds__(HNT) void k_hess_col(int n, T *A, int lda, T *V, T *Tp, int nb, T *Y,
+                                                 const T *Ypart, int S, T *tau, int k0, int i,
+                                                 int finalize_only) {
+    __shared__ T red[HNT / 64];
+    __shared__ T wv[64];
+    __shared__ T cv[64];
+    __shared__ T sh[4];
+    const int tid = threadIdx.x;
+    const int ldv = n;
+    if (i > 0) {
+        // finish column i-1: w = V(:,k0:k0+i-1)^T v_{i-1}; T(0:i-1, i-1); y_{i-1}
+        const int cp = k0 + i - 1;
+        const T tp = tau[cp];
+        for (int j = 0; j < i - 1; ++j) {
+            T acc = T(0);
+            for (int r = cp + 1 + tid; r < n; r += HNT) acc += CM(V, r, k0 + j, ldv) * CM(V, r, cp, ldv);
+            acc = block_sum(acc, red);
+            if (tid == 0) wv[j] = acc;
+        }
+        __syncthreads();
+        if (tid < i - 1) {
+            // T(0:i-1, i-1) = -tau T(0:i-1,0:i-1) w   (T upper triangular)
+            T acc = T(0);
+            for (int j = tid; j < i - 1; ++j) acc += Tp[j * nb + tid] * wv[j];
+            cv[tid] = -tp * acc;
+        }
+        __syncthreads();
+        if (tid < i - 1) Tp[(i - 1) * nb + tid] = cv[tid];
+        if (tid == 0) Tp[(i - 1) * nb + (i - 1)] = tp;
+        for (int r = tid; r < n; r += HNT) {
+            T yr = T(0);
+            for (int s = 0; s < S; ++s) yr += Ypart[(size_t)s * n + r];
+            T acc = T(0);
+            for (int j = 0; j < i - 1; ++j) acc += CM(Y, r, j, n) * wv[j];
+            CM(Y, r, i - 1, n) = tp * (yr - acc);
+        }
+        __syncthreads();
+    }
+    if (finalize_only) return;
+    const int col = k0 + i;
+    // right update of the current column by the panel's earlier reflectors:
+    // a(r) -= sum_j Y(r, j) V(col, k0+j)
+    for (int j = tid; j < i; j += HNT) cv[j] = CM(V, col, k0 + j, ldv);
+    __syncthreads();
+    for (int r = tid; r < n; r += HNT) {
+        T acc = T(0);
+        for (int j = 0; j < i; ++j) acc += CM(Y, r, j, n) * cv[j];
+        CM(A, r, col, lda) -= acc;
+    }
+    __syncthreads();
+    // left update on rows k0+1..n-1: a -= V T^T (V^T a)
+    if (i > 0) {
+        for (int j = 0; j < i; ++j) {
+            T acc = T(0);
+            for (int r = k0 + 1 + j + tid; r < n; r += HNT) acc += CM(V, r, k0 + j, ldv) * CM(A, r, col, lda);
+            acc = block_sum(acc, red);
+            if (tid == 0) wv[j] = acc;
+        }
+        __syncthreads();
+        if (tid < i) {
+            // c = T^T b: c(j) = sum_{j' <= j} T(j', j) b(j')
+            T acc = T(0);
+            for (int jp = 0; jp <= tid; ++jp) acc += Tp[tid * nb + jp] * wv[jp];
+            cv[tid] = acc;
+        }
+        __syncthreads();
+        for (int r = k0 + 1 + tid; r < n; r += HNT) {
+            T acc = T(0);
+            for (int j = 0; j < i; ++j) acc += CM(V, r, k0 + j, ldv) * cv[j];
+            CM(A, r, col, lda) -= acc;
+        }
+        __syncthreads();
+    }
+    // Householder vector for a(col+1:n): zeros below col+1
+    const int len = n - col - 1;
+    T mx = T(0);
+    for (int r = col + 2 + tid; r < n; r += HNT) mx = fmax(mx, fabs(CM(A, r, col, lda)));
+    // block max
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    mx = T(0);
+    for (int w = 0; w < HNT / 64; ++w) mx = fmax(mx, red[w]);
+    T ss = T(0);
+    if (mx > T(0))
+        for (int r = col + 2 + tid; r < n; r += HNT) {
+            T q = CM(A, r, col, lda) / mx;
+            ss += q * q;
+        }
+    ss = block_sum(ss, red);
+    if (tid == 0) {
+        T alpha = CM(A, col + 1, col, lda);
+        if (mx == T(0) || len < 2) {
+            sh[0] = T(0); sh[1] = alpha; sh[2] = T(0);
+        } else {
+            T xn = mx * sqrt(ss);
+            T nrm = hypot(alpha, xn);
+            T b = (alpha >= T(0)) ? -nrm : nrm;
+            sh[0] = (b - alpha) / b;
+            sh[1] = b;
+            sh[2] = T(1) / (alpha - b);
+        }
+    }
+    __syncthreads();
+    const T tc = sh[0], beta = sh[1], sc = sh[2];
+    for (int r = tid; r < n; r += HNT) {
+        T v;
+        if (r <= col) v = T(0);
+        else if (r == col + 1) v = T(1);
+        else v = CM(A, r, col, lda) * sc;
+        CM(V, r, col, ldv) = v;
+    }
+    __syncthreads();
+    for (int r = col + 1 + tid; r < n; r += HNT) CM(A, r, col, lda) = (r == col + 1) ? beta : T(0);
+    if (tid == 0) tau[col] = tc;
+}
+
+// Ypart[s][r] = sum_{c in slice s} A(r, c) v(c), c in [col+1, n)
+template <typename T>
+__global__ __launch_bounds__(256) void k_hess_gemv(int n, const T *A, int lda, const T *V, int col,
+                                                  T *Ypart, int S) {
+    __shared__ T vs[512];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int s = blockIdx.y;
+    const int c0 = col + 1, nc = n - c0;
+    const int per = (nc + S - 1) / S;
+    const int cb = c0 + s * per;
+    int ce = cb + per;
+    if (ce > n) ce = n;
+    const int ldv = n;
+    T acc = T(0);
+    for (int base = cb; base < ce; base += 512) {
+        int cnt = ce - base < 512 ? ce - base : 512;
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += 256) vs[q] = CM(V, base + q, col, ldv);
+        __syncthreads();
+        if (r < n)
+            for (int q = 0; q < cnt; ++q) acc += CM(A, r, base + q, lda) * vs[q];
+    }
+    if (r < n) Ypart[(size_t)s * n + r] = acc;
+}
+
+template <typename T>
+size_t hessenberg_work_elems(int n, int nb, int S) {
+    int np = (n + nb - 1) / nb;
+    return (size_t)n * n              // V
+           + (size_t)np * nb * nb     // T per panel
+           + (size_t)n * nb           // Y
+           + (size_t)S * n            // Ypart
+           + (size_t)n                // tau
+           + (size_t)2 * nb * n;      // W, W2 for the trailing update
+}
+template size_t hessenberg_work_elems<float>(int, int, int);
+template size_t hessenberg_work_elems<double>(int, int, int);
+
+// A (n x n) -> H in place; U (n x n) receives U0.  work: hessenberg_work_elems.
+template <typename T>
+void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int nb, int S) {
+    if (n <= 0) return;
+    identity<T>(s, n, U, ldu);
+    if (n <= 2) return;
+    const int np = (n - 2 + nb - 1) / nb;  // panels covering columns 0..n-3
+    T *V = work;
+    T *Tall = V + (size_t)n * n;
+    T *Y = Tall + (size_t)((n + nb - 1) / nb) * nb * nb;
+    T *Ypart = Y + (size_t)n * nb;
+    T *tau = Ypart + (size_t)S * n;
+    T *W = tau + n;
+    T *W2 = W + (size_t)nb * n;
+    hipMemsetAsync(V, 0, sizeof(T) * (size_t)n * n, s);
+    hipMemsetAsync(Tall, 0, sizeof(T) * (size_t)((n + nb - 1) / nb) * nb * nb, s);
+    const int rb = (n + 255) / 256;
+    for (int p = 0; p < np; ++p) {
+        const int k0 = p * nb;
+        const int nbp = (n - 2 - k0) < nb ? (n - 2 - k0) : nb;
+        T *Tp = Tall + (size_t)p * nb * nb;
+        for (int i = 0; i < nbp; ++i) {
+            hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y,
+                               Ypart, S, tau, k0, i, 0);
+            hipLaunchKernelGGL((k_hess_gemv<T>), dim3(rb, S), dim3(256), 0, s, n, A, lda, V, k0 + i,
+                               Ypart, S);
+        }
+        hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart,
+                           S, tau, k0, nbp, 1);
+        const int c1 = k0 + nbp;  // first trailing column
+        const int nt = n - c1;
+        if (nt > 0) {
+            // right: A(:, c1:n) -= Y V(c1:n, k0:k0+nbp)^T
+            gemm<T, T, T, T>(s, 0, 1, n, nt, nbp, T(-1), Y, n, V + (size_t)k0 * n + c1, n, T(1),
+                             A + (size_t)c1 * lda, lda);
+            // left: A(k0+1:n, c1:n) -= V T^T (V^T A(k0+1:n, c1:n))
+            const int mr = n - k0 - 1;
+            gemm<T, T, T, T>(s, 1, 0, nbp, nt, mr, T(1), V + (size_t)k0 * n + k0 + 1, n,
+                             A + (size_t)c1 * lda + k0 + 1, lda, T(0), W, nbp);
+            gemm<T, T, T, T>(s, 1, 0, nbp, nt, nbp, T(1), Tp, nb, W, nbp, T(0), W2, nbp);
+            gemm<T, T, T, T>(s, 0, 0, mr, nt, nbp, T(-1), V + (size_t)k0 * n + k0 + 1, n, W2, nbp,
+                             T(1), A + (size_t)c1 * lda + k0 + 1, lda);
+        }
+    }
+    // U0 = Q_0 Q_1 ... : apply the block reflectors backwards to the identity
+    for (int p = np - 1; p >= 0; --p) {
+        const int k0 = p * nb;
+        const int nbp = (n - 2 - k0) < nb ? (n - 2 - k0) : nb;
+        T *Tp = Tall + (size_t)p * nb * nb;
+        const int mr = n - k0 - 1;
+        T *Us = U + (size_t)(k0 + 1) * ldu + k0 + 1;
+        gemm<T, T, T, T>(s, 1, 0, nbp, mr, mr, T(1), V + (size_t)k0 * n + k0 + 1, n, Us, ldu, T(0),
+                         W, nbp);
+        gemm<T, T, T, T>(s, 0, 0, nbp, mr, nbp, T(1), Tp, nb, W, nbp, T(0), W2, nbp);
+        gemm<T, T, T, T>(s, 0, 0, mr, mr, nbp, T(-1), V + (size_t)k0 * n + k0 + 1, n, W2, nbp, T(1),
+                         Us, ldu);
+    }
+}
+template void hessenberg<float>(hipStream_t, int, float *, int, float *, int, float *, int, int);
+template void hessenberg<double>(hipStream_t, int, double *, int, double *, int, double *, int, int);
+
+}  // namespace sylv

@@ -1,0 +1,659 @@
+// QR algorithm kernels for the real Schur form (the low- or high-precision
+// Schur factorisations the paper's Sec. 2.1 assumes, computed by the QR
+// algorithm of Golub & Van Loan, Sec. 7.5).
+//
+// Three building blocks, all single-workgroup and LDS-resident:
+//   * francis_lds: implicit double-shift QR sweeps on a small dense upper
+//     Hessenberg matrix held in LDS, accumulating the orthogonal factor;
+//     deflation on negligible subdiagonal entries, exceptional shifts after
+//     10 and 20 stagnating sweeps, real-eigenvalue 2x2 blocks split by one
+//     rotation.  One barrier per bulge step: the 3x3 overlap block of a
+//     step is owned by one thread, so left and right updates never race.
+//   * k_aed: aggressive early deflation on the trailing window of the active
+//     block (Braman, Byers & Mathias 2002, part II): Schur form of the window,
+//     spike test from the bottom, restoration of Hessenberg form of the
+//     undeflated part; its eigenvalues become the next sweep's shifts.  With
+//     a zero spike it is simply the full Schur form of the window.
+//   * k_chase: one window phase of a small-bulge multishift sweep (part I of
+//     the same reference): a chain of bulges spaced three rows apart moves
+//     `adv` rows down inside an LDS window while the window's orthogonal
+//     factor is accumulated in LDS; the updates outside the window are
+//     applied afterwards with MFMA GEMMs by the host driver.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace sylv {
+
+// ------------------------------------------------------------------ helpers
+
+// Split the 2x2 block at (k, k) of the LDS matrix H (n x n) if its
+// eigenvalues are real: rotate so the block becomes upper triangular.
+// Updates rows k,k+1 (cols k..n-1), cols k,k+1 (rows 0..k+1) and cols k,k+1
+// of Z (nz rows).  Must be called by all threads (contains barriers).
+template <typename T, int NT>
+SYLV_DEVINL void std2x2_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int k) {
+    const int tid = threadIdx.x;
+    T a = CM(H, k, k, ldh), b = CM(H, k, k + 1, ldh);
+    T c = CM(H, k + 1, k, ldh), d = CM(H, k + 1, k + 1, ldh);
+    __syncthreads();
+    if (c == T(0)) return;
+    T p = T(0.5) * (a - d);
+    T disc = p * p + b * c;
+    if (disc < T(0)) return;  // complex pair: keep the block
+    // eigenvalue lam with |lam - d| = |p| + sqrt(disc); eigenvector (lam - d, c)
+    T e1 = p + copysign(sqrt(disc), p);
+    T nv = hypot(e1, c);
+    T cs = e1 / nv, sn = c / nv;
+    // rows k, k+1 of H: [r_k; r_k1] <- G^T [r_k; r_k1],  G = [[cs,-sn],[sn,cs]]
+    for (int j = k + tid; j < n; j += NT) {
+        T t1 = CM(H, k, j, ldh), t2 = CM(H, k + 1, j, ldh);
+        CM(H, k, j, ldh) = cs * t1 + sn * t2;
+        CM(H, k + 1, j, ldh) = cs * t2 - sn * t1;
+    }
+    __syncthreads();
+    for (int i = tid; i <= k + 1; i += NT) {
+        T t1 = CM(H, i, k, ldh), t2 = CM(H, i, k + 1, ldh);
+        CM(H, i, k, ldh) = cs * t1 + sn * t2;
+        CM(H, i, k + 1, ldh) = cs * t2 - sn * t1;
+    }
+    for (int i = tid; i < nz; i += NT) {
+        T t1 = CM(Z, i, k, ldz), t2 = CM(Z, i, k + 1, ldz);
+        CM(Z, i, k, ldz) = cs * t1 + sn * t2;
+        CM(Z, i, k + 1, ldz) = cs * t2 - sn * t1;
+    }
+    __syncthreads();
+    if (tid == 0) CM(H, k + 1, k, ldh) = T(0);
+    __syncthreads();
+}
+
+// Apply the reflector (1, v1, v2) with tau to a 3-vector (len 2 or 3).
+template <typename T>
+SYLV_DEVINL void refl_apply(int len, T v1, T v2, T tau, T &a0, T &a1, T &a2) {
+    T s = a0 + v1 * a1 + (len == 3 ? v2 * a2 : T(0));
+    s *= tau;
+    a0 -= s;
+    a1 -= s * v1;
+    if (len == 3) a2 -= s * v2;
+}
+
+// Francis double-shift QR on an n x n upper Hessenberg H in LDS (full Schur
+// form of H), Z (nz x n, LDS or global) <- Z * Q.  Returns 0 or 1
+// (iteration cap).  All threads must call it.  sint: one int of LDS scratch.
+template <typename T, int NT>
+SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *sint) {
+    const int tid = threadIdx.x;
+    const T ulp = num<T>::ulp, smlnum = num<T>::safmin * T(n) / num<T>::ulp;
+    int ihi = n - 1, its = 0, total = 0;
+    const int itmax = 30 * (n > 10 ? n : 10);
+    while (ihi >= 0) {
+        if (tid == 0) *sint = 0;
+        __syncthreads();
+        for (int k = 1 + tid; k <= ihi; k += NT) {
+            T hk = fabs(CM(H, k, k - 1, ldh));
+            T tst = fabs(CM(H, k - 1, k - 1, ldh)) + fabs(CM(H, k, k, ldh));
+            if (tst == T(0)) {
+                if (k >= 2) tst += fabs(CM(H, k - 1, k - 2, ldh));
+                if (k + 1 <= ihi) tst += fabs(CM(H, k + 1, k, ldh));
+            }
+            if (hk <= fmax(smlnum, ulp * tst)) atomicMax(sint, k);
+        }
+        __syncthreads();
+        const int l = *sint;
+        __syncthreads();
+        if (l > 0 && tid == 0) CM(H, l, l - 1, ldh) = T(0);
+        __syncthreads();
+        if (l == ihi) { ihi -= 1; its = 0; continue; }
+        if (l == ihi - 1) {
+            std2x2_lds<T, NT>(n, H, ldh, Z, ldz, nz, l);
+            ihi -= 2; its = 0;
+            continue;
+        }
+        if (++total > itmax) return 1;
+        ++its;
+        T h11 = CM(H, ihi - 1, ihi - 1, ldh), h12 = CM(H, ihi - 1, ihi, ldh);
+        T h21 = CM(H, ihi, ihi - 1, ldh), h22 = CM(H, ihi, ihi, ldh);
+        if (its == 10 || its == 20) {
+            T s = fabs(CM(H, ihi, ihi - 1, ldh)) + fabs(CM(H, ihi - 1, ihi - 2, ldh));
+            h11 = T(0.75) * s + CM(H, ihi, ihi, ldh);
+            h12 = T(-0.4375) * s;
+            h21 = s;
+            h22 = h11;
+        }
+        const T tr = h11 + h22, det = h11 * h22 - h12 * h21;
+        T x, y, z;
+        {
+            T a00 = CM(H, l, l, ldh), a01 = CM(H, l, l + 1, ldh), a10 = CM(H, l + 1, l, ldh);
+            T a11 = CM(H, l + 1, l + 1, ldh), a21 = CM(H, l + 2, l + 1, ldh);
+            // scale to avoid overflow in the shift polynomial
+            T sc = fabs(a00) + fabs(a10) + fabs(a01) + fabs(a11) + fabs(a21) + fabs(tr) + sqrt(fabs(det));
+            if (sc == T(0)) sc = T(1);
+            T b00 = a00 / sc, b01 = a01 / sc, b10 = a10 / sc, b11 = a11 / sc, b21 = a21 / sc;
+            T trs = tr / sc, dets = det / (sc * sc);
+            x = b00 * b00 + b01 * b10 - trs * b00 + dets;
+            y = b10 * (b00 + b11 - trs);
+            z = b10 * b21;
+        }
+        __syncthreads();
+        for (int k = l; k <= ihi - 1; ++k) {
+            const int len = (k <= ihi - 2) ? 3 : 2;
+            if (k > l) {
+                x = CM(H, k, k - 1, ldh);
+                y = CM(H, k + 1, k - 1, ldh);
+                z = (len == 3) ? CM(H, k + 2, k - 1, ldh) : T(0);
+            }
+            T v1, v2, tau, beta;
+            reflector3(len, x, y, z, v1, v2, tau, beta);
+            // work items: 0 overlap block, then left columns, right rows, Z rows
+            const int lc0 = (k > l) ? 1 : 0;                  // column k-1
+            const int nL = lc0 + (n - (k + len));              // cols {k-1} u [k+len, n)
+            const int extra = (len == 3 && k + 3 <= ihi) ? 1 : 0;
+            const int nR = k + extra;                          // rows [0,k) u {k+3}
+            const int tot = 1 + nL + nR + nz;
+            for (int e = tid; e < tot; e += NT) {
+                if (e == 0) {
+                    // overlap block: left then right on rows/cols k..k+len-1
+                    for (int j = k; j < k + len; ++j) {
+                        T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh);
+                        T a2 = (len == 3) ? CM(H, k + 2, j, ldh) : T(0);
+                        refl_apply(len, v1, v2, tau, a0, a1, a2);
+                        CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
+                        if (len == 3) CM(H, k + 2, j, ldh) = a2;
+                    }
+                    for (int i = k; i < k + len; ++i) {
+                        T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh);
+                        T a2 = (len == 3) ? CM(H, i, k + 2, ldh) : T(0);
+                        refl_apply(len, v1, v2, tau, a0, a1, a2);
+                        CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
+                        if (len == 3) CM(H, i, k + 2, ldh) = a2;
+                    }
+                } else if (e < 1 + nL) {
+                    int q = e - 1;
+                    if (lc0 && q == 0) {
+                        CM(H, k, k - 1, ldh) = beta;
+                        CM(H, k + 1, k - 1, ldh) = T(0);
+                        if (len == 3) CM(H, k + 2, k - 1, ldh) = T(0);
+                    } else {
+                        int j = k + len + q - lc0;
+                        T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh);
+                        T a2 = (len == 3) ? CM(H, k + 2, j, ldh) : T(0);
+                        refl_apply(len, v1, v2, tau, a0, a1, a2);
+                        CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
+                        if (len == 3) CM(H, k + 2, j, ldh) = a2;
+                    }
+                } else if (e < 1 + nL + nR) {
+                    int q = e - 1 - nL;
+                    int i = (q < k) ? q : k + 3;
+                    T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh);
+                    T a2 = (len == 3) ? CM(H, i, k + 2, ldh) : T(0);
+                    refl_apply(len, v1, v2, tau, a0, a1, a2);
+                    CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
+                    if (len == 3) CM(H, i, k + 2, ldh) = a2;
+                } else {
+                    int i = e - 1 - nL - nR;
+                    T a0 = CM(Z, i, k, ldz), a1 = CM(Z, i, k + 1, ldz);
+                    T a2 = (len == 3) ? CM(Z, i, k + 2, ldz) : T(0);
+                    refl_apply(len, v1, v2, tau, a0, a1, a2);
+                    CM(Z, i, k, ldz) = a0; CM(Z, i, k + 1, ldz) = a1;
+                    if (len == 3) CM(Z, i, k + 2, ldz) = a2;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // exact zeros below the first subdiagonal
+    for (int e = tid; e < n * n; e += NT) {
+        int i = e % n, j = e / n;
+        if (i > j + 1) CM(H, i, j, ldh) = T(0);
+    }
+    __syncthreads();
+    return 0;
+}
+
+// ---------------------------------------------------------------- k_aed
+// out[0] = status (0 ok, 1 QR cap), out[1] = nd (deflated count), out[2] =
+// ns (undeflated count); wr/wi (length nw) receive the eigenvalues of the
+// undeflated part in diagonal order.  Zw (global, nw x nw, ld nw) receives
+// the window's orthogonal factor.  spike_on = 0 means the window is the
+// whole active block (no spike): full Schur form, everything deflates.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, int spike_on,
+                                           T *Zw, int *out, T *wr, T *wi) {
+    extern __shared__ unsigned char smem_raw[];
+    T *Tw = reinterpret_cast<T *>(smem_raw);
+    T *Zl = Tw + nw * nw;
+    T *sp = Zl + nw * nw;  // spike, length nw
+    int *sint = reinterpret_cast<int *>(sp + nw);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nw * nw; e += NT) {
+        int i = e % nw, j = e / nw;
+        Tw[e] = CM(H, kwtop + i, kwtop + j, ldh);
+        Zl[e] = (i == j) ? T(1) : T(0);
+    }
+    __syncthreads();
+    int st = francis_lds<T, NT>(nw, Tw, nw, Zl, nw, nw, sint + 1);
+    if (st) {
+        if (tid == 0) { out[0] = 1; out[1] = 0; out[2] = 0; }
+        return;  // window left untouched in global memory
+    }
+    const T s = spike_on ? CM(H, kwtop, kwtop - 1, ldh) : T(0);
+    for (int j = tid; j < nw; j += NT) sp[j] = s * Zl[j * nw];
+    __syncthreads();
+    // deflation test from the bottom (no reordering)
+    const T ulp = num<T>::ulp, smlnum = num<T>::safmin * T(nw) / num<T>::ulp;
+    int ns = nw;
+    while (ns > 0) {
+        bool two = (ns >= 2) && (Tw[(ns - 2) * nw + (ns - 1)] != T(0));
+        if (!two) {
+            T foo = fabs(Tw[(ns - 1) * nw + (ns - 1)]);
+            if (foo == T(0)) foo = fabs(s);
+            if (fabs(sp[ns - 1]) <= fmax(smlnum, ulp * foo)) ns -= 1;
+            else break;
+        } else {
+            T foo = fabs(Tw[(ns - 1) * nw + (ns - 1)]) +
+                    sqrt(fabs(Tw[(ns - 2) * nw + (ns - 1)])) * sqrt(fabs(Tw[(ns - 1) * nw + (ns - 2)]));
+            if (foo == T(0)) foo = fabs(s);
+            if (fmax(fabs(sp[ns - 1]), fabs(sp[ns - 2])) <= fmax(smlnum, ulp * foo)) ns -= 2;
+            else break;
+        }
+    }
+    // eigenvalues of the undeflated part (shift candidates)
+    if (tid == 0) {
+        int i = 0;
+        while (i < ns) {
+            if (i + 1 < ns && Tw[i * nw + i + 1] != T(0)) {
+                T a = Tw[i * nw + i], b = Tw[(i + 1) * nw + i];
+                T c = Tw[i * nw + i + 1], d = Tw[(i + 1) * nw + i + 1];
+                T p = T(0.5) * (a - d), disc = p * p + b * c, mid = T(0.5) * (a + d);
+                if (disc >= T(0)) {
+                    T r = sqrt(disc);
+                    wr[i] = mid + r; wr[i + 1] = mid - r; wi[i] = wi[i + 1] = T(0);
+                } else {
+                    T r = sqrt(-disc);
+                    wr[i] = wr[i + 1] = mid; wi[i] = r; wi[i + 1] = -r;
+                }
+                i += 2;
+            } else {
+                wr[i] = Tw[i * nw + i]; wi[i] = T(0);
+                i += 1;
+            }
+        }
+    }
+    for (int j = ns + tid; j < nw; j += NT) sp[j] = T(0);
+    __syncthreads();
+    T newsub = (ns >= 1) ? sp[0] : T(0);
+    if (ns > 1 && s != T(0)) {
+        // reflect the spike onto its first entry: P sp = beta e1, P = I - tau v v^T
+        // (v stored in sp with v[0] = 1)
+        __shared__ T sh_tau, sh_beta;
+        if (tid == 0) {
+            T alpha = sp[0];
+            T mx = T(0);
+            for (int i = 1; i < ns; ++i) mx = fmax(mx, fabs(sp[i]));
+            if (mx == T(0)) { sh_tau = T(0); sh_beta = alpha; }
+            else {
+                T ss = T(0);
+                for (int i = 1; i < ns; ++i) { T q = sp[i] / mx; ss += q * q; }
+                T xn = mx * sqrt(ss);
+                T nrm = hypot(alpha, xn);
+                T b = (alpha >= T(0)) ? -nrm : nrm;
+                sh_tau = (b - alpha) / b;
+                T sc = T(1) / (alpha - b);
+                for (int i = 1; i < ns; ++i) sp[i] *= sc;
+                sh_beta = b;
+            }
+            sp[0] = T(1);
+        }
+        __syncthreads();
+        const T tau = sh_tau;
+        newsub = sh_beta;
+        if (tau != T(0)) {
+            // left: rows 0..ns-1, all columns
+            for (int j = tid; j < nw; j += NT) {
+                T acc = T(0);
+                for (int i = 0; i < ns; ++i) acc += sp[i] * Tw[j * nw + i];
+                acc *= tau;
+                for (int i = 0; i < ns; ++i) Tw[j * nw + i] -= acc * sp[i];
+            }
+            __syncthreads();
+            // right: columns 0..ns-1, rows 0..ns-1 (rows below are zero there)
+            for (int i = tid; i < ns; i += NT) {
+                T acc = T(0);
+                for (int j = 0; j < ns; ++j) acc += Tw[j * nw + i] * sp[j];
+                acc *= tau;
+                for (int j = 0; j < ns; ++j) Tw[j * nw + i] -= acc * sp[j];
+            }
+            for (int i = tid; i < nw; i += NT) {
+                T acc = T(0);
+                for (int j = 0; j < ns; ++j) acc += Zl[j * nw + i] * sp[j];
+                acc *= tau;
+                for (int j = 0; j < ns; ++j) Zl[j * nw + i] -= acc * sp[j];
+            }
+            __syncthreads();
+        }
+        // Householder reduction of Tw(0:ns, 0:ns) back to Hessenberg form;
+        // the left reflectors also act on columns ns..nw-1.
+        T *v = sp;  // reuse
+        for (int c = 0; c + 2 < ns; ++c) {
+            const int len = ns - c - 1;  // rows c+1..ns-1
+            if (tid == 0) {
+                T alpha = Tw[c * nw + c + 1];
+                T mx = T(0);
+                for (int i = 1; i < len; ++i) mx = fmax(mx, fabs(Tw[c * nw + c + 1 + i]));
+                if (mx == T(0)) { sh_tau = T(0); sh_beta = alpha; v[0] = T(1); for (int i = 1; i < len; ++i) v[i] = T(0); }
+                else {
+                    T ss = T(0);
+                    for (int i = 1; i < len; ++i) { T q = Tw[c * nw + c + 1 + i] / mx; ss += q * q; }
+                    T xn = mx * sqrt(ss), nrm = hypot(alpha, xn);
+                    T b = (alpha >= T(0)) ? -nrm : nrm;
+                    sh_tau = (b - alpha) / b;
+                    T sc = T(1) / (alpha - b);
+                    v[0] = T(1);
+                    for (int i = 1; i < len; ++i) v[i] = Tw[c * nw + c + 1 + i] * sc;
+                    sh_beta = b;
+                }
+            }
+            __syncthreads();
+            const T tau = sh_tau;
+            if (tau != T(0)) {
+                for (int j = c + 1 + tid; j < nw; j += NT) {
+                    T acc = T(0);
+                    for (int i = 0; i < len; ++i) acc += v[i] * Tw[j * nw + c + 1 + i];
+                    acc *= tau;
+                    for (int i = 0; i < len; ++i) Tw[j * nw + c + 1 + i] -= acc * v[i];
+                }
+                __syncthreads();
+                for (int i = tid; i < ns; i += NT) {
+                    T acc = T(0);
+                    for (int j = 0; j < len; ++j) acc += Tw[(c + 1 + j) * nw + i] * v[j];
+                    acc *= tau;
+                    for (int j = 0; j < len; ++j) Tw[(c + 1 + j) * nw + i] -= acc * v[j];
+                }
+                for (int i = tid; i < nw; i += NT) {
+                    T acc = T(0);
+                    for (int j = 0; j < len; ++j) acc += Zl[(c + 1 + j) * nw + i] * v[j];
+                    acc *= tau;
+                    for (int j = 0; j < len; ++j) Zl[(c + 1 + j) * nw + i] -= acc * v[j];
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                Tw[c * nw + c + 1] = sh_beta;
+                for (int i = 1; i < len; ++i) Tw[c * nw + c + 1 + i] = T(0);
+            }
+            __syncthreads();
+        }
+    }
+    // write back: window, spike column, Zw
+    for (int e = tid; e < nw * nw; e += NT) {
+        int i = e % nw, j = e / nw;
+        CM(H, kwtop + i, kwtop + j, ldh) = Tw[e];
+        Zw[e] = Zl[e];
+    }
+    if (spike_on) {
+        for (int i = tid; i < nw; i += NT) CM(H, kwtop + i, kwtop - 1, ldh) = (i == 0) ? newsub : T(0);
+    }
+    if (tid == 0) { out[0] = 0; out[1] = nw - ns; out[2] = ns; }
+}
+
+template <typename T>
+size_t aed_smem(int nw) {
+    return sizeof(T) * ((size_t)2 * nw * nw + nw) + 4 * sizeof(int);
+}
+
+template <typename T>
+int aed_launch(hipStream_t s, int nw, T *H, int ldh, int kwtop, int spike_on, T *Zw, int *out,
+               T *wr, T *wi) {
+    size_t sm = aed_smem<T>(nw);
+    if (sm > 160 * 1024) return -1;
+    auto kfn = k_aed<T, 256>;
+    static size_t attr_set = 0;
+    if (sm > attr_set) {
+        if (hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return -1;
+        }
+        attr_set = sm;
+    }
+    hipLaunchKernelGGL(kfn, dim3(1), dim3(256), sm, s, nw, H, ldh, kwtop, spike_on, Zw, out, wr, wi);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int aed_launch<float>(hipStream_t, int, float *, int, int, int, float *, int *, float *, float *);
+template int aed_launch<double>(hipStream_t, int, double *, int, int, int, double *, int *, double *, double *);
+template size_t aed_smem<float>(int);
+template size_t aed_smem<double>(int);
+
+// ------------------------------------------------------------- k_chase
+// One phase of a multishift sweep over the active block [ktop, kbot].
+// Bulge b (0-based, b = 0 introduced first) sits at position p = t - 3b at
+// time t (its reflector acts on rows/cols ktop+p .. ktop+p+2; p = 0 is the
+// introduction, p = N-2 the 2x2 exit step, N = kbot-ktop+1).  The phase runs
+// times t0 .. t0+adv-1 inside the window [ws, ws+W) of H, which is loaded to
+// LDS; Uw (W x W, LDS) accumulates the window's orthogonal factor and is
+// written to global memory for the off-window GEMM updates.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot, int ws, int W,
+                                             int t0, int adv, int nbulge, const T *trd,
+                                             T *Uw_out) {
+    extern __shared__ unsigned char smem_raw[];
+    T *Hw = reinterpret_cast<T *>(smem_raw);
+    T *Uw = Hw + W * W;
+    T *refl = Uw + W * W;  // per bulge: v1, v2, tau, beta
+    int *rinfo = reinterpret_cast<int *>(refl + 4 * nbulge);  // per bulge: local row q (or -1), len
+    const int tid = threadIdx.x;
+    const int N = kbot - ktop + 1;
+    for (int e = tid; e < W * W; e += NT) {
+        int i = e % W, j = e / W;
+        Hw[e] = CM(H, ws + i, ws + j, ldh);
+        Uw[e] = (i == j) ? T(1) : T(0);
+    }
+    __syncthreads();
+    const int kb = kbot - ws;  // local index of kbot
+    for (int t = t0; t < t0 + adv; ++t) {
+        // phase 0: reflectors of the active bulges
+        for (int b = tid; b < nbulge; b += NT) {
+            int p = t - 3 * b;
+            if (p < 0 || p > N - 2) { rinfo[2 * b] = -1; continue; }
+            int q = ktop + p - ws;  // local row of the reflector
+            int len = (p <= N - 3) ? 3 : 2;
+            T x, y, z;
+            if (p == 0) {
+                T tr = trd[2 * b], det = trd[2 * b + 1];
+                T a00 = Hw[q * W + q], a01 = Hw[(q + 1) * W + q], a10 = Hw[q * W + q + 1];
+                T a11 = Hw[(q + 1) * W + q + 1], a21 = Hw[(q + 1) * W + q + 2];
+                T sc = fabs(a00) + fabs(a10) + fabs(a01) + fabs(a11) + fabs(a21) + fabs(tr) + sqrt(fabs(det));
+                if (sc == T(0)) sc = T(1);
+                T b00 = a00 / sc, b01 = a01 / sc, b10 = a10 / sc, b11 = a11 / sc, b21 = a21 / sc;
+                T trs = tr / sc, dets = det / (sc * sc);
+                x = b00 * b00 + b01 * b10 - trs * b00 + dets;
+                y = b10 * (b00 + b11 - trs);
+                z = b10 * b21;
+            } else {
+                x = Hw[(q - 1) * W + q];
+                y = Hw[(q - 1) * W + q + 1];
+                z = (len == 3) ? Hw[(q - 1) * W + q + 2] : T(0);
+            }
+            T v1, v2, tau, beta;
+            reflector3(len, x, y, z, v1, v2, tau, beta);
+            refl[4 * b] = v1; refl[4 * b + 1] = v2; refl[4 * b + 2] = tau; refl[4 * b + 3] = beta;
+            rinfo[2 * b] = q; rinfo[2 * b + 1] = len;
+        }
+        __syncthreads();
+        // phase A: left applications, rows q..q+len-1, columns q-1 (p>0: set
+        // beta, zeros) and q..W-1.  Distinct bulges touch distinct rows.
+        for (int b = 0; b < nbulge; ++b) {
+            const int q = rinfo[2 * b];
+            if (q < 0) continue;
+            const int len = rinfo[2 * b + 1];
+            const T v1 = refl[4 * b], v2 = refl[4 * b + 1], tau = refl[4 * b + 2];
+            const int p = ktop - ws + 0;  // unused placeholder for clarity
+            (void)p;
+            const bool intro = (q + ws == ktop) && (t - 3 * b == 0);
+            const int c0 = intro ? q : q - 1;
+            for (int j = c0 + tid; j < W; j += NT) {
+                if (!intro && j == q - 1) {
+                    Hw[j * W + q] = refl[4 * b + 3];
+                    Hw[j * W + q + 1] = T(0);
+                    if (len == 3) Hw[j * W + q + 2] = T(0);
+                    continue;
+                }
+                T a0 = Hw[j * W + q], a1 = Hw[j * W + q + 1];
+                T a2 = (len == 3) ? Hw[j * W + q + 2] : T(0);
+                refl_apply(len, v1, v2, tau, a0, a1, a2);
+                Hw[j * W + q] = a0; Hw[j * W + q + 1] = a1;
+                if (len == 3) Hw[j * W + q + 2] = a2;
+            }
+        }
+        __syncthreads();
+        // phase B: right applications on columns q..q+len-1 (rows 0..min(q+3, kb))
+        // and on Uw (all rows).  Distinct bulges touch distinct columns.
+        for (int b = 0; b < nbulge; ++b) {
+            const int q = rinfo[2 * b];
+            if (q < 0) continue;
+            const int len = rinfo[2 * b + 1];
+            const T v1 = refl[4 * b], v2 = refl[4 * b + 1], tau = refl[4 * b + 2];
+            int rmax = q + 3 < kb ? q + 3 : kb;
+            if (rmax > W - 1) rmax = W - 1;
+            const int nr = rmax + 1;
+            for (int e = tid; e < nr + W; e += NT) {
+                T *M = (e < nr) ? Hw : Uw;
+                int i = (e < nr) ? e : e - nr;
+                T a0 = M[q * W + i], a1 = M[(q + 1) * W + i];
+                T a2 = (len == 3) ? M[(q + 2) * W + i] : T(0);
+                refl_apply(len, v1, v2, tau, a0, a1, a2);
+                M[q * W + i] = a0; M[(q + 1) * W + i] = a1;
+                if (len == 3) M[(q + 2) * W + i] = a2;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < W * W; e += NT) {
+        int i = e % W, j = e / W;
+        CM(H, ws + i, ws + j, ldh) = Hw[e];
+        Uw_out[e] = Uw[e];
+    }
+}
+
+template <typename T>
+size_t chase_smem(int W, int nbulge) {
+    return sizeof(T) * ((size_t)2 * W * W + 4 * nbulge) + sizeof(int) * 2 * nbulge;
+}
+
+template <typename T>
+int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W, int t0, int adv,
+                 int nbulge, const T *trd, T *Uw) {
+    size_t sm = chase_smem<T>(W, nbulge);
+    if (sm > 160 * 1024) return -1;
+    auto kfn = k_chase<T, 256>;
+    static size_t attr_set = 0;
+    if (sm > attr_set) {
+        if (hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return -1;
+        }
+        attr_set = sm;
+    }
+    hipLaunchKernelGGL(kfn, dim3(1), dim3(256), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge,
+                       trd, Uw);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int chase_launch<float>(hipStream_t, float *, int, int, int, int, int, int, int, int,
+                                 const float *, float *);
+template int chase_launch<double>(hipStream_t, double *, int, int, int, int, int, int, int, int,
+                                  const double *, double *);
+template size_t chase_smem<float>(int, int);
+template size_t chase_smem<double>(int, int);
+
+// ------------------------------------------------------- small utilities
+
+// Largest k in [klo+1, kbot] with a negligible subdiagonal H(k, k-1) (which is
+// then set to exact zero), or klo if none.  Written to *out.
+template <typename T>
+__global__ __launch_bounds__(256) void k_find_ktop(T *H, int ldh, int klo, int kbot, int *out) {
+    __shared__ int best;
+    if (threadIdx.x == 0) best = klo;
+    __syncthreads();
+    const T ulp = num<T>::ulp, smlnum = num<T>::safmin * T(kbot + 1) / num<T>::ulp;
+    for (int k = klo + 1 + threadIdx.x; k <= kbot; k += blockDim.x) {
+        T hk = fabs(CM(H, k, k - 1, ldh));
+        T tst = fabs(CM(H, k - 1, k - 1, ldh)) + fabs(CM(H, k, k, ldh));
+        if (tst == T(0)) {
+            if (k - 2 >= klo) tst += fabs(CM(H, k - 1, k - 2, ldh));
+            if (k + 1 <= kbot) tst += fabs(CM(H, k + 1, k, ldh));
+        }
+        if (hk <= fmax(smlnum, ulp * tst)) atomicMax(&best, k);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (best > klo) CM(H, best, best - 1, ldh) = T(0);
+        *out = best;
+    }
+}
+template <typename T>
+void find_ktop(hipStream_t s, T *H, int ldh, int klo, int kbot, int *out) {
+    hipLaunchKernelGGL((k_find_ktop<T>), dim3(1), dim3(256), 0, s, H, ldh, klo, kbot, out);
+}
+template void find_ktop<float>(hipStream_t, float *, int, int, int, int *);
+template void find_ktop<double>(hipStream_t, double *, int, int, int, int *);
+
+// Split a converged 2x2 block at (k, k) of the full n x n H (global) if its
+// eigenvalues are real; rotate rows k,k+1 / cols k,k+1 of H and U.
+template <typename T>
+__global__ __launch_bounds__(256) void k_std2x2(int n, T *H, int ldh, T *U, int ldu, int k) {
+    T a = CM(H, k, k, ldh), b = CM(H, k, k + 1, ldh);
+    T c = CM(H, k + 1, k, ldh), d = CM(H, k + 1, k + 1, ldh);
+    if (c == T(0)) return;
+    T p = T(0.5) * (a - d), disc = p * p + b * c;
+    if (disc < T(0)) return;
+    T e1 = p + copysign(sqrt(disc), p);
+    T nv = hypot(e1, c);
+    T cs = e1 / nv, sn = c / nv;
+    __syncthreads();
+    for (int j = k + threadIdx.x; j < n; j += blockDim.x) {
+        T t1 = CM(H, k, j, ldh), t2 = CM(H, k + 1, j, ldh);
+        CM(H, k, j, ldh) = cs * t1 + sn * t2;
+        CM(H, k + 1, j, ldh) = cs * t2 - sn * t1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= k + 1; i += blockDim.x) {
+        T t1 = CM(H, i, k, ldh), t2 = CM(H, i, k + 1, ldh);
+        CM(H, i, k, ldh) = cs * t1 + sn * t2;
+        CM(H, i, k + 1, ldh) = cs * t2 - sn * t1;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        T t1 = CM(U, i, k, ldu), t2 = CM(U, i, k + 1, ldu);
+        CM(U, i, k, ldu) = cs * t1 + sn * t2;
+        CM(U, i, k + 1, ldu) = cs * t2 - sn * t1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) CM(H, k + 1, k, ldh) = T(0);
+}
+template <typename T>
+void std2x2(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, int k) {
+    hipLaunchKernelGGL((k_std2x2<T>), dim3(1), dim3(256), 0, s, n, H, ldh, U, ldu, k);
+}
+template void std2x2<float>(hipStream_t, int, float *, int, float *, int, int);
+template void std2x2<double>(hipStream_t, int, double *, int, double *, int, int);
+
+// Zero every entry below the first subdiagonal (n x n).
+template <typename T>
+__global__ void k_clean_lower(int n, T *H, int ldh) {
+    size_t total = (size_t)n * n;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        int i = (int)(e % n), j = (int)(e / n);
+        if (i > j + 1) H[(size_t)j * ldh + i] = T(0);
+    }
+}
+template <typename T>
+void clean_lower(hipStream_t s, int n, T *H, int ldh) {
+    if (n <= 0) return;
+    size_t g = ((size_t)n * n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL((k_clean_lower<T>), dim3((int)g), dim3(256), 0, s, n, H, ldh);
+}
+template void clean_lower<float>(hipStream_t, int, float *, int);
+template void clean_lower<double>(hipStream_t, int, double *, int);
+
+}  // namespace sylv

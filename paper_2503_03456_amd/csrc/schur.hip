@@ -1,0 +1,255 @@
+// Host driver of the real Schur factorisation A = U T U^T on one GPU:
+// blocked Hessenberg reduction, then the small-bulge multishift QR algorithm
+// with aggressive early deflation (Braman, Byers & Mathias 2002), using the
+// single-workgroup LDS kernels of hqr.hip for the sequential parts and MFMA
+// GEMMs for every update outside the current LDS window.
+//
+// Loop on the active block [ktop, kbot] (kbot starts at n-1):
+//   - find the largest negligible subdiagonal entry above kbot -> ktop;
+//   - blocks of order 1 and 2 are finished directly (2x2 with real
+//     eigenvalues split by one rotation);
+//   - blocks small enough for one workgroup are finished by one full-window
+//     Schur kernel;
+//   - otherwise: AED on a trailing window, then (unless AED deflated enough)
+//     one multishift sweep with shifts taken from the undeflated window
+//     eigenvalues (exceptional shifts after 6 sweeps without deflation).
+// The host reads back a few integers and shifts per iteration.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "schur.hpp"
+
+#include <vector>
+#include <cmath>
+#include <algorithm>
+
+namespace sylv {
+
+template <typename T>
+size_t schur_work_bytes(int n) {
+    typedef SchurParams<T> P;
+    const int wmax = P::ADV + 3 * P::NB + 1;
+    const int wide = std::max(wmax, P::NSMALL);
+    size_t e = hessenberg_work_elems<T>(n, P::HNB, P::HS) + (size_t)P::NSMALL * P::NSMALL +
+               (size_t)wmax * wmax + (size_t)wide * n + 2 * (size_t)P::NSMALL + 2 * P::NB + 64;
+    return e * sizeof(T) + 1024 + 64 * sizeof(int);
+}
+template size_t schur_work_bytes<float>(int);
+template size_t schur_work_bytes<double>(int);
+
+namespace {
+
+template <typename T>
+struct Ctx {
+    hipStream_t s;
+    int n;
+    T *H;
+    int ldh;
+    T *U;
+    int ldu;
+    T *hw, *Zw, *Uw, *tmp, *wr, *wi, *trd;
+    int *dint;
+    char *hbuf;  // pinned host staging (>= 4 KiB)
+};
+
+template <typename T>
+void carve(Ctx<T> &c, char *ws) {
+    typedef SchurParams<T> P;
+    const int n = c.n;
+    const int wmax = P::ADV + 3 * P::NB + 1;
+    const int wide = std::max(wmax, P::NSMALL);
+    T *p = reinterpret_cast<T *>(ws);
+    c.hw = p; p += hessenberg_work_elems<T>(n, P::HNB, P::HS);
+    c.Zw = p; p += (size_t)P::NSMALL * P::NSMALL;
+    c.Uw = p; p += (size_t)wmax * wmax;
+    c.tmp = p; p += (size_t)wide * n;
+    c.wr = p; p += P::NSMALL;
+    c.wi = p; p += P::NSMALL;
+    c.trd = p; p += 2 * P::NB + 64;
+    size_t off = reinterpret_cast<char *>(p) - ws;
+    off = (off + 255) & ~(size_t)255;
+    c.dint = reinterpret_cast<int *>(ws + off);
+}
+
+template <typename T>
+hipError_t readback(Ctx<T> &c, const void *dsrc, size_t bytes) {
+    hipError_t e = hipMemcpyAsync(c.hbuf, dsrc, bytes, hipMemcpyDeviceToHost, c.s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c.s);
+}
+
+// Apply a window transform Z (w x w, ld w) acting on rows/cols [w0, w0+w):
+// H(w0:w0+w, w0+w:n) <- Z^T H(...), H(0:w0, w0:w0+w) <- H(...) Z,
+// U(:, w0:w0+w) <- U(...) Z.
+template <typename T>
+void apply_window(Ctx<T> &c, int w0, int w, const T *Z) {
+    const int n = c.n;
+    const int nc = n - (w0 + w);
+    if (nc > 0) {
+        T *blk = c.H + (size_t)(w0 + w) * c.ldh + w0;
+        gemm<T, T, T, T>(c.s, 1, 0, w, nc, w, T(1), Z, w, blk, c.ldh, T(0), c.tmp, w);
+        cast<T, T>(c.s, w, nc, c.tmp, w, blk, c.ldh, T(1));
+    }
+    if (w0 > 0) {
+        T *blk = c.H + (size_t)w0 * c.ldh;
+        gemm<T, T, T, T>(c.s, 0, 0, w0, w, w, T(1), blk, c.ldh, Z, w, T(0), c.tmp, w0);
+        cast<T, T>(c.s, w0, w, c.tmp, w0, blk, c.ldh, T(1));
+    }
+    T *ub = c.U + (size_t)w0 * c.ldu;
+    gemm<T, T, T, T>(c.s, 0, 0, n, w, w, T(1), ub, c.ldu, Z, w, T(0), c.tmp, n);
+    cast<T, T>(c.s, n, w, c.tmp, n, ub, c.ldu, T(1));
+}
+
+// Pair shifts (wr[i] + i wi[i]) into bulges: a complex pair -> (2 re, |s|^2);
+// two reals -> (s1 + s2, s1 s2).  Returns the (trace, det) list.
+template <typename T>
+void pair_shifts(const std::vector<double> &wr, const std::vector<double> &wi, int maxb,
+                 std::vector<T> &trd) {
+    trd.clear();
+    std::vector<double> reals;
+    // walk from the bottom (last entries are closest to kbot)
+    int i = (int)wr.size() - 1;
+    std::vector<std::pair<double, double>> bul;
+    while (i >= 0 && (int)bul.size() < maxb) {
+        if (wi[i] != 0.0 && i >= 1 && wi[i - 1] != 0.0) {
+            bul.push_back({2.0 * wr[i], wr[i] * wr[i] + wi[i] * wi[i]});
+            i -= 2;
+        } else if (wi[i] != 0.0) {
+            i -= 1;  // orphan half of a pair (cut window): skip
+        } else {
+            reals.push_back(wr[i]);
+            if (reals.size() == 2) {
+                bul.push_back({reals[0] + reals[1], reals[0] * reals[1]});
+                reals.clear();
+            }
+            i -= 1;
+        }
+    }
+    // the bulge introduced first should carry the shifts closest to the bottom
+    for (auto &b : bul) { trd.push_back((T)b.first); trd.push_back((T)b.second); }
+}
+
+}  // namespace
+
+template <typename T>
+int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char *hbuf,
+              int *qr_status) {
+    typedef SchurParams<T> P;
+    *qr_status = 0;
+    if (n <= 0) return 0;
+    Ctx<T> c{s, n, H, ldh, U, ldu};
+    c.hbuf = hbuf;
+    carve(c, ws);
+    hessenberg<T>(s, n, H, ldh, U, ldu, c.hw, P::HNB, P::HS);
+    int *hi = reinterpret_cast<int *>(c.hbuf);
+    hipError_t err;
+    int kbot = n - 1;
+    int ndfl = 1;
+    long iters = 0;
+    const long itmax = 100L + n / 2;  // AED + sweep rounds before giving up
+    std::vector<double> wr, wi;
+    std::vector<T> trd;
+    while (kbot >= 0) {
+        find_ktop<T>(s, H, ldh, 0, kbot, c.dint);
+        if ((err = readback(c, c.dint, sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+        const int ktop = hi[0];
+        const int N = kbot - ktop + 1;
+        if (N == 1) { kbot -= 1; ndfl = 1; continue; }
+        if (N == 2) { std2x2<T>(s, n, H, ldh, U, ldu, ktop); kbot -= 2; ndfl = 1; continue; }
+        if (++iters > itmax) { *qr_status = 1; break; }
+        if (N <= P::NSMALL) {
+            if (aed_launch<T>(s, N, H, ldh, ktop, 0, c.Zw, c.dint, c.wr, c.wi)) return -1;
+            if ((err = readback(c, c.dint, 4 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+            if (hi[0] != 0) { *qr_status = 1; break; }
+            apply_window(c, ktop, N, c.Zw);
+            kbot = ktop - 1;
+            ndfl = 1;
+            continue;
+        }
+        // aggressive early deflation on the trailing window
+        const int nw = std::min(P::NW, N - 1);
+        const int kwtop = kbot - nw + 1;
+        if (aed_launch<T>(s, nw, H, ldh, kwtop, 1, c.Zw, c.dint, c.wr, c.wi)) return -1;
+        if ((err = readback(c, c.dint, 4 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+        const int aed_st = hi[0], nd = hi[1], nsu = hi[2];
+        if (aed_st == 0) apply_window(c, kwtop, nw, c.Zw);
+        // shift candidates: eigenvalues of the undeflated part of the window
+        wr.clear(); wi.clear();
+        if (aed_st == 0 && nsu > 0) {
+            hipMemcpyAsync(c.hbuf, c.wr, sizeof(T) * nsu, hipMemcpyDeviceToHost, s);
+            hipMemcpyAsync(c.hbuf + sizeof(T) * nsu, c.wi, sizeof(T) * nsu, hipMemcpyDeviceToHost, s);
+            if ((err = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+            const T *hv = reinterpret_cast<const T *>(c.hbuf);
+            for (int i = 0; i < nsu; ++i) { wr.push_back(hv[i]); wi.push_back(hv[nsu + i]); }
+        }
+        const int ndef = (aed_st == 0) ? nd : 0;
+        kbot -= ndef;
+        ndfl = (ndef > 0) ? 1 : ndfl + 1;
+        // skip the sweep if AED deflated a good share of the window
+        if (ndef > 0 && 100 * ndef > 14 * nw) continue;
+        if (kbot - ktop + 1 <= P::NSMALL) continue;
+        const int N2 = kbot - ktop + 1;
+        const int maxb = std::min(P::NB, (N2 - 2) / 6 > 1 ? (N2 - 2) / 6 : 1);
+        if (ndfl % 6 == 0 || wr.size() < 2) {
+            // exceptional shifts from the trailing subdiagonal magnitudes
+            const int cnt = 2 * maxb + 2;
+            std::vector<T> dd(2 * (size_t)cnt);
+            // gather H(i,i) and H(i,i-1) for i in [kbot-cnt+1, kbot]
+            int i0 = std::max(ktop + 2, kbot - cnt + 1);
+            int m = kbot - i0 + 1;
+            for (int q = 0; q < m; ++q) {
+                hipMemcpyAsync(c.hbuf + sizeof(T) * (2 * q), H + (size_t)(i0 + q) * ldh + (i0 + q),
+                               sizeof(T), hipMemcpyDeviceToHost, s);
+                hipMemcpyAsync(c.hbuf + sizeof(T) * (2 * q + 1), H + (size_t)(i0 + q - 1) * ldh + (i0 + q),
+                               sizeof(T), hipMemcpyDeviceToHost, s);
+            }
+            // also H(i0-1, i0-2)
+            hipMemcpyAsync(c.hbuf + sizeof(T) * (2 * m), H + (size_t)(i0 - 2) * ldh + (i0 - 1), sizeof(T),
+                           hipMemcpyDeviceToHost, s);
+            if ((err = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+            const T *hv = reinterpret_cast<const T *>(c.hbuf);
+            trd.clear();
+            for (int q = m - 1; q >= 1 && (int)trd.size() < 2 * maxb; q -= 2) {
+                double sub_i = std::fabs((double)hv[2 * q + 1]);
+                double sub_im1 = std::fabs((double)hv[2 * (q - 1) + 1]);
+                double ss = sub_i + sub_im1;
+                double aa = 0.75 * ss + (double)hv[2 * q];
+                trd.push_back((T)(2.0 * aa));
+                trd.push_back((T)(aa * aa + 0.4375 * ss * ss));
+            }
+            if (trd.empty()) {
+                double ss = std::fabs((double)hv[2 * m]);
+                double aa = 0.75 * ss + (double)hv[2 * (m - 1)];
+                trd.push_back((T)(2.0 * aa));
+                trd.push_back((T)(aa * aa + 0.4375 * ss * ss));
+            }
+        } else {
+            pair_shifts<T>(wr, wi, maxb, trd);
+        }
+        const int nb = (int)trd.size() / 2;
+        if (nb == 0) continue;
+        T *htrd = reinterpret_cast<T *>(c.hbuf + 4096);
+        for (size_t q = 0; q < trd.size(); ++q) htrd[q] = trd[q];
+        hipMemcpyAsync(c.trd, htrd, sizeof(T) * trd.size(), hipMemcpyHostToDevice, s);
+        // multishift sweep over [ktop, kbot]
+        const int ttot = (N2 - 2) + 3 * (nb - 1) + 1;
+        for (int t0 = 0; t0 < ttot; t0 += P::ADV) {
+            const int t1 = std::min(t0 + P::ADV, ttot);
+            const int pmin = std::max(0, t0 - 3 * (nb - 1));
+            const int pmax = std::min(N2 - 2, t1 - 1);
+            if (pmax < pmin) continue;
+            const int ws_ = ktop + std::max(0, pmin - 1);
+            const int we_ = ktop + std::min(N2, pmax + 4);
+            const int W = we_ - ws_;
+            if (chase_launch<T>(s, H, ldh, ktop, kbot, ws_, W, t0, t1 - t0, nb, c.trd, c.Uw)) return -1;
+            apply_window(c, ws_, W, c.Uw);
+        }
+        // the pinned copy of the shifts must stay valid until the upload ran
+        if ((err = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+    }
+    clean_lower<T>(s, n, H, ldh);
+    return 0;
+}
+template int schur_run<float>(hipStream_t, int, float *, int, float *, int, char *, char *, int *);
+template int schur_run<double>(hipStream_t, int, double *, int, double *, int, char *, char *, int *);
+
+}  // namespace sylv

@@ -1,0 +1,710 @@
+// Solver orchestration and the C ABI of libsylv.so.
+//
+// sylv_solve / lyap_solve run, on one GPU:
+//   low precision (binary32):  Schur(A), Schur(B) -> first iterate by the
+//       Bartels-Stewart transform / tri-solve / back-transform (Sec. 2.2.1);
+//   refinement (Alg. 3.1 in the original basis): R = C - AX - XB in binary64
+//       against the original coefficients, correction D from the binary32
+//       Schur factors (U^T R V -> tri-solve -> U D V^T), X += D in binary64,
+//       until the relative residual of eq. (2.1) is below tol;
+//   fallback / baseline: the same stages instantiated in binary64 (plain
+//       Bartels-Stewart).
+// Lyapunov (eq. (1.3), real): one Schur form A = U T U^T; the right
+// coefficient T^T is lower quasi-triangular, so the tri-solve is run on the
+// equivalent upper form T Y' + Y' (P T^T P) = C~ P with P the reversal
+// permutation, i.e. with V = U P.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "schur.hpp"
+#include "../../include/sylv.h"
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+#include <algorithm>
+
+namespace sylv {
+
+// ------------------------------------------------------------ device context
+struct DevCtx {
+    bool ok = false;
+    bool checked = false;
+    char *hbuf = nullptr;       // pinned host staging, 64 KiB
+    void *work = nullptr;       // cached internal workspace
+    size_t work_bytes = 0;
+};
+
+static std::mutex g_mu;
+static DevCtx g_ctx[64];
+
+static int device_ctx(DevCtx **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SYLV_ERR_NOGPU;
+    DevCtx &c = g_ctx[dev];
+    if (!c.checked) {
+        c.checked = true;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return SYLV_ERR_NOGPU;
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SYLV_ERR_NOGPU;
+        if (hipHostMalloc((void **)&c.hbuf, 65536, hipHostMallocDefault) != hipSuccess) return SYLV_ERR_ALLOC;
+        c.ok = true;
+    }
+    if (!c.ok) return SYLV_ERR_NOGPU;
+    *out = &c;
+    return 0;
+}
+
+static int ensure_work(DevCtx *c, size_t bytes, void **out) {
+    if (c->work_bytes < bytes) {
+        if (c->work) hipFree(c->work);
+        c->work = nullptr;
+        c->work_bytes = 0;
+        if (hipMalloc(&c->work, bytes) != hipSuccess) return SYLV_ERR_ALLOC;
+        c->work_bytes = bytes;
+    }
+    *out = c->work;
+    return 0;
+}
+
+// ----------------------------------------------------------- workspace plan
+struct Arena {
+    char *base;
+    size_t off = 0;
+    explicit Arena(void *b) : base((char *)b) {}
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+template <typename T>
+struct Stage {  // buffers of one precision's Bartels-Stewart pipeline
+    T *TA, *UA, *TB, *UB, *W1, *Y;
+    char *schur_ws;
+};
+
+struct Plan {
+    Stage<float> lo;
+    Stage<double> hi;
+    double *R;        // m x n residual
+    double *G;        // orthogonality check scratch, 2 * max(m,n)^2
+    double *scal;     // 64 device scalars
+    double *nscr;     // 256-entry reduction scratch
+    int *flag;        // tri-solve perturbation flag
+    float *eig;       // eigenvalue scratch for sep_est (4 * max(m,n))
+};
+
+static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth, Plan &p) {
+    const int mx = std::max(m, n);
+    std::memset(&p, 0, sizeof(p));
+    if (need_lo) {
+        p.lo.TA = a.take<float>((size_t)m * m);
+        p.lo.UA = a.take<float>((size_t)m * m);
+        p.lo.TB = a.take<float>((size_t)n * n);
+        p.lo.UB = a.take<float>((size_t)n * n);
+        p.lo.W1 = a.take<float>((size_t)m * n);
+        p.lo.Y = a.take<float>((size_t)m * n);
+        p.lo.schur_ws = a.take<char>(schur_work_bytes<float>(mx));
+    }
+    if (need_hi) {
+        p.hi.TA = a.take<double>((size_t)m * m);
+        p.hi.UA = a.take<double>((size_t)m * m);
+        p.hi.TB = a.take<double>((size_t)n * n);
+        p.hi.UB = a.take<double>((size_t)n * n);
+        p.hi.W1 = a.take<double>((size_t)m * n);
+        p.hi.Y = a.take<double>((size_t)m * n);
+        p.hi.schur_ws = a.take<char>(schur_work_bytes<double>(mx));
+    }
+    p.R = a.take<double>((size_t)m * n);
+    if (orth) p.G = a.take<double>((size_t)2 * mx * mx);
+    p.scal = a.take<double>(64);
+    p.nscr = a.take<double>(256);
+    p.flag = a.take<int>(64);
+    p.eig = a.take<float>((size_t)4 * mx + 64);
+    (void)lyap;
+}
+
+static size_t plan_bytes(int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth) {
+    Arena a(nullptr);
+    Plan p;
+    plan(a, m, n, lyap, need_lo, need_hi, orth, p);
+    return a.off + 256;
+}
+
+// --------------------------------------------------------------- kernels
+// eigenvalues of an upper quasi-triangular float/double matrix -> (wr, wi)
+template <typename T>
+__global__ void k_quasi_eigs(int n, const T *Tm, int ld, float *wr, float *wi) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        bool lower = (i > 0) && CM(Tm, i, i - 1, ld) != T(0);
+        bool upper = (i + 1 < n) && CM(Tm, i + 1, i, ld) != T(0);
+        if (!lower && !upper) { wr[i] = (float)CM(Tm, i, i, ld); wi[i] = 0.f; continue; }
+        int k = upper ? i : i - 1;
+        double a = CM(Tm, k, k, ld), b = CM(Tm, k, k + 1, ld), c = CM(Tm, k + 1, k, ld), d = CM(Tm, k + 1, k + 1, ld);
+        double p = 0.5 * (a - d), disc = p * p + b * c, mid = 0.5 * (a + d);
+        if (disc >= 0) { double r = sqrt(disc); wr[i] = (float)(upper ? mid + r : mid - r); wi[i] = 0.f; }
+        else { double r = sqrt(-disc); wr[i] = (float)mid; wi[i] = (float)(upper ? r : -r); }
+    }
+}
+
+// min over i, j of |lambda_i + mu_j|
+__global__ __launch_bounds__(256) void k_sep_min(int m, int n, const float *wra, const float *wia,
+                                                 const float *wrb, const float *wib, double *out) {
+    __shared__ double red[256];
+    double best = 1e300;
+    size_t total = (size_t)m * n;
+    for (size_t e = threadIdx.x; e < total; e += 256) {
+        int i = (int)(e % m), j = (int)(e / m);
+        double re = (double)wra[i] + wrb[j], im = (double)wia[i] + wib[j];
+        best = fmin(best, sqrt(re * re + im * im));
+    }
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// -------------------------------------------------------- pipeline stages
+template <typename T>
+static int schur_stage(hipStream_t s, int n, const double *A, int lda, Stage<T> &st, T *Tm, T *Um,
+                       char *hbuf, int *qr) {
+    cast<double, T>(s, n, n, A, lda, Tm, n, 1.0);
+    return schur_run<T>(s, n, Tm, n, Um, n, st.schur_ws, hbuf, qr);
+}
+
+// Lyapunov: TB = P TA^T P, UB = UA P
+template <typename T>
+static void lyap_right_factor(hipStream_t s, int n, Stage<T> &st) {
+    transpose<T>(s, n, n, st.TA, n, st.TB, n, 1);
+    revcols<T, T>(s, n, n, st.UA, n, st.UB, n, T(1));
+}
+
+// X (binary64) <- alpha * UA * tri-solve(UA^T op(Rin) UB) * UB^T (+ X when accumulate)
+// Rin is binary64 (C or the residual); bscale scales it before the cast.
+template <typename T>
+static void correction(hipStream_t s, int m, int n, Stage<T> &st, const double *Rin, int ldr,
+                       double bscale, double *X, int ldx, bool accumulate, const double *maxab,
+                       int *flag);
+
+template <>
+void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const double *Rin, int ldr,
+                       double bscale, double *X, int ldx, bool accumulate, const double *maxab,
+                       int *flag) {
+    gemm<float, double, float, float>(s, 1, 0, m, n, m, 1.0f, st.UA, m, Rin, ldr, 0.0f, st.W1, m, bscale);
+    gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0f, st.W1, m, st.UB, n, 0.0f, st.Y, m);
+    trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
+    gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0f, st.UA, m, st.Y, m, 0.0f, st.W1, m);
+    gemm<float, float, double, float>(s, 0, 1, m, n, n, (float)(1.0 / bscale), st.W1, m, st.UB, n,
+                                      accumulate ? 1.0f : 0.0f, X, ldx);
+}
+
+template <>
+void correction<double>(hipStream_t s, int m, int n, Stage<double> &st, const double *Rin, int ldr,
+                        double bscale, double *X, int ldx, bool accumulate, const double *maxab,
+                        int *flag) {
+    gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0, st.W1, m, bscale);
+    gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0, st.Y, m);
+    trsyl<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
+    gemm<double, double, double, double>(s, 0, 0, m, n, m, 1.0, st.UA, m, st.Y, m, 0.0, st.W1, m);
+    gemm<double, double, double, double>(s, 0, 1, m, n, n, 1.0 / bscale, st.W1, m, st.UB, n,
+                                         accumulate ? 1.0 : 0.0, X, ldx);
+}
+
+// R = C - A X - X op(B); scal[slot] = ||R||_F, scal[slot+1] = max|R|, scal[slot+2] = ||X||_F
+static void residual(hipStream_t s, int m, int n, const double *A, int lda, const double *B, int ldb,
+                     bool lyap, const double *C, int ldc, const double *X, int ldx, double *R,
+                     double *scal, double *nscr) {
+    cast<double, double>(s, m, n, C, ldc, R, m, 1.0);
+    gemm<double, double, double, double>(s, 0, 0, m, n, m, -1.0, A, lda, X, ldx, 1.0, R, m);
+    if (lyap) gemm<double, double, double, double>(s, 0, 1, m, n, n, -1.0, X, ldx, A, lda, 1.0, R, m);
+    else gemm<double, double, double, double>(s, 0, 0, m, n, n, -1.0, X, ldx, B, ldb, 1.0, R, m);
+    matnorm<double>(s, m, n, R, m, scal + 0, nscr, 0);
+    matnorm<double>(s, m, n, R, m, scal + 1, nscr, 1);
+    matnorm<double>(s, m, n, X, ldx, scal + 2, nscr, 0);
+}
+
+static hipError_t read_scalars(hipStream_t s, DevCtx *c, const double *d, int cnt, double *h) {
+    hipError_t e = hipMemcpyAsync(c->hbuf, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    std::memcpy(h, c->hbuf, sizeof(double) * cnt);
+    return hipSuccess;
+}
+
+// ||U^T U - I||_F in binary64 for a float U (n x n)
+static void orth_check(hipStream_t s, int n, const float *U, double *G, double *out, double *nscr) {
+    double *Ud = G, *Gm = G + (size_t)n * n;
+    cast<float, double>(s, n, n, U, n, Ud, n, 1.0f);
+    gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, Ud, n, Ud, n, 0.0, Gm, n);
+    sub_identity(s, n, Gm, n);
+    matnorm<double>(s, n, n, Gm, n, out, nscr, 0);
+}
+
+template <typename T>
+static void sep_estimate(hipStream_t s, int m, int n, const T *TA, const T *TB, float *eig, double *out) {
+    float *wra = eig, *wia = eig + m, *wrb = eig + 2 * m, *wib = eig + 2 * m + n;
+    hipLaunchKernelGGL((k_quasi_eigs<T>), dim3((m + 255) / 256), dim3(256), 0, s, m, TA, m, wra, wia);
+    hipLaunchKernelGGL((k_quasi_eigs<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, TB, n, wrb, wib);
+    hipLaunchKernelGGL(k_sep_min, dim3(1), dim3(256), 0, s, m, n, wra, wia, wrb, wib, out);
+}
+
+// --------------------------------------------------------------- drivers
+struct Norms { double a, b, c; };
+
+// Plain binary64 Bartels-Stewart on the GPU.  Returns ABI code; fills info.
+static int run_fp64(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda, const double *B,
+                    int ldb, bool lyap, const double *C, int ldc, double *X, int ldx, Plan &p,
+                    const Norms &nm, sylv_info *info) {
+    int qa = 0, qb = 0, rc;
+    rc = schur_stage<double>(s, m, A, lda, p.hi, p.hi.TA, p.hi.UA, c->hbuf, &qa);
+    if (rc) return rc;
+    if (lyap) lyap_right_factor<double>(s, m, p.hi);
+    else {
+        rc = schur_stage<double>(s, n, B, ldb, p.hi, p.hi.TB, p.hi.UB, c->hbuf, &qb);
+        if (rc) return rc;
+    }
+    matnorm<double>(s, m, m, p.hi.TA, m, p.scal + 10, p.nscr, 1);
+    matnorm<double>(s, n, n, p.hi.TB, n, p.scal + 11, p.nscr, 1);
+    // maxab = max of both (computed on device by a max-norm over the two slots)
+    matnorm<double>(s, 2, 1, p.scal + 10, 2, p.scal + 12, p.nscr, 1);
+    hipMemsetAsync(p.flag, 0, sizeof(int), s);
+    correction<double>(s, m, n, p.hi, C, ldc, 1.0, X, ldx, false, p.scal + 12, p.flag);
+    sep_estimate<double>(s, m, n, p.hi.TA, p.hi.TB, p.eig, p.scal + 13);
+    residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr);
+    double h[16];
+    hipError_t e = read_scalars(s, c, p.scal, 16, h);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    int flag = 0;
+    hipMemcpy(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (info) {
+        info->rel_res = h[0] / (nm.c + h[2] * (nm.a + nm.b));
+        info->orth_u = 0.0;
+        info->orth_v = 0.0;
+        info->sep_est = h[13];
+        info->corr_ratio = 0.0;
+        info->iterations = 0;
+        info->precision_used = SYLV_PREC_FP64;
+        info->status = (qa || qb) ? SYLV_ST_QR_FAILED
+                       : (!(std::isfinite(info->rel_res))) ? SYLV_ST_NAN
+                       : flag ? SYLV_ST_PERTURBED : SYLV_OK;
+    }
+    return 0;
+}
+
+// binary32 factors + binary64 refinement.  *ok = 1 on convergence.
+static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
+                     const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
+                     int ldx, Plan &p, const Norms &nm, const sylv_opts &o, sylv_info *info,
+                     int *ok) {
+    *ok = 0;
+    int qa = 0, qb = 0, rc;
+    rc = schur_stage<float>(s, m, A, lda, p.lo, p.lo.TA, p.lo.UA, c->hbuf, &qa);
+    if (rc) return rc;
+    if (lyap) lyap_right_factor<float>(s, m, p.lo);
+    else {
+        rc = schur_stage<float>(s, n, B, ldb, p.lo, p.lo.TB, p.lo.UB, c->hbuf, &qb);
+        if (rc) return rc;
+    }
+    if (o.orth_check) {
+        orth_check(s, m, p.lo.UA, p.G, p.scal + 20, p.nscr);
+        if (!lyap) orth_check(s, n, p.lo.UB, p.G, p.scal + 21, p.nscr);
+    }
+    matnorm<float>(s, m, m, p.lo.TA, m, p.scal + 10, p.nscr, 1);
+    matnorm<float>(s, n, n, p.lo.TB, n, p.scal + 11, p.nscr, 1);
+    matnorm<double>(s, 2, 1, p.scal + 10, 2, p.scal + 12, p.nscr, 1);
+    sep_estimate<float>(s, m, n, p.lo.TA, p.lo.TB, p.eig, p.scal + 13);
+    hipMemsetAsync(p.flag, 0, sizeof(int), s);
+    // first iterate: X0 = U Y V^T from the binary32 factors
+    correction<float>(s, m, n, p.lo, C, ldc, 1.0, X, ldx, false, p.scal + 12, p.flag);
+    double prev = INFINITY, rel = INFINITY, corr = 0.0;
+    int it = 0, stall = 0, status = SYLV_ST_NOT_CONVERGED;
+    double h[32];
+    for (;;) {
+        residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr);
+        hipError_t e = read_scalars(s, c, p.scal, 32, h);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        rel = h[0] / (nm.c + h[2] * (nm.a + nm.b));
+        if (!std::isfinite(rel)) { status = SYLV_ST_NAN; break; }
+        if (rel <= o.tol) { status = SYLV_OK; break; }
+        if (it >= o.max_iter) break;
+        if (rel > 0.5 * prev) { if (++stall >= 2) break; } else stall = 0;
+        prev = rel;
+        // scale R by 2^-e so that max|R| is O(1) before the binary32 cast
+        int ex = 0;
+        std::frexp(h[1] > 0 ? h[1] : 1.0, &ex);
+        double sc = std::ldexp(1.0, -ex);
+        correction<float>(s, m, n, p.lo, p.R, m, sc, X, ldx, true, p.scal + 12, p.flag);
+        // ||D||_F ~ ||Y||_F / sc (orthogonal factors to binary32 accuracy)
+        matnorm<float>(s, m, n, p.lo.Y, m, p.scal + 30, p.nscr, 0);
+        ++it;
+        double hy;
+        e = read_scalars(s, c, p.scal + 30, 1, &hy);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        corr = hy / sc;
+    }
+    int flag = 0;
+    hipMemcpy(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (qa || qb) status = (status == SYLV_OK) ? SYLV_OK : SYLV_ST_QR_FAILED;
+    if (status == SYLV_OK && flag) status = SYLV_ST_PERTURBED;
+    *ok = (status == SYLV_OK || status == SYLV_ST_PERTURBED) ? 1 : 0;
+    if (info) {
+        info->rel_res = rel;
+        info->orth_u = o.orth_check ? h[20] : 0.0;
+        info->orth_v = o.orth_check ? (lyap ? h[20] : h[21]) : 0.0;
+        info->sep_est = h[13];
+        info->corr_ratio = (h[2] > 0) ? corr / h[2] : 0.0;
+        info->iterations = it;
+        info->precision_used = SYLV_PREC_FP32;
+        info->status = status;
+    }
+    return 0;
+}
+
+static int solve_common_impl(int m, int n, const double *A, int lda, const double *B, int ldb,
+                        const double *C, int ldc, double *X, int ldx, bool lyap,
+                        const sylv_opts *opts, sylv_info *info, void *work, size_t work_bytes,
+                        void *stream) {
+    sylv_opts o;
+    sylv_default_opts(&o);
+    if (opts) o = *opts;
+    // argument checks (ABI: -i for the i-th argument)
+    if (m < 0) return -1;
+    if (!lyap && n < 0) return -2;
+    if (lyap) n = m;
+    const int ai = lyap ? 2 : 3;  // position of A
+    if (lda < std::max(1, m)) return -(ai + 1);
+    if (!lyap && ldb < std::max(1, n)) return -6;
+    const int ci = lyap ? 4 : 7;
+    if (ldc < std::max(1, m)) return -(ci + 1);
+    if (ldx < std::max(1, m)) return -(ci + 3);
+    if (m > 0 && (A == nullptr)) return -ai;
+    if (!lyap && n > 0 && B == nullptr) return -5;
+    if (m > 0 && n > 0 && (C == nullptr)) return -ci;
+    if (m > 0 && n > 0 && (X == nullptr)) return -(ci + 2);
+    if (o.low != SYLV_PREC_FP64 && o.low != SYLV_PREC_FP32) return -(ci + 4);
+    if (!(o.tol >= 0.0) || o.max_iter < 0) return -(ci + 4);
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (m == 0 || n == 0) {
+        if (info) info->precision_used = o.low;
+        return 0;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *c = nullptr;
+    int rc = device_ctx(&c);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool mixed = o.low != SYLV_PREC_FP64;
+    const bool need_hi = !mixed || o.fallback;
+    const size_t need = plan_bytes(m, n, lyap, mixed, need_hi, mixed && o.orth_check);
+    void *base = work;
+    if (work) {
+        if (work_bytes < need) return lyap ? -11 : -15;
+    } else {
+        rc = ensure_work(c, need, &base);
+        if (rc) return rc;
+    }
+    Arena ar(base);
+    Plan p;
+    plan(ar, m, n, lyap, mixed, need_hi, mixed && o.orth_check, p);
+    // norms of the coefficients (eq. (2.1) denominators)
+    matnorm<double>(s, m, m, A, lda, p.scal + 40, p.nscr, 0);
+    if (!lyap) matnorm<double>(s, n, n, B, ldb, p.scal + 41, p.nscr, 0);
+    matnorm<double>(s, m, n, C, ldc, p.scal + 42, p.nscr, 0);
+    double hn[3];
+    hipError_t e = read_scalars(s, c, p.scal + 40, 3, hn);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2]};
+    if (!mixed) return run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, info);
+    int ok = 0;
+    rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
+    if (rc) return rc;
+    if (!ok && o.fallback) {
+        sylv_info keep;
+        if (info) keep = *info;
+        rc = run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, info);
+        if (rc) return rc;
+        if (info) {
+            info->fell_back = 1;
+            info->iterations = keep.iterations;
+            info->orth_u = keep.orth_u;
+            info->orth_v = keep.orth_v;
+        }
+    }
+    return 0;
+}
+
+// Runs the solve and converts any pending HIP error (launch failures are
+// reported asynchronously through hipGetLastError) into an ABI code, so no
+// error is left behind for the caller's next HIP call.
+static int solve_common(int m, int n, const double *A, int lda, const double *B, int ldb,
+                        const double *C, int ldc, double *X, int ldx, bool lyap,
+                        const sylv_opts *opts, sylv_info *info, void *work, size_t work_bytes,
+                        void *stream) {
+    int rc = solve_common_impl(m, n, A, lda, B, ldb, C, ldc, X, ldx, lyap, opts, info, work,
+                               work_bytes, stream);
+    hipError_t e = hipGetLastError();
+    if (rc == 0 && e != hipSuccess) rc = SYLV_ERR_HIP - (int)e;
+    if (rc == -1 && m >= 0) rc = SYLV_ERR_HIP;  // internal launch failure
+    return rc;
+}
+
+}  // namespace sylv
+
+using namespace sylv;
+
+extern "C" {
+
+void sylv_default_opts(sylv_opts *o) {
+    if (!o) return;
+    o->low = SYLV_PREC_FP32;
+    o->tol = 1e-14;
+    o->max_iter = 20;
+    o->fallback = 1;
+    o->orth_check = 1;
+}
+
+size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
+    sylv_opts o;
+    sylv_default_opts(&o);
+    if (opts) o = *opts;
+    if (m < 0 || (!lyap && n < 0)) return 0;
+    if (lyap) n = m;
+    const bool mixed = o.low != SYLV_PREC_FP64;
+    return plan_bytes(m, n, lyap != 0, mixed, !mixed || o.fallback, mixed && o.orth_check);
+}
+
+int sylv_solve(int m, int n, const double *A, int lda, const double *B, int ldb, const double *C,
+               int ldc, double *X, int ldx, const sylv_opts *opts, sylv_info *info, void *work,
+               size_t work_bytes, void *stream) {
+    try {
+        return solve_common(m, n, A, lda, B, ldb, C, ldc, X, ldx, false, opts, info, work, work_bytes,
+                            stream);
+    } catch (const std::bad_alloc &) {
+        return SYLV_ERR_ALLOC;
+    }
+}
+
+int lyap_solve(int n, const double *A, int lda, const double *C, int ldc, double *X, int ldx,
+               const sylv_opts *opts, sylv_info *info, void *work, size_t work_bytes, void *stream) {
+    try {
+        return solve_common(n, n, A, lda, nullptr, 1, C, ldc, X, ldx, true, opts, info, work,
+                            work_bytes, stream);
+    } catch (const std::bad_alloc &) {
+        return SYLV_ERR_ALLOC;
+    }
+}
+
+const char *sylv_status_string(int code) {
+    switch (code) {
+        case SYLV_OK: return "ok";
+        case SYLV_ST_PERTURBED: return "near-singular pivot perturbed in the quasi-triangular solve";
+        case SYLV_ST_NOT_CONVERGED: return "refinement did not reach the tolerance";
+        case SYLV_ST_NAN: return "NaN or Inf encountered";
+        case SYLV_ST_QR_FAILED: return "QR algorithm iteration cap reached";
+        case SYLV_ERR_ALLOC: return "device allocation failed";
+        case SYLV_ERR_NOGPU: return "no gfx950 device";
+        default:
+            if (code <= SYLV_ERR_HIP && code > SYLV_ERR_ALLOC) return "HIP runtime error";
+            if (code < 0) return "invalid argument";
+            return "unknown status";
+    }
+}
+
+// ---------------------------------------------------------- stage entry points
+int sylv_schur(int n, const void *A, int lda, void *T, int ldt, void *U, int ldu, int prec,
+               int *status, void *stream) {
+    if (n < 0) return -1;
+    if (lda < std::max(1, n)) return -3;
+    if (ldt < std::max(1, n)) return -5;
+    if (ldu < std::max(1, n)) return -7;
+    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -8;
+    if (n > 0 && (!A || !T || !U)) return !A ? -2 : (!T ? -4 : -6);
+    if (status) *status = 0;
+    if (n == 0) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *c = nullptr;
+    int rc = device_ctx(&c);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool f = prec == SYLV_PREC_FP32;
+    const size_t es = f ? sizeof(float) : sizeof(double);
+    size_t bytes = ((size_t)2 * n * n * es + 1024) + (f ? schur_work_bytes<float>(n) : schur_work_bytes<double>(n));
+    void *base;
+    rc = ensure_work(c, bytes, &base);
+    if (rc) return rc;
+    char *H = (char *)base;
+    char *Uc = H + (((size_t)n * n * es + 255) & ~(size_t)255);
+    char *ws = Uc + (((size_t)n * n * es + 255) & ~(size_t)255);
+    int qr = 0;
+    if (f) {
+        cast<float, float>(s, n, n, (const float *)A, lda, (float *)H, n, 1.0f);
+        rc = schur_run<float>(s, n, (float *)H, n, (float *)Uc, n, ws, c->hbuf, &qr);
+        if (!rc) {
+            cast<float, float>(s, n, n, (const float *)H, n, (float *)T, ldt, 1.0f);
+            cast<float, float>(s, n, n, (const float *)Uc, n, (float *)U, ldu, 1.0f);
+        }
+    } else {
+        cast<double, double>(s, n, n, (const double *)A, lda, (double *)H, n, 1.0);
+        rc = schur_run<double>(s, n, (double *)H, n, (double *)Uc, n, ws, c->hbuf, &qr);
+        if (!rc) {
+            cast<double, double>(s, n, n, (const double *)H, n, (double *)T, ldt, 1.0);
+            cast<double, double>(s, n, n, (const double *)Uc, n, (double *)U, ldu, 1.0);
+        }
+    }
+    if (rc) { (void)hipGetLastError(); return rc < 0 && rc > -100 ? SYLV_ERR_HIP : rc; }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    if (status) *status = qr ? SYLV_ST_QR_FAILED : SYLV_OK;
+    return 0;
+}
+
+int sylv_trsyl(int m, int n, const void *TA, int ldta, const void *TB, int ldtb, int trans_b, void *Cp,
+               int ldc, int prec, int *perturbed, void *stream) {
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (ldta < std::max(1, m)) return -4;
+    if (ldtb < std::max(1, n)) return -6;
+    if (ldc < std::max(1, m)) return -9;
+    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -10;
+    if (m > 0 && !TA) return -3;
+    if (n > 0 && !TB) return -5;
+    if (m > 0 && n > 0 && !Cp) return -8;
+    if (perturbed) *perturbed = 0;
+    if (m == 0 || n == 0) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *c = nullptr;
+    int rc = device_ctx(&c);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool f = prec == SYLV_PREC_FP32;
+    const size_t es = f ? sizeof(float) : sizeof(double);
+    // scratch: reversed TB (trans_b), reversed C, scalars
+    size_t bytes = (size_t)n * n * es + (size_t)m * n * es + 8192;
+    void *base;
+    rc = ensure_work(c, bytes, &base);
+    if (rc) return rc;
+    char *TBr = (char *)base;
+    char *Cr = TBr + (((size_t)n * n * es + 255) & ~(size_t)255);
+    double *scal = (double *)(Cr + (((size_t)m * n * es + 255) & ~(size_t)255));
+    double *nscr = scal + 8;
+    int *flag = (int *)(nscr + 256);
+    hipMemsetAsync(flag, 0, sizeof(int), s);
+    if (f) {
+        const float *ta = (const float *)TA, *tb = (const float *)TB;
+        matnorm<float>(s, m, m, ta, ldta, scal + 0, nscr, 1);
+        matnorm<float>(s, n, n, tb, ldtb, scal + 1, nscr, 1);
+        matnorm<double>(s, 2, 1, scal, 2, scal + 2, nscr, 1);
+        if (!trans_b) trsyl<float>(s, m, n, ta, ldta, tb, ldtb, (float *)Cp, ldc, scal + 2, flag);
+        else {
+            transpose<float>(s, n, n, tb, ldtb, (float *)TBr, n, 1);
+            revcols<float, float>(s, m, n, (const float *)Cp, ldc, (float *)Cr, m, 1.0f);
+            trsyl<float>(s, m, n, ta, ldta, (const float *)TBr, n, (float *)Cr, m, scal + 2, flag);
+            revcols<float, float>(s, m, n, (const float *)Cr, m, (float *)Cp, ldc, 1.0f);
+        }
+    } else {
+        const double *ta = (const double *)TA, *tb = (const double *)TB;
+        matnorm<double>(s, m, m, ta, ldta, scal + 0, nscr, 1);
+        matnorm<double>(s, n, n, tb, ldtb, scal + 1, nscr, 1);
+        matnorm<double>(s, 2, 1, scal, 2, scal + 2, nscr, 1);
+        if (!trans_b) trsyl<double>(s, m, n, ta, ldta, tb, ldtb, (double *)Cp, ldc, scal + 2, flag);
+        else {
+            transpose<double>(s, n, n, tb, ldtb, (double *)TBr, n, 1);
+            revcols<double, double>(s, m, n, (const double *)Cp, ldc, (double *)Cr, m, 1.0);
+            trsyl<double>(s, m, n, ta, ldta, (const double *)TBr, n, (double *)Cr, m, scal + 2, flag);
+            revcols<double, double>(s, m, n, (const double *)Cr, m, (double *)Cp, ldc, 1.0);
+        }
+    }
+    int hf = 0;
+    hipError_t e = hipMemcpyAsync(c->hbuf, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    std::memcpy(&hf, c->hbuf, sizeof(int));
+    if (perturbed) *perturbed = hf;
+    e = hipGetLastError();
+    return e == hipSuccess ? 0 : SYLV_ERR_HIP - (int)e;
+}
+
+int sylv_residual(int m, int n, const double *A, int lda, const double *B, int ldb, const double *C,
+                  int ldc, const double *X, int ldx, double *R, int ldr, int lyap, double *rel_res,
+                  void *stream) {
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (lyap && n != m) return -2;
+    if (lda < std::max(1, m)) return -4;
+    if (!lyap && ldb < std::max(1, n)) return -6;
+    if (ldc < std::max(1, m)) return -8;
+    if (ldx < std::max(1, m)) return -10;
+    if (R && ldr < std::max(1, m)) return -12;
+    if (m > 0 && !A) return -3;
+    if (!lyap && n > 0 && !B) return -5;
+    if (m > 0 && n > 0 && (!C || !X)) return !C ? -7 : -9;
+    if (rel_res) *rel_res = 0.0;
+    if (m == 0 || n == 0) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *c = nullptr;
+    int rc = device_ctx(&c);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    size_t bytes = (size_t)m * n * sizeof(double) + 8192;
+    void *base;
+    rc = ensure_work(c, bytes, &base);
+    if (rc) return rc;
+    double *Rw = (double *)base;
+    double *scal = (double *)((char *)base + (((size_t)m * n * sizeof(double) + 255) & ~(size_t)255));
+    double *nscr = scal + 16;
+    residual(s, m, n, A, lda, B, ldb, lyap != 0, C, ldc, X, ldx, Rw, scal, nscr);
+    matnorm<double>(s, m, m, A, lda, scal + 4, nscr, 0);
+    if (!lyap) matnorm<double>(s, n, n, B, ldb, scal + 5, nscr, 0);
+    matnorm<double>(s, m, n, C, ldc, scal + 6, nscr, 0);
+    if (R) cast<double, double>(s, m, n, Rw, m, R, ldr, 1.0);
+    double h[8];
+    hipError_t e = read_scalars(s, c, scal, 8, h);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    double nb = lyap ? h[4] : h[5];
+    if (rel_res) *rel_res = h[0] / (h[6] + h[2] * (h[4] + nb));
+    e = hipGetLastError();
+    return e == hipSuccess ? 0 : SYLV_ERR_HIP - (int)e;
+}
+
+int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha, const void *A, int lda,
+              const void *B, int ldb, double beta, void *C, int ldc, void *stream) {
+    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -1;
+    if (m < 0) return -4;
+    if (n < 0) return -5;
+    if (k < 0) return -6;
+    if (lda < std::max(1, ta ? k : m)) return -9;
+    if (ldb < std::max(1, tb ? n : k)) return -11;
+    if (ldc < std::max(1, m)) return -14;
+    if (m == 0 || n == 0) return 0;
+    if (!C) return -13;
+    if (k > 0 && (!A || !B)) return !A ? -8 : -10;
+    DevCtx *c = nullptr;
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        rc = device_ctx(&c);
+    }
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == SYLV_PREC_FP64)
+        gemm<double, double, double, double>(s, ta, tb, m, n, k, alpha, (const double *)A, lda,
+                                             (const double *)B, ldb, beta, (double *)C, ldc);
+    else
+        gemm<float, float, float, float>(s, ta, tb, m, n, k, (float)alpha, (const float *)A, lda,
+                                         (const float *)B, ldb, (float)beta, (float *)C, ldc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+// Quasi-triangular Sylvester equation TA Y + Y TB = C (the substitution step
+// of the Bartels-Stewart algorithm, paper Sec. 2.2.1), TA m x m and TB n x n
+// upper quasi-triangular, C overwritten by Y.
+//
+// GPU formulation: Y is cut into tiles of at most 64 x 64 whose boundaries
+// never split a 2x2 diagonal block.  Tile (I, J) depends on the tiles below
+// it in its block column (through TA) and on the tiles left of it in its
+// block row (through TB), so all tiles on one anti-diagonal (counted from
+// the bottom-left corner) are independent: one launch per anti-diagonal,
+// one workgroup per tile.  Each workgroup
+//   1. forms the updated right-hand side
+//        C_IJ - TA(I, below) Y(below, J) - Y(I, left) TB(left, J)
+//      on MFMA (the GEMM-shaped off-diagonal updates), and
+//   2. solves the small quasi-triangular tile equation in LDS by a wavefront
+//      over its 1x1/2x2 diagonal-block pairs: every pair is a p*q <= 4 linear
+//      system solved by Gaussian elimination with complete pivoting; a pivot
+//      below s_min = u * max(max|TA|, max|TB|) is replaced by +-s_min and a
+//      flag is raised (the usual triangular-Sylvester convention).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace sylv {
+
+template <typename T> struct mfma16t;
+template <> struct mfma16t<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static SYLV_DEVINL v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static SYLV_DEVINL int orow(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct mfma16t<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static SYLV_DEVINL v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static SYLV_DEVINL int orow(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+constexpr int TS = 64;       // tile capacity
+constexpr int TBASE = 63;    // nominal boundary spacing (adjusted by +1 at 2x2 blocks)
+constexpr int TLD = TS + 1;  // LDS leading dimension of tiles
+
+// Boundary k of a quasi-triangular matrix of order n cut every TBASE rows.
+template <typename T>
+SYLV_DEVINL int tile_bound(const T *Tm, int ld, int n, int k) {
+    int b = k * TBASE;
+    if (b <= 0) return 0;
+    if (b >= n) return n;
+    if (CM(Tm, b, b - 1, ld) != T(0)) b += 1;
+    return b;
+}
+
+// Small dense solve M z = r (k <= 4, M column-major ld 4) by Gaussian
+// elimination with complete pivoting; small pivots are perturbed to smin.
+template <typename T>
+SYLV_DEVINL int small_solve(int k, T M[16], T r[4], T smin) {
+    int perm[4] = {0, 1, 2, 3};
+    int flag = 0;
+    for (int p = 0; p < k; ++p) {
+        int bi = p, bj = p;
+        T bv = T(-1);
+        for (int j = p; j < k; ++j)
+            for (int i = p; i < k; ++i) {
+                T a = fabs(M[j * 4 + i]);
+                if (a > bv) { bv = a; bi = i; bj = j; }
+            }
+        if (bi != p) {
+            for (int j = 0; j < 4; ++j) { T t = M[j * 4 + p]; M[j * 4 + p] = M[j * 4 + bi]; M[j * 4 + bi] = t; }
+            T t = r[p]; r[p] = r[bi]; r[bi] = t;
+        }
+        if (bj != p) {
+            for (int i = 0; i < 4; ++i) { T t = M[p * 4 + i]; M[p * 4 + i] = M[bj * 4 + i]; M[bj * 4 + i] = t; }
+            int t = perm[p]; perm[p] = perm[bj]; perm[bj] = t;
+        }
+        T piv = M[p * 4 + p];
+        if (fabs(piv) < smin) {
+            piv = (piv >= T(0)) ? smin : -smin;
+            M[p * 4 + p] = piv;
+            flag = 1;
+        }
+        T inv = T(1) / piv;
+        for (int i = p + 1; i < k; ++i) {
+            T f = M[p * 4 + i] * inv;
+            for (int j = p + 1; j < k; ++j) M[j * 4 + i] -= f * M[j * 4 + p];
+            r[i] -= f * r[p];
+        }
+    }
+    T z[4];
+    for (int i = k - 1; i >= 0; --i) {
+        T s = r[i];
+        for (int j = i + 1; j < k; ++j) s -= M[j * 4 + i] * z[j];
+        z[i] = s / M[i * 4 + i];
+    }
+    for (int i = 0; i < k; ++i) r[perm[i]] = z[i];
+    return flag;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
+                                                   const T *__restrict__ TB, int ldtb, T *C, int ldc,
+                                                   int d, int nI, int jmin, const double *maxab,
+                                                   int *flag) {
+    __shared__ T sA[TS * TLD];   // TA diagonal tile, later reused
+    __shared__ T sB[TS * TLD];   // TB diagonal tile
+    __shared__ T sC[TS * TLD];   // rhs -> Y tile
+    __shared__ T stA[16][TS + 16];
+    __shared__ T stB[16][TS + 16];
+    __shared__ int rstart[TS + 1], cstart[TS + 1];
+    __shared__ int nrb_s, ncb_s;
+    typedef typename mfma16t<T>::v4 v4;
+
+    const int J = jmin + blockIdx.x;
+    const int I = nI - 1 - (d - J);
+    const int r0 = tile_bound(TA, ldta, m, I), r1 = tile_bound(TA, ldta, m, I + 1);
+    const int c0 = tile_bound(TB, ldtb, n, J), c1 = tile_bound(TB, ldtb, n, J + 1);
+    const int p = r1 - r0, q = c1 - c0;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wm = w & 1, wn = w >> 1;
+
+    // ---- 1. off-diagonal updates on MFMA: acc = TA(r0:r1, r1:m) Y(r1:m, c0:c1)
+    //         + Y(r0:r1, 0:c0) TB(0:c0, c0:c1)
+    v4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+    for (int phase = 0; phase < 2; ++phase) {
+        const T *Ap;
+        int lda_, K;
+        const T *Bp;
+        int ldb_;
+        if (phase == 0) { Ap = TA + (size_t)r1 * ldta + r0; lda_ = ldta; Bp = C + (size_t)c0 * ldc + r1; ldb_ = ldc; K = m - r1; }
+        else { Ap = C + r0; lda_ = ldc; Bp = TB + (size_t)c0 * ldtb; ldb_ = ldtb; K = c0; }
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            // A slab: rows 0..p-1 (of the tile), cols k0..k0+15 ; B slab: rows k0.., cols 0..q-1
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                int i = l, k = w + 4 * rr;
+                T v = T(0);
+                if (i < p && k0 + k < K) v = Ap[(size_t)(k0 + k) * lda_ + i];
+                stA[k][i] = v;
+                int kk = t & 15, j = (t >> 4) + 16 * rr;
+                T u = T(0);
+                if (j < q && k0 + kk < K) u = Bp[(size_t)j * ldb_ + k0 + kk];
+                stB[kk][j] = u;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int kr = 4 * kk + (l >> 4);
+                T fa[2], fb[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) fa[a] = stA[kr][32 * wm + 16 * a + (l & 15)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) fb[b] = stB[kr][32 * wn + 16 * b + (l & 15)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[a][b] = mfma16t<T>::op(fb[b], fa[a], acc[a][b]);
+            }
+            __syncthreads();
+        }
+    }
+    // rhs tile: sC(i, j) = C(r0+i, c0+j) - acc
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int i = 32 * wm + 16 * a + (l & 15);
+                int j = 32 * wn + 16 * b + mfma16t<T>::orow(l, r);
+                T v = T(0);
+                if (i < p && j < q) v = C[(size_t)(c0 + j) * ldc + r0 + i] - acc[a][b][r];
+                sC[j * TLD + i] = v;
+            }
+    for (int e = t; e < TS * TS; e += 256) {
+        int i = e % TS, j = e / TS;
+        sA[j * TLD + i] = (i < p && j < p) ? CM(TA, r0 + i, r0 + j, ldta) : T(0);
+        sB[j * TLD + i] = (i < q && j < q) ? CM(TB, c0 + i, c0 + j, ldtb) : T(0);
+    }
+    __syncthreads();
+    // block structure of the diagonal tiles (start rows of 1x1/2x2 blocks)
+    if (t == 0) {
+        int nb = 0, i = 0;
+        while (i < p) { rstart[nb++] = i; i += (i + 1 < p && sA[i * TLD + i + 1] != T(0)) ? 2 : 1; }
+        rstart[nb] = p;
+        nrb_s = nb;
+        nb = 0; i = 0;
+        while (i < q) { cstart[nb++] = i; i += (i + 1 < q && sB[i * TLD + i + 1] != T(0)) ? 2 : 1; }
+        cstart[nb] = q;
+        ncb_s = nb;
+    }
+    __syncthreads();
+    const int P = nrb_s, Q = ncb_s;
+    const T smin = (T)fmax((double)num<T>::ulp * (*maxab), (double)num<T>::safmin);
+    int myflag = 0;
+    // ---- 2. wavefront over block pairs: unit (ib, jb), ib counted from the
+    // bottom; anti-diagonal e = ib + jb.  Four threads per unit split the sums.
+    for (int e = 0; e <= P + Q - 2; ++e) {
+        const int jlo = e - (P - 1) > 0 ? e - (P - 1) : 0;
+        const int jhi = e < Q - 1 ? e : Q - 1;
+        const int nunits = jhi - jlo + 1;
+        const int u = t >> 2, sub = t & 3;
+        T part[4] = {T(0), T(0), T(0), T(0)};
+        int ri = 0, pi = 0, cj = 0, qj = 0;
+        const bool active = u < nunits;
+        if (active) {
+            const int jb = jlo + u, ibb = e - jb;  // ibb from the bottom
+            const int ib = P - 1 - ibb;
+            ri = rstart[ib]; pi = rstart[ib + 1] - ri;
+            cj = cstart[jb]; qj = cstart[jb + 1] - cj;
+            // rows below the block: r' in [ri+pi, p) ; cols left: c' in [0, cj)
+            for (int rp = ri + pi + sub; rp < p; rp += 4) {
+                T a0 = sA[rp * TLD + ri];
+                T a1 = (pi == 2) ? sA[rp * TLD + ri + 1] : T(0);
+                T y0 = sC[cj * TLD + rp];
+                T y1 = (qj == 2) ? sC[(cj + 1) * TLD + rp] : T(0);
+                part[0] += a0 * y0; part[1] += a1 * y0;
+                part[2] += a0 * y1; part[3] += a1 * y1;
+            }
+            for (int cp = sub; cp < cj; cp += 4) {
+                T b0 = sB[cj * TLD + cp];
+                T b1 = (qj == 2) ? sB[(cj + 1) * TLD + cp] : T(0);
+                T y0 = sC[cp * TLD + ri];
+                T y1 = (pi == 2) ? sC[cp * TLD + ri + 1] : T(0);
+                part[0] += y0 * b0; part[1] += y1 * b0;
+                part[2] += y0 * b1; part[3] += y1 * b1;
+            }
+        }
+#pragma unroll
+        for (int z = 0; z < 4; ++z) {
+            part[z] += __shfl_xor(part[z], 1);
+            part[z] += __shfl_xor(part[z], 2);
+        }
+        if (active && sub == 0) {
+            // rhs (column-major p x q block: index jj*pi + ii)
+            T rhs[4], M[16];
+            for (int z = 0; z < 16; ++z) M[z] = T(0);
+            for (int jj = 0; jj < qj; ++jj)
+                for (int ii = 0; ii < pi; ++ii)
+                    rhs[jj * pi + ii] = sC[(cj + jj) * TLD + ri + ii] - part[jj * 2 + ii];
+            // (I_q (x) TA_ii + TB_jj^T (x) I_p) vec(Y) = vec(rhs)
+            for (int jj = 0; jj < qj; ++jj)
+                for (int ii = 0; ii < pi; ++ii) {
+                    int row = jj * pi + ii;
+                    for (int kk = 0; kk < pi; ++kk) M[(jj * pi + kk) * 4 + row] += sA[(ri + kk) * TLD + ri + ii];
+                    for (int ll = 0; ll < qj; ++ll) M[(ll * pi + ii) * 4 + row] += sB[(cj + jj) * TLD + cj + ll];
+                }
+            myflag |= small_solve<T>(pi * qj, M, rhs, smin);
+            for (int jj = 0; jj < qj; ++jj)
+                for (int ii = 0; ii < pi; ++ii) sC[(cj + jj) * TLD + ri + ii] = rhs[jj * pi + ii];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < p * q; e += 256) {
+        int i = e % p, j = e / p;
+        C[(size_t)(c0 + j) * ldc + r0 + i] = sC[j * TLD + i];
+    }
+    if (myflag) atomicOr(flag, 1);
+}
+
+template <typename T>
+void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, T *C, int ldc,
+           const double *maxab, int *flag) {
+    if (m <= 0 || n <= 0) return;
+    const int nI = (m + TBASE - 1) / TBASE, nJ = (n + TBASE - 1) / TBASE;
+    for (int d = 0; d <= nI + nJ - 2; ++d) {
+        int jmin = d - (nI - 1) > 0 ? d - (nI - 1) : 0;
+        int jmax = d < nJ - 1 ? d : nJ - 1;
+        hipLaunchKernelGGL((k_trsyl_diag<T>), dim3(jmax - jmin + 1), dim3(256), 0, s, m, n, TA, ldta,
+                           TB, ldtb, C, ldc, d, nI, jmin, maxab, flag);
+    }
+}
+template void trsyl<float>(hipStream_t, int, int, const float *, int, const float *, int, float *, int,
+                           const double *, int *);
+template void trsyl<double>(hipStream_t, int, int, const double *, int, const double *, int, double *,
+                            int, const double *, int *);
+
+}  // namespace sylv

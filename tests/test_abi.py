@@ -1,0 +1,91 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/sylv.h declares, and rejects invalid arguments before touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2503_03456_amd", "libsylv.so")
+HEADER = os.path.join(ROOT, "include", "sylv.h")
+
+
+def declared():
+    with open(HEADER) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:sylv|lyap)_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libsylv.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_solver_calls():
+    names = declared()
+    for must in ["sylv_solve", "lyap_solve", "sylv_solve_batched", "sylv_workspace_size",
+                 "sylv_default_opts", "sylv_status_string", "sylv_schur", "sylv_trsyl",
+                 "sylv_residual", "sylv_gemm", "sylv_mlp_forward", "sylv_mlp_train_step"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    missing = [s for s in declared() if s not in exported]
+    assert not missing, missing
+    for s in declared():
+        getattr(lib, s)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("low", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("fallback", ctypes.c_int), ("orth_check", ctypes.c_int)]
+
+
+def test_default_opts(lib):
+    o = Opts()
+    lib.sylv_default_opts(ctypes.byref(o))
+    assert o.low == 1 and o.tol == 1e-14 and o.max_iter == 20 and o.fallback == 1
+
+
+def test_argument_errors_are_synchronous(lib):
+    vp = ctypes.c_void_p
+    lib.sylv_solve.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp,
+                               ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
+    # negative m
+    assert lib.sylv_solve(-1, 3, None, 1, None, 3, None, 1, None, 1, None, None, None, 0, None) == -1
+    # lda too small
+    assert lib.sylv_solve(4, 3, 8, 2, 8, 3, 8, 4, 8, 4, None, None, None, 0, None) == -4
+    # ldb too small
+    assert lib.sylv_solve(4, 3, 8, 4, 8, 2, 8, 4, 8, 4, None, None, None, 0, None) == -6
+    # null A
+    assert lib.sylv_solve(4, 3, None, 4, 8, 3, 8, 4, 8, 4, None, None, None, 0, None) == -3
+    # empty problem is a no-op success
+    assert lib.sylv_solve(0, 3, None, 1, 8, 3, None, 1, None, 1, None, None, None, 0, None) == 0
+    lib.lyap_solve.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
+                               vp, vp, vp, ctypes.c_size_t, vp]
+    assert lib.lyap_solve(-2, None, 1, None, 1, None, 1, None, None, None, 0, None) == -1
+    assert lib.lyap_solve(5, 8, 4, 8, 5, 8, 5, None, None, None, 0, None) == -3
+
+
+def test_workspace_size_monotone(lib):
+    lib.sylv_workspace_size.restype = ctypes.c_size_t
+    lib.sylv_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    a = lib.sylv_workspace_size(64, 64, 0, None)
+    b = lib.sylv_workspace_size(128, 64, 0, None)
+    c = lib.sylv_workspace_size(64, 64, 1, None)
+    assert 0 < a < b and c > 0
+    assert lib.sylv_workspace_size(-1, 4, 0, None) == 0
+
+
+def test_status_strings(lib):
+    lib.sylv_status_string.restype = ctypes.c_char_p
+    lib.sylv_status_string.argtypes = [ctypes.c_int]
+    assert lib.sylv_status_string(0) == b"ok"
+    assert b"invalid" in lib.sylv_status_string(-3)

@@ -1,0 +1,147 @@
+"""Stage-level parity on the GPU (each stage fed the same inputs as the
+oracle; results compared element by element or by invariants)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_common import U32, U64, binding, check_schur, dev, host, relerr, say
+
+pytestmark = pytest.mark.gpu
+
+
+# ------------------------------------------------------------------- GEMM
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("m,n,k,ta,tb", [(1, 1, 1, 0, 0), (17, 33, 5, 0, 0), (64, 64, 64, 1, 0),
+                                         (100, 70, 130, 0, 1), (129, 65, 200, 1, 1),
+                                         (300, 257, 19, 0, 0), (1, 300, 77, 1, 1)])
+def test_gemm_parity(prec, m, n, k, ta, tb):
+    sy = binding()
+    say("gemm", prec, m, n, k, ta, tb)
+    rs = np.random.RandomState(m * 7 + n + k)
+    A = rs.standard_normal((k, m) if ta else (m, k))
+    B = rs.standard_normal((n, k) if tb else (k, n))
+    C0 = rs.standard_normal((m, n))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Cg = sy.gemm(dev(A, dt), dev(B, dt), dev(C0, dt), alpha=-0.75, beta=0.5, ta=bool(ta), tb=bool(tb))
+    torch.cuda.synchronize()
+    Ah = host(dev(A, dt)); Bh = host(dev(B, dt)); Ch = host(dev(C0, dt))
+    ref = -0.75 * (Ah.T if ta else Ah) @ (Bh.T if tb else Bh) + 0.5 * Ch
+    u = U64 if prec == "fp64" else U32
+    scale = np.abs(Ah).max() * np.abs(Bh).max() * k + np.abs(Ch).max()
+    assert np.abs(host(Cg) - ref).max() <= 4 * k * u * scale
+
+
+# --------------------------------------------------------- tri-solve parity
+def quasi_tri(n, rs, frac2=0.4):
+    """Upper quasi-triangular test matrix: well conditioned (off-diagonal part
+    of norm ~0.5), eigenvalues with positive real parts in [1, 3], 2x2 blocks
+    carrying complex pairs."""
+    T = np.triu(rs.standard_normal((n, n)), 1) * (0.5 / np.sqrt(max(n, 1)))
+    i = 0
+    while i < n:
+        if i + 1 < n and rs.rand() < frac2:
+            a, w = rs.uniform(1.0, 3.0), rs.uniform(0.3, 2.0)
+            b = w * rs.uniform(0.5, 2.0)
+            T[i, i] = T[i + 1, i + 1] = a
+            T[i, i + 1] = b
+            T[i + 1, i] = -w * w / b
+            i += 2
+        else:
+            T[i, i] = rs.uniform(1.0, 3.0)
+            i += 1
+    return T
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("m,n,trans", [(1, 1, 0), (2, 3, 0), (5, 4, 1), (63, 64, 0), (64, 63, 1),
+                                       (65, 130, 0), (200, 127, 0), (191, 150, 1), (300, 310, 0)])
+def test_trsyl_parity(prec, m, n, trans):
+    sy = binding()
+    say("trsyl", prec, m, n, trans)
+    rs = np.random.RandomState(1000 + m + 3 * n + trans)
+    TA = quasi_tri(m, rs)
+    TB = quasi_tri(n, rs)
+    C = rs.standard_normal((m, n))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    # the oracle sees exactly the (rounded) inputs the GPU sees
+    TAh, TBh, Ch = host(dev(TA, dt)), host(dev(TB, dt)), host(dev(C, dt))
+    Yo, _ = oracle.trsyl(TAh, TBh, Ch, lower_b=bool(trans))
+    Yg, pf = sy.trsyl(dev(TA, dt), dev(TB, dt), dev(C, dt), trans_b=bool(trans))
+    torch.cuda.synchronize()
+    assert pf == 0
+    Y = host(Yg)
+    u = U64 if prec == "fp64" else U32
+    RB = TBh.T if trans else TBh
+    res = np.linalg.norm(TAh @ Y + Y @ RB - Ch) / (np.linalg.norm(Ch) + np.linalg.norm(Y) * (np.linalg.norm(TAh) + np.linalg.norm(RB)))
+    assert res <= 10 * u * np.sqrt(m + n)
+    assert relerr(Y, Yo) <= 1000 * u * np.sqrt(m + n)
+
+
+def test_trsyl_singular_pivot_perturbed():
+    sy = binding()
+    TA = np.array([[1.0, 0.5], [0.0, 2.0]])
+    TB = np.array([[-2.0]])
+    C = np.array([[1.0], [1.0]])
+    Yg, pf = sy.trsyl(dev(TA), dev(TB), dev(C))
+    assert pf == 1
+    assert np.all(np.isfinite(host(Yg)))
+
+
+# ----------------------------------------------------------- Schur stage
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 99, 140, 141, 257, 600])
+def test_schur_invariants_random(prec, n):
+    sy = binding()
+    say("schur random", prec, n)
+    rs = np.random.RandomState(n + 5)
+    A = rs.standard_normal((n, n))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    T, Uq, st = sy.schur(dev(A, dt))
+    torch.cuda.synchronize()
+    assert st == 0
+    Ah = host(dev(A, dt))
+    u = U64 if prec == "fp64" else U32
+    check_schur(Ah, host(T), host(Uq), u)
+    # spectrum against the oracle's (multiset match with tolerance)
+    ev = oracle.quasi_eigs(host(T))
+    To, _, sto = oracle.schur(Ah)
+    ref = oracle.quasi_eigs(To)
+    tol = (1e-9 if prec == "fp64" else 2e-3) * max(1.0, np.abs(ref).max())
+    for z in ref:
+        assert np.min(np.abs(ev - z)) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_schur_constructed_spectrum_700(prec):
+    """Normal matrix with known spectrum (workload recipe): GPU eigenvalues
+    equal the constructed ones."""
+    sy = binding()
+    say("schur constructed", prec)
+    A, eig, _, _ = workloads.normal_coeff(2, 700, 0.5, 5.0)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    T, Uq, st = sy.schur(dev(A, dt))
+    torch.cuda.synchronize()
+    assert st == 0
+    u = U64 if prec == "fp64" else U32
+    check_schur(host(dev(A, dt)), host(T), host(Uq), u)
+    ev = oracle.quasi_eigs(host(T))
+    nrm = np.linalg.norm(A, 2)
+    for z in eig:
+        assert np.min(np.abs(ev - z)) <= 10 * 700 * u * nrm
+
+
+# ------------------------------------------------------------- residual
+@pytest.mark.parametrize("lyap", [False, True])
+def test_residual_parity(lyap):
+    sy = binding()
+    m, n = (70, 70) if lyap else (70, 45)
+    A, B, C = workloads.sylv_random(77, m, n)
+    X = np.random.RandomState(78).standard_normal((m, n)) * 0.3
+    R, rr = sy.residual(dev(A), dev(B), dev(C), dev(X), lyap=lyap)
+    torch.cuda.synchronize()
+    Rr = oracle.residual_matrix(A, B, C, X, lyap=lyap)
+    assert np.abs(host(R) - Rr).max() <= 64 * U64 * (np.abs(A).max() * np.abs(X).max() * (m + n) + 1)
+    ro = oracle.rel_residual(A, B, C, X, lyap=lyap)
+    assert abs(rr - ro) <= 1e-12 * ro
