@@ -203,6 +203,21 @@ int sylv_selector_set(const float *blob, int nvalues);
 int sylv_selector_features(int m, int n, const double *A, int lda, const double *B,
                            int ldb, const double *C, int ldc, float *feats, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Per-kernel timing (for roofline measurements).  sylv_profile_begin arms
+ * one kernel family (ids: 1 gemm_kernel, 2 k_hess_col, 3 k_hess_gemv,
+ * 4 k_aed, 5 k_chase, 6 k_trsyl_diag, 7 k_find_ktop, 8 k_cast,
+ * 9 k_sumsq_partial); each later launch of that family is bracketed by two
+ * HIP events recorded on its launch stream.  sylv_profile_end disarms,
+ * waits for the events and returns the number of launches and the summed
+ * durations in milliseconds, plus the algorithmic work the library
+ * accounts for those launches (flops; k_chase and gemm_kernel only, else 0)
+ * (host pointers, may be NULL).
+ * ---------------------------------------------------------------------- */
+int sylv_profile_begin(int kernel_id);
+int sylv_profile_end(long *launches, double *total_ms, double *work);
+const char *sylv_kernel_name(int kernel_id);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,6 +3,7 @@
 // one workgroup combines them in a fixed order).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace sylv {
 
@@ -28,6 +29,7 @@ static inline int grid_for(size_t total) {
 template <typename TS, typename TD>
 void cast(hipStream_t s, int r, int c, const TS *src, int lds, TD *dst, int ldd, TS scale) {
     if (r <= 0 || c <= 0) return;
+    ProfScope ps(KID_CAST, s);
     hipLaunchKernelGGL((k_cast<TS, TD>), dim3(grid_for((size_t)r * c)), dim3(256), 0, s, r, c, src,
                        lds, dst, ldd, scale);
 }
@@ -163,7 +165,10 @@ void matnorm(hipStream_t s, int r, int c, const T *a, int ld, double *out, doubl
     int nb = (int)((total + 4095) / 4096);
     if (nb > NRM_BLOCKS) nb = NRM_BLOCKS;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL((k_sumsq_partial<T>), dim3(nb), dim3(256), 0, s, r, c, a, ld, scratch, mode);
+    {
+        ProfScope ps(KID_NORM, s);
+        hipLaunchKernelGGL((k_sumsq_partial<T>), dim3(nb), dim3(256), 0, s, r, c, a, ld, scratch, mode);
+    }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, nb, scratch, out, mode);
 }
 template void matnorm<float>(hipStream_t, int, int, const float *, int, double *, double *, int);

@@ -30,19 +30,24 @@ template <> struct num<double> {
         if (_e != hipSuccess) return SYLV_ERR_HIP - (int)_e;  \
     } while (0)
 
-// 2-norm of (a, b, c) without overflow for moderate ranges: scale by the
-// largest magnitude.
-template <typename T>
-SYLV_DEVINL T norm3(T a, T b, T c) {
-    T m = fmax(fabs(a), fmax(fabs(b), fabs(c)));
-    if (m == T(0)) return T(0);
-    T x = a / m, y = b / m, z = c / m;
-    return m * sqrt(x * x + y * y + z * z);
+// Fast reciprocal / square root for reflector generation: the hardware
+// approximations (1 ulp in binary32) and, for binary64, v_rcp_f64 refined by
+// two Newton steps.  A relative error of a few ulps in tau or v keeps the
+// reflector orthogonal to working precision.
+SYLV_DEVINL float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+SYLV_DEVINL double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
 }
+SYLV_DEVINL float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+SYLV_DEVINL double fsqrt(double x) { return sqrt(x); }
 
 // Householder reflector for a vector of length 2 or 3 (z ignored when
 // len == 2): P = I - tau v v^T, v = (1, v1, v2), P x = beta e1.  Returns
-// tau = 0 when x(1:) is zero (P = I).
+// tau = 0 when x(1:) is zero (P = I).  The norm is formed after scaling by
+// the largest magnitude (no overflow for moderate ranges).
 template <typename T>
 SYLV_DEVINL void reflector3(int len, T x, T y, T z, T &v1, T &v2, T &tau, T &beta) {
     if (len == 2) z = T(0);
@@ -51,12 +56,15 @@ SYLV_DEVINL void reflector3(int len, T x, T y, T z, T &v1, T &v2, T &tau, T &bet
         v1 = T(0); v2 = T(0); tau = T(0); beta = x;
         return;
     }
-    T nrm = norm3(x, y, z);
+    T m = fmax(fabs(x), tail);
+    T rm = frcp(m);
+    T xs = x * rm, ys = y * rm, zs = z * rm;
+    T nrm = m * fsqrt(xs * xs + ys * ys + zs * zs);
     T b = (x >= T(0)) ? -nrm : nrm;
-    tau = (b - x) / b;
-    T s = T(1) / (x - b);
-    v1 = y * s;
-    v2 = z * s;
+    tau = (b - x) * frcp(b);
+    T sc = frcp(x - b);
+    v1 = y * sc;
+    v2 = z * sc;
     beta = b;
 }
 

@@ -15,6 +15,7 @@
 // elements of a column per quarter-wave.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace sylv {
 
@@ -139,6 +140,8 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const T
           const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale) {
     if (M <= 0 || N <= 0) return;
     int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
+    prof_add_work(KID_GEMM, 2.0 * M * N * K);
+    ProfScope ps(KID_GEMM, s);
     hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, ACC>), dim3(tm * tn), dim3(256), 0, s, M, N, K, A,
                        lda, ta, B, ldb, tb, C, ldc, alpha, beta, tm, bscale);
 }

@@ -15,6 +15,7 @@
 // by applying the stored block reflectors backwards to the identity.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace sylv {
 
@@ -33,6 +34,34 @@ SYLV_DEVINL T block_sum(T v, T *red) {
     return s;
 }
 
+// Reduce cnt (<= 32) per-thread accumulators over the workgroup in one pass:
+// wave shuffles, one LDS round, fixed summation order.  out[j] for j < cnt.
+template <typename T>
+SYLV_DEVINL void multi_sum(int cnt, T acc[32], T *red /* 16 x 32 */, T *out) {
+    const int tid = threadIdx.x, w = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if (j < cnt) {
+            T v = acc[j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            acc[j] = v;
+        }
+    }
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+            if (j < cnt) red[w * 32 + j] = acc[j];
+    }
+    __syncthreads();
+    if (tid < cnt) {
+        T sum = T(0);
+        for (int q = 0; q < HNT / 64; ++q) sum += red[q * 32 + tid];
+        out[tid] = sum;
+    }
+    __syncthreads();
+}
+
 // State: A (n x n, lda), V (n x n, ldv = n) reflector vectors (column c holds
 // the vector of column c's reflector, 1 at row c+1, zeros above), Tp (nb x nb,
 // ld nb) the panel's T, Y (n x nb, ld n), Ypart (S x n) partials of y_raw for
@@ -42,6 +71,7 @@ __global__ __launch_bounds__(HNT) void k_hess_col(int n, T *A, int lda, T *V, T 
                                                  const T *Ypart, int S, T *tau, int k0, int i,
                                                  int finalize_only) {
     __shared__ T red[HNT / 64];
+    __shared__ T red2[(HNT / 64) * 32];
     __shared__ T wv[64];
     __shared__ T cv[64];
     __shared__ T sh[4];
@@ -51,13 +81,18 @@ __global__ __launch_bounds__(HNT) void k_hess_col(int n, T *A, int lda, T *V, T 
         // finish column i-1: w = V(:,k0:k0+i-1)^T v_{i-1}; T(0:i-1, i-1); y_{i-1}
         const int cp = k0 + i - 1;
         const T tp = tau[cp];
-        for (int j = 0; j < i - 1; ++j) {
-            T acc = T(0);
-            for (int r = cp + 1 + tid; r < n; r += HNT) acc += CM(V, r, k0 + j, ldv) * CM(V, r, cp, ldv);
-            acc = block_sum(acc, red);
-            if (tid == 0) wv[j] = acc;
+        {
+            T acc[32];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) acc[j] = T(0);
+            for (int r = cp + 1 + tid; r < n; r += HNT) {
+                const T vc = CM(V, r, cp, ldv);
+#pragma unroll
+                for (int j = 0; j < 32; ++j)
+                    if (j < i - 1) acc[j] += CM(V, r, k0 + j, ldv) * vc;
+            }
+            multi_sum(i - 1, acc, red2, wv);
         }
-        __syncthreads();
         if (tid < i - 1) {
             // T(0:i-1, i-1) = -tau T(0:i-1,0:i-1) w   (T upper triangular)
             T acc = T(0);
@@ -90,13 +125,18 @@ __global__ __launch_bounds__(HNT) void k_hess_col(int n, T *A, int lda, T *V, T 
     __syncthreads();
     // left update on rows k0+1..n-1: a -= V T^T (V^T a)
     if (i > 0) {
-        for (int j = 0; j < i; ++j) {
-            T acc = T(0);
-            for (int r = k0 + 1 + j + tid; r < n; r += HNT) acc += CM(V, r, k0 + j, ldv) * CM(A, r, col, lda);
-            acc = block_sum(acc, red);
-            if (tid == 0) wv[j] = acc;
+        {
+            T acc[32];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) acc[j] = T(0);
+            for (int r = k0 + 1 + tid; r < n; r += HNT) {
+                const T ar = CM(A, r, col, lda);
+#pragma unroll
+                for (int j = 0; j < 32; ++j)
+                    if (j < i) acc[j] += CM(V, r, k0 + j, ldv) * ar;
+            }
+            multi_sum(i, acc, red2, wv);
         }
-        __syncthreads();
         if (tid < i) {
             // c = T^T b: c(j) = sum_{j' <= j} T(j', j) b(j')
             T acc = T(0);
@@ -217,10 +257,16 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
         const int nbp = (n - 2 - k0) < nb ? (n - 2 - k0) : nb;
         T *Tp = Tall + (size_t)p * nb * nb;
         for (int i = 0; i < nbp; ++i) {
-            hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y,
-                               Ypart, S, tau, k0, i, 0);
-            hipLaunchKernelGGL((k_hess_gemv<T>), dim3(rb, S), dim3(256), 0, s, n, A, lda, V, k0 + i,
-                               Ypart, S);
+            {
+                ProfScope ps(KID_HESS_COL, s);
+                hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y,
+                                   Ypart, S, tau, k0, i, 0);
+            }
+            {
+                ProfScope ps(KID_HESS_GEMV, s);
+                hipLaunchKernelGGL((k_hess_gemv<T>), dim3(rb, S), dim3(256), 0, s, n, A, lda, V, k0 + i,
+                                   Ypart, S);
+            }
         }
         hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart,
                            S, tau, k0, nbp, 1);

@@ -21,6 +21,9 @@
 //     applied afterwards with MFMA GEMMs by the host driver.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
+
+#include <mutex>
 
 namespace sylv {
 
@@ -80,7 +83,8 @@ SYLV_DEVINL void refl_apply(int len, T v1, T v2, T tau, T &a0, T &a1, T &a2) {
 // form of H), Z (nz x n, LDS or global) <- Z * Q.  Returns 0 or 1
 // (iteration cap).  All threads must call it.  sint: one int of LDS scratch.
 template <typename T, int NT>
-SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *sint) {
+SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *sint,
+                            int *nsweep = nullptr, int *nstep = nullptr) {
     const int tid = threadIdx.x;
     const T ulp = num<T>::ulp, smlnum = num<T>::safmin * T(n) / num<T>::ulp;
     int ihi = n - 1, its = 0, total = 0;
@@ -110,6 +114,7 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
         }
         if (++total > itmax) return 1;
         ++its;
+        if (nsweep) { ++*nsweep; *nstep += ihi - l; }
         T h11 = CM(H, ihi - 1, ihi - 1, ldh), h12 = CM(H, ihi - 1, ihi, ldh);
         T h21 = CM(H, ihi, ihi - 1, ldh), h22 = CM(H, ihi, ihi, ldh);
         if (its == 10 || its == 20) {
@@ -143,31 +148,18 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
             }
             T v1, v2, tau, beta;
             reflector3(len, x, y, z, v1, v2, tau, beta);
-            // work items: 0 overlap block, then left columns, right rows, Z rows
+            // Work split by wave so that no wave runs two code paths:
+            //   wave 0: left application on columns {k-1} u [k+len, n)
+            //   wave 1: right application on rows [0, k) u {k+3}
+            //   waves 2..NW-2: the accumulated factor Z (rows 0..nz-1)
+            //   wave NW-1, lane 0: the overlap block rows/cols k..k+len-1
+            constexpr int NWV = NT / 64;
+            static_assert(NWV >= 4, "francis_lds needs at least 4 waves");
+            const int wv = tid >> 6, lane = tid & 63;
             const int lc0 = (k > l) ? 1 : 0;                  // column k-1
-            const int nL = lc0 + (n - (k + len));              // cols {k-1} u [k+len, n)
-            const int extra = (len == 3 && k + 3 <= ihi) ? 1 : 0;
-            const int nR = k + extra;                          // rows [0,k) u {k+3}
-            const int tot = 1 + nL + nR + nz;
-            for (int e = tid; e < tot; e += NT) {
-                if (e == 0) {
-                    // overlap block: left then right on rows/cols k..k+len-1
-                    for (int j = k; j < k + len; ++j) {
-                        T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh);
-                        T a2 = (len == 3) ? CM(H, k + 2, j, ldh) : T(0);
-                        refl_apply(len, v1, v2, tau, a0, a1, a2);
-                        CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
-                        if (len == 3) CM(H, k + 2, j, ldh) = a2;
-                    }
-                    for (int i = k; i < k + len; ++i) {
-                        T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh);
-                        T a2 = (len == 3) ? CM(H, i, k + 2, ldh) : T(0);
-                        refl_apply(len, v1, v2, tau, a0, a1, a2);
-                        CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
-                        if (len == 3) CM(H, i, k + 2, ldh) = a2;
-                    }
-                } else if (e < 1 + nL) {
-                    int q = e - 1;
+            if (wv == 0) {
+                const int nL = lc0 + (n - (k + len));
+                for (int q = lane; q < nL; q += 64) {
                     if (lc0 && q == 0) {
                         CM(H, k, k - 1, ldh) = beta;
                         CM(H, k + 1, k - 1, ldh) = T(0);
@@ -180,22 +172,44 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
                         CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
                         if (len == 3) CM(H, k + 2, j, ldh) = a2;
                     }
-                } else if (e < 1 + nL + nR) {
-                    int q = e - 1 - nL;
+                }
+            } else if (wv == 1) {
+                const int extra = (len == 3 && k + 3 <= ihi) ? 1 : 0;
+                const int nR = k + extra;
+                for (int q = lane; q < nR; q += 64) {
                     int i = (q < k) ? q : k + 3;
                     T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh);
                     T a2 = (len == 3) ? CM(H, i, k + 2, ldh) : T(0);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
                     CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
                     if (len == 3) CM(H, i, k + 2, ldh) = a2;
-                } else {
-                    int i = e - 1 - nL - nR;
+                }
+            } else if (wv < NWV - 1) {
+                for (int i = tid - 128; i < nz; i += NT - 192) {
                     T a0 = CM(Z, i, k, ldz), a1 = CM(Z, i, k + 1, ldz);
                     T a2 = (len == 3) ? CM(Z, i, k + 2, ldz) : T(0);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
                     CM(Z, i, k, ldz) = a0; CM(Z, i, k + 1, ldz) = a1;
                     if (len == 3) CM(Z, i, k + 2, ldz) = a2;
                 }
+            } else if (lane == 0) {
+                // overlap block in registers: left then right on
+                // rows/cols k..k+len-1 (one LDS load round, one store round)
+                T b[3][3];
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 3; ++ii)
+                        b[ii][jj] = (ii < len && jj < len) ? CM(H, k + ii, k + jj, ldh) : T(0);
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) refl_apply(len, v1, v2, tau, b[0][jj], b[1][jj], b[2][jj]);
+#pragma unroll
+                for (int ii = 0; ii < 3; ++ii) refl_apply(len, v1, v2, tau, b[ii][0], b[ii][1], b[ii][2]);
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 3; ++ii)
+                        if (ii < len && jj < len) CM(H, k + ii, k + jj, ldh) = b[ii][jj];
             }
             __syncthreads();
         }
@@ -230,7 +244,11 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
         Zl[e] = (i == j) ? T(1) : T(0);
     }
     __syncthreads();
-    int st = francis_lds<T, NT>(nw, Tw, nw, Zl, nw, nw, sint + 1);
+    int nsw = 0, nst = 0;
+    const long long c0 = clock64();
+    int st = francis_lds<T, NT>(nw, Tw, nw, Zl, nw, nw, sint + 1, &nsw, &nst);
+    const long long c1 = clock64();
+    if (tid == 0) { out[3] = nsw; out[4] = nst; out[5] = (int)((c1 - c0) >> 10); }
     if (st) {
         if (tid == 0) { out[0] = 1; out[1] = 0; out[2] = 0; }
         return;  // window left untouched in global memory
@@ -405,17 +423,24 @@ int aed_launch(hipStream_t s, int nw, T *H, int ldh, int kwtop, int spike_on, T 
                T *wr, T *wi) {
     size_t sm = aed_smem<T>(nw);
     if (sm > 160 * 1024) return -1;
-    auto kfn = k_aed<T, 256>;
+    auto kfn = k_aed<T, 320>;
+    static std::mutex mu;
     static size_t attr_set = 0;
-    if (sm > attr_set) {
-        if (hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return -1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (sm > attr_set) {
+            if (hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)sm) != hipSuccess) {
+                (void)hipGetLastError();
+                return -1;
+            }
+            attr_set = sm;
         }
-        attr_set = sm;
     }
-    hipLaunchKernelGGL(kfn, dim3(1), dim3(256), sm, s, nw, H, ldh, kwtop, spike_on, Zw, out, wr, wi);
+    {
+        ProfScope ps(KID_AED, s);
+        hipLaunchKernelGGL(kfn, dim3(1), dim3(320), sm, s, nw, H, ldh, kwtop, spike_on, Zw, out, wr, wi);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template int aed_launch<float>(hipStream_t, int, float *, int, int, int, float *, int *, float *, float *);
@@ -449,6 +474,8 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
     }
     __syncthreads();
     const int kb = kbot - ws;  // local index of kbot
+    const int tpb = NT / nbulge;             // threads per bulge (nbulge <= NT)
+    const int myb = tid / tpb, slot = tid % tpb;
     for (int t = t0; t < t0 + adv; ++t) {
         // phase 0: reflectors of the active bulges
         for (int b = tid; b < nbulge; b += NT) {
@@ -479,50 +506,54 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
             rinfo[2 * b] = q; rinfo[2 * b + 1] = len;
         }
         __syncthreads();
+        // Each active bulge gets a fixed group of tpb threads; a thread works
+        // only on its own bulge, so there is no sequential loop over bulges.
         // phase A: left applications, rows q..q+len-1, columns q-1 (p>0: set
         // beta, zeros) and q..W-1.  Distinct bulges touch distinct rows.
-        for (int b = 0; b < nbulge; ++b) {
-            const int q = rinfo[2 * b];
-            if (q < 0) continue;
-            const int len = rinfo[2 * b + 1];
-            const T v1 = refl[4 * b], v2 = refl[4 * b + 1], tau = refl[4 * b + 2];
-            const int p = ktop - ws + 0;  // unused placeholder for clarity
-            (void)p;
-            const bool intro = (q + ws == ktop) && (t - 3 * b == 0);
-            const int c0 = intro ? q : q - 1;
-            for (int j = c0 + tid; j < W; j += NT) {
-                if (!intro && j == q - 1) {
-                    Hw[j * W + q] = refl[4 * b + 3];
-                    Hw[j * W + q + 1] = T(0);
-                    if (len == 3) Hw[j * W + q + 2] = T(0);
-                    continue;
+        if (myb < nbulge) {
+            const int q = rinfo[2 * myb];
+            if (q >= 0) {
+                const int len = rinfo[2 * myb + 1];
+                const T v1 = refl[4 * myb], v2 = refl[4 * myb + 1], tau = refl[4 * myb + 2];
+                const bool intro = (t - 3 * myb == 0);
+                const int c0 = intro ? q : q - 1;
+#pragma unroll 2
+                for (int j = c0 + slot; j < W; j += tpb) {
+                    if (!intro && j == q - 1) {
+                        Hw[j * W + q] = refl[4 * myb + 3];
+                        Hw[j * W + q + 1] = T(0);
+                        if (len == 3) Hw[j * W + q + 2] = T(0);
+                        continue;
+                    }
+                    T a0 = Hw[j * W + q], a1 = Hw[j * W + q + 1];
+                    T a2 = (len == 3) ? Hw[j * W + q + 2] : T(0);
+                    refl_apply(len, v1, v2, tau, a0, a1, a2);
+                    Hw[j * W + q] = a0; Hw[j * W + q + 1] = a1;
+                    if (len == 3) Hw[j * W + q + 2] = a2;
                 }
-                T a0 = Hw[j * W + q], a1 = Hw[j * W + q + 1];
-                T a2 = (len == 3) ? Hw[j * W + q + 2] : T(0);
-                refl_apply(len, v1, v2, tau, a0, a1, a2);
-                Hw[j * W + q] = a0; Hw[j * W + q + 1] = a1;
-                if (len == 3) Hw[j * W + q + 2] = a2;
             }
         }
         __syncthreads();
         // phase B: right applications on columns q..q+len-1 (rows 0..min(q+3, kb))
         // and on Uw (all rows).  Distinct bulges touch distinct columns.
-        for (int b = 0; b < nbulge; ++b) {
-            const int q = rinfo[2 * b];
-            if (q < 0) continue;
-            const int len = rinfo[2 * b + 1];
-            const T v1 = refl[4 * b], v2 = refl[4 * b + 1], tau = refl[4 * b + 2];
-            int rmax = q + 3 < kb ? q + 3 : kb;
-            if (rmax > W - 1) rmax = W - 1;
-            const int nr = rmax + 1;
-            for (int e = tid; e < nr + W; e += NT) {
-                T *M = (e < nr) ? Hw : Uw;
-                int i = (e < nr) ? e : e - nr;
-                T a0 = M[q * W + i], a1 = M[(q + 1) * W + i];
-                T a2 = (len == 3) ? M[(q + 2) * W + i] : T(0);
-                refl_apply(len, v1, v2, tau, a0, a1, a2);
-                M[q * W + i] = a0; M[(q + 1) * W + i] = a1;
-                if (len == 3) M[(q + 2) * W + i] = a2;
+        if (myb < nbulge) {
+            const int q = rinfo[2 * myb];
+            if (q >= 0) {
+                const int len = rinfo[2 * myb + 1];
+                const T v1 = refl[4 * myb], v2 = refl[4 * myb + 1], tau = refl[4 * myb + 2];
+                int rmax = q + 3 < kb ? q + 3 : kb;
+                if (rmax > W - 1) rmax = W - 1;
+                const int nr = rmax + 1;
+#pragma unroll 2
+                for (int e = slot; e < nr + W; e += tpb) {
+                    T *M = (e < nr) ? Hw : Uw;
+                    int i = (e < nr) ? e : e - nr;
+                    T a0 = M[q * W + i], a1 = M[(q + 1) * W + i];
+                    T a2 = (len == 3) ? M[(q + 2) * W + i] : T(0);
+                    refl_apply(len, v1, v2, tau, a0, a1, a2);
+                    M[q * W + i] = a0; M[(q + 1) * W + i] = a1;
+                    if (len == 3) M[(q + 2) * W + i] = a2;
+                }
             }
         }
         __syncthreads();
@@ -544,18 +575,43 @@ int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W
                  int nbulge, const T *trd, T *Uw) {
     size_t sm = chase_smem<T>(W, nbulge);
     if (sm > 160 * 1024) return -1;
-    auto kfn = k_chase<T, 256>;
+    auto kfn = k_chase<T, 512>;
+    static std::mutex mu;
     static size_t attr_set = 0;
-    if (sm > attr_set) {
-        if (hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return -1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (sm > attr_set) {
+            if (hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)sm) != hipSuccess) {
+                (void)hipGetLastError();
+                return -1;
+            }
+            attr_set = sm;
         }
-        attr_set = sm;
     }
-    hipLaunchKernelGGL(kfn, dim3(1), dim3(256), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge,
-                       trd, Uw);
+    if (prof_armed(KID_CHASE)) {
+        // algorithmic flops of this phase: every application of a bulge's
+        // reflector to one row or column (length 3: 12 flops, length 2: 8),
+        // left (window columns right of the bulge), right (window rows up to
+        // the bulge) and on the window's orthogonal factor
+        const int N = kbot - ktop + 1, kb = kbot - ws;
+        double fl = 0.0;
+        for (int t = t0; t < t0 + adv; ++t)
+            for (int b = 0; b < nbulge; ++b) {
+                int p = t - 3 * b;
+                if (p < 0 || p > N - 2) continue;
+                int q = ktop + p - ws, len = (p <= N - 3) ? 3 : 2;
+                int rmax = q + 3 < kb ? q + 3 : kb;
+                if (rmax > W - 1) rmax = W - 1;
+                fl += (len == 3 ? 12.0 : 8.0) * ((W - q) + (rmax + 1) + W);
+            }
+        prof_add_work(KID_CHASE, fl);
+    }
+    {
+        ProfScope ps(KID_CHASE, s);
+        hipLaunchKernelGGL(kfn, dim3(1), dim3(512), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge,
+                           trd, Uw);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template int chase_launch<float>(hipStream_t, float *, int, int, int, int, int, int, int, int,
@@ -592,6 +648,7 @@ __global__ __launch_bounds__(256) void k_find_ktop(T *H, int ldh, int klo, int k
 }
 template <typename T>
 void find_ktop(hipStream_t s, T *H, int ldh, int klo, int kbot, int *out) {
+    ProfScope ps(KID_FIND_KTOP, s);
     hipLaunchKernelGGL((k_find_ktop<T>), dim3(1), dim3(256), 0, s, H, ldh, klo, kbot, out);
 }
 template void find_ktop<float>(hipStream_t, float *, int, int, int, int *);

@@ -20,6 +20,8 @@
 
 #include <vector>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <algorithm>
 
 namespace sylv {
@@ -148,6 +150,9 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
     const long itmax = 100L + n / 2;  // AED + sweep rounds before giving up
     std::vector<double> wr, wi;
     std::vector<T> trd;
+    // SYLV_TRACE=1: per-factorisation counters of the QR phase on stderr
+    const bool trace = std::getenv("SYLV_TRACE") != nullptr;
+    long st_aed = 0, st_sweeps = 0, st_chase = 0, st_fsw = 0, st_fst = 0, st_kcyc = 0, st_defl = 0;
     while (kbot >= 0) {
         find_ktop<T>(s, H, ldh, 0, kbot, c.dint);
         if ((err = readback(c, c.dint, sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
@@ -158,7 +163,8 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         if (++iters > itmax) { *qr_status = 1; break; }
         if (N <= P::NSMALL) {
             if (aed_launch<T>(s, N, H, ldh, ktop, 0, c.Zw, c.dint, c.wr, c.wi)) return -1;
-            if ((err = readback(c, c.dint, 4 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+            if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+            ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5];
             if (hi[0] != 0) { *qr_status = 1; break; }
             apply_window(c, ktop, N, c.Zw);
             kbot = ktop - 1;
@@ -169,8 +175,9 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         const int nw = std::min(P::NW, N - 1);
         const int kwtop = kbot - nw + 1;
         if (aed_launch<T>(s, nw, H, ldh, kwtop, 1, c.Zw, c.dint, c.wr, c.wi)) return -1;
-        if ((err = readback(c, c.dint, 4 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+        if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
         const int aed_st = hi[0], nd = hi[1], nsu = hi[2];
+        ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5]; st_defl += nd;
         if (aed_st == 0) apply_window(c, kwtop, nw, c.Zw);
         // shift candidates: eigenvalues of the undeflated part of the window
         wr.clear(); wi.clear();
@@ -232,6 +239,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         hipMemcpyAsync(c.trd, htrd, sizeof(T) * trd.size(), hipMemcpyHostToDevice, s);
         // multishift sweep over [ktop, kbot]
         const int ttot = (N2 - 2) + 3 * (nb - 1) + 1;
+        ++st_sweeps;
         for (int t0 = 0; t0 < ttot; t0 += P::ADV) {
             const int t1 = std::min(t0 + P::ADV, ttot);
             const int pmin = std::max(0, t0 - 3 * (nb - 1));
@@ -241,12 +249,19 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
             const int we_ = ktop + std::min(N2, pmax + 4);
             const int W = we_ - ws_;
             if (chase_launch<T>(s, H, ldh, ktop, kbot, ws_, W, t0, t1 - t0, nb, c.trd, c.Uw)) return -1;
+            ++st_chase;
             apply_window(c, ws_, W, c.Uw);
         }
         // the pinned copy of the shifts must stay valid until the upload ran
         if ((err = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
     }
     clean_lower<T>(s, n, H, ldh);
+    if (trace)
+        std::fprintf(stderr,
+                     "[sylv] schur<%s> n=%d: AED calls %ld (deflated %ld), sweeps %ld, chase "
+                     "phases %ld, window Francis sweeps %ld steps %ld kcycles %ld (%.0f cycles/step)\n",
+                     sizeof(T) == 4 ? "fp32" : "fp64", n, st_aed, st_defl, st_sweeps, st_chase, st_fsw,
+                     st_fst, st_kcyc, st_fst ? 1024.0 * st_kcyc / st_fst : 0.0);
     return 0;
 }
 template int schur_run<float>(hipStream_t, int, float *, int, float *, int, char *, char *, int *);

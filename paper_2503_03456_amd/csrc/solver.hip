@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <vector>
 #include <algorithm>
@@ -31,7 +32,11 @@ namespace sylv {
 struct DevCtx {
     bool ok = false;
     bool checked = false;
+    int dev = 0;
     char *hbuf = nullptr;       // pinned host staging, 64 KiB
+    char *hbuf2 = nullptr;      // second staging buffer (concurrent Schur of B)
+    hipStream_t s2 = nullptr;   // internal stream for the Schur form of B
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     void *work = nullptr;       // cached internal workspace
     size_t work_bytes = 0;
 };
@@ -49,6 +54,11 @@ static int device_ctx(DevCtx **out) {
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return SYLV_ERR_NOGPU;
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SYLV_ERR_NOGPU;
         if (hipHostMalloc((void **)&c.hbuf, 65536, hipHostMallocDefault) != hipSuccess) return SYLV_ERR_ALLOC;
+        if (hipHostMalloc((void **)&c.hbuf2, 65536, hipHostMallocDefault) != hipSuccess) return SYLV_ERR_ALLOC;
+        if (hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking) != hipSuccess) return SYLV_ERR_NOGPU;
+        if (hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming) != hipSuccess) return SYLV_ERR_NOGPU;
+        if (hipEventCreateWithFlags(&c.ev_out, hipEventDisableTiming) != hipSuccess) return SYLV_ERR_NOGPU;
+        c.dev = dev;
         c.ok = true;
     }
     if (!c.ok) return SYLV_ERR_NOGPU;
@@ -85,7 +95,8 @@ struct Arena {
 template <typename T>
 struct Stage {  // buffers of one precision's Bartels-Stewart pipeline
     T *TA, *UA, *TB, *UB, *W1, *Y;
-    char *schur_ws;
+    char *schur_ws;   // Schur workspace for A
+    char *schur_ws2;  // Schur workspace for B (the two run concurrently)
 };
 
 struct Plan {
@@ -109,7 +120,8 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
         p.lo.UB = a.take<float>((size_t)n * n);
         p.lo.W1 = a.take<float>((size_t)m * n);
         p.lo.Y = a.take<float>((size_t)m * n);
-        p.lo.schur_ws = a.take<char>(schur_work_bytes<float>(mx));
+        p.lo.schur_ws = a.take<char>(schur_work_bytes<float>(m));
+        if (!lyap) p.lo.schur_ws2 = a.take<char>(schur_work_bytes<float>(n));
     }
     if (need_hi) {
         p.hi.TA = a.take<double>((size_t)m * m);
@@ -118,7 +130,8 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
         p.hi.UB = a.take<double>((size_t)n * n);
         p.hi.W1 = a.take<double>((size_t)m * n);
         p.hi.Y = a.take<double>((size_t)m * n);
-        p.hi.schur_ws = a.take<char>(schur_work_bytes<double>(mx));
+        p.hi.schur_ws = a.take<char>(schur_work_bytes<double>(m));
+        if (!lyap) p.hi.schur_ws2 = a.take<char>(schur_work_bytes<double>(n));
     }
     p.R = a.take<double>((size_t)m * n);
     if (orth) p.G = a.take<double>((size_t)2 * mx * mx);
@@ -126,7 +139,6 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
     p.nscr = a.take<double>(256);
     p.flag = a.take<int>(64);
     p.eig = a.take<float>((size_t)4 * mx + 64);
-    (void)lyap;
 }
 
 static size_t plan_bytes(int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth) {
@@ -173,19 +185,48 @@ __global__ __launch_bounds__(256) void k_sep_min(int m, int n, const float *wra,
 }
 
 // -------------------------------------------------------- pipeline stages
-template <typename T>
-static int schur_stage(hipStream_t s, int n, const double *A, int lda, Stage<T> &st, T *Tm, T *Um,
-                       char *hbuf, int *qr) {
-    cast<double, T>(s, n, n, A, lda, Tm, n, 1.0);
-    return schur_run<T>(s, n, Tm, n, Um, n, st.schur_ws, hbuf, qr);
-}
-
 // Lyapunov: TB = P TA^T P, UB = UA P
 template <typename T>
 static void lyap_right_factor(hipStream_t s, int n, Stage<T> &st) {
     transpose<T>(s, n, n, st.TA, n, st.TB, n, 1);
     revcols<T, T>(s, n, n, st.UA, n, st.UB, n, T(1));
 }
+
+template <typename T>
+static int schur_stage(hipStream_t s, int n, const double *A, int lda, T *Tm, T *Um, char *ws,
+                       char *hbuf, int *qr) {
+    cast<double, T>(s, n, n, A, lda, Tm, n, 1.0);
+    return schur_run<T>(s, n, Tm, n, Um, n, ws, hbuf, qr);
+}
+
+// Schur forms of A (and of B for Sylvester).  The two factorisations are
+// independent and each is a chain of latency-bound single-workgroup kernels,
+// so B runs concurrently on the context's second stream, driven by a second
+// host thread; the caller's stream waits for it at the end.
+template <typename T>
+static int schur_pair(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
+                      const double *B, int ldb, bool lyap, Stage<T> &st, int *qa, int *qb) {
+    if (lyap) {
+        int rc = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa);
+        if (!rc) lyap_right_factor<T>(s, m, st);
+        return rc;
+    }
+    hipError_t e = hipEventRecord(c->ev_in, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->s2, c->ev_in, 0);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    int rcb = 0;
+    std::thread tb([&]() {
+        hipSetDevice(c->dev);
+        rcb = schur_stage<T>(c->s2, n, B, ldb, st.TB, st.UB, st.schur_ws2, c->hbuf2, qb);
+    });
+    int rca = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa);
+    tb.join();
+    e = hipEventRecord(c->ev_out, c->s2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_out, 0);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    return rca ? rca : rcb;
+}
+
 
 // X (binary64) <- alpha * UA * tri-solve(UA^T op(Rin) UB) * UB^T (+ X when accumulate)
 // Rin is binary64 (C or the residual); bscale scales it before the cast.
@@ -265,13 +306,8 @@ static int run_fp64(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
                     int ldb, bool lyap, const double *C, int ldc, double *X, int ldx, Plan &p,
                     const Norms &nm, sylv_info *info) {
     int qa = 0, qb = 0, rc;
-    rc = schur_stage<double>(s, m, A, lda, p.hi, p.hi.TA, p.hi.UA, c->hbuf, &qa);
+    rc = schur_pair<double>(s, c, m, n, A, lda, B, ldb, lyap, p.hi, &qa, &qb);
     if (rc) return rc;
-    if (lyap) lyap_right_factor<double>(s, m, p.hi);
-    else {
-        rc = schur_stage<double>(s, n, B, ldb, p.hi, p.hi.TB, p.hi.UB, c->hbuf, &qb);
-        if (rc) return rc;
-    }
     matnorm<double>(s, m, m, p.hi.TA, m, p.scal + 10, p.nscr, 1);
     matnorm<double>(s, n, n, p.hi.TB, n, p.scal + 11, p.nscr, 1);
     // maxab = max of both (computed on device by a max-norm over the two slots)
@@ -307,13 +343,8 @@ static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
                      int *ok) {
     *ok = 0;
     int qa = 0, qb = 0, rc;
-    rc = schur_stage<float>(s, m, A, lda, p.lo, p.lo.TA, p.lo.UA, c->hbuf, &qa);
+    rc = schur_pair<float>(s, c, m, n, A, lda, B, ldb, lyap, p.lo, &qa, &qb);
     if (rc) return rc;
-    if (lyap) lyap_right_factor<float>(s, m, p.lo);
-    else {
-        rc = schur_stage<float>(s, n, B, ldb, p.lo, p.lo.TB, p.lo.UB, c->hbuf, &qb);
-        if (rc) return rc;
-    }
     if (o.orth_check) {
         orth_check(s, m, p.lo.UA, p.G, p.scal + 20, p.nscr);
         if (!lyap) orth_check(s, n, p.lo.UB, p.G, p.scal + 21, p.nscr);

@@ -18,6 +18,7 @@
 //      flag is raised (the usual triangular-Sylvester convention).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace sylv {
 
@@ -36,6 +37,7 @@ template <> struct mfma16t<double> {
 constexpr int TS = 64;       // tile capacity
 constexpr int TBASE = 63;    // nominal boundary spacing (adjusted by +1 at 2x2 blocks)
 constexpr int TLD = TS + 1;  // LDS leading dimension of tiles
+constexpr int TBK = 32;      // K slab of the in-tile MFMA update
 
 // Boundary k of a quasi-triangular matrix of order n cut every TBASE rows.
 template <typename T>
@@ -100,8 +102,8 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
     __shared__ T sA[TS * TLD];   // TA diagonal tile, later reused
     __shared__ T sB[TS * TLD];   // TB diagonal tile
     __shared__ T sC[TS * TLD];   // rhs -> Y tile
-    __shared__ T stA[16][TS + 16];
-    __shared__ T stB[16][TS + 16];
+    __shared__ T stA[TBK][TS + 16];
+    __shared__ T stB[TBK][TS + 16];
     __shared__ int rstart[TS + 1], cstart[TS + 1];
     __shared__ int nrb_s, ncb_s;
     typedef typename mfma16t<T>::v4 v4;
@@ -128,22 +130,31 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
         int ldb_;
         if (phase == 0) { Ap = TA + (size_t)r1 * ldta + r0; lda_ = ldta; Bp = C + (size_t)c0 * ldc + r1; ldb_ = ldc; K = m - r1; }
         else { Ap = C + r0; lda_ = ldc; Bp = TB + (size_t)c0 * ldtb; ldb_ = ldtb; K = c0; }
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            // A slab: rows 0..p-1 (of the tile), cols k0..k0+15 ; B slab: rows k0.., cols 0..q-1
+        // A slab: tile rows 0..p-1 x k0..k0+TBK-1 ; B slab: k0.. x tile cols 0..q-1.
+        // Each thread holds 8 elements of each slab; the next slab is loaded
+        // into registers while the current one feeds the MFMAs.
+        T ra[8], rb[8];
+        auto load = [&](int k0) {
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
+            for (int rr = 0; rr < 8; ++rr) {
                 int i = l, k = w + 4 * rr;
-                T v = T(0);
-                if (i < p && k0 + k < K) v = Ap[(size_t)(k0 + k) * lda_ + i];
-                stA[k][i] = v;
-                int kk = t & 15, j = (t >> 4) + 16 * rr;
-                T u = T(0);
-                if (j < q && k0 + kk < K) u = Bp[(size_t)j * ldb_ + k0 + kk];
-                stB[kk][j] = u;
+                ra[rr] = (i < p && k0 + k < K) ? Ap[(size_t)(k0 + k) * lda_ + i] : T(0);
+                int kk = t & 31, j = (t >> 5) + 8 * rr;
+                rb[rr] = (j < q && k0 + kk < K) ? Bp[(size_t)j * ldb_ + k0 + kk] : T(0);
+            }
+        };
+        const int nk = (K + TBK - 1) / TBK;
+        if (nk > 0) load(0);
+        for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+            for (int rr = 0; rr < 8; ++rr) {
+                stA[w + 4 * rr][l] = ra[rr];
+                stB[t & 31][(t >> 5) + 8 * rr] = rb[rr];
             }
             __syncthreads();
+            if (kt + 1 < nk) load((kt + 1) * TBK);
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
+            for (int kk = 0; kk < TBK / 4; ++kk) {
                 const int kr = 4 * kk + (l >> 4);
                 T fa[2], fb[2];
 #pragma unroll
@@ -193,12 +204,15 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
     const T smin = (T)fmax((double)num<T>::ulp * (*maxab), (double)num<T>::safmin);
     int myflag = 0;
     // ---- 2. wavefront over block pairs: unit (ib, jb), ib counted from the
-    // bottom; anti-diagonal e = ib + jb.  Four threads per unit split the sums.
+    // bottom; anti-diagonal e = ib + jb.  A unit's sums over the solved rows
+    // below and columns to the left are split over tpu adjacent lanes (the
+    // largest power of two with tpu * units <= 256).
     for (int e = 0; e <= P + Q - 2; ++e) {
         const int jlo = e - (P - 1) > 0 ? e - (P - 1) : 0;
         const int jhi = e < Q - 1 ? e : Q - 1;
         const int nunits = jhi - jlo + 1;
-        const int u = t >> 2, sub = t & 3;
+        const int tpu = nunits <= 4 ? 64 : nunits <= 8 ? 32 : nunits <= 16 ? 16 : nunits <= 32 ? 8 : 4;
+        const int u = t / tpu, sub = t % tpu;
         T part[4] = {T(0), T(0), T(0), T(0)};
         int ri = 0, pi = 0, cj = 0, qj = 0;
         const bool active = u < nunits;
@@ -208,45 +222,59 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
             ri = rstart[ib]; pi = rstart[ib + 1] - ri;
             cj = cstart[jb]; qj = cstart[jb + 1] - cj;
             // rows below the block: r' in [ri+pi, p) ; cols left: c' in [0, cj)
-            for (int rp = ri + pi + sub; rp < p; rp += 4) {
-                T a0 = sA[rp * TLD + ri];
-                T a1 = (pi == 2) ? sA[rp * TLD + ri + 1] : T(0);
-                T y0 = sC[cj * TLD + rp];
-                T y1 = (qj == 2) ? sC[(cj + 1) * TLD + rp] : T(0);
-                part[0] += a0 * y0; part[1] += a1 * y0;
-                part[2] += a0 * y1; part[3] += a1 * y1;
-            }
-            for (int cp = sub; cp < cj; cp += 4) {
-                T b0 = sB[cj * TLD + cp];
-                T b1 = (qj == 2) ? sB[(cj + 1) * TLD + cp] : T(0);
-                T y0 = sC[cp * TLD + ri];
-                T y1 = (pi == 2) ? sC[cp * TLD + ri + 1] : T(0);
-                part[0] += y0 * b0; part[1] += y1 * b0;
-                part[2] += y0 * b1; part[3] += y1 * b1;
+            if (pi == 1 && qj == 1) {
+#pragma unroll 4
+                for (int rp = ri + 1 + sub; rp < p; rp += tpu) part[0] += sA[rp * TLD + ri] * sC[cj * TLD + rp];
+#pragma unroll 4
+                for (int cp = sub; cp < cj; cp += tpu) part[0] += sC[cp * TLD + ri] * sB[cj * TLD + cp];
+            } else {
+#pragma unroll 2
+                for (int rp = ri + pi + sub; rp < p; rp += tpu) {
+                    T a0 = sA[rp * TLD + ri];
+                    T a1 = (pi == 2) ? sA[rp * TLD + ri + 1] : T(0);
+                    T y0 = sC[cj * TLD + rp];
+                    T y1 = (qj == 2) ? sC[(cj + 1) * TLD + rp] : T(0);
+                    part[0] += a0 * y0; part[1] += a1 * y0;
+                    part[2] += a0 * y1; part[3] += a1 * y1;
+                }
+#pragma unroll 2
+                for (int cp = sub; cp < cj; cp += tpu) {
+                    T b0 = sB[cj * TLD + cp];
+                    T b1 = (qj == 2) ? sB[(cj + 1) * TLD + cp] : T(0);
+                    T y0 = sC[cp * TLD + ri];
+                    T y1 = (pi == 2) ? sC[cp * TLD + ri + 1] : T(0);
+                    part[0] += y0 * b0; part[1] += y1 * b0;
+                    part[2] += y0 * b1; part[3] += y1 * b1;
+                }
             }
         }
+        for (int o = 1; o < tpu; o <<= 1) {
 #pragma unroll
-        for (int z = 0; z < 4; ++z) {
-            part[z] += __shfl_xor(part[z], 1);
-            part[z] += __shfl_xor(part[z], 2);
+            for (int z = 0; z < 4; ++z) part[z] += __shfl_xor(part[z], o);
         }
         if (active && sub == 0) {
-            // rhs (column-major p x q block: index jj*pi + ii)
-            T rhs[4], M[16];
-            for (int z = 0; z < 16; ++z) M[z] = T(0);
-            for (int jj = 0; jj < qj; ++jj)
-                for (int ii = 0; ii < pi; ++ii)
-                    rhs[jj * pi + ii] = sC[(cj + jj) * TLD + ri + ii] - part[jj * 2 + ii];
-            // (I_q (x) TA_ii + TB_jj^T (x) I_p) vec(Y) = vec(rhs)
-            for (int jj = 0; jj < qj; ++jj)
-                for (int ii = 0; ii < pi; ++ii) {
-                    int row = jj * pi + ii;
-                    for (int kk = 0; kk < pi; ++kk) M[(jj * pi + kk) * 4 + row] += sA[(ri + kk) * TLD + ri + ii];
-                    for (int ll = 0; ll < qj; ++ll) M[(ll * pi + ii) * 4 + row] += sB[(cj + jj) * TLD + cj + ll];
-                }
-            myflag |= small_solve<T>(pi * qj, M, rhs, smin);
-            for (int jj = 0; jj < qj; ++jj)
-                for (int ii = 0; ii < pi; ++ii) sC[(cj + jj) * TLD + ri + ii] = rhs[jj * pi + ii];
+            if (pi == 1 && qj == 1) {
+                T d = sA[ri * TLD + ri] + sB[cj * TLD + cj];
+                if (fabs(d) < smin) { d = (d >= T(0)) ? smin : -smin; myflag = 1; }
+                sC[cj * TLD + ri] = (sC[cj * TLD + ri] - part[0]) / d;
+            } else {
+                // rhs (column-major p x q block: index jj*pi + ii)
+                T rhs[4], M[16];
+                for (int z = 0; z < 16; ++z) M[z] = T(0);
+                for (int jj = 0; jj < qj; ++jj)
+                    for (int ii = 0; ii < pi; ++ii)
+                        rhs[jj * pi + ii] = sC[(cj + jj) * TLD + ri + ii] - part[jj * 2 + ii];
+                // (I_q (x) TA_ii + TB_jj^T (x) I_p) vec(Y) = vec(rhs)
+                for (int jj = 0; jj < qj; ++jj)
+                    for (int ii = 0; ii < pi; ++ii) {
+                        int row = jj * pi + ii;
+                        for (int kk = 0; kk < pi; ++kk) M[(jj * pi + kk) * 4 + row] += sA[(ri + kk) * TLD + ri + ii];
+                        for (int ll = 0; ll < qj; ++ll) M[(ll * pi + ii) * 4 + row] += sB[(cj + jj) * TLD + cj + ll];
+                    }
+                myflag |= small_solve<T>(pi * qj, M, rhs, smin);
+                for (int jj = 0; jj < qj; ++jj)
+                    for (int ii = 0; ii < pi; ++ii) sC[(cj + jj) * TLD + ri + ii] = rhs[jj * pi + ii];
+            }
         }
         __syncthreads();
     }
@@ -265,6 +293,7 @@ void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int 
     for (int d = 0; d <= nI + nJ - 2; ++d) {
         int jmin = d - (nI - 1) > 0 ? d - (nI - 1) : 0;
         int jmax = d < nJ - 1 ? d : nJ - 1;
+        ProfScope ps(KID_TRSYL, s);
         hipLaunchKernelGGL((k_trsyl_diag<T>), dim3(jmax - jmin + 1), dim3(256), 0, s, m, n, TA, ldta,
                            TB, ldtb, C, ldc, d, nI, jmin, maxab, flag);
     }
