@@ -233,20 +233,23 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, int spike_on,
                                            T *Zw, int *out, T *wr, T *wi) {
     extern __shared__ unsigned char smem_raw[];
+    // odd leading dimension: row-wise accesses across consecutive columns hit
+    // distinct LDS banks
+    const int L = nw | 1;
     T *Tw = reinterpret_cast<T *>(smem_raw);
-    T *Zl = Tw + nw * nw;
-    T *sp = Zl + nw * nw;  // spike, length nw
+    T *Zl = Tw + L * nw;
+    T *sp = Zl + L * nw;  // spike, length nw
     int *sint = reinterpret_cast<int *>(sp + nw);
     const int tid = threadIdx.x;
     for (int e = tid; e < nw * nw; e += NT) {
         int i = e % nw, j = e / nw;
-        Tw[e] = CM(H, kwtop + i, kwtop + j, ldh);
-        Zl[e] = (i == j) ? T(1) : T(0);
+        Tw[j * L + i] = CM(H, kwtop + i, kwtop + j, ldh);
+        Zl[j * L + i] = (i == j) ? T(1) : T(0);
     }
     __syncthreads();
     int nsw = 0, nst = 0;
     const long long c0 = clock64();
-    int st = francis_lds<T, NT>(nw, Tw, nw, Zl, nw, nw, sint + 1, &nsw, &nst);
+    int st = francis_lds<T, NT>(nw, Tw, L, Zl, L, nw, sint + 1, &nsw, &nst);
     const long long c1 = clock64();
     if (tid == 0) { out[3] = nsw; out[4] = nst; out[5] = (int)((c1 - c0) >> 10); }
     if (st) {
@@ -254,21 +257,21 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
         return;  // window left untouched in global memory
     }
     const T s = spike_on ? CM(H, kwtop, kwtop - 1, ldh) : T(0);
-    for (int j = tid; j < nw; j += NT) sp[j] = s * Zl[j * nw];
+    for (int j = tid; j < nw; j += NT) sp[j] = s * Zl[j * L];
     __syncthreads();
     // deflation test from the bottom (no reordering)
     const T ulp = num<T>::ulp, smlnum = num<T>::safmin * T(nw) / num<T>::ulp;
     int ns = nw;
     while (ns > 0) {
-        bool two = (ns >= 2) && (Tw[(ns - 2) * nw + (ns - 1)] != T(0));
+        bool two = (ns >= 2) && (Tw[(ns - 2) * L + (ns - 1)] != T(0));
         if (!two) {
-            T foo = fabs(Tw[(ns - 1) * nw + (ns - 1)]);
+            T foo = fabs(Tw[(ns - 1) * L + (ns - 1)]);
             if (foo == T(0)) foo = fabs(s);
             if (fabs(sp[ns - 1]) <= fmax(smlnum, ulp * foo)) ns -= 1;
             else break;
         } else {
-            T foo = fabs(Tw[(ns - 1) * nw + (ns - 1)]) +
-                    sqrt(fabs(Tw[(ns - 2) * nw + (ns - 1)])) * sqrt(fabs(Tw[(ns - 1) * nw + (ns - 2)]));
+            T foo = fabs(Tw[(ns - 1) * L + (ns - 1)]) +
+                    sqrt(fabs(Tw[(ns - 2) * L + (ns - 1)])) * sqrt(fabs(Tw[(ns - 1) * L + (ns - 2)]));
             if (foo == T(0)) foo = fabs(s);
             if (fmax(fabs(sp[ns - 1]), fabs(sp[ns - 2])) <= fmax(smlnum, ulp * foo)) ns -= 2;
             else break;
@@ -278,9 +281,9 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
     if (tid == 0) {
         int i = 0;
         while (i < ns) {
-            if (i + 1 < ns && Tw[i * nw + i + 1] != T(0)) {
-                T a = Tw[i * nw + i], b = Tw[(i + 1) * nw + i];
-                T c = Tw[i * nw + i + 1], d = Tw[(i + 1) * nw + i + 1];
+            if (i + 1 < ns && Tw[i * L + i + 1] != T(0)) {
+                T a = Tw[i * L + i], b = Tw[(i + 1) * L + i];
+                T c = Tw[i * L + i + 1], d = Tw[(i + 1) * L + i + 1];
                 T p = T(0.5) * (a - d), disc = p * p + b * c, mid = T(0.5) * (a + d);
                 if (disc >= T(0)) {
                     T r = sqrt(disc);
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
                 }
                 i += 2;
             } else {
-                wr[i] = Tw[i * nw + i]; wi[i] = T(0);
+                wr[i] = Tw[i * L + i]; wi[i] = T(0);
                 i += 1;
             }
         }
@@ -328,23 +331,23 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
             // left: rows 0..ns-1, all columns
             for (int j = tid; j < nw; j += NT) {
                 T acc = T(0);
-                for (int i = 0; i < ns; ++i) acc += sp[i] * Tw[j * nw + i];
+                for (int i = 0; i < ns; ++i) acc += sp[i] * Tw[j * L + i];
                 acc *= tau;
-                for (int i = 0; i < ns; ++i) Tw[j * nw + i] -= acc * sp[i];
+                for (int i = 0; i < ns; ++i) Tw[j * L + i] -= acc * sp[i];
             }
             __syncthreads();
             // right: columns 0..ns-1, rows 0..ns-1 (rows below are zero there)
             for (int i = tid; i < ns; i += NT) {
                 T acc = T(0);
-                for (int j = 0; j < ns; ++j) acc += Tw[j * nw + i] * sp[j];
+                for (int j = 0; j < ns; ++j) acc += Tw[j * L + i] * sp[j];
                 acc *= tau;
-                for (int j = 0; j < ns; ++j) Tw[j * nw + i] -= acc * sp[j];
+                for (int j = 0; j < ns; ++j) Tw[j * L + i] -= acc * sp[j];
             }
             for (int i = tid; i < nw; i += NT) {
                 T acc = T(0);
-                for (int j = 0; j < ns; ++j) acc += Zl[j * nw + i] * sp[j];
+                for (int j = 0; j < ns; ++j) acc += Zl[j * L + i] * sp[j];
                 acc *= tau;
-                for (int j = 0; j < ns; ++j) Zl[j * nw + i] -= acc * sp[j];
+                for (int j = 0; j < ns; ++j) Zl[j * L + i] -= acc * sp[j];
             }
             __syncthreads();
         }
@@ -354,19 +357,19 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
         for (int c = 0; c + 2 < ns; ++c) {
             const int len = ns - c - 1;  // rows c+1..ns-1
             if (tid == 0) {
-                T alpha = Tw[c * nw + c + 1];
+                T alpha = Tw[c * L + c + 1];
                 T mx = T(0);
-                for (int i = 1; i < len; ++i) mx = fmax(mx, fabs(Tw[c * nw + c + 1 + i]));
+                for (int i = 1; i < len; ++i) mx = fmax(mx, fabs(Tw[c * L + c + 1 + i]));
                 if (mx == T(0)) { sh_tau = T(0); sh_beta = alpha; v[0] = T(1); for (int i = 1; i < len; ++i) v[i] = T(0); }
                 else {
                     T ss = T(0);
-                    for (int i = 1; i < len; ++i) { T q = Tw[c * nw + c + 1 + i] / mx; ss += q * q; }
+                    for (int i = 1; i < len; ++i) { T q = Tw[c * L + c + 1 + i] / mx; ss += q * q; }
                     T xn = mx * sqrt(ss), nrm = hypot(alpha, xn);
                     T b = (alpha >= T(0)) ? -nrm : nrm;
                     sh_tau = (b - alpha) / b;
                     T sc = T(1) / (alpha - b);
                     v[0] = T(1);
-                    for (int i = 1; i < len; ++i) v[i] = Tw[c * nw + c + 1 + i] * sc;
+                    for (int i = 1; i < len; ++i) v[i] = Tw[c * L + c + 1 + i] * sc;
                     sh_beta = b;
                 }
             }
@@ -375,28 +378,28 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
             if (tau != T(0)) {
                 for (int j = c + 1 + tid; j < nw; j += NT) {
                     T acc = T(0);
-                    for (int i = 0; i < len; ++i) acc += v[i] * Tw[j * nw + c + 1 + i];
+                    for (int i = 0; i < len; ++i) acc += v[i] * Tw[j * L + c + 1 + i];
                     acc *= tau;
-                    for (int i = 0; i < len; ++i) Tw[j * nw + c + 1 + i] -= acc * v[i];
+                    for (int i = 0; i < len; ++i) Tw[j * L + c + 1 + i] -= acc * v[i];
                 }
                 __syncthreads();
                 for (int i = tid; i < ns; i += NT) {
                     T acc = T(0);
-                    for (int j = 0; j < len; ++j) acc += Tw[(c + 1 + j) * nw + i] * v[j];
+                    for (int j = 0; j < len; ++j) acc += Tw[(c + 1 + j) * L + i] * v[j];
                     acc *= tau;
-                    for (int j = 0; j < len; ++j) Tw[(c + 1 + j) * nw + i] -= acc * v[j];
+                    for (int j = 0; j < len; ++j) Tw[(c + 1 + j) * L + i] -= acc * v[j];
                 }
                 for (int i = tid; i < nw; i += NT) {
                     T acc = T(0);
-                    for (int j = 0; j < len; ++j) acc += Zl[(c + 1 + j) * nw + i] * v[j];
+                    for (int j = 0; j < len; ++j) acc += Zl[(c + 1 + j) * L + i] * v[j];
                     acc *= tau;
-                    for (int j = 0; j < len; ++j) Zl[(c + 1 + j) * nw + i] -= acc * v[j];
+                    for (int j = 0; j < len; ++j) Zl[(c + 1 + j) * L + i] -= acc * v[j];
                 }
             }
             __syncthreads();
             if (tid == 0) {
-                Tw[c * nw + c + 1] = sh_beta;
-                for (int i = 1; i < len; ++i) Tw[c * nw + c + 1 + i] = T(0);
+                Tw[c * L + c + 1] = sh_beta;
+                for (int i = 1; i < len; ++i) Tw[c * L + c + 1 + i] = T(0);
             }
             __syncthreads();
         }
@@ -404,8 +407,8 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
     // write back: window, spike column, Zw
     for (int e = tid; e < nw * nw; e += NT) {
         int i = e % nw, j = e / nw;
-        CM(H, kwtop + i, kwtop + j, ldh) = Tw[e];
-        Zw[e] = Zl[e];
+        CM(H, kwtop + i, kwtop + j, ldh) = Tw[j * L + i];
+        Zw[e] = Zl[j * L + i];
     }
     if (spike_on) {
         for (int i = tid; i < nw; i += NT) CM(H, kwtop + i, kwtop - 1, ldh) = (i == 0) ? newsub : T(0);
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
 
 template <typename T>
 size_t aed_smem(int nw) {
-    return sizeof(T) * ((size_t)2 * nw * nw + nw) + 4 * sizeof(int);
+    return sizeof(T) * ((size_t)2 * (nw | 1) * nw + nw) + 8 * sizeof(int);
 }
 
 template <typename T>
@@ -461,49 +464,59 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
                                              int t0, int adv, int nbulge, const T *trd,
                                              T *Uw_out) {
     extern __shared__ unsigned char smem_raw[];
+    const int L = W | 1;  // odd leading dimension: conflict-free row-wise access
     T *Hw = reinterpret_cast<T *>(smem_raw);
-    T *Uw = Hw + W * W;
-    T *refl = Uw + W * W;  // per bulge: v1, v2, tau, beta
-    int *rinfo = reinterpret_cast<int *>(refl + 4 * nbulge);  // per bulge: local row q (or -1), len
+    T *Uw = Hw + L * W;
+    T *refl = Uw + L * W;  // per bulge: v1, v2, tau, beta
+    int *rinfo = reinterpret_cast<int *>(refl + 4 * nbulge);  // per bulge: q (or -1), len, ulo, uhi
+    int *ulo = rinfo + 4 * nbulge;  // per column of Uw: nonzero row range
+    int *uhi = ulo + W;
     const int tid = threadIdx.x;
     const int N = kbot - ktop + 1;
     for (int e = tid; e < W * W; e += NT) {
         int i = e % W, j = e / W;
-        Hw[e] = CM(H, ws + i, ws + j, ldh);
-        Uw[e] = (i == j) ? T(1) : T(0);
+        Hw[j * L + i] = CM(H, ws + i, ws + j, ldh);
+        Uw[j * L + i] = (i == j) ? T(1) : T(0);
     }
+    for (int j = tid; j < W; j += NT) { ulo[j] = j; uhi[j] = j; }
     __syncthreads();
     const int kb = kbot - ws;  // local index of kbot
     const int tpb = NT / nbulge;             // threads per bulge (nbulge <= NT)
     const int myb = tid / tpb, slot = tid % tpb;
     for (int t = t0; t < t0 + adv; ++t) {
-        // phase 0: reflectors of the active bulges
+        // phase 0: reflectors of the active bulges, and the row range of Uw
+        // their columns can touch (interval hull of the three columns' ranges;
+        // columns of distinct bulges are disjoint)
         for (int b = tid; b < nbulge; b += NT) {
             int p = t - 3 * b;
-            if (p < 0 || p > N - 2) { rinfo[2 * b] = -1; continue; }
+            if (p < 0 || p > N - 2) { rinfo[4 * b] = -1; continue; }
             int q = ktop + p - ws;  // local row of the reflector
             int len = (p <= N - 3) ? 3 : 2;
             T x, y, z;
             if (p == 0) {
                 T tr = trd[2 * b], det = trd[2 * b + 1];
-                T a00 = Hw[q * W + q], a01 = Hw[(q + 1) * W + q], a10 = Hw[q * W + q + 1];
-                T a11 = Hw[(q + 1) * W + q + 1], a21 = Hw[(q + 1) * W + q + 2];
+                T a00 = Hw[q * L + q], a01 = Hw[(q + 1) * L + q], a10 = Hw[q * L + q + 1];
+                T a11 = Hw[(q + 1) * L + q + 1], a21 = Hw[(q + 1) * L + q + 2];
                 T sc = fabs(a00) + fabs(a10) + fabs(a01) + fabs(a11) + fabs(a21) + fabs(tr) + sqrt(fabs(det));
                 if (sc == T(0)) sc = T(1);
-                T b00 = a00 / sc, b01 = a01 / sc, b10 = a10 / sc, b11 = a11 / sc, b21 = a21 / sc;
-                T trs = tr / sc, dets = det / (sc * sc);
+                T rs = T(1) / sc;
+                T b00 = a00 * rs, b01 = a01 * rs, b10 = a10 * rs, b11 = a11 * rs, b21 = a21 * rs;
+                T trs = tr * rs, dets = det * rs * rs;
                 x = b00 * b00 + b01 * b10 - trs * b00 + dets;
                 y = b10 * (b00 + b11 - trs);
                 z = b10 * b21;
             } else {
-                x = Hw[(q - 1) * W + q];
-                y = Hw[(q - 1) * W + q + 1];
-                z = (len == 3) ? Hw[(q - 1) * W + q + 2] : T(0);
+                x = Hw[(q - 1) * L + q];
+                y = Hw[(q - 1) * L + q + 1];
+                z = (len == 3) ? Hw[(q - 1) * L + q + 2] : T(0);
             }
             T v1, v2, tau, beta;
             reflector3(len, x, y, z, v1, v2, tau, beta);
             refl[4 * b] = v1; refl[4 * b + 1] = v2; refl[4 * b + 2] = tau; refl[4 * b + 3] = beta;
-            rinfo[2 * b] = q; rinfo[2 * b + 1] = len;
+            int lo = ulo[q], hi = uhi[q];
+            for (int c = 1; c < len; ++c) { lo = min(lo, ulo[q + c]); hi = max(hi, uhi[q + c]); }
+            for (int c = 0; c < len; ++c) { ulo[q + c] = lo; uhi[q + c] = hi; }
+            rinfo[4 * b] = q; rinfo[4 * b + 1] = len; rinfo[4 * b + 2] = lo; rinfo[4 * b + 3] = hi;
         }
         __syncthreads();
         // Each active bulge gets a fixed group of tpb threads; a thread works
@@ -511,48 +524,50 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
         // phase A: left applications, rows q..q+len-1, columns q-1 (p>0: set
         // beta, zeros) and q..W-1.  Distinct bulges touch distinct rows.
         if (myb < nbulge) {
-            const int q = rinfo[2 * myb];
+            const int q = rinfo[4 * myb];
             if (q >= 0) {
-                const int len = rinfo[2 * myb + 1];
+                const int len = rinfo[4 * myb + 1];
                 const T v1 = refl[4 * myb], v2 = refl[4 * myb + 1], tau = refl[4 * myb + 2];
                 const bool intro = (t - 3 * myb == 0);
                 const int c0 = intro ? q : q - 1;
 #pragma unroll 2
                 for (int j = c0 + slot; j < W; j += tpb) {
                     if (!intro && j == q - 1) {
-                        Hw[j * W + q] = refl[4 * myb + 3];
-                        Hw[j * W + q + 1] = T(0);
-                        if (len == 3) Hw[j * W + q + 2] = T(0);
+                        Hw[j * L + q] = refl[4 * myb + 3];
+                        Hw[j * L + q + 1] = T(0);
+                        if (len == 3) Hw[j * L + q + 2] = T(0);
                         continue;
                     }
-                    T a0 = Hw[j * W + q], a1 = Hw[j * W + q + 1];
-                    T a2 = (len == 3) ? Hw[j * W + q + 2] : T(0);
+                    T a0 = Hw[j * L + q], a1 = Hw[j * L + q + 1];
+                    T a2 = (len == 3) ? Hw[j * L + q + 2] : T(0);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
-                    Hw[j * W + q] = a0; Hw[j * W + q + 1] = a1;
-                    if (len == 3) Hw[j * W + q + 2] = a2;
+                    Hw[j * L + q] = a0; Hw[j * L + q + 1] = a1;
+                    if (len == 3) Hw[j * L + q + 2] = a2;
                 }
             }
         }
         __syncthreads();
         // phase B: right applications on columns q..q+len-1 (rows 0..min(q+3, kb))
-        // and on Uw (all rows).  Distinct bulges touch distinct columns.
+        // and on Uw (rows ulo..uhi only).  Distinct bulges touch distinct columns.
         if (myb < nbulge) {
-            const int q = rinfo[2 * myb];
+            const int q = rinfo[4 * myb];
             if (q >= 0) {
-                const int len = rinfo[2 * myb + 1];
+                const int len = rinfo[4 * myb + 1];
+                const int lo = rinfo[4 * myb + 2], hi = rinfo[4 * myb + 3];
                 const T v1 = refl[4 * myb], v2 = refl[4 * myb + 1], tau = refl[4 * myb + 2];
                 int rmax = q + 3 < kb ? q + 3 : kb;
                 if (rmax > W - 1) rmax = W - 1;
                 const int nr = rmax + 1;
+                const int nu = hi - lo + 1;
 #pragma unroll 2
-                for (int e = slot; e < nr + W; e += tpb) {
+                for (int e = slot; e < nr + nu; e += tpb) {
                     T *M = (e < nr) ? Hw : Uw;
-                    int i = (e < nr) ? e : e - nr;
-                    T a0 = M[q * W + i], a1 = M[(q + 1) * W + i];
-                    T a2 = (len == 3) ? M[(q + 2) * W + i] : T(0);
+                    int i = (e < nr) ? e : lo + (e - nr);
+                    T a0 = M[q * L + i], a1 = M[(q + 1) * L + i];
+                    T a2 = (len == 3) ? M[(q + 2) * L + i] : T(0);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
-                    M[q * W + i] = a0; M[(q + 1) * W + i] = a1;
-                    if (len == 3) M[(q + 2) * W + i] = a2;
+                    M[q * L + i] = a0; M[(q + 1) * L + i] = a1;
+                    if (len == 3) M[(q + 2) * L + i] = a2;
                 }
             }
         }
@@ -560,14 +575,14 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
     }
     for (int e = tid; e < W * W; e += NT) {
         int i = e % W, j = e / W;
-        CM(H, ws + i, ws + j, ldh) = Hw[e];
-        Uw_out[e] = Uw[e];
+        CM(H, ws + i, ws + j, ldh) = Hw[j * L + i];
+        Uw_out[e] = Uw[j * L + i];
     }
 }
 
 template <typename T>
 size_t chase_smem(int W, int nbulge) {
-    return sizeof(T) * ((size_t)2 * W * W + 4 * nbulge) + sizeof(int) * 2 * nbulge;
+    return sizeof(T) * ((size_t)2 * (W | 1) * W + 4 * nbulge) + sizeof(int) * (4 * nbulge + 2 * W);
 }
 
 template <typename T>

@@ -49,48 +49,70 @@ SYLV_DEVINL int tile_bound(const T *Tm, int ld, int n, int k) {
     return b;
 }
 
-// Small dense solve M z = r (k <= 4, M column-major ld 4) by Gaussian
-// elimination with complete pivoting; small pivots are perturbed to smin.
+// Block-pair system of the tri-solve: TA_ii Y + Y TB_jj = R with TA_ii, TB_jj
+// of order 1 or 2.  The unknowns are embedded in a fixed 4-vector
+// (y00, y10, y01, y11) -- an order-1 block leaves its entries as identity
+// rows -- so every lane runs the same straight-line code with static
+// register indices: Gaussian elimination with partial pivoting, a pivot
+// below smin replaced by +-smin (flag set).
 template <typename T>
-SYLV_DEVINL int small_solve(int k, T M[16], T r[4], T smin) {
-    int perm[4] = {0, 1, 2, 3};
+SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T b01, T b10, T b11,
+                           T r[4], T smin) {
+    T m[4][4];
+    const T zp = P ? T(1) : T(0), zq = Q ? T(1) : T(0), zpq = zp * zq;
+    m[0][0] = a00 + b00;       m[0][1] = a01 * zp;        m[0][2] = b10 * zq;        m[0][3] = T(0);
+    m[1][0] = a10 * zp;        m[1][1] = P ? a11 + b00 : T(1); m[1][2] = T(0);      m[1][3] = b10 * zpq;
+    m[2][0] = b01 * zq;        m[2][1] = T(0);            m[2][2] = Q ? a00 + b11 : T(1); m[2][3] = a01 * zpq;
+    m[3][0] = T(0);            m[3][1] = b01 * zpq;       m[3][2] = a10 * zpq;       m[3][3] = (P && Q) ? a11 + b11 : T(1);
+    if (!P) r[1] = T(0);
+    if (!Q) r[2] = T(0);
+    if (!(P && Q)) r[3] = T(0);
     int flag = 0;
-    for (int p = 0; p < k; ++p) {
-        int bi = p, bj = p;
-        T bv = T(-1);
-        for (int j = p; j < k; ++j)
-            for (int i = p; i < k; ++i) {
-                T a = fabs(M[j * 4 + i]);
-                if (a > bv) { bv = a; bi = i; bj = j; }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        // pivot: largest |m[r][c]|, r >= c; swap it into row c with selects
+        int pr = c;
+        T pv = fabs(m[c][c]);
+#pragma unroll
+        for (int rr = c + 1; rr < 4; ++rr) {
+            T v = fabs(m[rr][c]);
+            if (v > pv) { pv = v; pr = rr; }
+        }
+#pragma unroll
+        for (int rr = c + 1; rr < 4; ++rr) {
+            const bool sw = (pr == rr);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                T x = m[c][k], y = m[rr][k];
+                m[c][k] = sw ? y : x;
+                m[rr][k] = sw ? x : y;
             }
-        if (bi != p) {
-            for (int j = 0; j < 4; ++j) { T t = M[j * 4 + p]; M[j * 4 + p] = M[j * 4 + bi]; M[j * 4 + bi] = t; }
-            T t = r[p]; r[p] = r[bi]; r[bi] = t;
+            T x = r[c], y = r[rr];
+            r[c] = sw ? y : x;
+            r[rr] = sw ? x : y;
         }
-        if (bj != p) {
-            for (int i = 0; i < 4; ++i) { T t = M[p * 4 + i]; M[p * 4 + i] = M[bj * 4 + i]; M[bj * 4 + i] = t; }
-            int t = perm[p]; perm[p] = perm[bj]; perm[bj] = t;
-        }
-        T piv = M[p * 4 + p];
+        T piv = m[c][c];
         if (fabs(piv) < smin) {
             piv = (piv >= T(0)) ? smin : -smin;
-            M[p * 4 + p] = piv;
+            m[c][c] = piv;
             flag = 1;
         }
-        T inv = T(1) / piv;
-        for (int i = p + 1; i < k; ++i) {
-            T f = M[p * 4 + i] * inv;
-            for (int j = p + 1; j < k; ++j) M[j * 4 + i] -= f * M[j * 4 + p];
-            r[i] -= f * r[p];
+        const T inv = T(1) / piv;
+#pragma unroll
+        for (int rr = c + 1; rr < 4; ++rr) {
+            const T f = m[rr][c] * inv;
+#pragma unroll
+            for (int k = c + 1; k < 4; ++k) m[rr][k] -= f * m[c][k];
+            r[rr] -= f * r[c];
         }
     }
-    T z[4];
-    for (int i = k - 1; i >= 0; --i) {
-        T s = r[i];
-        for (int j = i + 1; j < k; ++j) s -= M[j * 4 + i] * z[j];
-        z[i] = s / M[i * 4 + i];
+#pragma unroll
+    for (int c = 3; c >= 0; --c) {
+        T acc = r[c];
+#pragma unroll
+        for (int k = c + 1; k < 4; ++k) acc -= m[c][k] * r[k];
+        r[c] = acc / m[c][c];
     }
-    for (int i = 0; i < k; ++i) r[perm[i]] = z[i];
     return flag;
 }
 
@@ -258,22 +280,26 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
                 if (fabs(d) < smin) { d = (d >= T(0)) ? smin : -smin; myflag = 1; }
                 sC[cj * TLD + ri] = (sC[cj * TLD + ri] - part[0]) / d;
             } else {
-                // rhs (column-major p x q block: index jj*pi + ii)
-                T rhs[4], M[16];
-                for (int z = 0; z < 16; ++z) M[z] = T(0);
-                for (int jj = 0; jj < qj; ++jj)
-                    for (int ii = 0; ii < pi; ++ii)
-                        rhs[jj * pi + ii] = sC[(cj + jj) * TLD + ri + ii] - part[jj * 2 + ii];
-                // (I_q (x) TA_ii + TB_jj^T (x) I_p) vec(Y) = vec(rhs)
-                for (int jj = 0; jj < qj; ++jj)
-                    for (int ii = 0; ii < pi; ++ii) {
-                        int row = jj * pi + ii;
-                        for (int kk = 0; kk < pi; ++kk) M[(jj * pi + kk) * 4 + row] += sA[(ri + kk) * TLD + ri + ii];
-                        for (int ll = 0; ll < qj; ++ll) M[(ll * pi + ii) * 4 + row] += sB[(cj + jj) * TLD + cj + ll];
-                    }
-                myflag |= small_solve<T>(pi * qj, M, rhs, smin);
-                for (int jj = 0; jj < qj; ++jj)
-                    for (int ii = 0; ii < pi; ++ii) sC[(cj + jj) * TLD + ri + ii] = rhs[jj * pi + ii];
+                const bool P = (pi == 2), Q = (qj == 2);
+                const T a00 = sA[ri * TLD + ri];
+                const T a01 = P ? sA[(ri + 1) * TLD + ri] : T(0);
+                const T a10 = P ? sA[ri * TLD + ri + 1] : T(0);
+                const T a11 = P ? sA[(ri + 1) * TLD + ri + 1] : T(0);
+                const T b00 = sB[cj * TLD + cj];
+                const T b01 = Q ? sB[(cj + 1) * TLD + cj] : T(0);
+                const T b10 = Q ? sB[cj * TLD + cj + 1] : T(0);
+                const T b11 = Q ? sB[(cj + 1) * TLD + cj + 1] : T(0);
+                // rhs entries (y00, y10, y01, y11) minus the accumulated sums
+                T r[4];
+                r[0] = sC[cj * TLD + ri] - part[0];
+                r[1] = P ? sC[cj * TLD + ri + 1] - part[1] : T(0);
+                r[2] = Q ? sC[(cj + 1) * TLD + ri] - part[2] : T(0);
+                r[3] = (P && Q) ? sC[(cj + 1) * TLD + ri + 1] - part[3] : T(0);
+                myflag |= pair_solve<T>(P, Q, a00, a01, a10, a11, b00, b01, b10, b11, r, smin);
+                sC[cj * TLD + ri] = r[0];
+                if (P) sC[cj * TLD + ri + 1] = r[1];
+                if (Q) sC[(cj + 1) * TLD + ri] = r[2];
+                if (P && Q) sC[(cj + 1) * TLD + ri + 1] = r[3];
             }
         }
         __syncthreads();
