@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed plain binary64 solves")
-    ap.add_argument("--roofline-kernel", default="k_chase")
+    ap.add_argument("--roofline-kernel", default="k_aed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=768)
     args = ap.parse_args()
@@ -188,14 +188,14 @@ def main():
 
 def roofline_entry(kname, launches, total_ms, work, steps, step_s):
     """Roofline object of the dominant kernel.  `work` is the algorithmic
-    flop count the library accounted for the timed launches (k_chase: every
-    application of a bulge reflector to a window row or column, 12 flops for
-    length 3 and 8 for length 2; gemm_kernel: 2mnk).  The chase works on an
-    LDS-resident window with vector ALU arithmetic, so its roof is the fp32
-    vector peak of the chip."""
+    flop count the library accounted for the timed launches (k_aed, k_chase:
+    every application of a 3x3 bulge reflector to a window row or column,
+    including the accumulated orthogonal factor, 12 flops; gemm_kernel: 2mnk).
+    The QR kernels work on an LDS-resident window with vector ALU arithmetic,
+    so their roof is the fp32 vector peak of the chip."""
     avg_ms = total_ms / launches
     ach = work / (total_ms * 1e-3) / 1e12 if total_ms > 0 else 0.0
-    bound = "alu" if kname == "k_chase" else "mfma"
+    bound = "alu" if kname in ("k_chase", "k_aed") else "mfma"
     peak = PEAKS["fp32_TFLOPs"]
     return {"kernel": kname, "bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
             "frac": ach / peak, "traffic": None, "avg_launch_ms": avg_ms,

@@ -211,7 +211,8 @@ int sylv_selector_features(int m, int n, const double *A, int lda, const double 
  * HIP events recorded on its launch stream.  sylv_profile_end disarms,
  * waits for the events and returns the number of launches and the summed
  * durations in milliseconds, plus the algorithmic work the library
- * accounts for those launches (flops; k_chase and gemm_kernel only, else 0)
+ * accounts for those launches (flops: gemm_kernel 2mnk; k_chase and k_aed
+ * 12 flops per length-3 reflector application to a row or column; else 0)
  * (host pointers, may be NULL).
  * ---------------------------------------------------------------------- */
 int sylv_profile_begin(int kernel_id);

@@ -69,14 +69,16 @@ SYLV_DEVINL void std2x2_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int k) 
     __syncthreads();
 }
 
-// Apply the reflector (1, v1, v2) with tau to a 3-vector (len 2 or 3).
+// Apply the reflector (1, v1, v2) with tau to a 3-vector.  A length-2
+// reflector has v2 = 0 and leaves a2 unchanged, so callers load a2 from a
+// clamped (valid) index and store it before a0/a1: no branches around LDS
+// accesses, which lets the loads of one item issue together.
 template <typename T>
-SYLV_DEVINL void refl_apply(int len, T v1, T v2, T tau, T &a0, T &a1, T &a2) {
-    T s = a0 + v1 * a1 + (len == 3 ? v2 * a2 : T(0));
-    s *= tau;
+SYLV_DEVINL void refl_apply(int, T v1, T v2, T tau, T &a0, T &a1, T &a2) {
+    T s = (a0 + v1 * a1 + v2 * a2) * tau;
     a0 -= s;
     a1 -= s * v1;
-    if (len == 3) a2 -= s * v2;
+    a2 -= s * v2;
 }
 
 // Francis double-shift QR on an n x n upper Hessenberg H in LDS (full Schur
@@ -144,7 +146,7 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
             if (k > l) {
                 x = CM(H, k, k - 1, ldh);
                 y = CM(H, k + 1, k - 1, ldh);
-                z = (len == 3) ? CM(H, k + 2, k - 1, ldh) : T(0);
+                z = CM(H, (len == 3) ? k + 2 : k + 1, k - 1, ldh);
             }
             T v1, v2, tau, beta;
             reflector3(len, x, y, z, v1, v2, tau, beta);
@@ -157,59 +159,54 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
             static_assert(NWV >= 4, "francis_lds needs at least 4 waves");
             const int wv = tid >> 6, lane = tid & 63;
             const int lc0 = (k > l) ? 1 : 0;                  // column k-1
+            const int k2 = (len == 3) ? k + 2 : k + 1;  // clamped third index
             if (wv == 0) {
                 const int nL = lc0 + (n - (k + len));
                 for (int q = lane; q < nL; q += 64) {
                     if (lc0 && q == 0) {
-                        CM(H, k, k - 1, ldh) = beta;
+                        CM(H, k2, k - 1, ldh) = T(0);
                         CM(H, k + 1, k - 1, ldh) = T(0);
-                        if (len == 3) CM(H, k + 2, k - 1, ldh) = T(0);
+                        CM(H, k, k - 1, ldh) = beta;
                     } else {
-                        int j = k + len + q - lc0;
-                        T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh);
-                        T a2 = (len == 3) ? CM(H, k + 2, j, ldh) : T(0);
+                        const int j = k + len + q - lc0;
+                        T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh), a2 = CM(H, k2, j, ldh);
                         refl_apply(len, v1, v2, tau, a0, a1, a2);
-                        CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
-                        if (len == 3) CM(H, k + 2, j, ldh) = a2;
+                        CM(H, k2, j, ldh) = a2; CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
                     }
                 }
             } else if (wv == 1) {
                 const int extra = (len == 3 && k + 3 <= ihi) ? 1 : 0;
                 const int nR = k + extra;
                 for (int q = lane; q < nR; q += 64) {
-                    int i = (q < k) ? q : k + 3;
-                    T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh);
-                    T a2 = (len == 3) ? CM(H, i, k + 2, ldh) : T(0);
+                    const int i = (q < k) ? q : k + 3;
+                    T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh), a2 = CM(H, i, k2, ldh);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
-                    CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
-                    if (len == 3) CM(H, i, k + 2, ldh) = a2;
+                    CM(H, i, k2, ldh) = a2; CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
                 }
             } else if (wv < NWV - 1) {
                 for (int i = tid - 128; i < nz; i += NT - 192) {
-                    T a0 = CM(Z, i, k, ldz), a1 = CM(Z, i, k + 1, ldz);
-                    T a2 = (len == 3) ? CM(Z, i, k + 2, ldz) : T(0);
+                    T a0 = CM(Z, i, k, ldz), a1 = CM(Z, i, k + 1, ldz), a2 = CM(Z, i, k2, ldz);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
-                    CM(Z, i, k, ldz) = a0; CM(Z, i, k + 1, ldz) = a1;
-                    if (len == 3) CM(Z, i, k + 2, ldz) = a2;
+                    CM(Z, i, k2, ldz) = a2; CM(Z, i, k, ldz) = a0; CM(Z, i, k + 1, ldz) = a1;
                 }
             } else if (lane == 0) {
-                // overlap block in registers: left then right on
-                // rows/cols k..k+len-1 (one LDS load round, one store round)
+                // overlap block in registers: left then right on rows/cols
+                // k, k+1, k2 (k2 = k+1 duplicates for a length-2 step: the
+                // duplicate is stored first so the genuine value wins)
+                const int ix[3] = {k, k + 1, k2};
                 T b[3][3];
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj)
 #pragma unroll
-                    for (int ii = 0; ii < 3; ++ii)
-                        b[ii][jj] = (ii < len && jj < len) ? CM(H, k + ii, k + jj, ldh) : T(0);
+                    for (int ii = 0; ii < 3; ++ii) b[ii][jj] = CM(H, ix[ii], ix[jj], ldh);
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj) refl_apply(len, v1, v2, tau, b[0][jj], b[1][jj], b[2][jj]);
 #pragma unroll
                 for (int ii = 0; ii < 3; ++ii) refl_apply(len, v1, v2, tau, b[ii][0], b[ii][1], b[ii][2]);
 #pragma unroll
-                for (int jj = 0; jj < 3; ++jj)
+                for (int jj = 2; jj >= 0; --jj)
 #pragma unroll
-                    for (int ii = 0; ii < 3; ++ii)
-                        if (ii < len && jj < len) CM(H, k + ii, k + jj, ldh) = b[ii][jj];
+                    for (int ii = 2; ii >= 0; --ii) CM(H, ix[ii], ix[jj], ldh) = b[ii][jj];
             }
             __syncthreads();
         }
@@ -508,7 +505,7 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
             } else {
                 x = Hw[(q - 1) * L + q];
                 y = Hw[(q - 1) * L + q + 1];
-                z = (len == 3) ? Hw[(q - 1) * L + q + 2] : T(0);
+                z = Hw[(q - 1) * L + ((len == 3) ? q + 2 : q + 1)];
             }
             T v1, v2, tau, beta;
             reflector3(len, x, y, z, v1, v2, tau, beta);
@@ -530,19 +527,18 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
                 const T v1 = refl[4 * myb], v2 = refl[4 * myb + 1], tau = refl[4 * myb + 2];
                 const bool intro = (t - 3 * myb == 0);
                 const int c0 = intro ? q : q - 1;
+                const int q2 = (len == 3) ? q + 2 : q + 1;  // clamped third row
 #pragma unroll 2
                 for (int j = c0 + slot; j < W; j += tpb) {
                     if (!intro && j == q - 1) {
-                        Hw[j * L + q] = refl[4 * myb + 3];
+                        Hw[j * L + q2] = T(0);
                         Hw[j * L + q + 1] = T(0);
-                        if (len == 3) Hw[j * L + q + 2] = T(0);
+                        Hw[j * L + q] = refl[4 * myb + 3];
                         continue;
                     }
-                    T a0 = Hw[j * L + q], a1 = Hw[j * L + q + 1];
-                    T a2 = (len == 3) ? Hw[j * L + q + 2] : T(0);
+                    T a0 = Hw[j * L + q], a1 = Hw[j * L + q + 1], a2 = Hw[j * L + q2];
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
-                    Hw[j * L + q] = a0; Hw[j * L + q + 1] = a1;
-                    if (len == 3) Hw[j * L + q + 2] = a2;
+                    Hw[j * L + q2] = a2; Hw[j * L + q] = a0; Hw[j * L + q + 1] = a1;
                 }
             }
         }
@@ -559,15 +555,14 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
                 if (rmax > W - 1) rmax = W - 1;
                 const int nr = rmax + 1;
                 const int nu = hi - lo + 1;
+                const int q2 = (len == 3) ? q + 2 : q + 1;  // clamped third column
 #pragma unroll 2
                 for (int e = slot; e < nr + nu; e += tpb) {
                     T *M = (e < nr) ? Hw : Uw;
                     int i = (e < nr) ? e : lo + (e - nr);
-                    T a0 = M[q * L + i], a1 = M[(q + 1) * L + i];
-                    T a2 = (len == 3) ? M[(q + 2) * L + i] : T(0);
+                    T a0 = M[q * L + i], a1 = M[(q + 1) * L + i], a2 = M[q2 * L + i];
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
-                    M[q * L + i] = a0; M[(q + 1) * L + i] = a1;
-                    if (len == 3) M[(q + 2) * L + i] = a2;
+                    M[q2 * L + i] = a2; M[q * L + i] = a0; M[(q + 1) * L + i] = a1;
                 }
             }
         }
@@ -590,7 +585,7 @@ int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W
                  int nbulge, const T *trd, T *Uw) {
     size_t sm = chase_smem<T>(W, nbulge);
     if (sm > 160 * 1024) return -1;
-    auto kfn = k_chase<T, 512>;
+    auto kfn = k_chase<T, 1024>;
     static std::mutex mu;
     static size_t attr_set = 0;
     {
@@ -624,7 +619,7 @@ int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W
     }
     {
         ProfScope ps(KID_CHASE, s);
-        hipLaunchKernelGGL(kfn, dim3(1), dim3(512), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge,
+        hipLaunchKernelGGL(kfn, dim3(1), dim3(1024), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge,
                            trd, Uw);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;

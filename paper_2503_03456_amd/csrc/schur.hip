@@ -17,6 +17,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "schur.hpp"
+#include "prof.hpp"
 
 #include <vector>
 #include <cmath>
@@ -165,6 +166,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
             if (aed_launch<T>(s, N, H, ldh, ktop, 0, c.Zw, c.dint, c.wr, c.wi)) return -1;
             if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
             ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5];
+            prof_add_work(KID_AED, 12.0 * (2.0 * N + 3.0) * hi[4]);
             if (hi[0] != 0) { *qr_status = 1; break; }
             apply_window(c, ktop, N, c.Zw);
             kbot = ktop - 1;
@@ -178,6 +180,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
         const int aed_st = hi[0], nd = hi[1], nsu = hi[2];
         ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5]; st_defl += nd;
+        prof_add_work(KID_AED, 12.0 * (2.0 * nw + 3.0) * hi[4]);
         if (aed_st == 0) apply_window(c, kwtop, nw, c.Zw);
         // shift candidates: eigenvalues of the undeflated part of the window
         wr.clear(); wi.clear();
