@@ -114,12 +114,20 @@ int lyap_solve(int n, const double *A, int lda, const double *C, int ldc,
                void *work, size_t work_bytes, void *stream);
 
 /* Solve `batch` independent equations (kind[i] = SYLV_KIND_SYLV or
- * SYLV_KIND_LYAP; B[i] ignored for Lyapunov).  kind, m, n, lda, ldb, ldc,
- * ldx, and the pointer arrays A, B, C, X are HOST arrays of length batch;
- * the matrices they point to live in device memory.  infos is a host array
- * of length batch.  Equations up to order 256 run in one persistent kernel
- * (one workgroup per equation, longest-first work queue); larger ones go
- * through sylv_solve one by one. */
+ * SYLV_KIND_LYAP; B[i] and n[i] ignored for Lyapunov, whose order is m[i]).
+ * kind, m, n, lda, ldb, ldc, ldx and the pointer arrays A, B, C, X are HOST
+ * arrays of length batch; the matrices they point to live in device memory
+ * (column-major, binary64).  infos is a host array of length batch (may be
+ * NULL).  Lyapunov equations of order 1..256 with low = SYLV_PREC_FP32 are
+ * solved together (Sec. 4 batched workloads): one workgroup per equation in
+ * every stage, equations ordered longest first, Schur form, tri-solve and
+ * corrections in binary32, residuals in binary64, per-equation convergence
+ * control; an equation that misses the tolerance is re-solved in binary64
+ * when opts->fallback is set (info.fell_back = 1).  All other equations go
+ * through sylv_solve / lyap_solve one after another.  work (device, may be
+ * NULL: the library keeps its own) must hold sylv_batched_workspace_size
+ * bytes.  Returns 0, -i for an invalid i-th argument (-15: work too small),
+ * or SYLV_ERR_*; synchronises the stream before returning. */
 int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
                        const double *const *A, const int *lda,
                        const double *const *B, const int *ldb,
@@ -127,6 +135,11 @@ int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
                        double *const *X, const int *ldx,
                        const sylv_opts *opts, sylv_info *infos,
                        void *work, size_t work_bytes, void *stream);
+
+/* Device workspace in bytes that sylv_solve_batched needs for this batch
+ * (host arrays as in sylv_solve_batched); 0 for invalid arguments. */
+size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, const int *n,
+                                   const sylv_opts *opts);
 
 /* Text for a return value or a status code. */
 const char *sylv_status_string(int code);

@@ -66,6 +66,12 @@ _lib.sylv_solve.restype = _i
 _lib.lyap_solve.argtypes = [_i, _vp, _i, _vp, _i, _vp, _i, ctypes.POINTER(Opts),
                             ctypes.POINTER(Info), _vp, _sz, _vp]
 _lib.lyap_solve.restype = _i
+_pp = ctypes.POINTER(ctypes.c_void_p)
+_lib.sylv_solve_batched.argtypes = [_i, _ip, _ip, _ip, _pp, _ip, _pp, _ip, _pp, _ip, _pp, _ip,
+                                    ctypes.POINTER(Opts), ctypes.POINTER(Info), _vp, _sz, _vp]
+_lib.sylv_solve_batched.restype = _i
+_lib.sylv_batched_workspace_size.argtypes = [_i, _ip, _ip, _ip, ctypes.POINTER(Opts)]
+_lib.sylv_batched_workspace_size.restype = _sz
 _lib.sylv_status_string.argtypes = [_i]
 _lib.sylv_status_string.restype = ctypes.c_char_p
 _lib.sylv_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _i, _i, _ip, _vp]
@@ -166,6 +172,51 @@ def lyap(A, C, X=None, work=None, stream=None, **kw):
                          ctypes.byref(o), ctypes.byref(info), wp, wb, _stream(stream))
     _check(rc, "lyap_solve")
     return X, info.as_dict()
+
+
+def _iarr(v):
+    return (ctypes.c_int * max(1, len(v)))(*[int(x) for x in v])
+
+
+def _parr(ts):
+    return (ctypes.c_void_p * max(1, len(ts)))(*[(t.data_ptr() if t is not None else None) for t in ts])
+
+
+def batched_workspace_size(kinds, ms, ns, **kw):
+    return int(_lib.sylv_batched_workspace_size(len(kinds), _iarr(kinds), _iarr(ms), _iarr(ns),
+                                                ctypes.byref(make_opts(**kw))))
+
+
+def solve_batched(eqs, Xs=None, work=None, stream=None, **kw):
+    """Solve a list of equations in one call.  Each item is (A, C) for
+    AX + XA^T = C or (A, B, C) for AX + XB = C.  Returns (list of X, list
+    of info dicts)."""
+    kinds, ms, ns, As, Bs, Cs, lda, ldb, ldc = [], [], [], [], [], [], [], [], []
+    for e in eqs:
+        if len(e) == 2:
+            A, C = colmajor(e[0]), colmajor(e[1])
+            kinds.append(1); As.append(A); Bs.append(None); Cs.append(C)
+            lda.append(_ld(A)); ldb.append(1); ldc.append(_ld(C))
+            ms.append(C.shape[0]); ns.append(C.shape[0])
+        else:
+            A, B, C = colmajor(e[0]), colmajor(e[1]), colmajor(e[2])
+            kinds.append(0); As.append(A); Bs.append(B); Cs.append(C)
+            lda.append(_ld(A)); ldb.append(_ld(B)); ldc.append(_ld(C))
+            ms.append(C.shape[0]); ns.append(C.shape[1])
+    if Xs is None:
+        Xs = [torch.empty((C.shape[1], C.shape[0]), dtype=torch.float64, device=C.device).t() for C in Cs]
+    Xs = [colmajor(X) for X in Xs]
+    ldx = [_ld(X) for X in Xs]
+    nb = len(eqs)
+    o = make_opts(**kw)
+    infos = (Info * max(1, nb))()
+    wp = ctypes.c_void_p(work.data_ptr()) if work is not None else None
+    wb = work.numel() * work.element_size() if work is not None else 0
+    rc = _lib.sylv_solve_batched(nb, _iarr(kinds), _iarr(ms), _iarr(ns), _parr(As), _iarr(lda),
+                                 _parr(Bs), _iarr(ldb), _parr(Cs), _iarr(ldc), _parr(Xs), _iarr(ldx),
+                                 ctypes.byref(o), infos, wp, wb, _stream(stream))
+    _check(rc, "sylv_solve_batched")
+    return Xs, [infos[i].as_dict() for i in range(nb)]
 
 
 def _prec_of(t):

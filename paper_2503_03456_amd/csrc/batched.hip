@@ -1,17 +1,58 @@
 // Batched entry point and selector state.
 //
-// sylv_solve_batched currently runs the equations one after another through
-// the single-equation path (each equation on the caller's stream).
+// Lyapunov equations of order 1..256 with a binary32 low precision run
+// through the batched kernels (one workgroup per equation and stage, all
+// equations in flight together, longest first); an equation whose
+// refinement does not reach the tolerance is re-solved in binary64 when the
+// options allow the fallback.  Every other equation goes through the
+// single-equation path one after another.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "../../include/sylv.h"
 
+#include <algorithm>
 #include <vector>
 #include <cstring>
 #include <mutex>
 
+namespace sylv {
+int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A, const int *lda,
+                 const double *const *C, const int *ldc, double *const *X, const int *ldx,
+                 const sylv_opts &o, sylv_info *infos, void *work, size_t work_bytes, char *hbuf);
+}
+using namespace sylv;
+
 static std::mutex g_sel_mu;
 static std::vector<float> g_selector;  // 5443 params + 16 means + 16 stds
+
+static bool batched_eligible(int kind, int n, const sylv_opts &o) {
+    return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 && o.low == SYLV_PREC_FP32;
+}
+
+extern "C" size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, const int *n,
+                                              const sylv_opts *opts) {
+    if (batch < 0 || (batch > 0 && (!kind || !m || !n))) return 0;
+    sylv_opts o;
+    sylv_default_opts(&o);
+    if (opts) o = *opts;
+    std::vector<int> nb;
+    size_t single = 0;
+    for (int i = 0; i < batch; ++i) {
+        if (batched_eligible(kind[i], m[i], o)) {
+            nb.push_back(m[i]);
+            if (o.fallback) {
+                sylv_opts f = o;
+                f.low = SYLV_PREC_FP64;
+                single = std::max(single, sylv_workspace_size(m[i], m[i], 1, &f));
+            }
+        } else {
+            const int lyap = kind[i] == SYLV_KIND_LYAP;
+            single = std::max(single, sylv_workspace_size(m[i], lyap ? m[i] : n[i], lyap, &o));
+        }
+    }
+    const size_t b = nb.empty() ? 0 : lyap_batched_bytes((int)nb.size(), nb.data());
+    return std::max(b, single);
+}
 
 extern "C" int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
                                   const double *const *A, const int *lda, const double *const *B,
@@ -31,14 +72,74 @@ extern "C" int sylv_solve_batched(int batch, const int *kind, const int *m, cons
     if (!ldx) return -12;
     for (int i = 0; i < batch; ++i)
         if (kind[i] == SYLV_KIND_SYLV && (!B || !ldb)) return -7;
+    sylv_opts o;
+    sylv_default_opts(&o);
+    if (opts) o = *opts;
+    if (!(o.tol >= 0.0) || o.max_iter < 0) return -13;
+    hipStream_t s = (hipStream_t)stream;
+
+    // equations for the batched kernels (validated like the single path)
+    std::vector<int> idx, bn, blda, bldc, bldx;
+    std::vector<const double *> bA, bC;
+    std::vector<double *> bX;
     for (int i = 0; i < batch; ++i) {
+        if (!batched_eligible(kind[i], m[i], o)) continue;
+        if (lda[i] < m[i] || ldc[i] < m[i] || ldx[i] < m[i]) return -6;
+        if (!A[i] || !C[i] || !X[i]) return -5;
+        idx.push_back(i);
+        bn.push_back(m[i]);
+        bA.push_back(A[i]); blda.push_back(lda[i]);
+        bC.push_back(C[i]); bldc.push_back(ldc[i]);
+        bX.push_back(X[i]); bldx.push_back(ldx[i]);
+    }
+    if (!idx.empty()) {
+        const int nb = (int)idx.size();
+        std::vector<sylv_info> binf(nb);
+        int rc;
+        {
+            std::lock_guard<std::mutex> lk(lib_mutex());
+            const size_t need = lyap_batched_bytes(nb, bn.data());
+            void *ws = nullptr;
+            char *hbuf = nullptr;
+            rc = device_work(work ? 0 : need, &ws, &hbuf);
+            if (rc) return rc;
+            if (work) {
+                if (work_bytes < need) return -15;
+                ws = work;
+            }
+            rc = lyap_batched(s, nb, bn.data(), bA.data(), blda.data(), bC.data(), bldc.data(),
+                              bX.data(), bldx.data(), o, binf.data(), ws, work ? work_bytes : need, hbuf);
+            hipError_t e = hipGetLastError();
+            if (rc == 0 && e != hipSuccess) rc = SYLV_ERR_HIP - (int)e;
+        }
+        if (rc) return rc;
+        for (int t = 0; t < nb; ++t) {
+            const int i = idx[t];
+            sylv_info f = binf[t];
+            const bool ok = f.status == SYLV_OK || f.status == SYLV_ST_PERTURBED;
+            if (!ok && o.fallback) {
+                sylv_opts f64 = o;
+                f64.low = SYLV_PREC_FP64;
+                sylv_info g;
+                rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &f64, &g, work,
+                                work_bytes, stream);
+                if (rc) return rc;
+                g.fell_back = 1;
+                g.iterations = f.iterations;
+                f = g;
+            }
+            if (infos) infos[i] = f;
+        }
+    }
+    for (int i = 0; i < batch; ++i) {
+        if (batched_eligible(kind[i], m[i], o)) continue;
         int rc;
         sylv_info *inf = infos ? infos + i : nullptr;
         if (kind[i] == SYLV_KIND_LYAP)
-            rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], opts, inf, work, work_bytes,
+            rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &o, inf, work, work_bytes,
                             stream);
         else
-            rc = sylv_solve(m[i], n[i], A[i], lda[i], B[i], ldb[i], C[i], ldc[i], X[i], ldx[i], opts,
+            rc = sylv_solve(m[i], n[i], A[i], lda[i], B[i], ldb[i], C[i], ldc[i], X[i], ldx[i], &o,
                             inf, work, work_bytes, stream);
         if (rc) return rc;
     }

@@ -38,23 +38,13 @@ template <> struct mfma16<double> {
 
 constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 16;
 
+// One 64x64 output tile (rows row0.., cols col0..) of C = alpha op(A) op(B) + beta C.
 template <typename TA, typename TB, typename TC, typename ACC>
-__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
-                                                   const TA *__restrict__ A, int lda, int ta,
-                                                   const TB *__restrict__ B, int ldb, int tb,
-                                                   TC *__restrict__ C, int ldc, ACC alpha, ACC beta,
-                                                   int tiles_m, TB bscale) {
-    __shared__ ACC As[GBK][GBM + GPAD];
-    __shared__ ACC Bs[GBK][GBN + GPAD];
+SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int lda, int ta,
+                           const TB *__restrict__ B, int ldb, int tb, TC *__restrict__ C, int ldc,
+                           ACC alpha, ACC beta, TB bscale, int row0, int col0,
+                           ACC (&As)[GBK][GBM + GPAD], ACC (&Bs)[GBK][GBN + GPAD]) {
     typedef typename mfma16<ACC>::v4 v4;
-
-    // XCD-aware tile order: consecutive workgroup ids go to different XCDs;
-    // give each XCD a contiguous run of tiles (shares operand panels in L2).
-    const int nblk = gridDim.x;
-    int bid = blockIdx.x;
-    if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
-    const int tm = bid % tiles_m, tn = bid / tiles_m;
-    const int row0 = tm * GBM, col0 = tn * GBN;
 
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = w & 1, wn = w >> 1;
@@ -134,6 +124,71 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
                 }
             }
 }
+
+template <typename TA, typename TB, typename TC, typename ACC>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
+                                                   const TA *__restrict__ A, int lda, int ta,
+                                                   const TB *__restrict__ B, int ldb, int tb,
+                                                   TC *__restrict__ C, int ldc, ACC alpha, ACC beta,
+                                                   int tiles_m, TB bscale) {
+    __shared__ ACC As[GBK][GBM + GPAD];
+    __shared__ ACC Bs[GBK][GBN + GPAD];
+    // XCD-aware tile order: consecutive workgroup ids go to different XCDs;
+    // give each XCD a contiguous run of tiles (shares operand panels in L2).
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+    const int tm = bid % tiles_m, tn = bid / tiles_m;
+    gemm_tile<TA, TB, TC, ACC>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, bscale, tm * GBM,
+                               tn * GBN, As, Bs);
+}
+
+// Batched form over the equations of a batch: grid.y = equation slot (in
+// the order given), grid.x = 64x64 tile of that equation's n x n product.
+// Operands are fields of the per-equation descriptor.
+template <typename TA, typename TB, typename TC, typename ACC>
+__global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__restrict__ eqs,
+                                                           const int *__restrict__ order, int fa,
+                                                           int ta, int fb, int tb, int fc,
+                                                           ACC alpha, int amode, ACC beta) {
+    __shared__ ACC As[GBK][GBM + GPAD];
+    __shared__ ACC Bs[GBK][GBN + GPAD];
+    const BatchEq &q = eqs[order[blockIdx.y]];
+    if (!q.active) return;
+    const int n = q.n;
+    const int tl = (n + GBM - 1) / GBM;
+    if ((int)blockIdx.x >= tl * tl) return;
+    const int tm = blockIdx.x % tl, tn = blockIdx.x / tl;
+    // amode 1 scales op(B) by scale_e before the conversion to ACC (a binary64
+    // residual brought to unit size ahead of the binary32 cast); amode 2
+    // multiplies the product by 1 / scale_e
+    ACC al = alpha;
+    TB bs = TB(1);
+    if (amode == 1) bs = (TB)q.scale;
+    else if (amode == 2) al = (ACC)(alpha / q.scale);
+    gemm_tile<TA, TB, TC, ACC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
+                               q.ld[fb], tb, (TC *)q.ptr[fc], q.ld[fc], al, beta, bs, tm * GBM,
+                               tn * GBN, As, Bs);
+}
+
+template <typename TA, typename TB, typename TC, typename ACC>
+void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch, int nmax, int fa,
+                  int ta, int fb, int tb, int fc, ACC alpha, int amode, ACC beta) {
+    if (batch <= 0) return;
+    const int tl = (nmax + GBM - 1) / GBM;
+    ProfScope ps(KID_BGEMM, s);
+    hipLaunchKernelGGL((gemm_batched_kernel<TA, TB, TC, ACC>), dim3(tl * tl, batch), dim3(256), 0, s,
+                       eqs, order, fa, ta, fb, tb, fc, alpha, amode, beta);
+}
+template void gemm_batched<double, double, double, double>(hipStream_t, const BatchEq *, const int *,
+                                                           int, int, int, int, int, int, int, double,
+                                                           int, double);
+template void gemm_batched<float, float, float, float>(hipStream_t, const BatchEq *, const int *, int,
+                                                       int, int, int, int, int, int, float, int, float);
+template void gemm_batched<float, double, float, float>(hipStream_t, const BatchEq *, const int *, int,
+                                                        int, int, int, int, int, int, float, int, float);
+template void gemm_batched<float, float, double, float>(hipStream_t, const BatchEq *, const int *, int,
+                                                        int, int, int, int, int, int, float, int, float);
 
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const TA *A, int lda,

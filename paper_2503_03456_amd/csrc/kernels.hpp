@@ -2,13 +2,46 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <mutex>
 
 namespace sylv {
+
+// Per-equation descriptor of the batched Lyapunov path (device resident).
+// ptr/ld fields: 0 A, 1 C, 2 X (binary64, caller's), 3 R (binary64
+// workspace), 4 H/T, 5 U (row-major), 6 W, 7 Y (binary32 workspace).
+enum BatchField { BF_A = 0, BF_C = 1, BF_X = 2, BF_R = 3, BF_H = 4, BF_U = 5, BF_W = 6, BF_Y = 7 };
+struct BatchEq {
+    void *ptr[8];
+    int ld[8];
+    int n;
+    int active;      // 1 while the equation still needs work
+    int status;      // sylv_info.status
+    int iterations;  // corrections applied
+    int qr_fail;
+    int flag;        // tri-solve pivot perturbed
+    double scale;    // 2^-e applied to the residual before the binary32 cast
+    double nA, nC;   // ||A||_F, ||C||_F
+    double rel_res, prev_rel, corr;
+    int stall;
+    int steps;       // double-shift QR steps of the Schur kernel
+    double napply;   // 3-element reflector applications of the Schur kernel
+};
+
+// solver.hip
+std::mutex &lib_mutex();
+int device_work(size_t bytes, void **work, char **hbuf);
+
+// lyap_batch.hip: all equations Lyapunov of order 1..256
+size_t lyap_batched_bytes(int batch, const int *n);
 
 // gemm.hip
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const TA *A, int lda,
           const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale = TB(1));
+
+template <typename TA, typename TB, typename TC, typename ACC>
+void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch, int nmax, int fa,
+                  int ta, int fb, int tb, int fc, ACC alpha, int amode, ACC beta);
 
 // blas.hip
 template <typename TS, typename TD>

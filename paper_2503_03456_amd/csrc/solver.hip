@@ -78,6 +78,18 @@ static int ensure_work(DevCtx *c, size_t bytes, void **out) {
     return 0;
 }
 
+// Library lock and per-device staging/workspace for the batched entry point
+// (the caller holds the lock while it uses them).
+std::mutex &lib_mutex() { return g_mu; }
+int device_work(size_t bytes, void **work, char **hbuf) {
+    DevCtx *c = nullptr;
+    int rc = device_ctx(&c);
+    if (rc) return rc;
+    *hbuf = c->hbuf;
+    if (bytes == 0) { *work = nullptr; return 0; }
+    return ensure_work(c, bytes, work);
+}
+
 // ----------------------------------------------------------- workspace plan
 struct Arena {
     char *base;
@@ -482,6 +494,8 @@ static int solve_common(int m, int n, const double *A, int lda, const double *B,
                         void *stream) {
     int rc = solve_common_impl(m, n, A, lda, B, ldb, C, ldc, X, ldx, lyap, opts, info, work,
                                work_bytes, stream);
+    // invalid sizes and empty problems return before any HIP call
+    if (m <= 0 || (!lyap && n <= 0)) return rc;
     hipError_t e = hipGetLastError();
     if (rc == 0 && e != hipSuccess) rc = SYLV_ERR_HIP - (int)e;
     if (rc == -1 && m >= 0) rc = SYLV_ERR_HIP;  // internal launch failure

@@ -1,0 +1,156 @@
+"""Batched Lyapunov path (sylv_solve_batched) on the GPU against the FP64
+oracle: the Sec. 4 batch recipe (orders 16..256, stable normal A, C = -BB^T),
+tiny and maximal orders, mixed batches routed to the single-equation path,
+per-equation convergence control, fallback and error reporting."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_common import U64, binding, dev, host, relerr, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-14
+
+
+def lyap_kappa(eig):
+    lam = eig[:, None] + eig[None, :]
+    return np.abs(lam).max() / np.abs(lam).min()
+
+
+def check_item(A, C, eig, Xg, info, allow_fallback=False):
+    Xo, st = oracle.lyap_solve(A, C)
+    assert st == 0
+    assert info["rel_res"] <= TOL, info
+    if not allow_fallback:
+        assert info["fell_back"] == 0, info
+    rr_o = oracle.rel_residual(A, A.T, C, Xo)
+    rr_g = oracle.rel_residual(A, A.T, C, Xg)
+    assert rr_g <= max(TOL, 10 * rr_o)
+    # A normal: ||L^-1|| = 1/min|l_i + l_j|, ||C|| <= max|l_i + l_j| ||X|| and
+    # ||A||_F <= sqrt(n) max|l|, so a relative residual r (eq. (2.1)) bounds the
+    # forward error by r * kappa * (1 + sqrt(n)); each side contributes its own r
+    kap = lyap_kappa(eig)
+    n = A.shape[0]
+    bound = (rr_g + rr_o) * kap * (1 + np.sqrt(n)) + 100 * U64 * kap
+    assert relerr(Xg, Xo) <= bound, (relerr(Xg, Xo), bound)
+    assert np.linalg.norm(Xg - Xg.T) <= 100 * U64 * kap * np.linalg.norm(Xg)
+
+
+def items(indices, sizes):
+    out = []
+    for i, n in zip(indices, sizes):
+        A, C, eig = workloads.config4_item(int(i), int(n))
+        out.append((A, C, eig))
+    return out
+
+
+def test_batch_recipe_mixed_orders():
+    """48 equations with orders drawn by the batch recipe (16..256)."""
+    sy = binding()
+    sizes = workloads.config4_sizes()[:48]
+    its = items(range(48), sizes)
+    say("batched recipe", list(sizes[:8]), "...")
+    Xs, infos = sy.solve_batched([(dev(A), dev(C)) for A, C, _ in its])
+    torch.cuda.synchronize()
+    for (A, C, eig), X, info in zip(its, Xs, infos):
+        check_item(A, C, eig, host(X), info)
+        assert info["precision_used"] == "fp32" and info["iterations"] >= 1
+
+
+@pytest.mark.parametrize("sizes", [[1], [2], [3], [1, 2, 3, 4, 5, 6, 7], [256, 256], [255, 17, 1, 64, 65]])
+def test_batch_edge_orders(sizes):
+    sy = binding()
+    say("batched edge", sizes)
+    its = items(range(500, 500 + len(sizes)), sizes)
+    Xs, infos = sy.solve_batched([(dev(A), dev(C)) for A, C, _ in its])
+    torch.cuda.synchronize()
+    for (A, C, eig), X, info in zip(its, Xs, infos):
+        check_item(A, C, eig, host(X), info)
+
+
+def test_batch_single_equation_matches_lyap_solve():
+    sy = binding()
+    A, C, eig = workloads.config4_item(7, 200)
+    Xs, infos = sy.solve_batched([(dev(A), dev(C))])
+    X1, info1 = sy.lyap(dev(A), dev(C))
+    torch.cuda.synchronize()
+    assert infos[0]["rel_res"] <= TOL and info1["rel_res"] <= TOL
+    assert relerr(host(Xs[0]), host(X1)) <= 100 * U64 * lyap_kappa(eig)
+
+
+def test_batch_mixed_kinds_and_large_orders():
+    """Sylvester equations and Lyapunov equations above order 256 go through
+    the single-equation path in the same call."""
+    sy = binding()
+    A1, C1, e1 = workloads.config4_item(11, 40)
+    A2, C2, e2 = workloads.config4_item(12, 300)
+    Am, Bm, Cm = workloads.sylv_random(13, 50, 30, scale=0.5 / np.sqrt(50))
+    A3, C3, e3 = workloads.config4_item(14, 120)
+    eqs = [(dev(A1), dev(C1)), (dev(A2), dev(C2)), (dev(Am), dev(Bm), dev(Cm)), (dev(A3), dev(C3))]
+    Xs, infos = sy.solve_batched(eqs)
+    torch.cuda.synchronize()
+    check_item(A1, C1, e1, host(Xs[0]), infos[0])
+    check_item(A2, C2, e2, host(Xs[1]), infos[1])
+    check_item(A3, C3, e3, host(Xs[3]), infos[3])
+    Xo, _ = oracle.bs_solve(Am, Bm, Cm)
+    assert infos[2]["rel_res"] <= TOL
+    assert relerr(host(Xs[2]), Xo) <= 1e-12
+
+
+def test_batch_fallback_and_no_fallback():
+    sy = binding()
+    its = items(range(600, 604), [30, 90, 150, 20])
+    eqs = [(dev(A), dev(C)) for A, C, _ in its]
+    Xs, infos = sy.solve_batched(eqs, max_iter=0)
+    torch.cuda.synchronize()
+    for (A, C, eig), X, info in zip(its, Xs, infos):
+        assert info["fell_back"] == 1 and info["precision_used"] == "fp64", info
+        check_item(A, C, eig, host(X), info, allow_fallback=True)
+    _, infos2 = sy.solve_batched(eqs, max_iter=0, fallback=False)
+    torch.cuda.synchronize()
+    assert all(i["status"] == 2 and i["fell_back"] == 0 for i in infos2)
+
+
+def test_batch_nan_isolated_to_its_equation():
+    sy = binding()
+    its = items(range(700, 703), [40, 60, 80])
+    C_bad = its[1][1].copy()
+    C_bad[5, 7] = np.nan
+    eqs = [(dev(its[0][0]), dev(its[0][1])), (dev(its[1][0]), dev(C_bad)), (dev(its[2][0]), dev(its[2][1]))]
+    Xs, infos = sy.solve_batched(eqs, fallback=False)
+    torch.cuda.synchronize()
+    assert infos[1]["status"] == 3
+    check_item(*its[0], host(Xs[0]), infos[0])
+    check_item(*its[2], host(Xs[2]), infos[2])
+
+
+def test_batch_caller_workspace_and_determinism():
+    sy = binding()
+    sizes = [100, 37, 256, 5]
+    its = items(range(800, 804), sizes)
+    eqs = [(dev(A), dev(C)) for A, C, _ in its]
+    nbytes = sy.batched_workspace_size([1] * 4, sizes, sizes)
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    Xa, ia = sy.solve_batched(eqs, work=work)
+    Xb, ib = sy.solve_batched(eqs)
+    torch.cuda.synchronize()
+    for x, y in zip(Xa, Xb):
+        assert torch.equal(x, y)
+    for (A, C, eig), X, info in zip(its, Xa, ia):
+        check_item(A, C, eig, host(X), info)
+    small = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    with pytest.raises(sy.SylvError):
+        sy.solve_batched(eqs, work=small)
+
+
+def test_batch_fp64_low_uses_single_path():
+    sy = binding()
+    its = items(range(900, 903), [20, 64, 130])
+    Xs, infos = sy.solve_batched([(dev(A), dev(C)) for A, C, _ in its], low="fp64")
+    torch.cuda.synchronize()
+    for (A, C, eig), X, info in zip(its, Xs, infos):
+        assert info["precision_used"] == "fp64"
+        check_item(A, C, eig, host(X), info)
