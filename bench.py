@@ -26,7 +26,8 @@ PEAKS = {  # MI355X published dense peaks
 }
 
 KERNEL_IDS = {"gemm_kernel": 1, "k_hess_col": 2, "k_hess_gemv": 3, "k_aed": 4, "k_chase": 5,
-              "k_trsyl_diag": 6, "k_find_ktop": 7, "k_cast": 8, "k_sumsq_partial": 9}
+              "k_trsyl_diag": 6, "k_find_ktop": 7, "k_cast": 8, "k_sumsq_partial": 9,
+              "k_bhess": 10, "k_bschur": 11, "k_btrsyl": 12, "gemm_batched_kernel": 13}
 
 
 def bs_flops(m, n, lyap=False):
@@ -70,6 +71,112 @@ def cpu_baseline(sample_n, target_m, target_n):
                        f"by the 25(m^3+n^3)+5mn(m+n) flop model")}
 
 
+def c4_batch(count):
+    import workloads
+    sizes = workloads.config4_sizes()[:count]
+    return [workloads.config4_item(i, int(n)) for i, n in enumerate(sizes)], sizes
+
+
+def cpu_baseline_batched(items, sizes, sample):
+    """The CPU oracle (plain C, binary64) on a sample of the batch, one
+    equation per host thread, scaled to the whole batch by sum n^3."""
+    import concurrent.futures as cf
+    import oracle
+    idx = list(range(0, len(items), max(1, len(items) // sample)))[:sample]
+    cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(lambda i: oracle.lyap_solve(items[i][0], items[i][1]), idx))
+    dt = time.perf_counter() - t0
+    n3 = sizes.astype(float) ** 3
+    scale = n3[idx].sum() / n3.sum()
+    return {"value": len(items) * scale / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{len(idx)} equations of the batch (every {max(1, len(items) // sample)}th) "
+                       f"solved by the oracle on {cores} threads in {dt:.2f} s, scaled to the "
+                       f"{len(items)}-equation batch by sum n^3")}
+
+
+def main_batched(args, np, torch, sy):
+    import ctypes
+    items, sizes = c4_batch(args.count)
+    desc = (f"batched lyapunov, {len(items)} equations, n~U{{16..256}} (sum n^3 = "
+            f"{(sizes.astype(float) ** 3).sum():.3e}), stable normal A (Re eig U[-5,-0.1], 30% "
+            "complex pairs), C=-BB^T with B n x 4")
+
+    def dev(a):
+        return torch.from_numpy(np.asfortranarray(a)).t().contiguous().t().cuda()
+
+    eqs = [(dev(A), dev(C)) for A, C, _ in items]
+    Xs = [torch.empty((int(n), int(n)), dtype=torch.float64, device="cuda").t() for n in sizes]
+    kinds = [1] * len(items)
+    work = torch.empty(sy.batched_workspace_size(kinds, list(sizes), list(sizes)), dtype=torch.uint8,
+                       device="cuda")
+    torch.cuda.synchronize()
+
+    def run(**kw):
+        return sy.solve_batched(eqs, Xs=Xs, work=work, **kw)[1]
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    lib = sy.lib()
+    kname = args.roofline_kernel if args.roofline_kernel != "k_aed" else "k_bschur"
+    lib.sylv_profile_end.argtypes = [ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.sylv_profile_begin(KERNEL_IDS[kname])
+    infos = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nl, tot, work_acc = ctypes.c_long(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    lib.sylv_profile_end(ctypes.byref(nl), ctypes.byref(tot), ctypes.byref(work_acc))
+    dt = (t1 - t0) / args.steps
+    ok = all(i["rel_res"] <= 1e-14 for i in infos)
+    iters = [i["iterations"] for i in infos]
+    n3 = (sizes.astype(float) ** 3).sum()
+    kbar = float(np.mean(iters))
+    # plain binary64 (single-equation path) on a sample, scaled by sum n^3
+    t64 = None
+    if args.fp64_steps > 0:
+        idx = list(range(0, len(items), max(1, len(items) // 128)))[:128]
+        sub = [eqs[i] for i in idx]
+        sy.solve_batched(sub, low="fp64")
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        sy.solve_batched(sub, low="fp64")
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - s0) * n3 / (sizes[idx].astype(float) ** 3).sum()
+    roof = None
+    if nl.value > 0:
+        roof = roofline_entry(kname, nl.value, tot.value, work_acc.value, args.steps, dt)
+    out = {
+        "metric": "solves/s and TFLOP/s at FP64-level residual: mixed-precision vs plain FP64",
+        "value": (len(items) / dt) if ok else 0.0,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "count": len(items), "path": "batched fp32 Schur + fp64 refinement",
+                   "tol": 1e-14},
+        "rel_res": max(i["rel_res"] for i in infos), "all_solves_at_tol": ok,
+        "iterations_mean": kbar, "iterations_max": int(max(iters)),
+        "fell_back": int(sum(i["fell_back"] for i in infos)),
+        "tflops_bs_equivalent": 35.0 * n3 / dt / 1e12,
+        "tflops_executed": {"fp32": (25.0 + 10.0 * (kbar + 1)) * n3 / dt / 1e12,
+                            "fp64": 4.0 * (kbar + 1) * n3 / dt / 1e12},
+        "fp64_plain": None if t64 is None else {
+            "solves_per_s": len(items) / t64, "ms_per_batch": t64 * 1e3,
+            "note": "single-equation binary64 path on 128 sampled equations, scaled by sum n^3"},
+        "speedup_vs_fp64": None if t64 is None else t64 / dt,
+        "roofline": roof, "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(items, sizes, args.cpu_sample_eqs)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +187,8 @@ def main():
     ap.add_argument("--roofline-kernel", default="k_aed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=768)
+    ap.add_argument("--count", type=int, default=4096, help="equations of the batched workload (c4)")
+    ap.add_argument("--cpu-sample-eqs", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this solver has no "
@@ -92,6 +201,8 @@ def main():
     import torch
     import paper_2503_03456_amd as sy
 
+    if args.workload == "c4":
+        return main_batched(args, np, torch, sy)
     cfg, desc = load_workload(args.workload)
     m, n = cfg["C"].shape
 

@@ -141,6 +141,11 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
             z = b10 * b21;
         }
         __syncthreads();
+        // The column a step reduces (k-1) is read by every thread at the top
+        // of that step, so its final values (beta, 0, 0) are written one step
+        // later, when no thread reads it.
+        int pcol = -1, pk2 = 0;
+        T pbeta = T(0);
         for (int k = l; k <= ihi - 1; ++k) {
             const int len = (k <= ihi - 2) ? 3 : 2;
             if (k > l) {
@@ -151,28 +156,27 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
             T v1, v2, tau, beta;
             reflector3(len, x, y, z, v1, v2, tau, beta);
             // Work split by wave so that no wave runs two code paths:
-            //   wave 0: left application on columns {k-1} u [k+len, n)
+            //   wave 0: left application on columns [k+len, n) (and the
+            //           deferred column of the previous step)
             //   wave 1: right application on rows [0, k) u {k+3}
             //   waves 2..NW-2: the accumulated factor Z (rows 0..nz-1)
             //   wave NW-1, lane 0: the overlap block rows/cols k..k+len-1
             constexpr int NWV = NT / 64;
             static_assert(NWV >= 4, "francis_lds needs at least 4 waves");
             const int wv = tid >> 6, lane = tid & 63;
-            const int lc0 = (k > l) ? 1 : 0;                  // column k-1
             const int k2 = (len == 3) ? k + 2 : k + 1;  // clamped third index
             if (wv == 0) {
-                const int nL = lc0 + (n - (k + len));
+                if (lane == 0 && pcol >= 0) {
+                    CM(H, pk2, pcol, ldh) = T(0);
+                    CM(H, pcol + 2, pcol, ldh) = T(0);
+                    CM(H, pcol + 1, pcol, ldh) = pbeta;
+                }
+                const int nL = n - (k + len);
                 for (int q = lane; q < nL; q += 64) {
-                    if (lc0 && q == 0) {
-                        CM(H, k2, k - 1, ldh) = T(0);
-                        CM(H, k + 1, k - 1, ldh) = T(0);
-                        CM(H, k, k - 1, ldh) = beta;
-                    } else {
-                        const int j = k + len + q - lc0;
-                        T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh), a2 = CM(H, k2, j, ldh);
-                        refl_apply(len, v1, v2, tau, a0, a1, a2);
-                        CM(H, k2, j, ldh) = a2; CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
-                    }
+                    const int j = k + len + q;
+                    T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh), a2 = CM(H, k2, j, ldh);
+                    refl_apply(len, v1, v2, tau, a0, a1, a2);
+                    CM(H, k2, j, ldh) = a2; CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
                 }
             } else if (wv == 1) {
                 const int extra = (len == 3 && k + 3 <= ihi) ? 1 : 0;
@@ -209,7 +213,16 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
                     for (int ii = 2; ii >= 0; --ii) CM(H, ix[ii], ix[jj], ldh) = b[ii][jj];
             }
             __syncthreads();
+            pcol = (k > l) ? k - 1 : -1;
+            pbeta = beta;
+            pk2 = k2;
         }
+        if (pcol >= 0 && tid == 0) {
+            CM(H, pk2, pcol, ldh) = T(0);
+            CM(H, pcol + 2, pcol, ldh) = T(0);
+            CM(H, pcol + 1, pcol, ldh) = pbeta;
+        }
+        __syncthreads();
     }
     // exact zeros below the first subdiagonal
     for (int e = tid; e < n * n; e += NT) {

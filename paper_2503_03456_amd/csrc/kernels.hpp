@@ -8,11 +8,15 @@ namespace sylv {
 
 // Per-equation descriptor of the batched Lyapunov path (device resident).
 // ptr/ld fields: 0 A, 1 C, 2 X (binary64, caller's), 3 R (binary64
-// workspace), 4 H/T, 5 U (row-major), 6 W, 7 Y (binary32 workspace).
-enum BatchField { BF_A = 0, BF_C = 1, BF_X = 2, BF_R = 3, BF_H = 4, BF_U = 5, BF_W = 6, BF_Y = 7 };
+// workspace), 4 H/T, 5 U, 6 W, 7 Y, 8 V = U P (U with its columns reversed),
+// 9 TB = P T^T P (binary32 workspace, column-major, ld n).
+enum BatchField {
+    BF_A = 0, BF_C = 1, BF_X = 2, BF_R = 3, BF_H = 4, BF_U = 5, BF_W = 6, BF_Y = 7, BF_V = 8, BF_TB = 9,
+    BF_COUNT = 10
+};
 struct BatchEq {
-    void *ptr[8];
-    int ld[8];
+    void *ptr[BF_COUNT];
+    int ld[BF_COUNT];
     int n;
     int active;      // 1 while the equation still needs work
     int status;      // sylv_info.status
@@ -22,6 +26,7 @@ struct BatchEq {
     double scale;    // 2^-e applied to the residual before the binary32 cast
     double nA, nC;   // ||A||_F, ||C||_F
     double rel_res, prev_rel, corr;
+    double tmax;     // max |T_ij| (pivot threshold of the tri-solve)
     int stall;
     int steps;       // double-shift QR steps of the Schur kernel
     double napply;   // 3-element reflector applications of the Schur kernel
@@ -33,6 +38,9 @@ int device_work(size_t bytes, void **work, char **hbuf);
 
 // lyap_batch.hip: all equations Lyapunov of order 1..256
 size_t lyap_batched_bytes(int batch, const int *n);
+
+// trsyl.hip: batched tri-solve T Y + Y TB = W over every active equation
+void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int nmax);
 
 // gemm.hip
 template <typename TA, typename TB, typename TC, typename ACC>

@@ -5,14 +5,17 @@
 // (longest first).
 //
 // Per equation:
-//   1. k_bprep    H = fl32(A) (dense, ld n), U = I (row-major), ||A||_F, ||C||_F
-//   2. k_bhess    Householder reduction of H to Hessenberg form, U <- U P_c
+//   1. k_bprep    ||A||_F, ||C||_F, control fields
+//   2. k_bhess_reg Householder reduction of fl32(A) to Hessenberg form H and
+//                 the orthogonal factor U0, both held in registers
 //   3. k_bschur   Francis double-shift QR on the Hessenberg band held in LDS
 //                 (3 subdiagonals: 33.7K floats at n = 256); the reflectors of
 //                 a sweep are logged and applied to the rows of U once per
 //                 sweep, each thread streaming one row through registers
-//   4. transforms on MFMA (gemm_batched), tri-solve T Y + Y T^T = C~ with T in
-//      LDS (k_btrsyl), back-transform accumulated in binary64
+//   4. transforms on MFMA (gemm_batched), tri-solve T Y + Y T^T = C~ as the
+//      upper-triangular Sylvester form T Y' + Y' (P T^T P) = C~ P with the
+//      tiled solver (one launch per tile anti-diagonal over all equations),
+//      back-transform accumulated in binary64
 //   5. refinement passes: R = C - AX - XA^T (binary64 MFMA), k_bnorm decides
 //      per equation (converged / stalled / cap / NaN) and the scale 2^-e of R
 //      for the binary32 correction.
@@ -30,7 +33,7 @@
 namespace sylv {
 
 constexpr int BNT = 256;   // threads of the per-equation kernels
-constexpr int BSNT = 320;  // threads of the Schur kernel (5 waves)
+constexpr int BSNT = 576;  // threads of the Schur kernel (9 waves: 4 left, 4 right, 1 overlap)
 
 template <typename T>
 SYLV_DEVINL T wg_sum(T v, T *red) {
@@ -59,14 +62,13 @@ SYLV_DEVINL T wg_max(T v, T *red) {
 }
 
 // ------------------------------------------------------------ 1. prepare
+// ||A||_F, ||C||_F and the per-equation control fields.
 __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
     __shared__ double red[8];
     BatchEq &q = eqs[order[blockIdx.x]];
     const int n = q.n;
     const double *A = (const double *)q.ptr[BF_A];
     const double *C = (const double *)q.ptr[BF_C];
-    float *H = (float *)q.ptr[BF_H];
-    float *U = (float *)q.ptr[BF_U];
     const int lda = q.ld[BF_A], ldc = q.ld[BF_C];
     double sa = 0.0, sc = 0.0;
     for (int e = threadIdx.x; e < n * n; e += BNT) {
@@ -74,8 +76,6 @@ __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
         const double a = A[(size_t)j * lda + i], c = C[(size_t)j * ldc + i];
         sa += a * a;
         sc += c * c;
-        H[e] = (float)a;
-        U[e] = (i == j) ? 1.f : 0.f;
     }
     sa = wg_sum(sa, red);
     sc = wg_sum(sc, red);
@@ -96,74 +96,194 @@ __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
 }
 
 // ----------------------------------------------------------- 2. Hessenberg
-__global__ __launch_bounds__(BNT) void k_bhess(BatchEq *eqs, const int *order) {
-    __shared__ float v[256];
-    __shared__ float red[8];
-    __shared__ float sh[3];
-    BatchEq &q = eqs[order[blockIdx.x]];
+// Householder reduction H = U0^T A U0 with the whole matrix held in
+// registers: a G x G thread grid, thread (tx, ty) owning the R x R entries
+// (tx + G a, ty + G b) (cyclic, so the shrinking trailing block stays spread
+// over all threads; capacity G R).  For column c the G threads with
+// ty = c mod G hold the column and build the reflector with lane shuffles;
+// the left update P H needs column sums (a reduction over tx: lane shuffles
+// inside a G-lane group), the right update H P row sums (a reduction over
+// ty: shuffles inside the wave, then one pass through LDS).  Three barriers
+// per column.  The reflectors go to global memory and U0 = P_0 ... P_{n-3}
+// is accumulated backwards afterwards in the same registers (left updates
+// only, no barrier).
+template <int G, int R>
+__global__ __launch_bounds__(G * G) void k_bhess_reg(BatchEq *eqs, const int *order, int first) {
+    constexpr int NT = G * G, NW = NT / 64, NP = G * R, LDP = NP + 1;
+    constexpr int TPW = 64 / G;  // ty rows per wave
+    __shared__ float vs[2][NP];
+    __shared__ float taus[2];
+    __shared__ float zs[NP];
+    __shared__ float P[NW][LDP];
+    BatchEq &q = eqs[order[first + blockIdx.x]];
     const int n = q.n;
-    float *H = (float *)q.ptr[BF_H];
-    float *U = (float *)q.ptr[BF_U];
-    const int tid = threadIdx.x;
+    const double *A = (const double *)q.ptr[BF_A];
+    const int lda = q.ld[BF_A];
+    float *Hg = (float *)q.ptr[BF_H];
+    float *Ug = (float *)q.ptr[BF_U];
+    float *Vg = (float *)q.ptr[BF_W];  // reflector c in column c, tau_c in column n-1
+    const int t = threadIdx.x, tx = t % G, ty = t / G, lane = t & 63, wid = t >> 6;
+    float h[R][R];
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            const int i = tx + G * a, j = ty + G * b;
+            h[a][b] = (i < n && j < n) ? (float)A[(size_t)j * lda + i] : 0.f;
+        }
     for (int c = 0; c + 2 < n; ++c) {
-        const int len = n - c - 1;  // rows c+1..n-1
-        float mx = 0.f;
-        for (int i = tid; i < len; i += BNT) {
-            const float x = H[(size_t)c * n + c + 1 + i];
-            v[i] = x;
-            if (i > 0) mx = fmaxf(mx, fabsf(x));
-        }
-        mx = wg_max(mx, red);
-        float ss = 0.f;
-        if (mx > 0.f)
-            for (int i = 1 + tid; i < len; i += BNT) {
-                const float t = v[i] / mx;
-                ss += t * t;
+        const int buf = c & 1;
+        // ---- reflector from column c (owner group ty == c mod G)
+        if (ty == c % G) {
+            const int bc = c / G;
+            float x[R];
+#pragma unroll
+            for (int a = 0; a < R; ++a) {
+                x[a] = 0.f;
+#pragma unroll
+                for (int b = 0; b < R; ++b)
+                    if (b == bc) x[a] = h[a][b];
             }
-        ss = wg_sum(ss, red);
-        if (tid == 0) {
-            const float alpha = v[0];
-            if (mx == 0.f) { sh[0] = 0.f; sh[1] = alpha; sh[2] = 0.f; }
-            else {
+            float mx = 0.f, alpha = 0.f;
+#pragma unroll
+            for (int a = 0; a < R; ++a) {
+                const int i = tx + G * a;
+                if (i >= c + 2) mx = fmaxf(mx, fabsf(x[a]));
+                if (i == c + 1) alpha = x[a];
+            }
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) {
+                mx = fmaxf(mx, __shfl_xor(mx, o));
+                alpha += __shfl_xor(alpha, o);
+            }
+            float ss = 0.f;
+            if (mx > 0.f) {
+                const float rm = 1.f / mx;
+#pragma unroll
+                for (int a = 0; a < R; ++a) {
+                    const int i = tx + G * a;
+                    const float y = x[a] * rm;
+                    if (i >= c + 2) ss += y * y;
+                }
+            }
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) ss += __shfl_xor(ss, o);
+            float tau = 0.f, beta = alpha, scl = 0.f;
+            if (mx > 0.f) {
                 const float nrm = hypotf(alpha, mx * sqrtf(ss));
-                const float b = (alpha >= 0.f) ? -nrm : nrm;
-                sh[0] = (b - alpha) / b;
-                sh[1] = b;
-                sh[2] = 1.f / (alpha - b);
+                beta = (alpha >= 0.f) ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scl = 1.f / (alpha - beta);
+            }
+#pragma unroll
+            for (int a = 0; a < R; ++a) {
+                const int i = tx + G * a;
+                const float v = (i == c + 1) ? 1.f : (i >= c + 2 ? x[a] * scl : 0.f);
+                vs[buf][i] = v;
+                if (i < n) Vg[(size_t)c * n + i] = v;
+                x[a] = (i == c + 1) ? beta : (i >= c + 2 ? 0.f : x[a]);
+            }
+#pragma unroll
+            for (int a = 0; a < R; ++a)
+#pragma unroll
+                for (int b = 0; b < R; ++b)
+                    if (b == bc) h[a][b] = x[a];
+            if (tx == 0) {
+                taus[buf] = tau;
+                Vg[(size_t)(n - 1) * n + c] = tau;
             }
         }
         __syncthreads();
-        const float tau = sh[0], beta = sh[1], scl = sh[2];
-        for (int i = tid; i < len; i += BNT) {
-            v[i] = (i == 0) ? 1.f : v[i] * scl;
-            H[(size_t)c * n + c + 1 + i] = (i == 0) ? beta : 0.f;
+        const float tau = taus[buf];
+        float vr[R], vc[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) vr[a] = vs[buf][tx + G * a];
+#pragma unroll
+        for (int b = 0; b < R; ++b) vc[b] = vs[buf][ty + G * b];
+        // ---- left update on columns > c: column sums over the G-lane group
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            float p = 0.f;
+#pragma unroll
+            for (int a = 0; a < R; ++a) p += vr[a] * h[a][b];
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) p += __shfl_xor(p, o);
+            const int j = ty + G * b;
+            const float sj = (j > c) ? tau * p : 0.f;
+#pragma unroll
+            for (int a = 0; a < R; ++a) h[a][b] -= vr[a] * sj;
+        }
+        // ---- right update: row sums over ty (wave shuffles, then LDS)
+        float zp[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+            float z = 0.f;
+#pragma unroll
+            for (int b = 0; b < R; ++b) z += h[a][b] * vc[b];
+#pragma unroll
+            for (int o = G; o < 64; o <<= 1) z += __shfl_xor(z, o);
+            zp[a] = z;
+        }
+        if (lane < G) {
+#pragma unroll
+            for (int a = 0; a < R; ++a) P[wid][tx + G * a] = zp[a];
         }
         __syncthreads();
-        if (tau != 0.f) {
-            // left: columns c+1..n-1, rows c+1..n-1 (one thread per column)
-            for (int j = c + 1 + tid; j < n; j += BNT) {
-                float *col = H + (size_t)j * n + c + 1;
-                float w = 0.f;
-                for (int i = 0; i < len; ++i) w += v[i] * col[i];
-                w *= tau;
-                for (int i = 0; i < len; ++i) col[i] -= w * v[i];
-            }
-            __syncthreads();
-            // right: rows 0..n-1, columns c+1..n-1 (one thread per row); U too
-            for (int i = tid; i < n; i += BNT) {
-                float w = 0.f;
-                for (int k = 0; k < len; ++k) w += H[(size_t)(c + 1 + k) * n + i] * v[k];
-                w *= tau;
-                for (int k = 0; k < len; ++k) H[(size_t)(c + 1 + k) * n + i] -= w * v[k];
-                float *urow = U + (size_t)i * n + c + 1;
-                float u = 0.f;
-                for (int k = 0; k < len; ++k) u += urow[k] * v[k];
-                u *= tau;
-                for (int k = 0; k < len; ++k) urow[k] -= u * v[k];
-            }
+        if (t < NP) {
+            float z = 0.f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) z += P[w][t];
+            zs[t] = tau * z;
         }
         __syncthreads();
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+            const float zi = zs[tx + G * a];
+#pragma unroll
+            for (int b = 0; b < R; ++b) h[a][b] -= zi * vc[b];
+        }
     }
+    // Hessenberg form out (exact zeros below the subdiagonal)
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            const int i = tx + G * a, j = ty + G * b;
+            if (i < n && j < n) Hg[(size_t)j * n + i] = (i > j + 1) ? 0.f : h[a][b];
+        }
+    __syncthreads();  // reflectors written by other threads become visible
+    // ---- U0 = P_0 P_1 ... P_{n-3}, accumulated backwards: U <- P_c U
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) h[a][b] = (tx + G * a == ty + G * b) ? 1.f : 0.f;
+    for (int c = n - 3; c >= 0; --c) {
+        float vr[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+            const int i = tx + G * a;
+            vr[a] = (i > c && i < n) ? Vg[(size_t)c * n + i] : 0.f;
+        }
+        const float tau = Vg[(size_t)(n - 1) * n + c];
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            float p = 0.f;
+#pragma unroll
+            for (int a = 0; a < R; ++a) p += vr[a] * h[a][b];
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) p += __shfl_xor(p, o);
+            const float sj = tau * p;
+#pragma unroll
+            for (int a = 0; a < R; ++a) h[a][b] -= vr[a] * sj;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            const int i = tx + G * a, j = ty + G * b;
+            if (i < n && j < n) Ug[(size_t)j * n + i] = h[a][b];
+        }
 }
 
 // ------------------------------------------------------ 3. band-LDS Schur
@@ -249,10 +369,10 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
                     HB(i, k + 1) = cs * t2 - sn * t1;
                 }
                 for (int i = tid; i < n; i += BSNT) {
-                    float *ur = U + (size_t)i * n;
-                    float t1 = ur[k], t2 = ur[k + 1];
-                    ur[k] = cs * t1 + sn * t2;
-                    ur[k + 1] = cs * t2 - sn * t1;
+                    float *u0 = U + (size_t)k * n + i, *u1 = u0 + n;
+                    const float t1 = *u0, t2 = *u1;
+                    *u0 = cs * t1 + sn * t2;
+                    *u1 = cs * t2 - sn * t1;
                 }
                 __syncthreads();
                 if (tid == 0) HB(k + 1, k) = 0.f;
@@ -265,9 +385,14 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
         ++its;
         float h11 = HB(ihi - 1, ihi - 1), h12 = HB(ihi - 1, ihi);
         float h21 = HB(ihi, ihi - 1), h22 = HB(ihi, ihi);
-        if (its == 10 || its == 20) {
-            float sx = fabsf(HB(ihi, ihi - 1)) + fabsf(HB(ihi - 1, ihi - 2));
-            h11 = 0.75f * sx + HB(ihi, ihi);
+        // exceptional shifts every 10 sweeps without a deflation, built from
+        // the bottom of the window and, every 20, from its top (breaks the
+        // cycles a stagnating window can fall into)
+        if (its % 10 == 0) {
+            const bool top = (its % 20 == 0);
+            const float sx = top ? fabsf(HB(l + 1, l)) + fabsf(HB(l + 2, l + 1))
+                                 : fabsf(HB(ihi, ihi - 1)) + fabsf(HB(ihi - 1, ihi - 2));
+            h11 = 0.75f * sx + (top ? HB(l, l) : HB(ihi, ihi));
             h12 = -0.4375f * sx;
             h21 = sx;
             h22 = h11;
@@ -287,6 +412,11 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
             z = b10 * b21;
         }
         __syncthreads();
+        // The column a step reduces (k-1) is read by every thread at the top
+        // of that step, so its final values (beta, 0, 0) are written one step
+        // later, when no thread reads it.
+        int pcol = -1, pk2 = 0;
+        float pbeta = 0.f;
         for (int k = l; k <= ihi - 1; ++k) {
             const int len = (k <= ihi - 2) ? 3 : 2;
             const int k2 = (len == 3) ? k + 2 : k + 1;
@@ -297,26 +427,26 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
             // left on n-k-len+lc0+3 columns, right on k+3 (+1) rows, the orthogonal factor on n rows
             napply += double(2 * n + 6 - len + lc0 + ((len == 3 && k + 3 <= ihi) ? 1 : 0));
             ++nsteps;
-            if (wv < 2) {
-                // left: columns {k-1} u [k+len, n), rows k, k+1, k2
-                const int nL = lc0 + (n - (k + len));
-                for (int qq = tid; qq < nL; qq += 128) {
-                    if (lc0 && qq == 0) {
-                        HB(k2, k - 1) = 0.f;
-                        HB(k + 1, k - 1) = 0.f;
-                        HB(k, k - 1) = beta;
-                    } else {
-                        const int j = k + len + qq - lc0;
-                        float a0 = HB(k, j), a1 = HB(k + 1, j), a2 = HB(k2, j);
-                        brefl(v1, v2, tau, a0, a1, a2);
-                        HB(k2, j) = a2; HB(k, j) = a0; HB(k + 1, j) = a1;
-                    }
+            if (wv < 4) {
+                // left: columns [k+len, n), rows k, k+1, k2, and the deferred
+                // column of the previous step
+                if (tid == 0 && pcol >= 0) {
+                    HB(pk2, pcol) = 0.f;
+                    HB(pcol + 2, pcol) = 0.f;
+                    HB(pcol + 1, pcol) = pbeta;
                 }
-            } else if (wv < 4) {
+                const int nL = n - (k + len);
+                for (int qq = tid; qq < nL; qq += 256) {
+                    const int j = k + len + qq;
+                    float a0 = HB(k, j), a1 = HB(k + 1, j), a2 = HB(k2, j);
+                    brefl(v1, v2, tau, a0, a1, a2);
+                    HB(k2, j) = a2; HB(k, j) = a0; HB(k + 1, j) = a1;
+                }
+            } else if (wv < 8) {
                 // right: rows [0, k) u {k+3}, columns k, k+1, k2
                 const int extra = (len == 3 && k + 3 <= ihi) ? 1 : 0;
                 const int nR = k + extra;
-                for (int qq = tid - 128; qq < nR; qq += 128) {
+                for (int qq = tid - 256; qq < nR; qq += 256) {
                     const int i = (qq < k) ? qq : k + 3;
                     float a0 = HB(i, k), a1 = HB(i, k + 1), a2 = HB(i, k2);
                     brefl(v1, v2, tau, a0, a1, a2);
@@ -341,20 +471,42 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
                 lv1[k] = v1; lv2[k] = v2; ltau[k] = tau;
             }
             __syncthreads();
+            pcol = (k > l) ? k - 1 : -1;
+            pbeta = beta;
+            pk2 = k2;
         }
-        // apply the sweep's reflectors to the rows of U (row-major), each
-        // thread streaming one row through a three-entry register window
+        if (tid == 0 && pcol >= 0) {
+            HB(pk2, pcol) = 0.f;
+            HB(pcol + 2, pcol) = 0.f;
+            HB(pcol + 1, pcol) = pbeta;
+        }
+        // apply the sweep's reflectors to the rows of U (column-major: a
+        // wave's loads and stores are contiguous), each thread streaming one
+        // row through a three-entry register window; the entries ahead are
+        // fetched 8 at a time so their loads overlap
         for (int i = tid; i < n; i += BSNT) {
-            float *ur = U + (size_t)i * n;
-            float z0 = ur[l], z1 = ur[l + 1], z2 = ur[l + 2];
-            for (int k = l; k <= ihi - 1; ++k) {
-                brefl(lv1[k], lv2[k], ltau[k], z0, z1, z2);
-                ur[k] = z0;
-                z0 = z1;
-                z1 = z2;
-                z2 = (k + 3 <= ihi) ? ur[k + 3] : 0.f;
+            float *ur = U + i;
+            float z0 = ur[(size_t)l * n], z1 = ur[(size_t)(l + 1) * n];
+            for (int k0 = l; k0 <= ihi - 1; k0 += 8) {
+                float ahead[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int c = k0 + 2 + r;
+                    ahead[r] = (c <= ihi) ? ur[(size_t)c * n] : 0.f;
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int k = k0 + r;
+                    if (k <= ihi - 1) {
+                        float z2 = ahead[r];
+                        brefl(lv1[k], lv2[k], ltau[k], z0, z1, z2);
+                        ur[(size_t)k * n] = z0;
+                        z0 = z1;
+                        z1 = z2;
+                    }
+                }
             }
-            ur[ihi] = z0;
+            ur[(size_t)ihi * n] = z0;
         }
         __syncthreads();
     }
@@ -376,171 +528,29 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
 }
 #undef HB
 
-// ------------------------------------------ 4. Lyapunov tri-solve (T in LDS)
-// T Y + Y T^T = W, T upper quasi-triangular (order n <= 256) stored packed
-// in LDS (column j: rows 0..j+1), Y overwrites W in global memory.  Block
-// pair (ib, jb) depends on the pairs below it (through T) and to its right
-// (through T^T): wavefront over ibb + jbb with ibb counted from the bottom
-// and jbb from the right.
-__host__ __device__ __forceinline__ int up_off(int i, int j) { return (j * (j + 3)) / 2 + i; }
-
-template <typename T>
-SYLV_DEVINL int pair_solve_b(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T b01, T b10, T b11,
-                             T r[4], T smin) {
-    T m[4][4];
-    const T zp = P ? T(1) : T(0), zq = Q ? T(1) : T(0), zpq = zp * zq;
-    m[0][0] = a00 + b00; m[0][1] = a01 * zp; m[0][2] = b10 * zq; m[0][3] = T(0);
-    m[1][0] = a10 * zp; m[1][1] = P ? a11 + b00 : T(1); m[1][2] = T(0); m[1][3] = b10 * zpq;
-    m[2][0] = b01 * zq; m[2][1] = T(0); m[2][2] = Q ? a00 + b11 : T(1); m[2][3] = a01 * zpq;
-    m[3][0] = T(0); m[3][1] = b01 * zpq; m[3][2] = a10 * zpq; m[3][3] = (P && Q) ? a11 + b11 : T(1);
-    int flag = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        int pr = c;
-        T pv = fabs(m[c][c]);
-#pragma unroll
-        for (int rr = c + 1; rr < 4; ++rr) {
-            T v = fabs(m[rr][c]);
-            if (v > pv) { pv = v; pr = rr; }
-        }
-#pragma unroll
-        for (int rr = c + 1; rr < 4; ++rr) {
-            const bool sw = (pr == rr);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                T x = m[c][k], y = m[rr][k];
-                m[c][k] = sw ? y : x;
-                m[rr][k] = sw ? x : y;
-            }
-            T x = r[c], y = r[rr];
-            r[c] = sw ? y : x;
-            r[rr] = sw ? x : y;
-        }
-        T piv = m[c][c];
-        if (fabs(piv) < smin) { piv = (piv >= T(0)) ? smin : -smin; m[c][c] = piv; flag = 1; }
-        const T inv = T(1) / piv;
-#pragma unroll
-        for (int rr = c + 1; rr < 4; ++rr) {
-            const T f = m[rr][c] * inv;
-#pragma unroll
-            for (int k = c + 1; k < 4; ++k) m[rr][k] -= f * m[c][k];
-            r[rr] -= f * r[c];
-        }
-    }
-#pragma unroll
-    for (int c = 3; c >= 0; --c) {
-        T acc = r[c];
-#pragma unroll
-        for (int k = c + 1; k < 4; ++k) acc -= m[c][k] * r[k];
-        r[c] = acc / m[c][c];
-    }
-    return flag;
-}
-
-__global__ __launch_bounds__(BNT) void k_btrsyl(BatchEq *eqs, const int *order) {
-    extern __shared__ unsigned char smem_raw[];
-    float *Tp = reinterpret_cast<float *>(smem_raw);
-    __shared__ int bstart[257];
-    __shared__ int nbs;
-    __shared__ float tmax_s;
+// ------------------------------------- 4. right factor of the tri-solve
+// With the reversal permutation P, T Y + Y T^T = W becomes
+// T Y' + Y' (P T^T P) = W P with Y = Y' P; P T^T P is upper quasi-triangular,
+// so the Sylvester tile solver applies.  W P and Y' P are folded into the
+// transforms by V = U P:  W P = U^T C V,  X = U Y' V^T.
+__global__ __launch_bounds__(BNT) void k_bpost(BatchEq *eqs, const int *order) {
     __shared__ float red[8];
     BatchEq &q = eqs[order[blockIdx.x]];
     if (!q.active) return;
     const int n = q.n;
-    const float *Tg = (const float *)q.ptr[BF_H];
-    float *Y = (float *)q.ptr[BF_W];
-    const int tid = threadIdx.x;
+    const float *T = (const float *)q.ptr[BF_H];
+    const float *U = (const float *)q.ptr[BF_U];
+    float *V = (float *)q.ptr[BF_V];
+    float *TB = (float *)q.ptr[BF_TB];
     float mx = 0.f;
-    for (int j = 0; j < n; ++j) {
-        const int rows = (j + 2 < n) ? j + 2 : n;
-        for (int i = tid; i < rows; i += BNT) {
-            const float t = Tg[(size_t)j * n + i];
-            Tp[up_off(i, j)] = t;
-            mx = fmaxf(mx, fabsf(t));
-        }
+    for (int e = threadIdx.x; e < n * n; e += BNT) {
+        const int i = e % n, j = e / n;
+        V[e] = U[(size_t)(n - 1 - j) * n + i];
+        TB[e] = T[(size_t)(n - 1 - i) * n + (n - 1 - j)];
+        mx = fmaxf(mx, fabsf(T[e]));
     }
     mx = wg_max(mx, red);
-    if (tid == 0) {
-        int nb = 0, i = 0;
-        while (i < n) {
-            bstart[nb++] = i;
-            i += (i + 1 < n && Tp[up_off(i + 1, i)] != 0.f) ? 2 : 1;
-        }
-        bstart[nb] = n;
-        nbs = nb;
-        tmax_s = mx;
-    }
-    __syncthreads();
-    const int P = nbs;
-    const float smin = fmaxf(num<float>::ulp * tmax_s, num<float>::safmin);
-    int myflag = 0;
-#define TT(i, j) Tp[up_off((i), (j))]
-#define YY(i, j) Y[(size_t)(j) * n + (i)]
-    for (int e = 0; e <= 2 * P - 2; ++e) {
-        const int lo = e - (P - 1) > 0 ? e - (P - 1) : 0;
-        const int hi = e < P - 1 ? e : P - 1;
-        const int nunits = hi - lo + 1;
-        const int tpu = nunits <= 4 ? 64 : nunits <= 8 ? 32 : nunits <= 16 ? 16 : nunits <= 32 ? 8
-                        : nunits <= 64 ? 4 : nunits <= 128 ? 2 : 1;
-        const int u = tid / tpu, sub = tid % tpu;
-        float part[4] = {0.f, 0.f, 0.f, 0.f};
-        int ri = 0, pi = 0, cj = 0, qj = 0;
-        const bool active = u < nunits;
-        if (active) {
-            const int ibb = lo + u, jbb = e - ibb;
-            const int ib = P - 1 - ibb, jb = P - 1 - jbb;
-            ri = bstart[ib]; pi = bstart[ib + 1] - ri;
-            cj = bstart[jb]; qj = bstart[jb + 1] - cj;
-            const int r2 = (pi == 2) ? ri + 1 : ri;
-            const int c2 = (qj == 2) ? cj + 1 : cj;
-            // sum over rows below: T(ri.., r') Y(r', cj..)
-#pragma unroll 2
-            for (int rp = ri + pi + sub; rp < n; rp += tpu) {
-                const float a0 = TT(ri, rp), a1 = TT(r2, rp);
-                const float y0 = YY(rp, cj), y1 = YY(rp, c2);
-                part[0] += a0 * y0; part[1] += a1 * y0;
-                part[2] += a0 * y1; part[3] += a1 * y1;
-            }
-            // sum over columns to the right: Y(ri.., c') T(cj.., c')
-#pragma unroll 2
-            for (int cp = cj + qj + sub; cp < n; cp += tpu) {
-                const float b0 = TT(cj, cp), b1 = TT(c2, cp);
-                const float y0 = YY(ri, cp), y1 = YY(r2, cp);
-                part[0] += y0 * b0; part[1] += y1 * b0;
-                part[2] += y0 * b1; part[3] += y1 * b1;
-            }
-        }
-        for (int o = 1; o < tpu; o <<= 1) {
-#pragma unroll
-            for (int z = 0; z < 4; ++z) part[z] += __shfl_xor(part[z], o);
-        }
-        if (active && sub == 0) {
-            const bool P2 = (pi == 2), Q2 = (qj == 2);
-            const float a00 = TT(ri, ri);
-            const float a01 = P2 ? TT(ri, ri + 1) : 0.f;
-            const float a10 = P2 ? TT(ri + 1, ri) : 0.f;
-            const float a11 = P2 ? TT(ri + 1, ri + 1) : 0.f;
-            // right coefficient T^T restricted to block jb
-            const float b00 = TT(cj, cj);
-            const float b01 = Q2 ? TT(cj + 1, cj) : 0.f;
-            const float b10 = Q2 ? TT(cj, cj + 1) : 0.f;
-            const float b11 = Q2 ? TT(cj + 1, cj + 1) : 0.f;
-            float r[4];
-            r[0] = YY(ri, cj) - part[0];
-            r[1] = P2 ? YY(ri + 1, cj) - part[1] : 0.f;
-            r[2] = Q2 ? YY(ri, cj + 1) - part[2] : 0.f;
-            r[3] = (P2 && Q2) ? YY(ri + 1, cj + 1) - part[3] : 0.f;
-            myflag |= pair_solve_b<float>(P2, Q2, a00, a01, a10, a11, b00, b01, b10, b11, r, smin);
-            YY(ri, cj) = r[0];
-            if (P2) YY(ri + 1, cj) = r[1];
-            if (Q2) YY(ri, cj + 1) = r[2];
-            if (P2 && Q2) YY(ri + 1, cj + 1) = r[3];
-        }
-        __syncthreads();
-    }
-#undef TT
-#undef YY
-    if (myflag) atomicOr(&q.flag, 1);
+    if (threadIdx.x == 0) q.tmax = (double)mx;
 }
 
 // --------------------------------------- 5. residual norms and loop control
@@ -615,7 +625,7 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
     size_t ws_f = 0, ws_d = 0;
     for (int i = 0; i < batch; ++i) {
         nmax = std::max(nmax, nn[i]);
-        ws_f += 4 * (size_t)nn[i] * nn[i];
+        ws_f += 6 * (size_t)nn[i] * nn[i];
         ws_d += (size_t)nn[i] * nn[i];
     }
     // workspace layout: [descriptors][order][counter][binary64 R...][binary32 H, U, W, Y ...]
@@ -645,6 +655,8 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
         q.ptr[BF_U] = pf; q.ld[BF_U] = n; pf += n2;
         q.ptr[BF_W] = pf; q.ld[BF_W] = n; pf += n2;
         q.ptr[BF_Y] = pf; q.ld[BF_Y] = n; pf += n2;
+        q.ptr[BF_V] = pf; q.ld[BF_V] = n; pf += n2;
+        q.ptr[BF_TB] = pf; q.ld[BF_TB] = n; pf += n2;
         q.active = 1;
     }
     BatchEq *deq = (BatchEq *)(base + o_eq);
@@ -658,14 +670,20 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
     // stages 1-3
     hipLaunchKernelGGL(k_bprep, dim3(batch), dim3(BNT), 0, s, deq, dord);
     {
+        // size buckets (order is longest first): n > 128, 64 < n <= 128, n <= 64
+        int e1 = 0, e2 = 0;
+        while (e1 < batch && nn[order[e1]] > 128) ++e1;
+        e2 = e1;
+        while (e2 < batch && nn[order[e2]] > 64) ++e2;
         double w = 0.0;
         for (int i = 0; i < batch; ++i) w += (14.0 / 3.0) * double(nn[i]) * nn[i] * nn[i];
         prof_add_work(KID_BHESS, w);
         ProfScope ps(KID_BHESS, s);
-        hipLaunchKernelGGL(k_bhess, dim3(batch), dim3(BNT), 0, s, deq, dord);
+        if (e1 > 0) hipLaunchKernelGGL((k_bhess_reg<32, 8>), dim3(e1), dim3(1024), 0, s, deq, dord, 0);
+        if (e2 > e1) hipLaunchKernelGGL((k_bhess_reg<16, 8>), dim3(e2 - e1), dim3(256), 0, s, deq, dord, e1);
+        if (batch > e2) hipLaunchKernelGGL((k_bhess_reg<16, 4>), dim3(batch - e2), dim3(256), 0, s, deq, dord, e2);
     }
     {
-        const size_t sm = sizeof(float) * (size_t)band_size(nmax);
         static bool attr = false;
         if (!attr) {
             if ((e = hipFuncSetAttribute((const void *)k_bschur, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -673,30 +691,30 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
                 return SYLV_ERR_HIP - (int)e;
             attr = true;
         }
+        // LDS buckets: the band of order 180 fits two workgroups per CU, of
+        // order 128 three
+        const int caps[3] = {256, 180, 128};
+        int b0 = 0;
         ProfScope ps(KID_BSCHUR, s);
-        hipLaunchKernelGGL(k_bschur, dim3(batch), dim3(BSNT), sm, s, deq, dord);
-    }
-    const size_t smt = sizeof(float) * (size_t)(up_off(0, nmax - 1) + nmax);
-    {
-        static bool attr = false;
-        if (!attr) {
-            if ((e = hipFuncSetAttribute((const void *)k_btrsyl, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)(sizeof(float) * (up_off(0, 255) + 256)))) != hipSuccess)
-                return SYLV_ERR_HIP - (int)e;
-            attr = true;
+        for (int bi = 0; bi < 3 && b0 < batch; ++bi) {
+            const int lo = (bi + 1 < 3) ? caps[bi + 1] : 0;
+            int b1 = b0;
+            while (b1 < batch && nn[order[b1]] > lo) ++b1;
+            if (b1 > b0) {
+                const size_t sm = sizeof(float) * (size_t)band_size(std::min(caps[bi], nn[order[b0]]));
+                hipLaunchKernelGGL(k_bschur, dim3(b1 - b0), dim3(BSNT), sm, s, deq, dord + b0);
+            }
+            b0 = b1;
         }
     }
-    auto trsolve = [&]() {
-        ProfScope ps(KID_BTRSYL, s);
-        hipLaunchKernelGGL(k_btrsyl, dim3(batch), dim3(BNT), smt, s, deq, dord);
-    };
-    // first iterate: W = U^T C U (U stored row-major = U^T column-major),
-    // Y solves T Y + Y T^T = W, X = U Y U^T
-    gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_C, 0, BF_Y, 1.f, 0, 0.f);
-    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_U, 1, BF_W, 1.f, 0, 0.f);
+    hipLaunchKernelGGL(k_bpost, dim3(batch), dim3(BNT), 0, s, deq, dord);
+    auto trsolve = [&]() { trsyl_batched(s, deq, dord, batch, nmax); };
+    // first iterate: W = U^T C V, Y' solves T Y' + Y' TB = W, X = U Y' V^T
+    gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 0, 0.f);
+    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f);
     trsolve();
-    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_W, 0, BF_Y, 1.f, 0, 0.f);
-    gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_U, 0, BF_X, 1.f, 0, 0.f);
+    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f);
+    gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 0, 0.f);
     int *hcnt = reinterpret_cast<int *>(hbuf);
     for (int pass = 0; pass <= o.max_iter; ++pass) {
         // R = C - A X - X A^T (binary64)
@@ -710,11 +728,11 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
         if (*hcnt == 0) break;
         // correction: W = 2^-e U^T R U ; tri-solve ; X += 2^e U Y U^T
-        gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_R, 0, BF_Y, 1.f, 1, 0.f);
-        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_U, 1, BF_W, 1.f, 0, 0.f);
+        gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_R, 0, BF_Y, 1.f, 1, 0.f);
+        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f);
         trsolve();
-        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_W, 0, BF_Y, 1.f, 0, 0.f);
-        gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_U, 0, BF_X, 1.f, 2, 1.f);
+        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f);
+        gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 1.f);
     }
     if ((e = hipMemcpyAsync(hq.data(), deq, sizeof(BatchEq) * batch, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return SYLV_ERR_HIP - (int)e;
@@ -740,7 +758,7 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
 size_t lyap_batched_bytes(int batch, const int *nn) {
     size_t ws_f = 0, ws_d = 0;
     for (int i = 0; i < batch; ++i) {
-        ws_f += 4 * (size_t)nn[i] * nn[i];
+        ws_f += 6 * (size_t)nn[i] * nn[i];
         ws_d += (size_t)nn[i] * nn[i];
     }
     size_t off = 0;

@@ -116,11 +116,10 @@ SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T 
     return flag;
 }
 
+// One tile (I, J) of Y: off-diagonal updates, then the in-LDS solve.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
-                                                   const T *__restrict__ TB, int ldtb, T *C, int ldc,
-                                                   int d, int nI, int jmin, const double *maxab,
-                                                   int *flag) {
+SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, const T *__restrict__ TB,
+                            int ldtb, T *C, int ldc, int I, int J, double maxab, int *flag) {
     __shared__ T sA[TS * TLD];   // TA diagonal tile, later reused
     __shared__ T sB[TS * TLD];   // TB diagonal tile
     __shared__ T sC[TS * TLD];   // rhs -> Y tile
@@ -130,8 +129,6 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
     __shared__ int nrb_s, ncb_s;
     typedef typename mfma16t<T>::v4 v4;
 
-    const int J = jmin + blockIdx.x;
-    const int I = nI - 1 - (d - J);
     const int r0 = tile_bound(TA, ldta, m, I), r1 = tile_bound(TA, ldta, m, I + 1);
     const int c0 = tile_bound(TB, ldtb, n, J), c1 = tile_bound(TB, ldtb, n, J + 1);
     const int p = r1 - r0, q = c1 - c0;
@@ -223,7 +220,7 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
     }
     __syncthreads();
     const int P = nrb_s, Q = ncb_s;
-    const T smin = (T)fmax((double)num<T>::ulp * (*maxab), (double)num<T>::safmin);
+    const T smin = (T)fmax((double)num<T>::ulp * maxab, (double)num<T>::safmin);
     int myflag = 0;
     // ---- 2. wavefront over block pairs: unit (ib, jb), ib counted from the
     // bottom; anti-diagonal e = ib + jb.  A unit's sums over the solved rows
@@ -309,6 +306,45 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
         C[(size_t)(c0 + j) * ldc + r0 + i] = sC[j * TLD + i];
     }
     if (myflag) atomicOr(flag, 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
+                                                   const T *__restrict__ TB, int ldtb, T *C, int ldc,
+                                                   int d, int nI, int jmin, const double *maxab,
+                                                   int *flag) {
+    const int J = jmin + blockIdx.x;
+    const int I = nI - 1 - (d - J);
+    trsyl_tile<T>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag);
+}
+
+// Batched form: tiles of anti-diagonal d of every active equation
+// (grid.x = tile within the anti-diagonal, grid.y = equation slot).
+// TA = T (field H), TB = the upper quasi-triangular right coefficient
+// (field TB), Y overwrites field W.
+__global__ __launch_bounds__(256) void k_btrsyl_diag(BatchEq *eqs, const int *order, int d) {
+    BatchEq &q = eqs[order[blockIdx.y]];
+    if (!q.active) return;
+    const int n = q.n;
+    const int nI = (n + TBASE - 1) / TBASE;
+    if (d > 2 * nI - 2) return;
+    const int jmin = d - (nI - 1) > 0 ? d - (nI - 1) : 0;
+    const int jmax = d < nI - 1 ? d : nI - 1;
+    const int J = jmin + (int)blockIdx.x;
+    if (J > jmax) return;
+    const int I = nI - 1 - (d - J);
+    trsyl_tile<float>(n, n, (const float *)q.ptr[BF_H], q.ld[BF_H], (const float *)q.ptr[BF_TB],
+                      q.ld[BF_TB], (float *)q.ptr[BF_W], q.ld[BF_W], I, J, q.tmax, &q.flag);
+}
+
+void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int nmax) {
+    if (batch <= 0 || nmax <= 0) return;
+    const int nI = (nmax + TBASE - 1) / TBASE;
+    for (int d = 0; d <= 2 * nI - 2; ++d) {
+        const int tiles = (d < nI ? d + 1 : 2 * nI - 1 - d);
+        ProfScope ps(KID_BTRSYL, s);
+        hipLaunchKernelGGL(k_btrsyl_diag, dim3(tiles, batch), dim3(256), 0, s, eqs, order, d);
+    }
 }
 
 template <typename T>

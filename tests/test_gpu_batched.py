@@ -154,3 +154,15 @@ def test_batch_fp64_low_uses_single_path():
     for (A, C, eig), X, info in zip(its, Xs, infos):
         assert info["precision_used"] == "fp64"
         check_item(A, C, eig, host(X), info)
+
+
+def test_batch_stagnating_window_converges():
+    """Item 2282 of the batch recipe (n = 188): its trailing 3x3 window
+    stagnates for dozens of binary32 sweeps; the exceptional shifts must get
+    it through without the binary64 fallback."""
+    sy = binding()
+    A, C, eig = workloads.config4_item(2282, 188)
+    Xs, infos = sy.solve_batched([(dev(A), dev(C))], fallback=False)
+    torch.cuda.synchronize()
+    assert infos[0]["status"] == 0, infos[0]
+    check_item(A, C, eig, host(Xs[0]), infos[0])
