@@ -55,8 +55,10 @@ extern "C" {
 typedef enum {
     SYLV_PREC_FP64 = 0, /* plain binary64 Bartels-Stewart (no refinement)          */
     SYLV_PREC_FP32 = 1, /* binary32 Schur/transforms/tri-solve + binary64 refinement */
-    SYLV_PREC_BF16 = 2, /* binary32 Schur, bfloat16-input MFMA products in the
-                           correction transforms + binary64 refinement             */
+    SYLV_PREC_BF16 = 2, /* as FP32, but every GEMM-shaped product (Hessenberg
+                           trailing updates, off-window QR updates, transforms)
+                           takes bfloat16-rounded inputs on BF16 MFMA; escalates
+                           to FP32 and then FP64 when fallback is set             */
     SYLV_PREC_AUTO = 4  /* per-equation choice by the learned selector (batched)   */
 } sylv_prec;
 
@@ -176,7 +178,9 @@ int sylv_residual(int m, int n, const double *A, int lda, const double *B, int l
                   double *R, int ldr, int lyap, double *rel_res, void *stream);
 
 /* C = alpha op(A) op(B) + beta C with op = transpose when ta/tb = 1.
- * prec FP64: double operands (FP64 MFMA); FP32: float operands (FP32 MFMA).
+ * prec FP64: double operands (FP64 MFMA); FP32: float operands (FP32 MFMA);
+ * BF16: float operands rounded to bfloat16 (nearest even) on load, BF16 MFMA
+ * with binary32 accumulation (the GEMM-shaped updates of the BF16 option).
  * op(A) is m x k, op(B) is k x n. */
 int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha,
               const void *A, int lda, const void *B, int ldb, double beta,

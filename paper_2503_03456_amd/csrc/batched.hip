@@ -26,7 +26,8 @@ static std::mutex g_sel_mu;
 static std::vector<float> g_selector;  // 5443 params + 16 means + 16 stds
 
 static bool batched_eligible(int kind, int n, const sylv_opts &o) {
-    return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 && o.low == SYLV_PREC_FP32;
+    return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 &&
+           (o.low == SYLV_PREC_FP32 || o.low == SYLV_PREC_BF16);
 }
 
 extern "C" size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, const int *n,
@@ -118,14 +119,16 @@ extern "C" int sylv_solve_batched(int batch, const int *kind, const int *m, cons
             sylv_info f = binf[t];
             const bool ok = f.status == SYLV_OK || f.status == SYLV_ST_PERTURBED;
             if (!ok && o.fallback) {
+                // next rung of the ladder: bfloat16 updates -> binary32 (which
+                // itself falls back to binary64) ; binary32 -> binary64
                 sylv_opts f64 = o;
-                f64.low = SYLV_PREC_FP64;
+                f64.low = (o.low == SYLV_PREC_BF16) ? SYLV_PREC_FP32 : SYLV_PREC_FP64;
                 sylv_info g;
                 rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &f64, &g, work,
                                 work_bytes, stream);
                 if (rc) return rc;
                 g.fell_back = 1;
-                g.iterations = f.iterations;
+                g.iterations += f.iterations;
                 f = g;
             }
             if (infos) infos[i] = f;

@@ -13,6 +13,7 @@
 // fed swapped (op(B)^T in the A slot, op(A)^T in the B slot) so that each
 // lane's accumulators run down a column of C: stores are 16 consecutive
 // elements of a column per quarter-wave.
+#include <type_traits>
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -125,6 +126,123 @@ SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int ld
             }
 }
 
+// ---------------------------------------------------------------- BF16 inputs
+// Operands rounded to bfloat16 (round to nearest even) on their way into LDS
+// and multiplied by v_mfma_f32_16x16x32_bf16 with binary32 accumulation.  A
+// binary64 operand is rounded to binary32 first.  Products of two bf16
+// values are exact in binary32, so the result equals the binary32 GEMM of
+// the rounded operands up to the order of the binary32 additions.
+SYLV_DEVINL unsigned short bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int HBK = 32, HLD = HBK + 8;  // K slab and LDS row length (ushort; 80-byte rows)
+
+template <typename TA, typename TB, typename TC>
+SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, int lda, int ta,
+                                const TB *__restrict__ B, int ldb, int tb, TC *__restrict__ C, int ldc,
+                                float alpha, float beta, TB bscale, int row0, int col0,
+                                unsigned short (&As)[GBM][HLD], unsigned short (&Bs)[GBN][HLD]) {
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wm = w & 1, wn = w >> 1;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    unsigned short ra[8], rb[8];
+    // slab element r of this thread: A (i, k) and B (k, j) with coalesced global reads
+    auto aidx = [&](int r, int &i, int &k) {
+        if (!ta) { i = t & 63; k = (t >> 6) + 4 * r; } else { k = t & 31; i = (t >> 5) + 8 * r; }
+    };
+    auto bidx = [&](int r, int &k, int &j) {
+        if (!tb) { k = t & 31; j = (t >> 5) + 8 * r; } else { j = t & 63; k = (t >> 6) + 4 * r; }
+    };
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            int i, k;
+            aidx(r, i, k);
+            const int gi = row0 + i, gk = k0 + k;
+            float v = 0.f;
+            if (gi < M && gk < K) v = (float)(ta ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi]);
+            ra[r] = bf16_rne(v);
+            int j;
+            bidx(r, k, j);
+            const int gj = col0 + j, gk2 = k0 + k;
+            float u = 0.f;
+            if (gj < N && gk2 < K) u = (float)(bscale * (tb ? B[(size_t)gk2 * ldb + gj] : B[(size_t)gj * ldb + gk2]));
+            rb[r] = bf16_rne(u);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            int i, k, j;
+            aidx(r, i, k);
+            As[i][k] = ra[r];
+            bidx(r, k, j);
+            Bs[j][k] = rb[r];
+        }
+    };
+    const int nk = (K + HBK - 1) / HBK;
+    if (nk > 0) load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        store();
+        __syncthreads();
+        if (kt + 1 < nk) load((kt + 1) * HBK);
+        const int kg = 8 * (l >> 4);
+        bf16x8 fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+            fa[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&As[32 * wm + 16 * a + (l & 15)][kg]));
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            fb[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&Bs[32 * wn + 16 * b + (l & 15)][kg]));
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[b], fa[a], acc[a][b], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = row0 + 32 * wm + 16 * a + (l & 15);
+                const int j = col0 + 32 * wn + 16 * b + mfma16<float>::orow(l, r);
+                if (i < M && j < N) {
+                    TC *p = C + (size_t)j * ldc + i;
+                    const float v = alpha * acc[a][b][r];
+                    if (beta != 0.f) *p = (TC)v + (TC)beta * (*p);
+                    else *p = (TC)v;
+                }
+            }
+}
+
+template <typename TA, typename TB, typename TC>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const TA *__restrict__ A,
+                                                        int lda, int ta, const TB *__restrict__ B, int ldb,
+                                                        int tb, TC *__restrict__ C, int ldc, float alpha,
+                                                        float beta, int tiles_m, TB bscale) {
+    __shared__ __align__(16) unsigned short As[GBM][HLD];
+    __shared__ __align__(16) unsigned short Bs[GBN][HLD];
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+    const int tm = bid % tiles_m, tn = bid / tiles_m;
+    gemm_bf16_tile<TA, TB, TC>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, bscale, tm * GBM,
+                               tn * GBN, As, Bs);
+}
+
 template <typename TA, typename TB, typename TC, typename ACC>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
                                                    const TA *__restrict__ A, int lda, int ta,
@@ -146,13 +264,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
 // Batched form over the equations of a batch: grid.y = equation slot (in
 // the order given), grid.x = 64x64 tile of that equation's n x n product.
 // Operands are fields of the per-equation descriptor.
-template <typename TA, typename TB, typename TC, typename ACC>
+template <typename TA, typename TB, typename TC, typename ACC, int BF16IN>
 __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__restrict__ eqs,
                                                            const int *__restrict__ order, int fa,
                                                            int ta, int fb, int tb, int fc,
                                                            ACC alpha, int amode, ACC beta) {
-    __shared__ ACC As[GBK][GBM + GPAD];
-    __shared__ ACC Bs[GBK][GBN + GPAD];
+    typedef typename std::conditional<BF16IN != 0, unsigned short, ACC>::type LT;
+    constexpr int R0 = BF16IN ? GBM : GBK, C0 = BF16IN ? HLD : GBM + GPAD;
+    constexpr int C1 = BF16IN ? HLD : GBN + GPAD;
+    __shared__ __align__(16) LT As[R0][C0];
+    __shared__ __align__(16) LT Bs[BF16IN ? GBN : GBK][C1];
     const BatchEq &q = eqs[order[blockIdx.y]];
     if (!q.active) return;
     const int n = q.n;
@@ -166,52 +287,74 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__rest
     TB bs = TB(1);
     if (amode == 1) bs = (TB)q.scale;
     else if (amode == 2) al = (ACC)(alpha / q.scale);
-    gemm_tile<TA, TB, TC, ACC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
-                               q.ld[fb], tb, (TC *)q.ptr[fc], q.ld[fc], al, beta, bs, tm * GBM,
-                               tn * GBN, As, Bs);
+    if constexpr (BF16IN != 0)
+        gemm_bf16_tile<TA, TB, TC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
+                                   q.ld[fb], tb, (TC *)q.ptr[fc], q.ld[fc], (float)al, (float)beta, bs,
+                                   tm * GBM, tn * GBN, As, Bs);
+    else
+        gemm_tile<TA, TB, TC, ACC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
+                                   q.ld[fb], tb, (TC *)q.ptr[fc], q.ld[fc], al, beta, bs, tm * GBM,
+                                   tn * GBN, As, Bs);
 }
 
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch, int nmax, int fa,
-                  int ta, int fb, int tb, int fc, ACC alpha, int amode, ACC beta) {
+                  int ta, int fb, int tb, int fc, ACC alpha, int amode, ACC beta, int in_bf16) {
     if (batch <= 0) return;
     const int tl = (nmax + GBM - 1) / GBM;
     ProfScope ps(KID_BGEMM, s);
-    hipLaunchKernelGGL((gemm_batched_kernel<TA, TB, TC, ACC>), dim3(tl * tl, batch), dim3(256), 0, s,
+    if constexpr (sizeof(ACC) == sizeof(float)) {
+        if (in_bf16) {
+            hipLaunchKernelGGL((gemm_batched_kernel<TA, TB, TC, ACC, 1>), dim3(tl * tl, batch), dim3(256), 0,
+                               s, eqs, order, fa, ta, fb, tb, fc, alpha, amode, beta);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((gemm_batched_kernel<TA, TB, TC, ACC, 0>), dim3(tl * tl, batch), dim3(256), 0, s,
                        eqs, order, fa, ta, fb, tb, fc, alpha, amode, beta);
 }
 template void gemm_batched<double, double, double, double>(hipStream_t, const BatchEq *, const int *,
                                                            int, int, int, int, int, int, int, double,
-                                                           int, double);
+                                                           int, double, int);
 template void gemm_batched<float, float, float, float>(hipStream_t, const BatchEq *, const int *, int,
-                                                       int, int, int, int, int, int, float, int, float);
+                                                       int, int, int, int, int, int, float, int, float,
+                                                       int);
 template void gemm_batched<float, double, float, float>(hipStream_t, const BatchEq *, const int *, int,
-                                                        int, int, int, int, int, int, float, int, float);
+                                                        int, int, int, int, int, int, float, int, float,
+                                                        int);
 template void gemm_batched<float, float, double, float>(hipStream_t, const BatchEq *, const int *, int,
-                                                        int, int, int, int, int, int, float, int, float);
+                                                        int, int, int, int, int, int, float, int, float,
+                                                        int);
 
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const TA *A, int lda,
-          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale) {
+          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale, int in_bf16) {
     if (M <= 0 || N <= 0) return;
     int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
     prof_add_work(KID_GEMM, 2.0 * M * N * K);
     ProfScope ps(KID_GEMM, s);
+    if constexpr (sizeof(ACC) == sizeof(float)) {
+        if (in_bf16) {
+            hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, TC>), dim3(tm * tn), dim3(256), 0, s, M, N, K, A,
+                               lda, ta, B, ldb, tb, C, ldc, (float)alpha, (float)beta, tm, bscale);
+            return;
+        }
+    }
     hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, ACC>), dim3(tm * tn), dim3(256), 0, s, M, N, K, A,
                        lda, ta, B, ldb, tb, C, ldc, alpha, beta, tm, bscale);
 }
 
 template void gemm<double, double, double, double>(hipStream_t, int, int, int, int, int, double,
                                                    const double *, int, const double *, int,
-                                                   double, double *, int, double);
+                                                   double, double *, int, double, int);
 template void gemm<float, float, float, float>(hipStream_t, int, int, int, int, int, float,
                                                const float *, int, const float *, int, float,
-                                               float *, int, float);
+                                               float *, int, float, int);
 template void gemm<float, double, float, float>(hipStream_t, int, int, int, int, int, float,
                                                 const float *, int, const double *, int, float,
-                                                float *, int, double);
+                                                float *, int, double, int);
 template void gemm<float, float, double, float>(hipStream_t, int, int, int, int, int, float,
                                                 const float *, int, const float *, int, float,
-                                                double *, int, float);
+                                                double *, int, float, int);
 
 }  // namespace sylv

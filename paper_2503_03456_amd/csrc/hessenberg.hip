@@ -237,7 +237,7 @@ template size_t hessenberg_work_elems<double>(int, int, int);
 
 // A (n x n) -> H in place; U (n x n) receives U0.  work: hessenberg_work_elems.
 template <typename T>
-void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int nb, int S) {
+void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int nb, int S, int bf16) {
     if (n <= 0) return;
     identity<T>(s, n, U, ldu);
     if (n <= 2) return;
@@ -275,14 +275,14 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
         if (nt > 0) {
             // right: A(:, c1:n) -= Y V(c1:n, k0:k0+nbp)^T
             gemm<T, T, T, T>(s, 0, 1, n, nt, nbp, T(-1), Y, n, V + (size_t)k0 * n + c1, n, T(1),
-                             A + (size_t)c1 * lda, lda);
+                             A + (size_t)c1 * lda, lda, T(1), bf16);
             // left: A(k0+1:n, c1:n) -= V T^T (V^T A(k0+1:n, c1:n))
             const int mr = n - k0 - 1;
             gemm<T, T, T, T>(s, 1, 0, nbp, nt, mr, T(1), V + (size_t)k0 * n + k0 + 1, n,
-                             A + (size_t)c1 * lda + k0 + 1, lda, T(0), W, nbp);
+                             A + (size_t)c1 * lda + k0 + 1, lda, T(0), W, nbp, T(1), bf16);
             gemm<T, T, T, T>(s, 1, 0, nbp, nt, nbp, T(1), Tp, nb, W, nbp, T(0), W2, nbp);
             gemm<T, T, T, T>(s, 0, 0, mr, nt, nbp, T(-1), V + (size_t)k0 * n + k0 + 1, n, W2, nbp,
-                             T(1), A + (size_t)c1 * lda + k0 + 1, lda);
+                             T(1), A + (size_t)c1 * lda + k0 + 1, lda, T(1), bf16);
         }
     }
     // U0 = Q_0 Q_1 ... : apply the block reflectors backwards to the identity
@@ -293,13 +293,13 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
         const int mr = n - k0 - 1;
         T *Us = U + (size_t)(k0 + 1) * ldu + k0 + 1;
         gemm<T, T, T, T>(s, 1, 0, nbp, mr, mr, T(1), V + (size_t)k0 * n + k0 + 1, n, Us, ldu, T(0),
-                         W, nbp);
+                         W, nbp, T(1), bf16);
         gemm<T, T, T, T>(s, 0, 0, nbp, mr, nbp, T(1), Tp, nb, W, nbp, T(0), W2, nbp);
         gemm<T, T, T, T>(s, 0, 0, mr, mr, nbp, T(-1), V + (size_t)k0 * n + k0 + 1, n, W2, nbp, T(1),
-                         Us, ldu);
+                         Us, ldu, T(1), bf16);
     }
 }
-template void hessenberg<float>(hipStream_t, int, float *, int, float *, int, float *, int, int);
-template void hessenberg<double>(hipStream_t, int, double *, int, double *, int, double *, int, int);
+template void hessenberg<float>(hipStream_t, int, float *, int, float *, int, float *, int, int, int);
+template void hessenberg<double>(hipStream_t, int, double *, int, double *, int, double *, int, int, int);
 
 }  // namespace sylv

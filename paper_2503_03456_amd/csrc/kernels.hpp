@@ -45,11 +45,11 @@ void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int
 // gemm.hip
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const TA *A, int lda,
-          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale = TB(1));
+          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale = TB(1), int in_bf16 = 0);
 
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch, int nmax, int fa,
-                  int ta, int fb, int tb, int fc, ACC alpha, int amode, ACC beta);
+                  int ta, int fb, int tb, int fc, ACC alpha, int amode, ACC beta, int in_bf16 = 0);
 
 // blas.hip
 template <typename TS, typename TD>
@@ -70,7 +70,8 @@ void axpy(hipStream_t s, int r, int c, double alpha, const TS *D, int ldd, doubl
 template <typename T>
 size_t hessenberg_work_elems(int n, int nb, int S);
 template <typename T>
-void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int nb, int S);
+void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int nb, int S,
+                int bf16 = 0);
 
 // hqr.hip
 template <typename T>

@@ -709,12 +709,13 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
     }
     hipLaunchKernelGGL(k_bpost, dim3(batch), dim3(BNT), 0, s, deq, dord);
     auto trsolve = [&]() { trsyl_batched(s, deq, dord, batch, nmax); };
+    const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
     // first iterate: W = U^T C V, Y' solves T Y' + Y' TB = W, X = U Y' V^T
-    gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 0, 0.f);
-    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f);
+    gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 0, 0.f, bf16);
+    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f, bf16);
     trsolve();
-    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f);
-    gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 0, 0.f);
+    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f, bf16);
+    gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 0, 0.f, bf16);
     int *hcnt = reinterpret_cast<int *>(hbuf);
     for (int pass = 0; pass <= o.max_iter; ++pass) {
         // R = C - A X - X A^T (binary64)
@@ -728,11 +729,11 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
         if (*hcnt == 0) break;
         // correction: W = 2^-e U^T R U ; tri-solve ; X += 2^e U Y U^T
-        gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_R, 0, BF_Y, 1.f, 1, 0.f);
-        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f);
+        gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_R, 0, BF_Y, 1.f, 1, 0.f, bf16);
+        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f, bf16);
         trsolve();
-        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f);
-        gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 1.f);
+        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f, bf16);
+        gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 1.f, bf16);
     }
     if ((e = hipMemcpyAsync(hq.data(), deq, sizeof(BatchEq) * batch, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return SYLV_ERR_HIP - (int)e;
@@ -747,7 +748,7 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
             std::memset(&f, 0, sizeof(f));
             f.rel_res = q.rel_res;
             f.iterations = q.iterations;
-            f.precision_used = SYLV_PREC_FP32;
+            f.precision_used = o.low;
             f.status = q.status;
             f.fell_back = 0;
         }

@@ -52,6 +52,7 @@ struct Ctx {
     T *hw, *Zw, *Uw, *tmp, *wr, *wi, *trd;
     int *dint;
     char *hbuf;  // pinned host staging (>= 4 KiB)
+    int bf16;    // off-window updates with bfloat16 inputs (binary32 forms only)
 };
 
 template <typename T>
@@ -89,16 +90,16 @@ void apply_window(Ctx<T> &c, int w0, int w, const T *Z) {
     const int nc = n - (w0 + w);
     if (nc > 0) {
         T *blk = c.H + (size_t)(w0 + w) * c.ldh + w0;
-        gemm<T, T, T, T>(c.s, 1, 0, w, nc, w, T(1), Z, w, blk, c.ldh, T(0), c.tmp, w);
+        gemm<T, T, T, T>(c.s, 1, 0, w, nc, w, T(1), Z, w, blk, c.ldh, T(0), c.tmp, w, T(1), c.bf16);
         cast<T, T>(c.s, w, nc, c.tmp, w, blk, c.ldh, T(1));
     }
     if (w0 > 0) {
         T *blk = c.H + (size_t)w0 * c.ldh;
-        gemm<T, T, T, T>(c.s, 0, 0, w0, w, w, T(1), blk, c.ldh, Z, w, T(0), c.tmp, w0);
+        gemm<T, T, T, T>(c.s, 0, 0, w0, w, w, T(1), blk, c.ldh, Z, w, T(0), c.tmp, w0, T(1), c.bf16);
         cast<T, T>(c.s, w0, w, c.tmp, w0, blk, c.ldh, T(1));
     }
     T *ub = c.U + (size_t)w0 * c.ldu;
-    gemm<T, T, T, T>(c.s, 0, 0, n, w, w, T(1), ub, c.ldu, Z, w, T(0), c.tmp, n);
+    gemm<T, T, T, T>(c.s, 0, 0, n, w, w, T(1), ub, c.ldu, Z, w, T(0), c.tmp, n, T(1), c.bf16);
     cast<T, T>(c.s, n, w, c.tmp, n, ub, c.ldu, T(1));
 }
 
@@ -135,14 +136,15 @@ void pair_shifts(const std::vector<double> &wr, const std::vector<double> &wi, i
 
 template <typename T>
 int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char *hbuf,
-              int *qr_status) {
+              int *qr_status, int bf16) {
     typedef SchurParams<T> P;
     *qr_status = 0;
     if (n <= 0) return 0;
     Ctx<T> c{s, n, H, ldh, U, ldu};
     c.hbuf = hbuf;
+    c.bf16 = (sizeof(T) == sizeof(float)) ? bf16 : 0;
     carve(c, ws);
-    hessenberg<T>(s, n, H, ldh, U, ldu, c.hw, P::HNB, P::HS);
+    hessenberg<T>(s, n, H, ldh, U, ldu, c.hw, P::HNB, P::HS, c.bf16);
     int *hi = reinterpret_cast<int *>(c.hbuf);
     hipError_t err;
     int kbot = n - 1;
@@ -267,7 +269,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
                      st_fst, st_kcyc, st_fst ? 1024.0 * st_kcyc / st_fst : 0.0);
     return 0;
 }
-template int schur_run<float>(hipStream_t, int, float *, int, float *, int, char *, char *, int *);
-template int schur_run<double>(hipStream_t, int, double *, int, double *, int, char *, char *, int *);
+template int schur_run<float>(hipStream_t, int, float *, int, float *, int, char *, char *, int *, int);
+template int schur_run<double>(hipStream_t, int, double *, int, double *, int, char *, char *, int *, int);
 
 }  // namespace sylv

@@ -27,6 +27,6 @@ size_t schur_work_bytes(int n);
 // memory.  *qr_status = 1 if the iteration cap was hit.  Synchronises s.
 template <typename T>
 int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char *hbuf,
-              int *qr_status);
+              int *qr_status, int bf16 = 0);
 
 }  // namespace sylv

@@ -206,9 +206,9 @@ static void lyap_right_factor(hipStream_t s, int n, Stage<T> &st) {
 
 template <typename T>
 static int schur_stage(hipStream_t s, int n, const double *A, int lda, T *Tm, T *Um, char *ws,
-                       char *hbuf, int *qr) {
+                       char *hbuf, int *qr, int bf16) {
     cast<double, T>(s, n, n, A, lda, Tm, n, 1.0);
-    return schur_run<T>(s, n, Tm, n, Um, n, ws, hbuf, qr);
+    return schur_run<T>(s, n, Tm, n, Um, n, ws, hbuf, qr, bf16);
 }
 
 // Schur forms of A (and of B for Sylvester).  The two factorisations are
@@ -217,9 +217,10 @@ static int schur_stage(hipStream_t s, int n, const double *A, int lda, T *Tm, T 
 // host thread; the caller's stream waits for it at the end.
 template <typename T>
 static int schur_pair(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
-                      const double *B, int ldb, bool lyap, Stage<T> &st, int *qa, int *qb) {
+                      const double *B, int ldb, bool lyap, Stage<T> &st, int *qa, int *qb,
+                      int bf16 = 0) {
     if (lyap) {
-        int rc = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa);
+        int rc = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa, bf16);
         if (!rc) lyap_right_factor<T>(s, m, st);
         return rc;
     }
@@ -229,9 +230,9 @@ static int schur_pair(hipStream_t s, DevCtx *c, int m, int n, const double *A, i
     int rcb = 0;
     std::thread tb([&]() {
         hipSetDevice(c->dev);
-        rcb = schur_stage<T>(c->s2, n, B, ldb, st.TB, st.UB, st.schur_ws2, c->hbuf2, qb);
+        rcb = schur_stage<T>(c->s2, n, B, ldb, st.TB, st.UB, st.schur_ws2, c->hbuf2, qb, bf16);
     });
-    int rca = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa);
+    int rca = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa, bf16);
     tb.join();
     e = hipEventRecord(c->ev_out, c->s2);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_out, 0);
@@ -242,27 +243,29 @@ static int schur_pair(hipStream_t s, DevCtx *c, int m, int n, const double *A, i
 
 // X (binary64) <- alpha * UA * tri-solve(UA^T op(Rin) UB) * UB^T (+ X when accumulate)
 // Rin is binary64 (C or the residual); bscale scales it before the cast.
+// bf16: the four transforms take bfloat16-rounded inputs (binary32 stage only).
 template <typename T>
 static void correction(hipStream_t s, int m, int n, Stage<T> &st, const double *Rin, int ldr,
                        double bscale, double *X, int ldx, bool accumulate, const double *maxab,
-                       int *flag);
+                       int *flag, int bf16 = 0);
 
 template <>
 void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const double *Rin, int ldr,
                        double bscale, double *X, int ldx, bool accumulate, const double *maxab,
-                       int *flag) {
-    gemm<float, double, float, float>(s, 1, 0, m, n, m, 1.0f, st.UA, m, Rin, ldr, 0.0f, st.W1, m, bscale);
-    gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0f, st.W1, m, st.UB, n, 0.0f, st.Y, m);
+                       int *flag, int bf16) {
+    gemm<float, double, float, float>(s, 1, 0, m, n, m, 1.0f, st.UA, m, Rin, ldr, 0.0f, st.W1, m, bscale,
+                                      bf16);
+    gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0f, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, bf16);
     trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
-    gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0f, st.UA, m, st.Y, m, 0.0f, st.W1, m);
+    gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0f, st.UA, m, st.Y, m, 0.0f, st.W1, m, 1.0f, bf16);
     gemm<float, float, double, float>(s, 0, 1, m, n, n, (float)(1.0 / bscale), st.W1, m, st.UB, n,
-                                      accumulate ? 1.0f : 0.0f, X, ldx);
+                                      accumulate ? 1.0f : 0.0f, X, ldx, 1.0f, bf16);
 }
 
 template <>
 void correction<double>(hipStream_t s, int m, int n, Stage<double> &st, const double *Rin, int ldr,
                         double bscale, double *X, int ldx, bool accumulate, const double *maxab,
-                        int *flag) {
+                        int *flag, int) {
     gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0, st.W1, m, bscale);
     gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0, st.Y, m);
     trsyl<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
@@ -348,14 +351,16 @@ static int run_fp64(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
     return 0;
 }
 
-// binary32 factors + binary64 refinement.  *ok = 1 on convergence.
+// binary32 factors (GEMM-shaped updates with bfloat16 inputs when o.low is
+// BF16) + binary64 refinement.  *ok = 1 on convergence.
 static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
                      const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
                      int ldx, Plan &p, const Norms &nm, const sylv_opts &o, sylv_info *info,
                      int *ok) {
     *ok = 0;
     int qa = 0, qb = 0, rc;
-    rc = schur_pair<float>(s, c, m, n, A, lda, B, ldb, lyap, p.lo, &qa, &qb);
+    const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
+    rc = schur_pair<float>(s, c, m, n, A, lda, B, ldb, lyap, p.lo, &qa, &qb, bf16);
     if (rc) return rc;
     if (o.orth_check) {
         orth_check(s, m, p.lo.UA, p.G, p.scal + 20, p.nscr);
@@ -367,7 +372,7 @@ static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
     sep_estimate<float>(s, m, n, p.lo.TA, p.lo.TB, p.eig, p.scal + 13);
     hipMemsetAsync(p.flag, 0, sizeof(int), s);
     // first iterate: X0 = U Y V^T from the binary32 factors
-    correction<float>(s, m, n, p.lo, C, ldc, 1.0, X, ldx, false, p.scal + 12, p.flag);
+    correction<float>(s, m, n, p.lo, C, ldc, 1.0, X, ldx, false, p.scal + 12, p.flag, bf16);
     double prev = INFINITY, rel = INFINITY, corr = 0.0;
     int it = 0, stall = 0, status = SYLV_ST_NOT_CONVERGED;
     double h[32];
@@ -385,7 +390,7 @@ static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
         int ex = 0;
         std::frexp(h[1] > 0 ? h[1] : 1.0, &ex);
         double sc = std::ldexp(1.0, -ex);
-        correction<float>(s, m, n, p.lo, p.R, m, sc, X, ldx, true, p.scal + 12, p.flag);
+        correction<float>(s, m, n, p.lo, p.R, m, sc, X, ldx, true, p.scal + 12, p.flag, bf16);
         // ||D||_F ~ ||Y||_F / sc (orthogonal factors to binary32 accuracy)
         matnorm<float>(s, m, n, p.lo.Y, m, p.scal + 30, p.nscr, 0);
         ++it;
@@ -406,7 +411,7 @@ static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
         info->sep_est = h[13];
         info->corr_ratio = (h[2] > 0) ? corr / h[2] : 0.0;
         info->iterations = it;
-        info->precision_used = SYLV_PREC_FP32;
+        info->precision_used = bf16 ? SYLV_PREC_BF16 : SYLV_PREC_FP32;
         info->status = status;
     }
     return 0;
@@ -433,7 +438,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     if (!lyap && n > 0 && B == nullptr) return -5;
     if (m > 0 && n > 0 && (C == nullptr)) return -ci;
     if (m > 0 && n > 0 && (X == nullptr)) return -(ci + 2);
-    if (o.low != SYLV_PREC_FP64 && o.low != SYLV_PREC_FP32) return -(ci + 4);
+    if (o.low != SYLV_PREC_FP64 && o.low != SYLV_PREC_FP32 && o.low != SYLV_PREC_BF16) return -(ci + 4);
     if (!(o.tol >= 0.0) || o.max_iter < 0) return -(ci + 4);
     if (info) std::memset(info, 0, sizeof(*info));
     if (m == 0 || n == 0) {
@@ -470,6 +475,20 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     int ok = 0;
     rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
     if (rc) return rc;
+    int escalated = 0, iters = info ? info->iterations : 0;
+    if (!ok && o.fallback && o.low == SYLV_PREC_BF16) {
+        // escalation ladder: bfloat16 updates -> binary32 -> plain binary64
+        sylv_opts o32 = o;
+        o32.low = SYLV_PREC_FP32;
+        rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o32, info, &ok);
+        if (rc) return rc;
+        escalated = 1;
+        if (info) iters += info->iterations;
+    }
+    if (escalated && info) {
+        info->fell_back = 1;
+        info->iterations = iters;
+    }
     if (!ok && o.fallback) {
         sylv_info keep;
         if (info) keep = *info;
@@ -723,7 +742,7 @@ int sylv_residual(int m, int n, const double *A, int lda, const double *B, int l
 
 int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha, const void *A, int lda,
               const void *B, int ldb, double beta, void *C, int ldc, void *stream) {
-    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -1;
+    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32 && prec != SYLV_PREC_BF16) return -1;
     if (m < 0) return -4;
     if (n < 0) return -5;
     if (k < 0) return -6;
@@ -746,7 +765,8 @@ int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha, const
                                              (const double *)B, ldb, beta, (double *)C, ldc);
     else
         gemm<float, float, float, float>(s, ta, tb, m, n, k, (float)alpha, (const float *)A, lda,
-                                         (const float *)B, ldb, (float)beta, (float *)C, ldc);
+                                         (const float *)B, ldb, (float)beta, (float *)C, ldc, 1.0f,
+                                         prec == SYLV_PREC_BF16 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
     return 0;
