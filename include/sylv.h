@@ -59,7 +59,8 @@ typedef enum {
                            trailing updates, off-window QR updates, transforms)
                            takes bfloat16-rounded inputs on BF16 MFMA; escalates
                            to FP32 and then FP64 when fallback is set             */
-    SYLV_PREC_AUTO = 4  /* per-equation choice by the learned selector (batched)   */
+    SYLV_PREC_AUTO = 4  /* per-equation choice by the learned selector (see
+                           sylv_selector_set); needs installed weights          */
 } sylv_prec;
 
 typedef enum { SYLV_KIND_SYLV = 0, SYLV_KIND_LYAP = 1 } sylv_kind;
@@ -82,6 +83,8 @@ typedef struct {
     int    precision_used; /* sylv_prec of the path that produced X                             */
     int    fell_back;   /* 1 if the binary64 fallback produced X                                 */
     int    status;      /* SYLV_OK, or one of the SYLV_ST_* codes below                          */
+    int    chosen;      /* SYLV_PREC_AUTO: class picked by the selector (0 BF16, 1 FP32, 2 FP64);
+                           -1 otherwise                                                          */
 } sylv_info;
 
 #define SYLV_OK               0
@@ -188,8 +191,10 @@ int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha,
 
 /* ------------------------------------------------------------------------
  * Learned precision selector (MLP 16-64-64-3, FP32).  Features are the 16
- * cheap quantities listed in sylv_selector_features; classes are
- * 0 = BF16 + refinement, 1 = FP32 + refinement, 2 = plain FP64.
+ * quantities listed in sylv_selector_features, read from the binary32 Schur
+ * forms; classes are 0 = refinement with bfloat16-input transforms on those
+ * forms, 1 = refinement with binary32 transforms, 2 = plain binary64.  The
+ * residual test overrules the choice (0 -> 1 -> 2 on failure).
  * ---------------------------------------------------------------------- */
 
 #define SYLV_NFEAT 16
@@ -212,13 +217,23 @@ int sylv_mlp_train_step(int n, const float *feats, const int *labels, float *par
                         float *loss, void *stream);
 
 /* Install selector weights (host: 5443 params followed by 16 feature means
- * and 16 feature standard deviations) used by SYLV_PREC_AUTO. */
+ * and 16 feature standard deviations; all finite) used by SYLV_PREC_AUTO;
+ * nvalues = 0 uninstalls them (AUTO is then an invalid option).  Returns 0,
+ * -1 for a NULL or non-finite blob, -2 for a wrong length. */
 int sylv_selector_set(const float *blob, int nvalues);
 
-/* Features of one equation from its coefficient data (device pointers):
- * writes 16 floats to feats (host).  Sylvester: B given; Lyapunov: B NULL. */
-int sylv_selector_features(int m, int n, const double *A, int lda, const double *B,
-                           int ldb, const double *C, int ldc, float *feats, void *stream);
+/* The 16 selector features of one equation (A, B, C device pointers,
+ * binary64, column-major; B = NULL selects the Lyapunov equation
+ * AX + XA^T = C, n ignored), computed from its binary32 Schur forms (the
+ * forms SYLV_PREC_AUTO refines on): log2 m, log2 n, log10(||A||_F/sqrt m), log10(||B||_F/sqrt n),
+ * log10(||C||_F/sqrt(mn)), log10 sep_est (sep_est = min |l_i + m_j| of the
+ * computed spectra, Sec. 2.2), log10 kappa_est = log10((||A||_F+||B||_F)/sep_est),
+ * Henrici departure ||N||_F/||T||_F of T_A and T_B, fraction of eigenvalues in
+ * complex pairs (A, B), log10 relative minimum eigenvalue gap (A, B),
+ * log10 ||U^T U - I||_F and ||V^T V - I||_F, Lyapunov flag.  feats: host,
+ * 16 floats.  Returns 0, -i for an invalid i-th argument, or SYLV_ERR_*. */
+int sylv_selector_features(int m, int n, const double *A, int lda, const double *B, int ldb,
+                           const double *C, int ldc, float *feats, void *stream);
 
 /* ------------------------------------------------------------------------
  * Per-kernel timing (for roofline measurements).  sylv_profile_begin arms

@@ -44,7 +44,7 @@ class Info(ctypes.Structure):
                 ("orth_v", ctypes.c_double), ("sep_est", ctypes.c_double),
                 ("corr_ratio", ctypes.c_double), ("iterations", ctypes.c_int),
                 ("precision_used", ctypes.c_int), ("fell_back", ctypes.c_int),
-                ("status", ctypes.c_int)]
+                ("status", ctypes.c_int), ("chosen", ctypes.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -66,6 +66,16 @@ _lib.sylv_solve.restype = _i
 _lib.lyap_solve.argtypes = [_i, _vp, _i, _vp, _i, _vp, _i, ctypes.POINTER(Opts),
                             ctypes.POINTER(Info), _vp, _sz, _vp]
 _lib.lyap_solve.restype = _i
+NFEAT, NCLASS, NPARAM = 16, 3, 5443
+_fp = ctypes.POINTER(ctypes.c_float)
+_lib.sylv_selector_features.argtypes = [_i, _i, _vp, _i, _vp, _i, _vp, _i, _fp, _vp]
+_lib.sylv_selector_features.restype = _i
+_lib.sylv_selector_set.argtypes = [_fp, _i]
+_lib.sylv_selector_set.restype = _i
+_lib.sylv_mlp_forward.argtypes = [_i, _vp, _vp, _vp, _vp]
+_lib.sylv_mlp_forward.restype = _i
+_lib.sylv_mlp_train_step.argtypes = [_i, _vp, _vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp, _fp, _vp]
+_lib.sylv_mlp_train_step.restype = _i
 _pp = ctypes.POINTER(ctypes.c_void_p)
 _lib.sylv_solve_batched.argtypes = [_i, _ip, _ip, _ip, _pp, _ip, _pp, _ip, _pp, _ip, _pp, _ip,
                                     ctypes.POINTER(Opts), ctypes.POINTER(Info), _vp, _sz, _vp]

@@ -22,9 +22,6 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
 }
 using namespace sylv;
 
-static std::mutex g_sel_mu;
-static std::vector<float> g_selector;  // 5443 params + 16 means + 16 stds
-
 static bool batched_eligible(int kind, int n, const sylv_opts &o) {
     return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 &&
            (o.low == SYLV_PREC_FP32 || o.low == SYLV_PREC_BF16);
@@ -147,19 +144,4 @@ extern "C" int sylv_solve_batched(int batch, const int *kind, const int *m, cons
         if (rc) return rc;
     }
     return 0;
-}
-
-extern "C" int sylv_selector_set(const float *blob, int nvalues) {
-    if (!blob) return -1;
-    if (nvalues != SYLV_MLP_NPARAM + 2 * SYLV_NFEAT) return -2;
-    std::lock_guard<std::mutex> lk(g_sel_mu);
-    g_selector.assign(blob, blob + nvalues);
-    return 0;
-}
-
-extern "C" int sylv_selector_features(int m, int n, const double *A, int lda, const double *B, int ldb,
-                                      const double *C, int ldc, float *feats, void *stream) {
-    (void)m; (void)n; (void)A; (void)lda; (void)B; (void)ldb; (void)C; (void)ldc; (void)feats;
-    (void)stream;
-    return -1;
 }

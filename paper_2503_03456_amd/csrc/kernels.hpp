@@ -32,6 +32,10 @@ struct BatchEq {
     double napply;   // 3-element reflector applications of the Schur kernel
 };
 
+// selector.hip
+bool selector_installed();
+int selector_choose(hipStream_t s, char *hbuf, const float *feats, int *cls, float *probs);
+
 // solver.hip
 std::mutex &lib_mutex();
 int device_work(size_t bytes, void **work, char **hbuf);

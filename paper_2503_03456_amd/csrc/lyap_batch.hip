@@ -749,6 +749,7 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
             f.rel_res = q.rel_res;
             f.iterations = q.iterations;
             f.precision_used = o.low;
+            f.chosen = -1;
             f.status = q.status;
             f.fell_back = 0;
         }

@@ -146,13 +146,17 @@ __global__ __launch_bounds__(256) void k_mlp_adam(int n, int nblk, const float *
     for (int b = 0; b < nblk; ++b) g += part[(size_t)b * NPAR + q];
     g /= (float)n;
     if (grad) grad[q] = g;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    float mq = b1 * m[q] + (1.f - b1) * g;
-    float vq = b2 * v[q] + (1.f - b2) * g * g;
+    // beta1 = 0.9, beta2 = 0.999 (Kingma & Ba); 1 - beta is written as its
+    // own constant (1.f - 0.999f is 1.3e-5 away from 0.001 in binary32) and
+    // the bias corrections are formed in binary64
+    const float b1 = 0.9f, b2 = 0.999f, omb1 = 0.1f, omb2 = 0.001f, eps = 1e-8f;
+    float mq = b1 * m[q] + omb1 * g;
+    float vq = b2 * v[q] + omb2 * g * g;
     m[q] = mq;
     v[q] = vq;
-    float mh = mq / (1.f - powf(b1, (float)t));
-    float vh = vq / (1.f - powf(b2, (float)t));
+    const float c1 = (float)(1.0 - pow(0.9, (double)t)), c2 = (float)(1.0 - pow(0.999, (double)t));
+    float mh = mq / c1;
+    float vh = vq / c2;
     P[q] -= lr * mh / (sqrtf(vh) + eps);
 }
 

@@ -351,18 +351,16 @@ static int run_fp64(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
     return 0;
 }
 
-// binary32 factors (GEMM-shaped updates with bfloat16 inputs when o.low is
-// BF16) + binary64 refinement.  *ok = 1 on convergence.
-static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
-                     const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
-                     int ldx, Plan &p, const Norms &nm, const sylv_opts &o, sylv_info *info,
-                     int *ok) {
-    *ok = 0;
-    int qa = 0, qb = 0, rc;
-    const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
-    rc = schur_pair<float>(s, c, m, n, A, lda, B, ldb, lyap, p.lo, &qa, &qb, bf16);
+// Low-precision Schur forms of A (and B): binary32, with the GEMM-shaped
+// updates on bfloat16 inputs when bf16 is set; then the orthogonality check
+// (orth), max|T| for the tri-solve pivot threshold and the sep estimate.
+static int mixed_forms(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
+                       const double *B, int ldb, bool lyap, Plan &p, int bf16, int orth, int *qa,
+                       int *qb) {
+    *qa = *qb = 0;
+    int rc = schur_pair<float>(s, c, m, n, A, lda, B, ldb, lyap, p.lo, qa, qb, bf16);
     if (rc) return rc;
-    if (o.orth_check) {
+    if (orth) {
         orth_check(s, m, p.lo.UA, p.G, p.scal + 20, p.nscr);
         if (!lyap) orth_check(s, n, p.lo.UB, p.G, p.scal + 21, p.nscr);
     }
@@ -370,8 +368,18 @@ static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
     matnorm<float>(s, n, n, p.lo.TB, n, p.scal + 11, p.nscr, 1);
     matnorm<double>(s, 2, 1, p.scal + 10, 2, p.scal + 12, p.nscr, 1);
     sep_estimate<float>(s, m, n, p.lo.TA, p.lo.TB, p.eig, p.scal + 13);
+    return 0;
+}
+
+// Binary64 refinement (Alg. 3.1 in the original basis) on the forms held in
+// p.lo.  *ok = 1 on convergence.
+static int mixed_refine(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
+                        const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
+                        int ldx, Plan &p, const Norms &nm, const sylv_opts &o, int bf16, int qa, int qb,
+                        sylv_info *info, int *ok) {
+    *ok = 0;
     hipMemsetAsync(p.flag, 0, sizeof(int), s);
-    // first iterate: X0 = U Y V^T from the binary32 factors
+    // first iterate: X0 = U Y V^T from the low-precision factors
     correction<float>(s, m, n, p.lo, C, ldc, 1.0, X, ldx, false, p.scal + 12, p.flag, bf16);
     double prev = INFINITY, rel = INFINITY, corr = 0.0;
     int it = 0, stall = 0, status = SYLV_ST_NOT_CONVERGED;
@@ -386,12 +394,12 @@ static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
         if (it >= o.max_iter) break;
         if (rel > 0.5 * prev) { if (++stall >= 2) break; } else stall = 0;
         prev = rel;
-        // scale R by 2^-e so that max|R| is O(1) before the binary32 cast
+        // scale R by 2^-e so that max|R| is O(1) before the low-precision cast
         int ex = 0;
         std::frexp(h[1] > 0 ? h[1] : 1.0, &ex);
         double sc = std::ldexp(1.0, -ex);
         correction<float>(s, m, n, p.lo, p.R, m, sc, X, ldx, true, p.scal + 12, p.flag, bf16);
-        // ||D||_F ~ ||Y||_F / sc (orthogonal factors to binary32 accuracy)
+        // ||D||_F ~ ||Y||_F / sc (orthogonal factors to working accuracy)
         matnorm<float>(s, m, n, p.lo.Y, m, p.scal + 30, p.nscr, 0);
         ++it;
         double hy;
@@ -417,6 +425,152 @@ static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
     return 0;
 }
 
+// binary32 factors (GEMM-shaped updates with bfloat16 inputs when o.low is
+// BF16) + binary64 refinement.  *ok = 1 on convergence.
+static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
+                     const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
+                     int ldx, Plan &p, const Norms &nm, const sylv_opts &o, sylv_info *info,
+                     int *ok) {
+    *ok = 0;
+    int qa = 0, qb = 0;
+    const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
+    int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, bf16, o.orth_check, &qa, &qb);
+    if (rc) return rc;
+    return mixed_refine(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, bf16, qa, qb, info,
+                        ok);
+}
+
+// -------------------------------------------------- learned precision choice
+// Spectral statistics of a quasi-triangular T with eigenvalues (wr, wi):
+// out[0] = number of eigenvalues in complex pairs, out[1] = squared Frobenius
+// norm of the block-diagonal part, out[2] = min_{i != j} |l_i - l_j|,
+// out[3] = max |l_i|.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_spec_stats(int n, const T *Tm, int ld, const float *wr,
+                                                     const float *wi, double *out) {
+    __shared__ double r0[16], r1[16], r2[16], r3[16];
+    double ncx = 0.0, bd = 0.0, gap = 1e300, mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        if (wi[i] != 0.f) ncx += 1.0;
+        const double d = CM(Tm, i, i, ld);
+        bd += d * d;
+        if (i + 1 < n && CM(Tm, i + 1, i, ld) != T(0)) {
+            const double b = CM(Tm, i, i + 1, ld), c = CM(Tm, i + 1, i, ld);
+            bd += b * b + c * c;
+        }
+        mx = fmax(mx, sqrt((double)wr[i] * wr[i] + (double)wi[i] * wi[i]));
+    }
+    const size_t pairs = (size_t)n * n;
+    for (size_t e = threadIdx.x; e < pairs; e += 1024) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        if (i < j) {
+            const double dr = (double)wr[i] - wr[j], di = (double)wi[i] - wi[j];
+            gap = fmin(gap, sqrt(dr * dr + di * di));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ncx += __shfl_xor(ncx, o);
+        bd += __shfl_xor(bd, o);
+        gap = fmin(gap, __shfl_xor(gap, o));
+        mx = fmax(mx, __shfl_xor(mx, o));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { r0[w] = ncx; r1[w] = bd; r2[w] = gap; r3[w] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0, g = 1e300, x = 0;
+        for (int k = 0; k < 16; ++k) { a += r0[k]; b += r1[k]; g = fmin(g, r2[k]); x = fmax(x, r3[k]); }
+        out[0] = a; out[1] = b; out[2] = g; out[3] = x;
+    }
+}
+
+// The 16 selector features from the low-precision forms in p.lo (mixed_forms
+// with orth = 1 must have run).  Order:
+//  0 log2 m, 1 log2 n, 2 log10(||A||_F/sqrt m), 3 log10(||B||_F/sqrt n),
+//  4 log10(||C||_F/sqrt(mn)), 5 log10 sep_est, 6 log10 kappa_est
+//  (= (||A||_F + ||B||_F)/sep_est), 7-8 Henrici departure ||N||_F/||T||_F of
+//  T_A, T_B, 9-10 fraction of eigenvalues in complex pairs, 11-12 log10 of the
+//  relative minimum eigenvalue gap, 13-14 log10 ||U^T U - I||_F, ||V^T V - I||_F,
+//  15 Lyapunov flag.
+static int selector_features(hipStream_t s, DevCtx *c, int m, int n, bool lyap, Plan &p,
+                             const Norms &nm, float *f) {
+    float *wra = p.eig, *wia = p.eig + m, *wrb = p.eig + 2 * m, *wib = p.eig + 2 * m + n;
+    hipLaunchKernelGGL((k_spec_stats<float>), dim3(1), dim3(1024), 0, s, m, p.lo.TA, m, wra, wia, p.scal + 40);
+    hipLaunchKernelGGL((k_spec_stats<float>), dim3(1), dim3(1024), 0, s, n, p.lo.TB, n, wrb, wib, p.scal + 44);
+    matnorm<float>(s, m, m, p.lo.TA, m, p.scal + 48, p.nscr, 0);
+    matnorm<float>(s, n, n, p.lo.TB, n, p.scal + 49, p.nscr, 0);
+    double h[64];
+    hipError_t e = read_scalars(s, c, p.scal, 64, h);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    auto lg = [](double x) { return std::log10(std::max(x, 1e-300)); };
+    const double sep = std::max(h[13], 1e-300);
+    f[0] = (float)std::log2((double)m);
+    f[1] = (float)std::log2((double)n);
+    f[2] = (float)lg(nm.a / std::sqrt((double)m));
+    f[3] = (float)lg(nm.b / std::sqrt((double)n));
+    f[4] = (float)lg(nm.c / std::sqrt((double)m * n));
+    f[5] = (float)lg(sep);
+    f[6] = (float)lg((nm.a + nm.b) / sep);
+    auto henrici = [](double tf, double bd) {
+        return tf > 0 ? std::sqrt(std::max(tf * tf - bd, 0.0)) / tf : 0.0;
+    };
+    f[7] = (float)henrici(h[48], h[41]);
+    f[8] = (float)henrici(h[49], h[45]);
+    f[9] = (float)(h[40] / m);
+    f[10] = (float)(h[44] / n);
+    f[11] = (float)lg(m > 1 ? h[42] / std::max(h[43], 1e-300) : 1.0);
+    f[12] = (float)lg(n > 1 ? h[46] / std::max(h[47], 1e-300) : 1.0);
+    f[13] = (float)lg(h[20]);
+    f[14] = (float)lg(lyap ? h[20] : h[21]);
+    f[15] = lyap ? 1.f : 0.f;
+    return 0;
+}
+
+// SYLV_PREC_AUTO: binary32 forms, their 16 features, the selector's class,
+// then the chosen refinement on those same forms:
+//   0: transforms on bfloat16 inputs, 1: binary32 transforms, 2: plain binary64;
+// a failing class escalates (0 -> 1 on the same forms -> 2).
+static int run_auto(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
+                    const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
+                    int ldx, Plan &p, const Norms &nm, const sylv_opts &o, sylv_info *info) {
+    int qa = 0, qb = 0;
+    int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, 0, 1, &qa, &qb);
+    if (rc) return rc;
+    float f[SYLV_NFEAT], pr[SYLV_NCLASS];
+    rc = selector_features(s, c, m, n, lyap, p, nm, f);
+    if (rc) return rc;
+    int cls = 1;
+    rc = selector_choose(s, c->hbuf, f, &cls, pr);
+    if (rc) return rc;
+    sylv_opts oo = o;
+    oo.orth_check = 1;
+    sylv_info tmp;
+    sylv_info *inf = info ? info : &tmp;
+    int ok = 0, iters = 0, esc = 0;
+    if (cls == 0) {
+        rc = mixed_refine(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, oo, 1, qa, qb, inf, &ok);
+        if (rc) return rc;
+        iters += inf->iterations;
+        if (!ok && o.fallback) esc = 1;
+    }
+    if (cls == 1 || (cls == 0 && esc)) {
+        rc = mixed_refine(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, oo, 0, qa, qb, inf, &ok);
+        if (rc) return rc;
+        iters += inf->iterations;
+        if (!ok && o.fallback) esc = 1;
+    }
+    if (cls == 2 || (!ok && o.fallback)) {
+        rc = run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, inf);
+        if (rc) return rc;
+        if (cls != 2) esc = 1;
+    }
+    inf->iterations = iters;
+    inf->fell_back = esc;
+    inf->chosen = cls;
+    return 0;
+}
+
 static int solve_common_impl(int m, int n, const double *A, int lda, const double *B, int ldb,
                         const double *C, int ldc, double *X, int ldx, bool lyap,
                         const sylv_opts *opts, sylv_info *info, void *work, size_t work_bytes,
@@ -438,11 +592,17 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     if (!lyap && n > 0 && B == nullptr) return -5;
     if (m > 0 && n > 0 && (C == nullptr)) return -ci;
     if (m > 0 && n > 0 && (X == nullptr)) return -(ci + 2);
-    if (o.low != SYLV_PREC_FP64 && o.low != SYLV_PREC_FP32 && o.low != SYLV_PREC_BF16) return -(ci + 4);
+    const bool autosel = o.low == SYLV_PREC_AUTO;
+    if (o.low != SYLV_PREC_FP64 && o.low != SYLV_PREC_FP32 && o.low != SYLV_PREC_BF16 && !autosel)
+        return -(ci + 4);
+    if (autosel && !selector_installed()) return -(ci + 4);
     if (!(o.tol >= 0.0) || o.max_iter < 0) return -(ci + 4);
     if (info) std::memset(info, 0, sizeof(*info));
     if (m == 0 || n == 0) {
-        if (info) info->precision_used = o.low;
+        if (info) {
+            info->precision_used = o.low;
+            info->chosen = -1;
+        }
         return 0;
     }
     std::lock_guard<std::mutex> lk(g_mu);
@@ -451,8 +611,9 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const bool mixed = o.low != SYLV_PREC_FP64;
-    const bool need_hi = !mixed || o.fallback;
-    const size_t need = plan_bytes(m, n, lyap, mixed, need_hi, mixed && o.orth_check);
+    const bool need_hi = !mixed || o.fallback || autosel;
+    const bool orth = mixed && (o.orth_check || autosel);
+    const size_t need = plan_bytes(m, n, lyap, mixed, need_hi, orth);
     void *base = work;
     if (work) {
         if (work_bytes < need) return lyap ? -11 : -15;
@@ -462,7 +623,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     }
     Arena ar(base);
     Plan p;
-    plan(ar, m, n, lyap, mixed, need_hi, mixed && o.orth_check, p);
+    plan(ar, m, n, lyap, mixed, need_hi, orth, p);
     // norms of the coefficients (eq. (2.1) denominators)
     matnorm<double>(s, m, m, A, lda, p.scal + 40, p.nscr, 0);
     if (!lyap) matnorm<double>(s, n, n, B, ldb, p.scal + 41, p.nscr, 0);
@@ -471,7 +632,9 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     hipError_t e = read_scalars(s, c, p.scal + 40, 3, hn);
     if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
     Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2]};
+    if (info) info->chosen = -1;
     if (!mixed) return run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, info);
+    if (autosel) return run_auto(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info);
     int ok = 0;
     rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
     if (rc) return rc;
@@ -543,7 +706,52 @@ size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
     if (m < 0 || (!lyap && n < 0)) return 0;
     if (lyap) n = m;
     const bool mixed = o.low != SYLV_PREC_FP64;
-    return plan_bytes(m, n, lyap != 0, mixed, !mixed || o.fallback, mixed && o.orth_check);
+    const bool autosel = o.low == SYLV_PREC_AUTO;
+    return plan_bytes(m, n, lyap != 0, mixed, !mixed || o.fallback || autosel,
+                      mixed && (o.orth_check || autosel));
+}
+
+int sylv_selector_features(int m, int n, const double *A, int lda, const double *B, int ldb,
+                           const double *C, int ldc, float *feats, void *stream) {
+    const bool lyap = (B == nullptr);
+    if (lyap) n = m;
+    if (m < 1) return -1;
+    if (n < 1) return -2;
+    if (!A) return -3;
+    if (lda < m) return -4;
+    if (!lyap && ldb < n) return -6;
+    if (!C) return -7;
+    if (ldc < m) return -8;
+    if (!feats) return -9;
+    try {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DevCtx *c = nullptr;
+        int rc = device_ctx(&c);
+        if (rc) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        void *base = nullptr;
+        rc = ensure_work(c, plan_bytes(m, n, lyap, true, false, true), &base);
+        if (rc) return rc;
+        Arena ar(base);
+        Plan p;
+        plan(ar, m, n, lyap, true, false, true, p);
+        matnorm<double>(s, m, m, A, lda, p.scal + 40, p.nscr, 0);
+        if (!lyap) matnorm<double>(s, n, n, B, ldb, p.scal + 41, p.nscr, 0);
+        matnorm<double>(s, m, n, C, ldc, p.scal + 42, p.nscr, 0);
+        double hn[3];
+        hipError_t e = read_scalars(s, c, p.scal + 40, 3, hn);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2]};
+        int qa = 0, qb = 0;
+        rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, 0, 1, &qa, &qb);
+        if (rc) return rc;
+        rc = selector_features(s, c, m, n, lyap, p, nm, feats);
+        if (rc) return rc;
+        e = hipGetLastError();
+        return e == hipSuccess ? 0 : SYLV_ERR_HIP - (int)e;
+    } catch (const std::bad_alloc &) {
+        return SYLV_ERR_ALLOC;
+    }
 }
 
 int sylv_solve(int m, int n, const double *A, int lda, const double *B, int ldb, const double *C,

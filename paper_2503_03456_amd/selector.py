@@ -1,0 +1,294 @@
+"""Learned precision selector: features, labels, GPU training, evaluation.
+
+The network (16-64-64-3, ReLU, softmax; FP32) predicts, from the features of
+the binary32 Schur forms of an equation (``features``), which refinement is
+the cheapest to reach the binary64 residual level within ``K_STEPS`` steps
+(the solver's default cap):
+class 0 = bfloat16-input transforms on those forms, 1 = binary32 transforms,
+2 = plain binary64 Bartels-Stewart.  Labels come from solving each instance
+through the SYLV_PREC_AUTO path with each class forced in turn (weights whose
+output is a constant class) and timing it (``label``).  Training runs on the GPU through ``sylv_mlp_train_step``
+(forward, cross-entropy, backward and Adam in the library's own kernels).
+In a solve the choice is advisory: the residual test overrules it.
+
+Command line (run where a GPU is present):
+    python -m paper_2503_03456_amd.selector train --count 1500 --hi 384 --out W.npz
+    python -m paper_2503_03456_amd.selector evaluate --weights W.npz --count 200
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import NFEAT, NPARAM, lib, make_opts, solve, lyap, _check
+
+# refinement steps a low-precision class may take to count as converging: the
+# solver's own cap (with its stagnation rule).  A cap of 3 labels equations
+# whose binary32 refinement needs 4-6 steps as binary64, although on this GPU
+# a refinement step costs far less than the binary64 solve.
+K_STEPS = 20
+TOL = 1e-14
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.npz")
+LAYERS = [(64, 16), (64,), (64, 64), (64,), (3, 64), (3,)]
+
+
+def _dev(a):
+    return torch.from_numpy(np.asfortranarray(a)).t().contiguous().t().cuda()
+
+
+def features(A, B, C, stream=None):
+    """16 features (numpy float32) of one equation; B None -> Lyapunov.
+    A, B, C: column-major float64 CUDA tensors."""
+    m = C.shape[0]
+    n = C.shape[1]
+    f = (ctypes.c_float * NFEAT)()
+    st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    rc = lib().sylv_selector_features(
+        m, n, ctypes.c_void_p(A.data_ptr()), max(1, A.stride(1)),
+        ctypes.c_void_p(B.data_ptr() if B is not None else None), max(1, B.stride(1)) if B is not None else 1,
+        ctypes.c_void_p(C.data_ptr()), max(1, C.stride(1)), f, st)
+    _check(rc, "sylv_selector_features")
+    return np.frombuffer(f, dtype=np.float32).copy()
+
+
+def pack_blob(params, mean, std):
+    blob = np.concatenate([np.asarray(params, np.float32).ravel(), np.asarray(mean, np.float32),
+                           np.asarray(std, np.float32)])
+    assert blob.size == NPARAM + 2 * NFEAT
+    return blob
+
+
+def install(params, mean, std):
+    blob = pack_blob(params, mean, std)
+    rc = lib().sylv_selector_set(blob.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(blob.size))
+    _check(rc, "sylv_selector_set")
+
+
+def uninstall():
+    _check(lib().sylv_selector_set(None, 0), "sylv_selector_set")
+
+
+def load(path=WEIGHTS):
+    z = np.load(path, allow_pickle=False)
+    return z["params"], z["mean"], z["std"]
+
+
+def rule_params(lo=2.0, hi=6.0):
+    """Hand-set weights of the same network that implement a Table 3.1 style
+    rule on kappa_est (feature 6, unstandardised: mean 0, std 1): class 0 if
+    log10 kappa_est < lo (kappa u_bf16 small), class 2 if > hi (kappa u_fp32
+    too large), class 1 otherwise.  Logits (lo - x, 0, x - hi) through two
+    ReLU pairs carrying +x and -x."""
+    W1 = np.zeros((64, 16)); b1 = np.zeros(64)
+    W1[0, 6] = 1.0; W1[1, 6] = -1.0
+    W2 = np.zeros((64, 64)); b2 = np.zeros(64)
+    W2[0, 0] = 1.0; W2[1, 1] = 1.0
+    W3 = np.zeros((3, 64)); b3 = np.zeros(3)
+    W3[0, 0] = -1.0; W3[0, 1] = 1.0; b3[0] = lo     # lo - x
+    W3[2, 0] = 1.0; W3[2, 1] = -1.0; b3[2] = -hi    # x - hi
+    params = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3]).astype(np.float32)
+    return params, np.zeros(NFEAT, np.float32), np.ones(NFEAT, np.float32)
+
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, info = fn()
+    torch.cuda.synchronize()
+    return X, info, time.perf_counter() - t0
+
+
+def _run(eq, **kw):
+    A, B, C = eq
+    if B is None:
+        return lyap(A, C, **kw)
+    return solve(A, B, C, **kw)
+
+
+def forced_params(k):
+    """Weights whose output is class k for every input."""
+    p = np.zeros(NPARAM, np.float32)
+    p[-3 + k] = 10.0
+    return p, np.zeros(NFEAT, np.float32), np.ones(NFEAT, np.float32)
+
+
+def label(eq):
+    """(label, times[3], converged[3]) for one device-resident equation
+    (A, B or None, C): the AUTO path with each class forced, no escalation;
+    a refinement class counts when it reaches TOL within K_STEPS steps."""
+    times, conv = [], []
+    for k in range(3):
+        install(*forced_params(k))
+        _, info, dt = _timed(lambda: _run(eq, low="auto", max_iter=K_STEPS, fallback=False))
+        times.append(dt)
+        conv.append(info["rel_res"] <= TOL and info["status"] in (0, 1))
+    cand = [k for k in range(3) if conv[k]]
+    lab = min(cand, key=lambda k: times[k]) if cand else 2
+    return lab, times, conv
+
+
+def make_dataset(indices, lo, hi, seed_base, progress=True):
+    import workloads
+    F, y, T, meta = [], [], [], []
+    t0 = time.time()
+    for c, i in enumerate(indices):
+        d = workloads.selector_instance(int(i), lo, hi, seed_base)
+        eq = (_dev(d["A"]), None if d["B"] is None else _dev(d["B"]), _dev(d["C"]))
+        F.append(features(*eq))
+        lab, times, conv = label(eq)
+        y.append(lab)
+        T.append(times)
+        meta.append((int(i), d["C"].shape[0], d["C"].shape[1], d["delta"], d["lyap"]))
+        if progress and (c % 25 == 0 or c == len(indices) - 1):
+            print(f"[selector data] {c + 1}/{len(indices)} n={d['C'].shape} delta={d['delta']:.1e} "
+                  f"label={lab} ({time.time() - t0:.0f} s)", flush=True)
+    return np.array(F, np.float32), np.array(y, np.int32), np.array(T), meta
+
+
+def he_init(seed=0):
+    rs = np.random.RandomState(seed)
+    parts = []
+    for shp in LAYERS:
+        if len(shp) == 2:
+            parts.append(rs.standard_normal(shp) * np.sqrt(2.0 / shp[1]))
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def train(F, y, epochs=30, batch=512, lr=1e-3, seed=0, stream=None):
+    """Train on the GPU with the library's kernels.  Returns (params, mean,
+    std, per-epoch mean loss)."""
+    F = np.asarray(F, np.float32)
+    mean = F.mean(axis=0)
+    std = F.std(axis=0)
+    std[std < 1e-6] = 1.0
+    Z = (F - mean) / std
+    dev = torch.device("cuda")
+    theta = torch.from_numpy(he_init(seed)).to(dev)
+    am = torch.zeros(NPARAM, dtype=torch.float32, device=dev)
+    av = torch.zeros_like(am)
+    st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    rs = np.random.RandomState(seed + 1)
+    step, hist = 0, []
+    L = lib()
+    for ep in range(epochs):
+        perm = rs.permutation(len(y))
+        losses = []
+        for b0 in range(0, len(y), batch):
+            idx = perm[b0:b0 + batch]
+            xb = torch.from_numpy(np.ascontiguousarray(Z[idx])).to(dev)
+            yb = torch.from_numpy(np.ascontiguousarray(y[idx].astype(np.int32))).to(dev)
+            step += 1
+            loss = ctypes.c_float(0.0)
+            rc = L.sylv_mlp_train_step(len(idx), ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(yb.data_ptr()),
+                                       ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(am.data_ptr()),
+                                       ctypes.c_void_p(av.data_ptr()), step, ctypes.c_float(lr), None,
+                                       ctypes.byref(loss), st)
+            _check(rc, "sylv_mlp_train_step")
+            losses.append(loss.value)
+        hist.append(float(np.mean(losses)))
+    torch.cuda.synchronize()
+    return theta.cpu().numpy(), mean.astype(np.float32), std.astype(np.float32), hist
+
+
+def predict(params, mean, std, F):
+    dev = torch.device("cuda")
+    Z = torch.from_numpy(((np.asarray(F, np.float32) - mean) / std).astype(np.float32)).to(dev)
+    th = torch.from_numpy(np.asarray(params, np.float32)).to(dev)
+    P = torch.empty((len(F), 3), dtype=torch.float32, device=dev)
+    rc = lib().sylv_mlp_forward(len(F), ctypes.c_void_p(Z.data_ptr()), ctypes.c_void_p(th.data_ptr()),
+                                ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    _check(rc, "sylv_mlp_forward")
+    torch.cuda.synchronize()
+    return P.cpu().numpy()
+
+
+POLICIES = {
+    "mlp": dict(low="auto"),
+    "no_selector_fp32": dict(low="fp32"),
+    "ladder_bf16_fp32_fp64": dict(low="bf16"),
+    "rule_kappa": dict(low="auto"),
+}
+# no_selector_fp32: binary32 forms + refinement, binary64 on failure (the
+# method without the selector); ladder: BF16-update forms -> binary32 ->
+# binary64; rule_kappa: a Table 3.1 style threshold rule on kappa_est run
+# through the same AUTO path.
+
+
+def evaluate(indices, lo, hi, seed_base, weights, progress=True):
+    """Solve every instance under each policy (full solves with fallback);
+    report time, escalations and accuracy of the MLP's class."""
+    import workloads
+    eqs = []
+    for i in indices:
+        d = workloads.selector_instance(int(i), lo, hi, seed_base)
+        eqs.append((_dev(d["A"]), None if d["B"] is None else _dev(d["B"]), _dev(d["C"])))
+    out = {}
+    for name, kw in POLICIES.items():
+        if name == "mlp":
+            install(*weights)
+        elif name == "rule_kappa":
+            install(*rule_params())
+        tot, esc, ok, chosen = 0.0, 0, 0, []
+        for eq in eqs:
+            _, info, dt = _timed(lambda: _run(eq, **kw))
+            tot += dt
+            esc += info["fell_back"]
+            ok += int(info["rel_res"] <= TOL)
+            chosen.append(info["chosen"])
+        out[name] = {"seconds": tot, "solves_per_s": len(eqs) / tot, "escalations": esc,
+                     "escalation_rate": esc / len(eqs), "converged": ok, "count": len(eqs)}
+        if name in ("mlp", "rule_kappa"):
+            out[name]["class_counts"] = [int(np.sum(np.array(chosen) == k)) for k in range(3)]
+        if progress:
+            print(f"[selector eval] {name}: {out[name]}", flush=True)
+    uninstall()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("cmd", choices=["train", "evaluate"])
+    ap.add_argument("--count", type=int, default=1500)
+    ap.add_argument("--lo", type=int, default=32)
+    ap.add_argument("--hi", type=int, default=384)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--report", default=None, help="JSON file for the evaluation / training summary")
+    a = ap.parse_args(argv)
+    if a.cmd == "train":
+        idx = np.arange(a.count)
+        F, y, T, meta = make_dataset(idx, a.lo, a.hi, 200000)
+        ntr = int(0.8 * len(y))
+        params, mean, std, hist = train(F[:ntr], y[:ntr], epochs=a.epochs)
+        P = predict(params, mean, std, F[ntr:])
+        acc = float(np.mean(P.argmax(1) == y[ntr:])) if len(y) > ntr else float("nan")
+        np.savez(a.out, params=params, mean=mean, std=std)
+        summ = {"instances": int(len(y)), "train": ntr, "val": int(len(y) - ntr), "val_accuracy": acc,
+                "label_counts": [int(np.sum(y == k)) for k in range(3)], "loss_first": hist[0],
+                "loss_last": hist[-1], "sizes": [a.lo, a.hi], "k_steps": K_STEPS}
+        print(json.dumps(summ), flush=True)
+        if a.report:
+            with open(a.report, "w") as fh:
+                json.dump(summ, fh, indent=1)
+    else:
+        w = load(a.weights)
+        idx = np.arange(a.count)
+        res = evaluate(idx, a.lo, a.hi, 300000, w)
+        print(json.dumps(res), flush=True)
+        if a.report:
+            with open(a.report, "w") as fh:
+                json.dump(res, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,125 @@
+"""Selector plumbing on the GPU: the features of constructed equations
+(sizes, norms, sep_est = delta by construction, fraction of complex pairs),
+SYLV_PREC_AUTO with weights that force each class, the escalation that
+overrules a wrong choice, and the kappa_est rule expressed as weights of the
+same network."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_common import binding, dev, host, relerr
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-14
+
+
+@pytest.fixture
+def sel():
+    binding()
+    from paper_2503_03456_amd import selector
+    yield selector
+    selector.uninstall()
+
+
+def test_features_of_constructed_equation(sel):
+    cfg = workloads.config3(2, m=300, n=200)    # delta = 1e-3, normal A and B
+    A, B, C = dev(cfg["A"]), dev(cfg["B"]), dev(cfg["C"])
+    f = sel.features(A, B, C)
+    torch.cuda.synchronize()
+    assert abs(f[0] - np.log2(300)) < 1e-5 and abs(f[1] - np.log2(200)) < 1e-5
+    assert abs(f[2] - np.log10(np.linalg.norm(cfg["A"]) / np.sqrt(300))) < 1e-4
+    assert abs(f[4] - np.log10(np.linalg.norm(cfg["C"]) / np.sqrt(300 * 200))) < 1e-4
+    # sep(A, -B) = delta exactly (normal coefficients); binary32 forms resolve it
+    assert abs(f[5] - np.log10(cfg["delta"])) < 0.02
+    na, nb = np.linalg.norm(cfg["A"]), np.linalg.norm(cfg["B"])
+    assert abs(f[6] - np.log10((na + nb) / cfg["delta"])) < 0.02
+    # normal coefficients: T is block diagonal up to rounding
+    assert f[7] < 1e-3 and f[8] < 1e-3
+    # fraction of eigenvalues in complex pairs, from the constructed spectra
+    fa = np.mean(np.abs(cfg["eigA"].imag) > 0)
+    fb = np.mean(np.abs(cfg["eigB"].imag) > 0)
+    assert abs(f[9] - fa) < 1e-6 and abs(f[10] - fb) < 1e-6
+    # ||U^T U - I||_F of binary32 forms: about sqrt(n) u_32 .. n u_32
+    assert -8 < f[13] < -3 and -8 < f[14] < -3
+    assert f[15] == 0.0
+    fl = sel.features(A, None, dev(np.eye(300)))   # Lyapunov form: n = m, flag set
+    assert fl[15] == 1.0 and abs(fl[1] - np.log2(300)) < 1e-5
+
+
+def test_auto_requires_installed_weights(sel):
+    sy = binding()
+    A, B, C = workloads.sylv_random(3, 40, 30)
+    sel.uninstall()
+    with pytest.raises(sy.SylvError):
+        sy.solve(dev(A), dev(B), dev(C), low="auto")
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_auto_forced_class(sel, k):
+    sy = binding()
+    A, B, C = workloads.sylv_random(4, 120, 90, scale=0.5 / np.sqrt(120))
+    sel.install(*sel.forced_params(k))
+    X, info = sy.solve(dev(A), dev(B), dev(C), low="auto")
+    torch.cuda.synchronize()
+    assert info["chosen"] == k and info["rel_res"] <= TOL and info["fell_back"] == 0, info
+    assert info["precision_used"] == ("bf16", "fp32", "fp64")[k]
+    Xo, _ = oracle.bs_solve(A, B, C)
+    assert relerr(host(X), Xo) <= 1e-12
+
+
+def test_wrong_choice_is_overruled(sel):
+    """Class 0 forced on an equation with kappa ~ 1e7: bfloat16 transforms
+    cannot converge, the same binary32 forms then cannot either within the
+    stagnation rule, and the binary64 path delivers."""
+    sy = binding()
+    cfg = workloads.config3(5, m=200, n=150)    # delta = 1e-6
+    sel.install(*sel.forced_params(0))
+    X, info = sy.solve(dev(cfg["A"]), dev(cfg["B"]), dev(cfg["C"]), low="auto")
+    torch.cuda.synchronize()
+    assert info["chosen"] == 0 and info["fell_back"] == 1, info
+    assert info["rel_res"] <= TOL
+    Xo, _ = oracle.bs_solve(cfg["A"], cfg["B"], cfg["C"])
+    assert relerr(host(X), Xo) <= 1e-6
+
+
+@pytest.mark.parametrize("j,expect", [(0, 1), (6, 2)])
+def test_kappa_rule_as_weights(sel, j, expect):
+    """log10 kappa_est = log10((||A||_F + ||B||_F)/delta) of config-3
+    equations at m = 160, n = 96: ~2.8 for delta = 1e-1 (class 1), ~8.8 for
+    delta = 1e-7 (class 2)."""
+    sy = binding()
+    cfg = workloads.config3(j, m=160, n=96)
+    sel.install(*sel.rule_params(lo=1.5, hi=6.0))
+    X, info = sy.solve(dev(cfg["A"]), dev(cfg["B"]), dev(cfg["C"]), low="auto")
+    torch.cuda.synchronize()
+    assert info["chosen"] == expect and info["rel_res"] <= TOL, info
+
+
+def test_trained_weights_cut_escalations(sel):
+    """The committed weights (trained on the GPU from solver-generated
+    instances, seeds 200000+) on held-out instances of the same recipe
+    (seeds 300000+): every solve reaches the tolerance, and the selector
+    escalates less often than the method without it (binary32 forms +
+    refinement, binary64 on failure)."""
+    sy = binding()
+    params, mean, std = sel.load()
+    eqs = []
+    for i in range(24):
+        d = workloads.selector_instance(i, 32, 256, 300000)
+        eqs.append((dev(d["A"]), None if d["B"] is None else dev(d["B"]), dev(d["C"])))
+    esc = {}
+    for name, kw in (("auto", dict(low="auto")), ("fp32", dict(low="fp32"))):
+        if name == "auto":
+            sel.install(params, mean, std)
+        n_esc = 0
+        for A, B, C in eqs:
+            X, info = (sy.lyap(A, C, **kw) if B is None else sy.solve(A, B, C, **kw))
+            torch.cuda.synchronize()
+            assert info["rel_res"] <= TOL, (name, info)
+            n_esc += info["fell_back"]
+        esc[name] = n_esc
+    assert esc["fp32"] >= 3
+    assert esc["auto"] < esc["fp32"], esc

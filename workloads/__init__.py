@@ -184,3 +184,34 @@ def manufactured(seed, m, n):
     B = rs.standard_normal((n, n)) * 0.125 + 2.0 * np.eye(n)
     X = rs.standard_normal((m, n))
     return _f(A), _f(B), _f(X)
+
+
+def selector_sizes(i: int, lo: int = 32, hi: int = 1024, seed_base: int = 200000):
+    """Orders of selector instance i: m, n independently log-uniform integers
+    in [lo, hi]; sep target delta log-uniform in [1e-8, 1e-1]; 10% of the
+    instances are Lyapunov (then n = m)."""
+    rs = np.random.RandomState(seed_base + i)
+    m = int(round(np.exp(rs.uniform(np.log(lo), np.log(hi)))))
+    n = int(round(np.exp(rs.uniform(np.log(lo), np.log(hi)))))
+    delta = float(10.0 ** rs.uniform(-8.0, -1.0))
+    lyap = bool(rs.uniform() < 0.10)
+    return m, (m if lyap else n), delta, lyap
+
+
+def selector_instance(i: int, lo: int = 32, hi: int = 1024, seed_base: int = 200000):
+    """Instance i of the selector recipe (config-3 construction at the drawn
+    sizes and sep).  Sylvester: A = Q_A D_A Q_A^T + (delta - 1) I and B with
+    planted eigenvalue 0.5, so min |l + m| = delta.  Lyapunov: A with Re(eig)
+    in [0.5, 5] and a planted eigenvalue delta/2 (min |l_i + l_j| = delta).
+    Returns dict(A, B (None for Lyapunov), C, delta, lyap)."""
+    m, n, delta, lyap = selector_sizes(i, lo, hi, seed_base)
+    s = seed_base + i
+    if lyap:
+        A, ea, _, _ = normal_coeff(s + 1, m, 0.5, 5.0, planted=0.5, shift=delta / 2 - 0.5)
+        C = np.random.RandomState(s + 3).standard_normal((m, m))
+        C = C + C.T
+        return dict(A=A, B=None, C=_f(C), delta=delta, lyap=True, eigA=ea)
+    A, ea, _, _ = normal_coeff(s + 1, m, 0.5, 5.0, planted=0.5, shift=delta - 1.0)
+    B, eb, _, _ = normal_coeff(s + 2, n, 0.5, 5.0, planted=0.5)
+    C = np.random.RandomState(s + 3).standard_normal((m, n))
+    return dict(A=A, B=B, C=_f(C), delta=delta, lyap=False, eigA=ea, eigB=eb)
