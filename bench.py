@@ -177,6 +177,42 @@ def main_batched(args, np, torch, sy):
     print(json.dumps(out), flush=True)
 
 
+def sweep_c3(args, np, torch, sy):
+    """Config 3 (m = 4096, n = 1024, sep = delta = 1e-1 .. 1e-6): one solve per
+    delta and path (binary32 forms, BF16-update forms, plain binary64), with
+    iterations, escalation, relative residual and the forward error against
+    the exact block-diagonal solution of the normal construction."""
+    import workloads
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from exact_route import exact_solution
+
+    def dev(a):
+        return torch.from_numpy(np.asfortranarray(a)).t().contiguous().t().cuda()
+
+    rows = []
+    for j in range(args.c3_first, 6):
+        cfg = workloads.config3(j)
+        A, B, C = dev(cfg["A"]), dev(cfg["B"]), dev(cfg["C"])
+        Xe = exact_solution(cfg)
+        row = {"delta": cfg["delta"]}
+        for low in ("fp32", "bf16", "fp64"):
+            sy.solve(A, B, C, low=low)   # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, info = sy.solve(A, B, C, low=low)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            fe = float(np.linalg.norm(X.cpu().numpy() - Xe) / np.linalg.norm(Xe))
+            row[low] = {"seconds": dt, "iterations": info["iterations"], "fell_back": info["fell_back"],
+                        "precision_used": info["precision_used"], "rel_res": info["rel_res"],
+                        "forward_error": fe, "sep_est": info["sep_est"]}
+        rows.append(row)
+        print(f"[c3] delta={cfg['delta']:.0e} " + " ".join(
+            f"{k}:{row[k]['seconds']:.2f}s/it{row[k]['iterations']}/fb{row[k]['fell_back']}"
+            for k in ("fp32", "bf16", "fp64")), file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "config 3 sweep, sylvester m=4096 n=1024", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,7 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=768)
     ap.add_argument("--count", type=int, default=4096, help="equations of the batched workload (c4)")
-    ap.add_argument("--cpu-sample-eqs", type=int, default=256)
+    ap.add_argument("--cpu-sample-eqs", type=int, default=1024)
+    ap.add_argument("--c3-first", type=int, default=0, help="first delta index of the c3sweep workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this solver has no "
@@ -203,6 +240,8 @@ def main():
 
     if args.workload == "c4":
         return main_batched(args, np, torch, sy)
+    if args.workload == "c3sweep":
+        return sweep_c3(args, np, torch, sy)
     cfg, desc = load_workload(args.workload)
     m, n = cfg["C"].shape
 
@@ -306,7 +345,7 @@ def roofline_entry(kname, launches, total_ms, work, steps, step_s):
     so their roof is the fp32 vector peak of the chip."""
     avg_ms = total_ms / launches
     ach = work / (total_ms * 1e-3) / 1e12 if total_ms > 0 else 0.0
-    bound = "alu" if kname in ("k_chase", "k_aed") else "mfma"
+    bound = "alu" if kname in ("k_chase", "k_aed", "k_bschur", "k_bhess") else "mfma"
     peak = PEAKS["fp32_TFLOPs"]
     return {"kernel": kname, "bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
             "frac": ach / peak, "traffic": None, "avg_launch_ms": avg_ms,
