@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -614,6 +615,158 @@ __global__ __launch_bounds__(BNT) void k_bnorm(BatchEq *eqs, const int *order, d
 
 namespace sylv {
 
+// ------------------------------------------------------- launch sequences
+__global__ void k_bzero(int *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+struct BatchPlan {
+    BatchEq *deq;
+    int *dord, *dcnt;
+    int batch, nmax, bf16, max_iter;
+    double tol;
+    int h1, h2;       // Hessenberg buckets [0,h1) [h1,h2) [h2,batch)
+    int sb[4];        // band-QR buckets [sb[i], sb[i+1])
+    size_t smem[3];   // their dynamic LDS
+};
+
+// stages 1-4 and the first iterate
+static void enqueue_front(hipStream_t s, const BatchPlan &P) {
+    const int batch = P.batch;
+    hipLaunchKernelGGL(k_bprep, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
+    {
+        ProfScope ps(KID_BHESS, s);
+        if (P.h1 > 0) hipLaunchKernelGGL((k_bhess_reg<32, 8>), dim3(P.h1), dim3(1024), 0, s, P.deq, P.dord, 0);
+        if (P.h2 > P.h1)
+            hipLaunchKernelGGL((k_bhess_reg<16, 8>), dim3(P.h2 - P.h1), dim3(256), 0, s, P.deq, P.dord, P.h1);
+        if (batch > P.h2)
+            hipLaunchKernelGGL((k_bhess_reg<16, 4>), dim3(batch - P.h2), dim3(256), 0, s, P.deq, P.dord, P.h2);
+    }
+    {
+        ProfScope ps(KID_BSCHUR, s);
+        for (int bi = 0; bi < 3; ++bi)
+            if (P.sb[bi + 1] > P.sb[bi])
+                hipLaunchKernelGGL(k_bschur, dim3(P.sb[bi + 1] - P.sb[bi]), dim3(BSNT), P.smem[bi], s, P.deq,
+                                   P.dord + P.sb[bi]);
+    }
+    hipLaunchKernelGGL(k_bpost, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
+    // first iterate: W = U^T C V, Y' solves T Y' + Y' TB = W, X = U Y' V^T
+    gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 0, 0.f,
+                                              P.bf16);
+    gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f,
+                                             P.bf16);
+    trsyl_batched(s, P.deq, P.dord, batch, P.nmax);
+    gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f,
+                                             P.bf16);
+    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 0, 0.f,
+                                              P.bf16);
+}
+
+// binary64 residual R = C - A X - X A^T, norms and the per-equation decision;
+// *dcnt = number of equations that take another correction
+static void enqueue_pass(hipStream_t s, const BatchPlan &P, bool) {
+    const int batch = P.batch;
+    hipLaunchKernelGGL(k_bcopy_c, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
+    gemm_batched<double, double, double, double>(s, P.deq, P.dord, batch, P.nmax, BF_A, 0, BF_X, 0, BF_R, -1.0, 0,
+                                                 1.0);
+    gemm_batched<double, double, double, double>(s, P.deq, P.dord, batch, P.nmax, BF_X, 0, BF_A, 1, BF_R, -1.0, 0,
+                                                 1.0);
+    hipLaunchKernelGGL(k_bzero, dim3(1), dim3(64), 0, s, P.dcnt);
+    hipLaunchKernelGGL(k_bnorm, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord, P.tol, P.max_iter, P.dcnt);
+}
+
+// correction of the active equations: W = 2^-e U^T R V, tri-solve,
+// X += 2^e U Y' V^T
+static void enqueue_correction(hipStream_t s, const BatchPlan &P) {
+    const int batch = P.batch;
+    gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_R, 0, BF_Y, 1.f, 1, 0.f,
+                                              P.bf16);
+    gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f,
+                                             P.bf16);
+    trsyl_batched(s, P.deq, P.dord, batch, P.nmax);
+    gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f,
+                                             P.bf16);
+    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 1.f,
+                                              P.bf16);
+}
+
+// ------------------------------------------------------------- hipGraph
+// The launch sequence of a batch shape (stages, first iterate, the first
+// refinement passes) is captured once on an internal stream and replayed;
+// equations are gated on the device (inactive ones return at once), so the
+// graph needs no host decisions.  A graph is keyed by the workspace, the
+// sorted orders and the options it was captured with.  SYLV_BATCH_GRAPH=0
+// in the environment selects eager launches.
+struct BatchGraph {
+    hipStream_t gs = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BatchEq *deq = nullptr;
+    int passes = 0, bf16 = 0, max_iter = 0;
+    double tol = 0.0;
+    std::vector<int> sizes;
+};
+static BatchGraph g_bgraph[64];
+
+static bool batch_graph_enabled() {
+    const char *v = std::getenv("SYLV_BATCH_GRAPH");
+    return !(v && v[0] == '0');
+}
+
+static int batch_graph_run(hipStream_t s, const BatchPlan &P, const std::vector<int> &order, const int *nn,
+                           int passes, int *dcnt, int *hcnt) {
+    int dev = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess || dev < 0 || dev >= 64) return SYLV_ERR_NOGPU;
+    BatchGraph &g = g_bgraph[dev];
+    if (!g.gs) {
+        if ((e = hipStreamCreateWithFlags(&g.gs, hipStreamNonBlocking)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        if ((e = hipEventCreateWithFlags(&g.e0, hipEventDisableTiming)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        if ((e = hipEventCreateWithFlags(&g.e1, hipEventDisableTiming)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    }
+    std::vector<int> sizes(P.batch);
+    for (int i = 0; i < P.batch; ++i) sizes[i] = nn[order[i]];
+    const bool hit = g.exec && g.deq == P.deq && g.passes == passes && g.bf16 == P.bf16 &&
+                     g.max_iter == P.max_iter && g.tol == P.tol && g.sizes == sizes;
+    if (!hit) {
+        if (g.exec) {
+            hipGraphExecDestroy(g.exec);
+            hipGraphDestroy(g.graph);
+            g.exec = nullptr;
+            g.graph = nullptr;
+        }
+        if ((e = hipStreamBeginCapture(g.gs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return SYLV_ERR_HIP - (int)e;
+        enqueue_front(g.gs, P);
+        for (int k = 0; k < passes; ++k) {
+            enqueue_pass(g.gs, P, true);
+            enqueue_correction(g.gs, P);
+        }
+        if ((e = hipStreamEndCapture(g.gs, &g.graph)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) {
+            hipGraphDestroy(g.graph);
+            g.graph = nullptr;
+            return SYLV_ERR_HIP - (int)e;
+        }
+        g.deq = P.deq;
+        g.passes = passes;
+        g.bf16 = P.bf16;
+        g.max_iter = P.max_iter;
+        g.tol = P.tol;
+        g.sizes = std::move(sizes);
+    }
+    if ((e = hipEventRecord(g.e0, s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    if ((e = hipStreamWaitEvent(g.gs, g.e0, 0)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    if ((e = hipGraphLaunch(g.exec, g.gs)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    if ((e = hipEventRecord(g.e1, g.gs)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    if ((e = hipStreamWaitEvent(s, g.e1, 0)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    if ((e = hipMemcpyAsync(hcnt, dcnt, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return SYLV_ERR_HIP - (int)e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    return 0;
+}
+
 // Host driver.  All equations must be Lyapunov with order <= 256.
 int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A, const int *lda,
                  const double *const *C, const int *ldc, double *const *X, const int *ldx,
@@ -667,73 +820,59 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
         return SYLV_ERR_HIP - (int)e;
     if ((e = hipMemcpyAsync(dord, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s)) != hipSuccess)
         return SYLV_ERR_HIP - (int)e;
-    // stages 1-3
-    hipLaunchKernelGGL(k_bprep, dim3(batch), dim3(BNT), 0, s, deq, dord);
-    {
-        // size buckets (order is longest first): n > 128, 64 < n <= 128, n <= 64
-        int e1 = 0, e2 = 0;
-        while (e1 < batch && nn[order[e1]] > 128) ++e1;
-        e2 = e1;
-        while (e2 < batch && nn[order[e2]] > 64) ++e2;
-        double w = 0.0;
-        for (int i = 0; i < batch; ++i) w += (14.0 / 3.0) * double(nn[i]) * nn[i] * nn[i];
-        prof_add_work(KID_BHESS, w);
-        ProfScope ps(KID_BHESS, s);
-        if (e1 > 0) hipLaunchKernelGGL((k_bhess_reg<32, 8>), dim3(e1), dim3(1024), 0, s, deq, dord, 0);
-        if (e2 > e1) hipLaunchKernelGGL((k_bhess_reg<16, 8>), dim3(e2 - e1), dim3(256), 0, s, deq, dord, e1);
-        if (batch > e2) hipLaunchKernelGGL((k_bhess_reg<16, 4>), dim3(batch - e2), dim3(256), 0, s, deq, dord, e2);
+    static bool attr = false;
+    if (!attr) {
+        if ((e = hipFuncSetAttribute((const void *)k_bschur, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(sizeof(float) * band_size(256)))) != hipSuccess)
+            return SYLV_ERR_HIP - (int)e;
+        attr = true;
     }
-    {
-        static bool attr = false;
-        if (!attr) {
-            if ((e = hipFuncSetAttribute((const void *)k_bschur, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)(sizeof(float) * band_size(256)))) != hipSuccess)
-                return SYLV_ERR_HIP - (int)e;
-            attr = true;
-        }
-        // LDS buckets: the band of order 180 fits two workgroups per CU, of
-        // order 128 three
-        const int caps[3] = {256, 180, 128};
-        int b0 = 0;
-        ProfScope ps(KID_BSCHUR, s);
-        for (int bi = 0; bi < 3 && b0 < batch; ++bi) {
-            const int lo = (bi + 1 < 3) ? caps[bi + 1] : 0;
-            int b1 = b0;
-            while (b1 < batch && nn[order[b1]] > lo) ++b1;
-            if (b1 > b0) {
-                const size_t sm = sizeof(float) * (size_t)band_size(std::min(caps[bi], nn[order[b0]]));
-                hipLaunchKernelGGL(k_bschur, dim3(b1 - b0), dim3(BSNT), sm, s, deq, dord + b0);
-            }
-            b0 = b1;
-        }
+    BatchPlan P;
+    P.deq = deq; P.dord = dord; P.dcnt = dcnt;
+    P.batch = batch; P.nmax = nmax;
+    P.bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
+    P.tol = o.tol; P.max_iter = o.max_iter;
+    // Hessenberg size buckets (order is longest first): n > 128, 64 < n <= 128, n <= 64
+    P.h1 = 0;
+    while (P.h1 < batch && nn[order[P.h1]] > 128) ++P.h1;
+    P.h2 = P.h1;
+    while (P.h2 < batch && nn[order[P.h2]] > 64) ++P.h2;
+    // band-QR LDS buckets: orders > 180, 128 < n <= 180 (two workgroups per CU), <= 128 (three)
+    const int caps[3] = {256, 180, 128};
+    int b0 = 0;
+    for (int bi = 0; bi < 3; ++bi) {
+        const int lo = (bi + 1 < 3) ? caps[bi + 1] : 0;
+        int b1 = b0;
+        while (b1 < batch && nn[order[b1]] > lo) ++b1;
+        P.sb[bi] = b0;
+        P.smem[bi] = (b1 > b0) ? sizeof(float) * (size_t)band_size(std::min(caps[bi], nn[order[b0]])) : 0;
+        b0 = b1;
     }
-    hipLaunchKernelGGL(k_bpost, dim3(batch), dim3(BNT), 0, s, deq, dord);
-    auto trsolve = [&]() { trsyl_batched(s, deq, dord, batch, nmax); };
-    const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
-    // first iterate: W = U^T C V, Y' solves T Y' + Y' TB = W, X = U Y' V^T
-    gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 0, 0.f, bf16);
-    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f, bf16);
-    trsolve();
-    gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f, bf16);
-    gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 0, 0.f, bf16);
+    P.sb[3] = batch;
+    double w = 0.0;
+    for (int i = 0; i < batch; ++i) w += (14.0 / 3.0) * double(nn[i]) * nn[i] * nn[i];
+    prof_add_work(KID_BHESS, w);
+
     int *hcnt = reinterpret_cast<int *>(hbuf);
-    for (int pass = 0; pass <= o.max_iter; ++pass) {
-        // R = C - A X - X A^T (binary64)
-        hipLaunchKernelGGL(k_bcopy_c, dim3(batch), dim3(BNT), 0, s, deq, dord);
-        gemm_batched<double, double, double, double>(s, deq, dord, batch, nmax, BF_A, 0, BF_X, 0, BF_R, -1.0, 0, 1.0);
-        gemm_batched<double, double, double, double>(s, deq, dord, batch, nmax, BF_X, 0, BF_A, 1, BF_R, -1.0, 0, 1.0);
-        if ((e = hipMemsetAsync(dcnt, 0, sizeof(int), s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
-        hipLaunchKernelGGL(k_bnorm, dim3(batch), dim3(BNT), 0, s, deq, dord, o.tol, o.max_iter, dcnt);
+    int rc = 0, pass0 = 0;
+    const int gpasses = std::min(o.max_iter + 1, 3);
+    if (batch_graph_enabled() && !prof_any_armed()) {
+        // the stages and the first refinement passes as one graph (captured
+        // once per batch shape and workspace, replayed afterwards)
+        rc = batch_graph_run(s, P, order, nn, gpasses, dcnt, hcnt);
+        if (rc) return rc;
+        pass0 = gpasses;
+        if (*hcnt == 0) pass0 = o.max_iter + 1;  // nothing left to refine
+    } else {
+        enqueue_front(s, P);
+    }
+    for (int pass = pass0; pass <= o.max_iter; ++pass) {
+        enqueue_pass(s, P, false);
         if ((e = hipMemcpyAsync(hcnt, dcnt, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
             return SYLV_ERR_HIP - (int)e;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
         if (*hcnt == 0) break;
-        // correction: W = 2^-e U^T R U ; tri-solve ; X += 2^e U Y U^T
-        gemm_batched<float, double, float, float>(s, deq, dord, batch, nmax, BF_U, 1, BF_R, 0, BF_Y, 1.f, 1, 0.f, bf16);
-        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f, bf16);
-        trsolve();
-        gemm_batched<float, float, float, float>(s, deq, dord, batch, nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f, bf16);
-        gemm_batched<float, float, double, float>(s, deq, dord, batch, nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 1.f, bf16);
+        enqueue_correction(s, P);
     }
     if ((e = hipMemcpyAsync(hq.data(), deq, sizeof(BatchEq) * batch, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return SYLV_ERR_HIP - (int)e;

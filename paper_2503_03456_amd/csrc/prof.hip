@@ -16,6 +16,7 @@ static thread_local hipEvent_t g_open = nullptr;
 static double g_work = 0.0;
 
 bool prof_armed(int id) { return g_target.load(std::memory_order_relaxed) == id; }
+bool prof_any_armed() { return g_target.load(std::memory_order_relaxed) != KID_NONE; }
 
 static hipEvent_t take_event() {
     if (!g_pool.empty()) {

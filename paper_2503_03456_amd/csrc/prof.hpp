@@ -14,6 +14,7 @@ enum KernelId {
 };
 
 bool prof_armed(int id);
+bool prof_any_armed();
 void prof_begin(int id, hipStream_t s);
 void prof_end(int id, hipStream_t s);
 // algorithmic work (flops or bytes) of the armed kernel family, summed over launches

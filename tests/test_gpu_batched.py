@@ -166,3 +166,34 @@ def test_batch_stagnating_window_converges():
     torch.cuda.synchronize()
     assert infos[0]["status"] == 0, infos[0]
     check_item(A, C, eig, host(Xs[0]), infos[0])
+
+
+def test_batch_graph_replays_match_eager(monkeypatch):
+    """The batched stages run as a captured hipGraph by default.  Eager
+    launches (SYLV_BATCH_GRAPH=0) give the reference; the graph is captured
+    on the first call and replayed on the later ones (with a different batch
+    shape captured in between and unrelated eager work and synchronisations
+    between the replays); every result must equal the eager one bit for bit."""
+    sy = binding()
+    sizes = [200, 33, 150, 64, 65, 7, 128, 129]
+    its = items(range(1200, 1200 + len(sizes)), sizes)
+    eqs = [(dev(A), dev(C)) for A, C, _ in its]
+    other = [(dev(A), dev(C)) for A, C, _ in items(range(1300, 1303), [90, 40, 12])]
+    monkeypatch.setenv("SYLV_BATCH_GRAPH", "0")
+    Xe, ie = sy.solve_batched(eqs)
+    torch.cuda.synchronize()
+    Xe = [x.clone() for x in Xe]
+    monkeypatch.setenv("SYLV_BATCH_GRAPH", "1")
+    for rep in range(4):
+        if rep == 2:
+            sy.solve_batched(other)          # another shape: re-capture
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        Xg, ig = sy.solve_batched(eqs)
+        torch.cuda.synchronize()
+        for a, b, fa, fb in zip(Xe, Xg, ie, ig):
+            assert torch.equal(a, b), rep
+            assert fa["iterations"] == fb["iterations"] and fa["status"] == fb["status"]
+        del junk
+    for (A, C, eig), X, info in zip(its, Xg, ig):
+        check_item(A, C, eig, host(X), info)
