@@ -220,7 +220,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed plain binary64 solves")
-    ap.add_argument("--roofline-kernel", default="k_aed")
+    ap.add_argument("--roofline-kernel", default="k_chase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=768)
     ap.add_argument("--count", type=int, default=4096, help="equations of the batched workload (c4)")

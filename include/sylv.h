@@ -146,6 +146,21 @@ int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
 size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, const int *n,
                                    const sylv_opts *opts);
 
+/* Tunables of the QR phase of the Schur factorisation for prec FP32 or
+ * FP64 (process-wide; take effect at the next factorisation; the library's
+ * defaults are the values its autotuner measured best on MI355X):
+ *   nsmall  largest active block finished by one full-window LDS kernel,
+ *   nw      aggressive-early-deflation window,
+ *   nb      bulges per multishift sweep,
+ *   adv     rows a bulge chain advances per LDS window phase,
+ *   nibble  percentage of the window AED must deflate to skip the sweep.
+ * A value <= 0 (nibble < 0) keeps the current one.  Returns 0, -1 for a bad
+ * prec, -2 when the combination exceeds the LDS/workspace bounds
+ * (FP32: nsmall, nw <= 140, adv + 3 nb + 1 <= 141; FP64: 98 and 99). */
+int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble);
+/* Current tunables (nsmall, nw, nb, adv, nibble) into vals[5] (host). */
+int sylv_schur_tune_get(int prec, int *vals);
+
 /* Text for a return value or a status code. */
 const char *sylv_status_string(int code);
 

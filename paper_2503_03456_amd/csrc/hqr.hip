@@ -155,40 +155,42 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
             }
             T v1, v2, tau, beta;
             reflector3(len, x, y, z, v1, v2, tau, beta);
-            // Work split by wave so that no wave runs two code paths:
-            //   wave 0: left application on columns [k+len, n) (and the
+            // Work split by wave so that no wave runs two code paths
+            // (WL = (NW-1)/3 waves per role):
+            //   waves [0, WL): left application on columns [k+len, n) (and the
             //           deferred column of the previous step)
-            //   wave 1: right application on rows [0, k) u {k+3}
-            //   waves 2..NW-2: the accumulated factor Z (rows 0..nz-1)
+            //   waves [WL, 2WL): right application on rows [0, k) u {k+3}
+            //   waves [2WL, NW-1): the accumulated factor Z (rows 0..nz-1)
             //   wave NW-1, lane 0: the overlap block rows/cols k..k+len-1
             constexpr int NWV = NT / 64;
+            constexpr int WL = (NWV - 1) / 3, TL = 64 * WL;
             static_assert(NWV >= 4, "francis_lds needs at least 4 waves");
             const int wv = tid >> 6, lane = tid & 63;
             const int k2 = (len == 3) ? k + 2 : k + 1;  // clamped third index
-            if (wv == 0) {
-                if (lane == 0 && pcol >= 0) {
+            if (wv < WL) {
+                if (tid == 0 && pcol >= 0) {
                     CM(H, pk2, pcol, ldh) = T(0);
                     CM(H, pcol + 2, pcol, ldh) = T(0);
                     CM(H, pcol + 1, pcol, ldh) = pbeta;
                 }
                 const int nL = n - (k + len);
-                for (int q = lane; q < nL; q += 64) {
+                for (int q = tid; q < nL; q += TL) {
                     const int j = k + len + q;
                     T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh), a2 = CM(H, k2, j, ldh);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
                     CM(H, k2, j, ldh) = a2; CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
                 }
-            } else if (wv == 1) {
+            } else if (wv < 2 * WL) {
                 const int extra = (len == 3 && k + 3 <= ihi) ? 1 : 0;
                 const int nR = k + extra;
-                for (int q = lane; q < nR; q += 64) {
+                for (int q = tid - TL; q < nR; q += TL) {
                     const int i = (q < k) ? q : k + 3;
                     T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh), a2 = CM(H, i, k2, ldh);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
                     CM(H, i, k2, ldh) = a2; CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
                 }
             } else if (wv < NWV - 1) {
-                for (int i = tid - 128; i < nz; i += NT - 192) {
+                for (int i = tid - 2 * TL; i < nz; i += NT - 64 - 2 * TL) {
                     T a0 = CM(Z, i, k, ldz), a1 = CM(Z, i, k + 1, ldz), a2 = CM(Z, i, k2, ldz);
                     refl_apply(len, v1, v2, tau, a0, a1, a2);
                     CM(Z, i, k2, ldz) = a2; CM(Z, i, k, ldz) = a0; CM(Z, i, k + 1, ldz) = a1;
@@ -426,6 +428,10 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
     if (tid == 0) { out[0] = 0; out[1] = nw - ns; out[2] = ns; }
 }
 
+// threads of the AED kernel: 7 waves, so that a window of up to 128 rows
+// gives every left/right/Z reflector application its own thread
+constexpr int AED_NT = 448;
+
 template <typename T>
 size_t aed_smem(int nw) {
     return sizeof(T) * ((size_t)2 * (nw | 1) * nw + nw) + 8 * sizeof(int);
@@ -436,7 +442,7 @@ int aed_launch(hipStream_t s, int nw, T *H, int ldh, int kwtop, int spike_on, T 
                T *wr, T *wi) {
     size_t sm = aed_smem<T>(nw);
     if (sm > 160 * 1024) return -1;
-    auto kfn = k_aed<T, 320>;
+    auto kfn = k_aed<T, AED_NT>;
     static std::mutex mu;
     static size_t attr_set = 0;
     {
@@ -452,7 +458,7 @@ int aed_launch(hipStream_t s, int nw, T *H, int ldh, int kwtop, int spike_on, T 
     }
     {
         ProfScope ps(KID_AED, s);
-        hipLaunchKernelGGL(kfn, dim3(1), dim3(320), sm, s, nw, H, ldh, kwtop, spike_on, Zw, out, wr, wi);
+        hipLaunchKernelGGL(kfn, dim3(1), dim3(AED_NT), sm, s, nw, H, ldh, kwtop, spike_on, Zw, out, wr, wi);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

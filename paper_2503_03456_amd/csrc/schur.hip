@@ -22,18 +22,57 @@
 #include <vector>
 #include <cmath>
 #include <cstdio>
+#include <atomic>
 #include <cstdlib>
 #include <algorithm>
 
 namespace sylv {
 
+// current tunables (defaults measured on MI355X by the autotuner)
+static std::atomic<long long> g_tune_f{0}, g_tune_d{0};
+static SchurTune tune_default(bool fp32) {
+    // selected by paper_2503_03456_amd.autotune (n = 2048, normal recipe,
+    // seed 7): Schur time 0.560 -> 0.398 s (binary32), 0.842 -> 0.629 s (binary64)
+    return fp32 ? SchurTune{128, 48, 20, 64, 40} : SchurTune{98, 48, 16, 48, 50};
+}
+static long long tune_pack(const SchurTune &t) {
+    return ((long long)t.nsmall << 48) | ((long long)t.nw << 36) | ((long long)t.nb << 24) |
+           ((long long)t.adv << 12) | (long long)t.nibble;
+}
+static SchurTune tune_unpack(long long v) {
+    return SchurTune{(int)((v >> 48) & 0xfff), (int)((v >> 36) & 0xfff), (int)((v >> 24) & 0xfff),
+                     (int)((v >> 12) & 0xfff), (int)(v & 0xfff)};
+}
+template <typename T>
+SchurTune schur_tune() {
+    const long long v = (sizeof(T) == 4 ? g_tune_f : g_tune_d).load();
+    return v ? tune_unpack(v) : tune_default(sizeof(T) == 4);
+}
+template <typename T>
+int schur_tune_set(const SchurTune &t) {
+    typedef SchurCaps<T> K;
+    if (t.nsmall < 16 || t.nsmall > K::NSMALL) return -1;
+    if (t.nw < 8 || t.nw > K::NSMALL) return -1;
+    if (t.nb < 1 || t.nb > K::NBMAX) return -1;
+    if (t.adv < 4 || t.adv + 3 * t.nb + 1 > K::WMAX) return -1;
+    if (t.nibble < 0 || t.nibble > 100) return -1;
+    if (aed_smem<T>(t.nw) > 160 * 1024) return -1;
+    if (chase_smem<T>(t.adv + 3 * t.nb + 1, t.nb) > 160 * 1024) return -1;
+    (sizeof(T) == 4 ? g_tune_f : g_tune_d).store(tune_pack(t));
+    return 0;
+}
+template SchurTune schur_tune<float>();
+template SchurTune schur_tune<double>();
+template int schur_tune_set<float>(const SchurTune &);
+template int schur_tune_set<double>(const SchurTune &);
+
 template <typename T>
 size_t schur_work_bytes(int n) {
-    typedef SchurParams<T> P;
-    const int wmax = P::ADV + 3 * P::NB + 1;
-    const int wide = std::max(wmax, P::NSMALL);
-    size_t e = hessenberg_work_elems<T>(n, P::HNB, P::HS) + (size_t)P::NSMALL * P::NSMALL +
-               (size_t)wmax * wmax + (size_t)wide * n + 2 * (size_t)P::NSMALL + 2 * P::NB + 64;
+    typedef SchurCaps<T> K;
+    const int wmax = K::WMAX;
+    const int wide = std::max(wmax, K::NSMALL);
+    size_t e = hessenberg_work_elems<T>(n, K::HNB, K::HS) + (size_t)K::NSMALL * K::NSMALL +
+               (size_t)wmax * wmax + (size_t)wide * n + 2 * (size_t)K::NSMALL + 2 * K::NBMAX + 64;
     return e * sizeof(T) + 1024 + 64 * sizeof(int);
 }
 template size_t schur_work_bytes<float>(int);
@@ -57,18 +96,18 @@ struct Ctx {
 
 template <typename T>
 void carve(Ctx<T> &c, char *ws) {
-    typedef SchurParams<T> P;
+    typedef SchurCaps<T> K;
     const int n = c.n;
-    const int wmax = P::ADV + 3 * P::NB + 1;
-    const int wide = std::max(wmax, P::NSMALL);
+    const int wmax = K::WMAX;
+    const int wide = std::max(wmax, K::NSMALL);
     T *p = reinterpret_cast<T *>(ws);
-    c.hw = p; p += hessenberg_work_elems<T>(n, P::HNB, P::HS);
-    c.Zw = p; p += (size_t)P::NSMALL * P::NSMALL;
+    c.hw = p; p += hessenberg_work_elems<T>(n, K::HNB, K::HS);
+    c.Zw = p; p += (size_t)K::NSMALL * K::NSMALL;
     c.Uw = p; p += (size_t)wmax * wmax;
     c.tmp = p; p += (size_t)wide * n;
-    c.wr = p; p += P::NSMALL;
-    c.wi = p; p += P::NSMALL;
-    c.trd = p; p += 2 * P::NB + 64;
+    c.wr = p; p += K::NSMALL;
+    c.wi = p; p += K::NSMALL;
+    c.trd = p; p += 2 * K::NBMAX + 64;
     size_t off = reinterpret_cast<char *>(p) - ws;
     off = (off + 255) & ~(size_t)255;
     c.dint = reinterpret_cast<int *>(ws + off);
@@ -137,14 +176,15 @@ void pair_shifts(const std::vector<double> &wr, const std::vector<double> &wi, i
 template <typename T>
 int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char *hbuf,
               int *qr_status, int bf16) {
-    typedef SchurParams<T> P;
+    typedef SchurCaps<T> K;
+    const SchurTune P = schur_tune<T>();
     *qr_status = 0;
     if (n <= 0) return 0;
     Ctx<T> c{s, n, H, ldh, U, ldu};
     c.hbuf = hbuf;
     c.bf16 = (sizeof(T) == sizeof(float)) ? bf16 : 0;
     carve(c, ws);
-    hessenberg<T>(s, n, H, ldh, U, ldu, c.hw, P::HNB, P::HS, c.bf16);
+    hessenberg<T>(s, n, H, ldh, U, ldu, c.hw, K::HNB, K::HS, c.bf16);
     int *hi = reinterpret_cast<int *>(c.hbuf);
     hipError_t err;
     int kbot = n - 1;
@@ -164,7 +204,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         if (N == 1) { kbot -= 1; ndfl = 1; continue; }
         if (N == 2) { std2x2<T>(s, n, H, ldh, U, ldu, ktop); kbot -= 2; ndfl = 1; continue; }
         if (++iters > itmax) { *qr_status = 1; break; }
-        if (N <= P::NSMALL) {
+        if (N <= P.nsmall) {
             if (aed_launch<T>(s, N, H, ldh, ktop, 0, c.Zw, c.dint, c.wr, c.wi)) return -1;
             if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
             ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5];
@@ -176,7 +216,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
             continue;
         }
         // aggressive early deflation on the trailing window
-        const int nw = std::min(P::NW, N - 1);
+        const int nw = std::min(P.nw, N - 1);
         const int kwtop = kbot - nw + 1;
         if (aed_launch<T>(s, nw, H, ldh, kwtop, 1, c.Zw, c.dint, c.wr, c.wi)) return -1;
         if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
@@ -197,10 +237,10 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         kbot -= ndef;
         ndfl = (ndef > 0) ? 1 : ndfl + 1;
         // skip the sweep if AED deflated a good share of the window
-        if (ndef > 0 && 100 * ndef > 14 * nw) continue;
-        if (kbot - ktop + 1 <= P::NSMALL) continue;
+        if (ndef > 0 && 100 * ndef > P.nibble * nw) continue;
+        if (kbot - ktop + 1 <= P.nsmall) continue;
         const int N2 = kbot - ktop + 1;
-        const int maxb = std::min(P::NB, (N2 - 2) / 6 > 1 ? (N2 - 2) / 6 : 1);
+        const int maxb = std::min(P.nb, (N2 - 2) / 6 > 1 ? (N2 - 2) / 6 : 1);
         if (ndfl % 6 == 0 || wr.size() < 2) {
             // exceptional shifts from the trailing subdiagonal magnitudes
             const int cnt = 2 * maxb + 2;
@@ -245,8 +285,8 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         // multishift sweep over [ktop, kbot]
         const int ttot = (N2 - 2) + 3 * (nb - 1) + 1;
         ++st_sweeps;
-        for (int t0 = 0; t0 < ttot; t0 += P::ADV) {
-            const int t1 = std::min(t0 + P::ADV, ttot);
+        for (int t0 = 0; t0 < ttot; t0 += P.adv) {
+            const int t1 = std::min(t0 + P.adv, ttot);
             const int pmin = std::max(0, t0 - 3 * (nb - 1));
             const int pmax = std::min(N2 - 2, t1 - 1);
             if (pmax < pmin) continue;

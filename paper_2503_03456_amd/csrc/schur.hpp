@@ -5,19 +5,28 @@
 
 namespace sylv {
 
-// NSMALL: largest active block finished by one full-window LDS kernel
-//         (bounded by 160 KiB of LDS: two NSMALL^2 matrices);
-// NW:     aggressive-early-deflation window;
-// NB:     bulges per multishift sweep (2*NB shifts); ADV: rows a bulge chain
-//         advances per LDS window phase (window <= ADV + 3*NB + 1);
-// HNB/HS: Hessenberg panel width and GEMV column slices.
-template <typename T> struct SchurParams;
-template <> struct SchurParams<float> {
-    static constexpr int NSMALL = 140, NW = 96, NB = 24, ADV = 48, HNB = 32, HS = 32;
+// Tunables of the QR phase (runtime, per precision):
+//   nsmall: largest active block finished by one full-window LDS kernel;
+//   nw:     aggressive-early-deflation window;
+//   nb:     bulges per multishift sweep (2 nb shifts);
+//   adv:    rows a bulge chain advances per LDS window phase (the phase
+//           window is <= adv + 3 nb + 1 rows);
+//   nibble: skip the sweep when AED deflated more than nibble% of the window.
+struct SchurTune {
+    int nsmall, nw, nb, adv, nibble;
 };
-template <> struct SchurParams<double> {
-    static constexpr int NSMALL = 98, NW = 80, NB = 16, ADV = 40, HNB = 32, HS = 32;
+// Compile-time bounds that size the workspace and keep every LDS window
+// within 160 KiB: two nsmall^2 matrices, a phase window of <= WMAX rows.
+template <typename T> struct SchurCaps;
+template <> struct SchurCaps<float> {
+    static constexpr int NSMALL = 140, WMAX = 141, NBMAX = 44, HNB = 32, HS = 32;
 };
+template <> struct SchurCaps<double> {
+    static constexpr int NSMALL = 98, WMAX = 99, NBMAX = 32, HNB = 32, HS = 32;
+};
+template <typename T> SchurTune schur_tune();
+// Validates against the bounds; returns 0 or -1.
+template <typename T> int schur_tune_set(const SchurTune &t);
 
 template <typename T>
 size_t schur_work_bytes(int n);

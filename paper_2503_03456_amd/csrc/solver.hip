@@ -711,6 +711,27 @@ size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
                       mixed && (o.orth_check || autosel));
 }
 
+int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble) {
+    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -1;
+    const bool f = prec == SYLV_PREC_FP32;
+    SchurTune t = f ? schur_tune<float>() : schur_tune<double>();
+    if (nsmall > 0) t.nsmall = nsmall;
+    if (nw > 0) t.nw = nw;
+    if (nb > 0) t.nb = nb;
+    if (adv > 0) t.adv = adv;
+    if (nibble >= 0) t.nibble = nibble;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return (f ? schur_tune_set<float>(t) : schur_tune_set<double>(t)) ? -2 : 0;
+}
+
+int sylv_schur_tune_get(int prec, int *vals) {
+    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -1;
+    if (!vals) return -2;
+    const SchurTune t = prec == SYLV_PREC_FP32 ? schur_tune<float>() : schur_tune<double>();
+    vals[0] = t.nsmall; vals[1] = t.nw; vals[2] = t.nb; vals[3] = t.adv; vals[4] = t.nibble;
+    return 0;
+}
+
 int sylv_selector_features(int m, int n, const double *A, int lda, const double *B, int ldb,
                            const double *C, int ldc, float *feats, void *stream) {
     const bool lyap = (B == nullptr);
