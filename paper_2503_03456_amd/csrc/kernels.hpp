@@ -30,6 +30,9 @@ struct BatchEq {
     int stall;
     int steps;       // double-shift QR steps of the Schur kernel
     double napply;   // 3-element reflector applications of the Schur kernel
+    long long cyc[4];  // Schur kernel cycles: total, sweeps, U updates, deflation scans
+    int sweeps;
+    int pad2;
 };
 
 // selector.hip

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -288,19 +289,11 @@ __global__ __launch_bounds__(G * G) void k_bhess_reg(BatchEq *eqs, const int *or
 }
 
 // ------------------------------------------------------ 3. band-LDS Schur
-// Column j of the band holds rows 0..min(j+3, n-1) (the Hessenberg part plus
-// the two extra subdiagonals a bulge occupies).
-SYLV_DEVINL int band_off(int i, int j, int n) {
-    if (n < 4) return j * n + i;
-    const int jt = n - 4;
-    const int cs = (j <= jt) ? (j * (j + 7)) / 2 : (jt * (jt + 7)) / 2 + (j - jt) * n;
-    return cs + i;
-}
-inline int band_size(int n) {
-    if (n < 4) return n * n;
-    const int jt = n - 4;
-    return (jt * (jt + 7)) / 2 + 4 * n;
-}
+// Column j of the band holds rows 0..j+3 (the Hessenberg part plus the two
+// extra subdiagonals a bulge occupies; slots past row n-1 in the last three
+// columns are padding), so the offset is branch-free.
+SYLV_DEVINL int band_off(int i, int j, int) { return ((j * (j + 7)) >> 1) + i; }
+inline int band_size(int n) { return (n * (n + 7)) / 2; }
 #define HB(i, j) Hb[band_off((i), (j), n)]
 
 template <typename T>
@@ -327,12 +320,21 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
     }
     __syncthreads();
     const float ulp = num<float>::ulp, smlnum = num<float>::safmin * float(n) / num<float>::ulp;
-    int ihi = n - 1, its = 0, total = 0, fail = 0, nsteps = 0;
+    int ihi = n - 1, its = 0, total = 0, fail = 0, nsteps = 0, nsweeps = 0;
     double napply = 0.0;
+    const long long c_start = clock64();
+    long long c_sweep = 0, c_u = 0, c_scan = 0;
     const int itmax = 30 * (n > 10 ? n : 10);
     while (ihi >= 0) {
+        const long long c0 = clock64();
         if (tid == 0) sint = 0;
         __syncthreads();
+        // after 20 sweeps without a deflation the window is taken to have
+        // stagnated (nearly coincident eigenvalues can hold binary32
+        // subdiagonals near 1e-5 for hundreds of sweeps): subdiagonals below
+        // sqrt(u) (|h_{k-1,k-1}| + |h_kk|) then deflate.  The backward error
+        // of the form becomes ~sqrt(u); the binary64 refinement absorbs it.
+        const float thr = (its >= 20) ? 2.44140625e-4f : ulp;  // 2^-12 = sqrt(2^-24)
         for (int k = 1 + tid; k <= ihi; k += BSNT) {
             float hk = fabsf(HB(k, k - 1));
             float tst = fabsf(HB(k - 1, k - 1)) + fabsf(HB(k, k));
@@ -340,13 +342,14 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
                 if (k >= 2) tst += fabsf(HB(k - 1, k - 2));
                 if (k + 1 <= ihi) tst += fabsf(HB(k + 1, k));
             }
-            if (hk <= fmaxf(smlnum, ulp * tst)) atomicMax(&sint, k);
+            if (hk <= fmaxf(smlnum, thr * tst)) atomicMax(&sint, k);
         }
         __syncthreads();
         const int l = sint;
         __syncthreads();
         if (l > 0 && tid == 0) HB(l, l - 1) = 0.f;
         __syncthreads();
+        c_scan += clock64() - c0;
         if (l == ihi) { ihi -= 1; its = 0; continue; }
         if (l == ihi - 1) {
             // converged 2x2 block: split it when its eigenvalues are real
@@ -384,6 +387,8 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
         }
         if (++total > itmax) { fail = 1; break; }
         ++its;
+        ++nsweeps;
+        const long long c1 = clock64();
         float h11 = HB(ihi - 1, ihi - 1), h12 = HB(ihi - 1, ihi);
         float h21 = HB(ihi, ihi - 1), h22 = HB(ihi, ihi);
         // exceptional shifts every 10 sweeps without a deflation, built from
@@ -454,7 +459,9 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
                     HB(i, k2) = a2; HB(i, k) = a0; HB(i, k + 1) = a1;
                 }
             } else if (lane == 0) {
-                // overlap block rows/cols k, k+1, k2: left then right
+                // overlap block rows/cols k, k+1, k2: left then right (k2 =
+                // k+1 duplicates for a length-2 step: the duplicate is stored
+                // first so the genuine value wins)
                 const int ix[3] = {k, k + 1, k2};
                 float b[3][3];
 #pragma unroll
@@ -481,6 +488,8 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
             HB(pcol + 2, pcol) = 0.f;
             HB(pcol + 1, pcol) = pbeta;
         }
+        const long long c2 = clock64();
+        c_sweep += c2 - c1;
         // apply the sweep's reflectors to the rows of U (column-major: a
         // wave's loads and stores are contiguous), each thread streaming one
         // row through a three-entry register window; the entries ahead are
@@ -510,6 +519,7 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
             ur[(size_t)ihi * n] = z0;
         }
         __syncthreads();
+        c_u += clock64() - c2;
     }
     __syncthreads();
     // T back to global (dense, exact zeros below the first subdiagonal)
@@ -520,6 +530,11 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
     if (tid == 0) {
         q.steps = nsteps;
         q.napply = napply;
+        q.sweeps = nsweeps;
+        q.cyc[0] = clock64() - c_start;
+        q.cyc[1] = c_sweep;
+        q.cyc[2] = c_u;
+        q.cyc[3] = c_scan;
     }
     if (tid == 0 && fail) {
         q.qr_fail = 1;
@@ -880,6 +895,25 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
     double napply = 0.0;
     for (int i = 0; i < batch; ++i) napply += hq[i].napply;
     prof_add_work(KID_BSCHUR, 12.0 * napply);
+    if (std::getenv("SYLV_TRACE")) {
+        // per order bucket: cycles per QR step of the band-QR kernel, split
+        // into the chase, the U row streams and the deflation scans
+        const int edges[5] = {0, 64, 128, 180, 257};
+        for (int b = 0; b < 4; ++b) {
+            double cy[4] = {0, 0, 0, 0}, st = 0, sw = 0, cnt = 0;
+            for (int i = 0; i < batch; ++i) {
+                if (hq[i].n <= edges[b] || hq[i].n >= edges[b + 1]) continue;
+                for (int k = 0; k < 4; ++k) cy[k] += (double)hq[i].cyc[k];
+                st += hq[i].steps; sw += hq[i].sweeps; cnt += 1;
+            }
+            if (cnt == 0) continue;
+            std::fprintf(stderr,
+                         "[sylv] band QR n in (%d,%d): %.0f eqs, %.0f sweeps/eq, %.0f steps/eq, cycles/step "
+                         "%.0f (chase %.0f, U %.0f, scan %.0f)\n",
+                         edges[b], edges[b + 1], cnt, sw / cnt, st / cnt, cy[0] / st, cy[1] / st, cy[2] / st,
+                         cy[3] / st);
+        }
+    }
     for (int i = 0; i < batch; ++i) {
         const BatchEq &q = hq[i];
         if (infos) {
