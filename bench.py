@@ -25,6 +25,13 @@ PEAKS = {  # MI355X published dense peaks
     "hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0,
 }
 
+# HBM bytes per launch of a kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs of the default workload, each scaled by what the counter reads for a
+# device copy of known size (bench.py --workload copy): x2.0 for FETCH_SIZE,
+# x1.0 for WRITE_SIZE.  Valid for the kernel version the counters were taken
+# on (profiles/hbm_traffic_sylvester_2048.md); None once the kernel changes.
+TRAFFIC_BYTES = {"k_chase": (77.1 + 103.6) * 1024}
+
 KERNEL_IDS = {"gemm_kernel": 1, "k_hess_col": 2, "k_hess_gemv": 3, "k_aed": 4, "k_chase": 5,
               "k_trsyl_diag": 6, "k_find_ktop": 7, "k_cast": 8, "k_sumsq_partial": 9,
               "k_bhess": 10, "k_bschur": 11, "k_btrsyl": 12, "gemm_batched_kernel": 13}
@@ -120,7 +127,8 @@ def main_batched(args, np, torch, sy):
         run()
     torch.cuda.synchronize()
     lib = sy.lib()
-    kname = args.roofline_kernel if args.roofline_kernel != "k_aed" else "k_bschur"
+    batched_kernels = ("k_bhess", "k_bschur", "k_btrsyl", "gemm_batched_kernel")
+    kname = args.roofline_kernel if args.roofline_kernel in batched_kernels else "k_bschur"
     lib.sylv_profile_end.argtypes = [ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.sylv_profile_begin(KERNEL_IDS[kname])
@@ -242,6 +250,18 @@ def main():
         return main_batched(args, np, torch, sy)
     if args.workload == "c3sweep":
         return sweep_c3(args, np, torch, sy)
+    if args.workload == "copy":
+        # calibration for hardware byte counters: device-to-device copies of a
+        # known size (read 256 MiB + write 256 MiB per copy)
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy", "bytes_read_per_copy": a.numel() * 4,
+                          "bytes_written_per_copy": a.numel() * 4, "copies": args.steps}), flush=True)
+        return
     cfg, desc = load_workload(args.workload)
     m, n = cfg["C"].shape
 
@@ -347,8 +367,9 @@ def roofline_entry(kname, launches, total_ms, work, steps, step_s):
     ach = work / (total_ms * 1e-3) / 1e12 if total_ms > 0 else 0.0
     bound = "alu" if kname in ("k_chase", "k_aed", "k_bschur", "k_bhess") else "mfma"
     peak = PEAKS["fp32_TFLOPs"]
+    tb = TRAFFIC_BYTES.get(kname)
     return {"kernel": kname, "bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-            "frac": ach / peak, "traffic": None, "avg_launch_ms": avg_ms,
+            "frac": ach / peak, "traffic": tb, "avg_launch_ms": avg_ms,
             "launches_per_step": launches / steps, "work_per_launch_flops": work / launches,
             "share_of_step": (total_ms * 1e-3 / steps) / step_s}
 
