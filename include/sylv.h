@@ -153,12 +153,17 @@ size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, con
  *   nw      aggressive-early-deflation window,
  *   nb      bulges per multishift sweep,
  *   adv     rows a bulge chain advances per LDS window phase,
- *   nibble  percentage of the window AED must deflate to skip the sweep.
+ *   nibble  percentage of the window AED must deflate to skip the sweep,
+ *   aed_waves    wavefronts of the AED kernel (4 or 7),
+ *   chase_waves  wavefronts of the bulge-chase kernel (8 or 16).
  * A value <= 0 (nibble < 0) keeps the current one.  Returns 0, -1 for a bad
  * prec, -2 when the combination exceeds the LDS/workspace bounds
- * (FP32: nsmall, nw <= 140, adv + 3 nb + 1 <= 141; FP64: 98 and 99). */
-int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble);
-/* Current tunables (nsmall, nw, nb, adv, nibble) into vals[5] (host). */
+ * (FP32: nsmall, nw <= 140, adv + 3 nb + 1 <= 141; FP64: 98 and 99) or names
+ * an unsupported wave count. */
+int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, int aed_waves,
+                    int chase_waves);
+/* Current tunables (nsmall, nw, nb, adv, nibble, aed_waves, chase_waves) into
+ * vals[7] (host). */
 int sylv_schur_tune_get(int prec, int *vals);
 
 /* Text for a return value or a status code. */

@@ -1,6 +1,7 @@
 """Autotuner of the Schur factorisation's QR-phase parameters.
 
-Coordinate search over (nw, nb, adv, nsmall, nibble) -- the aggressive early
+Coordinate search over (aedw, chasew, nw, nb, adv, nsmall, nibble) -- the
+wavefronts of the AED and bulge-chase kernels, the aggressive early
 deflation window, bulges per multishift sweep, rows per bulge-chain window
 phase, the full-window cutoff and the sweep-skip threshold (see
 ``sylv_schur_tune`` in include/sylv.h) -- timing ``sylv_schur`` on a matrix
@@ -30,22 +31,23 @@ from . import lib, _check
 PREC = {"fp32": 1, "fp64": 0}
 GRID = {
     "fp32": dict(nw=[24, 32, 40, 48, 64, 80, 96, 128], nb=[8, 12, 16, 20, 24, 32], adv=[24, 32, 40, 48, 64],
-                 nsmall=[64, 96, 128, 140], nibble=[14, 20, 30, 40, 50, 65]),
+                 nsmall=[64, 96, 128, 140], nibble=[14, 20, 30, 40, 50, 65], aedw=[4, 7], chasew=[8, 16]),
     "fp64": dict(nw=[24, 32, 40, 48, 64, 80, 96], nb=[8, 12, 16, 20, 24], adv=[24, 32, 40, 48],
-                 nsmall=[64, 80, 98], nibble=[14, 20, 30, 40, 50, 65]),
+                 nsmall=[64, 80, 98], nibble=[14, 20, 30, 40, 50, 65], aedw=[4, 7], chasew=[8, 16]),
 }
-ORDER = ["nw", "nb", "adv", "nsmall", "nibble"]
-KEYS = ["nsmall", "nw", "nb", "adv", "nibble"]
+ORDER = ["aedw", "chasew", "nw", "nb", "adv", "nsmall", "nibble"]
+KEYS = ["nsmall", "nw", "nb", "adv", "nibble", "aedw", "chasew"]
 
 
 def get(prec):
-    v = (ctypes.c_int * 5)()
+    v = (ctypes.c_int * 7)()
     _check(lib().sylv_schur_tune_get(PREC[prec], v), "sylv_schur_tune_get")
     return dict(zip(KEYS, list(v)))
 
 
 def set_(prec, t):
-    return lib().sylv_schur_tune(PREC[prec], t["nsmall"], t["nw"], t["nb"], t["adv"], t["nibble"])
+    return lib().sylv_schur_tune(PREC[prec], t["nsmall"], t["nw"], t["nb"], t["adv"], t["nibble"], t["aedw"],
+                                 t["chasew"])
 
 
 def _matrix(n, seed):

@@ -428,42 +428,48 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
     if (tid == 0) { out[0] = 0; out[1] = nw - ns; out[2] = ns; }
 }
 
-// threads of the AED kernel: 7 waves, so that a window of up to 128 rows
-// gives every left/right/Z reflector application its own thread
-constexpr int AED_NT = 448;
-
 template <typename T>
 size_t aed_smem(int nw) {
     return sizeof(T) * ((size_t)2 * (nw | 1) * nw + nw) + 8 * sizeof(int);
 }
 
+// Raises a kernel's dynamic-LDS limit to at least sm bytes (once per size).
+static int lds_limit(const void *kfn, size_t sm, size_t &attr_set, std::mutex &mu) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (sm > attr_set) {
+        if (hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) != hipSuccess) {
+            (void)hipGetLastError();
+            return -1;
+        }
+        attr_set = sm;
+    }
+    return 0;
+}
+
+// waves: 4 (256 threads: one wave per role, windows <= 64 in one pass) or 7
+// (448 threads: two waves per role)
 template <typename T>
 int aed_launch(hipStream_t s, int nw, T *H, int ldh, int kwtop, int spike_on, T *Zw, int *out,
-               T *wr, T *wi) {
+               T *wr, T *wi, int waves) {
     size_t sm = aed_smem<T>(nw);
     if (sm > 160 * 1024) return -1;
-    auto kfn = k_aed<T, AED_NT>;
     static std::mutex mu;
-    static size_t attr_set = 0;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        if (sm > attr_set) {
-            if (hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)sm) != hipSuccess) {
-                (void)hipGetLastError();
-                return -1;
-            }
-            attr_set = sm;
-        }
-    }
-    {
-        ProfScope ps(KID_AED, s);
-        hipLaunchKernelGGL(kfn, dim3(1), dim3(AED_NT), sm, s, nw, H, ldh, kwtop, spike_on, Zw, out, wr, wi);
+    static size_t attr4 = 0, attr7 = 0;
+    ProfScope ps(KID_AED, s);
+    if (waves == 4) {
+        auto kfn = k_aed<T, 256>;
+        if (lds_limit((const void *)kfn, sm, attr4, mu)) return -1;
+        hipLaunchKernelGGL(kfn, dim3(1), dim3(256), sm, s, nw, H, ldh, kwtop, spike_on, Zw, out, wr, wi);
+    } else {
+        auto kfn = k_aed<T, 448>;
+        if (lds_limit((const void *)kfn, sm, attr7, mu)) return -1;
+        hipLaunchKernelGGL(kfn, dim3(1), dim3(448), sm, s, nw, H, ldh, kwtop, spike_on, Zw, out, wr, wi);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-template int aed_launch<float>(hipStream_t, int, float *, int, int, int, float *, int *, float *, float *);
-template int aed_launch<double>(hipStream_t, int, double *, int, int, int, double *, int *, double *, double *);
+template int aed_launch<float>(hipStream_t, int, float *, int, int, int, float *, int *, float *, float *, int);
+template int aed_launch<double>(hipStream_t, int, double *, int, int, int, double *, int *, double *, double *,
+                                int);
 template size_t aed_smem<float>(int);
 template size_t aed_smem<double>(int);
 
@@ -601,23 +607,16 @@ size_t chase_smem(int W, int nbulge) {
 
 template <typename T>
 int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W, int t0, int adv,
-                 int nbulge, const T *trd, T *Uw) {
+                 int nbulge, const T *trd, T *Uw, int waves) {
     size_t sm = chase_smem<T>(W, nbulge);
     if (sm > 160 * 1024) return -1;
-    auto kfn = k_chase<T, 1024>;
+    if (nbulge > 64 * waves) return -1;
     static std::mutex mu;
-    static size_t attr_set = 0;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        if (sm > attr_set) {
-            if (hipFuncSetAttribute((const void *)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)sm) != hipSuccess) {
-                (void)hipGetLastError();
-                return -1;
-            }
-            attr_set = sm;
-        }
-    }
+    static size_t attr8 = 0, attr16 = 0;
+    auto k8 = k_chase<T, 512>;
+    auto k16 = k_chase<T, 1024>;
+    if (lds_limit(waves == 8 ? (const void *)k8 : (const void *)k16, sm, waves == 8 ? attr8 : attr16, mu))
+        return -1;
     if (prof_armed(KID_CHASE)) {
         // algorithmic flops of this phase: every application of a bulge's
         // reflector to one row or column (length 3: 12 flops, length 2: 8),
@@ -638,15 +637,19 @@ int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W
     }
     {
         ProfScope ps(KID_CHASE, s);
-        hipLaunchKernelGGL(kfn, dim3(1), dim3(1024), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge,
-                           trd, Uw);
+        if (waves == 8)
+            hipLaunchKernelGGL(k8, dim3(1), dim3(512), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge, trd,
+                               Uw);
+        else
+            hipLaunchKernelGGL(k16, dim3(1), dim3(1024), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge,
+                               trd, Uw);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template int chase_launch<float>(hipStream_t, float *, int, int, int, int, int, int, int, int,
-                                 const float *, float *);
+                                 const float *, float *, int);
 template int chase_launch<double>(hipStream_t, double *, int, int, int, int, int, int, int, int,
-                                  const double *, double *);
+                                  const double *, double *, int);
 template size_t chase_smem<float>(int, int);
 template size_t chase_smem<double>(int, int);
 

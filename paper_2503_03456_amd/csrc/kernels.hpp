@@ -85,12 +85,12 @@ template <typename T>
 size_t aed_smem(int nw);
 template <typename T>
 int aed_launch(hipStream_t s, int nw, T *H, int ldh, int kwtop, int spike_on, T *Zw, int *out, T *wr,
-               T *wi);
+               T *wi, int waves = 7);
 template <typename T>
 size_t chase_smem(int W, int nbulge);
 template <typename T>
 int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W, int t0, int adv,
-                 int nbulge, const T *trd, T *Uw);
+                 int nbulge, const T *trd, T *Uw, int waves = 16);
 template <typename T>
 void find_ktop(hipStream_t s, T *H, int ldh, int klo, int kbot, int *out);
 template <typename T>

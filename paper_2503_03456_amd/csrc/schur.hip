@@ -23,30 +23,26 @@
 #include <cmath>
 #include <cstdio>
 #include <atomic>
+#include <mutex>
 #include <cstdlib>
 #include <algorithm>
 
 namespace sylv {
 
 // current tunables (defaults measured on MI355X by the autotuner)
-static std::atomic<long long> g_tune_f{0}, g_tune_d{0};
+static std::mutex g_tune_mu;
+static bool g_tune_set[2] = {false, false};
+static SchurTune g_tune[2];
 static SchurTune tune_default(bool fp32) {
     // selected by paper_2503_03456_amd.autotune (n = 2048, normal recipe,
-    // seed 7): Schur time 0.560 -> 0.398 s (binary32), 0.842 -> 0.629 s (binary64)
-    return fp32 ? SchurTune{128, 48, 20, 64, 40} : SchurTune{98, 48, 16, 48, 50};
-}
-static long long tune_pack(const SchurTune &t) {
-    return ((long long)t.nsmall << 48) | ((long long)t.nw << 36) | ((long long)t.nb << 24) |
-           ((long long)t.adv << 12) | (long long)t.nibble;
-}
-static SchurTune tune_unpack(long long v) {
-    return SchurTune{(int)((v >> 48) & 0xfff), (int)((v >> 36) & 0xfff), (int)((v >> 24) & 0xfff),
-                     (int)((v >> 12) & 0xfff), (int)(v & 0xfff)};
+    // seed 7): Schur time 0.560 -> 0.389 s (binary32), 0.842 -> 0.601 s (binary64)
+    return fp32 ? SchurTune{128, 48, 20, 64, 40, 4, 16} : SchurTune{64, 48, 16, 48, 50, 4, 8};
 }
 template <typename T>
 SchurTune schur_tune() {
-    const long long v = (sizeof(T) == 4 ? g_tune_f : g_tune_d).load();
-    return v ? tune_unpack(v) : tune_default(sizeof(T) == 4);
+    const int f = sizeof(T) == 4 ? 1 : 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune_set[f] ? g_tune[f] : tune_default(f == 1);
 }
 template <typename T>
 int schur_tune_set(const SchurTune &t) {
@@ -56,9 +52,14 @@ int schur_tune_set(const SchurTune &t) {
     if (t.nb < 1 || t.nb > K::NBMAX) return -1;
     if (t.adv < 4 || t.adv + 3 * t.nb + 1 > K::WMAX) return -1;
     if (t.nibble < 0 || t.nibble > 100) return -1;
+    if (t.aedw != 4 && t.aedw != 7) return -1;
+    if (t.chasew != 8 && t.chasew != 16) return -1;
     if (aed_smem<T>(t.nw) > 160 * 1024) return -1;
     if (chase_smem<T>(t.adv + 3 * t.nb + 1, t.nb) > 160 * 1024) return -1;
-    (sizeof(T) == 4 ? g_tune_f : g_tune_d).store(tune_pack(t));
+    const int f = sizeof(T) == 4 ? 1 : 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[f] = t;
+    g_tune_set[f] = true;
     return 0;
 }
 template SchurTune schur_tune<float>();
@@ -205,7 +206,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         if (N == 2) { std2x2<T>(s, n, H, ldh, U, ldu, ktop); kbot -= 2; ndfl = 1; continue; }
         if (++iters > itmax) { *qr_status = 1; break; }
         if (N <= P.nsmall) {
-            if (aed_launch<T>(s, N, H, ldh, ktop, 0, c.Zw, c.dint, c.wr, c.wi)) return -1;
+            if (aed_launch<T>(s, N, H, ldh, ktop, 0, c.Zw, c.dint, c.wr, c.wi, P.aedw)) return -1;
             if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
             ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5];
             prof_add_work(KID_AED, 12.0 * (2.0 * N + 3.0) * hi[4]);
@@ -218,7 +219,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         // aggressive early deflation on the trailing window
         const int nw = std::min(P.nw, N - 1);
         const int kwtop = kbot - nw + 1;
-        if (aed_launch<T>(s, nw, H, ldh, kwtop, 1, c.Zw, c.dint, c.wr, c.wi)) return -1;
+        if (aed_launch<T>(s, nw, H, ldh, kwtop, 1, c.Zw, c.dint, c.wr, c.wi, P.aedw)) return -1;
         if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
         const int aed_st = hi[0], nd = hi[1], nsu = hi[2];
         ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5]; st_defl += nd;
@@ -293,7 +294,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
             const int ws_ = ktop + std::max(0, pmin - 1);
             const int we_ = ktop + std::min(N2, pmax + 4);
             const int W = we_ - ws_;
-            if (chase_launch<T>(s, H, ldh, ktop, kbot, ws_, W, t0, t1 - t0, nb, c.trd, c.Uw)) return -1;
+            if (chase_launch<T>(s, H, ldh, ktop, kbot, ws_, W, t0, t1 - t0, nb, c.trd, c.Uw, P.chasew)) return -1;
             ++st_chase;
             apply_window(c, ws_, W, c.Uw);
         }

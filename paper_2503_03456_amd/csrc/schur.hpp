@@ -11,9 +11,11 @@ namespace sylv {
 //   nb:     bulges per multishift sweep (2 nb shifts);
 //   adv:    rows a bulge chain advances per LDS window phase (the phase
 //           window is <= adv + 3 nb + 1 rows);
-//   nibble: skip the sweep when AED deflated more than nibble% of the window.
+//   nibble: skip the sweep when AED deflated more than nibble% of the window;
+//   aedw:   waves of the AED kernel (4 or 7);
+//   chasew: waves of the bulge-chase kernel (8 or 16).
 struct SchurTune {
-    int nsmall, nw, nb, adv, nibble;
+    int nsmall, nw, nb, adv, nibble, aedw, chasew;
 };
 // Compile-time bounds that size the workspace and keep every LDS window
 // within 160 KiB: two nsmall^2 matrices, a phase window of <= WMAX rows.

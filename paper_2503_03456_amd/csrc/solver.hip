@@ -711,7 +711,8 @@ size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
                       mixed && (o.orth_check || autosel));
 }
 
-int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble) {
+int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, int aed_waves,
+                    int chase_waves) {
     if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -1;
     const bool f = prec == SYLV_PREC_FP32;
     SchurTune t = f ? schur_tune<float>() : schur_tune<double>();
@@ -720,6 +721,8 @@ int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble) {
     if (nb > 0) t.nb = nb;
     if (adv > 0) t.adv = adv;
     if (nibble >= 0) t.nibble = nibble;
+    if (aed_waves > 0) t.aedw = aed_waves;
+    if (chase_waves > 0) t.chasew = chase_waves;
     std::lock_guard<std::mutex> lk(g_mu);
     return (f ? schur_tune_set<float>(t) : schur_tune_set<double>(t)) ? -2 : 0;
 }
@@ -729,6 +732,7 @@ int sylv_schur_tune_get(int prec, int *vals) {
     if (!vals) return -2;
     const SchurTune t = prec == SYLV_PREC_FP32 ? schur_tune<float>() : schur_tune<double>();
     vals[0] = t.nsmall; vals[1] = t.nw; vals[2] = t.nb; vals[3] = t.adv; vals[4] = t.nibble;
+    vals[5] = t.aedw; vals[6] = t.chasew;
     return 0;
 }
 
