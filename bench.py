@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--count", type=int, default=4096, help="equations of the batched workload (c4)")
     ap.add_argument("--cpu-sample-eqs", type=int, default=1024)
     ap.add_argument("--c3-first", type=int, default=0, help="first delta index of the c3sweep workload")
+    ap.add_argument("--alg", default="orig", choices=["orig", "orth"],
+                    help="mixed path: refinement in the original basis (orig) or the paper's Alg. 4.1 (orth)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this solver has no "
@@ -270,12 +272,12 @@ def main():
 
     A, B, C = dev(cfg["A"]), dev(cfg["B"]), dev(cfg["C"])
     X = torch.empty((n, m), dtype=torch.float64, device="cuda").t()
-    work = torch.empty(max(sy.workspace_size(m, n, low="fp32"), sy.workspace_size(m, n, low="fp64")),
+    work = torch.empty(max(sy.workspace_size(m, n, low="fp32", alg=args.alg), sy.workspace_size(m, n, low="fp64")),
                        dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
 
     def run(low):
-        return sy.solve(A, B, C, X=X, work=work, low=low)[1]
+        return sy.solve(A, B, C, X=X, work=work, low=low, alg=(args.alg if low != "fp64" else "orig"))[1]
 
     for _ in range(args.warmup):
         run("fp32")
@@ -335,7 +337,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": desc, "m": m, "n": n, "path": "fp32 Schur + fp64 refinement",
+        "config": {"workload": desc, "m": m, "n": n,
+                   "path": ("fp32 Schur + fp64 refinement" if args.alg == "orig" else
+                            "Alg. 4.1: fp32 Schur, fp64-orthonormalised factors, triangular-basis refinement"),
                    "tol": 1e-14},
         "rel_res": max(i["rel_res"] for i in infos),
         "all_solves_at_tol": ok,

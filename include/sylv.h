@@ -71,7 +71,14 @@ typedef struct {
     int    max_iter;   /* refinement cap (default 20, the cap used in the paper's experiments)    */
     int    fallback;   /* 1: on failure escalate to the plain binary64 path (default 1)           */
     int    orth_check; /* 0 off, 1 (default) binary64 ||U^T U - I||_F of the low-precision factors */
+    int    alg;        /* SYLV_ALG_ORIG (default): refinement in the original basis (binary64
+                          residual C - AX - XB, low-precision corrections); SYLV_ALG_ORTH: Alg. 4.1
+                          (binary64-orthonormalised Schur vectors, Alg. 3.1 in the triangular basis
+                          with binary64 tri-solves); ignored by SYLV_PREC_FP64 and AUTO        */
 } sylv_opts;
+
+#define SYLV_ALG_ORIG 0
+#define SYLV_ALG_ORTH 1
 
 typedef struct {
     double rel_res;     /* eq. (2.1) at exit, binary64, Frobenius norms                         */

@@ -36,7 +36,7 @@ KIND = {"sylv": 0, "lyap": 1}
 
 class Opts(ctypes.Structure):
     _fields_ = [("low", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("fallback", ctypes.c_int), ("orth_check", ctypes.c_int)]
+                ("fallback", ctypes.c_int), ("orth_check", ctypes.c_int), ("alg", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -140,9 +140,13 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def make_opts(low="fp32", tol=1e-14, max_iter=20, fallback=True, orth_check=True):
+ALG = {"orig": 0, "orth": 1}
+
+
+def make_opts(low="fp32", tol=1e-14, max_iter=20, fallback=True, orth_check=True, alg="orig"):
     o = Opts()
     _lib.sylv_default_opts(ctypes.byref(o))
+    o.alg = ALG[alg] if isinstance(alg, str) else int(alg)
     o.low = PREC[low] if isinstance(low, str) else int(low)
     o.tol = float(tol)
     o.max_iter = int(max_iter)

@@ -23,7 +23,7 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
 using namespace sylv;
 
 static bool batched_eligible(int kind, int n, const sylv_opts &o) {
-    return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 &&
+    return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 && o.alg == SYLV_ALG_ORIG &&
            (o.low == SYLV_PREC_FP32 || o.low == SYLV_PREC_BF16);
 }
 

@@ -111,9 +111,17 @@ struct Stage {  // buffers of one precision's Bartels-Stewart pipeline
     char *schur_ws2;  // Schur workspace for B (the two run concurrently)
 };
 
+// Alg. 4.1 buffers (binary64): orthonormalised factors, the triangular-basis
+// coefficients M = Q^T A Q (= T + L), the binary64 copies of T, F = QA^T C QB,
+// the triangular-basis iterate Y, and two scratch matrices.
+struct OrthStage {
+    double *QA, *QB, *MA, *MB, *TA, *TB, *F, *Y, *W, *E;
+};
+
 struct Plan {
     Stage<float> lo;
     Stage<double> hi;
+    OrthStage o;
     double *R;        // m x n residual
     double *G;        // orthogonality check scratch, 2 * max(m,n)^2
     double *scal;     // 64 device scalars
@@ -122,9 +130,23 @@ struct Plan {
     float *eig;       // eigenvalue scratch for sep_est (4 * max(m,n))
 };
 
-static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth, Plan &p) {
+static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth, Plan &p,
+                 bool alg41 = false) {
     const int mx = std::max(m, n);
     std::memset(&p, 0, sizeof(p));
+    if (alg41) {
+        const size_t mm = (size_t)m * m, nn = (size_t)n * n, mn = (size_t)m * n, xx = (size_t)mx * mx;
+        p.o.QA = a.take<double>(mm);
+        p.o.QB = a.take<double>(nn);
+        p.o.MA = a.take<double>(mm);
+        p.o.MB = a.take<double>(nn);
+        p.o.TA = a.take<double>(mm);
+        p.o.TB = a.take<double>(nn);
+        p.o.F = a.take<double>(mn);
+        p.o.Y = a.take<double>(mn);
+        p.o.W = a.take<double>(std::max(xx, mn));
+        p.o.E = a.take<double>(xx);
+    }
     if (need_lo) {
         p.lo.TA = a.take<float>((size_t)m * m);
         p.lo.UA = a.take<float>((size_t)m * m);
@@ -153,10 +175,11 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
     p.eig = a.take<float>((size_t)4 * mx + 64);
 }
 
-static size_t plan_bytes(int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth) {
+static size_t plan_bytes(int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth,
+                         bool alg41 = false) {
     Arena a(nullptr);
     Plan p;
-    plan(a, m, n, lyap, need_lo, need_hi, orth, p);
+    plan(a, m, n, lyap, need_lo, need_hi, orth, p, alg41);
     return a.off + 256;
 }
 
@@ -527,6 +550,120 @@ static int selector_features(hipStream_t s, DevCtx *c, int m, int n, bool lyap, 
     return 0;
 }
 
+// Alg. 4.1 (Sec. 4.1): orthonormalise the low-precision Schur vectors in
+// binary64, form the triangular-basis coefficients T + L = Q^T A Q and
+// F = QA^T C QB in binary64, take Y0 from the low-precision tri-solve, run the
+// stationary iteration of Alg. 3.1 in the triangular basis with binary64
+// residuals and a binary64 tri-solve, and recover X = QA Y QB^T.
+// Orthonormalisation: Newton-Schulz steps Q <- Q - Q (Q^T Q - I) / 2 from
+// Q = fl64(U), until ||Q^T Q - I||_F <= 8 n u_64 (at most 8 steps).  Q
+// converges quadratically to the polar factor of U, and ||Q^T U - I|| =
+// O(u_low) as the analysis of Sec. 4.1 requires of its QR factor.  Binary32
+// forms (||U^T U - I|| ~ 1e-4 at n = 2048) need two steps, BF16-update forms
+// (~6e-2) four.  Returns the number of steps or a negative ABI code.
+static int orthonormalize(hipStream_t s, DevCtx *c, int n, const float *U, double *Q, double *E, double *W,
+                          double *scal, double *nscr) {
+    cast<float, double>(s, n, n, U, n, Q, n, 1.0f);
+    const double target = 8.0 * n * 1.1102230246251565e-16;
+    for (int it = 0; it <= 8; ++it) {
+        gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, Q, n, Q, n, 0.0, E, n);
+        sub_identity(s, n, E, n);
+        matnorm<double>(s, n, n, E, n, scal, nscr, 0);
+        double h;
+        hipError_t e = read_scalars(s, c, scal, 1, &h);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        if (!(h > target) || it == 8) return it;
+        cast<double, double>(s, n, n, Q, n, W, n, 1.0);
+        gemm<double, double, double, double>(s, 0, 0, n, n, n, -0.5, Q, n, E, n, 1.0, W, n);
+        cast<double, double>(s, n, n, W, n, Q, n, 1.0);
+    }
+    return 8;
+}
+
+static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda, const double *B,
+                     int ldb, bool lyap, const double *C, int ldc, double *X, int ldx, Plan &p,
+                     const Norms &nm, const sylv_opts &o, sylv_info *info, int *ok) {
+    *ok = 0;
+    int qa = 0, qb = 0;
+    const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
+    int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, bf16, o.orth_check, &qa, &qb);
+    if (rc) return rc;
+    OrthStage &q = p.o;
+    // Q_A, Q_B
+    rc = orthonormalize(s, c, m, p.lo.UA, q.QA, q.E, q.W, p.scal + 53, p.nscr);
+    if (rc < 0) return rc;
+    if (lyap) revcols<double, double>(s, n, n, q.QA, n, q.QB, n, 1.0);  // V = U P
+    else if ((rc = orthonormalize(s, c, n, p.lo.UB, q.QB, q.E, q.W, p.scal + 53, p.nscr)) < 0) return rc;
+    // M_A = Q_A^T A Q_A, M_B = Q_B^T B Q_B (B = A^T for Lyapunov)
+    gemm<double, double, double, double>(s, 0, 0, m, m, m, 1.0, A, lda, q.QA, m, 0.0, q.W, m);
+    gemm<double, double, double, double>(s, 1, 0, m, m, m, 1.0, q.QA, m, q.W, m, 0.0, q.MA, m);
+    if (lyap) gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, A, lda, q.QB, n, 0.0, q.W, n);
+    else gemm<double, double, double, double>(s, 0, 0, n, n, n, 1.0, B, ldb, q.QB, n, 0.0, q.W, n);
+    gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, q.QB, n, q.W, n, 0.0, q.MB, n);
+    cast<float, double>(s, m, m, p.lo.TA, m, q.TA, m, 1.0f);
+    cast<float, double>(s, n, n, p.lo.TB, n, q.TB, n, 1.0f);
+    // F = Q_A^T C Q_B
+    gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, q.QA, m, C, ldc, 0.0, q.W, m);
+    gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, q.W, m, q.QB, n, 0.0, q.F, m);
+    // Y0: low-precision solve of T_A Y + Y T_B = F
+    hipMemsetAsync(p.flag, 0, sizeof(int), s);
+    cast<double, float>(s, m, n, q.F, m, p.lo.Y, m, 1.0);
+    trsyl<float>(s, m, n, p.lo.TA, m, p.lo.TB, n, p.lo.Y, m, p.scal + 12, p.flag);
+    cast<float, double>(s, m, n, p.lo.Y, m, q.Y, m, 1.0f);
+    // Alg. 3.1 in the triangular basis
+    double prev = INFINITY, rel = INFINITY, corr = 0.0, h[4];
+    int it = 0, stall = 0, status = SYLV_ST_NOT_CONVERGED;
+    for (;;) {
+        cast<double, double>(s, m, n, q.F, m, p.R, m, 1.0);
+        gemm<double, double, double, double>(s, 0, 0, m, n, m, -1.0, q.MA, m, q.Y, m, 1.0, p.R, m);
+        gemm<double, double, double, double>(s, 0, 0, m, n, n, -1.0, q.Y, m, q.MB, n, 1.0, p.R, m);
+        matnorm<double>(s, m, n, p.R, m, p.scal + 50, p.nscr, 0);
+        matnorm<double>(s, m, n, q.Y, m, p.scal + 51, p.nscr, 0);
+        hipError_t e = read_scalars(s, c, p.scal + 50, 2, h);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        rel = h[0] / (nm.c + h[1] * (nm.a + nm.b));
+        if (!std::isfinite(rel)) { status = SYLV_ST_NAN; break; }
+        if (rel <= o.tol) { status = SYLV_OK; break; }
+        if (it >= o.max_iter) break;
+        if (rel > 0.5 * prev) { if (++stall >= 2) break; } else stall = 0;
+        prev = rel;
+        // D from T_A D + D T_B = R (binary64 tri-solve), Y += D
+        trsyl<double>(s, m, n, q.TA, m, q.TB, n, p.R, m, p.scal + 12, p.flag);
+        axpy<double>(s, m, n, 1.0, p.R, m, q.Y, m);
+        matnorm<double>(s, m, n, p.R, m, p.scal + 52, p.nscr, 0);
+        ++it;
+        e = read_scalars(s, c, p.scal + 52, 1, h + 2);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        corr = h[2];
+    }
+    // X = Q_A Y Q_B^T, then the residual against the original coefficients
+    gemm<double, double, double, double>(s, 0, 0, m, n, m, 1.0, q.QA, m, q.Y, m, 0.0, q.W, m);
+    gemm<double, double, double, double>(s, 0, 1, m, n, n, 1.0, q.W, m, q.QB, n, 0.0, X, ldx);
+    residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr);
+    double hr[32];
+    hipError_t e = read_scalars(s, c, p.scal, 32, hr);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    const double rel_true = hr[0] / (nm.c + hr[2] * (nm.a + nm.b));
+    int flag = 0;
+    hipMemcpy(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (status == SYLV_OK && !(rel_true <= o.tol)) status = SYLV_ST_NOT_CONVERGED;
+    if (!std::isfinite(rel_true)) status = SYLV_ST_NAN;
+    if (qa || qb) status = (status == SYLV_OK) ? SYLV_OK : SYLV_ST_QR_FAILED;
+    if (status == SYLV_OK && flag) status = SYLV_ST_PERTURBED;
+    *ok = (status == SYLV_OK || status == SYLV_ST_PERTURBED) ? 1 : 0;
+    if (info) {
+        info->rel_res = rel_true;
+        info->orth_u = o.orth_check ? hr[20] : 0.0;
+        info->orth_v = o.orth_check ? (lyap ? hr[20] : hr[21]) : 0.0;
+        info->sep_est = hr[13];
+        info->corr_ratio = (h[1] > 0) ? corr / h[1] : 0.0;
+        info->iterations = it;
+        info->precision_used = bf16 ? SYLV_PREC_BF16 : SYLV_PREC_FP32;
+        info->status = status;
+    }
+    return 0;
+}
+
 // SYLV_PREC_AUTO: binary32 forms, their 16 features, the selector's class,
 // then the chosen refinement on those same forms:
 //   0: transforms on bfloat16 inputs, 1: binary32 transforms, 2: plain binary64;
@@ -597,6 +734,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
         return -(ci + 4);
     if (autosel && !selector_installed()) return -(ci + 4);
     if (!(o.tol >= 0.0) || o.max_iter < 0) return -(ci + 4);
+    if (o.alg != SYLV_ALG_ORIG && o.alg != SYLV_ALG_ORTH) return -(ci + 4);
     if (info) std::memset(info, 0, sizeof(*info));
     if (m == 0 || n == 0) {
         if (info) {
@@ -613,7 +751,8 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool need_hi = !mixed || o.fallback || autosel;
     const bool orth = mixed && (o.orth_check || autosel);
-    const size_t need = plan_bytes(m, n, lyap, mixed, need_hi, orth);
+    const bool alg41 = mixed && !autosel && o.alg == SYLV_ALG_ORTH;
+    const size_t need = plan_bytes(m, n, lyap, mixed, need_hi, orth, alg41);
     void *base = work;
     if (work) {
         if (work_bytes < need) return lyap ? -11 : -15;
@@ -623,7 +762,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     }
     Arena ar(base);
     Plan p;
-    plan(ar, m, n, lyap, mixed, need_hi, orth, p);
+    plan(ar, m, n, lyap, mixed, need_hi, orth, p, alg41);
     // norms of the coefficients (eq. (2.1) denominators)
     matnorm<double>(s, m, m, A, lda, p.scal + 40, p.nscr, 0);
     if (!lyap) matnorm<double>(s, n, n, B, ldb, p.scal + 41, p.nscr, 0);
@@ -636,7 +775,8 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     if (!mixed) return run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, info);
     if (autosel) return run_auto(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info);
     int ok = 0;
-    rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
+    if (alg41) rc = run_alg41(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
+    else rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
     if (rc) return rc;
     int escalated = 0, iters = info ? info->iterations : 0;
     if (!ok && o.fallback && o.low == SYLV_PREC_BF16) {
@@ -693,6 +833,7 @@ extern "C" {
 void sylv_default_opts(sylv_opts *o) {
     if (!o) return;
     o->low = SYLV_PREC_FP32;
+    o->alg = SYLV_ALG_ORIG;
     o->tol = 1e-14;
     o->max_iter = 20;
     o->fallback = 1;
@@ -708,7 +849,7 @@ size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool autosel = o.low == SYLV_PREC_AUTO;
     return plan_bytes(m, n, lyap != 0, mixed, !mixed || o.fallback || autosel,
-                      mixed && (o.orth_check || autosel));
+                      mixed && (o.orth_check || autosel), mixed && !autosel && o.alg == SYLV_ALG_ORTH);
 }
 
 int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, int aed_waves,
