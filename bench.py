@@ -234,8 +234,9 @@ def main():
     ap.add_argument("--count", type=int, default=4096, help="equations of the batched workload (c4)")
     ap.add_argument("--cpu-sample-eqs", type=int, default=1024)
     ap.add_argument("--c3-first", type=int, default=0, help="first delta index of the c3sweep workload")
-    ap.add_argument("--alg", default="orig", choices=["orig", "orth"],
-                    help="mixed path: refinement in the original basis (orig) or the paper's Alg. 4.1 (orth)")
+    ap.add_argument("--alg", default="orig", choices=["orig", "orth", "inv"],
+                    help="mixed path: refinement in the original basis (orig), the paper's Alg. 4.1 (orth) "
+                         "or Alg. 4.2 (inv)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this solver has no "
@@ -338,8 +339,9 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": desc, "m": m, "n": n,
-                   "path": ("fp32 Schur + fp64 refinement" if args.alg == "orig" else
-                            "Alg. 4.1: fp32 Schur, fp64-orthonormalised factors, triangular-basis refinement"),
+                   "path": {"orig": "fp32 Schur + fp64 refinement",
+                            "orth": "Alg. 4.1: fp32 Schur, fp64-orthonormalised factors, triangular-basis refinement",
+                            "inv": "Alg. 4.2: fp32 Schur, fp64 inverses of the factors, triangular-basis refinement"}[args.alg],
                    "tol": 1e-14},
         "rel_res": max(i["rel_res"] for i in infos),
         "all_solves_at_tol": ok,

@@ -74,11 +74,14 @@ typedef struct {
     int    alg;        /* SYLV_ALG_ORIG (default): refinement in the original basis (binary64
                           residual C - AX - XB, low-precision corrections); SYLV_ALG_ORTH: Alg. 4.1
                           (binary64-orthonormalised Schur vectors, Alg. 3.1 in the triangular basis
-                          with binary64 tri-solves); ignored by SYLV_PREC_FP64 and AUTO        */
+                          with binary64 tri-solves); SYLV_ALG_INV: Alg. 4.2 (the low-precision
+                          Schur vectors with their binary64 inverses, same iteration); ignored by
+                          SYLV_PREC_FP64 and AUTO                                               */
 } sylv_opts;
 
 #define SYLV_ALG_ORIG 0
 #define SYLV_ALG_ORTH 1
+#define SYLV_ALG_INV  2
 
 typedef struct {
     double rel_res;     /* eq. (2.1) at exit, binary64, Frobenius norms                         */

@@ -140,7 +140,7 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-ALG = {"orig": 0, "orth": 1}
+ALG = {"orig": 0, "orth": 1, "inv": 2}
 
 
 def make_opts(low="fp32", tol=1e-14, max_iter=20, fallback=True, orth_check=True, alg="orig"):

@@ -116,6 +116,7 @@ struct Stage {  // buffers of one precision's Bartels-Stewart pipeline
 // the triangular-basis iterate Y, and two scratch matrices.
 struct OrthStage {
     double *QA, *QB, *MA, *MB, *TA, *TB, *F, *Y, *W, *E;
+    double *UA, *UB;  // Alg. 4.2: binary64 copies of the low-precision factors (QA, QB hold their inverses)
 };
 
 struct Plan {
@@ -146,6 +147,8 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
         p.o.Y = a.take<double>(mn);
         p.o.W = a.take<double>(std::max(xx, mn));
         p.o.E = a.take<double>(xx);
+        p.o.UA = a.take<double>(mm);
+        p.o.UB = a.take<double>(nn);
     }
     if (need_lo) {
         p.lo.TA = a.take<float>((size_t)m * m);
@@ -580,31 +583,76 @@ static int orthonormalize(hipStream_t s, DevCtx *c, int n, const float *U, doubl
     return 8;
 }
 
+// Alg. 4.2 needs U^{-1} in binary64: Newton-Schulz steps for the inverse,
+// Z <- Z - Z (U Z - I) from Z = U^T, until ||U Z - I||_F <= 8 n u_64 (at most
+// 8 steps; quadratic convergence from ||U U^T - I|| ~ u_low).  Returns the
+// number of steps or a negative ABI code.
+static int invert_nearly_orthogonal(hipStream_t s, DevCtx *c, int n, const double *U, double *Z, double *E,
+                                    double *W, double *scal, double *nscr) {
+    transpose<double>(s, n, n, U, n, Z, n, 0);
+    const double target = 8.0 * n * 1.1102230246251565e-16;
+    for (int it = 0; it <= 8; ++it) {
+        gemm<double, double, double, double>(s, 0, 0, n, n, n, 1.0, U, n, Z, n, 0.0, E, n);
+        sub_identity(s, n, E, n);
+        matnorm<double>(s, n, n, E, n, scal, nscr, 0);
+        double h;
+        hipError_t e = read_scalars(s, c, scal, 1, &h);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        if (!(h > target) || it == 8) return it;
+        cast<double, double>(s, n, n, Z, n, W, n, 1.0);
+        gemm<double, double, double, double>(s, 0, 0, n, n, n, -1.0, Z, n, E, n, 1.0, W, n);
+        cast<double, double>(s, n, n, W, n, Z, n, 1.0);
+    }
+    return 8;
+}
+
+// inv = false: Alg. 4.1 (orthonormalised factors Q); inv = true: Alg. 4.2
+// (the low-precision factors U themselves, with their binary64 inverses):
+//   F = U_A^T C U_B,  M_A = U_A^T A U_A^{-T},  M_B = U_B^{-1} B U_B,
+//   X = U_A^{-T} Y U_B^{-1}.
 static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda, const double *B,
                      int ldb, bool lyap, const double *C, int ldc, double *X, int ldx, Plan &p,
-                     const Norms &nm, const sylv_opts &o, sylv_info *info, int *ok) {
+                     const Norms &nm, const sylv_opts &o, sylv_info *info, int *ok, bool inv = false) {
     *ok = 0;
     int qa = 0, qb = 0;
     const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
     int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, bf16, o.orth_check, &qa, &qb);
     if (rc) return rc;
     OrthStage &q = p.o;
-    // Q_A, Q_B
-    rc = orthonormalize(s, c, m, p.lo.UA, q.QA, q.E, q.W, p.scal + 53, p.nscr);
-    if (rc < 0) return rc;
-    if (lyap) revcols<double, double>(s, n, n, q.QA, n, q.QB, n, 1.0);  // V = U P
-    else if ((rc = orthonormalize(s, c, n, p.lo.UB, q.QB, q.E, q.W, p.scal + 53, p.nscr)) < 0) return rc;
-    // M_A = Q_A^T A Q_A, M_B = Q_B^T B Q_B (B = A^T for Lyapunov)
-    gemm<double, double, double, double>(s, 0, 0, m, m, m, 1.0, A, lda, q.QA, m, 0.0, q.W, m);
-    gemm<double, double, double, double>(s, 1, 0, m, m, m, 1.0, q.QA, m, q.W, m, 0.0, q.MA, m);
-    if (lyap) gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, A, lda, q.QB, n, 0.0, q.W, n);
-    else gemm<double, double, double, double>(s, 0, 0, n, n, n, 1.0, B, ldb, q.QB, n, 0.0, q.W, n);
-    gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, q.QB, n, q.W, n, 0.0, q.MB, n);
+    if (!inv) {
+        // Q_A, Q_B
+        rc = orthonormalize(s, c, m, p.lo.UA, q.QA, q.E, q.W, p.scal + 53, p.nscr);
+        if (rc < 0) return rc;
+        if (lyap) revcols<double, double>(s, n, n, q.QA, n, q.QB, n, 1.0);  // V = U P
+        else if ((rc = orthonormalize(s, c, n, p.lo.UB, q.QB, q.E, q.W, p.scal + 53, p.nscr)) < 0) return rc;
+        // M_A = Q_A^T A Q_A, M_B = Q_B^T B Q_B (B = A^T for Lyapunov)
+        gemm<double, double, double, double>(s, 0, 0, m, m, m, 1.0, A, lda, q.QA, m, 0.0, q.W, m);
+        gemm<double, double, double, double>(s, 1, 0, m, m, m, 1.0, q.QA, m, q.W, m, 0.0, q.MA, m);
+        if (lyap) gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, A, lda, q.QB, n, 0.0, q.W, n);
+        else gemm<double, double, double, double>(s, 0, 0, n, n, n, 1.0, B, ldb, q.QB, n, 0.0, q.W, n);
+        gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, q.QB, n, q.W, n, 0.0, q.MB, n);
+        // F = Q_A^T C Q_B
+        gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, q.QA, m, C, ldc, 0.0, q.W, m);
+        gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, q.W, m, q.QB, n, 0.0, q.F, m);
+    } else {
+        // binary64 U_A, U_B and Z_A = U_A^{-1}, Z_B = U_B^{-1} (in QA, QB)
+        cast<float, double>(s, m, m, p.lo.UA, m, q.UA, m, 1.0f);
+        cast<float, double>(s, n, n, p.lo.UB, n, q.UB, n, 1.0f);
+        if ((rc = invert_nearly_orthogonal(s, c, m, q.UA, q.QA, q.E, q.W, p.scal + 53, p.nscr)) < 0) return rc;
+        if ((rc = invert_nearly_orthogonal(s, c, n, q.UB, q.QB, q.E, q.W, p.scal + 53, p.nscr)) < 0) return rc;
+        // M_A = U_A^T (A Z_A^T)
+        gemm<double, double, double, double>(s, 0, 1, m, m, m, 1.0, A, lda, q.QA, m, 0.0, q.W, m);
+        gemm<double, double, double, double>(s, 1, 0, m, m, m, 1.0, q.UA, m, q.W, m, 0.0, q.MA, m);
+        // M_B = Z_B (B U_B), B = A^T for Lyapunov
+        if (lyap) gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, A, lda, q.UB, n, 0.0, q.W, n);
+        else gemm<double, double, double, double>(s, 0, 0, n, n, n, 1.0, B, ldb, q.UB, n, 0.0, q.W, n);
+        gemm<double, double, double, double>(s, 0, 0, n, n, n, 1.0, q.QB, n, q.W, n, 0.0, q.MB, n);
+        // F = U_A^T C U_B
+        gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, q.UA, m, C, ldc, 0.0, q.W, m);
+        gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, q.W, m, q.UB, n, 0.0, q.F, m);
+    }
     cast<float, double>(s, m, m, p.lo.TA, m, q.TA, m, 1.0f);
     cast<float, double>(s, n, n, p.lo.TB, n, q.TB, n, 1.0f);
-    // F = Q_A^T C Q_B
-    gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, q.QA, m, C, ldc, 0.0, q.W, m);
-    gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, q.W, m, q.QB, n, 0.0, q.F, m);
     // Y0: low-precision solve of T_A Y + Y T_B = F
     hipMemsetAsync(p.flag, 0, sizeof(int), s);
     cast<double, float>(s, m, n, q.F, m, p.lo.Y, m, 1.0);
@@ -636,9 +684,10 @@ static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
         if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
         corr = h[2];
     }
-    // X = Q_A Y Q_B^T, then the residual against the original coefficients
-    gemm<double, double, double, double>(s, 0, 0, m, n, m, 1.0, q.QA, m, q.Y, m, 0.0, q.W, m);
-    gemm<double, double, double, double>(s, 0, 1, m, n, n, 1.0, q.W, m, q.QB, n, 0.0, X, ldx);
+    // X = Q_A Y Q_B^T (Alg. 4.1) or Z_A^T Y Z_B (Alg. 4.2), then the residual
+    // against the original coefficients
+    gemm<double, double, double, double>(s, inv ? 1 : 0, 0, m, n, m, 1.0, q.QA, m, q.Y, m, 0.0, q.W, m);
+    gemm<double, double, double, double>(s, 0, inv ? 0 : 1, m, n, n, 1.0, q.W, m, q.QB, n, 0.0, X, ldx);
     residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr);
     double hr[32];
     hipError_t e = read_scalars(s, c, p.scal, 32, hr);
@@ -734,7 +783,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
         return -(ci + 4);
     if (autosel && !selector_installed()) return -(ci + 4);
     if (!(o.tol >= 0.0) || o.max_iter < 0) return -(ci + 4);
-    if (o.alg != SYLV_ALG_ORIG && o.alg != SYLV_ALG_ORTH) return -(ci + 4);
+    if (o.alg != SYLV_ALG_ORIG && o.alg != SYLV_ALG_ORTH && o.alg != SYLV_ALG_INV) return -(ci + 4);
     if (info) std::memset(info, 0, sizeof(*info));
     if (m == 0 || n == 0) {
         if (info) {
@@ -751,7 +800,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool need_hi = !mixed || o.fallback || autosel;
     const bool orth = mixed && (o.orth_check || autosel);
-    const bool alg41 = mixed && !autosel && o.alg == SYLV_ALG_ORTH;
+    const bool alg41 = mixed && !autosel && (o.alg == SYLV_ALG_ORTH || o.alg == SYLV_ALG_INV);
     const size_t need = plan_bytes(m, n, lyap, mixed, need_hi, orth, alg41);
     void *base = work;
     if (work) {
@@ -775,7 +824,9 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     if (!mixed) return run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, info);
     if (autosel) return run_auto(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info);
     int ok = 0;
-    if (alg41) rc = run_alg41(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
+    if (alg41)
+        rc = run_alg41(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok,
+                       o.alg == SYLV_ALG_INV);
     else rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
     if (rc) return rc;
     int escalated = 0, iters = info ? info->iterations : 0;
@@ -849,7 +900,8 @@ size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool autosel = o.low == SYLV_PREC_AUTO;
     return plan_bytes(m, n, lyap != 0, mixed, !mixed || o.fallback || autosel,
-                      mixed && (o.orth_check || autosel), mixed && !autosel && o.alg == SYLV_ALG_ORTH);
+                      mixed && (o.orth_check || autosel),
+                      mixed && !autosel && (o.alg == SYLV_ALG_ORTH || o.alg == SYLV_ALG_INV));
 }
 
 int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, int aed_waves,

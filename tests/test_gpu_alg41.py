@@ -1,6 +1,7 @@
-"""Alg. 4.1 of the paper (SYLV_ALG_ORTH): binary64-orthonormalised Schur
-vectors, triangular-basis coefficients and the stationary iteration of
-Alg. 3.1 with binary64 tri-solves, against the FP64 oracle and against the
+"""Algs. 4.1 (SYLV_ALG_ORTH: binary64-orthonormalised Schur vectors) and 4.2
+(SYLV_ALG_INV: the low-precision Schur vectors with binary64 inverses) of the
+paper -- triangular-basis coefficients and the stationary iteration of
+Alg. 3.1 with binary64 tri-solves -- against the FP64 oracle and against the
 original-basis refinement on the same equations."""
 import numpy as np
 import pytest
@@ -20,10 +21,11 @@ def kron_cond(A, B):
     return np.linalg.cond(np.kron(np.eye(n), A) + np.kron(B.T, np.eye(m)))
 
 
-def test_alg41_config1():
+@pytest.mark.parametrize("alg", ["orth", "inv"])
+def test_alg41_config1(alg):
     sy = binding()
     A, B, C = workloads.config1()
-    X, info = sy.solve(dev(A), dev(B), dev(C), alg="orth")
+    X, info = sy.solve(dev(A), dev(B), dev(C), alg=alg)
     torch.cuda.synchronize()
     say("alg41 config1", info)
     assert info["status"] == 0 and info["fell_back"] == 0 and info["rel_res"] <= TOL, info
@@ -32,15 +34,16 @@ def test_alg41_config1():
     assert relerr(host(X), Xo) <= 100 * U64 * kron_cond(A, B)
 
 
+@pytest.mark.parametrize("alg", ["orth", "inv"])
 @pytest.mark.parametrize("low", ["fp32", "bf16"])
 @pytest.mark.parametrize("m,n", [(1, 1), (2, 7), (33, 17), (150, 90), (301, 257)])
-def test_alg41_shapes(low, m, n):
+def test_alg41_shapes(alg, low, m, n):
     sy = binding()
     A, B, C = workloads.sylv_random(700 + m + n, m, n, scale=0.5 / np.sqrt(max(m, n)))
-    X, info = sy.solve(dev(A), dev(B), dev(C), alg="orth", low=low)
+    X, info = sy.solve(dev(A), dev(B), dev(C), alg=alg, low=low)
     X2, info2 = sy.solve(dev(A), dev(B), dev(C), alg="orig", low=low)
     torch.cuda.synchronize()
-    say("alg41", low, m, n, info["iterations"], info2["iterations"], info["rel_res"])
+    say("alg4x", alg, low, m, n, info["iterations"], info2["iterations"], info["rel_res"])
     assert info["rel_res"] <= TOL and info["fell_back"] == 0, info
     Xo, _ = oracle.bs_solve(A, B, C)
     kap = kron_cond(A, B) if m * n <= 2500 else 10.0
@@ -48,11 +51,12 @@ def test_alg41_shapes(low, m, n):
     assert relerr(host(X), host(X2)) <= 200 * U64 * kap * max(1.0, np.sqrt(m + n) / 8)
 
 
+@pytest.mark.parametrize("alg", ["orth", "inv"])
 @pytest.mark.parametrize("n", [16, 100, 256])
-def test_alg41_lyapunov(n):
+def test_alg41_lyapunov(alg, n):
     sy = binding()
     A, C, eig = workloads.config4_item(n + 3, n)
-    X, info = sy.lyap(dev(A), dev(C), alg="orth")
+    X, info = sy.lyap(dev(A), dev(C), alg=alg)
     torch.cuda.synchronize()
     assert info["rel_res"] <= TOL and info["fell_back"] == 0, info
     Xo, _ = oracle.lyap_solve(A, C)
@@ -63,12 +67,13 @@ def test_alg41_lyapunov(n):
     assert np.linalg.norm(Xg - Xg.T) <= 100 * U64 * kap * np.linalg.norm(Xg)
 
 
-def test_alg41_small_sep():
+@pytest.mark.parametrize("alg", ["orth", "inv"])
+def test_alg41_small_sep(alg):
     """sep = 1e-3 (kappa ~ 1e4): the triangular-basis iteration still reaches
     the binary64 residual level."""
     sy = binding()
     cfg = workloads.config3(2, m=300, n=200)
-    X, info = sy.solve(dev(cfg["A"]), dev(cfg["B"]), dev(cfg["C"]), alg="orth")
+    X, info = sy.solve(dev(cfg["A"]), dev(cfg["B"]), dev(cfg["C"]), alg=alg)
     torch.cuda.synchronize()
     say("alg41 small sep", info)
     assert info["rel_res"] <= TOL and info["fell_back"] == 0, info
