@@ -116,6 +116,26 @@ SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T 
     return flag;
 }
 
+// The 2 x 2 case of the block-pair system (one block of order 2, the other
+// of order 1): the same partial-pivoting elimination as the 4 x 4 embedding
+// restricted to its two live rows (the identity rows never pivot), with the
+// same smin rule, in straight-line code.
+template <typename T>
+SYLV_DEVINL int pair2_solve(T m00, T m01, T m10, T m11, T &r0, T &r1, T smin) {
+    int flag = 0;
+    const bool sw = fabs(m10) > fabs(m00);
+    T p00 = sw ? m10 : m00, p01 = sw ? m11 : m01, q0 = sw ? r1 : r0;
+    const T o10 = sw ? m00 : m10, o11 = sw ? m01 : m11, q1 = sw ? r0 : r1;
+    if (fabs(p00) < smin) { p00 = (p00 >= T(0)) ? smin : -smin; flag = 1; }
+    const T f = o10 * (T(1) / p00);
+    T u11 = o11 - f * p01;
+    const T s1 = q1 - f * q0;
+    if (fabs(u11) < smin) { u11 = (u11 >= T(0)) ? smin : -smin; flag = 1; }
+    r1 = s1 / u11;
+    r0 = (q0 - p01 * r1) / p00;
+    return flag;
+}
+
 // One tile (I, J) of Y: off-diagonal updates, then the in-LDS solve.
 template <typename T>
 SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, const T *__restrict__ TB,
@@ -292,7 +312,9 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
                 r[1] = P ? sC[cj * TLD + ri + 1] - part[1] : T(0);
                 r[2] = Q ? sC[(cj + 1) * TLD + ri] - part[2] : T(0);
                 r[3] = (P && Q) ? sC[(cj + 1) * TLD + ri + 1] - part[3] : T(0);
-                myflag |= pair_solve<T>(P, Q, a00, a01, a10, a11, b00, b01, b10, b11, r, smin);
+                if (P && Q) myflag |= pair_solve<T>(P, Q, a00, a01, a10, a11, b00, b01, b10, b11, r, smin);
+                else if (P) myflag |= pair2_solve<T>(a00 + b00, a01, a10, a11 + b00, r[0], r[1], smin);
+                else myflag |= pair2_solve<T>(a00 + b00, b10, b01, a00 + b11, r[0], r[2], smin);
                 sC[cj * TLD + ri] = r[0];
                 if (P) sC[cj * TLD + ri + 1] = r[1];
                 if (Q) sC[(cj + 1) * TLD + ri] = r[2];
