@@ -230,14 +230,29 @@ int orc_hqr(int n, double *H, int ldh, double *U, int ldu)
             h21 = s;
             h22 = h11;
         }
-        double tr = h11 + h22;
-        double det = h11 * h22 - h12 * h21;
-        /* first column of (H - s1 I)(H - s2 I), restricted to rows l..l+2 */
+        /* the two shifts: eigenvalues of the trailing 2x2, s1,2 = re +- r
+         * (real pair) or re +- i im (complex pair) */
+        double hp = 0.5 * (h11 - h22), disc = hp * hp + h12 * h21;
+        int cplx = disc < 0.0;
+        double sre = h22 + hp, srad = sqrt(fabs(disc));
+        double s1 = sre + srad, s2 = sre - srad;
+        /* first column of (H - s1 I)(H - s2 I), restricted to rows l..l+2,
+         * formed from the differences a00 - s and a11 - s (no trace and
+         * determinant): near a cluster of equal eigenvalues those
+         * differences are exact while the expanded polynomial cancels to
+         * rounding noise and the iteration would stagnate */
         double a00 = E(H, l, l, ldh), a01 = E(H, l, l + 1, ldh);
         double a10 = E(H, l + 1, l, ldh), a11 = E(H, l + 1, l + 1, ldh);
         double a21 = E(H, l + 2, l + 1, ldh);
-        double x = a00 * a00 + a01 * a10 - tr * a00 + det;
-        double y = a10 * (a00 + a11 - tr);
+        double x, y;
+        if (cplx) {
+            double d0 = a00 - sre;
+            x = d0 * d0 + srad * srad + a01 * a10;
+            y = a10 * (d0 + (a11 - sre));
+        } else {
+            x = (a00 - s1) * (a00 - s2) + a01 * a10;
+            y = a10 * ((a00 - s1) + (a11 - s2));
+        }
         double z = a10 * a21;
         for (int k = l; k <= ihi - 1; ++k) {
             int len = (k <= ihi - 2) ? 3 : 2;

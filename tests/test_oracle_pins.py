@@ -203,6 +203,58 @@ def test_jacobi_eigs_match_library():
     assert np.linalg.norm(S - V @ np.diag(d) @ V.T) < 1e-13 * np.linalg.norm(S)
 
 
+def test_jacobi_closed_form_tridiagonal_toeplitz():
+    """tridiag(-1, 2, -1) of order n has eigenvalues 2 - 2 cos(k pi/(n+1))
+    and eigenvectors sin(i k pi/(n+1)) (a textbook closed form)."""
+    for n in (1, 2, 7, 30):
+        S = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+        d, V = oracle.sym_eig(S)
+        k = np.arange(1, n + 1)
+        lam = np.sort(2 - 2 * np.cos(k * np.pi / (n + 1)))
+        assert np.abs(np.sort(d) - lam).max() <= 1e-14 * 4
+        i = np.argsort(d)[0]
+        v = np.sin(np.arange(1, n + 1) * np.pi / (n + 1))
+        v /= np.linalg.norm(v)
+        assert abs(abs(V[:, i] @ v) - 1) <= 1e-13
+
+
+def test_jacobi_closed_form_2x2_and_rank_one():
+    a, b, c = 3.0, 1.5, -2.0
+    d, V = oracle.sym_eig(np.array([[a, b], [b, c]]))
+    mid, rad = (a + c) / 2, np.hypot((a - c) / 2, b)
+    assert np.allclose(np.sort(d), [mid - rad, mid + rad], rtol=0, atol=1e-15 * 8)
+    # I + v v^T: eigenvalue 1 (multiplicity n-1) and 1 + |v|^2 with vector v
+    rs = np.random.RandomState(21)
+    v = rs.standard_normal(9)
+    d, V = oracle.sym_eig(np.eye(9) + np.outer(v, v))
+    ds = np.sort(d)
+    assert np.abs(ds[:-1] - 1).max() <= 1e-14 * 20 and abs(ds[-1] - (1 + v @ v)) <= 1e-13 * (1 + v @ v)
+    i = np.argmax(d)
+    assert abs(abs(V[:, i] @ v) / np.linalg.norm(v) - 1) <= 1e-13
+
+
+def test_symmetric_route_closed_form_diagonal():
+    """Diagonal A, B: X_ij = C_ij / (a_i + b_j) exactly (up to one rounding)."""
+    rs = np.random.RandomState(22)
+    a, b = rs.uniform(0.5, 5, 11), rs.uniform(0.5, 5, 6)
+    C = rs.standard_normal((11, 6))
+    X = oracle.sym_solve(np.diag(a), np.diag(b), C)
+    assert np.abs(X - C / (a[:, None] + b[None, :])).max() <= 4 * U * np.abs(X).max()
+
+
+def test_symmetric_route_planted_spectrum():
+    """A = Q_A diag(la) Q_A^T, B likewise: X = Q_A ((Q_A^T C Q_B) / (la_i + lb_j)) Q_B^T
+    from the planted factors agrees with the oracle's own eigen-decompositions."""
+    A, la, QA = workloads.sym_coeff(23, 40, repeated=5)
+    B, lb, QB = workloads.sym_coeff(24, 25)
+    C = np.random.RandomState(25).standard_normal((40, 25))
+    Xp = QA @ ((QA.T @ C @ QB) / (la[:, None] + lb[None, :])) @ QB.T
+    X = oracle.sym_solve(A, B, C)
+    assert relerr(X, Xp) <= 1e3 * U
+    d, V = oracle.sym_eig(A)
+    assert np.abs(np.sort(d) - np.sort(la)).max() <= 1e3 * U
+
+
 # ------------------------------------------------ P4 Lyapunov invariants
 
 def test_lyapunov_symmetry_and_psd():
@@ -277,6 +329,17 @@ def test_schur_invariants_constructed_spectrum():
     T, Uq, st = oracle.schur(A)
     assert st == 0
     check_schur(A, T, Uq, eig_true=ea)
+
+
+@pytest.mark.parametrize("rep", [5, 13, 20])
+def test_schur_repeated_eigenvalue_cluster(rep):
+    """A symmetric matrix whose spectrum holds `rep` copies of one value:
+    the QR iteration must still converge (no cap), with backward error and
+    orthogonality at the n u level and the planted spectrum recovered."""
+    A, lam, _ = workloads.sym_coeff(641, 40, repeated=rep)
+    T, Uq, st = oracle.schur(A)
+    assert st == 0
+    check_schur(A, T, Uq, eig_true=lam)
 
 
 def test_hessenberg_invariants():

@@ -21,6 +21,9 @@ Recipes (readings of the workload descriptions are marked in the design doc):
   min |lambda_i(A) + mu_j(B)| = delta exactly.
 * ``config4``  batched Lyapunov, sizes U{16..256}, Re(eig) in U[-5, -0.1],
   30% complex pairs, C = -B B^T with B n x 4 Gaussian.
+* ``sym_coeff``  symmetric Q diag(lam) Q^T, Q Haar, lam ~ U[lo, hi] (the
+  real-part range of ``config2``), optionally with a repeated eigenvalue;
+  ``config_sym`` m=n=2048, lam in U[0.5, 5], seeds 12 (A), 13 (B), 14 (C).
 """
 from __future__ import annotations
 
@@ -29,7 +32,7 @@ import numpy as np
 __all__ = [
     "haar_orthogonal", "block_spectrum", "normal_coeff", "config1", "config2",
     "config3", "config4_sizes", "config4_item", "sylv_random", "manufactured",
-    "config2_nonnormal",
+    "config2_nonnormal", "sym_coeff", "config_sym",
 ]
 
 
@@ -215,3 +218,27 @@ def selector_instance(i: int, lo: int = 32, hi: int = 1024, seed_base: int = 200
     B, eb, _, _ = normal_coeff(s + 2, n, 0.5, 5.0, planted=0.5)
     C = np.random.RandomState(s + 3).standard_normal((m, n))
     return dict(A=A, B=B, C=_f(C), delta=delta, lyap=False, eigA=ea, eigB=eb)
+
+
+def sym_coeff(seed, n, lo=0.5, hi=5.0, repeated=0, rep_value=None):
+    """Symmetric A = Q diag(lam) Q^T, Q Haar, lam ~ U[lo, hi] in random
+    order; the first ``repeated`` entries of lam equal ``rep_value`` (default
+    the middle of the range), a cluster of identical eigenvalues.  A is
+    symmetrised exactly ((A + A^T)/2).  Returns (A, lam, Q)."""
+    rs = np.random.RandomState(seed)
+    lam = rs.uniform(lo, hi, n)
+    if repeated:
+        lam[:repeated] = 0.5 * (lo + hi) if rep_value is None else rep_value
+    Q = haar_orthogonal(rs, n)
+    A = (Q * lam[None, :]) @ Q.T
+    A = 0.5 * (A + A.T)
+    return _f(A), lam, _f(Q)
+
+
+def config_sym(m: int = 2048, n: int = 2048, seeds=(12, 13, 14)):
+    """Symmetric-coefficient Sylvester workload: A, B from ``sym_coeff`` with
+    eigenvalues U[0.5, 5], C ~ N(0, 1)."""
+    A, la, QA = sym_coeff(seeds[0], m)
+    B, lb, QB = sym_coeff(seeds[1], n)
+    C = np.random.RandomState(seeds[2]).standard_normal((m, n))
+    return dict(A=A, B=B, C=_f(C), eigA=la, eigB=lb, QA=QA, QB=QB)
