@@ -68,6 +68,51 @@ SYLV_DEVINL void reflector3(int len, T x, T y, T z, T &v1, T &v2, T &tau, T &bet
     beta = b;
 }
 
+// First column (x, y, z) of (H - s1 I)(H - s2 I) e1 for the leading 3x2
+// corner a00 a01 / a10 a11 / . a21 of an unreduced Hessenberg block, up to a
+// positive scale.  The shifts are a real pair (cplx = 0: s1 = p, s2 = q) or
+// a complex pair p +- i q (cplx = 1).  Formed from the differences a00 - s
+// rather than from trace and determinant: near a cluster of equal
+// eigenvalues those differences are exact while the expanded polynomial
+// cancels to rounding noise and the QR iteration stagnates.
+template <typename T>
+SYLV_DEVINL void shift_column(T a00, T a01, T a10, T a11, T a21, T p, T q, bool cplx, T &x, T &y, T &z) {
+    if (cplx) {
+        const T d0 = a00 - p;
+        T sc = fabs(d0) + fabs(q) + fabs(a10);
+        if (sc == T(0)) sc = T(1);
+        const T h = a10 / sc;
+        x = h * a01 + d0 * (d0 / sc) + q * (q / sc);
+        y = h * (d0 + (a11 - p));
+        z = h * a21;
+    } else {
+        const T d1 = a00 - p, d2 = a00 - q;
+        T sc = fabs(d2) + fabs(a10);
+        if (sc == T(0)) sc = T(1);
+        const T h = a10 / sc;
+        x = h * a01 + d1 * (d2 / sc);
+        y = h * (d1 + (a11 - q));
+        z = h * a21;
+    }
+}
+
+// Eigenvalues of [[h11, h12], [h21, h22]] as a shift pair for shift_column.
+template <typename T>
+SYLV_DEVINL void shift_pair(T h11, T h12, T h21, T h22, T &p, T &q, bool &cplx) {
+    const T hp = T(0.5) * (h11 - h22), bc = h12 * h21, disc = hp * hp + bc;
+    if (disc >= T(0)) {
+        const T r = sqrt(disc);
+        const T w = hp + ((hp >= T(0)) ? r : -r);
+        p = h22 + w;
+        q = (w != T(0)) ? h22 - bc / w : h22;
+        cplx = false;
+    } else {
+        p = h22 + hp;
+        q = sqrt(-disc);
+        cplx = true;
+    }
+}
+
 }  // namespace sylv
 
 // ABI error codes (mirrors include/sylv.h)

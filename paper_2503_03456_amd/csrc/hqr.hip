@@ -126,19 +126,13 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
             h21 = s;
             h22 = h11;
         }
-        const T tr = h11 + h22, det = h11 * h22 - h12 * h21;
         T x, y, z;
         {
-            T a00 = CM(H, l, l, ldh), a01 = CM(H, l, l + 1, ldh), a10 = CM(H, l + 1, l, ldh);
-            T a11 = CM(H, l + 1, l + 1, ldh), a21 = CM(H, l + 2, l + 1, ldh);
-            // scale to avoid overflow in the shift polynomial
-            T sc = fabs(a00) + fabs(a10) + fabs(a01) + fabs(a11) + fabs(a21) + fabs(tr) + sqrt(fabs(det));
-            if (sc == T(0)) sc = T(1);
-            T b00 = a00 / sc, b01 = a01 / sc, b10 = a10 / sc, b11 = a11 / sc, b21 = a21 / sc;
-            T trs = tr / sc, dets = det / (sc * sc);
-            x = b00 * b00 + b01 * b10 - trs * b00 + dets;
-            y = b10 * (b00 + b11 - trs);
-            z = b10 * b21;
+            T sp, sq;
+            bool cplx;
+            shift_pair(h11, h12, h21, h22, sp, sq, cplx);
+            shift_column(CM(H, l, l, ldh), CM(H, l, l + 1, ldh), CM(H, l + 1, l, ldh), CM(H, l + 1, l + 1, ldh),
+                         CM(H, l + 2, l + 1, ldh), sp, sq, cplx, x, y, z);
         }
         __syncthreads();
         // The column a step reduces (k-1) is read by every thread at the top
@@ -516,17 +510,8 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
             int len = (p <= N - 3) ? 3 : 2;
             T x, y, z;
             if (p == 0) {
-                T tr = trd[2 * b], det = trd[2 * b + 1];
-                T a00 = Hw[q * L + q], a01 = Hw[(q + 1) * L + q], a10 = Hw[q * L + q + 1];
-                T a11 = Hw[(q + 1) * L + q + 1], a21 = Hw[(q + 1) * L + q + 2];
-                T sc = fabs(a00) + fabs(a10) + fabs(a01) + fabs(a11) + fabs(a21) + fabs(tr) + sqrt(fabs(det));
-                if (sc == T(0)) sc = T(1);
-                T rs = T(1) / sc;
-                T b00 = a00 * rs, b01 = a01 * rs, b10 = a10 * rs, b11 = a11 * rs, b21 = a21 * rs;
-                T trs = tr * rs, dets = det * rs * rs;
-                x = b00 * b00 + b01 * b10 - trs * b00 + dets;
-                y = b10 * (b00 + b11 - trs);
-                z = b10 * b21;
+                shift_column(Hw[q * L + q], Hw[(q + 1) * L + q], Hw[q * L + q + 1], Hw[(q + 1) * L + q + 1],
+                             Hw[(q + 1) * L + q + 2], trd[3 * b], trd[3 * b + 1], trd[3 * b + 2] != T(0), x, y, z);
             } else {
                 x = Hw[(q - 1) * L + q];
                 y = Hw[(q - 1) * L + q + 1];

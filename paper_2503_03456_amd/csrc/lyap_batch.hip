@@ -403,19 +403,13 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
             h21 = sx;
             h22 = h11;
         }
-        const float tr = h11 + h22, det = h11 * h22 - h12 * h21;
         float x, y, z;
         {
-            float a00 = HB(l, l), a01 = HB(l, l + 1), a10 = HB(l + 1, l);
-            float a11 = HB(l + 1, l + 1), a21 = HB(l + 2, l + 1);
-            float sc = fabsf(a00) + fabsf(a10) + fabsf(a01) + fabsf(a11) + fabsf(a21) + fabsf(tr) + sqrtf(fabsf(det));
-            if (sc == 0.f) sc = 1.f;
-            const float rs = frcp(sc);
-            float b00 = a00 * rs, b01 = a01 * rs, b10 = a10 * rs, b11 = a11 * rs, b21 = a21 * rs;
-            float trs = tr * rs, dets = det * rs * rs;
-            x = b00 * b00 + b01 * b10 - trs * b00 + dets;
-            y = b10 * (b00 + b11 - trs);
-            z = b10 * b21;
+            float sp, sq;
+            bool cplx;
+            shift_pair(h11, h12, h21, h22, sp, sq, cplx);
+            shift_column(HB(l, l), HB(l, l + 1), HB(l + 1, l), HB(l + 1, l + 1), HB(l + 2, l + 1), sp, sq, cplx, x,
+                         y, z);
         }
         __syncthreads();
         // The column a step reduces (k-1) is read by every thread at the top

@@ -17,6 +17,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "schur.hpp"
+
+#include <array>
 #include "prof.hpp"
 
 #include <vector>
@@ -73,7 +75,7 @@ size_t schur_work_bytes(int n) {
     const int wmax = K::WMAX;
     const int wide = std::max(wmax, K::NSMALL);
     size_t e = hessenberg_work_elems<T>(n, K::HNB, K::HS) + (size_t)K::NSMALL * K::NSMALL +
-               (size_t)wmax * wmax + (size_t)wide * n + 2 * (size_t)K::NSMALL + 2 * K::NBMAX + 64;
+               (size_t)wmax * wmax + (size_t)wide * n + 2 * (size_t)K::NSMALL + 3 * K::NBMAX + 64;
     return e * sizeof(T) + 1024 + 64 * sizeof(int);
 }
 template size_t schur_work_bytes<float>(int);
@@ -108,7 +110,7 @@ void carve(Ctx<T> &c, char *ws) {
     c.tmp = p; p += (size_t)wide * n;
     c.wr = p; p += K::NSMALL;
     c.wi = p; p += K::NSMALL;
-    c.trd = p; p += 2 * K::NBMAX + 64;
+    c.trd = p; p += 3 * K::NBMAX + 64;
     size_t off = reinterpret_cast<char *>(p) - ws;
     off = (off + 255) & ~(size_t)255;
     c.dint = reinterpret_cast<int *>(ws + off);
@@ -143,8 +145,8 @@ void apply_window(Ctx<T> &c, int w0, int w, const T *Z) {
     cast<T, T>(c.s, n, w, c.tmp, n, ub, c.ldu, T(1));
 }
 
-// Pair shifts (wr[i] + i wi[i]) into bulges: a complex pair -> (2 re, |s|^2);
-// two reals -> (s1 + s2, s1 s2).  Returns the (trace, det) list.
+// Pair shifts (wr[i] + i wi[i]) into bulges, three entries per bulge: a
+// complex pair -> (re, |im|, 1); two reals -> (s1, s2, 0).
 template <typename T>
 void pair_shifts(const std::vector<double> &wr, const std::vector<double> &wi, int maxb,
                  std::vector<T> &trd) {
@@ -152,24 +154,25 @@ void pair_shifts(const std::vector<double> &wr, const std::vector<double> &wi, i
     std::vector<double> reals;
     // walk from the bottom (last entries are closest to kbot)
     int i = (int)wr.size() - 1;
-    std::vector<std::pair<double, double>> bul;
+    std::vector<std::array<double, 3>> bul;
     while (i >= 0 && (int)bul.size() < maxb) {
         if (wi[i] != 0.0 && i >= 1 && wi[i - 1] != 0.0) {
-            bul.push_back({2.0 * wr[i], wr[i] * wr[i] + wi[i] * wi[i]});
+            bul.push_back({wr[i], std::fabs(wi[i]), 1.0});
             i -= 2;
         } else if (wi[i] != 0.0) {
             i -= 1;  // orphan half of a pair (cut window): skip
         } else {
             reals.push_back(wr[i]);
             if (reals.size() == 2) {
-                bul.push_back({reals[0] + reals[1], reals[0] * reals[1]});
+                bul.push_back({reals[0], reals[1], 0.0});
                 reals.clear();
             }
             i -= 1;
         }
     }
     // the bulge introduced first should carry the shifts closest to the bottom
-    for (auto &b : bul) { trd.push_back((T)b.first); trd.push_back((T)b.second); }
+    for (auto &b : bul)
+        for (int k = 0; k < 3; ++k) trd.push_back((T)b[k]);
 }
 
 }  // namespace
@@ -261,24 +264,28 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
             if ((err = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
             const T *hv = reinterpret_cast<const T *>(c.hbuf);
             trd.clear();
-            for (int q = m - 1; q >= 1 && (int)trd.size() < 2 * maxb; q -= 2) {
+            // exceptional pair aa +- i sqrt(0.4375) ss (the eigenvalues of
+            // [[aa, -0.4375 ss], [ss, aa]])
+            for (int q = m - 1; q >= 1 && (int)trd.size() < 3 * maxb; q -= 2) {
                 double sub_i = std::fabs((double)hv[2 * q + 1]);
                 double sub_im1 = std::fabs((double)hv[2 * (q - 1) + 1]);
                 double ss = sub_i + sub_im1;
                 double aa = 0.75 * ss + (double)hv[2 * q];
-                trd.push_back((T)(2.0 * aa));
-                trd.push_back((T)(aa * aa + 0.4375 * ss * ss));
+                trd.push_back((T)aa);
+                trd.push_back((T)(std::sqrt(0.4375) * ss));
+                trd.push_back(T(1));
             }
             if (trd.empty()) {
                 double ss = std::fabs((double)hv[2 * m]);
                 double aa = 0.75 * ss + (double)hv[2 * (m - 1)];
-                trd.push_back((T)(2.0 * aa));
-                trd.push_back((T)(aa * aa + 0.4375 * ss * ss));
+                trd.push_back((T)aa);
+                trd.push_back((T)(std::sqrt(0.4375) * ss));
+                trd.push_back(T(1));
             }
         } else {
             pair_shifts<T>(wr, wi, maxb, trd);
         }
-        const int nb = (int)trd.size() / 2;
+        const int nb = (int)trd.size() / 3;
         if (nb == 0) continue;
         T *htrd = reinterpret_cast<T *>(c.hbuf + 4096);
         for (size_t q = 0; q < trd.size(); ++q) htrd[q] = trd[q];
