@@ -75,13 +75,21 @@ typedef struct {
                           residual C - AX - XB, low-precision corrections); SYLV_ALG_ORTH: Alg. 4.1
                           (binary64-orthonormalised Schur vectors, Alg. 3.1 in the triangular basis
                           with binary64 tri-solves); SYLV_ALG_INV: Alg. 4.2 (the low-precision
-                          Schur vectors with their binary64 inverses, same iteration); ignored by
-                          SYLV_PREC_FP64 and AUTO                                               */
+                          Schur vectors with their binary64 inverses, same iteration);
+                          SYLV_ALG_SYM: symmetric coefficients (Sec. 2.2.2, Hermitian case):
+                          A = Q_A D_A Q_A^T and B = Q_B D_B Q_B^T by block Jacobi in the
+                          precision `low` (FP64: plain binary64, no refinement), the
+                          transformed equation solved elementwise, Y_ij = C~_ij / (d_i + e_j),
+                          and the original-basis refinement; A and B must be symmetric to
+                          ||A - A^T||_F <= 2^-26 ||A||_F (else -i for that argument); the
+                          fallback is the general binary64 path.  ORTH/INV/SYM are
+                          ignored by AUTO; ORTH/INV by FP64                                    */
 } sylv_opts;
 
 #define SYLV_ALG_ORIG 0
 #define SYLV_ALG_ORTH 1
 #define SYLV_ALG_INV  2
+#define SYLV_ALG_SYM  3
 
 typedef struct {
     double rel_res;     /* eq. (2.1) at exit, binary64, Frobenius norms                         */
@@ -195,6 +203,17 @@ const char *sylv_status_string(int code);
 int sylv_schur(int n, const void *A, int lda, void *T, int ldt, void *U, int ldu,
                int prec, int *status, void *stream);
 
+/* Symmetric eigen-decomposition S = Q diag(d) Q^T of the symmetric part
+ * (S + S^T)/2 of S (n x n, lds, read only) -- the factorisation of the
+ * symmetric-coefficient variant (Sec. 2.2.2) -- by two-sided block Jacobi
+ * with a round-robin parallel ordering (Golub & Van Loan Sec. 8.5).  d
+ * (device, n) receives the eigenvalues in no particular order, Q (ldq) the
+ * orthonormal eigenvectors (column i belongs to d[i]).  Element type per
+ * prec.  *sweeps (host, may be NULL): block sweeps taken; *status (host, may
+ * be NULL): SYLV_OK, or SYLV_ST_QR_FAILED if the sweep cap (60) ran out. */
+int sylv_sym_eig(int n, const void *S, int lds, void *d, void *Q, int ldq, int prec,
+                 int *sweeps, int *status, void *stream);
+
 /* Quasi-triangular equation TA Y + Y op(TB) = C (the Bartels-Stewart
  * substitution of Sec. 2.2.1): TA m x m and TB n x n upper quasi-triangular;
  * op(TB) = TB (trans_b = 0) or TB^T (trans_b = 1, the Lyapunov case).  C
@@ -269,7 +288,8 @@ int sylv_selector_features(int m, int n, const double *A, int lda, const double 
  * Per-kernel timing (for roofline measurements).  sylv_profile_begin arms
  * one kernel family (ids: 1 gemm_kernel, 2 k_hess_col, 3 k_hess_gemv,
  * 4 k_aed, 5 k_chase, 6 k_trsyl_diag, 7 k_find_ktop, 8 k_cast,
- * 9 k_sumsq_partial); each later launch of that family is bracketed by two
+ * 9 k_sumsq_partial, 10 k_bhess, 11 k_bschur, 12 k_btrsyl,
+ * 13 gemm_batched_kernel, 14 k_jac_pairs, 15 k_jac_apply); each later launch of that family is bracketed by two
  * HIP events recorded on its launch stream.  sylv_profile_end disarms,
  * waits for the events and returns the number of launches and the summed
  * durations in milliseconds, plus the algorithmic work the library

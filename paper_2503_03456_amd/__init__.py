@@ -90,6 +90,8 @@ _lib.sylv_status_string.argtypes = [_i]
 _lib.sylv_status_string.restype = ctypes.c_char_p
 _lib.sylv_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _i, _i, _ip, _vp]
 _lib.sylv_schur.restype = _i
+_lib.sylv_sym_eig.argtypes = [_i, _vp, _i, _vp, _vp, _i, _i, _ip, _ip, _vp]
+_lib.sylv_sym_eig.restype = _i
 _lib.sylv_trsyl.argtypes = [_i, _i, _vp, _i, _vp, _i, _i, _vp, _i, _i, _ip, _vp]
 _lib.sylv_trsyl.restype = _i
 _lib.sylv_residual.argtypes = [_i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _dp, _vp]
@@ -140,7 +142,7 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-ALG = {"orig": 0, "orth": 1, "inv": 2}
+ALG = {"orig": 0, "orth": 1, "inv": 2, "sym": 3}
 
 
 def make_opts(low="fp32", tol=1e-14, max_iter=20, fallback=True, orth_check=True, alg="orig"):
@@ -256,6 +258,20 @@ def schur(A, stream=None):
                          _prec_of(A), ctypes.byref(st), _stream(stream))
     _check(rc, "sylv_schur")
     return T, U, st.value
+
+
+def sym_eig(S, stream=None):
+    """Symmetric eigen-decomposition on the GPU in S's precision (block
+    Jacobi on (S + S^T)/2): (d, Q, sweeps, status) with S = Q diag(d) Q^T."""
+    S = colmajor(S)
+    n = S.shape[0]
+    d = torch.empty(n, dtype=S.dtype, device=S.device)
+    Q = torch.empty((n, n), dtype=S.dtype, device=S.device).t()
+    sw, st = ctypes.c_int(0), ctypes.c_int(0)
+    rc = _lib.sylv_sym_eig(n, S.data_ptr(), _ld(S), d.data_ptr(), Q.data_ptr(), _ld(Q), _prec_of(S),
+                           ctypes.byref(sw), ctypes.byref(st), _stream(stream))
+    _check(rc, "sylv_sym_eig")
+    return d, Q, sw.value, st.value
 
 
 def trsyl(TA, TB, C, trans_b=False, stream=None):

@@ -98,6 +98,22 @@ void std2x2(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, int k);
 template <typename T>
 void clean_lower(hipStream_t s, int n, T *H, int ldh);
 
+// syevj.hip: symmetric eigen-decomposition (block Jacobi) and the
+// elementwise solve of the symmetric-coefficient variant
+template <typename T>
+size_t sym_eig_work_bytes(int n);
+template <typename T>
+int sym_eig(hipStream_t s, int n, T *S, int lds, T *Q, int ldq, char *ws, char *hbuf, int max_sweeps,
+            int *sweeps);
+template <typename TS, typename T>
+void sym_part(hipStream_t s, int n, const TS *A, int lda, T *D, int ldd);
+template <typename T>
+void diag_solve(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, T *Y, int ldy,
+                const double *maxab, int *flag);
+template <typename T>
+void get_diag(hipStream_t s, int n, const T *D, int ldd, T *d);
+void asym_norm(hipStream_t s, int n, const double *A, int lda, double *out, double *scratch);
+
 // trsyl.hip
 template <typename T>
 void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, T *C, int ldc,

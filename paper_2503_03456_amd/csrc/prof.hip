@@ -87,7 +87,8 @@ extern "C" const char *sylv_kernel_name(int kernel_id) {
     static const char *names[KID_COUNT] = {"none", "gemm_kernel", "k_hess_col", "k_hess_gemv",
                                            "k_aed", "k_chase", "k_trsyl_diag", "k_find_ktop",
                                            "k_cast", "k_sumsq_partial", "k_bhess", "k_bschur",
-                                           "k_btrsyl", "gemm_batched_kernel"};
+                                           "k_btrsyl", "gemm_batched_kernel", "k_jac_pairs",
+                                           "k_jac_apply"};
     if (kernel_id < 0 || kernel_id >= KID_COUNT) return "unknown";
     return names[kernel_id];
 }

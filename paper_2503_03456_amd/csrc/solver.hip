@@ -109,6 +109,7 @@ struct Stage {  // buffers of one precision's Bartels-Stewart pipeline
     T *TA, *UA, *TB, *UB, *W1, *Y;
     char *schur_ws;   // Schur workspace for A
     char *schur_ws2;  // Schur workspace for B (the two run concurrently)
+    int diag;         // symmetric coefficients: TA, TB diagonal (eigen-decompositions)
 };
 
 // Alg. 4.1 buffers (binary64): orthonormalised factors, the triangular-basis
@@ -157,8 +158,9 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
         p.lo.UB = a.take<float>((size_t)n * n);
         p.lo.W1 = a.take<float>((size_t)m * n);
         p.lo.Y = a.take<float>((size_t)m * n);
-        p.lo.schur_ws = a.take<char>(schur_work_bytes<float>(m));
-        if (!lyap) p.lo.schur_ws2 = a.take<char>(schur_work_bytes<float>(n));
+        p.lo.schur_ws = a.take<char>(std::max(schur_work_bytes<float>(m), sym_eig_work_bytes<float>(m)));
+        if (!lyap)
+            p.lo.schur_ws2 = a.take<char>(std::max(schur_work_bytes<float>(n), sym_eig_work_bytes<float>(n)));
     }
     if (need_hi) {
         p.hi.TA = a.take<double>((size_t)m * m);
@@ -167,8 +169,9 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
         p.hi.UB = a.take<double>((size_t)n * n);
         p.hi.W1 = a.take<double>((size_t)m * n);
         p.hi.Y = a.take<double>((size_t)m * n);
-        p.hi.schur_ws = a.take<char>(schur_work_bytes<double>(m));
-        if (!lyap) p.hi.schur_ws2 = a.take<char>(schur_work_bytes<double>(n));
+        p.hi.schur_ws = a.take<char>(std::max(schur_work_bytes<double>(m), sym_eig_work_bytes<double>(m)));
+        if (!lyap)
+            p.hi.schur_ws2 = a.take<char>(std::max(schur_work_bytes<double>(n), sym_eig_work_bytes<double>(n)));
     }
     p.R = a.take<double>((size_t)m * n);
     if (orth) p.G = a.take<double>((size_t)2 * mx * mx);
@@ -230,9 +233,22 @@ static void lyap_right_factor(hipStream_t s, int n, Stage<T> &st) {
     revcols<T, T>(s, n, n, st.UA, n, st.UB, n, T(1));
 }
 
+// Cap on the block-Jacobi sweeps of the symmetric eigen-decomposition.
+constexpr int kSymSweeps = 60;
+
+// Schur form of A into (Tm, Um); with sym, the eigen-decomposition of the
+// symmetric part of A (Tm diagonal).  *qr = 1 when the iteration cap ran out.
 template <typename T>
 static int schur_stage(hipStream_t s, int n, const double *A, int lda, T *Tm, T *Um, char *ws,
-                       char *hbuf, int *qr, int bf16) {
+                       char *hbuf, int *qr, int bf16, int sym = 0) {
+    if (sym) {
+        sym_part<double, T>(s, n, A, lda, Tm, n);
+        int sweeps = 0;
+        const int rc = sym_eig<T>(s, n, Tm, n, Um, n, ws, hbuf, kSymSweeps, &sweeps);
+        if (rc < 0) return rc;
+        *qr = rc;
+        return 0;
+    }
     cast<double, T>(s, n, n, A, lda, Tm, n, 1.0);
     return schur_run<T>(s, n, Tm, n, Um, n, ws, hbuf, qr, bf16);
 }
@@ -246,7 +262,7 @@ static int schur_pair(hipStream_t s, DevCtx *c, int m, int n, const double *A, i
                       const double *B, int ldb, bool lyap, Stage<T> &st, int *qa, int *qb,
                       int bf16 = 0) {
     if (lyap) {
-        int rc = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa, bf16);
+        int rc = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa, bf16, st.diag);
         if (!rc) lyap_right_factor<T>(s, m, st);
         return rc;
     }
@@ -256,9 +272,9 @@ static int schur_pair(hipStream_t s, DevCtx *c, int m, int n, const double *A, i
     int rcb = 0;
     std::thread tb([&]() {
         hipSetDevice(c->dev);
-        rcb = schur_stage<T>(c->s2, n, B, ldb, st.TB, st.UB, st.schur_ws2, c->hbuf2, qb, bf16);
+        rcb = schur_stage<T>(c->s2, n, B, ldb, st.TB, st.UB, st.schur_ws2, c->hbuf2, qb, bf16, st.diag);
     });
-    int rca = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa, bf16);
+    int rca = schur_stage<T>(s, m, A, lda, st.TA, st.UA, st.schur_ws, c->hbuf, qa, bf16, st.diag);
     tb.join();
     e = hipEventRecord(c->ev_out, c->s2);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_out, 0);
@@ -282,7 +298,8 @@ void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const doub
     gemm<float, double, float, float>(s, 1, 0, m, n, m, 1.0f, st.UA, m, Rin, ldr, 0.0f, st.W1, m, bscale,
                                       bf16);
     gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0f, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, bf16);
-    trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
+    if (st.diag) diag_solve<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
+    else trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
     gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0f, st.UA, m, st.Y, m, 0.0f, st.W1, m, 1.0f, bf16);
     gemm<float, float, double, float>(s, 0, 1, m, n, n, (float)(1.0 / bscale), st.W1, m, st.UB, n,
                                       accumulate ? 1.0f : 0.0f, X, ldx, 1.0f, bf16);
@@ -294,7 +311,8 @@ void correction<double>(hipStream_t s, int m, int n, Stage<double> &st, const do
                         int *flag, int) {
     gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0, st.W1, m, bscale);
     gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0, st.Y, m);
-    trsyl<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
+    if (st.diag) diag_solve<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
+    else trsyl<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
     gemm<double, double, double, double>(s, 0, 0, m, n, m, 1.0, st.UA, m, st.Y, m, 0.0, st.W1, m);
     gemm<double, double, double, double>(s, 0, 1, m, n, n, 1.0 / bscale, st.W1, m, st.UB, n,
                                          accumulate ? 1.0 : 0.0, X, ldx);
@@ -783,7 +801,8 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
         return -(ci + 4);
     if (autosel && !selector_installed()) return -(ci + 4);
     if (!(o.tol >= 0.0) || o.max_iter < 0) return -(ci + 4);
-    if (o.alg != SYLV_ALG_ORIG && o.alg != SYLV_ALG_ORTH && o.alg != SYLV_ALG_INV) return -(ci + 4);
+    if (o.alg != SYLV_ALG_ORIG && o.alg != SYLV_ALG_ORTH && o.alg != SYLV_ALG_INV && o.alg != SYLV_ALG_SYM)
+        return -(ci + 4);
     if (info) std::memset(info, 0, sizeof(*info));
     if (m == 0 || n == 0) {
         if (info) {
@@ -816,10 +835,24 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     matnorm<double>(s, m, m, A, lda, p.scal + 40, p.nscr, 0);
     if (!lyap) matnorm<double>(s, n, n, B, ldb, p.scal + 41, p.nscr, 0);
     matnorm<double>(s, m, n, C, ldc, p.scal + 42, p.nscr, 0);
-    double hn[3];
-    hipError_t e = read_scalars(s, c, p.scal + 40, 3, hn);
+    const bool sym = !autosel && o.alg == SYLV_ALG_SYM;
+    if (sym) {
+        asym_norm(s, m, A, lda, p.scal + 43, p.nscr);
+        if (!lyap) asym_norm(s, n, B, ldb, p.scal + 44, p.nscr);
+    }
+    double hn[5] = {0, 0, 0, 0, 0};
+    hipError_t e = read_scalars(s, c, p.scal + 40, sym ? 5 : 3, hn);
     if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
     Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2]};
+    if (sym) {
+        // symmetric coefficients are required up to rounding: ||A - A^T||_F
+        // <= sqrt(u) ||A||_F (u = 2^-53), below binary32 resolution
+        const double tol_sym = 1.4901161193847656e-08;
+        if (!(hn[3] <= tol_sym * hn[0])) return -ai;
+        if (!lyap && !(hn[4] <= tol_sym * hn[1])) return -5;
+    }
+    p.lo.diag = sym ? 1 : 0;
+    p.hi.diag = sym ? 1 : 0;
     if (info) info->chosen = -1;
     if (!mixed) return run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, info);
     if (autosel) return run_auto(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info);
@@ -846,6 +879,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     if (!ok && o.fallback) {
         sylv_info keep;
         if (info) keep = *info;
+        p.hi.diag = 0;  // the fallback is the general binary64 Bartels-Stewart
         rc = run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, info);
         if (rc) return rc;
         if (info) {
@@ -999,7 +1033,7 @@ const char *sylv_status_string(int code) {
         case SYLV_ST_PERTURBED: return "near-singular pivot perturbed in the quasi-triangular solve";
         case SYLV_ST_NOT_CONVERGED: return "refinement did not reach the tolerance";
         case SYLV_ST_NAN: return "NaN or Inf encountered";
-        case SYLV_ST_QR_FAILED: return "QR algorithm iteration cap reached";
+        case SYLV_ST_QR_FAILED: return "QR algorithm (or symmetric Jacobi) iteration cap reached";
         case SYLV_ERR_ALLOC: return "device allocation failed";
         case SYLV_ERR_NOGPU: return "no gfx950 device";
         default:
@@ -1055,6 +1089,49 @@ int sylv_schur(int n, const void *A, int lda, void *T, int ldt, void *U, int ldu
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
     if (status) *status = qr ? SYLV_ST_QR_FAILED : SYLV_OK;
+    return 0;
+}
+
+int sylv_sym_eig(int n, const void *S, int lds, void *d, void *Q, int ldq, int prec, int *sweeps,
+                 int *status, void *stream) {
+    if (n < 0) return -1;
+    if (lds < std::max(1, n)) return -3;
+    if (ldq < std::max(1, n)) return -6;
+    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -7;
+    if (n > 0 && (!S || !d || !Q)) return !S ? -2 : (!d ? -4 : -5);
+    if (sweeps) *sweeps = 0;
+    if (status) *status = 0;
+    if (n == 0) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx *c = nullptr;
+    int rc = device_ctx(&c);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool f = prec == SYLV_PREC_FP32;
+    const size_t es = f ? sizeof(float) : sizeof(double);
+    const size_t hb = ((size_t)n * n * es + 255) & ~(size_t)255;
+    const size_t bytes = hb + 256 + (f ? sym_eig_work_bytes<float>(n) : sym_eig_work_bytes<double>(n));
+    void *base;
+    rc = ensure_work(c, bytes, &base);
+    if (rc) return rc;
+    char *H = (char *)base;
+    char *ws = H + hb;
+    int sw = 0;
+    if (f) {
+        sym_part<float, float>(s, n, (const float *)S, lds, (float *)H, n);
+        rc = sym_eig<float>(s, n, (float *)H, n, (float *)Q, ldq, ws, c->hbuf, kSymSweeps, &sw);
+        if (rc >= 0) get_diag<float>(s, n, (const float *)H, n, (float *)d);
+    } else {
+        sym_part<double, double>(s, n, (const double *)S, lds, (double *)H, n);
+        rc = sym_eig<double>(s, n, (double *)H, n, (double *)Q, ldq, ws, c->hbuf, kSymSweeps, &sw);
+        if (rc >= 0) get_diag<double>(s, n, (const double *)H, n, (double *)d);
+    }
+    if (rc < 0) { (void)hipGetLastError(); return rc; }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    if (sweeps) *sweeps = sw;
+    if (status) *status = rc ? SYLV_ST_QR_FAILED : SYLV_OK;
     return 0;
 }
 
