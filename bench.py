@@ -34,7 +34,8 @@ TRAFFIC_BYTES = {"k_chase": (77.1 + 103.6) * 1024}
 
 KERNEL_IDS = {"gemm_kernel": 1, "k_hess_col": 2, "k_hess_gemv": 3, "k_aed": 4, "k_chase": 5,
               "k_trsyl_diag": 6, "k_find_ktop": 7, "k_cast": 8, "k_sumsq_partial": 9,
-              "k_bhess": 10, "k_bschur": 11, "k_btrsyl": 12, "gemm_batched_kernel": 13}
+              "k_bhess": 10, "k_bschur": 11, "k_btrsyl": 12, "gemm_batched_kernel": 13,
+              "k_jac_pairs": 14, "k_jac_apply": 15}
 
 
 def bs_flops(m, n, lyap=False):
@@ -49,8 +50,17 @@ def mixed_flops(m, n, k):
     return 25.0 * a + 5.0 * (k + 1) * b, 2.0 * (k + 1) * b
 
 
+def sym_flops(m, n):
+    """Symmetric-coefficient route (paper Sec. 2.2.2): eigen-decompositions
+    9(m^3+n^3), transforms and back-transform 4mn(m+n), elementwise solve."""
+    return 9.0 * (m ** 3 + n ** 3) + 4.0 * m * n * (m + n) + 2.0 * m * n
+
+
 def load_workload(name):
     import workloads
+    if name == "sym":
+        cfg = workloads.config_sym()
+        return cfg, "sylvester m=n=2048, symmetric A,B (eig U[0.5,5]), C~N(0,1)"
     if name == "c2":
         cfg = workloads.config2()
         return cfg, "sylvester m=n=2048, normal A,B (Re eig U[0.5,5], 30% complex pairs), C~N(0,1)"
@@ -76,6 +86,24 @@ def cpu_baseline(sample_n, target_m, target_n):
             "sample": (f"one oracle solve of the same recipe at m=n={sample_n} "
                        f"({dt:.2f} s, rel_res {rr:.1e}), scaled to m={target_m} n={target_n} "
                        f"by the 25(m^3+n^3)+5mn(m+n) flop model")}
+
+
+def cpu_baseline_sym(sample_n, target_m, target_n):
+    """Time the oracle's symmetric route (plain C cyclic Jacobi, binary64,
+    one thread) on the same recipe at a smaller size, scaled by the
+    Sec. 2.2.2 flop model."""
+    import oracle
+    import workloads
+    cfg = workloads.config_sym(m=sample_n, n=sample_n)
+    t0 = time.perf_counter()
+    X = oracle.sym_solve(cfg["A"], cfg["B"], cfg["C"])
+    dt = time.perf_counter() - t0
+    rr = oracle.rel_residual(cfg["A"], cfg["B"], cfg["C"], X)
+    scale = sym_flops(sample_n, sample_n) / sym_flops(target_m, target_n)
+    return {"value": (1.0 / dt) * scale, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one oracle symmetric-route solve of the same recipe at m=n={sample_n} "
+                       f"({dt:.2f} s, rel_res {rr:.1e}), scaled to m={target_m} n={target_n} "
+                       f"by the 9(m^3+n^3)+4mn(m+n) flop model")}
 
 
 def c4_batch(count):
@@ -178,6 +206,9 @@ def main_batched(args, np, torch, sy):
             "solves_per_s": len(items) / t64, "ms_per_batch": t64 * 1e3,
             "note": "single-equation binary64 path on 128 sampled equations, scaled by sum n^3"},
         "speedup_vs_fp64": None if t64 is None else t64 / dt,
+        "general_path": None if tgen is None else {
+            "ms_per_solve": tgen * 1e3, "rel_res": infg["rel_res"],
+            "note": "fp32 Schur + fp64 refinement on the same symmetric equation"},
         "roofline": roof, "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
@@ -234,9 +265,12 @@ def main():
     ap.add_argument("--count", type=int, default=4096, help="equations of the batched workload (c4)")
     ap.add_argument("--cpu-sample-eqs", type=int, default=1024)
     ap.add_argument("--c3-first", type=int, default=0, help="first delta index of the c3sweep workload")
-    ap.add_argument("--alg", default="orig", choices=["orig", "orth", "inv"],
+    ap.add_argument("--alg", default="orig", choices=["orig", "orth", "inv", "sym"],
                     help="mixed path: refinement in the original basis (orig), the paper's Alg. 4.1 (orth) "
-                         "or Alg. 4.2 (inv)")
+                         "or Alg. 4.2 (inv); the sym workload always runs the symmetric-coefficient "
+                         "route (sym), with the plain binary64 symmetric route as its baseline")
+    ap.add_argument("--general-steps", type=int, default=1,
+                    help="sym workload: timed solves of the same equation by the general path (context)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this solver has no "
@@ -267,6 +301,10 @@ def main():
         return
     cfg, desc = load_workload(args.workload)
     m, n = cfg["C"].shape
+    if args.workload == "sym":
+        args.alg = "sym"
+        if args.roofline_kernel == "k_chase":
+            args.roofline_kernel = "k_jac_pairs"
 
     def dev(a):
         return torch.from_numpy(np.asfortranarray(a)).t().contiguous().t().cuda()
@@ -277,8 +315,10 @@ def main():
                        dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
 
-    def run(low):
-        return sy.solve(A, B, C, X=X, work=work, low=low, alg=(args.alg if low != "fp64" else "orig"))[1]
+    def run(low, alg=None):
+        if alg is None:
+            alg = args.alg if (low != "fp64" or args.alg == "sym") else "orig"
+        return sy.solve(A, B, C, X=X, work=work, low=low, alg=alg)[1]
 
     for _ in range(args.warmup):
         run("fp32")
@@ -318,6 +358,17 @@ def main():
         torch.cuda.synchronize()
         t64 = (time.perf_counter() - s0) / args.fp64_steps
 
+    # symmetric workload: the general path on the same equation (context)
+    tgen = None
+    if args.alg == "sym" and args.general_steps > 0:
+        run("fp32", alg="orig")
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(args.general_steps):
+            infg = run("fp32", alg="orig")
+        torch.cuda.synchronize()
+        tgen = (time.perf_counter() - s0) / args.general_steps
+
     lo, hi = mixed_flops(m, n, iters)
     bsf = bs_flops(m, n)
     roof = None
@@ -341,7 +392,9 @@ def main():
         "config": {"workload": desc, "m": m, "n": n,
                    "path": {"orig": "fp32 Schur + fp64 refinement",
                             "orth": "Alg. 4.1: fp32 Schur, fp64-orthonormalised factors, triangular-basis refinement",
-                            "inv": "Alg. 4.2: fp32 Schur, fp64 inverses of the factors, triangular-basis refinement"}[args.alg],
+                            "inv": "Alg. 4.2: fp32 Schur, fp64 inverses of the factors, triangular-basis refinement",
+                            "sym": "symmetric route: fp32 block-Jacobi eigen-decompositions, elementwise solve, "
+                                   "fp64 refinement"}[args.alg],
                    "tol": 1e-14},
         "rel_res": max(i["rel_res"] for i in infos),
         "all_solves_at_tol": ok,
@@ -356,8 +409,15 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if args.alg == "sym":
+        out["tflops_bs_equivalent"] = sym_flops(m, n) / dt / 1e12
+        out["tflops_executed"] = None
+        if out["fp64_plain"] is not None:
+            out["fp64_plain"]["tflops_bs_equivalent"] = sym_flops(m, n) / t64 / 1e12
+            out["fp64_plain"]["path"] = "plain binary64 symmetric route (block Jacobi, elementwise solve)"
     if rank == 0 and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, m, n)
+        out["cpu_baseline"] = (cpu_baseline_sym(min(args.cpu_sample_n, 256), m, n) if args.alg == "sym"
+                               else cpu_baseline(args.cpu_sample_n, m, n))
     if rank == 0:
         print(json.dumps(out), flush=True)
 
@@ -371,7 +431,7 @@ def roofline_entry(kname, launches, total_ms, work, steps, step_s):
     so their roof is the fp32 vector peak of the chip."""
     avg_ms = total_ms / launches
     ach = work / (total_ms * 1e-3) / 1e12 if total_ms > 0 else 0.0
-    bound = "alu" if kname in ("k_chase", "k_aed", "k_bschur", "k_bhess") else "mfma"
+    bound = "alu" if kname in ("k_chase", "k_aed", "k_bschur", "k_bhess", "k_jac_pairs") else "mfma"
     peak = PEAKS["fp32_TFLOPs"]
     tb = TRAFFIC_BYTES.get(kname)
     return {"kernel": kname, "bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",

@@ -68,6 +68,26 @@ SYLV_DEVINL void reflector3(int len, T x, T y, T z, T &v1, T &v2, T &tau, T &bet
     beta = b;
 }
 
+// 16x16x4 MFMA in the precision T (binary32 or binary64 accumulate).  With
+// the operands fed swapped (op(B)^T in the A slot, op(A)^T in the B slot),
+// lane l ends up holding C(l & 15, orow(l, r)) in accumulator r, i.e. each
+// lane's accumulators run down a column of C.
+template <typename T> struct mfma16;
+template <> struct mfma16<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static SYLV_DEVINL v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static SYLV_DEVINL int orow(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct mfma16<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static SYLV_DEVINL v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static SYLV_DEVINL int orow(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
 // First column (x, y, z) of (H - s1 I)(H - s2 I) e1 for the leading 3x2
 // corner a00 a01 / a10 a11 / . a21 of an unreduced Hessenberg block, up to a
 // positive scale.  The shifts are a real pair (cplx = 0: s1 = p, s2 = q) or

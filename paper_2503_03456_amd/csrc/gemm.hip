@@ -20,23 +20,6 @@
 
 namespace sylv {
 
-template <typename T> struct mfma16;
-template <> struct mfma16<float> {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    static SYLV_DEVINL v4 op(float a, float b, v4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    // output row (within the 16x16 block) held by lane l in accumulator r
-    static SYLV_DEVINL int orow(int l, int r) { return 4 * (l >> 4) + r; }
-};
-template <> struct mfma16<double> {
-    typedef double v4 __attribute__((ext_vector_type(4)));
-    static SYLV_DEVINL v4 op(double a, double b, v4 c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static SYLV_DEVINL int orow(int l, int r) { return (l >> 4) + 4 * r; }
-};
-
 constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 16;
 
 // One 64x64 output tile (rows row0.., cols col0..) of C = alpha op(A) op(B) + beta C.

@@ -9,9 +9,9 @@
 // nb2 blocks of JB rows (nb2 even; a trailing block may be partly or wholly
 // outside the matrix).  A sweep is nb2 - 1 rounds; in each round the blocks
 // are matched into nb2/2 disjoint pairs and
-//   k_jac_pairs  (one wavefront per pair) diagonalises the 2JB x 2JB pair
-//                block in LDS by cyclic Jacobi sweeps of its own, keeping
-//                the accumulated rotation J_g (2JB x 2JB);
+//   k_jac_pairs  (one workgroup per pair) runs one cyclic Jacobi sweep over
+//                the 2JB x 2JB pair block in LDS, keeping the accumulated
+//                rotation J_g (2JB x 2JB);
 //   k_jac_apply  applies every J_g at once, S <- J^T S J and Q <- Q J
 //                (J = the direct sum of the J_g), tile by tile: tile (g, h)
 //                of S becomes J_g^T S(I_g, I_h) J_h, written together with
@@ -30,7 +30,10 @@ namespace sylv {
 constexpr int JB = 16;        // rows per block
 constexpr int JP = 2 * JB;    // order of a pair block
 constexpr int JLD = JP + 1;   // padded LDS leading dimension
-constexpr int JIN = 12;       // cap on the inner sweeps of one pair block
+// Inner sweeps per pair block and round.  One suffices: the block meets its
+// partner again in the next outer sweep, and exact inner diagonalisation
+// neither saves outer sweeps nor improves accuracy (it only adds rotations).
+constexpr int JIN = 1;
 
 // Round-robin tournament of m + 1 players (m odd), round r in [0, m):
 // match g pairs player 0 with 1 + r (g = 0) or 1 + (r + g) mod m with
@@ -50,174 +53,202 @@ SYLV_DEVINL void rr_match(int r, int g, int m, int &x, int &y) {
 // tau = (s_qq - s_pp) / (2 s_pq), c = 1/sqrt(1 + t^2), s = t c.
 template <typename T>
 SYLV_DEVINL void jac_rot(T app, T aqq, T apq, T &c, T &s, T &t) {
-    const T tau = (aqq - app) / (T(2) * apq);
+    // hardware reciprocal / square root (a few ulps): the rotation stays
+    // orthogonal to working accuracy and the closed-form diagonal update
+    // uses the same t
+    const T tau = (aqq - app) * frcp(T(2) * apq);
     const T at = fabs(tau);
     T tt;
     if (at > T(1)) {
-        const T ri = T(1) / at;
-        tt = ri / (T(1) + sqrt(T(1) + ri * ri));
+        const T ri = frcp(at);
+        tt = ri * frcp(T(1) + fsqrt(T(1) + ri * ri));
     } else {
-        tt = T(1) / (at + sqrt(T(1) + at * at));
+        tt = frcp(at + fsqrt(T(1) + at * at));
     }
     t = (tau >= T(0)) ? tt : -tt;
-    c = T(1) / sqrt(T(1) + t * t);
+    c = frcp(fsqrt(T(1) + t * t));
     s = t * c;
 }
 
 SYLV_DEVINL int pair_first(int t, int bx, int by) { return t < JB ? bx * JB + t : by * JB + (t - JB); }
 
-// One wavefront per pair g of round r: S(I_g, I_g) <- its diagonalised
-// form, J (device) <- the JP x JP rotation J_g (column-major, ld JP),
-// rot[g] = 1 if it is not the identity, *count += rotations taken.
-// nrm: ||S||_F (binary64, device).
+// 32x32x32 product on MFMA by the four wavefronts of a workgroup, wave w
+// computing the 16x16 block (w & 1, w >> 1) of Out = op(A) B with A, B in
+// LDS (column-major, ld JLD); op(A) = A^T when ta.  Lane l returns
+// Out(16 (w & 1) + (l & 15), 16 (w >> 1) + orow(l, r)) in acc[r].
 template <typename T>
-__global__ __launch_bounds__(64) void k_jac_pairs(int n, T *S, int lds, T *J, int *rot, int r, int m,
-                                                 const double *nrm, int *count) {
+SYLV_DEVINL typename mfma16<T>::v4 mm32(const T *A, bool ta, const T *B) {
+    typedef typename mfma16<T>::v4 v4;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = 16 * (w & 1) + (l & 15), j = 16 * (w >> 1) + (l & 15);
+    v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < JP / 4; ++kk) {
+        const int k = 4 * kk + (l >> 4);
+        const T fa = ta ? A[i * JLD + k] : A[k * JLD + i];
+        const T fb = B[j * JLD + k];
+        acc = mfma16<T>::op(fb, fa, acc);
+    }
+    return acc;
+}
+
+// One workgroup (four wavefronts) per pair g of round r: S(I_g, I_g) <- its
+// rotated form, J (device) <- the JP x JP rotation J_g (column-major, ld
+// JP), rot[g] = 1 if it is not the identity, count[0] += rotations taken,
+// count[1] += 1 if any.  nrm: ||S||_F (binary64, device).
+//
+// In an inner round the 16 disjoint rotations act on the block as R^T P R,
+// which splits into independent 2x2 sub-blocks: thread (p1, p2) owns rows
+// {x1, y1} of rotation p1 and columns {x2, y2} of rotation p2 and applies
+// R1^T B R2 to them in one pass (the diagonal sub-blocks p1 = p2 take the
+// closed form), plus rotation p2 to two rows of the accumulated Q.  Every
+// thread forms the two rotations it needs itself, in one loop, so all users
+// of a rotation get bit-identical parameters.  Two barriers per round: all
+// reads before any write, then the end of the round (which also counts the
+// rotations).
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_pairs(int n, T *S, int lds, T *J, int *rot, int r, int m,
+                                                  const double *nrm, int *count) {
     __shared__ T P[JP * JLD];
     __shared__ T Q[JP * JLD];
-    __shared__ T rs[JB], rtr[JB], rdx[JB], rdy[JB];
-    __shared__ int ract[JB];
-    const int g = blockIdx.x, lane = threadIdx.x;
+    __shared__ T M[JP * JLD];
+    const int g = blockIdx.x, tid = threadIdx.x;
     int bx, by;
     rr_match(r, g, m, bx, by);
     const T thr = (T)((double)num<T>::ulp * (*nrm) / (double)(n > 0 ? n : 1));
-    for (int e = lane; e < JP * JP; e += 64) {
+    bool big = false;
+    for (int e = tid; e < JP * JP; e += 256) {
         const int i = e % JP, j = e / JP;
         const int gi = pair_first(i, bx, by), gj = pair_first(j, bx, by);
-        P[j * JLD + i] = (gi < n && gj < n) ? CM(S, gi, gj, lds) : T(0);
+        const T v = (gi < n && gj < n) ? CM(S, gi, gj, lds) : T(0);
+        P[j * JLD + i] = v;
         Q[j * JLD + i] = (i == j) ? T(1) : T(0);
+        big = big || (i != j && fabs(v) > thr);
     }
-    __syncthreads();
+    // a block already below the threshold takes no rotation
     int total = 0;
-    for (int sw = 0; sw < JIN; ++sw) {
-        int taken = 0;
-        for (int rr = 0; rr < JP - 1; ++rr) {
-            bool act = false;
-            if (lane < JB) {
-                int x, y;
-                rr_match(rr, lane, JP - 1, x, y);
-                const T apq = P[y * JLD + x];
-                T c = T(1), s = T(0), t = T(0);
-                const T app = P[x * JLD + x], aqq = P[y * JLD + y];
-                if (fabs(apq) > thr) {
-                    jac_rot(app, aqq, apq, c, s, t);
-                    act = true;
-                }
-                rs[lane] = s;
-                rtr[lane] = s / (T(1) + c);
-                rdx[lane] = app - t * apq;
-                rdy[lane] = aqq + t * apq;
-                ract[lane] = act ? 1 : 0;
-            }
-            const unsigned long long vote = __ballot(act);
-            taken += __popcll(vote);
-            __syncthreads();
-            if (vote) {
-                // rows: P <- R^T P (16 pairs x 32 columns, 8 per lane)
+    if (__syncthreads_or(big)) {
+        const int p1 = tid >> 4, p2 = tid & 15;
+        for (int sw = 0; sw < JIN; ++sw) {
+            int taken = 0;
+            for (int rr = 0; rr < JP - 1; ++rr) {
+                int xs[2], ys[2];
+                T app[2], aqq[2], apq[2];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int e = lane + 64 * q, pr = e >> 5, k = e & 31;
-                    int x, y;
-                    rr_match(rr, pr, JP - 1, x, y);
-                    const T s = rs[pr], tr = rtr[pr];
-                    const T a = P[k * JLD + x], b = P[k * JLD + y];
-                    P[k * JLD + x] = a - s * (b + tr * a);
-                    P[k * JLD + y] = b + s * (a - tr * b);
+                for (int h = 0; h < 2; ++h) {
+                    rr_match(rr, h ? p2 : p1, JP - 1, xs[h], ys[h]);
+                    app[h] = P[xs[h] * JLD + xs[h]];
+                    aqq[h] = P[ys[h] * JLD + ys[h]];
+                    apq[h] = P[ys[h] * JLD + xs[h]];
                 }
+                const int x1 = xs[0], y1 = ys[0], x2 = xs[1], y2 = ys[1];
+                T b00 = P[x2 * JLD + x1], b01 = P[y2 * JLD + x1];
+                T b10 = P[x2 * JLD + y1], b11 = P[y2 * JLD + y1];
+                const int q0 = 2 * p1, q1 = 2 * p1 + 1;
+                T qa0 = Q[x2 * JLD + q0], qb0 = Q[y2 * JLD + q0];
+                T qa1 = Q[x2 * JLD + q1], qb1 = Q[y2 * JLD + q1];
                 __syncthreads();
-                // columns: P <- P R, Q <- Q R
+                T sn[2], tr[2], tt[2];
+                bool act[2];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int e = lane + 64 * q, pr = e >> 5, k = e & 31;
-                    int x, y;
-                    rr_match(rr, pr, JP - 1, x, y);
-                    const T s = rs[pr], tr = rtr[pr];
-                    const T a = P[x * JLD + k], b = P[y * JLD + k];
-                    P[x * JLD + k] = a - s * (b + tr * a);
-                    P[y * JLD + k] = b + s * (a - tr * b);
-                    const T qa = Q[x * JLD + k], qb = Q[y * JLD + k];
-                    Q[x * JLD + k] = qa - s * (qb + tr * qa);
-                    Q[y * JLD + k] = qb + s * (qa - tr * qb);
+                for (int h = 0; h < 2; ++h) {
+                    T c = T(1);
+                    sn[h] = T(0);
+                    tt[h] = T(0);
+                    act[h] = fabs(apq[h]) > thr;
+                    if (act[h]) jac_rot(app[h], aqq[h], apq[h], c, sn[h], tt[h]);
+                    tr[h] = act[h] ? sn[h] * frcp(T(1) + c) : T(0);
                 }
-                __syncthreads();
-                // the rotated 2x2 diagonal block in closed form (Alg. 8.5.1):
-                // s_pp - t s_pq, s_qq + t s_pq and an exact zero
-                if (lane < JB && ract[lane]) {
-                    int x, y;
-                    rr_match(rr, lane, JP - 1, x, y);
-                    P[x * JLD + x] = rdx[lane];
-                    P[y * JLD + y] = rdy[lane];
-                    P[x * JLD + y] = T(0);
-                    P[y * JLD + x] = T(0);
+                if (p1 == p2) {
+                    if (act[0]) {
+                        P[x1 * JLD + x1] = app[0] - tt[0] * apq[0];
+                        P[y1 * JLD + y1] = aqq[0] + tt[0] * apq[0];
+                        P[y1 * JLD + x1] = T(0);
+                        P[x1 * JLD + y1] = T(0);
+                    }
+                } else if (act[0] || act[1]) {
+                    // rows x1, y1 by rotation 1, then columns x2, y2 by rotation 2
+                    T u, v;
+                    u = b00; v = b10;
+                    b00 = u - sn[0] * (v + tr[0] * u);
+                    b10 = v + sn[0] * (u - tr[0] * v);
+                    u = b01; v = b11;
+                    b01 = u - sn[0] * (v + tr[0] * u);
+                    b11 = v + sn[0] * (u - tr[0] * v);
+                    u = b00; v = b01;
+                    b00 = u - sn[1] * (v + tr[1] * u);
+                    b01 = v + sn[1] * (u - tr[1] * v);
+                    u = b10; v = b11;
+                    b10 = u - sn[1] * (v + tr[1] * u);
+                    b11 = v + sn[1] * (u - tr[1] * v);
+                    P[x2 * JLD + x1] = b00;
+                    P[y2 * JLD + x1] = b01;
+                    P[x2 * JLD + y1] = b10;
+                    P[y2 * JLD + y1] = b11;
                 }
-                __syncthreads();
+                if (act[1]) {
+                    Q[x2 * JLD + q0] = qa0 - sn[1] * (qb0 + tr[1] * qa0);
+                    Q[y2 * JLD + q0] = qb0 + sn[1] * (qa0 - tr[1] * qb0);
+                    Q[x2 * JLD + q1] = qa1 - sn[1] * (qb1 + tr[1] * qa1);
+                    Q[y2 * JLD + q1] = qb1 + sn[1] * (qa1 - tr[1] * qb1);
+                }
+                taken += __syncthreads_count(p1 == p2 && act[0]);
             }
+            total += taken;
+            if (taken == 0) break;
         }
-        total += taken;
-        if (taken == 0) break;
     }
     T *Jg = J + (size_t)g * JP * JP;
-    // The diagonalised pair block goes back as computed here (symmetrised),
-    // not as J_g^T S J_g re-formed by the apply kernel: that product would
-    // put rounding noise of order u |s_ii| back into the entries just
-    // zeroed, which for close eigenvalues exceeds the rotation threshold.
-    if (total > 0)
-        for (int e = lane; e < JP * JP; e += 64) {
+    if (total == 0) {
+        for (int e = tid; e < JP * JP; e += 256) Jg[e] = ((e / JP) == (e % JP)) ? T(1) : T(0);
+    } else {
+        // The rotated pair block goes back as computed here (symmetrised),
+        // not as J_g^T S J_g re-formed by the apply kernel: that product would
+        // put rounding noise of order u |s_ii| back into the entries just
+        // zeroed, which for close eigenvalues exceeds the rotation threshold.
+        for (int e = tid; e < JP * JP; e += 256) {
             const int i = e % JP, j = e / JP;
             const int gi = pair_first(i, bx, by), gj = pair_first(j, bx, by);
-            if (gi < n && gj < n)
-                CM(S, gi, gj, lds) = T(0.5) * (P[j * JLD + i] + P[i * JLD + j]);
+            if (gi < n && gj < n) CM(S, gi, gj, lds) = T(0.5) * (P[j * JLD + i] + P[i * JLD + j]);
         }
-    if (total == 0) {
-        for (int e = lane; e < JP * JP; e += 64) Jg[e] = ((e / JP) == (e % JP)) ? T(1) : T(0);
-    } else {
         // One Newton-Schulz step J <- J (3I - J^T J) / 2 squares the
         // departure from orthogonality that the rotations accumulated, so
         // that the products of J's forming the eigenvectors do not drift.
-        // Lane -> column j, rows i0 .. i0+15.
-        __syncthreads();
-        const int jc = lane & 31, i0 = (lane >> 5) * 16;
-        T acc[16];
+        const int w = tid >> 6, l = tid & 63, oi = 16 * (w & 1) + (l & 15);
+        auto acc = mm32<T>(Q, true, Q);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = T(0);
-        for (int k = 0; k < JP; ++k) {
-            const T qj = Q[jc * JLD + k];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q] += Q[(i0 + q) * JLD + k] * qj;
+        for (int q = 0; q < 4; ++q) {
+            const int oj = 16 * (w >> 1) + mfma16<T>::orow(l, q);
+            M[oj * JLD + oi] = (oi == oj ? T(1.5) : T(0)) - T(0.5) * acc[q];
         }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) P[jc * JLD + i0 + q] = ((i0 + q) == jc ? T(1.5) : T(0)) - T(0.5) * acc[q];
         __syncthreads();
+        acc = mm32<T>(Q, false, M);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = T(0);
-        for (int k = 0; k < JP; ++k) {
-            const T mkj = P[jc * JLD + k];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q] += Q[k * JLD + i0 + q] * mkj;
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) Jg[jc * JP + i0 + q] = acc[q];
+        for (int q = 0; q < 4; ++q) Jg[(16 * (w >> 1) + mfma16<T>::orow(l, q)) * JP + oi] = acc[q];
     }
-    if (lane == 0) {
+    if (tid == 0) {
         rot[g] = total > 0 ? 1 : 0;
-        if (total > 0) atomicAdd(count, total);
+        if (total > 0) {
+            atomicAdd(count, total);
+            atomicAdd(count + 1, 1);
+        }
     }
 }
 
 // Tiles: [0, kp(kp-1)/2) are the off-diagonal S tiles (g < h; the pair
 // kernel has already written the diagonal ones), then nrt * kp tiles of Q
-// (row tile of JP rows x column pair h).  256 threads, 4 outputs each.
+// (row tile of JP rows x column pair h).  256 threads = 4 wavefronts.
 template <typename T>
 __global__ __launch_bounds__(256) void k_jac_apply(int n, T *S, int lds, T *Qm, int ldq, const T *J,
                                                   const int *rot, int r, int m, int kp) {
     __shared__ T X[JP * JLD];
     __shared__ T L[JP * JLD];
     __shared__ T R[JP * JLD];
-    const int tid = threadIdx.x;
+    __shared__ T W[JP * JLD];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int ntri = kp * (kp - 1) / 2;
+    const int oi = 16 * (w & 1) + (l & 15);   // output row of this lane
     int tile = blockIdx.x;
-    // thread -> column j, rows i0..i0+3 of the 32 x 32 output
-    const int j = tid >> 3, i0 = (tid & 7) * 4;
     if (tile < ntri) {
         // tile = h (h - 1) / 2 + g, 0 <= g < h
         int h = (int)((1.0 + sqrt(1.0 + 8.0 * tile)) * 0.5);
@@ -238,31 +269,25 @@ __global__ __launch_bounds__(256) void k_jac_apply(int n, T *S, int lds, T *Qm, 
         }
         __syncthreads();
         // W = Jg^T X
-        T w[4] = {T(0), T(0), T(0), T(0)};
-        for (int k = 0; k < JP; ++k) {
-            const T xv = X[j * JLD + k];
+        auto acc = mm32<T>(L, true, X);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) w[q] += L[(i0 + q) * JLD + k] * xv;
-        }
+        for (int q = 0; q < 4; ++q) W[(16 * (w >> 1) + mfma16<T>::orow(l, q)) * JLD + oi] = acc[q];
         __syncthreads();
+        // Out = W Jh, staged in X for the two coalesced stores
+        acc = mm32<T>(W, false, R);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) X[j * JLD + i0 + q] = w[q];
+        for (int q = 0; q < 4; ++q) X[(16 * (w >> 1) + mfma16<T>::orow(l, q)) * JLD + oi] = acc[q];
         __syncthreads();
-        // Out = W Jh
-        T o[4] = {T(0), T(0), T(0), T(0)};
-        for (int k = 0; k < JP; ++k) {
-            const T rv = R[j * JLD + k];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] += X[k * JLD + i0 + q] * rv;
-        }
-        const int hb = pair_first(j, hx, hy);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int ga = pair_first(i0 + q, gx, gy);
-            if (ga < n && hb < n) {
-                CM(S, ga, hb, lds) = o[q];
-                CM(S, hb, ga, lds) = o[q];
-            }
+        for (int e = tid; e < JP * JP; e += 256) {
+            int a = e % JP, b = e / JP;
+            int ga = pair_first(a, gx, gy), hb = pair_first(b, hx, hy);
+            if (ga < n && hb < n) CM(S, ga, hb, lds) = X[b * JLD + a];
+            // transposed tile: consecutive threads walk down a column of S
+            b = e % JP;
+            a = e / JP;
+            ga = pair_first(a, gx, gy);
+            hb = pair_first(b, hx, hy);
+            if (ga < n && hb < n) CM(S, hb, ga, lds) = X[b * JLD + a];
         }
     } else {
         tile -= ntri;
@@ -278,17 +303,12 @@ __global__ __launch_bounds__(256) void k_jac_apply(int n, T *S, int lds, T *Qm, 
             R[b * JLD + a] = Jh[e];
         }
         __syncthreads();
-        T o[4] = {T(0), T(0), T(0), T(0)};
-        for (int k = 0; k < JP; ++k) {
-            const T rv = R[j * JLD + k];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] += X[k * JLD + i0 + q] * rv;
-        }
-        const int hb = pair_first(j, hx, hy);
+        const auto acc = mm32<T>(X, false, R);
+        const int ra = rb * JP + oi;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int ra = rb * JP + i0 + q;
-            if (ra < n && hb < n) CM(Qm, ra, hb, ldq) = o[q];
+            const int hb = pair_first(16 * (w >> 1) + mfma16<T>::orow(l, q), hx, hy);
+            if (ra < n && hb < n) CM(Qm, ra, hb, ldq) = acc[q];
         }
     }
 }
@@ -412,11 +432,11 @@ int sym_eig(hipStream_t s, int n, T *S, int lds, T *Q, int ldq, char *ws, char *
     const int tiles = kp * (kp - 1) / 2 + nrt * kp;
     int sw = 0, conv = 0;
     for (; sw < max_sweeps; ++sw) {
-        HIP_TRY(hipMemsetAsync(count, 0, sizeof(int), s));
+        HIP_TRY(hipMemsetAsync(count, 0, 2 * sizeof(int), s));
         for (int r = 0; r < m; ++r) {
             {
                 ProfScope ps(KID_JAC_PAIRS, s);
-                hipLaunchKernelGGL((k_jac_pairs<T>), dim3(kp), dim3(64), 0, s, n, S, lds, J, rot, r, m, nrm,
+                hipLaunchKernelGGL((k_jac_pairs<T>), dim3(kp), dim3(256), 0, s, n, S, lds, J, rot, r, m, nrm,
                                    count);
             }
             {
@@ -425,10 +445,17 @@ int sym_eig(hipStream_t s, int n, T *S, int lds, T *Q, int ldq, char *ws, char *
                                    r, m, kp);
             }
         }
-        HIP_TRY(hipMemcpyAsync(hbuf, count, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hbuf, count, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        int taken = 0;
-        std::memcpy(&taken, hbuf, sizeof(int));
+        int cnt[2] = {0, 0};
+        std::memcpy(cnt, hbuf, 2 * sizeof(int));
+        const int taken = cnt[0];
+        // algorithmic work of the pair kernels of this sweep: every rotation
+        // updates 32 element pairs of the block's rows, of its columns and of
+        // the accumulated rotation (8 flops per pair in Rutishauser's form),
+        // plus the Newton-Schulz step of each rotated block (two 32^3 products)
+        if (prof_armed(KID_JAC_PAIRS))
+            prof_add_work(KID_JAC_PAIRS, 768.0 * taken + 2.0 * 2.0 * JP * JP * JP * cnt[1]);
         if (taken == 0) { conv = 1; ++sw; break; }
     }
     hipLaunchKernelGGL((k_keep_diag<T>), dim3(grid_for((size_t)n * n)), dim3(256), 0, s, n, S, lds);
