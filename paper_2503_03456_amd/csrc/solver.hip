@@ -205,17 +205,32 @@ __global__ void k_quasi_eigs(int n, const T *Tm, int ld, float *wr, float *wi) {
     }
 }
 
-// min over i, j of |lambda_i + mu_j|
+// min over i, j of |lambda_i + mu_j|: per-workgroup minima into part[],
+// then one workgroup folds them (fixed order, deterministic)
+constexpr int SEP_BLOCKS = 256;
 __global__ __launch_bounds__(256) void k_sep_min(int m, int n, const float *wra, const float *wia,
-                                                 const float *wrb, const float *wib, double *out) {
+                                                 const float *wrb, const float *wib, double *part) {
     __shared__ double red[256];
     double best = 1e300;
-    size_t total = (size_t)m * n;
-    for (size_t e = threadIdx.x; e < total; e += 256) {
-        int i = (int)(e % m), j = (int)(e / m);
-        double re = (double)wra[i] + wrb[j], im = (double)wia[i] + wib[j];
+    const size_t total = (size_t)m * n;
+    for (size_t e = blockIdx.x * (size_t)256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        const double re = (double)wra[i] + wrb[j], im = (double)wia[i] + wib[j];
         best = fmin(best, sqrt(re * re + im * im));
     }
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_min_final(int cnt, const double *part, double *out) {
+    __shared__ double red[256];
+    double best = 1e300;
+    for (int i = threadIdx.x; i < cnt; i += 256) best = fmin(best, part[i]);
     red[threadIdx.x] = best;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -349,12 +364,17 @@ static void orth_check(hipStream_t s, int n, const float *U, double *G, double *
     matnorm<double>(s, n, n, Gm, n, out, nscr, 0);
 }
 
+// scratch: SEP_BLOCKS doubles
 template <typename T>
-static void sep_estimate(hipStream_t s, int m, int n, const T *TA, const T *TB, float *eig, double *out) {
+static void sep_estimate(hipStream_t s, int m, int n, const T *TA, const T *TB, float *eig, double *out,
+                         double *scratch) {
     float *wra = eig, *wia = eig + m, *wrb = eig + 2 * m, *wib = eig + 2 * m + n;
     hipLaunchKernelGGL((k_quasi_eigs<T>), dim3((m + 255) / 256), dim3(256), 0, s, m, TA, m, wra, wia);
     hipLaunchKernelGGL((k_quasi_eigs<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, TB, n, wrb, wib);
-    hipLaunchKernelGGL(k_sep_min, dim3(1), dim3(256), 0, s, m, n, wra, wia, wrb, wib, out);
+    const size_t total = (size_t)m * n;
+    const int nb = (int)std::min<size_t>(SEP_BLOCKS, (total + 255) / 256);
+    hipLaunchKernelGGL(k_sep_min, dim3(nb), dim3(256), 0, s, m, n, wra, wia, wrb, wib, scratch);
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, s, nb, scratch, out);
 }
 
 // --------------------------------------------------------------- drivers
@@ -373,7 +393,7 @@ static int run_fp64(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
     matnorm<double>(s, 2, 1, p.scal + 10, 2, p.scal + 12, p.nscr, 1);
     hipMemsetAsync(p.flag, 0, sizeof(int), s);
     correction<double>(s, m, n, p.hi, C, ldc, 1.0, X, ldx, false, p.scal + 12, p.flag);
-    sep_estimate<double>(s, m, n, p.hi.TA, p.hi.TB, p.eig, p.scal + 13);
+    sep_estimate<double>(s, m, n, p.hi.TA, p.hi.TB, p.eig, p.scal + 13, p.nscr);
     residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr);
     double h[16];
     hipError_t e = read_scalars(s, c, p.scal, 16, h);
@@ -411,7 +431,7 @@ static int mixed_forms(hipStream_t s, DevCtx *c, int m, int n, const double *A, 
     matnorm<float>(s, m, m, p.lo.TA, m, p.scal + 10, p.nscr, 1);
     matnorm<float>(s, n, n, p.lo.TB, n, p.scal + 11, p.nscr, 1);
     matnorm<double>(s, 2, 1, p.scal + 10, 2, p.scal + 12, p.nscr, 1);
-    sep_estimate<float>(s, m, n, p.lo.TA, p.lo.TB, p.eig, p.scal + 13);
+    sep_estimate<float>(s, m, n, p.lo.TA, p.lo.TB, p.eig, p.scal + 13, p.nscr);
     return 0;
 }
 
