@@ -207,9 +207,6 @@ def main_batched(args, np, torch, sy):
             "solves_per_s": len(items) / t64, "ms_per_batch": t64 * 1e3,
             "note": "single-equation binary64 path on 128 sampled equations, scaled by sum n^3"},
         "speedup_vs_fp64": None if t64 is None else t64 / dt,
-        "general_path": None if tgen is None else {
-            "ms_per_solve": tgen * 1e3, "rel_res": infg["rel_res"],
-            "note": "fp32 Schur + fp64 refinement on the same symmetric equation"},
         "roofline": roof, "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
@@ -407,6 +404,9 @@ def main():
             "solves_per_s": 1.0 / t64, "ms_per_solve": t64 * 1e3, "rel_res": inf64["rel_res"],
             "tflops_bs_equivalent": bsf / t64 / 1e12},
         "speedup_vs_fp64": None if t64 is None else t64 / dt,
+        "general_path": None if tgen is None else {
+            "ms_per_solve": tgen * 1e3, "rel_res": infg["rel_res"],
+            "note": "fp32 Schur + fp64 refinement on the same symmetric equation"},
         "roofline": roof,
         "cpu_baseline": None,
     }

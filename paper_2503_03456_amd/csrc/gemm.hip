@@ -259,17 +259,19 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__rest
     __shared__ __align__(16) LT Bs[BF16IN ? GBN : GBK][C1];
     const BatchEq &q = eqs[order[blockIdx.y]];
     if (!q.active) return;
+    if ((amode & 4) && q.sym) return;  // product not needed by the symmetric specialisation
     const int n = q.n;
     const int tl = (n + GBM - 1) / GBM;
     if ((int)blockIdx.x >= tl * tl) return;
     const int tm = blockIdx.x % tl, tn = blockIdx.x / tl;
-    // amode 1 scales op(B) by scale_e before the conversion to ACC (a binary64
-    // residual brought to unit size ahead of the binary32 cast); amode 2
-    // multiplies the product by 1 / scale_e
+    // amode & 3 == 1 scales op(B) by scale_e before the conversion to ACC (a
+    // binary64 residual brought to unit size ahead of the binary32 cast);
+    // == 2 multiplies the product by 1 / scale_e; amode & 4 skips equations
+    // with the symmetric flag
     ACC al = alpha;
     TB bs = TB(1);
-    if (amode == 1) bs = (TB)q.scale;
-    else if (amode == 2) al = (ACC)(alpha / q.scale);
+    if ((amode & 3) == 1) bs = (TB)q.scale;
+    else if ((amode & 3) == 2) al = (ACC)(alpha / q.scale);
     if constexpr (BF16IN != 0)
         gemm_bf16_tile<TA, TB, TC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
                                    q.ld[fb], tb, (TC *)q.ptr[fc], q.ld[fc], (float)al, (float)beta, bs,

@@ -32,7 +32,7 @@ struct BatchEq {
     double napply;   // 3-element reflector applications of the Schur kernel
     long long cyc[4];  // Schur kernel cycles: total, sweeps, U updates, deflation scans
     int sweeps;
-    int pad2;
+    int sym;         // C symmetric to rounding: X kept symmetric, one-product residual, half tri-solve
 };
 
 // selector.hip

@@ -5,7 +5,7 @@
 // (longest first).
 //
 // Per equation:
-//   1. k_bprep    ||A||_F, ||C||_F, control fields
+//   1. k_bprep    ||A||_F, ||C||_F, control fields, symmetry test of C
 //   2. k_bhess_reg Householder reduction of fl32(A) to Hessenberg form H and
 //                 the orthogonal factor U0, both held in registers
 //   3. k_bschur   Francis double-shift QR on the Hessenberg band held in LDS
@@ -19,6 +19,10 @@
 //   5. refinement passes: R = C - AX - XA^T (binary64 MFMA), k_bnorm decides
 //      per equation (converged / stalled / cap / NaN) and the scale 2^-e of R
 //      for the binary32 correction.
+// Symmetric specialisation (C symmetric to rounding, so X is symmetric):
+// the iterate is kept exactly symmetric, the residual takes one product
+// (C - W - W^T with W = A X), and the tri-solve computes one tile of each
+// mirror pair of the persymmetric Y' = Y P and stores the other by mirroring.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -64,7 +68,10 @@ SYLV_DEVINL T wg_max(T v, T *red) {
 }
 
 // ------------------------------------------------------------ 1. prepare
-// ||A||_F, ||C||_F and the per-equation control fields.
+// ||A||_F, ||C||_F, the symmetry test of C and the per-equation control
+// fields.  With ||C - C^T||_F <= 2u ||C||_F (u = 2^-53) the solution is
+// symmetric to working accuracy and the equation takes the symmetric
+// specialisation (Lyapunov with symmetric right-hand side).
 __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
     __shared__ double red[8];
     BatchEq &q = eqs[order[blockIdx.x]];
@@ -72,18 +79,22 @@ __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
     const double *A = (const double *)q.ptr[BF_A];
     const double *C = (const double *)q.ptr[BF_C];
     const int lda = q.ld[BF_A], ldc = q.ld[BF_C];
-    double sa = 0.0, sc = 0.0;
+    double sa = 0.0, sc = 0.0, sd = 0.0;
     for (int e = threadIdx.x; e < n * n; e += BNT) {
         const int i = e % n, j = e / n;
         const double a = A[(size_t)j * lda + i], c = C[(size_t)j * ldc + i];
+        const double d = c - C[(size_t)i * ldc + j];
         sa += a * a;
         sc += c * c;
+        sd += d * d;
     }
     sa = wg_sum(sa, red);
     sc = wg_sum(sc, red);
+    sd = wg_sum(sd, red);
     if (threadIdx.x == 0) {
         q.nA = sqrt(sa);
         q.nC = sqrt(sc);
+        q.sym = sqrt(sd) <= 0x1p-52 * q.nC ? 1 : 0;
         q.active = 1;
         q.status = SYLV_ST_NOT_CONVERGED;
         q.iterations = 0;
@@ -564,6 +575,7 @@ __global__ __launch_bounds__(BNT) void k_bpost(BatchEq *eqs, const int *order) {
 }
 
 // --------------------------------------- 5. residual norms and loop control
+// R = C (general), or R = 0 ahead of the one-product symmetric residual
 __global__ __launch_bounds__(BNT) void k_bcopy_c(BatchEq *eqs, const int *order) {
     BatchEq &q = eqs[order[blockIdx.x]];
     if (!q.active) return;
@@ -571,7 +583,46 @@ __global__ __launch_bounds__(BNT) void k_bcopy_c(BatchEq *eqs, const int *order)
     const double *C = (const double *)q.ptr[BF_C];
     double *R = (double *)q.ptr[BF_R];
     const int ldc = q.ld[BF_C];
-    for (int e = threadIdx.x; e < n * n; e += BNT) R[e] = C[(size_t)(e / n) * ldc + e % n];
+    if (q.sym)
+        for (int e = threadIdx.x; e < n * n; e += BNT) R[e] = 0.0;
+    else
+        for (int e = threadIdx.x; e < n * n; e += BNT) R[e] = C[(size_t)(e / n) * ldc + e % n];
+}
+
+// Symmetric specialisation: with X = X^T, X A^T = (A X)^T, so after
+// R = -A X the residual is C - A X - X A^T = C + R + R^T (one product
+// instead of two).  Each thread owns an entry pair (i, j), (j, i).
+__global__ __launch_bounds__(BNT) void k_bsymres(BatchEq *eqs, const int *order) {
+    BatchEq &q = eqs[order[blockIdx.x]];
+    if (!q.active || !q.sym) return;
+    const int n = q.n;
+    const double *C = (const double *)q.ptr[BF_C];
+    double *R = (double *)q.ptr[BF_R];
+    const int ldc = q.ld[BF_C];
+    for (int e = threadIdx.x; e < n * n; e += BNT) {
+        const int i = e % n, j = e / n;
+        if (i > j) continue;
+        const double w = R[(size_t)j * n + i] + R[(size_t)i * n + j];
+        R[(size_t)j * n + i] = C[(size_t)j * ldc + i] + w;
+        if (i != j) R[(size_t)i * n + j] = C[(size_t)i * ldc + j] + w;
+    }
+}
+
+// X <- (X + X^T) / 2 for the symmetric specialisation (keeps the iterate
+// exactly symmetric, which the one-product residual relies on)
+__global__ __launch_bounds__(BNT) void k_bsymx(BatchEq *eqs, const int *order) {
+    BatchEq &q = eqs[order[blockIdx.x]];
+    if (!q.active || !q.sym) return;
+    const int n = q.n;
+    double *X = (double *)q.ptr[BF_X];
+    const int ldx = q.ld[BF_X];
+    for (int e = threadIdx.x; e < n * n; e += BNT) {
+        const int i = e % n, j = e / n;
+        if (i >= j) continue;
+        const double v = 0.5 * (X[(size_t)j * ldx + i] + X[(size_t)i * ldx + j]);
+        X[(size_t)j * ldx + i] = v;
+        X[(size_t)i * ldx + j] = v;
+    }
 }
 
 __global__ __launch_bounds__(BNT) void k_bnorm(BatchEq *eqs, const int *order, double tol,
@@ -669,17 +720,20 @@ static void enqueue_front(hipStream_t s, const BatchPlan &P) {
                                              P.bf16);
     gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 0, 0.f,
                                               P.bf16);
+    hipLaunchKernelGGL(k_bsymx, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
 }
 
-// binary64 residual R = C - A X - X A^T, norms and the per-equation decision;
+// binary64 residual R = C - A X - X A^T (one product for symmetric
+// equations), norms and the per-equation decision;
 // *dcnt = number of equations that take another correction
 static void enqueue_pass(hipStream_t s, const BatchPlan &P, bool) {
     const int batch = P.batch;
     hipLaunchKernelGGL(k_bcopy_c, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
     gemm_batched<double, double, double, double>(s, P.deq, P.dord, batch, P.nmax, BF_A, 0, BF_X, 0, BF_R, -1.0, 0,
                                                  1.0);
-    gemm_batched<double, double, double, double>(s, P.deq, P.dord, batch, P.nmax, BF_X, 0, BF_A, 1, BF_R, -1.0, 0,
+    gemm_batched<double, double, double, double>(s, P.deq, P.dord, batch, P.nmax, BF_X, 0, BF_A, 1, BF_R, -1.0, 4,
                                                  1.0);
+    hipLaunchKernelGGL(k_bsymres, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
     hipLaunchKernelGGL(k_bzero, dim3(1), dim3(64), 0, s, P.dcnt);
     hipLaunchKernelGGL(k_bnorm, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord, P.tol, P.max_iter, P.dcnt);
 }
@@ -697,6 +751,7 @@ static void enqueue_correction(hipStream_t s, const BatchPlan &P) {
                                              P.bf16);
     gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 1.f,
                                               P.bf16);
+    hipLaunchKernelGGL(k_bsymx, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
 }
 
 // ------------------------------------------------------------- hipGraph

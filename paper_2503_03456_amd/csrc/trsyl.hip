@@ -137,9 +137,15 @@ SYLV_DEVINL int pair2_solve(T m00, T m01, T m10, T m11, T &r0, T &r1, T smin) {
 }
 
 // One tile (I, J) of Y: off-diagonal updates, then the in-LDS solve.
+// mirror (symmetric Lyapunov, m = n, TB = P TA^T P): the column tiles are
+// the mirror images of the row tiles, c_J = n - r_{nt-J}, so that the
+// solution Y' = Y P of a symmetric Y (persymmetric: Y'(i, j) =
+// Y'(n-1-j, n-1-i)) maps tile (I, J) onto tile (nt-1-J, nt-1-I) of the same
+// anti-diagonal; wmirror also stores that mirror tile.
 template <typename T>
 SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, const T *__restrict__ TB,
-                            int ldtb, T *C, int ldc, int I, int J, double maxab, int *flag) {
+                            int ldtb, T *C, int ldc, int I, int J, double maxab, int *flag, int mirror = 0,
+                            int wmirror = 0) {
     __shared__ T sA[TS * TLD];   // TA diagonal tile, later reused
     __shared__ T sB[TS * TLD];   // TB diagonal tile
     __shared__ T sC[TS * TLD];   // rhs -> Y tile
@@ -150,7 +156,15 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
     typedef typename mfma16t<T>::v4 v4;
 
     const int r0 = tile_bound(TA, ldta, m, I), r1 = tile_bound(TA, ldta, m, I + 1);
-    const int c0 = tile_bound(TB, ldtb, n, J), c1 = tile_bound(TB, ldtb, n, J + 1);
+    int c0, c1;
+    if (mirror) {
+        const int nt = (m + TBASE - 1) / TBASE;
+        c0 = n - tile_bound(TA, ldta, m, nt - J);
+        c1 = n - tile_bound(TA, ldta, m, nt - 1 - J);
+    } else {
+        c0 = tile_bound(TB, ldtb, n, J);
+        c1 = tile_bound(TB, ldtb, n, J + 1);
+    }
     const int p = r1 - r0, q = c1 - c0;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = w & 1, wn = w >> 1;
@@ -327,6 +341,11 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
         int i = e % p, j = e / p;
         C[(size_t)(c0 + j) * ldc + r0 + i] = sC[j * TLD + i];
     }
+    if (wmirror)  // Y'(n-1-j, n-1-i) = Y'(i, j), consecutive threads down a column
+        for (int e = t; e < p * q; e += 256) {
+            int j = e % q, i = e / q;
+            C[(size_t)(n - 1 - (r0 + i)) * ldc + (n - 1 - (c0 + j))] = sC[j * TLD + i];
+        }
     if (myflag) atomicOr(flag, 1);
 }
 
@@ -354,9 +373,13 @@ __global__ __launch_bounds__(256) void k_btrsyl_diag(BatchEq *eqs, const int *or
     const int jmax = d < nI - 1 ? d : nI - 1;
     const int J = jmin + (int)blockIdx.x;
     if (J > jmax) return;
+    // symmetric equations: one tile of each mirror pair (2J < d) also
+    // stores its mirror; the self-mirror tile (2J = d) is solved whole
+    if (q.sym && 2 * J > d) return;
     const int I = nI - 1 - (d - J);
     trsyl_tile<float>(n, n, (const float *)q.ptr[BF_H], q.ld[BF_H], (const float *)q.ptr[BF_TB],
-                      q.ld[BF_TB], (float *)q.ptr[BF_W], q.ld[BF_W], I, J, q.tmax, &q.flag);
+                      q.ld[BF_TB], (float *)q.ptr[BF_W], q.ld[BF_W], I, J, q.tmax, &q.flag, q.sym,
+                      q.sym && 2 * J < d);
 }
 
 void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int nmax) {

@@ -20,7 +20,7 @@ def lyap_kappa(eig):
     return np.abs(lam).max() / np.abs(lam).min()
 
 
-def check_item(A, C, eig, Xg, info, allow_fallback=False):
+def check_item(A, C, eig, Xg, info, allow_fallback=False, symmetric=True):
     Xo, st = oracle.lyap_solve(A, C)
     assert st == 0
     assert info["rel_res"] <= TOL, info
@@ -36,7 +36,8 @@ def check_item(A, C, eig, Xg, info, allow_fallback=False):
     n = A.shape[0]
     bound = (rr_g + rr_o) * kap * (1 + np.sqrt(n)) + 100 * U64 * kap
     assert relerr(Xg, Xo) <= bound, (relerr(Xg, Xo), bound)
-    assert np.linalg.norm(Xg - Xg.T) <= 100 * U64 * kap * np.linalg.norm(Xg)
+    if symmetric:
+        assert np.linalg.norm(Xg - Xg.T) <= 100 * U64 * kap * np.linalg.norm(Xg)
 
 
 def items(indices, sizes):
@@ -197,3 +198,28 @@ def test_batch_graph_replays_match_eager(monkeypatch):
         del junk
     for (A, C, eig), X, info in zip(its, Xg, ig):
         check_item(A, C, eig, host(X), info)
+
+
+def test_batch_symmetric_specialisation_mixed_with_general():
+    """Equations with symmetric C take the symmetric specialisation (one-
+    product residual, half tri-solve with mirrored tiles, iterate kept
+    exactly symmetric); equations with a general C in the same batch take the
+    general path.  Orders span several 64-row tiles and ragged tails; 2x2
+    blocks fall on tile boundaries for some of them."""
+    sy = binding()
+    sizes = [256, 200, 130, 129, 65, 64, 63, 17, 2, 1, 190, 255]
+    its = items(range(700, 700 + len(sizes)), sizes)
+    eqs, ref = [], []
+    for k, (A, C, eig) in enumerate(its):
+        if k % 3 == 2:   # general right-hand side
+            C = np.random.RandomState(800 + k).standard_normal(C.shape)
+        ref.append((A, C, eig, k % 3 != 2))
+        eqs.append((dev(A), dev(C)))
+    say("batched symmetric + general", sizes)
+    Xs, infos = sy.solve_batched(eqs)
+    torch.cuda.synchronize()
+    for (A, C, eig, sym), X, info in zip(ref, Xs, infos):
+        Xh = host(X)
+        check_item(A, C, eig, Xh, info, symmetric=sym)
+        if sym:
+            assert np.array_equal(Xh, Xh.T)
