@@ -70,6 +70,8 @@ void identity(hipStream_t s, int n, T *U, int ldu);
 template <typename T>
 void matnorm(hipStream_t s, int r, int c, const T *a, int ld, double *out, double *scratch, int mode);
 void sub_identity(hipStream_t s, int n, double *G, int ldg);
+void sym_residual(hipStream_t s, int n, const double *C, int ldc, double *R, int ldr);
+void symmetrize(hipStream_t s, int n, double *X, int ldx);
 template <typename TS>
 void axpy(hipStream_t s, int r, int c, double alpha, const TS *D, int ldd, double *X, int ldx);
 
@@ -115,8 +117,10 @@ void get_diag(hipStream_t s, int n, const T *D, int ldd, T *d);
 void asym_norm(hipStream_t s, int n, const double *A, int lda, double *out, double *scratch);
 
 // trsyl.hip
+// mirror: symmetric Lyapunov (m = n, TB = P TA^T P, C persymmetric up to
+// rounding): one tile of each mirror pair is solved and stores the other
 template <typename T>
 void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, T *C, int ldc,
-           const double *maxab, int *flag);
+           const double *maxab, int *flag, int mirror = 0);
 
 }  // namespace sylv

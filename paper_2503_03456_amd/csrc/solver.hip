@@ -110,6 +110,7 @@ struct Stage {  // buffers of one precision's Bartels-Stewart pipeline
     char *schur_ws;   // Schur workspace for A
     char *schur_ws2;  // Schur workspace for B (the two run concurrently)
     int diag;         // symmetric coefficients: TA, TB diagonal (eigen-decompositions)
+    int lsym;         // Lyapunov with symmetric C: symmetric iterate, half tri-solve
 };
 
 // Alg. 4.1 buffers (binary64): orthonormalised factors, the triangular-basis
@@ -314,10 +315,11 @@ void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const doub
                                       bf16);
     gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0f, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, bf16);
     if (st.diag) diag_solve<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
-    else trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
+    else trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag, st.lsym);
     gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0f, st.UA, m, st.Y, m, 0.0f, st.W1, m, 1.0f, bf16);
     gemm<float, float, double, float>(s, 0, 1, m, n, n, (float)(1.0 / bscale), st.W1, m, st.UB, n,
                                       accumulate ? 1.0f : 0.0f, X, ldx, 1.0f, bf16);
+    if (st.lsym) symmetrize(s, m, X, ldx);
 }
 
 template <>
@@ -327,20 +329,27 @@ void correction<double>(hipStream_t s, int m, int n, Stage<double> &st, const do
     gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0, st.W1, m, bscale);
     gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0, st.Y, m);
     if (st.diag) diag_solve<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
-    else trsyl<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
+    else trsyl<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag, st.lsym);
     gemm<double, double, double, double>(s, 0, 0, m, n, m, 1.0, st.UA, m, st.Y, m, 0.0, st.W1, m);
     gemm<double, double, double, double>(s, 0, 1, m, n, n, 1.0 / bscale, st.W1, m, st.UB, n,
                                          accumulate ? 1.0 : 0.0, X, ldx);
+    if (st.lsym) symmetrize(s, m, X, ldx);
 }
 
-// R = C - A X - X op(B); scal[slot] = ||R||_F, scal[slot+1] = max|R|, scal[slot+2] = ||X||_F
+// R = C - A X - X op(B); scal[slot] = ||R||_F, scal[slot+1] = max|R|, scal[slot+2] = ||X||_F.
+// lsym (Lyapunov, X symmetric): X A^T = (A X)^T, one product.
 static void residual(hipStream_t s, int m, int n, const double *A, int lda, const double *B, int ldb,
                      bool lyap, const double *C, int ldc, const double *X, int ldx, double *R,
-                     double *scal, double *nscr) {
-    cast<double, double>(s, m, n, C, ldc, R, m, 1.0);
-    gemm<double, double, double, double>(s, 0, 0, m, n, m, -1.0, A, lda, X, ldx, 1.0, R, m);
-    if (lyap) gemm<double, double, double, double>(s, 0, 1, m, n, n, -1.0, X, ldx, A, lda, 1.0, R, m);
-    else gemm<double, double, double, double>(s, 0, 0, m, n, n, -1.0, X, ldx, B, ldb, 1.0, R, m);
+                     double *scal, double *nscr, bool lsym = false) {
+    if (lyap && lsym) {
+        gemm<double, double, double, double>(s, 0, 0, m, n, m, -1.0, A, lda, X, ldx, 0.0, R, m);
+        sym_residual(s, m, C, ldc, R, m);
+    } else {
+        cast<double, double>(s, m, n, C, ldc, R, m, 1.0);
+        gemm<double, double, double, double>(s, 0, 0, m, n, m, -1.0, A, lda, X, ldx, 1.0, R, m);
+        if (lyap) gemm<double, double, double, double>(s, 0, 1, m, n, n, -1.0, X, ldx, A, lda, 1.0, R, m);
+        else gemm<double, double, double, double>(s, 0, 0, m, n, n, -1.0, X, ldx, B, ldb, 1.0, R, m);
+    }
     matnorm<double>(s, m, n, R, m, scal + 0, nscr, 0);
     matnorm<double>(s, m, n, R, m, scal + 1, nscr, 1);
     matnorm<double>(s, m, n, X, ldx, scal + 2, nscr, 0);
@@ -394,7 +403,7 @@ static int run_fp64(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
     hipMemsetAsync(p.flag, 0, sizeof(int), s);
     correction<double>(s, m, n, p.hi, C, ldc, 1.0, X, ldx, false, p.scal + 12, p.flag);
     sep_estimate<double>(s, m, n, p.hi.TA, p.hi.TB, p.eig, p.scal + 13, p.nscr);
-    residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr);
+    residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr, p.hi.lsym);
     double h[16];
     hipError_t e = read_scalars(s, c, p.scal, 16, h);
     if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
@@ -449,7 +458,7 @@ static int mixed_refine(hipStream_t s, DevCtx *c, int m, int n, const double *A,
     int it = 0, stall = 0, status = SYLV_ST_NOT_CONVERGED;
     double h[32];
     for (;;) {
-        residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr);
+        residual(s, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p.R, p.scal, p.nscr, p.lo.lsym);
         hipError_t e = read_scalars(s, c, p.scal, 32, h);
         if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
         rel = h[0] / (nm.c + h[2] * (nm.a + nm.b));
@@ -860,8 +869,9 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
         asym_norm(s, m, A, lda, p.scal + 43, p.nscr);
         if (!lyap) asym_norm(s, n, B, ldb, p.scal + 44, p.nscr);
     }
-    double hn[5] = {0, 0, 0, 0, 0};
-    hipError_t e = read_scalars(s, c, p.scal + 40, sym ? 5 : 3, hn);
+    if (lyap) asym_norm(s, m, C, ldc, p.scal + 45, p.nscr);
+    double hn[6] = {0, 0, 0, 0, 0, 0};
+    hipError_t e = read_scalars(s, c, p.scal + 40, lyap ? 6 : (sym ? 5 : 3), hn);
     if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
     Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2]};
     if (sym) {
@@ -873,6 +883,13 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     }
     p.lo.diag = sym ? 1 : 0;
     p.hi.diag = sym ? 1 : 0;
+    // Lyapunov with C symmetric to 2u ||C||_F: the solution is symmetric;
+    // the iterate is kept symmetric, the residual takes one product and the
+    // tri-solve one tile of each mirror pair (Alg. 4.1/4.2 keep the general
+    // forms)
+    const bool lsym = lyap && !alg41 && hn[5] <= 0x1p-52 * hn[2];
+    p.lo.lsym = lsym ? 1 : 0;
+    p.hi.lsym = lsym ? 1 : 0;
     if (info) info->chosen = -1;
     if (!mixed) return run_fp64(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, info);
     if (autosel) return run_auto(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info);

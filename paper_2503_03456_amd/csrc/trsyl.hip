@@ -349,14 +349,16 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
     if (myflag) atomicOr(flag, 1);
 }
 
+// mirror: symmetric Lyapunov (see trsyl_tile); the grid then covers only
+// the tiles with 2J <= d
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
                                                    const T *__restrict__ TB, int ldtb, T *C, int ldc,
                                                    int d, int nI, int jmin, const double *maxab,
-                                                   int *flag) {
+                                                   int *flag, int mirror) {
     const int J = jmin + blockIdx.x;
     const int I = nI - 1 - (d - J);
-    trsyl_tile<T>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag);
+    trsyl_tile<T>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror, mirror && 2 * J < d);
 }
 
 // Batched form: tiles of anti-diagonal d of every active equation
@@ -394,20 +396,22 @@ void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int
 
 template <typename T>
 void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, T *C, int ldc,
-           const double *maxab, int *flag) {
+           const double *maxab, int *flag, int mirror) {
     if (m <= 0 || n <= 0) return;
+    if (m != n) mirror = 0;
     const int nI = (m + TBASE - 1) / TBASE, nJ = (n + TBASE - 1) / TBASE;
     for (int d = 0; d <= nI + nJ - 2; ++d) {
         int jmin = d - (nI - 1) > 0 ? d - (nI - 1) : 0;
         int jmax = d < nJ - 1 ? d : nJ - 1;
+        if (mirror && jmax > d / 2) jmax = d / 2;
         ProfScope ps(KID_TRSYL, s);
         hipLaunchKernelGGL((k_trsyl_diag<T>), dim3(jmax - jmin + 1), dim3(256), 0, s, m, n, TA, ldta,
-                           TB, ldtb, C, ldc, d, nI, jmin, maxab, flag);
+                           TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror);
     }
 }
 template void trsyl<float>(hipStream_t, int, int, const float *, int, const float *, int, float *, int,
-                           const double *, int *);
+                           const double *, int *, int);
 template void trsyl<double>(hipStream_t, int, int, const double *, int, const double *, int, double *,
-                            int, const double *, int *);
+                            int, const double *, int *, int);
 
 }  // namespace sylv

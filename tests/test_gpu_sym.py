@@ -202,3 +202,28 @@ def test_batched_lyapunov_on_eigenvalue_cluster():
     torch.cuda.synchronize()
     for (A, C), X, info in zip(ref, Xs, infos):
         assert info["rel_res"] <= TOL and info["fell_back"] == 0, info
+
+
+@pytest.mark.parametrize("low", ["fp32", "fp64"])
+@pytest.mark.parametrize("n", [1, 64, 65, 200, 300])
+def test_lyapunov_symmetric_rhs_specialisation(n, low):
+    """lyap_solve with a symmetric right-hand side takes the symmetric
+    specialisation (one-product residual, mirrored half tri-solve, iterate
+    kept exactly symmetric); a general right-hand side of the same equation
+    takes the general path.  Both against the oracle."""
+    sy = binding()
+    say(f"lyap symmetric rhs n={n} {low}")
+    A, C, eig = workloads.config4_item(1000 + n, n)
+    lam = eig[:, None] + eig[None, :]
+    kap = np.abs(lam).max() / np.abs(lam).min()
+    for general in (False, True):
+        Cc = np.random.RandomState(n).standard_normal((n, n)) if general else C
+        X, info = sy.lyap(dev(A), dev(Cc), low=low)
+        torch.cuda.synchronize()
+        Xh = host(X)
+        assert info["rel_res"] <= (TOL if low == "fp32" else 1e-13) and info["fell_back"] == 0, info
+        Xo, st = oracle.lyap_solve(A, Cc)
+        assert st == 0
+        assert relerr(Xh, Xo) <= 200 * kap * n * U64 + 1e-15
+        if not general:
+            assert np.array_equal(Xh, Xh.T)
