@@ -289,7 +289,7 @@ int sylv_selector_features(int m, int n, const double *A, int lda, const double 
  * one kernel family (ids: 1 gemm_kernel, 2 k_hess_col, 3 k_hess_gemv,
  * 4 k_aed, 5 k_chase, 6 k_trsyl_diag, 7 k_find_ktop, 8 k_cast,
  * 9 k_sumsq_partial, 10 k_bhess, 11 k_bschur, 12 k_btrsyl,
- * 13 gemm_batched_kernel, 14 k_jac_pairs, 15 k_jac_apply); each later launch of that family is bracketed by two
+ * 13 gemm_batched_kernel, 14 k_jac_pairs, 15 k_jac_apply, 16 k_win_update); each later launch of that family is bracketed by two
  * HIP events recorded on its launch stream.  sylv_profile_end disarms,
  * waits for the events and returns the number of launches and the summed
  * durations in milliseconds, plus the algorithmic work the library

@@ -88,7 +88,7 @@ extern "C" const char *sylv_kernel_name(int kernel_id) {
                                            "k_aed", "k_chase", "k_trsyl_diag", "k_find_ktop",
                                            "k_cast", "k_sumsq_partial", "k_bhess", "k_bschur",
                                            "k_btrsyl", "gemm_batched_kernel", "k_jac_pairs",
-                                           "k_jac_apply"};
+                                           "k_jac_apply", "k_win_update"};
     if (kernel_id < 0 || kernel_id >= KID_COUNT) return "unknown";
     return names[kernel_id];
 }

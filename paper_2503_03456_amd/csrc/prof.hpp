@@ -11,7 +11,7 @@ enum KernelId {
     KID_NONE = 0, KID_GEMM = 1, KID_HESS_COL = 2, KID_HESS_GEMV = 3, KID_AED = 4, KID_CHASE = 5,
     KID_TRSYL = 6, KID_FIND_KTOP = 7, KID_CAST = 8, KID_NORM = 9, KID_BHESS = 10,
     KID_BSCHUR = 11, KID_BTRSYL = 12, KID_BGEMM = 13, KID_JAC_PAIRS = 14, KID_JAC_APPLY = 15,
-    KID_COUNT = 16
+    KID_WIN = 16, KID_COUNT = 17
 };
 
 bool prof_armed(int id);

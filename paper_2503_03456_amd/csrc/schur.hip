@@ -123,13 +123,138 @@ hipError_t readback(Ctx<T> &c, const void *dsrc, size_t bytes) {
     return hipStreamSynchronize(c.s);
 }
 
+// In-place window update on MFMA, all three regions in one launch:
+//   H(w0:w0+w, w0+w:n) <- Z^T H(...)   strips of SS columns,
+//   H(0:w0, w0:w0+w)   <- H(...) Z     strips of SS rows,
+//   U(:, w0:w0+w)      <- U(...) Z     strips of SS rows.
+// Each product reads only its own strip (w <= WMAX rows or columns), so a
+// workgroup caches the whole strip in LDS, multiplies and writes it back in
+// place: no temporary and no copy-back.  Z is staged whole in LDS too
+// (dynamic shared memory: 121 KiB binary32, 131 KiB binary64, one workgroup
+// per CU); the four wavefronts then take the 16x16 output blocks in turn
+// with no further barrier.
+template <typename T>
+struct WinLds {
+    static constexpr int WP = ((SchurCaps<T>::WMAX + 15) / 16) * 16;
+    static constexpr int SS = sizeof(T) == 4 ? 64 : 32;
+    static constexpr int LDK = WP + 1, LDI = SS + 1, LDZ = WP + 1;
+    static constexpr int SZ = (SS * LDK > WP * LDI) ? SS * LDK : WP * LDI;
+    static constexpr size_t bytes = sizeof(T) * ((size_t)SZ + (size_t)WP * LDZ);
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, int ldu, int w0, int w,
+                                                   const T *__restrict__ Z, int nl, int nr) {
+    typedef typename mfma16<T>::v4 v4;
+    typedef WinLds<T> L;
+    constexpr int WP = L::WP, SS = L::SS, LDK = L::LDK, LDI = L::LDI, LDZ = L::LDZ;
+    constexpr int RB = SS / 16;   // 16x16 output blocks across the strip
+    extern __shared__ __align__(16) unsigned char win_smem[];
+    T *S = reinterpret_cast<T *>(win_smem);
+    T *Zs = S + L::SZ;
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+    const int nkk = (w + 3) / 4;
+    const int nch = (w + 15) / 16;
+    int b = blockIdx.x;
+    const bool left = b < nl;
+    T *M;
+    int ldm, r0, c0, ext;   // strip origin in M and its extent (columns for left, rows for right)
+    if (left) {
+        M = H; ldm = ldh;
+        r0 = w0;
+        c0 = w0 + w + SS * b;
+        ext = min(SS, n - c0);
+        // S[j * LDK + k] = H(w0 + k, c0 + j)
+        for (int e = tid; e < SS * WP; e += 256) {
+            const int k = e % WP, j = e / WP;
+            S[j * LDK + k] = (k < w && j < ext) ? CM(M, r0 + k, c0 + j, ldm) : T(0);
+        }
+    } else {
+        b -= nl;
+        int rows;
+        if (b < nr) { M = H; ldm = ldh; rows = w0; }
+        else { b -= nr; M = U; ldm = ldu; rows = n; }
+        r0 = SS * b;
+        c0 = w0;
+        ext = min(SS, rows - r0);
+        // S[k * LDI + i] = M(r0 + i, w0 + k)
+        for (int e = tid; e < SS * WP; e += 256) {
+            const int i = e % SS, k = e / SS;
+            S[k * LDI + i] = (k < w && i < ext) ? CM(M, r0 + i, c0 + k, ldm) : T(0);
+        }
+    }
+    // Zs[j * LDZ + k] = Z(k, j), zero outside w (rows j up to 16 nch)
+    for (int e = tid; e < 16 * nch * WP; e += 256) {
+        const int k = e % WP, j = e / WP;
+        Zs[j * LDZ + k] = (k < w && j < w) ? Z[(size_t)j * w + k] : T(0);
+    }
+    __syncthreads();
+    for (int blk = wv; blk < RB * nch; blk += 4) {
+        const int ob = blk % RB, ch = blk / RB;
+        const int bo = 16 * ob;   // first strip row (right) / column (left) of the block
+        const T *zc = Zs + (16 * ch + (l & 15)) * LDZ;
+        v4 acc = v4{0, 0, 0, 0};
+        if (left) {
+            // out(i, j) = sum_k Z(k, i) S(k, j): i in chunk ch, j in block ob
+            const T *sp = S + (bo + (l & 15)) * LDK;
+            for (int kk = 0; kk < nkk; ++kk) {
+                const int k = 4 * kk + (l >> 4);
+                acc = mfma16<T>::op(sp[k], zc[k], acc);
+            }
+            const int i = 16 * ch + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = bo + mfma16<T>::orow(l, r);
+                if (i < w && j < ext) CM(M, r0 + i, c0 + j, ldm) = acc[r];
+            }
+        } else {
+            // out(i, j) = sum_k S(i, k) Z(k, j): i in block ob, j in chunk ch
+            const T *sp = S + bo + (l & 15);
+            for (int kk = 0; kk < nkk; ++kk) {
+                const int k = 4 * kk + (l >> 4);
+                acc = mfma16<T>::op(zc[k], sp[k * LDI], acc);
+            }
+            const int i = bo + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = 16 * ch + mfma16<T>::orow(l, r);
+                if (i < ext && j < w) CM(M, r0 + i, c0 + j, ldm) = acc[r];
+            }
+        }
+    }
+}
+
+// raises k_win_update's dynamic-LDS limit once per element type
+template <typename T>
+bool win_lds_ready() {
+    static std::once_flag once;
+    static bool ok = false;
+    std::call_once(once, [] {
+        ok = hipFuncSetAttribute((const void *)k_win_update<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)WinLds<T>::bytes) == hipSuccess;
+        if (!ok) (void)hipGetLastError();
+    });
+    return ok;
+}
+
 // Apply a window transform Z (w x w, ld w) acting on rows/cols [w0, w0+w):
 // H(w0:w0+w, w0+w:n) <- Z^T H(...), H(0:w0, w0:w0+w) <- H(...) Z,
-// U(:, w0:w0+w) <- U(...) Z.
+// U(:, w0:w0+w) <- U(...) Z.  Binary32/binary64: the fused in-place kernel;
+// the BF16 option keeps bfloat16-input GEMMs through a temporary.
 template <typename T>
 void apply_window(Ctx<T> &c, int w0, int w, const T *Z) {
     const int n = c.n;
     const int nc = n - (w0 + w);
+    if (!c.bf16 && w <= SchurCaps<T>::WMAX && win_lds_ready<T>()) {
+        constexpr int SS = WinLds<T>::SS;
+        const int nl = nc > 0 ? (nc + SS - 1) / SS : 0;
+        const int nr = (w0 + SS - 1) / SS;
+        const int nu = (n + SS - 1) / SS;
+        ProfScope ps(KID_WIN, c.s);
+        hipLaunchKernelGGL((k_win_update<T>), dim3(nl + nr + nu), dim3(256), WinLds<T>::bytes, c.s, n, c.H,
+                           c.ldh, c.U, c.ldu, w0, w, Z, nl, nr);
+        return;
+    }
     if (nc > 0) {
         T *blk = c.H + (size_t)(w0 + w) * c.ldh + w0;
         gemm<T, T, T, T>(c.s, 1, 0, w, nc, w, T(1), Z, w, blk, c.ldh, T(0), c.tmp, w, T(1), c.bf16);
