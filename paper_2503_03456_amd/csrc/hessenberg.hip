@@ -96,16 +96,21 @@ __global__ __launch_bounds__(HNT) void k_hess_col(int n, T *A, int lda, T *V, T 
         if (tid < i - 1) {
             // T(0:i-1, i-1) = -tau T(0:i-1,0:i-1) w   (T upper triangular)
             T acc = T(0);
+#pragma unroll 8
             for (int j = tid; j < i - 1; ++j) acc += Tp[j * nb + tid] * wv[j];
             cv[tid] = -tp * acc;
         }
         __syncthreads();
         if (tid < i - 1) Tp[(i - 1) * nb + tid] = cv[tid];
         if (tid == 0) Tp[(i - 1) * nb + (i - 1)] = tp;
+        // the loops below have run-time trip counts; unrolling lets their
+        // independent loads overlap (the summation order is unchanged)
         for (int r = tid; r < n; r += HNT) {
             T yr = T(0);
+#pragma unroll 8
             for (int s = 0; s < S; ++s) yr += Ypart[(size_t)s * n + r];
             T acc = T(0);
+#pragma unroll 8
             for (int j = 0; j < i - 1; ++j) acc += CM(Y, r, j, n) * wv[j];
             CM(Y, r, i - 1, n) = tp * (yr - acc);
         }
@@ -119,6 +124,7 @@ __global__ __launch_bounds__(HNT) void k_hess_col(int n, T *A, int lda, T *V, T 
     __syncthreads();
     for (int r = tid; r < n; r += HNT) {
         T acc = T(0);
+#pragma unroll 8
         for (int j = 0; j < i; ++j) acc += CM(Y, r, j, n) * cv[j];
         CM(A, r, col, lda) -= acc;
     }
@@ -140,12 +146,14 @@ __global__ __launch_bounds__(HNT) void k_hess_col(int n, T *A, int lda, T *V, T 
         if (tid < i) {
             // c = T^T b: c(j) = sum_{j' <= j} T(j', j) b(j')
             T acc = T(0);
+#pragma unroll 8
             for (int jp = 0; jp <= tid; ++jp) acc += Tp[tid * nb + jp] * wv[jp];
             cv[tid] = acc;
         }
         __syncthreads();
         for (int r = k0 + 1 + tid; r < n; r += HNT) {
             T acc = T(0);
+#pragma unroll 8
             for (int j = 0; j < i; ++j) acc += CM(V, r, k0 + j, ldv) * cv[j];
             CM(A, r, col, lda) -= acc;
         }
@@ -217,6 +225,7 @@ __global__ __launch_bounds__(256) void k_hess_gemv(int n, const T *A, int lda, c
         for (int q = threadIdx.x; q < cnt; q += 256) vs[q] = CM(V, base + q, col, ldv);
         __syncthreads();
         if (r < n)
+#pragma unroll 8
             for (int q = 0; q < cnt; ++q) acc += CM(A, r, base + q, lda) * vs[q];
     }
     if (r < n) Ypart[(size_t)s * n + r] = acc;
