@@ -54,7 +54,9 @@ SYLV_DEVINL int tile_bound(const T *Tm, int ld, int n, int k) {
 // (y00, y10, y01, y11) -- an order-1 block leaves its entries as identity
 // rows -- so every lane runs the same straight-line code with static
 // register indices: Gaussian elimination with partial pivoting, a pivot
-// below smin replaced by +-smin (flag set).
+// below smin replaced by +-smin (flag set).  Each pivot's reciprocal is
+// formed once (hardware reciprocal, Newton-refined in binary64) and serves
+// both the elimination and the back substitution.
 template <typename T>
 SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T b01, T b10, T b11,
                            T r[4], T smin) {
@@ -68,6 +70,7 @@ SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T 
     if (!Q) r[2] = T(0);
     if (!(P && Q)) r[3] = T(0);
     int flag = 0;
+    T inv[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         // pivot: largest |m[r][c]|, r >= c; swap it into row c with selects
@@ -97,10 +100,10 @@ SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T 
             m[c][c] = piv;
             flag = 1;
         }
-        const T inv = T(1) / piv;
+        inv[c] = frcp(piv);
 #pragma unroll
         for (int rr = c + 1; rr < 4; ++rr) {
-            const T f = m[rr][c] * inv;
+            const T f = m[rr][c] * inv[c];
 #pragma unroll
             for (int k = c + 1; k < 4; ++k) m[rr][k] -= f * m[c][k];
             r[rr] -= f * r[c];
@@ -111,28 +114,8 @@ SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T 
         T acc = r[c];
 #pragma unroll
         for (int k = c + 1; k < 4; ++k) acc -= m[c][k] * r[k];
-        r[c] = acc / m[c][c];
+        r[c] = acc * inv[c];
     }
-    return flag;
-}
-
-// The 2 x 2 case of the block-pair system (one block of order 2, the other
-// of order 1): the same partial-pivoting elimination as the 4 x 4 embedding
-// restricted to its two live rows (the identity rows never pivot), with the
-// same smin rule, in straight-line code.
-template <typename T>
-SYLV_DEVINL int pair2_solve(T m00, T m01, T m10, T m11, T &r0, T &r1, T smin) {
-    int flag = 0;
-    const bool sw = fabs(m10) > fabs(m00);
-    T p00 = sw ? m10 : m00, p01 = sw ? m11 : m01, q0 = sw ? r1 : r0;
-    const T o10 = sw ? m00 : m10, o11 = sw ? m01 : m11, q1 = sw ? r0 : r1;
-    if (fabs(p00) < smin) { p00 = (p00 >= T(0)) ? smin : -smin; flag = 1; }
-    const T f = o10 * (T(1) / p00);
-    T u11 = o11 - f * p01;
-    const T s1 = q1 - f * q0;
-    if (fabs(u11) < smin) { u11 = (u11 >= T(0)) ? smin : -smin; flag = 1; }
-    r1 = s1 / u11;
-    r0 = (q0 - p01 * r1) / p00;
     return flag;
 }
 
@@ -274,31 +257,28 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
             const int ib = P - 1 - ibb;
             ri = rstart[ib]; pi = rstart[ib + 1] - ri;
             cj = cstart[jb]; qj = cstart[jb + 1] - cj;
-            // rows below the block: r' in [ri+pi, p) ; cols left: c' in [0, cj)
-            if (pi == 1 && qj == 1) {
-#pragma unroll 4
-                for (int rp = ri + 1 + sub; rp < p; rp += tpu) part[0] += sA[rp * TLD + ri] * sC[cj * TLD + rp];
-#pragma unroll 4
-                for (int cp = sub; cp < cj; cp += tpu) part[0] += sC[cp * TLD + ri] * sB[cj * TLD + cp];
-            } else {
+            // rows below the block: r' in [ri+pi, p) ; cols left: c' in [0, cj).
+            // One loop for every block shape (an order-1 block masks its
+            // second row or column), so units of different shapes sharing
+            // a wavefront do not split it.
+            const bool P2 = (pi == 2), Q2 = (qj == 2);
 #pragma unroll 2
-                for (int rp = ri + pi + sub; rp < p; rp += tpu) {
-                    T a0 = sA[rp * TLD + ri];
-                    T a1 = (pi == 2) ? sA[rp * TLD + ri + 1] : T(0);
-                    T y0 = sC[cj * TLD + rp];
-                    T y1 = (qj == 2) ? sC[(cj + 1) * TLD + rp] : T(0);
-                    part[0] += a0 * y0; part[1] += a1 * y0;
-                    part[2] += a0 * y1; part[3] += a1 * y1;
-                }
+            for (int rp = ri + pi + sub; rp < p; rp += tpu) {
+                const T a0 = sA[rp * TLD + ri];
+                const T a1 = P2 ? sA[rp * TLD + ri + 1] : T(0);
+                const T y0 = sC[cj * TLD + rp];
+                const T y1 = Q2 ? sC[(cj + 1) * TLD + rp] : T(0);
+                part[0] += a0 * y0; part[1] += a1 * y0;
+                part[2] += a0 * y1; part[3] += a1 * y1;
+            }
 #pragma unroll 2
-                for (int cp = sub; cp < cj; cp += tpu) {
-                    T b0 = sB[cj * TLD + cp];
-                    T b1 = (qj == 2) ? sB[(cj + 1) * TLD + cp] : T(0);
-                    T y0 = sC[cp * TLD + ri];
-                    T y1 = (pi == 2) ? sC[cp * TLD + ri + 1] : T(0);
-                    part[0] += y0 * b0; part[1] += y1 * b0;
-                    part[2] += y0 * b1; part[3] += y1 * b1;
-                }
+            for (int cp = sub; cp < cj; cp += tpu) {
+                const T b0 = sB[cj * TLD + cp];
+                const T b1 = Q2 ? sB[(cj + 1) * TLD + cp] : T(0);
+                const T y0 = sC[cp * TLD + ri];
+                const T y1 = P2 ? sC[cp * TLD + ri + 1] : T(0);
+                part[0] += y0 * b0; part[1] += y1 * b0;
+                part[2] += y0 * b1; part[3] += y1 * b1;
             }
         }
         for (int o = 1; o < tpu; o <<= 1) {
@@ -306,34 +286,28 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
             for (int z = 0; z < 4; ++z) part[z] += __shfl_xor(part[z], o);
         }
         if (active && sub == 0) {
-            if (pi == 1 && qj == 1) {
-                T d = sA[ri * TLD + ri] + sB[cj * TLD + cj];
-                if (fabs(d) < smin) { d = (d >= T(0)) ? smin : -smin; myflag = 1; }
-                sC[cj * TLD + ri] = (sC[cj * TLD + ri] - part[0]) / d;
-            } else {
-                const bool P = (pi == 2), Q = (qj == 2);
-                const T a00 = sA[ri * TLD + ri];
-                const T a01 = P ? sA[(ri + 1) * TLD + ri] : T(0);
-                const T a10 = P ? sA[ri * TLD + ri + 1] : T(0);
-                const T a11 = P ? sA[(ri + 1) * TLD + ri + 1] : T(0);
-                const T b00 = sB[cj * TLD + cj];
-                const T b01 = Q ? sB[(cj + 1) * TLD + cj] : T(0);
-                const T b10 = Q ? sB[cj * TLD + cj + 1] : T(0);
-                const T b11 = Q ? sB[(cj + 1) * TLD + cj + 1] : T(0);
-                // rhs entries (y00, y10, y01, y11) minus the accumulated sums
-                T r[4];
-                r[0] = sC[cj * TLD + ri] - part[0];
-                r[1] = P ? sC[cj * TLD + ri + 1] - part[1] : T(0);
-                r[2] = Q ? sC[(cj + 1) * TLD + ri] - part[2] : T(0);
-                r[3] = (P && Q) ? sC[(cj + 1) * TLD + ri + 1] - part[3] : T(0);
-                if (P && Q) myflag |= pair_solve<T>(P, Q, a00, a01, a10, a11, b00, b01, b10, b11, r, smin);
-                else if (P) myflag |= pair2_solve<T>(a00 + b00, a01, a10, a11 + b00, r[0], r[1], smin);
-                else myflag |= pair2_solve<T>(a00 + b00, b10, b01, a00 + b11, r[0], r[2], smin);
-                sC[cj * TLD + ri] = r[0];
-                if (P) sC[cj * TLD + ri + 1] = r[1];
-                if (Q) sC[(cj + 1) * TLD + ri] = r[2];
-                if (P && Q) sC[(cj + 1) * TLD + ri + 1] = r[3];
-            }
+            // every block pair through the 4 x 4 embedding (order-1 blocks
+            // as identity rows): one code path for all shapes
+            const bool P2 = (pi == 2), Q2 = (qj == 2);
+            const T a00 = sA[ri * TLD + ri];
+            const T a01 = P2 ? sA[(ri + 1) * TLD + ri] : T(0);
+            const T a10 = P2 ? sA[ri * TLD + ri + 1] : T(0);
+            const T a11 = P2 ? sA[(ri + 1) * TLD + ri + 1] : T(0);
+            const T b00 = sB[cj * TLD + cj];
+            const T b01 = Q2 ? sB[(cj + 1) * TLD + cj] : T(0);
+            const T b10 = Q2 ? sB[cj * TLD + cj + 1] : T(0);
+            const T b11 = Q2 ? sB[(cj + 1) * TLD + cj + 1] : T(0);
+            // rhs entries (y00, y10, y01, y11) minus the accumulated sums
+            T r[4];
+            r[0] = sC[cj * TLD + ri] - part[0];
+            r[1] = P2 ? sC[cj * TLD + ri + 1] - part[1] : T(0);
+            r[2] = Q2 ? sC[(cj + 1) * TLD + ri] - part[2] : T(0);
+            r[3] = (P2 && Q2) ? sC[(cj + 1) * TLD + ri + 1] - part[3] : T(0);
+            myflag |= pair_solve<T>(P2, Q2, a00, a01, a10, a11, b00, b01, b10, b11, r, smin);
+            sC[cj * TLD + ri] = r[0];
+            if (P2) sC[cj * TLD + ri + 1] = r[1];
+            if (Q2) sC[(cj + 1) * TLD + ri] = r[2];
+            if (P2 && Q2) sC[(cj + 1) * TLD + ri + 1] = r[3];
         }
         __syncthreads();
     }
