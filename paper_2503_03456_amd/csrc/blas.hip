@@ -172,44 +172,29 @@ void matnorm(hipStream_t s, int r, int c, const T *a, int ld, double *out, doubl
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, nb, scratch, out, mode);
 }
 // Symmetric Lyapunov residual: on entry R = -A X with X = X^T, so
-// X A^T = (A X)^T and C - A X - X A^T = C + R + R^T.  One thread per entry
-// pair (i, j), (j, i) (the thread of the lower entry skips it).
-__global__ __launch_bounds__(256) void k_sym_residual(int n, const double *__restrict__ C, int ldc, double *R,
-                                                      int ldr) {
-    const size_t total = (size_t)n * n;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % n), j = (int)(e / n);
-        if (i > j) continue;
-        const double w = R[(size_t)j * ldr + i] + R[(size_t)i * ldr + j];
-        R[(size_t)j * ldr + i] = C[(size_t)j * ldc + i] + w;
-        if (i != j) R[(size_t)i * ldr + j] = C[(size_t)i * ldc + j] + w;
-    }
+// X A^T = (A X)^T and C - A X - X A^T = C + R + R^T; and X <- (X + X^T)/2.
+// One workgroup per 32 x 32 tile pair (sym_tile_pair).
+__global__ __launch_bounds__(256) void k_sym_pairs(int n, const double *__restrict__ C, int ldc, double *R, int ldr,
+                                                   int res) {
+    __shared__ double sa[32][33], sb[32][33];
+    int ti, tj;
+    sym_pair_index(blockIdx.x, ti, tj);
+    sym_tile_pair(res != 0, n, C, ldc, R, ldr, ti, tj, sa, sb);
 }
 
-// X <- (X + X^T) / 2
-__global__ __launch_bounds__(256) void k_symmetrize(int n, double *X, int ldx) {
-    const size_t total = (size_t)n * n;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % n), j = (int)(e / n);
-        if (i >= j) continue;
-        const double v = 0.5 * (X[(size_t)j * ldx + i] + X[(size_t)i * ldx + j]);
-        X[(size_t)j * ldx + i] = v;
-        X[(size_t)i * ldx + j] = v;
-    }
+static unsigned sym_grid(int n) {
+    const unsigned nt = (unsigned)(n + 31) / 32;
+    return nt * (nt + 1) / 2;
 }
 
 void sym_residual(hipStream_t s, int n, const double *C, int ldc, double *R, int ldr) {
     if (n <= 0) return;
-    const size_t b = ((size_t)n * n + 255) / 256;
-    hipLaunchKernelGGL(k_sym_residual, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(256), 0, s, n, C, ldc, R, ldr);
+    hipLaunchKernelGGL(k_sym_pairs, dim3(sym_grid(n)), dim3(256), 0, s, n, C, ldc, R, ldr, 1);
 }
 
 void symmetrize(hipStream_t s, int n, double *X, int ldx) {
     if (n <= 0) return;
-    const size_t b = ((size_t)n * n + 255) / 256;
-    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(256), 0, s, n, X, ldx);
+    hipLaunchKernelGGL(k_sym_pairs, dim3(sym_grid(n)), dim3(256), 0, s, n, (const double *)nullptr, 0, X, ldx, 0);
 }
 
 template void matnorm<float>(hipStream_t, int, int, const float *, int, double *, double *, int);

@@ -88,6 +88,48 @@ template <> struct mfma16<double> {
     static SYLV_DEVINL int orow(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
+// Symmetric Lyapunov helpers on one pair of 32 x 32 tiles (ti <= tj) of an
+// n x n binary64 matrix R, in place, 256 threads.  Both tiles are staged in
+// LDS so that every global access runs down columns (coalesced):
+//   res = true:  R(i, j) <- C(i, j) + w, w = R(i, j) + R(j, i)  (R = -A X on entry)
+//   res = false: R(i, j) <- (R(i, j) + R(j, i)) / 2
+// w is the same sum for (i, j) and (j, i), so the result of res = false is
+// exactly symmetric.  sa, sb: 32 x 33 doubles of LDS each.
+SYLV_DEVINL int sym_pair_count(int n) {
+    const int nt = (n + 31) / 32;
+    return nt * (nt + 1) / 2;
+}
+SYLV_DEVINL void sym_pair_index(int k, int &ti, int &tj) {
+    // k = tj (tj + 1) / 2 + ti, 0 <= ti <= tj
+    int j = (int)((sqrt(8.0 * k + 1.0) - 1.0) * 0.5);
+    while (j * (j + 1) / 2 > k) --j;
+    while ((j + 1) * (j + 2) / 2 <= k) ++j;
+    tj = j;
+    ti = k - j * (j + 1) / 2;
+}
+SYLV_DEVINL void sym_tile_pair(bool res, int n, const double *C, int ldc, double *R, int ldr, int ti, int tj,
+                               double (*sa)[33], double (*sb)[33]) {
+    const int r0 = 32 * ti, c0 = 32 * tj;
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int ii = e & 31, jj = e >> 5;
+        // sa[jj][ii] = R(r0 + ii, c0 + jj), sb[jj][ii] = R(c0 + ii, r0 + jj)
+        sa[jj][ii] = (r0 + ii < n && c0 + jj < n) ? R[(size_t)(c0 + jj) * ldr + r0 + ii] : 0.0;
+        sb[jj][ii] = (c0 + ii < n && r0 + jj < n) ? R[(size_t)(r0 + jj) * ldr + c0 + ii] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int ii = e & 31, jj = e >> 5;
+        if (r0 + ii < n && c0 + jj < n) {
+            const double w = sa[jj][ii] + sb[ii][jj];   // R(i, j) + R(j, i)
+            R[(size_t)(c0 + jj) * ldr + r0 + ii] = res ? C[(size_t)(c0 + jj) * ldc + r0 + ii] + w : 0.5 * w;
+        }
+        if (ti != tj && c0 + ii < n && r0 + jj < n) {
+            const double w = sa[ii][jj] + sb[jj][ii];   // R(j', i') + R(i', j'), same sum
+            R[(size_t)(r0 + jj) * ldr + c0 + ii] = res ? C[(size_t)(r0 + jj) * ldc + c0 + ii] + w : 0.5 * w;
+        }
+    }
+}
+
 // First column (x, y, z) of (H - s1 I)(H - s2 I) e1 for the leading 3x2
 // corner a00 a01 / a10 a11 / . a21 of an unreduced Hessenberg block, up to a
 // positive scale.  The shifts are a real pair (cplx = 0: s1 = p, s2 = q) or

@@ -591,38 +591,29 @@ __global__ __launch_bounds__(BNT) void k_bcopy_c(BatchEq *eqs, const int *order)
 
 // Symmetric specialisation: with X = X^T, X A^T = (A X)^T, so after
 // R = -A X the residual is C - A X - X A^T = C + R + R^T (one product
-// instead of two).  Each thread owns an entry pair (i, j), (j, i).
-__global__ __launch_bounds__(BNT) void k_bsymres(BatchEq *eqs, const int *order) {
-    BatchEq &q = eqs[order[blockIdx.x]];
+// instead of two).  grid.x = tile pair, grid.y = equation slot.
+__global__ __launch_bounds__(256) void k_bsymres(BatchEq *eqs, const int *order) {
+    __shared__ double sa[32][33], sb[32][33];
+    BatchEq &q = eqs[order[blockIdx.y]];
     if (!q.active || !q.sym) return;
     const int n = q.n;
-    const double *C = (const double *)q.ptr[BF_C];
-    double *R = (double *)q.ptr[BF_R];
-    const int ldc = q.ld[BF_C];
-    for (int e = threadIdx.x; e < n * n; e += BNT) {
-        const int i = e % n, j = e / n;
-        if (i > j) continue;
-        const double w = R[(size_t)j * n + i] + R[(size_t)i * n + j];
-        R[(size_t)j * n + i] = C[(size_t)j * ldc + i] + w;
-        if (i != j) R[(size_t)i * n + j] = C[(size_t)i * ldc + j] + w;
-    }
+    if ((int)blockIdx.x >= sym_pair_count(n)) return;
+    int ti, tj;
+    sym_pair_index(blockIdx.x, ti, tj);
+    sym_tile_pair(true, n, (const double *)q.ptr[BF_C], q.ld[BF_C], (double *)q.ptr[BF_R], n, ti, tj, sa, sb);
 }
 
 // X <- (X + X^T) / 2 for the symmetric specialisation (keeps the iterate
 // exactly symmetric, which the one-product residual relies on)
-__global__ __launch_bounds__(BNT) void k_bsymx(BatchEq *eqs, const int *order) {
-    BatchEq &q = eqs[order[blockIdx.x]];
+__global__ __launch_bounds__(256) void k_bsymx(BatchEq *eqs, const int *order) {
+    __shared__ double sa[32][33], sb[32][33];
+    BatchEq &q = eqs[order[blockIdx.y]];
     if (!q.active || !q.sym) return;
     const int n = q.n;
-    double *X = (double *)q.ptr[BF_X];
-    const int ldx = q.ld[BF_X];
-    for (int e = threadIdx.x; e < n * n; e += BNT) {
-        const int i = e % n, j = e / n;
-        if (i >= j) continue;
-        const double v = 0.5 * (X[(size_t)j * ldx + i] + X[(size_t)i * ldx + j]);
-        X[(size_t)j * ldx + i] = v;
-        X[(size_t)i * ldx + j] = v;
-    }
+    if ((int)blockIdx.x >= sym_pair_count(n)) return;
+    int ti, tj;
+    sym_pair_index(blockIdx.x, ti, tj);
+    sym_tile_pair(false, n, nullptr, 0, (double *)q.ptr[BF_X], q.ld[BF_X], ti, tj, sa, sb);
 }
 
 __global__ __launch_bounds__(BNT) void k_bnorm(BatchEq *eqs, const int *order, double tol,
@@ -680,6 +671,12 @@ __global__ void k_bzero(int *p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
+// 32 x 32 tile pairs (ti <= tj) of an order-n matrix
+static int sym_pairs(int n) {
+    const int nt = (n + 31) / 32;
+    return nt * (nt + 1) / 2;
+}
+
 struct BatchPlan {
     BatchEq *deq;
     int *dord, *dcnt;
@@ -720,7 +717,7 @@ static void enqueue_front(hipStream_t s, const BatchPlan &P) {
                                              P.bf16);
     gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 0, 0.f,
                                               P.bf16);
-    hipLaunchKernelGGL(k_bsymx, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
+    hipLaunchKernelGGL(k_bsymx, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
 }
 
 // binary64 residual R = C - A X - X A^T (one product for symmetric
@@ -733,7 +730,7 @@ static void enqueue_pass(hipStream_t s, const BatchPlan &P, bool) {
                                                  1.0);
     gemm_batched<double, double, double, double>(s, P.deq, P.dord, batch, P.nmax, BF_X, 0, BF_A, 1, BF_R, -1.0, 4,
                                                  1.0);
-    hipLaunchKernelGGL(k_bsymres, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
+    hipLaunchKernelGGL(k_bsymres, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
     hipLaunchKernelGGL(k_bzero, dim3(1), dim3(64), 0, s, P.dcnt);
     hipLaunchKernelGGL(k_bnorm, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord, P.tol, P.max_iter, P.dcnt);
 }
@@ -751,7 +748,7 @@ static void enqueue_correction(hipStream_t s, const BatchPlan &P) {
                                              P.bf16);
     gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 1.f,
                                               P.bf16);
-    hipLaunchKernelGGL(k_bsymx, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
+    hipLaunchKernelGGL(k_bsymx, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
 }
 
 // ------------------------------------------------------------- hipGraph
