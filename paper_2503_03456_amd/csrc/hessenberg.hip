@@ -205,6 +205,244 @@ __global__ __launch_bounds__(HNT) void k_hess_col(int n, T *A, int lda, T *V, T 
     if (tid == 0) tau[col] = tc;
 }
 
+// ------------------------------------------------- register-resident variant
+// The same per-column step for n <= NQ * HNT with the column held in
+// registers (each thread owns rows tid + q HNT, q < NQ), arranged for
+// latency: every loop issues its loads unconditionally (clamped indices,
+// masked values) so they overlap, the two panel reductions run one
+// wavefront per (column, row part) with a single shuffle tree each, y and the
+// right update share one pass over Y, and the column is read from and written
+// to global memory once.  Requires nb <= 32.
+
+template <typename T>
+SYLV_DEVINL T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// out[j] = sum_{r in [r0, n)} V(r, k0 + j) xs[r] for j < cnt (cnt <= 32),
+// xs in LDS indexed by row.  Work unit = (column, part of the rows): with cnt
+// columns over NWV wavefronts each column's rows split into P = NWV / cnt
+// parts (P = 1 once cnt >= NWV); parts combine in a fixed order.
+template <typename T>
+SYLV_DEVINL void panel_dots(int n, int r0, const T *V, int ldv, int k0, int cnt, const T *xs, T *part,
+                            T *out) {
+    constexpr int NWV = HNT / 64;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int P = cnt >= NWV ? 1 : NWV / (cnt > 0 ? cnt : 1);
+    if (cnt > 0) {
+        const int rows = n - r0;
+        const int chunk = ((rows + P - 1) / P + 63) & ~63;
+        for (int u = w; u < cnt * P; u += NWV) {
+            const int j = u / P, p = u - j * P;
+            const int lo = r0 + p * chunk;
+            const int hi = (lo + chunk < n) ? lo + chunk : n;
+            const T *vc = V + (size_t)(k0 + j) * ldv;
+            T acc = T(0);
+#pragma unroll 8
+            for (int r = lo + lane; r < hi; r += 64) acc += vc[r] * xs[r];
+            acc = wave_sum(acc);
+            if (lane == 0) part[j * NWV + p] = acc;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+        T sum = T(0);
+        for (int p = 0; p < P; ++p) sum += part[threadIdx.x * NWV + p];
+        out[threadIdx.x] = sum;
+    }
+    __syncthreads();
+}
+
+template <typename T, int NQ>
+__global__ __launch_bounds__(HNT) void k_hess_col_r(int n, T *A, int lda, T *V, T *Tp, int nb, T *Y,
+                                                   const T *Ypart, int S, T *tau, int k0, int i,
+                                                   int finalize_only) {
+    constexpr int NWV = HNT / 64;
+    __shared__ T xs[NQ * HNT];
+    __shared__ T tps[32 * 32];  // panel T, column c at tps[32 c]
+    __shared__ T part[32 * NWV];
+    __shared__ T wv[32], cm[32], cc[32], bv[32];
+    __shared__ T red[NWV];
+    __shared__ T sh[4];
+    const int tid = threadIdx.x;
+    const int ldv = n;
+    const int col = k0 + i;
+    const bool upd = !finalize_only;
+    // stage: finished columns of T, the row V(col, k0:k0+i) (right update
+    // coefficients, zero beyond), and for i > 0 the vector v_{i-1}
+    for (int e = tid; e < 32 * 32; e += HNT) {
+        const int c = e >> 5, r = e & 31;
+        tps[e] = (c < i - 1 && r < nb) ? Tp[c * nb + r] : T(0);
+    }
+    if (tid < 32) cm[tid] = (upd && tid < i) ? CM(V, col, k0 + tid, ldv) : T(0);
+    const int cp = k0 + i - 1;
+    if (i > 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int r = tid + q * HNT;
+            if (r < n) xs[r] = CM(V, r, cp, ldv);
+        }
+    }
+    __syncthreads();
+    T yfix = T(0);
+    if (i > 0) {
+        // w = V(:, k0:k0+i-1)^T v_{i-1}; T(0:i-1, i-1) = -tau T(0:i-1, 0:i-1) w
+        panel_dots(n, cp + 1, V, ldv, k0, i - 1, xs, part, wv);
+        const T tp = tau[cp];
+        if (tid < 32) {
+            T acc = T(0);
+            for (int j = tid; j < i - 1; ++j) acc += tps[j * 32 + tid] * wv[j];
+            const T v = (tid < i - 1) ? -tp * acc : (tid == i - 1 ? tp : T(0));
+            if (tid < i) {
+                tps[(i - 1) * 32 + tid] = v;
+                Tp[(i - 1) * nb + tid] = v;
+            }
+            if (tid >= i - 1) wv[tid] = T(0);  // mask for the Y pass
+        }
+        __syncthreads();
+        yfix = tp;
+    }
+    // one pass over Y: y_{i-1}(r) = tau (sum_s Ypart(s, r) - Y(r, 0:i-1) w) and
+    // the right update a(r) -= Y(r, 0:i) V(col, k0:k0+i)^T
+    T a[NQ];
+    int rr[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        rr[q] = tid + q * HNT;
+        a[q] = (upd && rr[q] < n) ? CM(A, rr[q], col, lda) : T(0);
+    }
+    if (i > 0) {
+        T yr[NQ], s1[NQ], s2[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) { yr[q] = T(0); s1[q] = T(0); s2[q] = T(0); }
+        for (int sb = 0; sb < S; sb += 8) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int sc = (sb + t < S) ? sb + t : S - 1;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int r = rr[q] < n ? rr[q] : n - 1;
+                    const T v = Ypart[(size_t)sc * n + r];
+                    yr[q] += (sb + t < S) ? v : T(0);
+                }
+            }
+        }
+        const int jm = i >= 2 ? i - 2 : 0;
+        for (int jb = 0; jb < i - 1; jb += 8) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = jb + t;
+                const int jc = j < jm ? j : jm;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int r = rr[q] < n ? rr[q] : n - 1;
+                    T yv = CM(Y, r, jc, n);
+                    yv = (j < i - 1) ? yv : T(0);
+                    s1[q] += yv * wv[j & 31];
+                    s2[q] += yv * cm[j & 31];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (rr[q] < n) {
+                const T y = yfix * (yr[q] - s1[q]);
+                CM(Y, rr[q], i - 1, n) = y;
+                a[q] -= s2[q] + y * cm[i - 1];
+            }
+        }
+    }
+    if (finalize_only) return;
+    // left update on rows k0+1..n-1: a -= V T^T (V^T a)
+    if (i > 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (rr[q] < n) xs[rr[q]] = a[q];
+        __syncthreads();
+        panel_dots(n, k0 + 1, V, ldv, k0, i, xs, part, bv);
+        if (tid < 32) {
+            // c = T^T b: c(t) = sum_{j <= t} T(j, t) b(j)
+            T acc = T(0);
+            if (tid < i)
+                for (int jp = 0; jp <= tid; ++jp) acc += tps[tid * 32 + jp] * bv[jp];
+            cc[tid] = acc;
+        }
+        __syncthreads();
+        T s3[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s3[q] = T(0);
+        const int jm = i - 1;
+        for (int jb = 0; jb < i; jb += 8) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = jb + t;
+                const int jc = j < jm ? j : jm;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int r = rr[q] < n ? rr[q] : n - 1;
+                    T vv = CM(V, r, k0 + jc, ldv);
+                    vv = (j < i) ? vv : T(0);
+                    s3[q] += vv * cc[j & 31];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (rr[q] >= k0 + 1 && rr[q] < n) a[q] -= s3[q];
+    }
+    // Householder vector for a(col+1:n): zeros below col+1
+    const int len = n - col - 1;
+    T mx = T(0);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (rr[q] >= col + 2 && rr[q] < n) mx = fmax(mx, fabs(a[q]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (rr[q] == col + 1) sh[3] = a[q];
+    __syncthreads();
+    mx = T(0);
+    for (int w = 0; w < NWV; ++w) mx = fmax(mx, red[w]);
+    T ss = T(0);
+    if (mx > T(0)) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (rr[q] >= col + 2 && rr[q] < n) {
+                const T z = a[q] / mx;
+                ss += z * z;
+            }
+    }
+    ss = block_sum(ss, red);
+    if (tid == 0) {
+        const T alpha = sh[3];
+        if (mx == T(0) || len < 2) {
+            sh[0] = T(0); sh[1] = alpha; sh[2] = T(0);
+        } else {
+            const T xn = mx * sqrt(ss);
+            const T nrm = hypot(alpha, xn);
+            const T b = (alpha >= T(0)) ? -nrm : nrm;
+            sh[0] = (b - alpha) / b;
+            sh[1] = b;
+            sh[2] = T(1) / (alpha - b);
+        }
+    }
+    __syncthreads();
+    const T tc = sh[0], beta = sh[1], scl = sh[2];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int r = rr[q];
+        if (r < n) {
+            CM(V, r, col, ldv) = (r <= col) ? T(0) : (r == col + 1 ? T(1) : a[q] * scl);
+            CM(A, r, col, lda) = (r <= col) ? a[q] : (r == col + 1 ? beta : T(0));
+        }
+    }
+    if (tid == 0) tau[col] = tc;
+}
+
 // Ypart[s][r] = sum_{c in slice s} A(r, c) v(c), c in [col+1, n)
 template <typename T>
 __global__ __launch_bounds__(256) void k_hess_gemv(int n, const T *A, int lda, const T *V, int col,
@@ -244,6 +482,25 @@ size_t hessenberg_work_elems(int n, int nb, int S) {
 template size_t hessenberg_work_elems<float>(int, int, int);
 template size_t hessenberg_work_elems<double>(int, int, int);
 
+// One column step: the register-resident kernel while the column fits
+// (n <= 4 HNT, nb <= 32), else the general one.
+template <typename T>
+static void hess_col(hipStream_t s, int n, T *A, int lda, T *V, T *Tp, int nb, T *Y, const T *Ypart, int S,
+                     T *tau, int k0, int i, int fin) {
+    if (nb <= 32 && n <= HNT)
+        hipLaunchKernelGGL((k_hess_col_r<T, 1>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart, S,
+                           tau, k0, i, fin);
+    else if (nb <= 32 && n <= 2 * HNT)
+        hipLaunchKernelGGL((k_hess_col_r<T, 2>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart, S,
+                           tau, k0, i, fin);
+    else if (nb <= 32 && n <= 4 * HNT)
+        hipLaunchKernelGGL((k_hess_col_r<T, 4>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart, S,
+                           tau, k0, i, fin);
+    else
+        hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart, S, tau,
+                           k0, i, fin);
+}
+
 // A (n x n) -> H in place; U (n x n) receives U0.  work: hessenberg_work_elems.
 template <typename T>
 void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int nb, int S, int bf16) {
@@ -268,8 +525,7 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
         for (int i = 0; i < nbp; ++i) {
             {
                 ProfScope ps(KID_HESS_COL, s);
-                hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y,
-                                   Ypart, S, tau, k0, i, 0);
+                hess_col<T>(s, n, A, lda, V, Tp, nb, Y, Ypart, S, tau, k0, i, 0);
             }
             {
                 ProfScope ps(KID_HESS_GEMV, s);
@@ -277,8 +533,7 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
                                    Ypart, S);
             }
         }
-        hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart,
-                           S, tau, k0, nbp, 1);
+        hess_col<T>(s, n, A, lda, V, Tp, nb, Y, Ypart, S, tau, k0, nbp, 1);
         const int c1 = k0 + nbp;  // first trailing column
         const int nt = n - c1;
         if (nt > 0) {

@@ -229,6 +229,152 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
     return 0;
 }
 
+// -------------------------------------------------------- francis_wave
+// The same double-shift QR sweeps for a window of order n <= 64, run by one
+// wavefront: lane i owns row / column i.  Every lane forms the same
+// reflector; the left update (columns of rows k..k+2), the right update
+// (rows of columns k..k+2) and the Z update of a bulge step follow each other
+// in program order, and the LDS operations of one wavefront complete in
+// order, so a step needs no barrier.  The deflation scan is a ballot.
+// Returns 0, or 1 when the iteration cap ran out.
+// Orders the LDS accesses of one wavefront around this point (a compiler
+// fence at wavefront scope; the hardware keeps a wave's LDS operations in order).
+SYLV_DEVINL void wave_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+SYLV_DEVINL int francis_wave(int n, T *H, int ldh, T *Z, int ldz, int nz, int *nsweep, int *nstep) {
+    const int lane = threadIdx.x & 63;
+    const T ulp = num<T>::ulp, smlnum = num<T>::safmin * T(n) / num<T>::ulp;
+    int ihi = n - 1, its = 0, total = 0;
+    const int itmax = 30 * (n > 10 ? n : 10);
+    while (ihi >= 0) {
+        bool neg = false;
+        if (lane >= 1 && lane <= ihi) {
+            const int k = lane;
+            const T hk = fabs(CM(H, k, k - 1, ldh));
+            T tst = fabs(CM(H, k - 1, k - 1, ldh)) + fabs(CM(H, k, k, ldh));
+            if (tst == T(0)) {
+                if (k >= 2) tst += fabs(CM(H, k - 1, k - 2, ldh));
+                if (k + 1 <= ihi) tst += fabs(CM(H, k + 1, k, ldh));
+            }
+            neg = hk <= fmax(smlnum, ulp * tst);
+        }
+        const unsigned long long mask = __ballot(neg);
+        const int l = mask ? 63 - __clzll(mask) : 0;   // largest negligible index
+        wave_order();
+        if (l > 0 && lane == 0) CM(H, l, l - 1, ldh) = T(0);
+        wave_order();
+        if (l == ihi) { ihi -= 1; its = 0; continue; }
+        if (l == ihi - 1) {
+            // 2x2 block: split by one rotation when its eigenvalues are real
+            const int k = l;
+            const T a = CM(H, k, k, ldh), b = CM(H, k, k + 1, ldh);
+            const T c = CM(H, k + 1, k, ldh), d = CM(H, k + 1, k + 1, ldh);
+            const T pp = T(0.5) * (a - d), disc = pp * pp + b * c;
+            wave_order();
+            if (c != T(0) && disc >= T(0)) {
+                const T e1 = pp + copysign(sqrt(disc), pp);
+                const T nv = hypot(e1, c);
+                const T cs = e1 / nv, sn = c / nv;
+                if (lane >= k && lane < n) {
+                    const int j = lane;
+                    const T t1 = CM(H, k, j, ldh), t2 = CM(H, k + 1, j, ldh);
+                    CM(H, k, j, ldh) = cs * t1 + sn * t2;
+                    CM(H, k + 1, j, ldh) = cs * t2 - sn * t1;
+                }
+                wave_order();
+                if (lane <= k + 1) {
+                    const int i = lane;
+                    const T t1 = CM(H, i, k, ldh), t2 = CM(H, i, k + 1, ldh);
+                    CM(H, i, k, ldh) = cs * t1 + sn * t2;
+                    CM(H, i, k + 1, ldh) = cs * t2 - sn * t1;
+                }
+                if (lane < nz) {
+                    const int i = lane;
+                    const T t1 = CM(Z, i, k, ldz), t2 = CM(Z, i, k + 1, ldz);
+                    CM(Z, i, k, ldz) = cs * t1 + sn * t2;
+                    CM(Z, i, k + 1, ldz) = cs * t2 - sn * t1;
+                }
+                wave_order();
+                if (lane == 0) CM(H, k + 1, k, ldh) = T(0);
+                wave_order();
+            }
+            ihi -= 2; its = 0;
+            continue;
+        }
+        if (++total > itmax) return 1;
+        ++its;
+        if (nsweep && lane == 0) { ++*nsweep; *nstep += ihi - l; }
+        T h11 = CM(H, ihi - 1, ihi - 1, ldh), h12 = CM(H, ihi - 1, ihi, ldh);
+        T h21 = CM(H, ihi, ihi - 1, ldh), h22 = CM(H, ihi, ihi, ldh);
+        if (its == 10 || its == 20) {
+            const T sx = fabs(CM(H, ihi, ihi - 1, ldh)) + fabs(CM(H, ihi - 1, ihi - 2, ldh));
+            h11 = T(0.75) * sx + CM(H, ihi, ihi, ldh);
+            h12 = T(-0.4375) * sx;
+            h21 = sx;
+            h22 = h11;
+        }
+        T x, y, z;
+        {
+            T sp, sq;
+            bool cplx;
+            shift_pair(h11, h12, h21, h22, sp, sq, cplx);
+            shift_column(CM(H, l, l, ldh), CM(H, l, l + 1, ldh), CM(H, l + 1, l, ldh), CM(H, l + 1, l + 1, ldh),
+                         CM(H, l + 2, l + 1, ldh), sp, sq, cplx, x, y, z);
+        }
+        for (int k = l; k <= ihi - 1; ++k) {
+            const int len = (k <= ihi - 2) ? 3 : 2;
+            const int k2 = (len == 3) ? k + 2 : k + 1;   // clamped third index
+            if (k > l) {
+                x = CM(H, k, k - 1, ldh);
+                y = CM(H, k + 1, k - 1, ldh);
+                z = CM(H, k2, k - 1, ldh);
+            }
+            T v1, v2, tau, beta;
+            reflector3(len, x, y, z, v1, v2, tau, beta);
+            wave_order();
+            // left: rows k..k2, columns k..n-1; column k-1 becomes (beta, 0, 0)
+            if (k > l && lane == k - 1) {
+                CM(H, k2, lane, ldh) = T(0);
+                CM(H, k + 1, lane, ldh) = T(0);
+                CM(H, k, lane, ldh) = beta;
+            } else if (lane >= k && lane < n) {
+                const int j = lane;
+                T a0 = CM(H, k, j, ldh), a1 = CM(H, k + 1, j, ldh), a2 = CM(H, k2, j, ldh);
+                refl_apply(len, v1, v2, tau, a0, a1, a2);
+                CM(H, k2, j, ldh) = a2; CM(H, k, j, ldh) = a0; CM(H, k + 1, j, ldh) = a1;
+            }
+            wave_order();
+            // right: columns k..k2, rows 0..min(k+3, ihi)
+            const int rmax = (k + 3 < ihi) ? k + 3 : ihi;
+            if (lane <= rmax) {
+                const int i = lane;
+                T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh), a2 = CM(H, i, k2, ldh);
+                refl_apply(len, v1, v2, tau, a0, a1, a2);
+                CM(H, i, k2, ldh) = a2; CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
+            }
+            if (lane < nz) {
+                const int i = lane;
+                T a0 = CM(Z, i, k, ldz), a1 = CM(Z, i, k + 1, ldz), a2 = CM(Z, i, k2, ldz);
+                refl_apply(len, v1, v2, tau, a0, a1, a2);
+                CM(Z, i, k2, ldz) = a2; CM(Z, i, k, ldz) = a0; CM(Z, i, k + 1, ldz) = a1;
+            }
+            wave_order();
+        }
+    }
+    // exact zeros below the first subdiagonal
+    for (int e = lane; e < n * n; e += 64) {
+        const int i = e % n, j = e / n;
+        if (i > j + 1) CM(H, i, j, ldh) = T(0);
+    }
+    wave_order();
+    return 0;
+}
+
 // ---------------------------------------------------------------- k_aed
 // out[0] = status (0 ok, 1 QR cap), out[1] = nd (deflated count), out[2] =
 // ns (undeflated count); wr/wi (length nw) receive the eigenvalues of the
@@ -255,7 +401,18 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
     __syncthreads();
     int nsw = 0, nst = 0;
     const long long c0 = clock64();
-    int st = francis_lds<T, NT>(nw, Tw, L, Zl, L, nw, sint + 1, &nsw, &nst);
+    int st;
+    if (nw <= 64) {
+        // one wavefront, no barriers; the others wait for its status
+        if (tid < 64) {
+            st = francis_wave<T>(nw, Tw, L, Zl, L, nw, &nsw, &nst);
+            if (tid == 0) sint[1] = st;
+        }
+        __syncthreads();
+        st = sint[1];
+    } else {
+        st = francis_lds<T, NT>(nw, Tw, L, Zl, L, nw, sint + 1, &nsw, &nst);
+    }
     const long long c1 = clock64();
     if (tid == 0) { out[3] = nsw; out[4] = nst; out[5] = (int)((c1 - c0) >> 10); }
     if (st) {

@@ -113,6 +113,23 @@ def test_schur_invariants_random(prec, n):
         assert np.min(np.abs(ev - z)) <= tol
 
 
+@pytest.mark.parametrize("prec,n", [("fp32", 1100), ("fp64", 1100), ("fp32", 2100), ("fp64", 2100),
+                                    ("fp32", 4200)])
+def test_schur_invariants_large(prec, n):
+    """Sizes that take each Hessenberg column kernel: the register-resident
+    one with two and four rows per thread, and the general one above 4096."""
+    sy = binding()
+    say("schur large", prec, n)
+    rs = np.random.RandomState(n + 9)
+    A = rs.standard_normal((n, n))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    T, Uq, st = sy.schur(dev(A, dt))
+    torch.cuda.synchronize()
+    assert st == 0
+    u = U64 if prec == "fp64" else U32
+    check_schur(host(dev(A, dt)), host(T), host(Uq), u)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_schur_constructed_spectrum_700(prec):
     """Normal matrix with known spectrum (workload recipe): GPU eigenvalues
