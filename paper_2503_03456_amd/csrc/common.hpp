@@ -14,13 +14,16 @@
 namespace sylv {
 
 template <typename T> struct num;
+// big: a power of two well below the magnitude whose reciprocal is subnormal.
 template <> struct num<float> {
     static constexpr float ulp = 5.9604644775390625e-08f;  // 2^-24, unit roundoff of binary32
     static constexpr float safmin = 1.17549435e-38f;
+    static constexpr float big = 0x1p100f;
 };
 template <> struct num<double> {
     static constexpr double ulp = 1.1102230246251565e-16;  // 2^-53
     static constexpr double safmin = 2.2250738585072014e-308;
+    static constexpr double big = 0x1p1000;
 };
 
 // Error checking on the host: returns the negative ABI code from the caller.
@@ -46,8 +49,11 @@ SYLV_DEVINL double fsqrt(double x) { return sqrt(x); }
 
 // Householder reflector for a vector of length 2 or 3 (z ignored when
 // len == 2): P = I - tau v v^T, v = (1, v1, v2), P x = beta e1.  Returns
-// tau = 0 when x(1:) is zero (P = I).  The norm is formed after scaling by
-// the largest magnitude (no overflow for moderate ranges).
+// tau = 0 when x(1:) is zero (P = I).  Everything but beta is formed from the
+// vector scaled by 1/mm, mm its largest magnitude clamped to [safmin, big]:
+// a collapsed bulge can leave entries below the normal range, where the
+// reciprocal of the magnitude itself would overflow, and near the top of the
+// range that reciprocal would be subnormal.
 template <typename T>
 SYLV_DEVINL void reflector3(int len, T x, T y, T z, T &v1, T &v2, T &tau, T &beta) {
     if (len == 2) z = T(0);
@@ -56,16 +62,16 @@ SYLV_DEVINL void reflector3(int len, T x, T y, T z, T &v1, T &v2, T &tau, T &bet
         v1 = T(0); v2 = T(0); tau = T(0); beta = x;
         return;
     }
-    T m = fmax(fabs(x), tail);
-    T rm = frcp(m);
-    T xs = x * rm, ys = y * rm, zs = z * rm;
-    T nrm = m * fsqrt(xs * xs + ys * ys + zs * zs);
-    T b = (x >= T(0)) ? -nrm : nrm;
-    tau = (b - x) * frcp(b);
-    T sc = frcp(x - b);
-    v1 = y * sc;
-    v2 = z * sc;
-    beta = b;
+    const T mm = fmin(fmax(fmax(fabs(x), tail), num<T>::safmin), num<T>::big);
+    const T rm = frcp(mm);
+    const T xs = x * rm, ys = y * rm, zs = z * rm;
+    const T ns = fsqrt(xs * xs + ys * ys + zs * zs);
+    const T bs = (x >= T(0)) ? -ns : ns;
+    tau = (bs - xs) * frcp(bs);
+    const T sc = frcp(xs - bs);
+    v1 = ys * sc;
+    v2 = zs * sc;
+    beta = bs * mm;
 }
 
 // 16x16x4 MFMA in the precision T (binary32 or binary64 accumulate).  With

@@ -5,10 +5,12 @@
 // Three building blocks, all single-workgroup and LDS-resident:
 //   * francis_lds: implicit double-shift QR sweeps on a small dense upper
 //     Hessenberg matrix held in LDS, accumulating the orthogonal factor;
-//     deflation on negligible subdiagonal entries, exceptional shifts after
-//     10 and 20 stagnating sweeps, real-eigenvalue 2x2 blocks split by one
+//     deflation on negligible subdiagonal entries, exceptional shifts every
+//     10 sweeps without a deflation, real-eigenvalue 2x2 blocks split by one
 //     rotation.  One barrier per bulge step: the 3x3 overlap block of a
 //     step is owned by one thread, so left and right updates never race.
+//   * francis_wave: the same sweeps for windows of order <= 64 on one
+//     wavefront, without barriers.
 //   * k_aed: aggressive early deflation on the trailing window of the active
 //     block (Braman, Byers & Mathias 2002, part II): Schur form of the window,
 //     spike test from the bottom, restoration of Hessenberg form of the
@@ -119,9 +121,14 @@ SYLV_DEVINL int francis_lds(int n, T *H, int ldh, T *Z, int ldz, int nz, int *si
         if (nsweep) { ++*nsweep; *nstep += ihi - l; }
         T h11 = CM(H, ihi - 1, ihi - 1, ldh), h12 = CM(H, ihi - 1, ihi, ldh);
         T h21 = CM(H, ihi, ihi - 1, ldh), h22 = CM(H, ihi, ihi, ldh);
-        if (its == 10 || its == 20) {
-            T s = fabs(CM(H, ihi, ihi - 1, ldh)) + fabs(CM(H, ihi - 1, ihi - 2, ldh));
-            h11 = T(0.75) * s + CM(H, ihi, ihi, ldh);
+        // exceptional shifts every 10 sweeps without a deflation, built from
+        // the bottom of the active block and, every 20, from its top (breaks
+        // the cycles a stagnating block can fall into)
+        if (its % 10 == 0) {
+            const bool top = (its % 20 == 0);
+            const T s = top ? fabs(CM(H, l + 1, l, ldh)) + fabs(CM(H, l + 2, l + 1, ldh))
+                            : fabs(CM(H, ihi, ihi - 1, ldh)) + fabs(CM(H, ihi - 1, ihi - 2, ldh));
+            h11 = T(0.75) * s + (top ? CM(H, l, l, ldh) : CM(H, ihi, ihi, ldh));
             h12 = T(-0.4375) * s;
             h21 = s;
             h22 = h11;
@@ -311,9 +318,12 @@ SYLV_DEVINL int francis_wave(int n, T *H, int ldh, T *Z, int ldz, int nz, int *n
         if (nsweep && lane == 0) { ++*nsweep; *nstep += ihi - l; }
         T h11 = CM(H, ihi - 1, ihi - 1, ldh), h12 = CM(H, ihi - 1, ihi, ldh);
         T h21 = CM(H, ihi, ihi - 1, ldh), h22 = CM(H, ihi, ihi, ldh);
-        if (its == 10 || its == 20) {
-            const T sx = fabs(CM(H, ihi, ihi - 1, ldh)) + fabs(CM(H, ihi - 1, ihi - 2, ldh));
-            h11 = T(0.75) * sx + CM(H, ihi, ihi, ldh);
+        if (its % 10 == 0) {
+            // exceptional shifts as in the barrier version above
+            const bool top = (its % 20 == 0);
+            const T sx = top ? fabs(CM(H, l + 1, l, ldh)) + fabs(CM(H, l + 2, l + 1, ldh))
+                             : fabs(CM(H, ihi, ihi - 1, ldh)) + fabs(CM(H, ihi - 1, ihi - 2, ldh));
+            h11 = T(0.75) * sx + (top ? CM(H, l, l, ldh) : CM(H, ihi, ihi, ldh));
             h12 = T(-0.4375) * sx;
             h21 = sx;
             h22 = h11;
