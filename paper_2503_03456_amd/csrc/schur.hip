@@ -153,8 +153,18 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
     T *S = reinterpret_cast<T *>(win_smem);
     T *Zs = S + L::SZ;
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
-    const int nkk = (w + 3) / 4;
+    // k steps of 4, rounded up to whole groups of 4 steps: S and Zs are zero
+    // from k = w up to WP, a multiple of 16
+    const int nkk = (((w + 3) / 4) + 3) & ~3;
     const int nch = (w + 15) / 16;
+    // Staging: every thread issues UL (UZ) loads before their LDS stores, at
+    // addresses clamped into the matrix, with exact trip counts and no
+    // value-dependent selects, so nothing turns them back into one branch
+    // and one wait per load.  Only Zs needs zeros outside w (rows k >= w, by
+    // a 0/1 factor; Z is finite): with those, the strip's padding reaches
+    // only outputs that are not stored.
+    constexpr int UL = sizeof(T) == 4 ? 12 : 14, UZ = sizeof(T) == 4 ? 9 : 7;
+    static_assert((SS * WP) % (256 * UL) == 0 && (WP * WP) % (256 * UZ) == 0, "staging trip counts");
     int b = blockIdx.x;
     const bool left = b < nl;
     T *M;
@@ -165,9 +175,18 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
         c0 = w0 + w + SS * b;
         ext = min(SS, n - c0);
         // S[j * LDK + k] = H(w0 + k, c0 + j)
-        for (int e = tid; e < SS * WP; e += 256) {
-            const int k = e % WP, j = e / WP;
-            S[j * LDK + k] = (k < w && j < ext) ? CM(M, r0 + k, c0 + j, ldm) : T(0);
+        for (int e0 = tid; e0 < SS * WP; e0 += 256 * UL) {
+            T v[UL];
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int e = e0 + 256 * u, k = e % WP, j = e / WP;
+                v[u] = CM(M, r0 + (k < w ? k : w - 1), c0 + (j < ext ? j : ext - 1), ldm);
+            }
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int e = e0 + 256 * u;
+                S[(e / WP) * LDK + e % WP] = v[u];
+            }
         }
     } else {
         b -= nl;
@@ -178,15 +197,33 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
         c0 = w0;
         ext = min(SS, rows - r0);
         // S[k * LDI + i] = M(r0 + i, w0 + k)
-        for (int e = tid; e < SS * WP; e += 256) {
-            const int i = e % SS, k = e / SS;
-            S[k * LDI + i] = (k < w && i < ext) ? CM(M, r0 + i, c0 + k, ldm) : T(0);
+        for (int e0 = tid; e0 < SS * WP; e0 += 256 * UL) {
+            T v[UL];
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int e = e0 + 256 * u, i = e % SS, k = e / SS;
+                v[u] = CM(M, r0 + (i < ext ? i : ext - 1), c0 + (k < w ? k : w - 1), ldm);
+            }
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int e = e0 + 256 * u;
+                S[(e / SS) * LDI + e % SS] = v[u];
+            }
         }
     }
-    // Zs[j * LDZ + k] = Z(k, j), zero outside w (rows j up to 16 nch)
-    for (int e = tid; e < 16 * nch * WP; e += 256) {
-        const int k = e % WP, j = e / WP;
-        Zs[j * LDZ + k] = (k < w && j < w) ? Z[(size_t)j * w + k] : T(0);
+    // Zs[j * LDZ + k] = Z(k, j) for k < w, zero for k >= w (all WP columns j)
+    for (int e0 = tid; e0 < WP * WP; e0 += 256 * UZ) {
+        T v[UZ];
+#pragma unroll
+        for (int u = 0; u < UZ; ++u) {
+            const int e = e0 + 256 * u, k = e % WP, j = e / WP;
+            v[u] = Z[(size_t)(j < w ? j : w - 1) * w + (k < w ? k : w - 1)] * T(k < w ? 1 : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < UZ; ++u) {
+            const int e = e0 + 256 * u;
+            Zs[(e / WP) * LDZ + e % WP] = v[u];
+        }
     }
     __syncthreads();
     for (int blk = wv; blk < RB * nch; blk += 4) {
@@ -197,9 +234,15 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
         if (left) {
             // out(i, j) = sum_k Z(k, i) S(k, j): i in chunk ch, j in block ob
             const T *sp = S + (bo + (l & 15)) * LDK;
-            for (int kk = 0; kk < nkk; ++kk) {
-                const int k = 4 * kk + (l >> 4);
-                acc = mfma16<T>::op(sp[k], zc[k], acc);
+            for (int kk0 = 0; kk0 < nkk; kk0 += 4) {
+                T sa[4], za[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = 4 * (kk0 + u) + (l >> 4);
+                    sa[u] = sp[k]; za[u] = zc[k];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc = mfma16<T>::op(sa[u], za[u], acc);
             }
             const int i = 16 * ch + (l & 15);
 #pragma unroll
@@ -210,9 +253,15 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
         } else {
             // out(i, j) = sum_k S(i, k) Z(k, j): i in block ob, j in chunk ch
             const T *sp = S + bo + (l & 15);
-            for (int kk = 0; kk < nkk; ++kk) {
-                const int k = 4 * kk + (l >> 4);
-                acc = mfma16<T>::op(zc[k], sp[k * LDI], acc);
+            for (int kk0 = 0; kk0 < nkk; kk0 += 4) {
+                T sa[4], za[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = 4 * (kk0 + u) + (l >> 4);
+                    sa[u] = sp[k * LDI]; za[u] = zc[k];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc = mfma16<T>::op(za[u], sa[u], acc);
             }
             const int i = bo + (l & 15);
 #pragma unroll
