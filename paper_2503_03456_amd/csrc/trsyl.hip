@@ -119,7 +119,58 @@ SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T 
     return flag;
 }
 
-// One tile (I, J) of Y: off-diagonal updates, then the in-LDS solve.
+// acc += A B on MFMA for one output tile (p x q <= TS x TS): A is p x K
+// (leading dimension lda_), B is K x q (ldb_).  The four wavefronts take a
+// 2 x 2 grid of 32 x 32 output blocks; stA / stB are the LDS slabs.  All
+// 256 threads call it.
+template <typename T>
+SYLV_DEVINL void tile_gemm(typename mfma16t<T>::v4 (&acc)[2][2], const T *Ap, int lda_, const T *Bp, int ldb_,
+                           int K, int p, int q, T (*stA)[TS + 16], T (*stB)[TS + 16]) {
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wm = w & 1, wn = w >> 1;
+    // A slab: tile rows 0..p-1 x k0..k0+TBK-1 ; B slab: k0.. x tile cols 0..q-1.
+    // Each thread holds 8 elements of each slab; the next slab is loaded
+    // into registers while the current one feeds the MFMAs.
+    T ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) {
+            int i = l, k = w + 4 * rr;
+            ra[rr] = (i < p && k0 + k < K) ? Ap[(size_t)(k0 + k) * lda_ + i] : T(0);
+            int kk = t & 31, j = (t >> 5) + 8 * rr;
+            rb[rr] = (j < q && k0 + kk < K) ? Bp[(size_t)j * ldb_ + k0 + kk] : T(0);
+        }
+    };
+    const int nk = (K + TBK - 1) / TBK;
+    if (nk > 0) load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) {
+            stA[w + 4 * rr][l] = ra[rr];
+            stB[t & 31][(t >> 5) + 8 * rr] = rb[rr];
+        }
+        __syncthreads();
+        if (kt + 1 < nk) load((kt + 1) * TBK);
+#pragma unroll
+        for (int kk = 0; kk < TBK / 4; ++kk) {
+            const int kr = 4 * kk + (l >> 4);
+            T fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) fa[a] = stA[kr][32 * wm + 16 * a + (l & 15)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) fb[b] = stB[kr][32 * wn + 16 * b + (l & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = mfma16t<T>::op(fb[b], fa[a], acc[a][b]);
+        }
+        __syncthreads();
+    }
+}
+
+// One tile (I, J) of Y: off-diagonal updates (lazy: all of them here, the
+// left-looking form; otherwise the right-looking updates of
+// k_trsyl_update have already been applied to C), then the in-LDS solve.
 // mirror (symmetric Lyapunov, m = n, TB = P TA^T P): the column tiles are
 // the mirror images of the row tiles, c_J = n - r_{nt-J}, so that the
 // solution Y' = Y P of a symmetric Y (persymmetric: Y'(i, j) =
@@ -128,7 +179,7 @@ SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T 
 template <typename T>
 SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, const T *__restrict__ TB,
                             int ldtb, T *C, int ldc, int I, int J, double maxab, int *flag, int mirror = 0,
-                            int wmirror = 0) {
+                            int wmirror = 0, bool lazy = true) {
     __shared__ T sA[TS * TLD];   // TA diagonal tile, later reused
     __shared__ T sB[TS * TLD];   // TB diagonal tile
     __shared__ T sC[TS * TLD];   // rhs -> Y tile
@@ -152,58 +203,16 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = w & 1, wn = w >> 1;
 
-    // ---- 1. off-diagonal updates on MFMA: acc = TA(r0:r1, r1:m) Y(r1:m, c0:c1)
-    //         + Y(r0:r1, 0:c0) TB(0:c0, c0:c1)
+    // ---- 1. off-diagonal updates on MFMA (left-looking form): acc =
+    //         TA(r0:r1, r1:m) Y(r1:m, c0:c1) + Y(r0:r1, 0:c0) TB(0:c0, c0:c1)
     v4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
-    for (int phase = 0; phase < 2; ++phase) {
-        const T *Ap;
-        int lda_, K;
-        const T *Bp;
-        int ldb_;
-        if (phase == 0) { Ap = TA + (size_t)r1 * ldta + r0; lda_ = ldta; Bp = C + (size_t)c0 * ldc + r1; ldb_ = ldc; K = m - r1; }
-        else { Ap = C + r0; lda_ = ldc; Bp = TB + (size_t)c0 * ldtb; ldb_ = ldtb; K = c0; }
-        // A slab: tile rows 0..p-1 x k0..k0+TBK-1 ; B slab: k0.. x tile cols 0..q-1.
-        // Each thread holds 8 elements of each slab; the next slab is loaded
-        // into registers while the current one feeds the MFMAs.
-        T ra[8], rb[8];
-        auto load = [&](int k0) {
-#pragma unroll
-            for (int rr = 0; rr < 8; ++rr) {
-                int i = l, k = w + 4 * rr;
-                ra[rr] = (i < p && k0 + k < K) ? Ap[(size_t)(k0 + k) * lda_ + i] : T(0);
-                int kk = t & 31, j = (t >> 5) + 8 * rr;
-                rb[rr] = (j < q && k0 + kk < K) ? Bp[(size_t)j * ldb_ + k0 + kk] : T(0);
-            }
-        };
-        const int nk = (K + TBK - 1) / TBK;
-        if (nk > 0) load(0);
-        for (int kt = 0; kt < nk; ++kt) {
-#pragma unroll
-            for (int rr = 0; rr < 8; ++rr) {
-                stA[w + 4 * rr][l] = ra[rr];
-                stB[t & 31][(t >> 5) + 8 * rr] = rb[rr];
-            }
-            __syncthreads();
-            if (kt + 1 < nk) load((kt + 1) * TBK);
-#pragma unroll
-            for (int kk = 0; kk < TBK / 4; ++kk) {
-                const int kr = 4 * kk + (l >> 4);
-                T fa[2], fb[2];
-#pragma unroll
-                for (int a = 0; a < 2; ++a) fa[a] = stA[kr][32 * wm + 16 * a + (l & 15)];
-#pragma unroll
-                for (int b = 0; b < 2; ++b) fb[b] = stB[kr][32 * wn + 16 * b + (l & 15)];
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) acc[a][b] = mfma16t<T>::op(fb[b], fa[a], acc[a][b]);
-            }
-            __syncthreads();
-        }
+    if (lazy) {
+        tile_gemm<T>(acc, TA + (size_t)r1 * ldta + r0, ldta, C + (size_t)c0 * ldc + r1, ldc, m - r1, p, q, stA, stB);
+        tile_gemm<T>(acc, C + r0, ldc, TB + (size_t)c0 * ldtb, ldtb, c0, p, q, stA, stB);
     }
     // rhs tile: sC(i, j) = C(r0+i, c0+j) - acc
 #pragma unroll
@@ -332,7 +341,64 @@ __global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__res
                                                    int *flag, int mirror) {
     const int J = jmin + blockIdx.x;
     const int I = nI - 1 - (d - J);
-    trsyl_tile<T>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror, mirror && 2 * J < d);
+    trsyl_tile<T>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror, mirror && 2 * J < d, false);
+}
+
+// Right-looking updates after anti-diagonal d is solved: every tile (I, J)
+// of a later anti-diagonal loses the contributions of the solved tile of its
+// block column, (K, J) with K = nI-1-d+J (through TA(I, K)), and of the
+// solved tile of its block row, (I, L) with L = d-(nI-1-I) (through TB(L, J)):
+//   C_IJ -= TA(I, K) Y(K, J) + Y(I, L) TB(L, J).
+// Every pair (destination, source) is met exactly once over the sweep, so
+// C_IJ holds the full right-hand side when its own anti-diagonal comes up.
+// One workgroup per tile (grid nJ x nI); tiles without a source exit at
+// once.  mirror: tiles with 2J > their anti-diagonal are never solved
+// directly (their mirror images are written instead) and need no update.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsyl_update(int m, int n, const T *__restrict__ TA, int ldta,
+                                                     const T *__restrict__ TB, int ldtb, T *C, int ldc, int d,
+                                                     int nI, int nJ, int mirror) {
+    __shared__ T stA[TBK][TS + 16];
+    __shared__ T stB[TBK][TS + 16];
+    typedef typename mfma16t<T>::v4 v4;
+    const int J = blockIdx.x, I = blockIdx.y;
+    const int dIJ = nI - 1 - I + J;
+    if (dIJ <= d) return;
+    if (mirror && 2 * J > dIJ) return;
+    const int K = nI - 1 - d + J, L = d - (nI - 1 - I);
+    const bool hasK = K < nI, hasL = L >= 0;   // K > I and L < J hold since dIJ > d
+    if (!hasK && !hasL) return;
+    auto rb_ = [&](int k) { return tile_bound(TA, ldta, m, k); };
+    auto cb_ = [&](int k) {
+        return mirror ? n - tile_bound(TA, ldta, m, nI - k) : tile_bound(TB, ldtb, n, k);
+    };
+    const int r0 = rb_(I), r1 = rb_(I + 1), c0 = cb_(J), c1 = cb_(J + 1);
+    const int p = r1 - r0, q = c1 - c0;
+    v4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+    if (hasK) {
+        const int k0 = rb_(K), k1 = rb_(K + 1);
+        tile_gemm<T>(acc, TA + (size_t)k0 * ldta + r0, ldta, C + (size_t)c0 * ldc + k0, ldc, k1 - k0, p, q, stA, stB);
+    }
+    if (hasL) {
+        const int l0 = cb_(L), l1 = cb_(L + 1);
+        tile_gemm<T>(acc, C + (size_t)l0 * ldc + r0, ldc, TB + (size_t)c0 * ldtb + l0, ldtb, l1 - l0, p, q, stA, stB);
+    }
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wm = w & 1, wn = w >> 1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 32 * wm + 16 * a + (l & 15);
+                const int j = 32 * wn + 16 * b + mfma16t<T>::orow(l, r);
+                if (i < p && j < q) C[(size_t)(c0 + j) * ldc + r0 + i] -= acc[a][b][r];
+            }
 }
 
 // Batched form: tiles of anti-diagonal d of every active equation
@@ -381,6 +447,9 @@ void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int 
         ProfScope ps(KID_TRSYL, s);
         hipLaunchKernelGGL((k_trsyl_diag<T>), dim3(jmax - jmin + 1), dim3(256), 0, s, m, n, TA, ldta,
                            TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror);
+        if (d < nI + nJ - 2)
+            hipLaunchKernelGGL((k_trsyl_update<T>), dim3(nJ, nI), dim3(256), 0, s, m, n, TA, ldta, TB, ldtb, C,
+                               ldc, d, nI, nJ, mirror);
     }
 }
 template void trsyl<float>(hipStream_t, int, int, const float *, int, const float *, int, float *, int,
