@@ -650,9 +650,10 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
     const int L = W | 1;  // odd leading dimension: conflict-free row-wise access
     T *Hw = reinterpret_cast<T *>(smem_raw);
     T *Uw = Hw + L * W;
-    T *refl = Uw + L * W;  // per bulge: v1, v2, tau, beta
-    int *rinfo = reinterpret_cast<int *>(refl + 4 * nbulge);  // per bulge: q (or -1), len, ulo, uhi
-    int *ulo = rinfo + 4 * nbulge;  // per column of Uw: nonzero row range
+    // per bulge and time parity: v1, v2, tau, beta and q (or -1), len, ulo, uhi
+    T *refl = Uw + L * W;
+    int *rinfo = reinterpret_cast<int *>(refl + 8 * nbulge);
+    int *ulo = rinfo + 8 * nbulge;  // per column of Uw: nonzero row range
     int *uhi = ulo + W;
     const int tid = threadIdx.x;
     const int N = kbot - ktop + 1;
@@ -664,44 +665,64 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
     for (int j = tid; j < W; j += NT) { ulo[j] = j; uhi[j] = j; }
     __syncthreads();
     const int kb = kbot - ws;  // local index of kbot
-    const int tpb = NT / nbulge;             // threads per bulge (nbulge <= NT)
+    const int tpb = NT / nbulge;             // phase A: threads per bulge
     const int myb = tid / tpb, slot = tid % tpb;
-    for (int t = t0; t < t0 + adv; ++t) {
-        // phase 0: reflectors of the active bulges, and the row range of Uw
-        // their columns can touch (interval hull of the three columns' ranges;
-        // columns of distinct bulges are disjoint)
-        for (int b = tid; b < nbulge; b += NT) {
-            int p = t - 3 * b;
-            if (p < 0 || p > N - 2) { rinfo[4 * b] = -1; continue; }
-            int q = ktop + p - ws;  // local row of the reflector
-            int len = (p <= N - 3) ? 3 : 2;
-            T x, y, z;
-            if (p == 0) {
-                shift_column(Hw[q * L + q], Hw[(q + 1) * L + q], Hw[q * L + q + 1], Hw[(q + 1) * L + q + 1],
-                             Hw[(q + 1) * L + q + 2], trd[3 * b], trd[3 * b + 1], trd[3 * b + 2] != T(0), x, y, z);
-            } else {
-                x = Hw[(q - 1) * L + q];
-                y = Hw[(q - 1) * L + q + 1];
-                z = Hw[(q - 1) * L + ((len == 3) ? q + 2 : q + 1)];
-            }
-            T v1, v2, tau, beta;
-            reflector3(len, x, y, z, v1, v2, tau, beta);
-            refl[4 * b] = v1; refl[4 * b + 1] = v2; refl[4 * b + 2] = tau; refl[4 * b + 3] = beta;
-            int lo = ulo[q], hi = uhi[q];
-            for (int c = 1; c < len; ++c) { lo = min(lo, ulo[q + c]); hi = max(hi, uhi[q + c]); }
-            for (int c = 0; c < len; ++c) { ulo[q + c] = lo; uhi[q + c] = hi; }
-            rinfo[4 * b] = q; rinfo[4 * b + 1] = len; rinfo[4 * b + 2] = lo; rinfo[4 * b + 3] = hi;
+    // phase B: lane b of wavefront 0 leads bulge b (nbulge <= 64); the other
+    // wavefronts split the bulges' remaining rows, tpr threads per bulge
+    const int tpr = (NT - 64) / nbulge;
+    const int rb = (tid - 64) / tpr, rslot = (tid - 64) % tpr;
+    // Reflector of bulge b from its column (x, y, z) into parity buf, with
+    // the row range of Uw its columns can touch (interval hull of the three
+    // columns' ranges; columns of distinct bulges are disjoint).
+    auto commit = [&](int b, int buf, int q, int len, T x, T y, T z) {
+        T v1, v2, tau, beta;
+        reflector3(len, x, y, z, v1, v2, tau, beta);
+        T *rf = refl + 4 * (buf * nbulge + b);
+        rf[0] = v1; rf[1] = v2; rf[2] = tau; rf[3] = beta;
+        int lo = ulo[q], hi = uhi[q];
+        for (int c = 1; c < len; ++c) { lo = min(lo, ulo[q + c]); hi = max(hi, uhi[q + c]); }
+        for (int c = 0; c < len; ++c) { ulo[q + c] = lo; uhi[q + c] = hi; }
+        int *ri = rinfo + 4 * (buf * nbulge + b);
+        ri[0] = q; ri[1] = len; ri[2] = lo; ri[3] = hi;
+    };
+    // Reflector of bulge b at time t read from the window: at the start of
+    // the phase, and for a bulge introduced mid-phase (its first column
+    // depends on the previous bulge's last updates).
+    auto form = [&](int b, int t, int buf) {
+        const int p = t - 3 * b;
+        if (p < 0 || p > N - 2) { rinfo[4 * (buf * nbulge + b)] = -1; return; }
+        const int q = ktop + p - ws;  // local row of the reflector
+        const int len = (p <= N - 3) ? 3 : 2;
+        T x, y, z;
+        if (p == 0) {
+            shift_column(Hw[q * L + q], Hw[(q + 1) * L + q], Hw[q * L + q + 1], Hw[(q + 1) * L + q + 1],
+                         Hw[(q + 1) * L + q + 2], trd[3 * b], trd[3 * b + 1], trd[3 * b + 2] != T(0), x, y, z);
+        } else {
+            x = Hw[(q - 1) * L + q];
+            y = Hw[(q - 1) * L + q + 1];
+            z = Hw[(q - 1) * L + ((len == 3) ? q + 2 : q + 1)];
         }
-        __syncthreads();
+        commit(b, buf, q, len, x, y, z);
+    };
+    for (int b = tid; b < nbulge; b += NT) form(b, t0, t0 & 1);
+    __syncthreads();
+    for (int t = t0; t < t0 + adv; ++t) {
+        const int buf = t & 1;
+        if (t > t0 && t % 3 == 0 && t / 3 < nbulge) {
+            if (tid == 0) form(t / 3, t, buf);
+            __syncthreads();
+        }
         // Each active bulge gets a fixed group of tpb threads; a thread works
         // only on its own bulge, so there is no sequential loop over bulges.
         // phase A: left applications, rows q..q+len-1, columns q-1 (p>0: set
         // beta, zeros) and q..W-1.  Distinct bulges touch distinct rows.
         if (myb < nbulge) {
-            const int q = rinfo[4 * myb];
+            const int *ri = rinfo + 4 * (buf * nbulge + myb);
+            const int q = ri[0];
             if (q >= 0) {
-                const int len = rinfo[4 * myb + 1];
-                const T v1 = refl[4 * myb], v2 = refl[4 * myb + 1], tau = refl[4 * myb + 2];
+                const int len = ri[1];
+                const T *rf = refl + 4 * (buf * nbulge + myb);
+                const T v1 = rf[0], v2 = rf[1], tau = rf[2];
                 const bool intro = (t - 3 * myb == 0);
                 const int c0 = intro ? q : q - 1;
                 const int q2 = (len == 3) ? q + 2 : q + 1;  // clamped third row
@@ -710,7 +731,7 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
                     if (!intro && j == q - 1) {
                         Hw[j * L + q2] = T(0);
                         Hw[j * L + q + 1] = T(0);
-                        Hw[j * L + q] = refl[4 * myb + 3];
+                        Hw[j * L + q] = rf[3];
                         continue;
                     }
                     T a0 = Hw[j * L + q], a1 = Hw[j * L + q + 1], a2 = Hw[j * L + q2];
@@ -721,20 +742,58 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
         }
         __syncthreads();
         // phase B: right applications on columns q..q+len-1 (rows 0..min(q+3, kb))
-        // and on Uw (rows ulo..uhi only).  Distinct bulges touch distinct columns.
-        if (myb < nbulge) {
-            const int q = rinfo[4 * myb];
+        // and on Uw (rows ulo..uhi only).  Distinct bulges touch distinct
+        // columns.  The rows q+1..q+3 hold the bulge's next column (column q
+        // after this step): the bulge's lead lane in wavefront 0 updates them
+        // itself and forms the next step's reflector from them, so there is
+        // no separate reflector phase (no other bulge touches column q in this
+        // step), and the leads run side by side in one wavefront.
+        if (tid < 64) {
+            const int b = tid;
+            if (b < nbulge) {
+                const int *ri = rinfo + 4 * (buf * nbulge + b);
+                const int q = ri[0];
+                int *rn = rinfo + 4 * ((buf ^ 1) * nbulge + b);
+                if (q >= 0) {
+                    const int len = ri[1];
+                    const T *rf = refl + 4 * (buf * nbulge + b);
+                    const T v1 = rf[0], v2 = rf[1], tau = rf[2];
+                    int rmax = q + 3 < kb ? q + 3 : kb;
+                    if (rmax > W - 1) rmax = W - 1;
+                    const int q2 = (len == 3) ? q + 2 : q + 1;
+                    T nx = T(0), ny = T(0), nz = T(0);
+                    for (int i = q + 1; i <= rmax; ++i) {
+                        T a0 = Hw[q * L + i], a1 = Hw[(q + 1) * L + i], a2 = Hw[q2 * L + i];
+                        refl_apply(len, v1, v2, tau, a0, a1, a2);
+                        Hw[q2 * L + i] = a2; Hw[q * L + i] = a0; Hw[(q + 1) * L + i] = a1;
+                        if (i == q + 1) nx = a0;
+                        else if (i == q + 2) ny = a0;
+                        else nz = a0;
+                    }
+                    const int pn = t + 1 - 3 * b;
+                    if (t + 1 < t0 + adv && pn <= N - 2)
+                        commit(b, buf ^ 1, q + 1, (pn <= N - 3) ? 3 : 2, nx, ny, nz);
+                    else
+                        rn[0] = -1;
+                } else {
+                    rn[0] = -1;
+                }
+            }
+        } else if (rb < nbulge) {
+            const int *ri = rinfo + 4 * (buf * nbulge + rb);
+            const int q = ri[0];
             if (q >= 0) {
-                const int len = rinfo[4 * myb + 1];
-                const int lo = rinfo[4 * myb + 2], hi = rinfo[4 * myb + 3];
-                const T v1 = refl[4 * myb], v2 = refl[4 * myb + 1], tau = refl[4 * myb + 2];
+                const int len = ri[1];
+                const int lo = ri[2], hi = ri[3];
+                const T *rf = refl + 4 * (buf * nbulge + rb);
+                const T v1 = rf[0], v2 = rf[1], tau = rf[2];
                 int rmax = q + 3 < kb ? q + 3 : kb;
                 if (rmax > W - 1) rmax = W - 1;
-                const int nr = rmax + 1;
+                const int nr = q + 1;  // rows 0..q here; q+1..rmax go to the lead lane
                 const int nu = hi - lo + 1;
                 const int q2 = (len == 3) ? q + 2 : q + 1;  // clamped third column
 #pragma unroll 2
-                for (int e = slot; e < nr + nu; e += tpb) {
+                for (int e = rslot; e < nr + nu; e += tpr) {
                     T *M = (e < nr) ? Hw : Uw;
                     int i = (e < nr) ? e : lo + (e - nr);
                     T a0 = M[q * L + i], a1 = M[(q + 1) * L + i], a2 = M[q2 * L + i];
@@ -754,7 +813,7 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
 
 template <typename T>
 size_t chase_smem(int W, int nbulge) {
-    return sizeof(T) * ((size_t)2 * (W | 1) * W + 4 * nbulge) + sizeof(int) * (4 * nbulge + 2 * W);
+    return sizeof(T) * ((size_t)2 * (W | 1) * W + 8 * nbulge) + sizeof(int) * (8 * nbulge + 2 * W);
 }
 
 template <typename T>
@@ -762,7 +821,7 @@ int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W
                  int nbulge, const T *trd, T *Uw, int waves) {
     size_t sm = chase_smem<T>(W, nbulge);
     if (sm > 160 * 1024) return -1;
-    if (nbulge > 64 * waves) return -1;
+    if (nbulge > 64 || (64 * waves - 64) / nbulge < 1) return -1;  // one lead lane per bulge in wavefront 0
     static std::mutex mu;
     static size_t attr8 = 0, attr16 = 0;
     auto k8 = k_chase<T, 512>;
