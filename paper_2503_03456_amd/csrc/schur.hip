@@ -37,8 +37,9 @@ static bool g_tune_set[2] = {false, false};
 static SchurTune g_tune[2];
 static SchurTune tune_default(bool fp32) {
     // selected by paper_2503_03456_amd.autotune (n = 2048, normal recipe,
-    // seed 7): Schur time 0.560 -> 0.389 s (binary32), 0.842 -> 0.601 s (binary64)
-    return fp32 ? SchurTune{128, 48, 20, 64, 40, 4, 16} : SchurTune{64, 48, 16, 48, 50, 4, 8};
+    // seed 7), last run after the chase kernel's reflector change: Schur
+    // time 0.258 -> 0.252 s (binary32), 0.407 -> 0.396 s (binary64)
+    return fp32 ? SchurTune{64, 48, 20, 48, 40, 7, 16} : SchurTune{64, 48, 16, 48, 40, 7, 8};
 }
 template <typename T>
 SchurTune schur_tune() {
