@@ -385,6 +385,34 @@ SYLV_DEVINL int francis_wave(int n, T *H, int ldh, T *Z, int ldz, int nz, int *n
     return 0;
 }
 
+// Householder vector of x (len entries, LDS, stride 1) by wavefront 0:
+// P x = beta e1, P = I - tau v v^T, v[0] = 1, written to v (may alias x).
+// Max and scaled sum of squares are wavefront reductions.  Lanes 0..63 call
+// it; lane 0 stores tau and beta.
+template <typename T>
+SYLV_DEVINL void house_wave(int len, T *x, T *v, T *tau_out, T *beta_out) {
+    const int lane = threadIdx.x & 63;
+    const T alpha = x[0];
+    T mx = T(0);
+    for (int i = 1 + lane; i < len; i += 64) mx = fmax(mx, fabs(x[i]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    T tau = T(0), beta = alpha, sc = T(0);
+    if (mx > T(0)) {
+        T ss = T(0);
+        for (int i = 1 + lane; i < len; i += 64) { const T q = x[i] / mx; ss += q * q; }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+        const T xn = mx * sqrt(ss), nrm = hypot(alpha, xn);
+        const T b = (alpha >= T(0)) ? -nrm : nrm;
+        tau = (b - alpha) / b;
+        sc = T(1) / (alpha - b);
+        beta = b;
+    }
+    for (int i = 1 + lane; i < len; i += 64) v[i] = x[i] * sc;
+    if (lane == 0) { v[0] = T(1); *tau_out = tau; *beta_out = beta; }
+}
+
 // ---------------------------------------------------------------- k_aed
 // out[0] = status (0 ok, 1 QR cap), out[1] = nd (deflated count), out[2] =
 // ns (undeflated count); wr/wi (length nw) receive the eigenvalues of the
@@ -479,24 +507,7 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
         // reflect the spike onto its first entry: P sp = beta e1, P = I - tau v v^T
         // (v stored in sp with v[0] = 1)
         __shared__ T sh_tau, sh_beta;
-        if (tid == 0) {
-            T alpha = sp[0];
-            T mx = T(0);
-            for (int i = 1; i < ns; ++i) mx = fmax(mx, fabs(sp[i]));
-            if (mx == T(0)) { sh_tau = T(0); sh_beta = alpha; }
-            else {
-                T ss = T(0);
-                for (int i = 1; i < ns; ++i) { T q = sp[i] / mx; ss += q * q; }
-                T xn = mx * sqrt(ss);
-                T nrm = hypot(alpha, xn);
-                T b = (alpha >= T(0)) ? -nrm : nrm;
-                sh_tau = (b - alpha) / b;
-                T sc = T(1) / (alpha - b);
-                for (int i = 1; i < ns; ++i) sp[i] *= sc;
-                sh_beta = b;
-            }
-            sp[0] = T(1);
-        }
+        if (tid < 64) house_wave<T>(ns, sp, sp, &sh_tau, &sh_beta);
         __syncthreads();
         const T tau = sh_tau;
         newsub = sh_beta;
@@ -529,23 +540,7 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
         T *v = sp;  // reuse
         for (int c = 0; c + 2 < ns; ++c) {
             const int len = ns - c - 1;  // rows c+1..ns-1
-            if (tid == 0) {
-                T alpha = Tw[c * L + c + 1];
-                T mx = T(0);
-                for (int i = 1; i < len; ++i) mx = fmax(mx, fabs(Tw[c * L + c + 1 + i]));
-                if (mx == T(0)) { sh_tau = T(0); sh_beta = alpha; v[0] = T(1); for (int i = 1; i < len; ++i) v[i] = T(0); }
-                else {
-                    T ss = T(0);
-                    for (int i = 1; i < len; ++i) { T q = Tw[c * L + c + 1 + i] / mx; ss += q * q; }
-                    T xn = mx * sqrt(ss), nrm = hypot(alpha, xn);
-                    T b = (alpha >= T(0)) ? -nrm : nrm;
-                    sh_tau = (b - alpha) / b;
-                    T sc = T(1) / (alpha - b);
-                    v[0] = T(1);
-                    for (int i = 1; i < len; ++i) v[i] = Tw[c * L + c + 1 + i] * sc;
-                    sh_beta = b;
-                }
-            }
+            if (tid < 64) house_wave<T>(len, Tw + c * L + c + 1, v, &sh_tau, &sh_beta);
             __syncthreads();
             const T tau = sh_tau;
             if (tau != T(0)) {
@@ -570,10 +565,7 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
                 }
             }
             __syncthreads();
-            if (tid == 0) {
-                Tw[c * L + c + 1] = sh_beta;
-                for (int i = 1; i < len; ++i) Tw[c * L + c + 1 + i] = T(0);
-            }
+            for (int i = tid; i < len; i += NT) Tw[c * L + c + 1 + i] = (i == 0) ? sh_beta : T(0);
             __syncthreads();
         }
     }
