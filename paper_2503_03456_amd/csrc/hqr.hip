@@ -889,6 +889,27 @@ void find_ktop(hipStream_t s, T *H, int ldh, int klo, int kbot, int *out) {
 template void find_ktop<float>(hipStream_t, float *, int, int, int, int *);
 template void find_ktop<double>(hipStream_t, double *, int, int, int, int *);
 
+// Trailing entries for exceptional shifts, written to out (host-mapped or
+// device memory): out[2q] = H(i0+q, i0+q), out[2q+1] = H(i0+q, i0+q-1) for
+// q < m, out[2m] = H(i0-1, i0-2).  Requires i0 >= 2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_sub(const T *H, int ldh, int i0, int m, T *out) {
+    for (int q = threadIdx.x; q <= m; q += blockDim.x) {
+        if (q < m) {
+            out[2 * q] = CM(H, i0 + q, i0 + q, ldh);
+            out[2 * q + 1] = CM(H, i0 + q, i0 + q - 1, ldh);
+        } else {
+            out[2 * m] = CM(H, i0 - 1, i0 - 2, ldh);
+        }
+    }
+}
+template <typename T>
+void gather_sub(hipStream_t s, const T *H, int ldh, int i0, int m, T *out) {
+    hipLaunchKernelGGL((k_gather_sub<T>), dim3(1), dim3(256), 0, s, H, ldh, i0, m, out);
+}
+template void gather_sub<float>(hipStream_t, const float *, int, int, int, float *);
+template void gather_sub<double>(hipStream_t, const double *, int, int, int, double *);
+
 // Split a converged 2x2 block at (k, k) of the full n x n H (global) if its
 // eigenvalues are real; rotate rows k,k+1 / cols k,k+1 of H and U.
 template <typename T>

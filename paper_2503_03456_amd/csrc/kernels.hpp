@@ -96,6 +96,8 @@ int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W
 template <typename T>
 void find_ktop(hipStream_t s, T *H, int ldh, int klo, int kbot, int *out);
 template <typename T>
+void gather_sub(hipStream_t s, const T *H, int ldh, int i0, int m, T *out);
+template <typename T>
 void std2x2(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, int k);
 template <typename T>
 void clean_lower(hipStream_t s, int n, T *H, int ldh);

@@ -117,10 +117,16 @@ void carve(Ctx<T> &c, char *ws) {
     c.dint = reinterpret_cast<int *>(ws + off);
 }
 
+// Layout of the pinned host buffer: the small-result kernels (k_find_ktop,
+// k_aed, k_gather_sub) write their outputs there directly, so reading a
+// result costs a stream synchronisation and no copy.
+constexpr size_t HB_INT = 0;      // 8 ints: ktop / AED status and counters
+constexpr size_t HB_WR = 512;     // AED shift candidates: wr, then wi (NSMALL each)
+constexpr size_t HB_EXC = 4096;   // trailing diagonal / subdiagonal for exceptional shifts
+constexpr size_t HB_TRD = 8192;   // shifts staged for upload
+
 template <typename T>
-hipError_t readback(Ctx<T> &c, const void *dsrc, size_t bytes) {
-    hipError_t e = hipMemcpyAsync(c.hbuf, dsrc, bytes, hipMemcpyDeviceToHost, c.s);
-    if (e != hipSuccess) return e;
+hipError_t sync_host(Ctx<T> &c) {
     return hipStreamSynchronize(c.s);
 }
 
@@ -364,7 +370,11 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
     c.bf16 = (sizeof(T) == sizeof(float)) ? bf16 : 0;
     carve(c, ws);
     hessenberg<T>(s, n, H, ldh, U, ldu, c.hw, K::HNB, K::HS, c.bf16);
-    int *hi = reinterpret_cast<int *>(c.hbuf);
+    int *hi = reinterpret_cast<int *>(c.hbuf + HB_INT);
+    T *hwr = reinterpret_cast<T *>(c.hbuf + HB_WR);
+    T *hwi = hwr + K::NSMALL;
+    static_assert(HB_WR + 2 * sizeof(T) * K::NSMALL <= HB_EXC && HB_EXC + sizeof(T) * (4 * K::NBMAX + 8) <= HB_TRD,
+                  "host buffer layout");
     hipError_t err;
     int kbot = n - 1;
     int ndfl = 1;
@@ -376,16 +386,16 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
     const bool trace = std::getenv("SYLV_TRACE") != nullptr;
     long st_aed = 0, st_sweeps = 0, st_chase = 0, st_fsw = 0, st_fst = 0, st_kcyc = 0, st_defl = 0;
     while (kbot >= 0) {
-        find_ktop<T>(s, H, ldh, 0, kbot, c.dint);
-        if ((err = readback(c, c.dint, sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+        find_ktop<T>(s, H, ldh, 0, kbot, hi);
+        if ((err = sync_host(c)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
         const int ktop = hi[0];
         const int N = kbot - ktop + 1;
         if (N == 1) { kbot -= 1; ndfl = 1; continue; }
         if (N == 2) { std2x2<T>(s, n, H, ldh, U, ldu, ktop); kbot -= 2; ndfl = 1; continue; }
         if (++iters > itmax) { *qr_status = 1; break; }
         if (N <= P.nsmall) {
-            if (aed_launch<T>(s, N, H, ldh, ktop, 0, c.Zw, c.dint, c.wr, c.wi, P.aedw)) return -1;
-            if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+            if (aed_launch<T>(s, N, H, ldh, ktop, 0, c.Zw, hi, hwr, hwi, P.aedw)) return -1;
+            if ((err = sync_host(c)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
             ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5];
             prof_add_work(KID_AED, 12.0 * (2.0 * N + 3.0) * hi[4]);
             if (hi[0] != 0) { *qr_status = 1; break; }
@@ -397,21 +407,16 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         // aggressive early deflation on the trailing window
         const int nw = std::min(P.nw, N - 1);
         const int kwtop = kbot - nw + 1;
-        if (aed_launch<T>(s, nw, H, ldh, kwtop, 1, c.Zw, c.dint, c.wr, c.wi, P.aedw)) return -1;
-        if ((err = readback(c, c.dint, 8 * sizeof(int))) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+        if (aed_launch<T>(s, nw, H, ldh, kwtop, 1, c.Zw, hi, hwr, hwi, P.aedw)) return -1;
+        if ((err = sync_host(c)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
         const int aed_st = hi[0], nd = hi[1], nsu = hi[2];
         ++st_aed; st_fsw += hi[3]; st_fst += hi[4]; st_kcyc += hi[5]; st_defl += nd;
         prof_add_work(KID_AED, 12.0 * (2.0 * nw + 3.0) * hi[4]);
         if (aed_st == 0) apply_window(c, kwtop, nw, c.Zw);
         // shift candidates: eigenvalues of the undeflated part of the window
         wr.clear(); wi.clear();
-        if (aed_st == 0 && nsu > 0) {
-            hipMemcpyAsync(c.hbuf, c.wr, sizeof(T) * nsu, hipMemcpyDeviceToHost, s);
-            hipMemcpyAsync(c.hbuf + sizeof(T) * nsu, c.wi, sizeof(T) * nsu, hipMemcpyDeviceToHost, s);
-            if ((err = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
-            const T *hv = reinterpret_cast<const T *>(c.hbuf);
-            for (int i = 0; i < nsu; ++i) { wr.push_back(hv[i]); wi.push_back(hv[nsu + i]); }
-        }
+        if (aed_st == 0 && nsu > 0)
+            for (int i = 0; i < nsu; ++i) { wr.push_back(hwr[i]); wi.push_back(hwi[i]); }
         const int ndef = (aed_st == 0) ? nd : 0;
         kbot -= ndef;
         ndfl = (ndef > 0) ? 1 : ndfl + 1;
@@ -423,21 +428,12 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         if (ndfl % 6 == 0 || wr.size() < 2) {
             // exceptional shifts from the trailing subdiagonal magnitudes
             const int cnt = 2 * maxb + 2;
-            std::vector<T> dd(2 * (size_t)cnt);
-            // gather H(i,i) and H(i,i-1) for i in [kbot-cnt+1, kbot]
+            // H(i,i) and H(i,i-1) for i in [i0, kbot], and H(i0-1, i0-2)
             int i0 = std::max(ktop + 2, kbot - cnt + 1);
             int m = kbot - i0 + 1;
-            for (int q = 0; q < m; ++q) {
-                hipMemcpyAsync(c.hbuf + sizeof(T) * (2 * q), H + (size_t)(i0 + q) * ldh + (i0 + q),
-                               sizeof(T), hipMemcpyDeviceToHost, s);
-                hipMemcpyAsync(c.hbuf + sizeof(T) * (2 * q + 1), H + (size_t)(i0 + q - 1) * ldh + (i0 + q),
-                               sizeof(T), hipMemcpyDeviceToHost, s);
-            }
-            // also H(i0-1, i0-2)
-            hipMemcpyAsync(c.hbuf + sizeof(T) * (2 * m), H + (size_t)(i0 - 2) * ldh + (i0 - 1), sizeof(T),
-                           hipMemcpyDeviceToHost, s);
-            if ((err = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
-            const T *hv = reinterpret_cast<const T *>(c.hbuf);
+            T *hv = reinterpret_cast<T *>(c.hbuf + HB_EXC);
+            gather_sub<T>(s, H, ldh, i0, m, hv);
+            if ((err = sync_host(c)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
             trd.clear();
             // exceptional pair aa +- i sqrt(0.4375) ss (the eigenvalues of
             // [[aa, -0.4375 ss], [ss, aa]])
@@ -462,7 +458,7 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         }
         const int nb = (int)trd.size() / 3;
         if (nb == 0) continue;
-        T *htrd = reinterpret_cast<T *>(c.hbuf + 4096);
+        T *htrd = reinterpret_cast<T *>(c.hbuf + HB_TRD);
         for (size_t q = 0; q < trd.size(); ++q) htrd[q] = trd[q];
         hipMemcpyAsync(c.trd, htrd, sizeof(T) * trd.size(), hipMemcpyHostToDevice, s);
         // multishift sweep over [ktop, kbot]
@@ -480,8 +476,8 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
             ++st_chase;
             apply_window(c, ws_, W, c.Uw);
         }
-        // the pinned copy of the shifts must stay valid until the upload ran
-        if ((err = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)err;
+        // no synchronisation here: the staged shifts are next rewritten after
+        // the next find_ktop synchronisation, which follows their upload
     }
     clean_lower<T>(s, n, H, ldh);
     if (trace)
