@@ -76,8 +76,8 @@ size_t schur_work_bytes(int n) {
     const int wmax = K::WMAX;
     const int wide = std::max(wmax, K::NSMALL);
     size_t e = hessenberg_work_elems<T>(n, K::HNB, K::HS) + (size_t)K::NSMALL * K::NSMALL +
-               (size_t)wmax * wmax + (size_t)wide * n + 2 * (size_t)K::NSMALL + 3 * K::NBMAX + 64;
-    return e * sizeof(T) + 1024 + 64 * sizeof(int);
+               (size_t)wmax * wmax + (size_t)wide * n + 3 * K::NBMAX + 64;
+    return e * sizeof(T) + 1024;
 }
 template size_t schur_work_bytes<float>(int);
 template size_t schur_work_bytes<double>(int);
@@ -92,9 +92,8 @@ struct Ctx {
     int ldh;
     T *U;
     int ldu;
-    T *hw, *Zw, *Uw, *tmp, *wr, *wi, *trd;
-    int *dint;
-    char *hbuf;  // pinned host staging (>= 4 KiB)
+    T *hw, *Zw, *Uw, *tmp, *trd;
+    char *hbuf;  // pinned host buffer (64 KiB): small kernel results, staged shifts
     int bf16;    // off-window updates with bfloat16 inputs (binary32 forms only)
 };
 
@@ -109,12 +108,7 @@ void carve(Ctx<T> &c, char *ws) {
     c.Zw = p; p += (size_t)K::NSMALL * K::NSMALL;
     c.Uw = p; p += (size_t)wmax * wmax;
     c.tmp = p; p += (size_t)wide * n;
-    c.wr = p; p += K::NSMALL;
-    c.wi = p; p += K::NSMALL;
     c.trd = p; p += 3 * K::NBMAX + 64;
-    size_t off = reinterpret_cast<char *>(p) - ws;
-    off = (off + 255) & ~(size_t)255;
-    c.dint = reinterpret_cast<int *>(ws + off);
 }
 
 // Layout of the pinned host buffer: the small-result kernels (k_find_ktop,
