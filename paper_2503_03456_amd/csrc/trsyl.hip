@@ -131,14 +131,19 @@ SYLV_DEVINL void tile_gemm(typename mfma16t<T>::v4 (&acc)[2][2], const T *Ap, in
     // A slab: tile rows 0..p-1 x k0..k0+TBK-1 ; B slab: k0.. x tile cols 0..q-1.
     // Each thread holds 8 elements of each slab; the next slab is loaded
     // into registers while the current one feeds the MFMAs.
+    // Loads at clamped addresses (p, q, K >= 1 here), masked by a 0/1
+    // factor (the operands are finite): no branch per load, so the 16 loads
+    // of a slab are in flight together.
     T ra[8], rb[8];
     auto load = [&](int k0) {
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr) {
-            int i = l, k = w + 4 * rr;
-            ra[rr] = (i < p && k0 + k < K) ? Ap[(size_t)(k0 + k) * lda_ + i] : T(0);
-            int kk = t & 31, j = (t >> 5) + 8 * rr;
-            rb[rr] = (j < q && k0 + kk < K) ? Bp[(size_t)j * ldb_ + k0 + kk] : T(0);
+            const int i = l, k = w + 4 * rr;
+            const int ic = i < p ? i : p - 1, kc = k0 + k < K ? k0 + k : K - 1;
+            ra[rr] = Ap[(size_t)kc * lda_ + ic] * T((i < p && k0 + k < K) ? 1 : 0);
+            const int kk = t & 31, j = (t >> 5) + 8 * rr;
+            const int jc = j < q ? j : q - 1, kkc = k0 + kk < K ? k0 + kk : K - 1;
+            rb[rr] = Bp[(size_t)jc * ldb_ + kkc] * T((j < q && k0 + kk < K) ? 1 : 0);
         }
     };
     const int nk = (K + TBK - 1) / TBK;
@@ -200,6 +205,7 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
         c1 = tile_bound(TB, ldtb, n, J + 1);
     }
     const int p = r1 - r0, q = c1 - c0;
+    if (p <= 0 || q <= 0) return;  // empty tile (uniform over the workgroup)
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = w & 1, wn = w >> 1;
 
@@ -223,14 +229,17 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
             for (int r = 0; r < 4; ++r) {
                 int i = 32 * wm + 16 * a + (l & 15);
                 int j = 32 * wn + 16 * b + mfma16t<T>::orow(l, r);
-                T v = T(0);
-                if (i < p && j < q) v = C[(size_t)(c0 + j) * ldc + r0 + i] - acc[a][b][r];
-                sC[j * TLD + i] = v;
+                const int ic = i < p ? i : p - 1, jc = j < q ? j : q - 1;
+                const T cv = C[(size_t)(c0 + jc) * ldc + r0 + ic];
+                sC[j * TLD + i] = (cv - acc[a][b][r]) * T((i < p && j < q) ? 1 : 0);
             }
+#pragma unroll 8
     for (int e = t; e < TS * TS; e += 256) {
-        int i = e % TS, j = e / TS;
-        sA[j * TLD + i] = (i < p && j < p) ? CM(TA, r0 + i, r0 + j, ldta) : T(0);
-        sB[j * TLD + i] = (i < q && j < q) ? CM(TB, c0 + i, c0 + j, ldtb) : T(0);
+        const int i = e % TS, j = e / TS;
+        const T av = CM(TA, r0 + (i < p ? i : p - 1), r0 + (j < p ? j : p - 1), ldta);
+        const T bv = CM(TB, c0 + (i < q ? i : q - 1), c0 + (j < q ? j : q - 1), ldtb);
+        sA[j * TLD + i] = av * T((i < p && j < p) ? 1 : 0);
+        sB[j * TLD + i] = bv * T((i < q && j < q) ? 1 : 0);
     }
     __syncthreads();
     // block structure of the diagonal tiles (start rows of 1x1/2x2 blocks)
@@ -374,6 +383,7 @@ __global__ __launch_bounds__(256) void k_trsyl_update(int m, int n, const T *__r
     };
     const int r0 = rb_(I), r1 = rb_(I + 1), c0 = cb_(J), c1 = cb_(J + 1);
     const int p = r1 - r0, q = c1 - c0;
+    if (p <= 0 || q <= 0) return;
     v4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
