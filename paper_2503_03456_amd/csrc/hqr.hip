@@ -2,7 +2,7 @@
 // Schur factorisations the paper's Sec. 2.1 assumes, computed by the QR
 // algorithm of Golub & Van Loan, Sec. 7.5).
 //
-// Three building blocks, all single-workgroup and LDS-resident:
+// Building blocks, all single-workgroup and LDS-resident:
 //   * francis_lds: implicit double-shift QR sweeps on a small dense upper
 //     Hessenberg matrix held in LDS, accumulating the orthogonal factor;
 //     deflation on negligible subdiagonal entries, exceptional shifts every
@@ -19,8 +19,10 @@
 //   * k_chase: one window phase of a small-bulge multishift sweep (part I of
 //     the same reference): a chain of bulges spaced three rows apart moves
 //     `adv` rows down inside an LDS window while the window's orthogonal
-//     factor is accumulated in LDS; the updates outside the window are
-//     applied afterwards with MFMA GEMMs by the host driver.
+//     factor is accumulated in LDS.  A step is a left phase and a right
+//     phase; in the right phase one lane per bulge also forms the bulge's
+//     next reflector.  The updates outside the window follow in one MFMA
+//     launch (k_win_update).
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
