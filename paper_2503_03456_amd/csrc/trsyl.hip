@@ -7,15 +7,17 @@
 // it in its block column (through TA) and on the tiles left of it in its
 // block row (through TB), so all tiles on one anti-diagonal (counted from
 // the bottom-left corner) are independent: one launch per anti-diagonal,
-// one workgroup per tile.  Each workgroup
-//   1. forms the updated right-hand side
+// one workgroup per tile.  The updated right-hand side
 //        C_IJ - TA(I, below) Y(below, J) - Y(I, left) TB(left, J)
-//      on MFMA (the GEMM-shaped off-diagonal updates), and
-//   2. solves the small quasi-triangular tile equation in LDS by a wavefront
-//      over its 1x1/2x2 diagonal-block pairs: every pair is a p*q <= 4 linear
-//      system solved by Gaussian elimination with complete pivoting; a pivot
-//      below s_min = u * max(max|TA|, max|TB|) is replaced by +-s_min and a
-//      flag is raised (the usual triangular-Sylvester convention).
+// is formed on MFMA: right-looking for a single equation (after each
+// anti-diagonal, k_trsyl_update subtracts its contributions from every later
+// tile on the whole chip), left-looking inside the tile's own workgroup for
+// the batched form.  Each tile's workgroup then solves the small
+// quasi-triangular tile equation in LDS by a wavefront over its 1x1/2x2
+// diagonal-block pairs: every pair is a p*q <= 4 linear system, embedded in
+// a fixed 4x4 system and solved by Gaussian elimination with partial
+// pivoting; a pivot below s_min = u * max(max|TA|, max|TB|) is replaced by
+// +-s_min and a flag is raised (the usual triangular-Sylvester convention).
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
