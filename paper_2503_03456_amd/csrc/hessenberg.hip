@@ -7,7 +7,9 @@
 //   k_hess_col  (one workgroup): finish y and T of the previous column,
 //               bring the current column up to date with the panel's earlier
 //               reflectors (right: -Y V(col,:)^T; left: -V T^T V^T a), and
-//               generate its Householder vector.
+//               generate its Householder vector.  For n <= 4096 the
+//               register-resident k_hess_col_r does the same with the column
+//               held in registers and latency-oriented loads and reductions.
 //   k_hess_gemv (many workgroups): y_raw = A(:, col+1:n) v over row blocks x
 //               column slices; partial sums are combined in a fixed order by
 //               the next k_hess_col (deterministic).
