@@ -7,7 +7,7 @@ float32 for the stage-level calls) CUDA tensors; they are passed to the
 library column-major.  A tensor that is not column-major is copied into a
 column-major buffer first (``colmajor``).
 
-The library must be built (``python -m paper_2503_03456_amd.build`` or
+The library must be built (``python paper_2503_03456_amd/build.py`` or
 ``__graft_entry__.build()``).  Importing this module raises ImportError if it
 is missing: there is no CPU fallback.
 """
@@ -25,7 +25,7 @@ HEADER = os.path.join(_HERE, "..", "include", "sylv.h")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_2503_03456_amd.build`")
+        f"{LIB_PATH} is missing: build it with `python paper_2503_03456_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
