@@ -57,6 +57,131 @@ def sym_flops(m, n):
     return 9.0 * (m ** 3 + n ** 3) + 4.0 * m * n * (m + n) + 2.0 * m * n
 
 
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo) and its logical core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def forward_error(np, cfg, X, workload):
+    """||X - X*||_F / ||X*||_F against the closed-form block-diagonal route of
+    the normal constructions (no Schur factorisation involved); None for
+    workloads without one."""
+    if "DA" not in cfg and "QA" not in cfg:
+        return None
+    Xh = X.detach().cpu().numpy()
+    if workload == "sym":
+        QA, QB, la, lb = cfg["QA"], cfg["QB"], cfg["eigA"], cfg["eigB"]
+        Xe = QA @ ((QA.T @ cfg["C"] @ QB) / (la[:, None] + lb[None, :])) @ QB.T
+    else:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from exact_route import exact_solution
+        Xe = exact_solution(cfg)
+    return float(np.linalg.norm(Xh - Xe) / np.linalg.norm(Xe))
+
+
+def kappa_est(np, cfg):
+    lam = np.abs(np.asarray(cfg["eigA"])[:, None] + np.asarray(cfg["eigB"])[None, :])
+    return float(lam.max() / lam.min())
+
+
+def measure_rho(torch, sy, n=2048, reps=5):
+    """rho = cost of a binary32 flop / cost of a binary64 flop on this chip,
+    measured as the ratio of the library's own n^3 GEMM times (binary32 MFMA
+    vs binary64 MFMA), with HIP events on the current stream."""
+    out = {}
+    for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        # column-major views (the library's layout, so the binding copies nothing)
+        a = torch.randn(n, n, dtype=dt, device="cuda").t()
+        b = torch.randn(n, n, dtype=dt, device="cuda").t()
+        c = torch.empty(n, n, dtype=dt, device="cuda").t()
+        sy.gemm(a, b, c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            sy.gemm(a, b, c)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    return {"rho": out["fp32"] / out["fp64"], "gemm_ms": out, "gemm_n": n,
+            "tflops": {k: 2.0 * n ** 3 / (v * 1e-3) / 1e12 for k, v in out.items()}}
+
+
+def predicted_speedup(m, n, k, rho):
+    """Flop-model speedup of the mixed path over plain binary64
+    Bartels-Stewart: (25a + 5b) / (rho (25a + 5(k+1) b) + 2(k+1) b),
+    a = m^3 + n^3, b = mn(m+n) (paper Sec. 2.2.1 and Sec. 5 cost terms)."""
+    a, b = m ** 3 + n ** 3, m * n * (m + n)
+    return (25.0 * a + 5.0 * b) / (rho * (25.0 * a + 5.0 * (k + 1) * b) + 2.0 * (k + 1) * b)
+
+
+def scipy_context(np, sample_n, target_m, target_n):
+    """scipy.linalg.solve_sylvester (LAPACK gees + trsyl on the installed
+    BLAS) on the same recipe at a smaller size, scaled by the flop model; a
+    library reference point, not a target."""
+    try:
+        import scipy.linalg as sl
+    except ImportError:
+        return None
+    import workloads
+    cfg = workloads.config2(m=sample_n, n=sample_n)
+    t0 = time.perf_counter()
+    Xs = sl.solve_sylvester(cfg["A"], cfg["B"], cfg["C"])
+    dt = time.perf_counter() - t0
+    r = cfg["C"] - cfg["A"] @ Xs - Xs @ cfg["B"]
+    rr = np.linalg.norm(r) / (np.linalg.norm(cfg["C"]) + np.linalg.norm(Xs) *
+                              (np.linalg.norm(cfg["A"]) + np.linalg.norm(cfg["B"])))
+    scale = bs_flops(sample_n, sample_n) / bs_flops(target_m, target_n)
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return {"value": scale / dt, "unit": "solves/s", "threads": threads,
+            "sample": (f"scipy.linalg.solve_sylvester at m=n={sample_n} ({dt:.2f} s, rel_res {rr:.1e}), "
+                       f"scaled to m={target_m} n={target_n} by the 25(m^3+n^3)+5mn(m+n) flop model")}
+
+
+def c4_block(np, torch, sy, count, reps):
+    """Compact record of the batched Lyapunov workload (count equations of
+    orders U{16..256}): batch time, solves/s, worst relative residual,
+    fallbacks; the library's captured graph path (nothing armed)."""
+    items, sizes = c4_batch(count)
+
+    def dev(a):
+        return torch.from_numpy(np.asfortranarray(a)).t().contiguous().t().cuda()
+
+    eqs = [(dev(A), dev(C)) for A, C, _ in items]
+    Xs = [torch.empty((int(n), int(n)), dtype=torch.float64, device="cuda").t() for n in sizes]
+    kinds = [1] * len(items)
+    work = torch.empty(sy.batched_workspace_size(kinds, list(sizes), list(sizes)), dtype=torch.uint8,
+                       device="cuda")
+    sy.solve_batched(eqs, Xs=Xs, work=work)
+    torch.cuda.synchronize()
+    per, infos = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        infos = sy.solve_batched(eqs, Xs=Xs, work=work)[1]
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - t0)
+    dt = float(np.median(per))
+    n3 = (sizes.astype(float) ** 3).sum()
+    del eqs, Xs, work
+    torch.cuda.empty_cache()
+    return {"workload": f"batched lyapunov, {count} equations, n~U{{16..256}}", "batch_ms_median": dt * 1e3,
+            "batch_ms_min": min(per) * 1e3, "solves_per_s": count / dt,
+            "max_rel_res": max(i["rel_res"] for i in infos),
+            "all_solves_at_tol": all(i["rel_res"] <= 1e-14 for i in infos),
+            "iterations_max": int(max(i["iterations"] for i in infos)),
+            "fell_back": int(sum(i["fell_back"] for i in infos)),
+            "tflops_bs_equivalent": 35.0 * n3 / dt / 1e12}
+
+
 def load_workload(name):
     import workloads
     if name == "sym":
@@ -84,6 +209,7 @@ def cpu_baseline(sample_n, target_m, target_n):
     rr = oracle.rel_residual(cfg["A"], cfg["B"], cfg["C"], X)
     scale = bs_flops(sample_n, sample_n) / bs_flops(target_m, target_n)
     return {"value": (1.0 / dt) * scale, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu()[0], "host_logical_cores": host_cpu()[1],
             "sample": (f"one oracle solve of the same recipe at m=n={sample_n} "
                        f"({dt:.2f} s, rel_res {rr:.1e}), scaled to m={target_m} n={target_n} "
                        f"by the 25(m^3+n^3)+5mn(m+n) flop model")}
@@ -102,6 +228,7 @@ def cpu_baseline_sym(sample_n, target_m, target_n):
     rr = oracle.rel_residual(cfg["A"], cfg["B"], cfg["C"], X)
     scale = sym_flops(sample_n, sample_n) / sym_flops(target_m, target_n)
     return {"value": (1.0 / dt) * scale, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu()[0], "host_logical_cores": host_cpu()[1],
             "sample": (f"one oracle symmetric-route solve of the same recipe at m=n={sample_n} "
                        f"({dt:.2f} s, rel_res {rr:.1e}), scaled to m={target_m} n={target_n} "
                        f"by the 9(m^3+n^3)+4mn(m+n) flop model")}
@@ -127,6 +254,7 @@ def cpu_baseline_batched(items, sizes, sample):
     n3 = sizes.astype(float) ** 3
     scale = n3[idx].sum() / n3.sum()
     return {"value": len(items) * scale / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "host_cpu": host_cpu()[0],
             "sample": (f"{len(idx)} equations of the batch (every {max(1, len(items) // sample)}th) "
                        f"solved by the oracle on {cores} threads in {dt:.2f} s, scaled to the "
                        f"{len(items)}-equation batch by sum n^3")}
@@ -160,16 +288,25 @@ def main_batched(args, np, torch, sy):
     kname = args.roofline_kernel if args.roofline_kernel in batched_kernels else "k_bschur"
     lib.sylv_profile_end.argtypes = [ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
-    lib.sylv_profile_begin(KERNEL_IDS[kname])
-    infos = None
+    # timed region: nothing armed, so the batch runs through its captured graph
+    infos, per = None, []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        s0 = time.perf_counter()
         infos = run()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - s0)
     t1 = time.perf_counter()
-    nl, tot, work_acc = ctypes.c_long(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
-    lib.sylv_profile_end(ctypes.byref(nl), ctypes.byref(tot), ctypes.byref(work_acc))
     dt = (t1 - t0) / args.steps
+    # roofline: separate batches with the kernel's launches bracketed by HIP
+    # events (armed profiling switches the batch to eager launches)
+    nl, tot, work_acc = ctypes.c_long(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    if args.roofline_steps > 0:
+        lib.sylv_profile_begin(KERNEL_IDS[kname])
+        for _ in range(args.roofline_steps):
+            run()
+        torch.cuda.synchronize()
+        lib.sylv_profile_end(ctypes.byref(nl), ctypes.byref(tot), ctypes.byref(work_acc))
     ok = all(i["rel_res"] <= 1e-14 for i in infos)
     iters = [i["iterations"] for i in infos]
     n3 = (sizes.astype(float) ** 3).sum()
@@ -187,7 +324,8 @@ def main_batched(args, np, torch, sy):
         t64 = (time.perf_counter() - s0) * n3 / (sizes[idx].astype(float) ** 3).sum()
     roof = None
     if nl.value > 0:
-        roof = roofline_entry(kname, nl.value, tot.value, work_acc.value, args.steps, dt)
+        roof = roofline_entry(kname, nl.value, tot.value, work_acc.value, args.roofline_steps, dt)
+        roof["note"] = "eager launches (profiling armed); the timed batches replay the captured graph"
     out = {
         "metric": "solves/s and TFLOP/s at FP64-level residual: mixed-precision vs plain FP64",
         "value": (len(items) / dt) if ok else 0.0,
@@ -197,6 +335,7 @@ def main_batched(args, np, torch, sy):
         "data": "synthetic",
         "config": {"workload": desc, "count": len(items), "path": "batched fp32 Schur + fp64 refinement",
                    "tol": 1e-14},
+        "ms_median": 1e3 * float(np.median(per)), "ms_min": 1e3 * min(per),
         "rel_res": max(i["rel_res"] for i in infos), "all_solves_at_tol": ok,
         "iterations_mean": kbar, "iterations_max": int(max(iters)),
         "fell_back": int(sum(i["fell_back"] for i in infos)),
@@ -258,6 +397,15 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed plain binary64 solves")
     ap.add_argument("--roofline-kernel", default="k_chase")
+    ap.add_argument("--roofline-steps", type=int, default=2,
+                    help="solves (batches) run after the timed region with the roofline kernel's "
+                         "launches bracketed by HIP events")
+    ap.add_argument("--rho", type=int, default=1, help="measure rho (binary32/binary64 GEMM time ratio)")
+    ap.add_argument("--c4-count", type=int, default=4096,
+                    help="default workload: equations of the batched Lyapunov block added to the line (0: off)")
+    ap.add_argument("--c4-reps", type=int, default=3)
+    ap.add_argument("--scipy-n", type=int, default=1024,
+                    help="size of the scipy.linalg.solve_sylvester context sample (0: off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=768)
     ap.add_argument("--count", type=int, default=4096, help="equations of the batched workload (c4)")
@@ -324,37 +472,36 @@ def main():
         run("fp64")
     torch.cuda.synchronize()
 
-    # timed region: K mixed-precision solves; the roofline kernel's launches
-    # are bracketed by HIP events on their launch stream
-    lib = sy.lib()
-    kid = KERNEL_IDS[args.roofline_kernel]
-    import ctypes
-    lib.sylv_profile_end.argtypes = [ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_double),
-                                     ctypes.POINTER(ctypes.c_double)]
-    lib.sylv_profile_begin(kid)
-    infos = []
+    # timed region: K mixed-precision solves, nothing armed (no per-launch
+    # events, no profiling hooks); each solve is synchronous, so per-solve
+    # wall times give the median and the minimum
+    infos, per = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        s0 = time.perf_counter()
         infos.append(run("fp32"))
+        per.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    nl, tot, work_acc = ctypes.c_long(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
-    lib.sylv_profile_end(ctypes.byref(nl), ctypes.byref(tot), ctypes.byref(work_acc))
     dt = (t1 - t0) / args.steps
     ok = all(i["rel_res"] <= 1e-14 for i in infos)
     iters = infos[-1]["iterations"]
+    fwd = forward_error(np, cfg, X, args.workload)
 
-    # plain binary64 path (context, not the headline value)
+    # plain binary64 path (the comparison, not the headline value)
     t64 = None
     inf64 = None
+    per64 = []
     if args.fp64_steps > 0:
         torch.cuda.synchronize()
-        s0 = time.perf_counter()
         for _ in range(args.fp64_steps):
+            s0 = time.perf_counter()
             inf64 = run("fp64")
+            per64.append(time.perf_counter() - s0)
         torch.cuda.synchronize()
-        t64 = (time.perf_counter() - s0) / args.fp64_steps
+        t64 = sum(per64) / len(per64)
+        fwd64 = forward_error(np, cfg, X, args.workload)
 
     # symmetric workload: the general path on the same equation (context)
     tgen = None
@@ -367,13 +514,27 @@ def main():
         torch.cuda.synchronize()
         tgen = (time.perf_counter() - s0) / args.general_steps
 
+    # roofline of the dominant kernel: separate solves with that kernel's
+    # launches bracketed by HIP events on their launch stream
+    lib = sy.lib()
+    kid = KERNEL_IDS[args.roofline_kernel]
+    import ctypes
+    lib.sylv_profile_end.argtypes = [ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    nl, tot, work_acc = ctypes.c_long(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    if args.roofline_steps > 0:
+        lib.sylv_profile_begin(kid)
+        for _ in range(args.roofline_steps):
+            run("fp32")
+        torch.cuda.synchronize()
+        lib.sylv_profile_end(ctypes.byref(nl), ctypes.byref(tot), ctypes.byref(work_acc))
+
     lo, hi = mixed_flops(m, n, iters)
     bsf = bs_flops(m, n)
     roof = None
     if nl.value > 0:
-        avg_ms = tot.value / nl.value
-        roof = roofline_entry(args.roofline_kernel, nl.value, tot.value, work_acc.value, args.steps,
-                              dt)
+        roof = roofline_entry(args.roofline_kernel, nl.value, tot.value, work_acc.value,
+                              args.roofline_steps, dt)
     out = {
         "metric": "solves/s and TFLOP/s at FP64-level residual: mixed-precision vs plain FP64",
         "value": (1.0 / dt) if ok else 0.0,
@@ -394,14 +555,17 @@ def main():
                             "sym": "symmetric route: fp32 block-Jacobi eigen-decompositions, elementwise solve, "
                                    "fp64 refinement"}[args.alg],
                    "tol": 1e-14},
+        "ms_median": 1e3 * float(np.median(per)), "ms_min": 1e3 * min(per),
         "rel_res": max(i["rel_res"] for i in infos),
+        "forward_error": fwd,
         "all_solves_at_tol": ok,
         "iterations": iters,
         "fell_back": infos[-1]["fell_back"],
         "tflops_bs_equivalent": bsf / dt / 1e12,
         "tflops_executed": {"fp32": lo / dt / 1e12, "fp64": hi / dt / 1e12},
         "fp64_plain": None if t64 is None else {
-            "solves_per_s": 1.0 / t64, "ms_per_solve": t64 * 1e3, "rel_res": inf64["rel_res"],
+            "solves_per_s": 1.0 / t64, "ms_per_solve": t64 * 1e3, "ms_median": 1e3 * float(np.median(per64)),
+            "ms_min": 1e3 * min(per64), "rel_res": inf64["rel_res"], "forward_error": fwd64,
             "tflops_bs_equivalent": bsf / t64 / 1e12},
         "speedup_vs_fp64": None if t64 is None else t64 / dt,
         "general_path": None if tgen is None else {
@@ -416,9 +580,22 @@ def main():
         if out["fp64_plain"] is not None:
             out["fp64_plain"]["tflops_bs_equivalent"] = sym_flops(m, n) / t64 / 1e12
             out["fp64_plain"]["path"] = "plain binary64 symmetric route (block Jacobi, elementwise solve)"
+    if "eigA" in cfg and "eigB" in cfg:
+        kap = kappa_est(np, cfg)
+        out["kappa_est"] = kap
+        out["forward_error_bound"] = 100 * 2.0 ** -53 * kap
+    if args.alg != "sym" and t64 is not None and args.rho:
+        r = measure_rho(torch, sy)
+        r["predicted_speedup"] = predicted_speedup(m, n, iters, r["rho"])
+        r["measured_speedup"] = t64 / dt
+        out["flop_model"] = r
+    if args.c4_count > 0 and args.workload == "c2":
+        out["batched_c4"] = c4_block(np, torch, sy, args.c4_count, args.c4_reps)
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = (cpu_baseline_sym(min(args.cpu_sample_n, 256), m, n) if args.alg == "sym"
                                else cpu_baseline(args.cpu_sample_n, m, n))
+        if args.alg != "sym" and args.scipy_n > 0:
+            out["scipy_context"] = scipy_context(np, args.scipy_n, m, n)
     if rank == 0:
         print(json.dumps(out), flush=True)
 

@@ -26,7 +26,7 @@ constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 16;
 template <typename TA, typename TB, typename TC, typename ACC>
 SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int lda, int ta,
                            const TB *__restrict__ B, int ldb, int tb, TC *__restrict__ C, int ldc,
-                           ACC alpha, ACC beta, TB bscale, int row0, int col0,
+                           double alpha, ACC beta, TB bscale, int row0, int col0,
                            ACC (&As)[GBK][GBM + GPAD], ACC (&Bs)[GBK][GBN + GPAD]) {
     typedef typename mfma16<ACC>::v4 v4;
 
@@ -101,10 +101,13 @@ SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int ld
                 int i = row0 + 32 * wm + 16 * a + (l & 15);
                 int j = col0 + 32 * wn + 16 * b + mfma16<ACC>::orow(l, r);
                 if (i < M && j < N) {
+                    // alpha is applied in the precision of C: a binary64 C
+                    // takes an un-scaling power of two without binary32
+                    // overflow or underflow
                     TC *p = C + (size_t)j * ldc + i;
-                    ACC v = alpha * acc[a][b][r];
-                    if (beta != ACC(0)) *p = (TC)v + (TC)beta * (*p);
-                    else *p = (TC)v;
+                    const TC v = (TC)alpha * (TC)acc[a][b][r];
+                    if (beta != ACC(0)) *p = v + (TC)beta * (*p);
+                    else *p = v;
                 }
             }
 }
@@ -129,7 +132,7 @@ constexpr int HBK = 32, HLD = HBK + 8;  // K slab and LDS row length (ushort; 80
 template <typename TA, typename TB, typename TC>
 SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, int lda, int ta,
                                 const TB *__restrict__ B, int ldb, int tb, TC *__restrict__ C, int ldc,
-                                float alpha, float beta, TB bscale, int row0, int col0,
+                                double alpha, float beta, TB bscale, int row0, int col0,
                                 unsigned short (&As)[GBM][HLD], unsigned short (&Bs)[GBN][HLD]) {
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = w & 1, wn = w >> 1;
@@ -204,9 +207,9 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
                 const int j = col0 + 32 * wn + 16 * b + mfma16<float>::orow(l, r);
                 if (i < M && j < N) {
                     TC *p = C + (size_t)j * ldc + i;
-                    const float v = alpha * acc[a][b][r];
-                    if (beta != 0.f) *p = (TC)v + (TC)beta * (*p);
-                    else *p = (TC)v;
+                    const TC v = (TC)alpha * (TC)acc[a][b][r];
+                    if (beta != 0.f) *p = v + (TC)beta * (*p);
+                    else *p = v;
                 }
             }
 }
@@ -214,7 +217,7 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
 template <typename TA, typename TB, typename TC>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const TA *__restrict__ A,
                                                         int lda, int ta, const TB *__restrict__ B, int ldb,
-                                                        int tb, TC *__restrict__ C, int ldc, float alpha,
+                                                        int tb, TC *__restrict__ C, int ldc, double alpha,
                                                         float beta, int tiles_m, TB bscale) {
     __shared__ __align__(16) unsigned short As[GBM][HLD];
     __shared__ __align__(16) unsigned short Bs[GBN][HLD];
@@ -230,7 +233,7 @@ template <typename TA, typename TB, typename TC, typename ACC>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
                                                    const TA *__restrict__ A, int lda, int ta,
                                                    const TB *__restrict__ B, int ldb, int tb,
-                                                   TC *__restrict__ C, int ldc, ACC alpha, ACC beta,
+                                                   TC *__restrict__ C, int ldc, double alpha, ACC beta,
                                                    int tiles_m, TB bscale) {
     __shared__ ACC As[GBK][GBM + GPAD];
     __shared__ ACC Bs[GBK][GBN + GPAD];
@@ -251,7 +254,7 @@ template <typename TA, typename TB, typename TC, typename ACC, int BF16IN>
 __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__restrict__ eqs,
                                                            const int *__restrict__ order, int fa,
                                                            int ta, int fb, int tb, int fc,
-                                                           ACC alpha, int amode, ACC beta) {
+                                                           double alpha, int amode, ACC beta) {
     typedef typename std::conditional<BF16IN != 0, unsigned short, ACC>::type LT;
     constexpr int R0 = BF16IN ? GBM : GBK, C0 = BF16IN ? HLD : GBM + GPAD;
     constexpr int C1 = BF16IN ? HLD : GBN + GPAD;
@@ -268,13 +271,13 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__rest
     // binary64 residual brought to unit size ahead of the binary32 cast);
     // == 2 multiplies the product by 1 / scale_e; amode & 4 skips equations
     // with the symmetric flag
-    ACC al = alpha;
+    double al = alpha;
     TB bs = TB(1);
     if ((amode & 3) == 1) bs = (TB)q.scale;
-    else if ((amode & 3) == 2) al = (ACC)(alpha / q.scale);
+    else if ((amode & 3) == 2) al = alpha / q.scale;
     if constexpr (BF16IN != 0)
         gemm_bf16_tile<TA, TB, TC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
-                                   q.ld[fb], tb, (TC *)q.ptr[fc], q.ld[fc], (float)al, (float)beta, bs,
+                                   q.ld[fb], tb, (TC *)q.ptr[fc], q.ld[fc], al, (float)beta, bs,
                                    tm * GBM, tn * GBN, As, Bs);
     else
         gemm_tile<TA, TB, TC, ACC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__rest
 
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch, int nmax, int fa,
-                  int ta, int fb, int tb, int fc, ACC alpha, int amode, ACC beta, int in_bf16) {
+                  int ta, int fb, int tb, int fc, double alpha, int amode, ACC beta, int in_bf16) {
     if (batch <= 0) return;
     const int tl = (nmax + GBM - 1) / GBM;
     ProfScope ps(KID_BGEMM, s);
@@ -302,17 +305,17 @@ template void gemm_batched<double, double, double, double>(hipStream_t, const Ba
                                                            int, int, int, int, int, int, int, double,
                                                            int, double, int);
 template void gemm_batched<float, float, float, float>(hipStream_t, const BatchEq *, const int *, int,
-                                                       int, int, int, int, int, int, float, int, float,
+                                                       int, int, int, int, int, int, double, int, float,
                                                        int);
 template void gemm_batched<float, double, float, float>(hipStream_t, const BatchEq *, const int *, int,
-                                                        int, int, int, int, int, int, float, int, float,
+                                                        int, int, int, int, int, int, double, int, float,
                                                         int);
 template void gemm_batched<float, float, double, float>(hipStream_t, const BatchEq *, const int *, int,
-                                                        int, int, int, int, int, int, float, int, float,
+                                                        int, int, int, int, int, int, double, int, float,
                                                         int);
 
 template <typename TA, typename TB, typename TC, typename ACC>
-void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const TA *A, int lda,
+void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, const TA *A, int lda,
           const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale, int in_bf16) {
     if (M <= 0 || N <= 0) return;
     int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
@@ -321,7 +324,7 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const T
     if constexpr (sizeof(ACC) == sizeof(float)) {
         if (in_bf16) {
             hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, TC>), dim3(tm * tn), dim3(256), 0, s, M, N, K, A,
-                               lda, ta, B, ldb, tb, C, ldc, (float)alpha, (float)beta, tm, bscale);
+                               lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale);
             return;
         }
     }
@@ -332,13 +335,13 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const T
 template void gemm<double, double, double, double>(hipStream_t, int, int, int, int, int, double,
                                                    const double *, int, const double *, int,
                                                    double, double *, int, double, int);
-template void gemm<float, float, float, float>(hipStream_t, int, int, int, int, int, float,
+template void gemm<float, float, float, float>(hipStream_t, int, int, int, int, int, double,
                                                const float *, int, const float *, int, float,
                                                float *, int, float, int);
-template void gemm<float, double, float, float>(hipStream_t, int, int, int, int, int, float,
+template void gemm<float, double, float, float>(hipStream_t, int, int, int, int, int, double,
                                                 const float *, int, const double *, int, float,
                                                 float *, int, double, int);
-template void gemm<float, float, double, float>(hipStream_t, int, int, int, int, int, float,
+template void gemm<float, float, double, float>(hipStream_t, int, int, int, int, int, double,
                                                 const float *, int, const float *, int, float,
                                                 double *, int, float, int);
 

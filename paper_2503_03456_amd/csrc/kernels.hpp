@@ -27,6 +27,7 @@ struct BatchEq {
     double nA, nC;   // ||A||_F, ||C||_F
     double rel_res, prev_rel, corr;
     double tmax;     // max |T_ij| (pivot threshold of the tri-solve)
+    double lmax;     // max |lambda_i| of the binary32 Schur form (max |l_i + l_j| = 2 lmax)
     int stall;
     int steps;       // double-shift QR steps of the Schur kernel
     double napply;   // 3-element reflector applications of the Schur kernel
@@ -51,12 +52,12 @@ void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int
 
 // gemm.hip
 template <typename TA, typename TB, typename TC, typename ACC>
-void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, ACC alpha, const TA *A, int lda,
+void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, const TA *A, int lda,
           const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale = TB(1), int in_bf16 = 0);
 
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch, int nmax, int fa,
-                  int ta, int fb, int tb, int fc, ACC alpha, int amode, ACC beta, int in_bf16 = 0);
+                  int ta, int fb, int tb, int fc, double alpha, int amode, ACC beta, int in_bf16 = 0);
 
 // blas.hip
 template <typename TS, typename TD>

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
     const double *A = (const double *)q.ptr[BF_A];
     const double *C = (const double *)q.ptr[BF_C];
     const int lda = q.ld[BF_A], ldc = q.ld[BF_C];
-    double sa = 0.0, sc = 0.0, sd = 0.0;
+    double sa = 0.0, sc = 0.0, sd = 0.0, mc = 0.0;
     for (int e = threadIdx.x; e < n * n; e += BNT) {
         const int i = e % n, j = e / n;
         const double a = A[(size_t)j * lda + i], c = C[(size_t)j * ldc + i];
@@ -87,10 +87,12 @@ __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
         sa += a * a;
         sc += c * c;
         sd += d * d;
+        mc = fmax(mc, fabs(c));
     }
     sa = wg_sum(sa, red);
     sc = wg_sum(sc, red);
     sd = wg_sum(sd, red);
+    mc = wg_max(mc, red);
     if (threadIdx.x == 0) {
         q.nA = sqrt(sa);
         q.nC = sqrt(sc);
@@ -100,7 +102,11 @@ __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
         q.iterations = 0;
         q.qr_fail = 0;
         q.flag = 0;
-        q.scale = 1.0;
+        // C brought to [1/2, 1) by a power of two before the binary32 cast of
+        // the first iterate (undone on the binary64 result)
+        int ex = 0;
+        frexp((mc > 0.0 && isfinite(mc)) ? mc : 1.0, &ex);
+        q.scale = ldexp(1.0, -ex);
         q.rel_res = INFINITY;
         q.prev_rel = INFINITY;
         q.corr = 0.0;
@@ -554,6 +560,8 @@ __global__ __launch_bounds__(BSNT) void k_bschur(BatchEq *eqs, const int *order)
 // T Y' + Y' (P T^T P) = W P with Y = Y' P; P T^T P is upper quasi-triangular,
 // so the Sylvester tile solver applies.  W P and Y' P are folded into the
 // transforms by V = U P:  W P = U^T C V,  X = U Y' V^T.
+// V = U P, TB = P T^T P, max |T_ij| and the largest eigenvalue modulus of T
+// (from its 1x1 and 2x2 diagonal blocks)
 __global__ __launch_bounds__(BNT) void k_bpost(BatchEq *eqs, const int *order) {
     __shared__ float red[8];
     BatchEq &q = eqs[order[blockIdx.x]];
@@ -570,8 +578,24 @@ __global__ __launch_bounds__(BNT) void k_bpost(BatchEq *eqs, const int *order) {
         TB[e] = T[(size_t)(n - 1 - i) * n + (n - 1 - j)];
         mx = fmaxf(mx, fabsf(T[e]));
     }
+    float lm = 0.f;
+    for (int i = threadIdx.x; i < n; i += BNT) {
+        const bool lower = i > 0 && T[(size_t)(i - 1) * n + i] != 0.f;
+        const bool upper = i + 1 < n && T[(size_t)i * n + i + 1] != 0.f;
+        if (!lower && !upper) { lm = fmaxf(lm, fabsf(T[(size_t)i * n + i])); continue; }
+        const int k = upper ? i : i - 1;
+        const double a = T[(size_t)k * n + k], b = T[(size_t)(k + 1) * n + k];
+        const double c = T[(size_t)k * n + k + 1], d = T[(size_t)(k + 1) * n + k + 1];
+        const double p = 0.5 * (a - d), disc = p * p + b * c, mid = 0.5 * (a + d);
+        const double mod = disc >= 0.0 ? fabs(mid) + sqrt(disc) : sqrt(mid * mid - disc);
+        lm = fmaxf(lm, (float)mod);
+    }
     mx = wg_max(mx, red);
-    if (threadIdx.x == 0) q.tmax = (double)mx;
+    lm = wg_max(lm, red);
+    if (threadIdx.x == 0) {
+        q.tmax = (double)mx;
+        q.lmax = (double)lm;
+    }
 }
 
 // --------------------------------------- 5. residual norms and loop control
@@ -637,15 +661,26 @@ __global__ __launch_bounds__(BNT) void k_bnorm(BatchEq *eqs, const int *order, d
     sx = wg_sum(sx, red);
     mr = wg_max(mr, red);
     if (threadIdx.x == 0) {
-        const double rel = sqrt(sr) / (q.nC + sqrt(sx) * 2.0 * q.nA);
+        // accepted when rel <= tol and the forward error it implies is at the
+        // binary64 level: rel * (2||A||_F + ||C||_F / ||X||_F) <= 100 u max|l_i + l_j|
+        // (the rule of the single-equation refinement; max|l_i + l_j| = 2 lmax)
+        const double nx = sqrt(sx);
+        const double rel = sqrt(sr) / (q.nC + nx * 2.0 * q.nA);
+        const bool at_tol = rel <= tol;
+        const double growth = 2.0 * q.nA + (nx > 0.0 ? q.nC / nx : 0.0);
+        const bool fwd_ok = rel * growth <= 100.0 * 0x1p-53 * 2.0 * q.lmax;
+        const int ok_status = q.flag ? SYLV_ST_PERTURBED : SYLV_OK;
         q.rel_res = rel;
         int done = 0;
         if (!(rel == rel) || !isfinite(rel) || !(mr == mr)) { q.status = SYLV_ST_NAN; done = 1; }
-        else if (rel <= tol) { q.status = q.flag ? SYLV_ST_PERTURBED : SYLV_OK; done = 1; }
-        else if (q.iterations >= max_iter) { q.status = SYLV_ST_NOT_CONVERGED; done = 1; }
+        else if (at_tol && fwd_ok) { q.status = ok_status; done = 1; }
+        else if (q.iterations >= max_iter) { q.status = at_tol ? ok_status : SYLV_ST_NOT_CONVERGED; done = 1; }
         else {
             if (rel > 0.5 * q.prev_rel) {
-                if (++q.stall >= 2) { q.status = SYLV_ST_NOT_CONVERGED; done = 1; }
+                if (++q.stall >= (at_tol ? 1 : 2)) {
+                    q.status = at_tol ? ok_status : SYLV_ST_NOT_CONVERGED;
+                    done = 1;
+                }
             } else {
                 q.stall = 0;
             }
@@ -707,15 +742,15 @@ static void enqueue_front(hipStream_t s, const BatchPlan &P) {
                                    P.dord + P.sb[bi]);
     }
     hipLaunchKernelGGL(k_bpost, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
-    // first iterate: W = U^T C V, Y' solves T Y' + Y' TB = W, X = U Y' V^T
-    gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 0, 0.f,
+    // first iterate: W = U^T (2^-e C) V, Y' solves T Y' + Y' TB = W, X = 2^e U Y' V^T
+    gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 1, 0.f,
                                               P.bf16);
     gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f,
                                              P.bf16);
     trsyl_batched(s, P.deq, P.dord, batch, P.nmax);
     gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f,
                                              P.bf16);
-    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 0, 0.f,
+    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 0.f,
                                               P.bf16);
     hipLaunchKernelGGL(k_bsymx, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
 }

@@ -367,7 +367,8 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
     int *hi = reinterpret_cast<int *>(c.hbuf + HB_INT);
     T *hwr = reinterpret_cast<T *>(c.hbuf + HB_WR);
     T *hwi = hwr + K::NSMALL;
-    static_assert(HB_WR + 2 * sizeof(T) * K::NSMALL <= HB_EXC && HB_EXC + sizeof(T) * (4 * K::NBMAX + 8) <= HB_TRD,
+    static_assert(HB_WR + 2 * sizeof(T) * K::NSMALL <= HB_EXC && HB_EXC + sizeof(T) * (4 * K::NBMAX + 8) <= HB_TRD &&
+                      schur_hbuf_bytes<T>() <= 65536,
                   "host buffer layout");
     hipError_t err;
     int kbot = n - 1;

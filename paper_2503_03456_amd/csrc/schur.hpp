@@ -33,9 +33,18 @@ template <typename T> int schur_tune_set(const SchurTune &t);
 template <typename T>
 size_t schur_work_bytes(int n);
 
+// Pinned host staging the driver uses: control words, AED shift candidates
+// and exceptional-shift data below 8 KiB, then up to 3 NBMAX staged shifts
+// (3 values per bulge) from byte 8192 on.
+template <typename T>
+constexpr size_t schur_hbuf_bytes() {
+    return 8192 + 3 * (size_t)SchurCaps<T>::NBMAX * sizeof(T);
+}
+
 // H (n x n, ldh): in = A, out = T (real Schur form).  U (ldu): out = Schur
-// vectors.  ws: schur_work_bytes(n) device bytes; hbuf: >= 8 KiB pinned host
-// memory.  *qr_status = 1 if the iteration cap was hit.  Synchronises s.
+// vectors.  ws: schur_work_bytes(n) device bytes; hbuf: at least
+// schur_hbuf_bytes<T>() bytes of pinned host memory.  *qr_status = 1 if the
+// iteration cap was hit.  Synchronises s.
 template <typename T>
 int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char *hbuf,
               int *qr_status, int bf16 = 0);

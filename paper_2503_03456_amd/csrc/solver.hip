@@ -128,7 +128,7 @@ struct Plan {
     double *R;        // m x n residual
     double *G;        // orthogonality check scratch, 2 * max(m,n)^2
     double *scal;     // 64 device scalars
-    double *nscr;     // 256-entry reduction scratch
+    double *nscr;     // 512-entry reduction scratch
     int *flag;        // tri-solve perturbation flag
     float *eig;       // eigenvalue scratch for sep_est (4 * max(m,n))
 };
@@ -177,7 +177,7 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
     p.R = a.take<double>((size_t)m * n);
     if (orth) p.G = a.take<double>((size_t)2 * mx * mx);
     p.scal = a.take<double>(64);
-    p.nscr = a.take<double>(256);
+    p.nscr = a.take<double>(512);
     p.flag = a.take<int>(64);
     p.eig = a.take<float>((size_t)4 * mx + 64);
 }
@@ -206,39 +206,60 @@ __global__ void k_quasi_eigs(int n, const T *Tm, int ld, float *wr, float *wi) {
     }
 }
 
-// min over i, j of |lambda_i + mu_j|: per-workgroup minima into part[],
-// then one workgroup folds them (fixed order, deterministic)
+// min and max over i, j of |lambda_i + mu_j|: per-workgroup extremes into
+// part[0..nb) (min) and part[SEP_BLOCKS..SEP_BLOCKS+nb) (max), then one
+// workgroup folds them (fixed order, deterministic)
 constexpr int SEP_BLOCKS = 256;
-__global__ __launch_bounds__(256) void k_sep_min(int m, int n, const float *wra, const float *wia,
-                                                 const float *wrb, const float *wib, double *part) {
-    __shared__ double red[256];
-    double best = 1e300;
+__global__ __launch_bounds__(256) void k_sep_range(int m, int n, const float *wra, const float *wia,
+                                                   const float *wrb, const float *wib, double *part) {
+    __shared__ double rlo[256], rhi[256];
+    double lo = 1e300, hi = 0.0;
     const size_t total = (size_t)m * n;
     for (size_t e = blockIdx.x * (size_t)256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
         const int i = (int)(e % m), j = (int)(e / m);
         const double re = (double)wra[i] + wrb[j], im = (double)wia[i] + wib[j];
-        best = fmin(best, sqrt(re * re + im * im));
+        const double a = sqrt(re * re + im * im);
+        lo = fmin(lo, a);
+        hi = fmax(hi, a);
     }
-    red[threadIdx.x] = best;
+    rlo[threadIdx.x] = lo;
+    rhi[threadIdx.x] = hi;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        if (threadIdx.x < s) {
+            rlo[threadIdx.x] = fmin(rlo[threadIdx.x], rlo[threadIdx.x + s]);
+            rhi[threadIdx.x] = fmax(rhi[threadIdx.x], rhi[threadIdx.x + s]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rlo[0];
+        part[SEP_BLOCKS + blockIdx.x] = rhi[0];
+    }
 }
 
-__global__ __launch_bounds__(256) void k_min_final(int cnt, const double *part, double *out) {
-    __shared__ double red[256];
-    double best = 1e300;
-    for (int i = threadIdx.x; i < cnt; i += 256) best = fmin(best, part[i]);
-    red[threadIdx.x] = best;
+// out[0] = min of part[0..cnt), out[1] = max of part[SEP_BLOCKS..SEP_BLOCKS+cnt)
+__global__ __launch_bounds__(256) void k_range_final(int cnt, const double *part, double *out) {
+    __shared__ double rlo[256], rhi[256];
+    double lo = 1e300, hi = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += 256) {
+        lo = fmin(lo, part[i]);
+        hi = fmax(hi, part[SEP_BLOCKS + i]);
+    }
+    rlo[threadIdx.x] = lo;
+    rhi[threadIdx.x] = hi;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        if (threadIdx.x < s) {
+            rlo[threadIdx.x] = fmin(rlo[threadIdx.x], rlo[threadIdx.x + s]);
+            rhi[threadIdx.x] = fmax(rhi[threadIdx.x], rhi[threadIdx.x + s]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) {
+        out[0] = rlo[0];
+        out[1] = rhi[0];
+    }
 }
 
 // -------------------------------------------------------- pipeline stages
@@ -311,13 +332,14 @@ template <>
 void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const double *Rin, int ldr,
                        double bscale, double *X, int ldx, bool accumulate, const double *maxab,
                        int *flag, int bf16) {
-    gemm<float, double, float, float>(s, 1, 0, m, n, m, 1.0f, st.UA, m, Rin, ldr, 0.0f, st.W1, m, bscale,
+    gemm<float, double, float, float>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0f, st.W1, m, bscale,
                                       bf16);
-    gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0f, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, bf16);
+    gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, bf16);
     if (st.diag) diag_solve<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
     else trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag, st.lsym);
-    gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0f, st.UA, m, st.Y, m, 0.0f, st.W1, m, 1.0f, bf16);
-    gemm<float, float, double, float>(s, 0, 1, m, n, n, (float)(1.0 / bscale), st.W1, m, st.UB, n,
+    gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0, st.UA, m, st.Y, m, 0.0f, st.W1, m, 1.0f, bf16);
+    // the un-scaling power of two is applied to the binary64 result
+    gemm<float, float, double, float>(s, 0, 1, m, n, n, 1.0 / bscale, st.W1, m, st.UB, n,
                                       accumulate ? 1.0f : 0.0f, X, ldx, 1.0f, bf16);
     if (st.lsym) symmetrize(s, m, X, ldx);
 }
@@ -373,7 +395,8 @@ static void orth_check(hipStream_t s, int n, const float *U, double *G, double *
     matnorm<double>(s, n, n, Gm, n, out, nscr, 0);
 }
 
-// scratch: SEP_BLOCKS doubles
+// out[0] = sep_est = min |lambda_i + mu_j|, out[1] = max |lambda_i + mu_j|
+// (kappa_est = out[1] / out[0]); scratch: 2 * SEP_BLOCKS doubles
 template <typename T>
 static void sep_estimate(hipStream_t s, int m, int n, const T *TA, const T *TB, float *eig, double *out,
                          double *scratch) {
@@ -382,12 +405,12 @@ static void sep_estimate(hipStream_t s, int m, int n, const T *TA, const T *TB, 
     hipLaunchKernelGGL((k_quasi_eigs<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, TB, n, wrb, wib);
     const size_t total = (size_t)m * n;
     const int nb = (int)std::min<size_t>(SEP_BLOCKS, (total + 255) / 256);
-    hipLaunchKernelGGL(k_sep_min, dim3(nb), dim3(256), 0, s, m, n, wra, wia, wrb, wib, scratch);
-    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, s, nb, scratch, out);
+    hipLaunchKernelGGL(k_sep_range, dim3(nb), dim3(256), 0, s, m, n, wra, wia, wrb, wib, scratch);
+    hipLaunchKernelGGL(k_range_final, dim3(1), dim3(256), 0, s, nb, scratch, out);
 }
 
 // --------------------------------------------------------------- drivers
-struct Norms { double a, b, c; };
+struct Norms { double a, b, c, cmax; };  // ||A||_F, ||B||_F, ||C||_F, max|C_ij|
 
 // Plain binary64 Bartels-Stewart on the GPU.  Returns ABI code; fills info.
 static int run_fp64(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda, const double *B,
@@ -444,16 +467,40 @@ static int mixed_forms(hipStream_t s, DevCtx *c, int m, int n, const double *A, 
     return 0;
 }
 
+// Power of two 2^-e with 2^(e-1) <= mx < 2^e: scaling by it brings a binary64
+// array with max-abs entry mx to [1/2, 1) exactly, ahead of a low-precision
+// cast (the range of binary32 and of the narrower formats, Table 2.1).
+static double pow2_scale(double mx) {
+    int ex = 0;
+    std::frexp((mx > 0 && std::isfinite(mx)) ? mx : 1.0, &ex);
+    return std::ldexp(1.0, -ex);
+}
+
 // Binary64 refinement (Alg. 3.1 in the original basis) on the forms held in
 // p.lo.  *ok = 1 on convergence.
+//
+// Stopping rule.  The iterate is accepted once the relative residual of
+// eq. (2.1) is at most tol and, in addition, the forward error it implies is
+// at the level the binary64 Bartels-Stewart solution reaches (the limiting
+// accuracy of Thm 3.2): with R = C - AX - XB, ||X - X*||_F <= ||R||_F / sep,
+// so the relative error of X is at most
+//     rel_res * (||A||_F + ||B||_F + ||C||_F / ||X||_F) / sep,
+// and the target is 100 u kappa with kappa = max|l_i + m_j| / sep (u = 2^-53,
+// l, m the eigenvalues of the binary32 Schur forms).  sep cancels, so the
+// extra test is rel_res * (||A||_F + ||B||_F + ||C||_F / ||X||_F)
+// <= 100 u max|l_i + m_j|.  Steps past tol stop when the residual no longer
+// halves (it has reached its floor) or at max_iter; the result is then still
+// accepted because tol holds.
 static int mixed_refine(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
                         const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
                         int ldx, Plan &p, const Norms &nm, const sylv_opts &o, int bf16, int qa, int qb,
                         sylv_info *info, int *ok) {
     *ok = 0;
     hipMemsetAsync(p.flag, 0, sizeof(int), s);
-    // first iterate: X0 = U Y V^T from the low-precision factors
-    correction<float>(s, m, n, p.lo, C, ldc, 1.0, X, ldx, false, p.scal + 12, p.flag, bf16);
+    // first iterate: X0 = U Y V^T from the low-precision factors, C brought to
+    // unit size by a power of two before the cast
+    const double sc0 = pow2_scale(nm.cmax);
+    correction<float>(s, m, n, p.lo, C, ldc, sc0, X, ldx, false, p.scal + 12, p.flag, bf16);
     double prev = INFINITY, rel = INFINITY, corr = 0.0;
     int it = 0, stall = 0, status = SYLV_ST_NOT_CONVERGED;
     double h[32];
@@ -463,14 +510,16 @@ static int mixed_refine(hipStream_t s, DevCtx *c, int m, int n, const double *A,
         if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
         rel = h[0] / (nm.c + h[2] * (nm.a + nm.b));
         if (!std::isfinite(rel)) { status = SYLV_ST_NAN; break; }
-        if (rel <= o.tol) { status = SYLV_OK; break; }
+        const bool at_tol = rel <= o.tol;
+        const double growth = nm.a + nm.b + (h[2] > 0 ? nm.c / h[2] : 0.0);
+        const bool fwd_ok = rel * growth <= 100.0 * 0x1p-53 * h[14];
+        if (at_tol) status = SYLV_OK;
+        if (at_tol && fwd_ok) break;
         if (it >= o.max_iter) break;
-        if (rel > 0.5 * prev) { if (++stall >= 2) break; } else stall = 0;
+        if (rel > 0.5 * prev) { if (++stall >= (at_tol ? 1 : 2)) break; } else stall = 0;
         prev = rel;
         // scale R by 2^-e so that max|R| is O(1) before the low-precision cast
-        int ex = 0;
-        std::frexp(h[1] > 0 ? h[1] : 1.0, &ex);
-        double sc = std::ldexp(1.0, -ex);
+        const double sc = pow2_scale(h[1]);
         correction<float>(s, m, n, p.lo, p.R, m, sc, X, ldx, true, p.scal + 12, p.flag, bf16);
         // ||D||_F ~ ||Y||_F / sc (orthogonal factors to working accuracy)
         matnorm<float>(s, m, n, p.lo.Y, m, p.scal + 30, p.nscr, 0);
@@ -706,6 +755,9 @@ static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
     trsyl<float>(s, m, n, p.lo.TA, m, p.lo.TB, n, p.lo.Y, m, p.scal + 12, p.flag);
     cast<float, double>(s, m, n, p.lo.Y, m, q.Y, m, 1.0f);
     // Alg. 3.1 in the triangular basis
+    double hsep[2];
+    hipError_t es = read_scalars(s, c, p.scal + 13, 2, hsep);
+    if (es != hipSuccess) return SYLV_ERR_HIP - (int)es;
     double prev = INFINITY, rel = INFINITY, corr = 0.0, h[4];
     int it = 0, stall = 0, status = SYLV_ST_NOT_CONVERGED;
     for (;;) {
@@ -718,9 +770,15 @@ static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
         if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
         rel = h[0] / (nm.c + h[1] * (nm.a + nm.b));
         if (!std::isfinite(rel)) { status = SYLV_ST_NAN; break; }
-        if (rel <= o.tol) { status = SYLV_OK; break; }
+        // the stopping rule of the original-basis refinement (tol, then the
+        // forward-error level 100 u kappa_est); ||Y||_F = ||X||_F up to the
+        // binary64 orthogonality of the basis
+        const bool at_tol = rel <= o.tol;
+        const double growth = nm.a + nm.b + (h[1] > 0 ? nm.c / h[1] : 0.0);
+        if (at_tol) status = SYLV_OK;
+        if (at_tol && rel * growth <= 100.0 * 0x1p-53 * hsep[1]) break;
         if (it >= o.max_iter) break;
-        if (rel > 0.5 * prev) { if (++stall >= 2) break; } else stall = 0;
+        if (rel > 0.5 * prev) { if (++stall >= (at_tol ? 1 : 2)) break; } else stall = 0;
         prev = rel;
         // D from T_A D + D T_B = R (binary64 tri-solve), Y += D
         trsyl<double>(s, m, n, q.TA, m, q.TB, n, p.R, m, p.scal + 12, p.flag);
@@ -870,10 +928,11 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
         if (!lyap) asym_norm(s, n, B, ldb, p.scal + 44, p.nscr);
     }
     if (lyap) asym_norm(s, m, C, ldc, p.scal + 45, p.nscr);
-    double hn[6] = {0, 0, 0, 0, 0, 0};
-    hipError_t e = read_scalars(s, c, p.scal + 40, lyap ? 6 : (sym ? 5 : 3), hn);
+    matnorm<double>(s, m, n, C, ldc, p.scal + 46, p.nscr, 1);
+    double hn[7] = {0, 0, 0, 0, 0, 0, 0};
+    hipError_t e = read_scalars(s, c, p.scal + 40, 7, hn);
     if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
-    Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2]};
+    Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2], hn[6]};
     if (sym) {
         // symmetric coefficients are required up to rounding: ||A - A^T||_F
         // <= sqrt(u) ||A||_F (u = 2^-53), below binary32 resolution
@@ -1027,10 +1086,11 @@ int sylv_selector_features(int m, int n, const double *A, int lda, const double 
         matnorm<double>(s, m, m, A, lda, p.scal + 40, p.nscr, 0);
         if (!lyap) matnorm<double>(s, n, n, B, ldb, p.scal + 41, p.nscr, 0);
         matnorm<double>(s, m, n, C, ldc, p.scal + 42, p.nscr, 0);
-        double hn[3];
-        hipError_t e = read_scalars(s, c, p.scal + 40, 3, hn);
+        matnorm<double>(s, m, n, C, ldc, p.scal + 43, p.nscr, 1);
+        double hn[4];
+        hipError_t e = read_scalars(s, c, p.scal + 40, 4, hn);
         if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
-        Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2]};
+        Norms nm{hn[0], lyap ? hn[0] : hn[1], hn[2], hn[3]};
         int qa = 0, qb = 0;
         rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, 0, 1, &qa, &qb);
         if (rc) return rc;

@@ -62,7 +62,7 @@ def test_alg41_lyapunov(alg, n):
     Xo, _ = oracle.lyap_solve(A, C)
     lam = eig[:, None] + eig[None, :]
     kap = np.abs(lam).max() / np.abs(lam).min()
-    assert relerr(host(X), Xo) <= (info["rel_res"] + 1e-16) * kap * (1 + np.sqrt(n)) + 100 * U64 * kap
+    assert relerr(host(X), Xo) <= 100 * U64 * kap
     Xg = host(X)
     assert np.linalg.norm(Xg - Xg.T) <= 100 * U64 * kap * np.linalg.norm(Xg)
 

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import workloads
-from gpu_common import binding, dev, host, relerr, say
+from gpu_common import U64, binding, dev, host, relerr, say
 
 pytestmark = pytest.mark.gpu
 
@@ -99,4 +99,4 @@ def test_bf16_batched_lyapunov():
         Xo, _ = oracle.lyap_solve(A, C)
         lam = eig[:, None] + eig[None, :]
         kap = np.abs(lam).max() / np.abs(lam).min()
-        assert relerr(host(X), Xo) <= 1e-14 * kap * (1 + np.sqrt(A.shape[0])) * 4
+        assert relerr(host(X), Xo) <= 100 * U64 * kap
