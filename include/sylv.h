@@ -111,9 +111,11 @@ typedef struct {
 #define SYLV_ST_NAN           3  /* NaN or Inf in the iterate or residual                            */
 #define SYLV_ST_QR_FAILED     4  /* the QR algorithm hit its iteration cap                            */
 
-#define SYLV_ERR_HIP   (-100)
-#define SYLV_ERR_ALLOC (-200)
-#define SYLV_ERR_NOGPU (-300)
+#define SYLV_ERR_HIP     (-100)
+#define SYLV_ERR_ALLOC   (-200)
+#define SYLV_ERR_NOGPU   (-300)
+#define SYLV_ERR_SCRATCH (-400)  /* sylv_solve_noalloc: workspace beyond its static scratch */
+#define SYLV_ERR_NOINIT  (-500)  /* sylv_solve_noalloc: sylv_init not called on this device */
 
 /* Fill *opts with the defaults listed in sylv_opts. */
 void sylv_default_opts(sylv_opts *opts);
@@ -158,6 +160,34 @@ int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
                        double *const *X, const int *ldx,
                        const sylv_opts *opts, sylv_info *infos,
                        void *work, size_t work_bytes, void *stream);
+
+/* Per-device set-up for the current device: pinned host staging, the
+ * internal stream and events, and the device address of the static scratch
+ * used by sylv_solve_noalloc.  Idempotent; other entry points do this set-up
+ * themselves on first use.  Returns 0, SYLV_ERR_NOGPU, SYLV_ERR_ALLOC or
+ * SYLV_ERR_HIP - k. */
+int sylv_init(void);
+
+/* Bytes of the static device scratch behind sylv_solve_noalloc (per GPU). */
+#define SYLV_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* sylv_solve without any allocation, for callers that cannot allocate
+ * device or pinned memory at solve time (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments,
+ * semantics and results as sylv_solve, with the workspace taken from a
+ * static device array of SYLV_NOALLOC_SCRATCH_BYTES per GPU instead of a
+ * `work` argument.  Requires a prior sylv_init() on the current device
+ * (else SYLV_ERR_NOINIT).  Sizes whose sylv_workspace_size exceeds the
+ * scratch return SYLV_ERR_SCRATCH (with the defaults: m = n up to about 490;
+ * Lyapunov problems call it with B = A^T).  low = SYLV_PREC_AUTO returns -11
+ * (the selector's device copy of its weights is made on first use).  Every
+ * call on a GPU reuses that GPU's scratch, which keeps the last call's
+ * contents; nothing in it needs to start at zero.  Calls from several host
+ * threads are serialised by the library; work from several processes uses
+ * separate copies. */
+int sylv_solve_noalloc(int m, int n, const double *A, int lda, const double *B, int ldb,
+                       const double *C, int ldc, double *X, int ldx,
+                       const sylv_opts *opts, sylv_info *info, void *stream);
 
 /* Device workspace in bytes that sylv_solve_batched needs for this batch
  * (host arrays as in sylv_solve_batched); 0 for invalid arguments. */

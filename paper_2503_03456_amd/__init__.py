@@ -86,6 +86,11 @@ _lib.sylv_solve_batched.argtypes = [_i, _ip, _ip, _ip, _pp, _ip, _pp, _ip, _pp, 
 _lib.sylv_solve_batched.restype = _i
 _lib.sylv_batched_workspace_size.argtypes = [_i, _ip, _ip, _ip, ctypes.POINTER(Opts)]
 _lib.sylv_batched_workspace_size.restype = _sz
+_lib.sylv_init.argtypes = []
+_lib.sylv_init.restype = _i
+_lib.sylv_solve_noalloc.argtypes = [_i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, ctypes.POINTER(Opts),
+                                    ctypes.POINTER(Info), _vp]
+_lib.sylv_solve_noalloc.restype = _i
 _lib.sylv_status_string.argtypes = [_i]
 _lib.sylv_status_string.restype = ctypes.c_char_p
 _lib.sylv_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _i, _i, _ip, _vp]
@@ -175,6 +180,26 @@ def solve(A, B, C, X=None, work=None, stream=None, **kw):
                          X.data_ptr(), _ld(X), ctypes.byref(o), ctypes.byref(info), wp, wb,
                          _stream(stream))
     _check(rc, "sylv_solve")
+    return X, info.as_dict()
+
+
+def init():
+    """Per-device set-up of the current device (needed before solve_noalloc)."""
+    _check(_lib.sylv_init(), "sylv_init")
+
+
+def solve_noalloc(A, B, C, X, stream=None, **kw):
+    """AX + XB = C with the library's static scratch: no allocation by the
+    library or here (X must be a column-major float64 CUDA tensor)."""
+    A, B, C = colmajor(A), colmajor(B), colmajor(C)
+    m, n = C.shape
+    if X.stride(0) != 1:
+        raise ValueError("X must be column-major")
+    o = make_opts(**kw)
+    info = Info()
+    rc = _lib.sylv_solve_noalloc(m, n, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), C.data_ptr(), _ld(C),
+                                 X.data_ptr(), _ld(X), ctypes.byref(o), ctypes.byref(info), _stream(stream))
+    _check(rc, "sylv_solve_noalloc")
     return X, info.as_dict()
 
 

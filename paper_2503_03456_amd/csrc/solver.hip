@@ -1005,6 +1005,15 @@ static int solve_common(int m, int n, const double *A, int lda, const double *B,
     return rc;
 }
 
+// ------------------------------------------------ allocation-free scratch
+// Device scratch of sylv_solve_noalloc: a file-scope device array (each GPU
+// holds its own copy for the life of the process).  Host code never uses the
+// array's name as an address: sylv_init looks the copy of the current device
+// up once and keeps it in g_scratch[dev].
+constexpr size_t kScratchBytes = (size_t)SYLV_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+static void *g_scratch[64];
+
 }  // namespace sylv
 
 using namespace sylv;
@@ -1124,6 +1133,44 @@ int lyap_solve(int n, const double *A, int lda, const double *C, int ldc, double
     }
 }
 
+int sylv_init(void) {
+    try {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DevCtx *c = nullptr;
+        int rc = device_ctx(&c);
+        if (rc) return rc;
+        if (!g_scratch[c->dev]) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) return SYLV_ERR_HIP - (int)(e != hipSuccess ? e : hipErrorUnknown);
+            g_scratch[c->dev] = ptr;
+        }
+        return 0;
+    } catch (const std::bad_alloc &) {
+        return SYLV_ERR_ALLOC;
+    }
+}
+
+int sylv_solve_noalloc(int m, int n, const double *A, int lda, const double *B, int ldb, const double *C,
+                       int ldc, double *X, int ldx, const sylv_opts *opts, sylv_info *info, void *stream) {
+    sylv_opts o;
+    sylv_default_opts(&o);
+    if (opts) o = *opts;
+    // the learned selector keeps a device copy of its weights, made on first use
+    if (o.low == SYLV_PREC_AUTO) return -11;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SYLV_ERR_NOGPU;
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ptr = g_scratch[dev];
+    }
+    if (!ptr) return SYLV_ERR_NOINIT;
+    const size_t need = sylv_workspace_size(m, n, 0, &o);
+    if (need > kScratchBytes) return SYLV_ERR_SCRATCH;
+    return sylv_solve(m, n, A, lda, B, ldb, C, ldc, X, ldx, &o, info, ptr, kScratchBytes, stream);
+}
+
 const char *sylv_status_string(int code) {
     switch (code) {
         case SYLV_OK: return "ok";
@@ -1133,6 +1180,8 @@ const char *sylv_status_string(int code) {
         case SYLV_ST_QR_FAILED: return "QR algorithm (or symmetric Jacobi) iteration cap reached";
         case SYLV_ERR_ALLOC: return "device allocation failed";
         case SYLV_ERR_NOGPU: return "no gfx950 device";
+        case SYLV_ERR_NOINIT: return "sylv_init has not been called on this device";
+        case SYLV_ERR_SCRATCH: return "problem needs more than the static scratch of sylv_solve_noalloc";
         default:
             if (code <= SYLV_ERR_HIP && code > SYLV_ERR_ALLOC) return "HIP runtime error";
             if (code < 0) return "invalid argument";
