@@ -59,6 +59,17 @@ typedef enum {
                            trailing updates, off-window QR updates, transforms)
                            takes bfloat16-rounded inputs on BF16 MFMA; escalates
                            to FP32 and then FP64 when fallback is set             */
+    SYLV_PREC_FP16 = 3, /* as BF16 with binary16 (IEEE half) operands on FP16 MFMA
+                           (v_mfma_f32_16x16x32_f16, binary32 accumulation).
+                           Binary16 has 5 exponent bits (Table 2.1), so every
+                           operand is brought into its range by an exact power
+                           of two: A and B before their factorisations (T
+                           rescaled after), C and each residual before the
+                           forward transform, the tri-solve output before the
+                           back-transform; the powers are undone on the binary64
+                           result.  Escalates like BF16.  Batched Lyapunov
+                           equations skip the tri-solve scaling: a binary16
+                           overflow there gives status NaN and escalates   */
     SYLV_PREC_AUTO = 4  /* per-equation choice by the learned selector (see
                            sylv_selector_set); needs installed weights          */
 } sylv_prec;
@@ -70,7 +81,10 @@ typedef struct {
     double tol;        /* target relative residual, eq. (2.1), Frobenius (default 1e-14)          */
     int    max_iter;   /* refinement cap (default 20, the cap used in the paper's experiments)    */
     int    fallback;   /* 1: on failure escalate to the plain binary64 path (default 1)           */
-    int    orth_check; /* 0 off, 1 (default) binary64 ||U^T U - I||_F of the low-precision factors */
+    int    orth_check; /* orthogonality of the low-precision Schur vectors (Sec. 2.1: ~u_low):
+                          0 off; 1 (default) randomised estimate of ||U^T U - I||_F from 8
+                          random sign probes, O(n^2) binary64 flops; 2 exact binary64
+                          ||U^T U - I||_F by a full product, O(n^3); other values: -i  */
     int    alg;        /* SYLV_ALG_ORIG (default): refinement in the original basis (binary64
                           residual C - AX - XB, low-precision corrections); SYLV_ALG_ORTH: Alg. 4.1
                           (binary64-orthonormalised Schur vectors, Alg. 3.1 in the triangular basis
@@ -93,7 +107,8 @@ typedef struct {
 
 typedef struct {
     double rel_res;     /* eq. (2.1) at exit, binary64, Frobenius norms                         */
-    double orth_u;      /* ||U^T U - I||_F of the Schur vectors of A (0 if not checked)         */
+    double orth_u;      /* ||U^T U - I||_F of the Schur vectors of A: the probe estimate
+                           (orth_check 1) or the exact value (2); 0 if not checked              */
     double orth_v;      /* same for B (Lyapunov: equals orth_u)                                 */
     double sep_est;     /* min |lambda_i + mu_j| over the computed eigenvalues (estimate of sep) */
     double corr_ratio;  /* ||D||_F / ||X||_F of the last correction (stopping quantity of Alg. 3.1) */
@@ -262,7 +277,8 @@ int sylv_residual(int m, int n, const double *A, int lda, const double *B, int l
 /* C = alpha op(A) op(B) + beta C with op = transpose when ta/tb = 1.
  * prec FP64: double operands (FP64 MFMA); FP32: float operands (FP32 MFMA);
  * BF16: float operands rounded to bfloat16 (nearest even) on load, BF16 MFMA
- * with binary32 accumulation (the GEMM-shaped updates of the BF16 option).
+ * with binary32 accumulation (the GEMM-shaped updates of the BF16 option);
+ * FP16: the same with binary16 (nearest even, no scaling) on FP16 MFMA.
  * op(A) is m x k, op(B) is k x n. */
 int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha,
               const void *A, int lda, const void *B, int ldb, double beta,

@@ -29,7 +29,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "auto": 4}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "auto": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
 KIND = {"sylv": 0, "lyap": 1}
 
@@ -150,7 +150,7 @@ def _stream(stream):
 ALG = {"orig": 0, "orth": 1, "inv": 2, "sym": 3}
 
 
-def make_opts(low="fp32", tol=1e-14, max_iter=20, fallback=True, orth_check=True, alg="orig"):
+def make_opts(low="fp32", tol=1e-14, max_iter=20, fallback=True, orth_check=1, alg="orig"):
     o = Opts()
     _lib.sylv_default_opts(ctypes.byref(o))
     o.alg = ALG[alg] if isinstance(alg, str) else int(alg)
@@ -158,7 +158,7 @@ def make_opts(low="fp32", tol=1e-14, max_iter=20, fallback=True, orth_check=True
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.fallback = int(bool(fallback))
-    o.orth_check = int(bool(orth_check))
+    o.orth_check = int({"off": 0, "probe": 1, "full": 2}.get(orth_check, orth_check))
     return o
 
 

@@ -1,6 +1,7 @@
 // Batched entry point and selector state.
 //
-// Lyapunov equations of order 1..256 with a binary32 low precision run
+// Lyapunov equations of order 1..256 with a binary32 low precision (binary32,
+// or bfloat16 / binary16 operands in the transforms) run
 // through the batched kernels (one workgroup per equation and stage, all
 // equations in flight together, longest first); an equation whose
 // refinement does not reach the tolerance is re-solved in binary64 when the
@@ -24,7 +25,7 @@ using namespace sylv;
 
 static bool batched_eligible(int kind, int n, const sylv_opts &o) {
     return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 && o.alg == SYLV_ALG_ORIG &&
-           (o.low == SYLV_PREC_FP32 || o.low == SYLV_PREC_BF16);
+           (o.low == SYLV_PREC_FP32 || o.low == SYLV_PREC_BF16 || o.low == SYLV_PREC_FP16);
 }
 
 extern "C" size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, const int *n,
@@ -116,10 +117,11 @@ extern "C" int sylv_solve_batched(int batch, const int *kind, const int *m, cons
             sylv_info f = binf[t];
             const bool ok = f.status == SYLV_OK || f.status == SYLV_ST_PERTURBED;
             if (!ok && o.fallback) {
-                // next rung of the ladder: bfloat16 updates -> binary32 (which
-                // itself falls back to binary64) ; binary32 -> binary64
+                // next rung of the ladder: bfloat16 / binary16 updates ->
+                // binary32 (which itself falls back to binary64); binary32 ->
+                // binary64
                 sylv_opts f64 = o;
-                f64.low = (o.low == SYLV_PREC_BF16) ? SYLV_PREC_FP32 : SYLV_PREC_FP64;
+                f64.low = (o.low == SYLV_PREC_BF16 || o.low == SYLV_PREC_FP16) ? SYLV_PREC_FP32 : SYLV_PREC_FP64;
                 sylv_info g;
                 rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &f64, &g, work,
                                 work_bytes, stream);

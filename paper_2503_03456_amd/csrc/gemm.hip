@@ -125,11 +125,39 @@ SYLV_DEVINL unsigned short bf16_rne(float x) {
     return (unsigned short)(u >> 16);
 }
 
+// binary16 (round to nearest even by the hardware conversion; overflow to
+// Inf, gradual underflow), the narrow format of the FP16 option
+SYLV_DEVINL unsigned short fp16_rne(float x) {
+    const _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(unsigned short, h);
+}
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// narrow-operand formats of the GEMM-shaped updates
+constexpr int NARROW_BF16 = 1, NARROW_FP16 = 2;
+
+template <int FMT>
+SYLV_DEVINL unsigned short narrow_rne(float x) {
+    if constexpr (FMT == NARROW_FP16) return fp16_rne(x);
+    else return bf16_rne(x);
+}
+
+// one 16x16x32 MFMA step on 8 narrow values per lane
+template <int FMT>
+SYLV_DEVINL f32x4 mfma_narrow(uint4 a, uint4 b, f32x4 c) {
+    if constexpr (FMT == NARROW_FP16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                     0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                      c, 0, 0, 0);
+}
 constexpr int HBK = 32, HLD = HBK + 8;  // K slab and LDS row length (ushort; 80-byte rows)
 
-template <typename TA, typename TB, typename TC>
+template <int FMT, typename TA, typename TB, typename TC>
 SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, int lda, int ta,
                                 const TB *__restrict__ B, int ldb, int tb, TC *__restrict__ C, int ldc,
                                 double alpha, float beta, TB bscale, int row0, int col0,
@@ -157,13 +185,13 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
             const int gi = row0 + i, gk = k0 + k;
             float v = 0.f;
             if (gi < M && gk < K) v = (float)(ta ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi]);
-            ra[r] = bf16_rne(v);
+            ra[r] = narrow_rne<FMT>(v);
             int j;
             bidx(r, k, j);
             const int gj = col0 + j, gk2 = k0 + k;
             float u = 0.f;
             if (gj < N && gk2 < K) u = (float)(bscale * (tb ? B[(size_t)gk2 * ldb + gj] : B[(size_t)gj * ldb + gk2]));
-            rb[r] = bf16_rne(u);
+            rb[r] = narrow_rne<FMT>(u);
         }
     };
     auto store = [&]() {
@@ -183,18 +211,15 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
         __syncthreads();
         if (kt + 1 < nk) load((kt + 1) * HBK);
         const int kg = 8 * (l >> 4);
-        bf16x8 fa[2], fb[2];
+        uint4 fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) fa[a] = *reinterpret_cast<const uint4 *>(&As[32 * wm + 16 * a + (l & 15)][kg]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) fb[b] = *reinterpret_cast<const uint4 *>(&Bs[32 * wn + 16 * b + (l & 15)][kg]);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
-            fa[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&As[32 * wm + 16 * a + (l & 15)][kg]));
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-            fb[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&Bs[32 * wn + 16 * b + (l & 15)][kg]));
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[b], fa[a], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 2; ++b) acc[a][b] = mfma_narrow<FMT>(fb[b], fa[a], acc[a][b]);
         __syncthreads();
     }
 #pragma unroll
@@ -214,7 +239,7 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
             }
 }
 
-template <typename TA, typename TB, typename TC>
+template <int FMT, typename TA, typename TB, typename TC>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const TA *__restrict__ A,
                                                         int lda, int ta, const TB *__restrict__ B, int ldb,
                                                         int tb, TC *__restrict__ C, int ldc, double alpha,
@@ -225,8 +250,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
     int bid = blockIdx.x;
     if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
     const int tm = bid % tiles_m, tn = bid / tiles_m;
-    gemm_bf16_tile<TA, TB, TC>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, bscale, tm * GBM,
-                               tn * GBN, As, Bs);
+    gemm_bf16_tile<FMT, TA, TB, TC>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, bscale, tm * GBM,
+                                    tn * GBN, As, Bs);
 }
 
 template <typename TA, typename TB, typename TC, typename ACC>
@@ -276,7 +301,7 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__rest
     if ((amode & 3) == 1) bs = (TB)q.scale;
     else if ((amode & 3) == 2) al = alpha / q.scale;
     if constexpr (BF16IN != 0)
-        gemm_bf16_tile<TA, TB, TC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
+        gemm_bf16_tile<BF16IN, TA, TB, TC>(n, n, n, (const TA *)q.ptr[fa], q.ld[fa], ta, (const TB *)q.ptr[fb],
                                    q.ld[fb], tb, (TC *)q.ptr[fc], q.ld[fc], al, (float)beta, bs,
                                    tm * GBM, tn * GBN, As, Bs);
     else
@@ -292,9 +317,14 @@ void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch
     const int tl = (nmax + GBM - 1) / GBM;
     ProfScope ps(KID_BGEMM, s);
     if constexpr (sizeof(ACC) == sizeof(float)) {
+        if (in_bf16 == NARROW_FP16) {
+            hipLaunchKernelGGL((gemm_batched_kernel<TA, TB, TC, ACC, NARROW_FP16>), dim3(tl * tl, batch), dim3(256),
+                               0, s, eqs, order, fa, ta, fb, tb, fc, alpha, amode, beta);
+            return;
+        }
         if (in_bf16) {
-            hipLaunchKernelGGL((gemm_batched_kernel<TA, TB, TC, ACC, 1>), dim3(tl * tl, batch), dim3(256), 0,
-                               s, eqs, order, fa, ta, fb, tb, fc, alpha, amode, beta);
+            hipLaunchKernelGGL((gemm_batched_kernel<TA, TB, TC, ACC, NARROW_BF16>), dim3(tl * tl, batch), dim3(256),
+                               0, s, eqs, order, fa, ta, fb, tb, fc, alpha, amode, beta);
             return;
         }
     }
@@ -322,9 +352,14 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, cons
     prof_add_work(KID_GEMM, 2.0 * M * N * K);
     ProfScope ps(KID_GEMM, s);
     if constexpr (sizeof(ACC) == sizeof(float)) {
+        if (in_bf16 == NARROW_FP16) {
+            hipLaunchKernelGGL((gemm_bf16_kernel<NARROW_FP16, TA, TB, TC>), dim3(tm * tn), dim3(256), 0, s, M, N, K,
+                               A, lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale);
+            return;
+        }
         if (in_bf16) {
-            hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, TC>), dim3(tm * tn), dim3(256), 0, s, M, N, K, A,
-                               lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale);
+            hipLaunchKernelGGL((gemm_bf16_kernel<NARROW_BF16, TA, TB, TC>), dim3(tm * tn), dim3(256), 0, s, M, N, K,
+                               A, lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale);
             return;
         }
     }
@@ -335,6 +370,9 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, cons
 template void gemm<double, double, double, double>(hipStream_t, int, int, int, int, int, double,
                                                    const double *, int, const double *, int,
                                                    double, double *, int, double, int);
+template void gemm<float, double, double, double>(hipStream_t, int, int, int, int, int, double,
+                                                  const float *, int, const double *, int, double,
+                                                  double *, int, double, int);
 template void gemm<float, float, float, float>(hipStream_t, int, int, int, int, int, double,
                                                const float *, int, const float *, int, float,
                                                float *, int, float, int);

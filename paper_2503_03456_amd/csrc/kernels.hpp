@@ -28,6 +28,7 @@ struct BatchEq {
     double rel_res, prev_rel, corr;
     double tmax;     // max |T_ij| (pivot threshold of the tri-solve)
     double lmax;     // max |lambda_i| of the binary32 Schur form (max |l_i + l_j| = 2 lmax)
+    double orth;     // randomised estimate of ||U^T U - I||_F (binary64)
     int stall;
     int steps;       // double-shift QR steps of the Schur kernel
     double napply;   // 3-element reflector applications of the Schur kernel

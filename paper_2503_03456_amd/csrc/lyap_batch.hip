@@ -598,6 +598,58 @@ __global__ __launch_bounds__(BNT) void k_bpost(BatchEq *eqs, const int *order) {
     }
 }
 
+// Randomised estimate of ||U^T U - I||_F per equation (Hutchinson's trace
+// estimator of ||E||_F^2, E = U^T U - I): 8 probe columns z_k with entries
+// +-1/sqrt(8) from a counter-based hash (splitmix64 finaliser) of (equation,
+// entry); w_k = U z_k, then ||U^T w_k - z_k|| summed over k, in binary64
+// (binary32 U entries are exact in binary64).  O(16 n^2) flops per equation.
+constexpr int BPROBES = 8;
+__global__ __launch_bounds__(BNT) void k_borth(BatchEq *eqs, const int *order) {
+    __shared__ double wz[BPROBES][256];
+    __shared__ double red[8];
+    const int slot = order[blockIdx.x];
+    BatchEq &q = eqs[slot];
+    if (!q.active) return;
+    const int n = q.n;
+    const float *U = (const float *)q.ptr[BF_U];
+    auto z = [&](int i, int k) {
+        unsigned long long x = ((unsigned long long)(slot + 1) << 24) ^ (unsigned long long)(i * BPROBES + k);
+        x += 0x9e3779b97f4a7c15ull;
+        x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+        x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+        x ^= x >> 31;
+        return (x & 1ull) ? 0.35355339059327373 : -0.35355339059327373;
+    };
+    for (int i = threadIdx.x; i < n; i += BNT) {
+        double w[BPROBES];
+#pragma unroll
+        for (int k = 0; k < BPROBES; ++k) w[k] = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double u = (double)U[(size_t)j * n + i];
+#pragma unroll
+            for (int k = 0; k < BPROBES; ++k) w[k] += u * z(j, k);
+        }
+#pragma unroll
+        for (int k = 0; k < BPROBES; ++k) wz[k][i] = w[k];
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n; j += BNT) {
+        double e[BPROBES];
+#pragma unroll
+        for (int k = 0; k < BPROBES; ++k) e[k] = -z(j, k);
+        for (int i = 0; i < n; ++i) {
+            const double u = (double)U[(size_t)j * n + i];
+#pragma unroll
+            for (int k = 0; k < BPROBES; ++k) e[k] += u * wz[k][i];
+        }
+#pragma unroll
+        for (int k = 0; k < BPROBES; ++k) acc += e[k] * e[k];
+    }
+    acc = wg_sum(acc, red);
+    if (threadIdx.x == 0) q.orth = sqrt(acc);
+}
+
 // --------------------------------------- 5. residual norms and loop control
 // R = C (general), or R = 0 ahead of the one-product symmetric residual
 __global__ __launch_bounds__(BNT) void k_bcopy_c(BatchEq *eqs, const int *order) {
@@ -718,6 +770,7 @@ struct BatchPlan {
     int batch, nmax, bf16, max_iter;
     double tol;
     int h1, h2;       // Hessenberg buckets [0,h1) [h1,h2) [h2,batch)
+    int orth;         // orthogonality probe of the binary32 Schur vectors
     int sb[4];        // band-QR buckets [sb[i], sb[i+1])
     size_t smem[3];   // their dynamic LDS
 };
@@ -742,6 +795,7 @@ static void enqueue_front(hipStream_t s, const BatchPlan &P) {
                                    P.dord + P.sb[bi]);
     }
     hipLaunchKernelGGL(k_bpost, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
+    if (P.orth) hipLaunchKernelGGL(k_borth, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
     // first iterate: W = U^T (2^-e C) V, Y' solves T Y' + Y' TB = W, X = 2^e U Y' V^T
     gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 1, 0.f,
                                               P.bf16);
@@ -799,7 +853,7 @@ struct BatchGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     BatchEq *deq = nullptr;
-    int passes = 0, bf16 = 0, max_iter = 0;
+    int passes = 0, bf16 = 0, max_iter = 0, orth = 0;
     double tol = 0.0;
     std::vector<int> sizes;
 };
@@ -824,7 +878,7 @@ static int batch_graph_run(hipStream_t s, const BatchPlan &P, const std::vector<
     std::vector<int> sizes(P.batch);
     for (int i = 0; i < P.batch; ++i) sizes[i] = nn[order[i]];
     const bool hit = g.exec && g.deq == P.deq && g.passes == passes && g.bf16 == P.bf16 &&
-                     g.max_iter == P.max_iter && g.tol == P.tol && g.sizes == sizes;
+                     g.max_iter == P.max_iter && g.tol == P.tol && g.orth == P.orth && g.sizes == sizes;
     if (!hit) {
         if (g.exec) {
             hipGraphExecDestroy(g.exec);
@@ -850,6 +904,7 @@ static int batch_graph_run(hipStream_t s, const BatchPlan &P, const std::vector<
         g.bf16 = P.bf16;
         g.max_iter = P.max_iter;
         g.tol = P.tol;
+        g.orth = P.orth;
         g.sizes = std::move(sizes);
     }
     if ((e = hipEventRecord(g.e0, s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
@@ -926,8 +981,11 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
     BatchPlan P;
     P.deq = deq; P.dord = dord; P.dcnt = dcnt;
     P.batch = batch; P.nmax = nmax;
-    P.bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
+    // narrow operands of the transforms: 1 bfloat16, 2 binary16 (a binary16
+    // overflow of the tri-solve output shows as NaN and escalates)
+    P.bf16 = (o.low == SYLV_PREC_BF16) ? 1 : (o.low == SYLV_PREC_FP16) ? 2 : 0;
     P.tol = o.tol; P.max_iter = o.max_iter;
+    P.orth = o.orth_check != 0 ? 1 : 0;
     // Hessenberg size buckets (order is longest first): n > 128, 64 < n <= 128, n <= 64
     P.h1 = 0;
     while (P.h1 < batch && nn[order[P.h1]] > 128) ++P.h1;
@@ -1001,6 +1059,8 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
             sylv_info &f = infos[i];
             std::memset(&f, 0, sizeof(f));
             f.rel_res = q.rel_res;
+            f.orth_u = P.orth ? q.orth : 0.0;
+            f.orth_v = f.orth_u;
             f.iterations = q.iterations;
             f.precision_used = o.low;
             f.chosen = -1;

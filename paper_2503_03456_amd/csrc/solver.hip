@@ -121,19 +121,33 @@ struct OrthStage {
     double *UA, *UB;  // Alg. 4.2: binary64 copies of the low-precision factors (QA, QB hold their inverses)
 };
 
+// random probe vectors of the orthogonality estimate
+constexpr int kProbes = 8;
+
+// Narrow operand format of the GEMM-shaped updates for a precision option:
+// 0 binary32 inputs, 1 bfloat16, 2 binary16 (the code the GEMM wrappers take)
+static int narrow_of(int low) {
+    return low == SYLV_PREC_BF16 ? 1 : low == SYLV_PREC_FP16 ? 2 : 0;
+}
+static int prec_of_narrow(int nf) {
+    return nf == 1 ? SYLV_PREC_BF16 : nf == 2 ? SYLV_PREC_FP16 : SYLV_PREC_FP32;
+}
+
 struct Plan {
     Stage<float> lo;
     Stage<double> hi;
     OrthStage o;
     double *R;        // m x n residual
-    double *G;        // orthogonality check scratch, 2 * max(m,n)^2
+    double *G;        // orthogonality check scratch (full: 2 max(m,n)^2, probe: 24 max(m,n))
     double *scal;     // 64 device scalars
     double *nscr;     // 512-entry reduction scratch
     int *flag;        // tri-solve perturbation flag
     float *eig;       // eigenvalue scratch for sep_est (4 * max(m,n))
 };
 
-static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth, Plan &p,
+// orth: 0 no orthogonality check, 1 probe (three n x 8 binary64 blocks),
+// 2 full product (two n x n binary64 matrices)
+static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, int orth, Plan &p,
                  bool alg41 = false) {
     const int mx = std::max(m, n);
     std::memset(&p, 0, sizeof(p));
@@ -175,14 +189,15 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
             p.hi.schur_ws2 = a.take<char>(std::max(schur_work_bytes<double>(n), sym_eig_work_bytes<double>(n)));
     }
     p.R = a.take<double>((size_t)m * n);
-    if (orth) p.G = a.take<double>((size_t)2 * mx * mx);
+    if (orth == 2) p.G = a.take<double>((size_t)2 * mx * mx);
+    else if (orth == 1) p.G = a.take<double>((size_t)3 * kProbes * mx);
     p.scal = a.take<double>(64);
     p.nscr = a.take<double>(512);
     p.flag = a.take<int>(64);
     p.eig = a.take<float>((size_t)4 * mx + 64);
 }
 
-static size_t plan_bytes(int m, int n, bool lyap, bool need_lo, bool need_hi, bool orth,
+static size_t plan_bytes(int m, int n, bool lyap, bool need_lo, bool need_hi, int orth,
                          bool alg41 = false) {
     Arena a(nullptr);
     Plan p;
@@ -286,6 +301,25 @@ static int schur_stage(hipStream_t s, int n, const double *A, int lda, T *Tm, T 
         *qr = rc;
         return 0;
     }
+    if (bf16 == 2) {
+        // binary16 operands: A is brought to max|a_ij| in [1/2, 1) by a power
+        // of two before the factorisation (exact; U unchanged, T scaled by
+        // the same power, undone afterwards)
+        double *mx = reinterpret_cast<double *>(ws);
+        matnorm<double>(s, n, n, A, lda, mx, mx + 1, 1);
+        hipError_t e = hipMemcpyAsync(hbuf, mx, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        double amax = 0.0;
+        std::memcpy(&amax, hbuf, sizeof(double));
+        int ex = 0;
+        std::frexp((amax > 0 && std::isfinite(amax)) ? amax : 1.0, &ex);
+        cast<double, T>(s, n, n, A, lda, Tm, n, std::ldexp(1.0, -ex));
+        const int rc = schur_run<T>(s, n, Tm, n, Um, n, ws, hbuf, qr, bf16);
+        if (rc) return rc;
+        cast<T, T>(s, n, n, Tm, n, Tm, n, (T)std::ldexp(1.0, ex));
+        return 0;
+    }
     cast<double, T>(s, n, n, A, lda, Tm, n, 1.0);
     return schur_run<T>(s, n, Tm, n, Um, n, ws, hbuf, qr, bf16);
 }
@@ -322,32 +356,49 @@ static int schur_pair(hipStream_t s, DevCtx *c, int m, int n, const double *A, i
 
 // X (binary64) <- alpha * UA * tri-solve(UA^T op(Rin) UB) * UB^T (+ X when accumulate)
 // Rin is binary64 (C or the residual); bscale scales it before the cast.
-// bf16: the four transforms take bfloat16-rounded inputs (binary32 stage only).
+// nf (binary32 stage only): narrow operand format of the four transforms,
+// 1 bfloat16, 2 binary16.  With binary16 the tri-solve output Y is brought
+// to max|y_ij| in [1/2, 1) by a power of two before the back-transform (one
+// scalar read; yscr is a device scalar, hbuf pinned host staging), and the
+// power is undone on the binary64 result.
 template <typename T>
 static void correction(hipStream_t s, int m, int n, Stage<T> &st, const double *Rin, int ldr,
                        double bscale, double *X, int ldx, bool accumulate, const double *maxab,
-                       int *flag, int bf16 = 0);
+                       int *flag, int nf = 0, double *yscr = nullptr, double *nscr = nullptr,
+                       char *hbuf = nullptr);
 
 template <>
 void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const double *Rin, int ldr,
                        double bscale, double *X, int ldx, bool accumulate, const double *maxab,
-                       int *flag, int bf16) {
+                       int *flag, int nf, double *yscr, double *nscr, char *hbuf) {
     gemm<float, double, float, float>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0f, st.W1, m, bscale,
-                                      bf16);
-    gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, bf16);
+                                      nf);
+    gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, nf);
     if (st.diag) diag_solve<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
     else trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag, st.lsym);
-    gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0, st.UA, m, st.Y, m, 0.0f, st.W1, m, 1.0f, bf16);
-    // the un-scaling power of two is applied to the binary64 result
-    gemm<float, float, double, float>(s, 0, 1, m, n, n, 1.0 / bscale, st.W1, m, st.UB, n,
-                                      accumulate ? 1.0f : 0.0f, X, ldx, 1.0f, bf16);
+    double ys = 1.0;
+    if (nf == 2 && yscr && nscr && hbuf) {
+        matnorm<float>(s, m, n, st.Y, m, yscr, nscr, 1);
+        if (hipMemcpyAsync(hbuf, yscr, sizeof(double), hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipStreamSynchronize(s) == hipSuccess) {
+            double ymax = 0.0;
+            std::memcpy(&ymax, hbuf, sizeof(double));
+            int ex = 0;
+            std::frexp((ymax > 0 && std::isfinite(ymax)) ? ymax : 1.0, &ex);
+            ys = std::ldexp(1.0, -ex);
+        }
+    }
+    gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0, st.UA, m, st.Y, m, 0.0f, st.W1, m, (float)ys, nf);
+    // the un-scaling powers of two are applied to the binary64 result
+    gemm<float, float, double, float>(s, 0, 1, m, n, n, 1.0 / (bscale * ys), st.W1, m, st.UB, n,
+                                      accumulate ? 1.0f : 0.0f, X, ldx, 1.0f, nf);
     if (st.lsym) symmetrize(s, m, X, ldx);
 }
 
 template <>
 void correction<double>(hipStream_t s, int m, int n, Stage<double> &st, const double *Rin, int ldr,
                         double bscale, double *X, int ldx, bool accumulate, const double *maxab,
-                        int *flag, int) {
+                        int *flag, int, double *, double *, char *) {
     gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0, st.W1, m, bscale);
     gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0, st.Y, m);
     if (st.diag) diag_solve<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
@@ -393,6 +444,36 @@ static void orth_check(hipStream_t s, int n, const float *U, double *G, double *
     gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, Ud, n, Ud, n, 0.0, Gm, n);
     sub_identity(s, n, Gm, n);
     matnorm<double>(s, n, n, Gm, n, out, nscr, 0);
+}
+
+// Probe columns z_k (k < kProbes) with independent entries +-1/sqrt(kProbes)
+// from a counter-based hash of (seed, i, k) (the splitmix64 finaliser).
+__global__ void k_probe_vectors(int n, unsigned seed, double *Z) {
+    const size_t total = (size_t)n * kProbes;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        unsigned long long x = ((unsigned long long)seed << 40) ^ (unsigned long long)e;
+        x += 0x9e3779b97f4a7c15ull;
+        x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+        x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+        x ^= x >> 31;
+        Z[e] = (x & 1ull) ? 0.35355339059327373 : -0.35355339059327373;
+    }
+}
+
+// Randomised estimate of ||U^T U - I||_F (Hutchinson's trace estimator of
+// ||E||_F^2 = tr(E^T E) with E = U^T U - I): for independent random sign
+// vectors z, E ||E z||^2 = ||E||_F^2, so with Z = [z_1 .. z_k] / sqrt(k) the
+// value ||U^T (U Z) - Z||_F estimates ||E||_F in O(k n^2) binary64 flops
+// (binary32 U entries are exact in binary64).  G holds 3 kProbes n doubles.
+static void orth_probe(hipStream_t s, int n, const float *U, double *G, double *out, double *nscr,
+                       unsigned seed) {
+    double *Z = G, *W = G + (size_t)kProbes * n, *E = G + (size_t)2 * kProbes * n;
+    const int nb = (int)std::min<size_t>(1024, ((size_t)n * kProbes + 255) / 256);
+    hipLaunchKernelGGL(k_probe_vectors, dim3(nb), dim3(256), 0, s, n, seed, Z);
+    gemm<float, double, double, double>(s, 0, 0, n, kProbes, n, 1.0, U, n, Z, n, 0.0, W, n);
+    cast<double, double>(s, n, kProbes, Z, n, E, n, -1.0);
+    gemm<float, double, double, double>(s, 1, 0, n, kProbes, n, 1.0, U, n, W, n, 1.0, E, n);
+    matnorm<double>(s, n, kProbes, E, n, out, nscr, 0);
 }
 
 // out[0] = sep_est = min |lambda_i + mu_j|, out[1] = max |lambda_i + mu_j|
@@ -449,16 +530,20 @@ static int run_fp64(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
 
 // Low-precision Schur forms of A (and B): binary32, with the GEMM-shaped
 // updates on bfloat16 inputs when bf16 is set; then the orthogonality check
-// (orth), max|T| for the tri-solve pivot threshold and the sep estimate.
+// (orth: 1 probe estimate, 2 full product), max|T| for the tri-solve pivot
+// threshold and the sep estimate.
 static int mixed_forms(hipStream_t s, DevCtx *c, int m, int n, const double *A, int lda,
                        const double *B, int ldb, bool lyap, Plan &p, int bf16, int orth, int *qa,
                        int *qb) {
     *qa = *qb = 0;
     int rc = schur_pair<float>(s, c, m, n, A, lda, B, ldb, lyap, p.lo, qa, qb, bf16);
     if (rc) return rc;
-    if (orth) {
+    if (orth == 2) {
         orth_check(s, m, p.lo.UA, p.G, p.scal + 20, p.nscr);
         if (!lyap) orth_check(s, n, p.lo.UB, p.G, p.scal + 21, p.nscr);
+    } else if (orth == 1) {
+        orth_probe(s, m, p.lo.UA, p.G, p.scal + 20, p.nscr, 1u);
+        if (!lyap) orth_probe(s, n, p.lo.UB, p.G, p.scal + 21, p.nscr, 2u);
     }
     matnorm<float>(s, m, m, p.lo.TA, m, p.scal + 10, p.nscr, 1);
     matnorm<float>(s, n, n, p.lo.TB, n, p.scal + 11, p.nscr, 1);
@@ -500,7 +585,8 @@ static int mixed_refine(hipStream_t s, DevCtx *c, int m, int n, const double *A,
     // first iterate: X0 = U Y V^T from the low-precision factors, C brought to
     // unit size by a power of two before the cast
     const double sc0 = pow2_scale(nm.cmax);
-    correction<float>(s, m, n, p.lo, C, ldc, sc0, X, ldx, false, p.scal + 12, p.flag, bf16);
+    correction<float>(s, m, n, p.lo, C, ldc, sc0, X, ldx, false, p.scal + 12, p.flag, bf16, p.scal + 32,
+                      p.nscr, c->hbuf);
     double prev = INFINITY, rel = INFINITY, corr = 0.0;
     int it = 0, stall = 0, status = SYLV_ST_NOT_CONVERGED;
     double h[32];
@@ -520,7 +606,8 @@ static int mixed_refine(hipStream_t s, DevCtx *c, int m, int n, const double *A,
         prev = rel;
         // scale R by 2^-e so that max|R| is O(1) before the low-precision cast
         const double sc = pow2_scale(h[1]);
-        correction<float>(s, m, n, p.lo, p.R, m, sc, X, ldx, true, p.scal + 12, p.flag, bf16);
+        correction<float>(s, m, n, p.lo, p.R, m, sc, X, ldx, true, p.scal + 12, p.flag, bf16, p.scal + 32,
+                          p.nscr, c->hbuf);
         // ||D||_F ~ ||Y||_F / sc (orthogonal factors to working accuracy)
         matnorm<float>(s, m, n, p.lo.Y, m, p.scal + 30, p.nscr, 0);
         ++it;
@@ -541,7 +628,7 @@ static int mixed_refine(hipStream_t s, DevCtx *c, int m, int n, const double *A,
         info->sep_est = h[13];
         info->corr_ratio = (h[2] > 0) ? corr / h[2] : 0.0;
         info->iterations = it;
-        info->precision_used = bf16 ? SYLV_PREC_BF16 : SYLV_PREC_FP32;
+        info->precision_used = prec_of_narrow(bf16);
         info->status = status;
     }
     return 0;
@@ -555,7 +642,7 @@ static int run_mixed(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
                      int *ok) {
     *ok = 0;
     int qa = 0, qb = 0;
-    const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
+    const int bf16 = narrow_of(o.low);
     int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, bf16, o.orth_check, &qa, &qb);
     if (rc) return rc;
     return mixed_refine(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, bf16, qa, qb, info,
@@ -711,7 +798,7 @@ static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
                      const Norms &nm, const sylv_opts &o, sylv_info *info, int *ok, bool inv = false) {
     *ok = 0;
     int qa = 0, qb = 0;
-    const int bf16 = (o.low == SYLV_PREC_BF16) ? 1 : 0;
+    const int bf16 = narrow_of(o.low);
     int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, bf16, o.orth_check, &qa, &qb);
     if (rc) return rc;
     OrthStage &q = p.o;
@@ -812,7 +899,7 @@ static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
         info->sep_est = hr[13];
         info->corr_ratio = (h[1] > 0) ? corr / h[1] : 0.0;
         info->iterations = it;
-        info->precision_used = bf16 ? SYLV_PREC_BF16 : SYLV_PREC_FP32;
+        info->precision_used = prec_of_narrow(bf16);
         info->status = status;
     }
     return 0;
@@ -826,7 +913,7 @@ static int run_auto(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
                     const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
                     int ldx, Plan &p, const Norms &nm, const sylv_opts &o, sylv_info *info) {
     int qa = 0, qb = 0;
-    int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, 0, 1, &qa, &qb);
+    int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, 0, 2, &qa, &qb);
     if (rc) return rc;
     float f[SYLV_NFEAT], pr[SYLV_NCLASS];
     rc = selector_features(s, c, m, n, lyap, p, nm, f);
@@ -835,7 +922,7 @@ static int run_auto(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
     rc = selector_choose(s, c->hbuf, f, &cls, pr);
     if (rc) return rc;
     sylv_opts oo = o;
-    oo.orth_check = 1;
+    oo.orth_check = 2;
     sylv_info tmp;
     sylv_info *inf = info ? info : &tmp;
     int ok = 0, iters = 0, esc = 0;
@@ -884,12 +971,14 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     if (m > 0 && n > 0 && (C == nullptr)) return -ci;
     if (m > 0 && n > 0 && (X == nullptr)) return -(ci + 2);
     const bool autosel = o.low == SYLV_PREC_AUTO;
-    if (o.low != SYLV_PREC_FP64 && o.low != SYLV_PREC_FP32 && o.low != SYLV_PREC_BF16 && !autosel)
+    if (o.low != SYLV_PREC_FP64 && o.low != SYLV_PREC_FP32 && o.low != SYLV_PREC_BF16 &&
+        o.low != SYLV_PREC_FP16 && !autosel)
         return -(ci + 4);
     if (autosel && !selector_installed()) return -(ci + 4);
     if (!(o.tol >= 0.0) || o.max_iter < 0) return -(ci + 4);
     if (o.alg != SYLV_ALG_ORIG && o.alg != SYLV_ALG_ORTH && o.alg != SYLV_ALG_INV && o.alg != SYLV_ALG_SYM)
         return -(ci + 4);
+    if (o.orth_check < 0 || o.orth_check > 2) return -(ci + 4);
     if (info) std::memset(info, 0, sizeof(*info));
     if (m == 0 || n == 0) {
         if (info) {
@@ -905,7 +994,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     hipStream_t s = (hipStream_t)stream;
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool need_hi = !mixed || o.fallback || autosel;
-    const bool orth = mixed && (o.orth_check || autosel);
+    const int orth = !mixed ? 0 : autosel ? 2 : o.orth_check;
     const bool alg41 = mixed && !autosel && (o.alg == SYLV_ALG_ORTH || o.alg == SYLV_ALG_INV);
     const size_t need = plan_bytes(m, n, lyap, mixed, need_hi, orth, alg41);
     void *base = work;
@@ -959,8 +1048,8 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     else rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o, info, &ok);
     if (rc) return rc;
     int escalated = 0, iters = info ? info->iterations : 0;
-    if (!ok && o.fallback && o.low == SYLV_PREC_BF16) {
-        // escalation ladder: bfloat16 updates -> binary32 -> plain binary64
+    if (!ok && o.fallback && (o.low == SYLV_PREC_BF16 || o.low == SYLV_PREC_FP16)) {
+        // escalation ladder: bfloat16 / binary16 updates -> binary32 -> plain binary64
         sylv_opts o32 = o;
         o32.low = SYLV_PREC_FP32;
         rc = run_mixed(s, c, m, n, A, lda, B, ldb, lyap, C, ldc, X, ldx, p, nm, o32, info, &ok);
@@ -1035,11 +1124,12 @@ size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
     sylv_default_opts(&o);
     if (opts) o = *opts;
     if (m < 0 || (!lyap && n < 0)) return 0;
+    if (o.orth_check < 0 || o.orth_check > 2) return 0;
     if (lyap) n = m;
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool autosel = o.low == SYLV_PREC_AUTO;
     return plan_bytes(m, n, lyap != 0, mixed, !mixed || o.fallback || autosel,
-                      mixed && (o.orth_check || autosel),
+                      !mixed ? 0 : (o.low == SYLV_PREC_AUTO) ? 2 : o.orth_check,
                       mixed && !autosel && (o.alg == SYLV_ALG_ORTH || o.alg == SYLV_ALG_INV));
 }
 
@@ -1087,11 +1177,11 @@ int sylv_selector_features(int m, int n, const double *A, int lda, const double 
         if (rc) return rc;
         hipStream_t s = (hipStream_t)stream;
         void *base = nullptr;
-        rc = ensure_work(c, plan_bytes(m, n, lyap, true, false, true), &base);
+        rc = ensure_work(c, plan_bytes(m, n, lyap, true, false, 2), &base);
         if (rc) return rc;
         Arena ar(base);
         Plan p;
-        plan(ar, m, n, lyap, true, false, true, p);
+        plan(ar, m, n, lyap, true, false, 2, p);
         matnorm<double>(s, m, m, A, lda, p.scal + 40, p.nscr, 0);
         if (!lyap) matnorm<double>(s, n, n, B, ldb, p.scal + 41, p.nscr, 0);
         matnorm<double>(s, m, n, C, ldc, p.scal + 42, p.nscr, 0);
@@ -1391,7 +1481,8 @@ int sylv_residual(int m, int n, const double *A, int lda, const double *B, int l
 
 int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha, const void *A, int lda,
               const void *B, int ldb, double beta, void *C, int ldc, void *stream) {
-    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32 && prec != SYLV_PREC_BF16) return -1;
+    if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32 && prec != SYLV_PREC_BF16 && prec != SYLV_PREC_FP16)
+        return -1;
     if (m < 0) return -4;
     if (n < 0) return -5;
     if (k < 0) return -6;
@@ -1415,7 +1506,7 @@ int sylv_gemm(int prec, int ta, int tb, int m, int n, int k, double alpha, const
     else
         gemm<float, float, float, float>(s, ta, tb, m, n, k, (float)alpha, (const float *)A, lda,
                                          (const float *)B, ldb, (float)beta, (float *)C, ldc, 1.0f,
-                                         prec == SYLV_PREC_BF16 ? 1 : 0);
+                                         narrow_of(prec));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
     return 0;
