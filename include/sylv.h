@@ -25,8 +25,9 @@
  *     stacks columns as in eq. (1.2).
  *   - Matrix arguments (A, B, C, X and the stage-level T, U, Y) are DEVICE
  *     pointers.  The caller owns them.  A, B and C are never modified; X is
- *     fully written.  Every other pointer argument (opts, info, size
- *     arrays, pointer arrays) is a HOST pointer.
+ *     fully written.  Every other pointer argument (opts, size arrays,
+ *     pointer arrays) is a HOST pointer; the per-equation sylv_info results
+ *     may be in host or device memory.
  *   - `stream` is a hipStream_t passed as void*.  NULL means the default
  *     stream.  All work is enqueued on `stream`; the solve entry points make
  *     host decisions from device results (deflation points of the QR
@@ -36,11 +37,18 @@
  *     the size returned by the matching *_workspace_size call; with
  *     work == NULL the library allocates (and caches per device) what it
  *     needs.
+ *   - Graph capture: the solve calls (sylv_solve, lyap_solve,
+ *     sylv_solve_batched, sylv_solve_noalloc) check the stream first and,
+ *     when it is being captured, return SYLV_ERR_CAPTURE_ALLOC (work ==
+ *     NULL) or SYLV_ERR_CAPTURE without touching the stream: their stages
+ *     take host decisions from device results (QR deflation points,
+ *     residual norms).  The batched path records its own graph internally.
  *   - Return value (synchronous errors only): 0 = success; -i = the i-th
  *     argument is invalid (negative size, leading dimension too small, NULL
  *     pointer with a positive size, workspace too small); SYLV_ERR_HIP - k
  *     = HIP runtime error k; SYLV_ERR_ALLOC = device allocation failed;
- *     SYLV_ERR_NOGPU = no usable gfx950 device.
+ *     SYLV_ERR_NOGPU = no usable gfx950 device; SYLV_ERR_CAPTURE(_ALLOC) as
+ *     above.
  *   - Numerical outcome is reported per equation in sylv_info.status.
  */
 #ifndef SYLV_H
@@ -129,8 +137,12 @@ typedef struct {
 #define SYLV_ERR_HIP     (-100)
 #define SYLV_ERR_ALLOC   (-200)
 #define SYLV_ERR_NOGPU   (-300)
-#define SYLV_ERR_SCRATCH (-400)  /* sylv_solve_noalloc: workspace beyond its static scratch */
-#define SYLV_ERR_NOINIT  (-500)  /* sylv_solve_noalloc: sylv_init not called on this device */
+/* below every SYLV_ERR_HIP - k (HIP error codes are < 1100) */
+#define SYLV_ERR_SCRATCH (-2000)  /* sylv_solve_noalloc: workspace beyond its static scratch */
+#define SYLV_ERR_NOINIT  (-2001)  /* sylv_solve_noalloc: sylv_init not called on this device */
+#define SYLV_ERR_CAPTURE_ALLOC (-2002)  /* stream under graph capture and work == NULL           */
+#define SYLV_ERR_CAPTURE (-2003)  /* stream under graph capture: the solves read device results on
+                                     the host between stages, so they cannot be recorded        */
 
 /* Fill *opts with the defaults listed in sylv_opts. */
 void sylv_default_opts(sylv_opts *opts);
@@ -141,7 +153,9 @@ void sylv_default_opts(sylv_opts *opts);
 size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts);
 
 /* Solve AX + XB = C (eq. (1.1)), A m x m, B n x n, C and X m x n.
- * opts may be NULL (defaults).  info must be a host pointer (may be NULL). */
+ * opts may be NULL (defaults).  info (may be NULL) is host memory (pageable
+ * or pinned) or device memory; a device info is filled by a copy on
+ * `stream` before the call returns. */
 int sylv_solve(int m, int n, const double *A, int lda, const double *B, int ldb,
                const double *C, int ldc, double *X, int ldx,
                const sylv_opts *opts, sylv_info *info,
@@ -157,7 +171,7 @@ int lyap_solve(int n, const double *A, int lda, const double *C, int ldc,
  * SYLV_KIND_LYAP; B[i] and n[i] ignored for Lyapunov, whose order is m[i]).
  * kind, m, n, lda, ldb, ldc, ldx and the pointer arrays A, B, C, X are HOST
  * arrays of length batch; the matrices they point to live in device memory
- * (column-major, binary64).  infos is a host array of length batch (may be
+ * (column-major, binary64).  infos is a host or device array of length batch (may be
  * NULL).  Lyapunov equations of order 1..256 with low = SYLV_PREC_FP32 are
  * solved together (Sec. 4 batched workloads): one workgroup per equation in
  * every stage, equations ordered longest first, Schur form, tri-solve and
@@ -166,7 +180,7 @@ int lyap_solve(int n, const double *A, int lda, const double *C, int ldc,
  * when opts->fallback is set (info.fell_back = 1).  All other equations go
  * through sylv_solve / lyap_solve one after another.  work (device, may be
  * NULL: the library keeps its own) must hold sylv_batched_workspace_size
- * bytes.  Returns 0, -i for an invalid i-th argument (-15: work too small),
+ * bytes; infos may also be a device array.  Returns 0, -i for an invalid i-th argument (-15: work too small),
  * or SYLV_ERR_*; synchronises the stream before returning. */
 int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
                        const double *const *A, const int *lda,
@@ -316,6 +330,38 @@ int sylv_mlp_train_step(int n, const float *feats, const int *labels, float *par
  * nvalues = 0 uninstalls them (AUTO is then an invalid option).  Returns 0,
  * -1 for a NULL or non-finite blob, -2 for a wrong length. */
 int sylv_selector_set(const float *blob, int nvalues);
+
+/* Install selector weights from a file written by the package's selector
+ * module (little-endian: 8 bytes "SYLVSEL1", int32 5443, int32 16, int32 3,
+ * then 5443 parameters, 16 feature means and 16 feature standard deviations
+ * as binary32).  Returns 0, -1 if the file cannot be opened, -2 for a wrong
+ * header or a short file, -3 for non-finite values. */
+int sylv_selector_load(const char *path);
+
+/* Training options of sylv_selector_train. */
+typedef struct {
+    int   epochs;   /* passes over the samples (default 30)          */
+    int   batch;    /* mini-batch size (default 512)                 */
+    float lr;       /* Adam step size (default 1e-3)                 */
+    unsigned long long seed; /* initial weights and shuffling (default 0) */
+} sylv_train_opts;
+
+void sylv_default_train_opts(sylv_train_opts *opts);
+
+/* Train the selector network on the GPU: feats (device, n_samples x 16
+ * row-major, raw features as sylv_selector_features returns them), labels
+ * (device, int32 class per sample).  The feature means and standard
+ * deviations are computed on the device and the network is trained on the
+ * standardised features by the library's forward/backward/Adam kernels
+ * (He-normal initial weights, shuffled mini-batches, mean cross-entropy).
+ * weights_out (device, 5443 + 32 floats) receives the blob sylv_selector_set
+ * takes (params, means, standard deviations); loss_hist (host, `epochs`
+ * floats, may be NULL) the mean batch loss of every epoch.  opts may be
+ * NULL (defaults).  Allocates its own device scratch; synchronises the
+ * stream.  Returns 0, -i for an invalid i-th argument, or SYLV_ERR_*. */
+int sylv_selector_train(int n_samples, const float *feats, const int *labels,
+                        const sylv_train_opts *opts, float *weights_out, float *loss_hist,
+                        void *stream);
 
 /* The 16 selector features of one equation (A, B, C device pointers,
  * binary64, column-major; B = NULL selects the Lyapunov equation

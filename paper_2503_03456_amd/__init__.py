@@ -91,6 +91,8 @@ _lib.sylv_init.restype = _i
 _lib.sylv_solve_noalloc.argtypes = [_i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, ctypes.POINTER(Opts),
                                     ctypes.POINTER(Info), _vp]
 _lib.sylv_solve_noalloc.restype = _i
+_lib.sylv_selector_load.argtypes = [ctypes.c_char_p]
+_lib.sylv_selector_load.restype = _i
 _lib.sylv_status_string.argtypes = [_i]
 _lib.sylv_status_string.restype = ctypes.c_char_p
 _lib.sylv_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _i, _i, _ip, _vp]

@@ -53,11 +53,29 @@ extern "C" size_t sylv_batched_workspace_size(int batch, const int *kind, const 
     return std::max(b, single);
 }
 
+static int solve_batched_impl(int batch, const int *kind, const int *m, const int *n,
+                              const double *const *A, const int *lda, const double *const *B,
+                              const int *ldb, const double *const *C, const int *ldc,
+                              double *const *X, const int *ldx, const sylv_opts *opts,
+                              sylv_info *infos, void *work, size_t work_bytes, void *stream);
+
 extern "C" int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
                                   const double *const *A, const int *lda, const double *const *B,
                                   const int *ldb, const double *const *C, const int *ldc,
                                   double *const *X, const int *ldx, const sylv_opts *opts,
                                   sylv_info *infos, void *work, size_t work_bytes, void *stream) {
+    if (batch <= 0) return batch < 0 ? -1 : 0;
+    InfoSink sink(infos, batch);
+    const int rc = solve_batched_impl(batch, kind, m, n, A, lda, B, ldb, C, ldc, X, ldx, opts, sink.host(), work,
+                                      work_bytes, stream);
+    return sink.finish(rc, (hipStream_t)stream);
+}
+
+static int solve_batched_impl(int batch, const int *kind, const int *m, const int *n,
+                              const double *const *A, const int *lda, const double *const *B,
+                              const int *ldb, const double *const *C, const int *ldc,
+                              double *const *X, const int *ldx, const sylv_opts *opts,
+                              sylv_info *infos, void *work, size_t work_bytes, void *stream) {
     if (batch < 0) return -1;
     if (batch == 0) return 0;
     if (!kind) return -2;
@@ -76,6 +94,7 @@ extern "C" int sylv_solve_batched(int batch, const int *kind, const int *m, cons
     if (opts) o = *opts;
     if (!(o.tol >= 0.0) || o.max_iter < 0) return -13;
     hipStream_t s = (hipStream_t)stream;
+    if (const int cap = stream_capture_code(s, work == nullptr)) return cap;
 
     // equations for the batched kernels (validated like the single path)
     std::vector<int> idx, bn, blda, bldc, bldx;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <mutex>
+#include <vector>
+#include "../../include/sylv.h"
 
 namespace sylv {
 
@@ -37,12 +39,32 @@ struct BatchEq {
     int sym;         // C symmetric to rounding: X kept symmetric, one-product residual, half tri-solve
 };
 
+// mlp.hip: feature standardisation and mini-batch gathering
+void mlp_feature_stats(hipStream_t s, int n, const float *F, float *mean, float *sd);
+void mlp_standardize(hipStream_t s, int n, const float *F, const float *mean, const float *sd, float *Z);
+void mlp_gather(hipStream_t s, int cnt, const int *perm, const float *Z, const int *y, float *Zb, int *yb);
+
 // selector.hip
 bool selector_installed();
 int selector_choose(hipStream_t s, char *hbuf, const float *feats, int *cls, float *probs);
 
 // solver.hip
 std::mutex &lib_mutex();
+int stream_capture_code(hipStream_t s, bool needs_alloc);
+bool is_device_pointer(const void *p);
+// Per-equation results for a caller array that may live in device memory:
+// host() is where the solver writes, finish() copies to the device array
+// (and synchronises) when the caller's pointer is device memory.
+class InfoSink {
+  public:
+    InfoSink(sylv_info *user, int count);
+    sylv_info *host();
+    int finish(int rc, hipStream_t s);
+  private:
+    sylv_info *user_;
+    int count_;
+    std::vector<sylv_info> local_;
+};
 int device_work(size_t bytes, void **work, char **hbuf);
 
 // lyap_batch.hip: all equations Lyapunov of order 1..256

@@ -10,6 +10,7 @@
 // gradient with one thread per parameter summing over its samples in a fixed
 // order; a second kernel sums the partials in workgroup order, divides by
 // the batch size and applies Adam (Kingma & Ba, Algorithm 1).
+#include <algorithm>
 #include "common.hpp"
 #include "kernels.hpp"
 #include "../../include/sylv.h"
@@ -171,6 +172,71 @@ __global__ void k_sum_loss(int n, const float *lossv, float *out) {
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = red[0] / (float)n;
+}
+
+// Per-feature mean and standard deviation (population, binary64 sums in a
+// fixed order) of n raw feature rows; a deviation below 1e-6 is set to 1.
+__global__ __launch_bounds__(256) void k_feat_stats(int n, const float *__restrict__ F, float *mean, float *sd) {
+    __shared__ double r1[256], r2[256];
+    const int k = blockIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double v = F[(size_t)i * NIN + k];
+        a += v;
+        b += v * v;
+    }
+    r1[threadIdx.x] = a;
+    r2[threadIdx.x] = b;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            r1[threadIdx.x] += r1[threadIdx.x + st];
+            r2[threadIdx.x] += r2[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mu = r1[0] / n;
+        const double var = fmax(r2[0] / n - mu * mu, 0.0);
+        const double d = sqrt(var);
+        mean[k] = (float)mu;
+        sd[k] = d < 1e-6 ? 1.f : (float)d;
+    }
+}
+
+// Z = (F - mean) / sd, row-major n x 16
+__global__ void k_standardize(int n, const float *__restrict__ F, const float *__restrict__ mean,
+                              const float *__restrict__ sd, float *__restrict__ Z) {
+    const size_t total = (size_t)n * NIN;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % NIN);
+        const float d = sd[k] > 0.f ? sd[k] : 1.f;
+        Z[e] = (F[e] - mean[k]) / d;
+    }
+}
+
+// rows perm[0..cnt) of Z and labels into Zb, yb
+__global__ void k_gather_rows(int cnt, const int *__restrict__ perm, const float *__restrict__ Z,
+                              const int *__restrict__ y, float *__restrict__ Zb, int *__restrict__ yb) {
+    const int total = cnt * NIN;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int r = e / NIN, k = e % NIN;
+        const int src = perm[r];
+        Zb[e] = Z[(size_t)src * NIN + k];
+        if (k == 0) yb[r] = y[src];
+    }
+}
+
+void mlp_feature_stats(hipStream_t s, int n, const float *F, float *mean, float *sd) {
+    hipLaunchKernelGGL(k_feat_stats, dim3(NIN), dim3(256), 0, s, n, F, mean, sd);
+}
+void mlp_standardize(hipStream_t s, int n, const float *F, const float *mean, const float *sd, float *Z) {
+    const int nb = (int)std::min<size_t>(1024, ((size_t)n * NIN + 255) / 256);
+    hipLaunchKernelGGL(k_standardize, dim3(nb), dim3(256), 0, s, n, F, mean, sd, Z);
+}
+void mlp_gather(hipStream_t s, int cnt, const int *perm, const float *Z, const int *y, float *Zb, int *yb) {
+    const int nb = std::min(1024, (cnt * NIN + 255) / 256);
+    hipLaunchKernelGGL(k_gather_rows, dim3(nb), dim3(256), 0, s, cnt, perm, Z, y, Zb, yb);
 }
 
 }  // namespace sylv

@@ -90,6 +90,38 @@ int device_work(size_t bytes, void **work, char **hbuf) {
     return ensure_work(c, bytes, work);
 }
 
+// SYLV_ERR_CAPTURE_ALLOC (work == NULL) or SYLV_ERR_CAPTURE when `s` is being
+// captured into a graph, else 0
+int stream_capture_code(hipStream_t s, bool needs_alloc) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return 0;
+    if (cs == hipStreamCaptureStatusNone) return 0;
+    return needs_alloc ? SYLV_ERR_CAPTURE_ALLOC : SYLV_ERR_CAPTURE;
+}
+
+// True when p is device memory (an info array the caller keeps on the GPU);
+// host memory, pinned or pageable, is written directly.  Any error the query
+// leaves behind is cleared.
+bool is_device_pointer(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof(at));
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    (void)hipGetLastError();
+    return e == hipSuccess && at.type == hipMemoryTypeDevice;
+}
+
+InfoSink::InfoSink(sylv_info *user, int count) : user_(user), count_(count) {
+    if (user && count > 0 && is_device_pointer(user)) local_.resize((size_t)count);
+}
+sylv_info *InfoSink::host() { return local_.empty() ? user_ : local_.data(); }
+int InfoSink::finish(int rc, hipStream_t s) {
+    if (rc != 0 || local_.empty()) return rc;
+    hipError_t e = hipMemcpyAsync(user_, local_.data(), sizeof(sylv_info) * local_.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? 0 : SYLV_ERR_HIP - (int)e;
+}
+
 // ----------------------------------------------------------- workspace plan
 struct Arena {
     char *base;
@@ -987,6 +1019,13 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
         }
         return 0;
     }
+    {
+        // the solve reads device results on the host between its stages, so
+        // it cannot be recorded into a graph; with work == NULL it would also
+        // allocate.  Refuse before any other call on the stream.
+        const int cap = stream_capture_code((hipStream_t)stream, work == nullptr);
+        if (cap) return cap;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     DevCtx *c = nullptr;
     int rc = device_ctx(&c);
@@ -1206,8 +1245,10 @@ int sylv_solve(int m, int n, const double *A, int lda, const double *B, int ldb,
                int ldc, double *X, int ldx, const sylv_opts *opts, sylv_info *info, void *work,
                size_t work_bytes, void *stream) {
     try {
-        return solve_common(m, n, A, lda, B, ldb, C, ldc, X, ldx, false, opts, info, work, work_bytes,
-                            stream);
+        InfoSink sink(info, 1);
+        const int rc = solve_common(m, n, A, lda, B, ldb, C, ldc, X, ldx, false, opts, sink.host(), work,
+                                    work_bytes, stream);
+        return sink.finish(rc, (hipStream_t)stream);
     } catch (const std::bad_alloc &) {
         return SYLV_ERR_ALLOC;
     }
@@ -1216,8 +1257,10 @@ int sylv_solve(int m, int n, const double *A, int lda, const double *B, int ldb,
 int lyap_solve(int n, const double *A, int lda, const double *C, int ldc, double *X, int ldx,
                const sylv_opts *opts, sylv_info *info, void *work, size_t work_bytes, void *stream) {
     try {
-        return solve_common(n, n, A, lda, nullptr, 1, C, ldc, X, ldx, true, opts, info, work,
-                            work_bytes, stream);
+        InfoSink sink(info, 1);
+        const int rc = solve_common(n, n, A, lda, nullptr, 1, C, ldc, X, ldx, true, opts, sink.host(), work,
+                                    work_bytes, stream);
+        return sink.finish(rc, (hipStream_t)stream);
     } catch (const std::bad_alloc &) {
         return SYLV_ERR_ALLOC;
     }
@@ -1256,6 +1299,7 @@ int sylv_solve_noalloc(int m, int n, const double *A, int lda, const double *B, 
         ptr = g_scratch[dev];
     }
     if (!ptr) return SYLV_ERR_NOINIT;
+    if (const int cap = stream_capture_code((hipStream_t)stream, false)) return cap;
     const size_t need = sylv_workspace_size(m, n, 0, &o);
     if (need > kScratchBytes) return SYLV_ERR_SCRATCH;
     return sylv_solve(m, n, A, lda, B, ldb, C, ldc, X, ldx, &o, info, ptr, kScratchBytes, stream);
@@ -1271,6 +1315,9 @@ const char *sylv_status_string(int code) {
         case SYLV_ERR_ALLOC: return "device allocation failed";
         case SYLV_ERR_NOGPU: return "no gfx950 device";
         case SYLV_ERR_NOINIT: return "sylv_init has not been called on this device";
+        case SYLV_ERR_CAPTURE_ALLOC:
+            return "the stream is being captured and work == NULL asks the library to allocate";
+        case SYLV_ERR_CAPTURE: return "the stream is being captured (the solve reads device results between stages)";
         case SYLV_ERR_SCRATCH: return "problem needs more than the static scratch of sylv_solve_noalloc";
         default:
             if (code <= SYLV_ERR_HIP && code > SYLV_ERR_ALLOC) return "HIP runtime error";

@@ -80,6 +80,50 @@ def load(path=WEIGHTS):
     return z["params"], z["mean"], z["std"]
 
 
+def save_blob(path, params, mean, std):
+    """Write the weights file sylv_selector_load reads: 8 bytes "SYLVSEL1",
+    int32 5443, 16, 3, then params, means, standard deviations (binary32,
+    little-endian)."""
+    blob = pack_blob(params, mean, std).astype("<f4")
+    with open(path, "wb") as fh:
+        fh.write(b"SYLVSEL1")
+        fh.write(np.array([NPARAM, NFEAT, 3], dtype="<i4").tobytes())
+        fh.write(blob.tobytes())
+
+
+def load_file(path):
+    """Install weights from a file written by save_blob (sylv_selector_load)."""
+    rc = lib().sylv_selector_load(path.encode())
+    _check(rc, "sylv_selector_load")
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_ulonglong)]
+
+
+def train_device(F, y, epochs=30, batch=512, lr=1e-3, seed=0, stream=None):
+    """Train through sylv_selector_train: standardisation, initialisation,
+    shuffling and the optimiser all in the library.  Returns (params, mean,
+    std, per-epoch mean loss)."""
+    L = lib()
+    L.sylv_selector_train.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(TrainOpts),
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
+    L.sylv_selector_train.restype = ctypes.c_int
+    dev = torch.device("cuda")
+    Fd = torch.from_numpy(np.ascontiguousarray(F, dtype=np.float32)).to(dev)
+    yd = torch.from_numpy(np.ascontiguousarray(y, dtype=np.int32)).to(dev)
+    out = torch.empty(NPARAM + 2 * NFEAT, dtype=torch.float32, device=dev)
+    o = TrainOpts(int(epochs), int(batch), float(lr), int(seed))
+    hist = (ctypes.c_float * max(1, epochs))()
+    st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    rc = L.sylv_selector_train(len(y), ctypes.c_void_p(Fd.data_ptr()), ctypes.c_void_p(yd.data_ptr()),
+                               ctypes.byref(o), ctypes.c_void_p(out.data_ptr()), hist, st)
+    _check(rc, "sylv_selector_train")
+    w = out.cpu().numpy()
+    return w[:NPARAM], w[NPARAM:NPARAM + NFEAT], w[NPARAM + NFEAT:], [float(v) for v in hist[:epochs]]
+
+
 def rule_params(lo=2.0, hi=6.0):
     """Hand-set weights of the same network that implement a Table 3.1 style
     rule on kappa_est (feature 6, unstandardised: mean 0, std 1): class 0 if
@@ -269,10 +313,11 @@ def main(argv=None):
         idx = np.arange(a.count)
         F, y, T, meta = make_dataset(idx, a.lo, a.hi, 200000)
         ntr = int(0.8 * len(y))
-        params, mean, std, hist = train(F[:ntr], y[:ntr], epochs=a.epochs)
+        params, mean, std, hist = train_device(F[:ntr], y[:ntr], epochs=a.epochs)
         P = predict(params, mean, std, F[ntr:])
         acc = float(np.mean(P.argmax(1) == y[ntr:])) if len(y) > ntr else float("nan")
         np.savez(a.out, params=params, mean=mean, std=std)
+        save_blob(os.path.splitext(a.out)[0] + ".bin", params, mean, std)
         summ = {"instances": int(len(y)), "train": ntr, "val": int(len(y) - ntr), "val_accuracy": acc,
                 "label_counts": [int(np.sum(y == k)) for k in range(3)], "loss_first": hist[0],
                 "loss_last": hist[-1], "sizes": [a.lo, a.hi], "k_steps": K_STEPS}

@@ -89,3 +89,12 @@ def test_status_strings(lib):
     lib.sylv_status_string.argtypes = [ctypes.c_int]
     assert lib.sylv_status_string(0) == b"ok"
     assert b"invalid" in lib.sylv_status_string(-3)
+
+
+def test_status_strings_of_library_codes(lib):
+    lib.sylv_status_string.restype = ctypes.c_char_p
+    lib.sylv_status_string.argtypes = [ctypes.c_int]
+    assert b"captured" in lib.sylv_status_string(-2002) and b"allocate" in lib.sylv_status_string(-2002)
+    assert b"captured" in lib.sylv_status_string(-2003)
+    assert b"scratch" in lib.sylv_status_string(-2000)
+    assert b"sylv_init" in lib.sylv_status_string(-2001)

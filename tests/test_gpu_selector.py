@@ -123,3 +123,42 @@ def test_trained_weights_cut_escalations(sel):
         esc[name] = n_esc
     assert esc["fp32"] >= 3
     assert esc["auto"] < esc["fp32"], esc
+
+
+def test_selector_train_entry_point(sel):
+    """sylv_selector_train: the feature statistics it computes on the device
+    equal numpy's, the loss falls, a separable synthetic set is learnt, the
+    same seed gives the same weights, and the blob installs."""
+    rs = np.random.RandomState(5)
+    n = 1500
+    F = rs.standard_normal((n, 16)).astype(np.float32) * 3.0 + 1.5
+    # class by two standardised coordinates: a task the network must fit
+    y = np.where(F[:, 6] < 0.5, 0, np.where(F[:, 6] < 3.5, 1, 2)).astype(np.int32)
+    p1, m1, s1, h1 = sel.train_device(F, y, epochs=25, batch=256, seed=7)
+    p2, m2, s2, h2 = sel.train_device(F, y, epochs=25, batch=256, seed=7)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(m1, F.astype(np.float64).mean(axis=0), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(s1, F.astype(np.float64).std(axis=0), rtol=1e-5)
+    assert h1[-1] < 0.5 * h1[0]
+    assert np.array_equal(p1, p2) and h1 == h2
+    P = sel.predict(p1, m1, s1, F)
+    assert np.mean(P.argmax(1) == y) > 0.95
+    sel.install(p1, m1, s1)
+
+
+def test_selector_load_file(sel, tmp_path):
+    """sylv_selector_load: a file written by save_blob installs the same
+    weights (forced class 2 chosen by AUTO); a wrong header is refused."""
+    sy = binding()
+    path = str(tmp_path / "w.bin")
+    sel.save_blob(path, *sel.forced_params(2))
+    sel.load_file(path)
+    A, B, C = workloads.sylv_random(9, 30, 20)
+    X, info = sy.solve(dev(A), dev(B), dev(C), low="auto")
+    torch.cuda.synchronize()
+    assert info["chosen"] == 2 and info["precision_used"] == "fp64" and info["rel_res"] <= TOL
+    bad = str(tmp_path / "bad.bin")
+    with open(bad, "wb") as fh:
+        fh.write(b"SYLVSEL0" + b"\0" * 64)
+    assert sy.lib().sylv_selector_load(bad.encode()) == -2
+    assert sy.lib().sylv_selector_load(str(tmp_path / "missing.bin").encode()) == -1

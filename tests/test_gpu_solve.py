@@ -139,3 +139,26 @@ def test_caller_workspace():
     small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
     with pytest.raises(sy.SylvError):
         sy.solve(dev(A), dev(B), dev(C), work=small)
+
+
+def test_info_in_device_memory():
+    """sylv_info may be a device array: the solve fills it by a copy on its
+    stream (single and batched calls)."""
+    import ctypes
+    sy = binding()
+    A, B, C = workloads.sylv_random(61, 50, 40)
+    dA, dB, dC = dev(A), dev(B), dev(C)
+    X = torch.empty((40, 50), dtype=torch.float64, device="cuda").t()
+    nbytes = ctypes.sizeof(sy.Info)
+    dinfo = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    o = sy.make_opts()
+    rc = sy.lib().sylv_solve(50, 40, dA.data_ptr(), sy._ld(dA), dB.data_ptr(), sy._ld(dB), dC.data_ptr(),
+                             sy._ld(dC), X.data_ptr(), sy._ld(X), ctypes.byref(o),
+                             ctypes.cast(ctypes.c_void_p(dinfo.data_ptr()), ctypes.POINTER(sy.Info)), None, 0,
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert rc == 0
+    got = sy.Info.from_buffer_copy(bytes(dinfo.cpu().numpy())).as_dict()
+    _, ref = sy.solve(dA, dB, dC)
+    torch.cuda.synchronize()
+    assert got["status"] == 0 and got["rel_res"] == ref["rel_res"] and got["iterations"] == ref["iterations"]
