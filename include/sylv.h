@@ -281,6 +281,16 @@ int sylv_sym_eig(int n, const void *S, int lds, void *d, void *Q, int ldq, int p
 int sylv_trsyl(int m, int n, const void *TA, int ldta, const void *TB, int ldtb,
                int trans_b, void *C, int ldc, int prec, int *perturbed, void *stream);
 
+/* Binary64 QR factorisation of a nearly orthogonal square matrix by
+ * CholQR2 (G = Q^T Q, R = chol(G), Q <- Q R^{-1}, twice), the binary64 QR
+ * step of Alg. 4.1 applied to the low-precision Schur vectors: Q (n x n,
+ * ldq, device, binary64) is overwritten by the Q factor with positive
+ * diag(R); R (ldr, device, may be NULL) receives the upper triangular R
+ * (zero below the diagonal) with Q_in = Q R.  *status (host, may be NULL):
+ * SYLV_OK, or SYLV_ST_NOT_CONVERGED when a Cholesky pivot was not positive
+ * (Q too far from orthogonal for a Cholesky QR).  Synchronises the stream. */
+int sylv_cholqr(int n, double *Q, int ldq, double *R, int ldr, int *status, void *stream);
+
 /* Binary64 residual R = C - A X - X op(B) with op(B) = B (lyap = 0) or A^T
  * (lyap = 1), and the relative residual of eq. (2.1) (Frobenius norms)
  * returned in *rel_res (host).  R (ldr) may be NULL. */

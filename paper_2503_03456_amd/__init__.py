@@ -91,6 +91,8 @@ _lib.sylv_init.restype = _i
 _lib.sylv_solve_noalloc.argtypes = [_i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, ctypes.POINTER(Opts),
                                     ctypes.POINTER(Info), _vp]
 _lib.sylv_solve_noalloc.restype = _i
+_lib.sylv_cholqr.argtypes = [_i, _vp, _i, _vp, _i, _ip, _vp]
+_lib.sylv_cholqr.restype = _i
 _lib.sylv_selector_load.argtypes = [ctypes.c_char_p]
 _lib.sylv_selector_load.restype = _i
 _lib.sylv_status_string.argtypes = [_i]
@@ -285,6 +287,19 @@ def schur(A, stream=None):
                          _prec_of(A), ctypes.byref(st), _stream(stream))
     _check(rc, "sylv_schur")
     return T, U, st.value
+
+
+def cholqr(Q, stream=None):
+    """CholQR2 of a nearly orthogonal float64 matrix: (Q factor, R, status)
+    with positive diag(R); the input is not modified."""
+    Qo = colmajor(Q).clone()
+    Qo = Qo.t().contiguous().t()
+    n = Qo.shape[0]
+    R = torch.empty((n, n), dtype=torch.float64, device=Qo.device).t()
+    st = ctypes.c_int(0)
+    rc = _lib.sylv_cholqr(n, Qo.data_ptr(), _ld(Qo), R.data_ptr(), _ld(R), ctypes.byref(st), _stream(stream))
+    _check(rc, "sylv_cholqr")
+    return Qo, R, st.value
 
 
 def sym_eig(S, stream=None):

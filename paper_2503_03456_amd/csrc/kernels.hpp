@@ -142,6 +142,12 @@ template <typename T>
 void get_diag(hipStream_t s, int n, const T *D, int ldd, T *d);
 void asym_norm(hipStream_t s, int n, const double *A, int lda, double *out, double *scratch);
 
+// cholqr.hip: binary64 CholQR2 of a nearly orthogonal square matrix
+void chol_upper(hipStream_t s, int n, double *G, int ldg, int *fail);
+void clear_lower(hipStream_t s, int n, double *A, int lda);
+void trsm_right_upper(hipStream_t s, int m, int n, const double *R, int ldr, double *Q, int ldq);
+void cholqr2(hipStream_t s, int n, double *Q, int ldq, double *G, double *R1, int *fail);
+
 // trsyl.hip
 // mirror: symmetric Lyapunov (m = n, TB = P TA^T P, C persymmetric up to
 // rounding): one tile of each mirror pair is solved and stores the other

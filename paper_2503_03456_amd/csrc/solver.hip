@@ -768,34 +768,26 @@ static int selector_features(hipStream_t s, DevCtx *c, int m, int n, bool lyap, 
     return 0;
 }
 
-// Alg. 4.1 (Sec. 4.1): orthonormalise the low-precision Schur vectors in
-// binary64, form the triangular-basis coefficients T + L = Q^T A Q and
-// F = QA^T C QB in binary64, take Y0 from the low-precision tri-solve, run the
-// stationary iteration of Alg. 3.1 in the triangular basis with binary64
-// residuals and a binary64 tri-solve, and recover X = QA Y QB^T.
-// Orthonormalisation: Newton-Schulz steps Q <- Q - Q (Q^T Q - I) / 2 from
-// Q = fl64(U), until ||Q^T Q - I||_F <= 8 n u_64 (at most 8 steps).  Q
-// converges quadratically to the polar factor of U, and ||Q^T U - I|| =
-// O(u_low) as the analysis of Sec. 4.1 requires of its QR factor.  Binary32
-// forms (||U^T U - I|| ~ 1e-4 at n = 2048) need two steps, BF16-update forms
-// (~6e-2) four.  Returns the number of steps or a negative ABI code.
-static int orthonormalize(hipStream_t s, DevCtx *c, int n, const float *U, double *Q, double *E, double *W,
-                          double *scal, double *nscr) {
+// Alg. 4.1 (Sec. 4.1): the Q factor, with positive diag(R), of the binary64
+// copy of the low-precision Schur vectors, by CholQR2 in binary64 (G = U^T U,
+// R = chol(G), Q = U R^{-1}, twice; FP64 MFMA for the products, LDS kernels
+// for the diagonal blocks).  Then the triangular-basis coefficients
+// T + L = Q^T A Q and F = QA^T C QB in binary64, Y0 from the low-precision
+// tri-solve, the stationary iteration of Alg. 3.1 in the triangular basis
+// with binary64 residuals and a binary64 tri-solve, and X = QA Y QB^T.
+// Returns 0 or a negative ABI code; *bad = 1 when a Cholesky pivot was not
+// positive (U too far from orthogonal for the method).
+static int orthonormalize(hipStream_t s, DevCtx *c, int n, const float *U, double *Q, double *E, int *dfail,
+                          int *bad) {
     cast<float, double>(s, n, n, U, n, Q, n, 1.0f);
-    const double target = 8.0 * n * 1.1102230246251565e-16;
-    for (int it = 0; it <= 8; ++it) {
-        gemm<double, double, double, double>(s, 1, 0, n, n, n, 1.0, Q, n, Q, n, 0.0, E, n);
-        sub_identity(s, n, E, n);
-        matnorm<double>(s, n, n, E, n, scal, nscr, 0);
-        double h;
-        hipError_t e = read_scalars(s, c, scal, 1, &h);
-        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
-        if (!(h > target) || it == 8) return it;
-        cast<double, double>(s, n, n, Q, n, W, n, 1.0);
-        gemm<double, double, double, double>(s, 0, 0, n, n, n, -0.5, Q, n, E, n, 1.0, W, n);
-        cast<double, double>(s, n, n, W, n, Q, n, 1.0);
-    }
-    return 8;
+    hipError_t e = hipMemsetAsync(dfail, 0, sizeof(int), s);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    cholqr2(s, n, Q, n, E, nullptr, dfail);
+    e = hipMemcpyAsync(c->hbuf, dfail, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    std::memcpy(bad, c->hbuf, sizeof(int));
+    return 0;
 }
 
 // Alg. 4.2 needs U^{-1} in binary64: Newton-Schulz steps for the inverse,
@@ -836,10 +828,21 @@ static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
     OrthStage &q = p.o;
     if (!inv) {
         // Q_A, Q_B
-        rc = orthonormalize(s, c, m, p.lo.UA, q.QA, q.E, q.W, p.scal + 53, p.nscr);
-        if (rc < 0) return rc;
+        int bad_a = 0, bad_b = 0;
+        if ((rc = orthonormalize(s, c, m, p.lo.UA, q.QA, q.E, p.flag + 1, &bad_a)) < 0) return rc;
         if (lyap) revcols<double, double>(s, n, n, q.QA, n, q.QB, n, 1.0);  // V = U P
-        else if ((rc = orthonormalize(s, c, n, p.lo.UB, q.QB, q.E, q.W, p.scal + 53, p.nscr)) < 0) return rc;
+        else if ((rc = orthonormalize(s, c, n, p.lo.UB, q.QB, q.E, p.flag + 1, &bad_b)) < 0) return rc;
+        if (bad_a || bad_b) {
+            // the binary32 factor is not orthogonal enough for a Cholesky QR:
+            // report failure (the caller's fallback takes over)
+            if (info) {
+                std::memset(info, 0, sizeof(*info));
+                info->status = SYLV_ST_NOT_CONVERGED;
+                info->rel_res = INFINITY;
+                info->precision_used = prec_of_narrow(bf16);
+            }
+            return 0;
+        }
         // M_A = Q_A^T A Q_A, M_B = Q_B^T B Q_B (B = A^T for Lyapunov)
         gemm<double, double, double, double>(s, 0, 0, m, m, m, 1.0, A, lda, q.QA, m, 0.0, q.W, m);
         gemm<double, double, double, double>(s, 1, 0, m, m, m, 1.0, q.QA, m, q.W, m, 0.0, q.MA, m);
@@ -1303,6 +1306,47 @@ int sylv_solve_noalloc(int m, int n, const double *A, int lda, const double *B, 
     const size_t need = sylv_workspace_size(m, n, 0, &o);
     if (need > kScratchBytes) return SYLV_ERR_SCRATCH;
     return sylv_solve(m, n, A, lda, B, ldb, C, ldc, X, ldx, &o, info, ptr, kScratchBytes, stream);
+}
+
+int sylv_cholqr(int n, double *Q, int ldq, double *R, int ldr, int *status, void *stream) {
+    if (n < 0) return -1;
+    if (ldq < std::max(1, n)) return -3;
+    if (R && ldr < std::max(1, n)) return -5;
+    if (n > 0 && !Q) return -2;
+    if (status) *status = 0;
+    if (n == 0) return 0;
+    try {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DevCtx *c = nullptr;
+        int rc = device_ctx(&c);
+        if (rc) return rc;
+        void *base = nullptr;
+        const size_t nn = (size_t)n * n;
+        rc = ensure_work(c, sizeof(double) * (2 * nn + 64), &base);
+        if (rc) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        double *G = (double *)base, *R1 = G + nn;
+        int *dfail = (int *)(R1 + nn);
+        hipError_t e = hipMemsetAsync(dfail, 0, sizeof(int), s);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        cholqr2(s, n, Q, ldq, G, R ? R1 : nullptr, dfail);
+        if (R) {
+            // R = R2 R1 with the strict lower parts of both cleared first
+            clear_lower(s, n, G, n);
+            clear_lower(s, n, R1, n);
+            gemm<double, double, double, double>(s, 0, 0, n, n, n, 1.0, G, n, R1, n, 0.0, R, ldr);
+        }
+        e = hipMemcpyAsync(c->hbuf, dfail, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+        int bad = 0;
+        std::memcpy(&bad, c->hbuf, sizeof(int));
+        if (status) *status = bad ? SYLV_ST_NOT_CONVERGED : SYLV_OK;
+        e = hipGetLastError();
+        return e == hipSuccess ? 0 : SYLV_ERR_HIP - (int)e;
+    } catch (const std::bad_alloc &) {
+        return SYLV_ERR_ALLOC;
+    }
 }
 
 const char *sylv_status_string(int code) {

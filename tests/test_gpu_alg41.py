@@ -79,3 +79,34 @@ def test_alg41_small_sep(alg):
     assert info["rel_res"] <= TOL and info["fell_back"] == 0, info
     Xo, _ = oracle.bs_solve(cfg["A"], cfg["B"], cfg["C"])
     assert relerr(host(X), Xo) <= 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 300])
+def test_cholqr_is_the_qr_factor(n):
+    """sylv_cholqr (the binary64 QR step of Alg. 4.1) returns the QR factor
+    with positive diag(R) of a nearly orthogonal matrix: equal to numpy's
+    Householder QR after its signs are made positive."""
+    sy = binding()
+    rs = np.random.RandomState(40 + n)
+    U = workloads.haar_orthogonal(rs, n) + 1e-5 * rs.standard_normal((n, n))
+    Q, R, st = sy.cholqr(dev(U))
+    torch.cuda.synchronize()
+    assert st == 0
+    Qh, Rh = host(Q), host(R)
+    Qn, Rn = np.linalg.qr(U)
+    d = np.sign(np.diag(Rn))
+    Qn, Rn = Qn * d[None, :], Rn * d[:, None]
+    assert np.all(np.tril(Rh, -1) == 0) and np.all(np.diag(Rh) > 0)
+    assert np.linalg.norm(Qh - Qn) <= 20 * n * U64
+    assert np.linalg.norm(Rh - Rn) <= 20 * n * U64 * np.linalg.norm(Rn)
+    assert np.linalg.norm(Qh.T @ Qh - np.eye(n)) <= 10 * n * U64
+    assert np.linalg.norm(Qh @ Rh - U) <= 10 * n * U64 * np.linalg.norm(U)
+
+
+def test_cholqr_reports_a_breakdown():
+    sy = binding()
+    U = np.eye(70)
+    U[:, 5] = 0.0    # rank deficient: G has a zero pivot
+    _, _, st = sy.cholqr(dev(U))
+    torch.cuda.synchronize()
+    assert st == 2
