@@ -192,10 +192,56 @@ void sym_residual(hipStream_t s, int n, const double *C, int ldc, double *R, int
     hipLaunchKernelGGL(k_sym_pairs, dim3(sym_grid(n)), dim3(256), 0, s, n, C, ldc, R, ldr, 1);
 }
 
-void symmetrize(hipStream_t s, int n, double *X, int ldx) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_sym_pairs, dim3(sym_grid(n)), dim3(256), 0, s, n, (const double *)nullptr, 0, X, ldx, 0);
+// Strict lower triangle of X <- the transpose of its strict upper triangle,
+// one 32 x 32 tile pair (ti <= tj) per workgroup through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mirror_upper(int n, T *X, int ldx) {
+    __shared__ T t[32][33];
+    int ti, tj;
+    sym_pair_index(blockIdx.x, ti, tj);
+    const int r0 = 32 * ti, c0 = 32 * tj;
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int ii = e & 31, jj = e >> 5;
+        if (r0 + ii < n && c0 + jj < n) t[jj][ii] = X[(size_t)(c0 + jj) * ldx + r0 + ii];  // X(r0+ii, c0+jj)
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int ii = e & 31, jj = e >> 5;
+        // target X(c0 + ii, r0 + jj) = X(r0 + jj, c0 + ii), below the diagonal only
+        const int gi = c0 + ii, gj = r0 + jj;
+        if (gi < n && gj < n && gi > gj) X[(size_t)gj * ldx + gi] = t[ii][jj];
+    }
 }
+
+template <typename T>
+void mirror_upper(hipStream_t s, int n, T *X, int ldx) {
+    if (n <= 1) return;
+    hipLaunchKernelGGL((k_mirror_upper<T>), dim3(sym_grid(n)), dim3(256), 0, s, n, X, ldx);
+}
+template void mirror_upper<float>(hipStream_t, int, float *, int);
+template void mirror_upper<double>(hipStream_t, int, double *, int);
+
+// Out = S P with S the symmetric matrix whose upper triangle is that of In
+// and P the reversal permutation: Out(i, j) = S(i, n-1-j).
+template <typename T>
+__global__ void k_mirror_reverse(int n, const T *__restrict__ In, int ldi, T *__restrict__ Out, int ldo) {
+    const size_t total = (size_t)n * n;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        const int c = n - 1 - j;
+        Out[(size_t)j * ldo + i] = (i <= c) ? In[(size_t)c * ldi + i] : In[(size_t)i * ldi + c];
+    }
+}
+
+template <typename T>
+void mirror_reverse(hipStream_t s, int n, const T *In, int ldi, T *Out, int ldo) {
+    if (n <= 0) return;
+    const int nb = (int)std::min<size_t>(2048, ((size_t)n * n + 255) / 256);
+    hipLaunchKernelGGL((k_mirror_reverse<T>), dim3(nb), dim3(256), 0, s, n, In, ldi, Out, ldo);
+}
+template void mirror_reverse<float>(hipStream_t, int, const float *, int, float *, int);
+template void mirror_reverse<double>(hipStream_t, int, const double *, int, double *, int);
+
 
 template void matnorm<float>(hipStream_t, int, int, const float *, int, double *, double *, int);
 template void matnorm<double>(hipStream_t, int, int, const double *, int, double *, double *, int);

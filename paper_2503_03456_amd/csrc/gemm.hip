@@ -239,17 +239,30 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
             }
 }
 
+// Output tile of workgroup bid: all tiles column by column, or (upper = 1,
+// square C) only the tiles on or above the diagonal, tm <= tn, in the order
+// of sym_pair_index (the products whose result is known to be symmetric: the
+// caller mirrors the upper triangle afterwards).
+SYLV_DEVINL void tile_of(int bid, int tiles_m, int upper, int &tm, int &tn) {
+    if (upper) sym_pair_index(bid, tm, tn);
+    else {
+        tm = bid % tiles_m;
+        tn = bid / tiles_m;
+    }
+}
+
 template <int FMT, typename TA, typename TB, typename TC>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const TA *__restrict__ A,
                                                         int lda, int ta, const TB *__restrict__ B, int ldb,
                                                         int tb, TC *__restrict__ C, int ldc, double alpha,
-                                                        float beta, int tiles_m, TB bscale) {
+                                                        float beta, int tiles_m, TB bscale, int upper) {
     __shared__ __align__(16) unsigned short As[GBM][HLD];
     __shared__ __align__(16) unsigned short Bs[GBN][HLD];
     const int nblk = gridDim.x;
     int bid = blockIdx.x;
     if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
-    const int tm = bid % tiles_m, tn = bid / tiles_m;
+    int tm, tn;
+    tile_of(bid, tiles_m, upper, tm, tn);
     gemm_bf16_tile<FMT, TA, TB, TC>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, bscale, tm * GBM,
                                     tn * GBN, As, Bs);
 }
@@ -259,7 +272,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
                                                    const TA *__restrict__ A, int lda, int ta,
                                                    const TB *__restrict__ B, int ldb, int tb,
                                                    TC *__restrict__ C, int ldc, double alpha, ACC beta,
-                                                   int tiles_m, TB bscale) {
+                                                   int tiles_m, TB bscale, int upper) {
     __shared__ ACC As[GBK][GBM + GPAD];
     __shared__ ACC Bs[GBK][GBN + GPAD];
     // XCD-aware tile order: consecutive workgroup ids go to different XCDs;
@@ -267,7 +280,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
     const int nblk = gridDim.x;
     int bid = blockIdx.x;
     if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
-    const int tm = bid % tiles_m, tn = bid / tiles_m;
+    int tm, tn;
+    tile_of(bid, tiles_m, upper, tm, tn);
     gemm_tile<TA, TB, TC, ACC>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, bscale, tm * GBM,
                                tn * GBN, As, Bs);
 }
@@ -287,11 +301,15 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__rest
     __shared__ __align__(16) LT Bs[BF16IN ? GBN : GBK][C1];
     const BatchEq &q = eqs[order[blockIdx.y]];
     if (!q.active) return;
-    if ((amode & 4) && q.sym) return;  // product not needed by the symmetric specialisation
+    if ((amode & 4) && q.sym) return;    // product not needed by the symmetric specialisation
+    if ((amode & 16) && !q.sym) return;  // product of the symmetric specialisation only
     const int n = q.n;
     const int tl = (n + GBM - 1) / GBM;
     if ((int)blockIdx.x >= tl * tl) return;
     const int tm = blockIdx.x % tl, tn = blockIdx.x / tl;
+    // amode & 8: a symmetric result of a symmetric equation, only the tiles
+    // on or above the diagonal (the caller mirrors them)
+    if ((amode & 8) && q.sym && tm > tn) return;
     // amode & 3 == 1 scales op(B) by scale_e before the conversion to ACC (a
     // binary64 residual brought to unit size ahead of the binary32 cast);
     // == 2 multiplies the product by 1 / scale_e; amode & 4 skips equations
@@ -346,41 +364,43 @@ template void gemm_batched<float, float, double, float>(hipStream_t, const Batch
 
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, const TA *A, int lda,
-          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale, int in_bf16) {
+          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale, int in_bf16, int upper) {
     if (M <= 0 || N <= 0) return;
     int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
-    prof_add_work(KID_GEMM, 2.0 * M * N * K);
+    if (M != N || tm != tn) upper = 0;
+    const int ntiles = upper ? tm * (tm + 1) / 2 : tm * tn;
+    prof_add_work(KID_GEMM, upper ? 1.0 * M * (N + GBN) * K : 2.0 * M * N * K);
     ProfScope ps(KID_GEMM, s);
     if constexpr (sizeof(ACC) == sizeof(float)) {
         if (in_bf16 == NARROW_FP16) {
-            hipLaunchKernelGGL((gemm_bf16_kernel<NARROW_FP16, TA, TB, TC>), dim3(tm * tn), dim3(256), 0, s, M, N, K,
-                               A, lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale);
+            hipLaunchKernelGGL((gemm_bf16_kernel<NARROW_FP16, TA, TB, TC>), dim3(ntiles), dim3(256), 0, s, M, N, K,
+                               A, lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale, upper);
             return;
         }
         if (in_bf16) {
-            hipLaunchKernelGGL((gemm_bf16_kernel<NARROW_BF16, TA, TB, TC>), dim3(tm * tn), dim3(256), 0, s, M, N, K,
-                               A, lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale);
+            hipLaunchKernelGGL((gemm_bf16_kernel<NARROW_BF16, TA, TB, TC>), dim3(ntiles), dim3(256), 0, s, M, N, K,
+                               A, lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale, upper);
             return;
         }
     }
-    hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, ACC>), dim3(tm * tn), dim3(256), 0, s, M, N, K, A,
-                       lda, ta, B, ldb, tb, C, ldc, alpha, beta, tm, bscale);
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, ACC>), dim3(ntiles), dim3(256), 0, s, M, N, K, A,
+                       lda, ta, B, ldb, tb, C, ldc, alpha, beta, tm, bscale, upper);
 }
 
 template void gemm<double, double, double, double>(hipStream_t, int, int, int, int, int, double,
                                                    const double *, int, const double *, int,
-                                                   double, double *, int, double, int);
+                                                   double, double *, int, double, int, int);
 template void gemm<float, double, double, double>(hipStream_t, int, int, int, int, int, double,
                                                   const float *, int, const double *, int, double,
-                                                  double *, int, double, int);
+                                                  double *, int, double, int, int);
 template void gemm<float, float, float, float>(hipStream_t, int, int, int, int, int, double,
                                                const float *, int, const float *, int, float,
-                                               float *, int, float, int);
+                                               float *, int, float, int, int);
 template void gemm<float, double, float, float>(hipStream_t, int, int, int, int, int, double,
                                                 const float *, int, const double *, int, float,
-                                                float *, int, double, int);
+                                                float *, int, double, int, int);
 template void gemm<float, float, double, float>(hipStream_t, int, int, int, int, int, double,
                                                 const float *, int, const float *, int, float,
-                                                double *, int, float, int);
+                                                double *, int, float, int, int);
 
 }  // namespace sylv

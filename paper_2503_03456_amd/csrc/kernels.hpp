@@ -76,7 +76,8 @@ void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int
 // gemm.hip
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, const TA *A, int lda,
-          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale = TB(1), int in_bf16 = 0);
+          const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale = TB(1), int in_bf16 = 0,
+          int upper = 0);
 
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch, int nmax, int fa,
@@ -95,7 +96,10 @@ template <typename T>
 void matnorm(hipStream_t s, int r, int c, const T *a, int ld, double *out, double *scratch, int mode);
 void sub_identity(hipStream_t s, int n, double *G, int ldg);
 void sym_residual(hipStream_t s, int n, const double *C, int ldc, double *R, int ldr);
-void symmetrize(hipStream_t s, int n, double *X, int ldx);
+template <typename T>
+void mirror_upper(hipStream_t s, int n, T *X, int ldx);
+template <typename T>
+void mirror_reverse(hipStream_t s, int n, const T *In, int ldi, T *Out, int ldo);
 template <typename TS>
 void axpy(hipStream_t s, int r, int c, double alpha, const TS *D, int ldd, double *X, int ldx);
 

@@ -21,7 +21,9 @@
 //      for the binary32 correction.
 // Symmetric specialisation (C symmetric to rounding, so X is symmetric):
 // the iterate is kept exactly symmetric, the residual takes one product
-// (C - W - W^T with W = A X), and the tri-solve computes one tile of each
+// (C - W - W^T with W = A X), the second product of each transform forms
+// only the tiles on or above the diagonal of its symmetric result (U^T R U,
+// U Y U^T) and mirrors them, and the tri-solve computes one tile of each
 // mirror pair of the persymmetric Y' = Y P and stores the other by mirroring.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -679,18 +681,6 @@ __global__ __launch_bounds__(256) void k_bsymres(BatchEq *eqs, const int *order)
     sym_tile_pair(true, n, (const double *)q.ptr[BF_C], q.ld[BF_C], (double *)q.ptr[BF_R], n, ti, tj, sa, sb);
 }
 
-// X <- (X + X^T) / 2 for the symmetric specialisation (keeps the iterate
-// exactly symmetric, which the one-product residual relies on)
-__global__ __launch_bounds__(256) void k_bsymx(BatchEq *eqs, const int *order) {
-    __shared__ double sa[32][33], sb[32][33];
-    BatchEq &q = eqs[order[blockIdx.y]];
-    if (!q.active || !q.sym) return;
-    const int n = q.n;
-    if ((int)blockIdx.x >= sym_pair_count(n)) return;
-    int ti, tj;
-    sym_pair_index(blockIdx.x, ti, tj);
-    sym_tile_pair(false, n, nullptr, 0, (double *)q.ptr[BF_X], q.ld[BF_X], ti, tj, sa, sb);
-}
 
 __global__ __launch_bounds__(BNT) void k_bnorm(BatchEq *eqs, const int *order, double tol,
                                                int max_iter, int *nactive) {
@@ -775,6 +765,59 @@ struct BatchPlan {
     size_t smem[3];   // their dynamic LDS
 };
 
+// Symmetric equations: lower triangle of X <- its upper triangle (the
+// back-transform formed only the tiles on or above the diagonal).
+// grid.x = 32 x 32 tile pair, grid.y = equation slot.
+__global__ __launch_bounds__(256) void k_bmirror_x(BatchEq *eqs, const int *order) {
+    __shared__ double t[32][33];
+    BatchEq &q = eqs[order[blockIdx.y]];
+    if (!q.active || !q.sym) return;
+    const int n = q.n;
+    if ((int)blockIdx.x >= sym_pair_count(n)) return;
+    int ti, tj;
+    sym_pair_index(blockIdx.x, ti, tj);
+    double *X = (double *)q.ptr[BF_X];
+    const int ldx = q.ld[BF_X];
+    const int r0 = 32 * ti, c0 = 32 * tj;
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int ii = e & 31, jj = e >> 5;
+        if (r0 + ii < n && c0 + jj < n) t[jj][ii] = X[(size_t)(c0 + jj) * ldx + r0 + ii];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int ii = e & 31, jj = e >> 5;
+        const int gi = c0 + ii, gj = r0 + jj;
+        if (gi < n && gj < n && gi > gj) X[(size_t)gj * ldx + gi] = t[ii][jj];
+    }
+}
+
+// Symmetric equations: W = S P, S the symmetric matrix whose upper triangle
+// is that of the binary32 product held in the R buffer (U^T R U, upper tiles
+// only), P the reversal permutation.  One workgroup per equation.
+__global__ __launch_bounds__(BNT) void k_bsym_fwd(BatchEq *eqs, const int *order) {
+    BatchEq &q = eqs[order[blockIdx.x]];
+    if (!q.active || !q.sym) return;
+    const int n = q.n;
+    const float *S = (const float *)q.ptr[BF_R];
+    float *W = (float *)q.ptr[BF_W];
+    for (int e = threadIdx.x; e < n * n; e += BNT) {
+        const int i = e % n, j = e / n, c = n - 1 - j;
+        W[e] = (i <= c) ? S[(size_t)c * n + i] : S[(size_t)i * n + c];
+    }
+}
+
+// second product of the forward transform, W = Y V: in full for general
+// equations; for symmetric ones Y U = U^T R U is symmetric, so only its
+// tiles on or above the diagonal are formed (into the free R buffer) and W
+// is read off their mirror with the column reversal of V = U P
+static void second_forward_product(hipStream_t s, const BatchPlan &P) {
+    gemm_batched<float, float, float, float>(s, P.deq, P.dord, P.batch, P.nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 4,
+                                             0.f, P.bf16);
+    gemm_batched<float, float, float, float>(s, P.deq, P.dord, P.batch, P.nmax, BF_Y, 0, BF_U, 0, BF_R, 1.f,
+                                             8 | 16, 0.f, P.bf16);
+    hipLaunchKernelGGL(k_bsym_fwd, dim3(P.batch), dim3(BNT), 0, s, P.deq, P.dord);
+}
+
 // stages 1-4 and the first iterate
 static void enqueue_front(hipStream_t s, const BatchPlan &P) {
     const int batch = P.batch;
@@ -799,14 +842,13 @@ static void enqueue_front(hipStream_t s, const BatchPlan &P) {
     // first iterate: W = U^T (2^-e C) V, Y' solves T Y' + Y' TB = W, X = 2^e U Y' V^T
     gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 1, 0.f,
                                               P.bf16);
-    gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f,
-                                             P.bf16);
+    second_forward_product(s, P);
     trsyl_batched(s, P.deq, P.dord, batch, P.nmax);
     gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f,
                                              P.bf16);
-    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 0.f,
-                                              P.bf16);
-    hipLaunchKernelGGL(k_bsymx, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
+    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2 | 8,
+                                              0.f, P.bf16);
+    hipLaunchKernelGGL(k_bmirror_x, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
 }
 
 // binary64 residual R = C - A X - X A^T (one product for symmetric
@@ -830,14 +872,13 @@ static void enqueue_correction(hipStream_t s, const BatchPlan &P) {
     const int batch = P.batch;
     gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_R, 0, BF_Y, 1.f, 1, 0.f,
                                               P.bf16);
-    gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 0, 0.f,
-                                             P.bf16);
+    second_forward_product(s, P);
     trsyl_batched(s, P.deq, P.dord, batch, P.nmax);
     gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f,
                                              P.bf16);
-    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2, 1.f,
-                                              P.bf16);
-    hipLaunchKernelGGL(k_bsymx, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
+    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2 | 8,
+                                              1.f, P.bf16);
+    hipLaunchKernelGGL(k_bmirror_x, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
 }
 
 // ------------------------------------------------------------- hipGraph

@@ -139,6 +139,7 @@ struct Arena {
 template <typename T>
 struct Stage {  // buffers of one precision's Bartels-Stewart pipeline
     T *TA, *UA, *TB, *UB, *W1, *Y;
+    T *W2;            // Lyapunov: the symmetric second product of the forward transform
     char *schur_ws;   // Schur workspace for A
     char *schur_ws2;  // Schur workspace for B (the two run concurrently)
     int diag;         // symmetric coefficients: TA, TB diagonal (eigen-decompositions)
@@ -205,6 +206,7 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
         p.lo.UB = a.take<float>((size_t)n * n);
         p.lo.W1 = a.take<float>((size_t)m * n);
         p.lo.Y = a.take<float>((size_t)m * n);
+        if (lyap) p.lo.W2 = a.take<float>((size_t)m * n);
         p.lo.schur_ws = a.take<char>(std::max(schur_work_bytes<float>(m), sym_eig_work_bytes<float>(m)));
         if (!lyap)
             p.lo.schur_ws2 = a.take<char>(std::max(schur_work_bytes<float>(n), sym_eig_work_bytes<float>(n)));
@@ -216,6 +218,7 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
         p.hi.UB = a.take<double>((size_t)n * n);
         p.hi.W1 = a.take<double>((size_t)m * n);
         p.hi.Y = a.take<double>((size_t)m * n);
+        if (lyap) p.hi.W2 = a.take<double>((size_t)m * n);
         p.hi.schur_ws = a.take<char>(std::max(schur_work_bytes<double>(m), sym_eig_work_bytes<double>(m)));
         if (!lyap)
             p.hi.schur_ws2 = a.take<char>(std::max(schur_work_bytes<double>(n), sym_eig_work_bytes<double>(n)));
@@ -405,7 +408,15 @@ void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const doub
                        int *flag, int nf, double *yscr, double *nscr, char *hbuf) {
     gemm<float, double, float, float>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0f, st.W1, m, bscale,
                                       nf);
-    gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, nf);
+    if (st.lsym) {
+        // Lyapunov with a symmetric right-hand side: U^T R U is symmetric, so
+        // the second product forms only the tiles on or above the diagonal
+        // and Y = (U^T R U) P is read off their mirror (V = U P)
+        gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UA, n, 0.0f, st.W2, m, 1.0f, nf, 1);
+        mirror_reverse<float>(s, m, st.W2, m, st.Y, m);
+    } else {
+        gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, nf);
+    }
     if (st.diag) diag_solve<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
     else trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag, st.lsym);
     double ys = 1.0;
@@ -422,9 +433,11 @@ void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const doub
     }
     gemm<float, float, float, float>(s, 0, 0, m, n, m, 1.0, st.UA, m, st.Y, m, 0.0f, st.W1, m, (float)ys, nf);
     // the un-scaling powers of two are applied to the binary64 result
+    // symmetric iterate: U Y V^T is symmetric, only its upper tiles are
+    // formed and mirrored (X stays exactly symmetric)
     gemm<float, float, double, float>(s, 0, 1, m, n, n, 1.0 / (bscale * ys), st.W1, m, st.UB, n,
-                                      accumulate ? 1.0f : 0.0f, X, ldx, 1.0f, nf);
-    if (st.lsym) symmetrize(s, m, X, ldx);
+                                      accumulate ? 1.0f : 0.0f, X, ldx, 1.0f, nf, st.lsym ? 1 : 0);
+    if (st.lsym) mirror_upper<double>(s, m, X, ldx);
 }
 
 template <>
@@ -432,13 +445,19 @@ void correction<double>(hipStream_t s, int m, int n, Stage<double> &st, const do
                         double bscale, double *X, int ldx, bool accumulate, const double *maxab,
                         int *flag, int, double *, double *, char *) {
     gemm<double, double, double, double>(s, 1, 0, m, n, m, 1.0, st.UA, m, Rin, ldr, 0.0, st.W1, m, bscale);
-    gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0, st.Y, m);
+    if (st.lsym) {
+        // symmetric U^T R U: tiles on or above the diagonal, then Y = S P
+        gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UA, n, 0.0, st.W2, m, 1.0, 0, 1);
+        mirror_reverse<double>(s, m, st.W2, m, st.Y, m);
+    } else {
+        gemm<double, double, double, double>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0, st.Y, m);
+    }
     if (st.diag) diag_solve<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
     else trsyl<double>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag, st.lsym);
     gemm<double, double, double, double>(s, 0, 0, m, n, m, 1.0, st.UA, m, st.Y, m, 0.0, st.W1, m);
     gemm<double, double, double, double>(s, 0, 1, m, n, n, 1.0 / bscale, st.W1, m, st.UB, n,
-                                         accumulate ? 1.0 : 0.0, X, ldx);
-    if (st.lsym) symmetrize(s, m, X, ldx);
+                                         accumulate ? 1.0 : 0.0, X, ldx, 1.0, 0, st.lsym ? 1 : 0);
+    if (st.lsym) mirror_upper<double>(s, m, X, ldx);
 }
 
 // R = C - A X - X op(B); scal[slot] = ||R||_F, scal[slot+1] = max|R|, scal[slot+2] = ||X||_F.
