@@ -243,6 +243,27 @@ int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, i
  * vals[7] (host). */
 int sylv_schur_tune_get(int prec, int *vals);
 
+/* Tunables of the batched Lyapunov path (process-wide, next call on; the
+ * defaults are the values the project's autotuner measured best on MI355X
+ * for the 4096-equation batch of orders 16..256):
+ *   hess_hi, hess_lo  Hessenberg kernel buckets: orders > hess_hi use the
+ *                     1024-thread register kernel (capacity 256), orders in
+ *                     (hess_lo, hess_hi] the 256-thread one of capacity 128,
+ *                     the rest the 256-thread one of capacity 64
+ *                     (1 <= hess_lo <= 64, hess_lo <= hess_hi <= 128);
+ *   band1 > band2 > band3  band-QR LDS buckets below the top one (orders
+ *                     256..band1+1, band1..band2+1, ...); each bucket's
+ *                     launch reserves the band of its largest order, so
+ *                     smaller buckets fit more workgroups per CU; 0 ends
+ *                     the list (band1 < 256);
+ *   graph_passes      refinement passes per captured graph (1..8).
+ * Returns 0, or -1/-2/-3/-4 for an invalid hess_hi / hess_lo / band list /
+ * graph_passes. */
+int sylv_batched_tune(int hess_hi, int hess_lo, int band1, int band2, int band3, int graph_passes);
+/* Current batched tunables (hess_hi, hess_lo, band1, band2, band3,
+ * graph_passes) into vals[6] (host). */
+int sylv_batched_tune_get(int *vals);
+
 /* Text for a return value or a status code. */
 const char *sylv_status_string(int code);
 

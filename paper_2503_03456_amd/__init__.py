@@ -91,6 +91,10 @@ _lib.sylv_init.restype = _i
 _lib.sylv_solve_noalloc.argtypes = [_i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, ctypes.POINTER(Opts),
                                     ctypes.POINTER(Info), _vp]
 _lib.sylv_solve_noalloc.restype = _i
+_lib.sylv_batched_tune.argtypes = [_i, _i, _i, _i, _i, _i]
+_lib.sylv_batched_tune.restype = _i
+_lib.sylv_batched_tune_get.argtypes = [_ip]
+_lib.sylv_batched_tune_get.restype = _i
 _lib.sylv_cholqr.argtypes = [_i, _vp, _i, _vp, _i, _ip, _vp]
 _lib.sylv_cholqr.restype = _i
 _lib.sylv_selector_load.argtypes = [ctypes.c_char_p]

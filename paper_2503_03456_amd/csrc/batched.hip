@@ -166,3 +166,14 @@ static int solve_batched_impl(int batch, const int *kind, const int *m, const in
     }
     return 0;
 }
+
+extern "C" int sylv_batched_tune(int hess_hi, int hess_lo, int band1, int band2, int band3, int graph_passes) {
+    const int band[3] = {band1, band2, band3};
+    return batch_tune_set(hess_hi, hess_lo, band, graph_passes);
+}
+
+extern "C" int sylv_batched_tune_get(int *vals) {
+    if (!vals) return -1;
+    batch_tune_get(vals);
+    return 0;
+}

@@ -69,6 +69,8 @@ int device_work(size_t bytes, void **work, char **hbuf);
 
 // lyap_batch.hip: all equations Lyapunov of order 1..256
 size_t lyap_batched_bytes(int batch, const int *n);
+int batch_tune_set(int hess_hi, int hess_lo, const int *band, int gpasses);
+void batch_tune_get(int *vals);
 
 // trsyl.hip: batched tri-solve T Y + Y TB = W over every active equation
 void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int nmax);

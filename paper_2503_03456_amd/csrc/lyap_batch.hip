@@ -35,6 +35,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -761,9 +762,31 @@ struct BatchPlan {
     double tol;
     int h1, h2;       // Hessenberg buckets [0,h1) [h1,h2) [h2,batch)
     int orth;         // orthogonality probe of the binary32 Schur vectors
-    int sb[4];        // band-QR buckets [sb[i], sb[i+1])
-    size_t smem[3];   // their dynamic LDS
+    int nsb;          // band-QR buckets [sb[i], sb[i+1]), i < nsb
+    int sb[5];
+    size_t smem[4];   // their dynamic LDS
 };
+
+// Tunables of the batched path (process-wide; the defaults are what the
+// project's autotuner measured best on MI355X for the 4096-equation
+// Lyapunov batch): Hessenberg kernel buckets (orders > hess_hi take the
+// 32 x 32-thread register kernel, orders in (hess_lo, hess_hi] the 16 x 16 one
+// with 8 x 8 entries per thread, the rest 4 x 4), the band-QR LDS buckets
+// (each bucket's launch reserves the band of its largest order: orders above
+// band[0], then (band[1], band[0]], ...; a zero ends the list) and the passes
+// per captured refinement graph.
+struct BatchTune {
+    int hess_hi = 128, hess_lo = 64;
+    int band[3] = {180, 128, 0};
+    int gpasses = 3;
+};
+static std::mutex g_btune_mu;
+static BatchTune g_btune;
+
+static BatchTune batch_tune() {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    return g_btune;
+}
 
 // Symmetric equations: lower triangle of X <- its upper triangle (the
 // back-transform formed only the tiles on or above the diagonal).
@@ -832,7 +855,7 @@ static void enqueue_front(hipStream_t s, const BatchPlan &P) {
     }
     {
         ProfScope ps(KID_BSCHUR, s);
-        for (int bi = 0; bi < 3; ++bi)
+        for (int bi = 0; bi < P.nsb; ++bi)
             if (P.sb[bi + 1] > P.sb[bi])
                 hipLaunchKernelGGL(k_bschur, dim3(P.sb[bi + 1] - P.sb[bi]), dim3(BSNT), P.smem[bi], s, P.deq,
                                    P.dord + P.sb[bi]);
@@ -882,21 +905,28 @@ static void enqueue_correction(hipStream_t s, const BatchPlan &P) {
 }
 
 // ------------------------------------------------------------- hipGraph
-// The launch sequence of a batch shape (stages, first iterate, the first
-// refinement passes) is captured once on an internal stream and replayed;
-// equations are gated on the device (inactive ones return at once), so the
-// graph needs no host decisions.  A graph is keyed by the workspace, the
-// sorted orders and the options it was captured with.  SYLV_BATCH_GRAPH=0
-// in the environment selects eager launches.
+// The launch sequence of a batch shape is captured once on an internal
+// stream and replayed, as two graphs: the front graph (stages, first
+// iterate, then `passes` refinement passes, each a residual with the
+// per-equation decision followed by a correction) and the tail graph
+// (`passes` more passes).  Equations are gated on the device (inactive ones
+// return at once), so the graphs need no host decisions; the host reads one
+// counter after each graph -- the number of equations the last pass sent to
+// another correction -- and replays the tail graph while it is nonzero.  The
+// per-equation cap of max_iter corrections ends every equation, so the
+// whole refinement runs from graphs.  A graph pair is keyed by the
+// workspace, the sorted orders and the options it was captured with.
+// SYLV_BATCH_GRAPH=0 in the environment selects eager launches.
 struct BatchGraph {
     hipStream_t gs = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     BatchEq *deq = nullptr;
     int passes = 0, bf16 = 0, max_iter = 0, orth = 0;
     double tol = 0.0;
     std::vector<int> sizes;
+    int tune[6] = {0, 0, 0, 0, 0, 0};  // batched tunables the graphs were captured with
 };
 static BatchGraph g_bgraph[64];
 
@@ -905,8 +935,28 @@ static bool batch_graph_enabled() {
     return !(v && v[0] == '0');
 }
 
+// Capture of graph `which` (0 front, 1 tail) on g.gs.
+static hipError_t batch_graph_capture(BatchGraph &g, const BatchPlan &P, int passes, int which) {
+    hipError_t e;
+    if ((e = hipStreamBeginCapture(g.gs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    if (which == 0) enqueue_front(g.gs, P);
+    for (int k = 0; k < passes; ++k) {
+        enqueue_pass(g.gs, P, true);
+        enqueue_correction(g.gs, P);
+    }
+    if ((e = hipStreamEndCapture(g.gs, &g.graph[which])) != hipSuccess) return e;
+    if ((e = hipGraphInstantiate(&g.exec[which], g.graph[which], nullptr, nullptr, 0)) != hipSuccess) {
+        hipGraphDestroy(g.graph[which]);
+        g.graph[which] = nullptr;
+        g.exec[which] = nullptr;
+    }
+    return e;
+}
+
+// Replays graph `which` (0 front, 1 tail) for this batch on stream s and
+// reads the pending-correction counter into *hcnt.
 static int batch_graph_run(hipStream_t s, const BatchPlan &P, const std::vector<int> &order, const int *nn,
-                           int passes, int *dcnt, int *hcnt) {
+                           int passes, int which, int *dcnt, int *hcnt) {
     int dev = 0;
     hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess || dev < 0 || dev >= 64) return SYLV_ERR_NOGPU;
@@ -918,28 +968,19 @@ static int batch_graph_run(hipStream_t s, const BatchPlan &P, const std::vector<
     }
     std::vector<int> sizes(P.batch);
     for (int i = 0; i < P.batch; ++i) sizes[i] = nn[order[i]];
-    const bool hit = g.exec && g.deq == P.deq && g.passes == passes && g.bf16 == P.bf16 &&
-                     g.max_iter == P.max_iter && g.tol == P.tol && g.orth == P.orth && g.sizes == sizes;
-    if (!hit) {
-        if (g.exec) {
-            hipGraphExecDestroy(g.exec);
-            hipGraphDestroy(g.graph);
-            g.exec = nullptr;
-            g.graph = nullptr;
-        }
-        if ((e = hipStreamBeginCapture(g.gs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return SYLV_ERR_HIP - (int)e;
-        enqueue_front(g.gs, P);
-        for (int k = 0; k < passes; ++k) {
-            enqueue_pass(g.gs, P, true);
-            enqueue_correction(g.gs, P);
-        }
-        if ((e = hipStreamEndCapture(g.gs, &g.graph)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
-        if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) {
-            hipGraphDestroy(g.graph);
-            g.graph = nullptr;
-            return SYLV_ERR_HIP - (int)e;
-        }
+    int tv[6];
+    batch_tune_get(tv);
+    const bool same = g.deq == P.deq && g.passes == passes && g.bf16 == P.bf16 && g.max_iter == P.max_iter &&
+                      g.tol == P.tol && g.orth == P.orth && g.sizes == sizes &&
+                      std::equal(tv, tv + 6, g.tune);
+    if (!same) {
+        for (int k = 0; k < 2; ++k)
+            if (g.exec[k]) {
+                hipGraphExecDestroy(g.exec[k]);
+                hipGraphDestroy(g.graph[k]);
+                g.exec[k] = nullptr;
+                g.graph[k] = nullptr;
+            }
         g.deq = P.deq;
         g.passes = passes;
         g.bf16 = P.bf16;
@@ -947,10 +988,12 @@ static int batch_graph_run(hipStream_t s, const BatchPlan &P, const std::vector<
         g.tol = P.tol;
         g.orth = P.orth;
         g.sizes = std::move(sizes);
+        std::copy(tv, tv + 6, g.tune);
     }
+    if (!g.exec[which] && (e = batch_graph_capture(g, P, passes, which)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
     if ((e = hipEventRecord(g.e0, s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
     if ((e = hipStreamWaitEvent(g.gs, g.e0, 0)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
-    if ((e = hipGraphLaunch(g.exec, g.gs)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    if ((e = hipGraphLaunch(g.exec[which], g.gs)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
     if ((e = hipEventRecord(g.e1, g.gs)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
     if ((e = hipStreamWaitEvent(s, g.e1, 0)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
     if ((e = hipMemcpyAsync(hcnt, dcnt, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -1027,47 +1070,55 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
     P.bf16 = (o.low == SYLV_PREC_BF16) ? 1 : (o.low == SYLV_PREC_FP16) ? 2 : 0;
     P.tol = o.tol; P.max_iter = o.max_iter;
     P.orth = o.orth_check != 0 ? 1 : 0;
-    // Hessenberg size buckets (order is longest first): n > 128, 64 < n <= 128, n <= 64
+    const BatchTune tu = batch_tune();
+    // Hessenberg size buckets (order is longest first): n > hess_hi,
+    // hess_lo < n <= hess_hi, n <= hess_lo
     P.h1 = 0;
-    while (P.h1 < batch && nn[order[P.h1]] > 128) ++P.h1;
+    while (P.h1 < batch && nn[order[P.h1]] > tu.hess_hi) ++P.h1;
     P.h2 = P.h1;
-    while (P.h2 < batch && nn[order[P.h2]] > 64) ++P.h2;
-    // band-QR LDS buckets: orders > 180, 128 < n <= 180 (two workgroups per CU), <= 128 (three)
-    const int caps[3] = {256, 180, 128};
+    while (P.h2 < batch && nn[order[P.h2]] > tu.hess_lo) ++P.h2;
+    // band-QR LDS buckets: orders above band[0], (band[1], band[0]], ...
+    int caps[4] = {256, 0, 0, 0}, ncap = 1;
+    for (int k = 0; k < 3 && tu.band[k] > 0; ++k) caps[ncap++] = tu.band[k];
     int b0 = 0;
-    for (int bi = 0; bi < 3; ++bi) {
-        const int lo = (bi + 1 < 3) ? caps[bi + 1] : 0;
+    for (int bi = 0; bi < ncap; ++bi) {
+        const int lo = (bi + 1 < ncap) ? caps[bi + 1] : 0;
         int b1 = b0;
         while (b1 < batch && nn[order[b1]] > lo) ++b1;
         P.sb[bi] = b0;
         P.smem[bi] = (b1 > b0) ? sizeof(float) * (size_t)band_size(std::min(caps[bi], nn[order[b0]])) : 0;
         b0 = b1;
     }
-    P.sb[3] = batch;
+    P.nsb = ncap;
+    P.sb[ncap] = batch;
     double w = 0.0;
     for (int i = 0; i < batch; ++i) w += (14.0 / 3.0) * double(nn[i]) * nn[i] * nn[i];
     prof_add_work(KID_BHESS, w);
 
     int *hcnt = reinterpret_cast<int *>(hbuf);
-    int rc = 0, pass0 = 0;
-    const int gpasses = std::min(o.max_iter + 1, 3);
+    int rc = 0;
     if (batch_graph_enabled() && !prof_any_armed()) {
-        // the stages and the first refinement passes as one graph (captured
-        // once per batch shape and workspace, replayed afterwards)
-        rc = batch_graph_run(s, P, order, nn, gpasses, dcnt, hcnt);
+        // front graph, then tail graphs while equations remain (every pass
+        // replayed from a captured graph)
+        const int gpasses = tu.gpasses;
+        rc = batch_graph_run(s, P, order, nn, gpasses, 0, dcnt, hcnt);
         if (rc) return rc;
-        pass0 = gpasses;
-        if (*hcnt == 0) pass0 = o.max_iter + 1;  // nothing left to refine
+        const int max_chunks = (o.max_iter + 1 + gpasses - 1) / gpasses + 1;
+        for (int chunk = 1; *hcnt > 0 && chunk <= max_chunks; ++chunk) {
+            rc = batch_graph_run(s, P, order, nn, gpasses, 1, dcnt, hcnt);
+            if (rc) return rc;
+        }
     } else {
+        // eager launches (profiling armed, or graphs switched off)
         enqueue_front(s, P);
-    }
-    for (int pass = pass0; pass <= o.max_iter; ++pass) {
-        enqueue_pass(s, P, false);
-        if ((e = hipMemcpyAsync(hcnt, dcnt, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
-            return SYLV_ERR_HIP - (int)e;
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
-        if (*hcnt == 0) break;
-        enqueue_correction(s, P);
+        for (int pass = 0; pass <= o.max_iter; ++pass) {
+            enqueue_pass(s, P, false);
+            if ((e = hipMemcpyAsync(hcnt, dcnt, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return SYLV_ERR_HIP - (int)e;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return SYLV_ERR_HIP - (int)e;
+            if (*hcnt == 0) break;
+            enqueue_correction(s, P);
+        }
     }
     if ((e = hipMemcpyAsync(hq.data(), deq, sizeof(BatchEq) * batch, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return SYLV_ERR_HIP - (int)e;
@@ -1110,6 +1161,35 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
         }
     }
     return 0;
+}
+
+int batch_tune_set(int hess_hi, int hess_lo, const int *band, int gpasses) {
+    if (hess_hi < 1 || hess_hi > 128) return -1;
+    if (hess_lo < 1 || hess_lo > 64 || hess_lo > hess_hi) return -2;
+    int prev = 256;
+    bool ended = false;
+    for (int k = 0; k < 3; ++k) {
+        if (band[k] < 0 || (band[k] > 0 && (ended || band[k] >= prev))) return -3;
+        if (band[k] == 0) ended = true;
+        else prev = band[k];
+    }
+    if (gpasses < 1 || gpasses > 8) return -4;
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    g_btune.hess_hi = hess_hi;
+    g_btune.hess_lo = hess_lo;
+    for (int k = 0; k < 3; ++k) g_btune.band[k] = band[k];
+    g_btune.gpasses = gpasses;
+    return 0;
+}
+
+void batch_tune_get(int *vals) {
+    const BatchTune t = batch_tune();
+    vals[0] = t.hess_hi;
+    vals[1] = t.hess_lo;
+    vals[2] = t.band[0];
+    vals[3] = t.band[1];
+    vals[4] = t.band[2];
+    vals[5] = t.gpasses;
 }
 
 size_t lyap_batched_bytes(int batch, const int *nn) {

@@ -98,3 +98,19 @@ def test_status_strings_of_library_codes(lib):
     assert b"captured" in lib.sylv_status_string(-2003)
     assert b"scratch" in lib.sylv_status_string(-2000)
     assert b"sylv_init" in lib.sylv_status_string(-2001)
+
+
+def test_batched_tune_validation(lib):
+    """sylv_batched_tune checks its arguments on the host (no GPU needed)
+    and keeps the defaults on rejection."""
+    v = (ctypes.c_int * 6)()
+    assert lib.sylv_batched_tune_get(v) == 0
+    before = list(v)
+    assert lib.sylv_batched_tune(129, 64, 180, 128, 0, 3) == -1   # beyond the 128-capacity kernel
+    assert lib.sylv_batched_tune(128, 65, 180, 128, 0, 3) == -2   # beyond the 64-capacity kernel
+    assert lib.sylv_batched_tune(128, 64, 128, 180, 0, 3) == -3   # bands not descending
+    assert lib.sylv_batched_tune(128, 64, 180, 0, 128, 3) == -3   # entry after the terminating 0
+    assert lib.sylv_batched_tune(128, 64, 256, 0, 0, 3) == -3     # must be below the top bucket
+    assert lib.sylv_batched_tune(128, 64, 180, 128, 0, 0) == -4
+    assert lib.sylv_batched_tune_get(v) == 0 and list(v) == before
+    assert lib.sylv_batched_tune(*before) == 0

@@ -221,3 +221,28 @@ def test_batch_symmetric_specialisation_mixed_with_general():
         check_item(A, C, eig, Xh, info, symmetric=sym)
         if sym:
             assert np.array_equal(Xh, Xh.T)
+
+
+def test_refinement_beyond_the_front_graph_matches_eager_launches(monkeypatch):
+    """Equations that need more corrections than the front graph holds (sep
+    moved to 2e-3 by a shift, kappa ~ 1e4) run their remaining passes from
+    the tail graph; the result equals the eager launch sequence bit for bit
+    and meets the oracle."""
+    sy = binding()
+    its = []
+    for i, n in enumerate([150, 64, 23]):
+        A, C, eig = workloads.config4_item(2300 + i, n)
+        shift = -eig.real.max() - 1e-3          # largest real part -> -1e-3
+        its.append((A + shift * np.eye(n), C, eig + shift))
+    eqs = [(dev(A), dev(C)) for A, C, _ in its]
+    Xg, ig = sy.solve_batched(eqs)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("SYLV_BATCH_GRAPH", "0")
+    Xe, ie = sy.solve_batched(eqs)
+    torch.cuda.synchronize()
+    for (A, C, eig), xg, xe, a, b in zip(its, Xg, Xe, ig, ie):
+        say("tail graph", A.shape[0], a["iterations"], a["rel_res"])
+        assert a["iterations"] >= 3, a
+        assert a == b
+        assert np.array_equal(host(xg), host(xe))
+        check_item(A, C, eig, host(xg), a)
