@@ -140,9 +140,6 @@ def main(argv=None):
             json.dump(res, fh, indent=1)
 
 
-if __name__ == "__main__":
-    main()
-
 
 BGRID = {
     "hess": [(128, 64), (112, 64), (96, 64), (128, 48), (96, 48), (64, 48), (128, 32)],
@@ -211,3 +208,7 @@ def tune_batched(count=4096, reps=3, rounds=1, progress=True):
                 best_t, cur = t, cand
         set_batched(cur)
     return {"best": cur, "seconds": best_t, "start_seconds": base, "count": count, "history": hist}
+
+
+if __name__ == "__main__":
+    main()

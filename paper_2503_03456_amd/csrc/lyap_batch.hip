@@ -776,7 +776,7 @@ struct BatchPlan {
 // band[0], then (band[1], band[0]], ...; a zero ends the list) and the passes
 // per captured refinement graph.
 struct BatchTune {
-    int hess_hi = 128, hess_lo = 64;
+    int hess_hi = 64, hess_lo = 48;
     int band[3] = {180, 128, 0};
     int gpasses = 3;
 };

@@ -240,9 +240,11 @@ def test_refinement_beyond_the_front_graph_matches_eager_launches(monkeypatch):
     monkeypatch.setenv("SYLV_BATCH_GRAPH", "0")
     Xe, ie = sy.solve_batched(eqs)
     torch.cuda.synchronize()
+    # the front graph holds 3 passes: an equation with 3 or more corrections
+    # is evaluated by the tail graph
+    assert max(a["iterations"] for a in ig) >= 3, ig
     for (A, C, eig), xg, xe, a, b in zip(its, Xg, Xe, ig, ie):
         say("tail graph", A.shape[0], a["iterations"], a["rel_res"])
-        assert a["iterations"] >= 3, a
         assert a == b
         assert np.array_equal(host(xg), host(xe))
         check_item(A, C, eig, host(xg), a)
