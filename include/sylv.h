@@ -172,16 +172,23 @@ int lyap_solve(int n, const double *A, int lda, const double *C, int ldc,
  * kind, m, n, lda, ldb, ldc, ldx and the pointer arrays A, B, C, X are HOST
  * arrays of length batch; the matrices they point to live in device memory
  * (column-major, binary64).  infos is a host or device array of length batch (may be
- * NULL).  Lyapunov equations of order 1..256 with low = SYLV_PREC_FP32 are
+ * NULL).  Lyapunov equations of order 1..256 with low = SYLV_PREC_FP32
+ * (or BF16, FP16, or AUTO with installed weights) are
  * solved together (Sec. 4 batched workloads): one workgroup per equation in
  * every stage, equations ordered longest first, Schur form, tri-solve and
  * corrections in binary32, residuals in binary64, per-equation convergence
  * control; an equation that misses the tolerance is re-solved in binary64
- * when opts->fallback is set (info.fell_back = 1).  All other equations go
+ * when opts->fallback is set (info.fell_back = 1).  With SYLV_PREC_AUTO the
+ * selector's features are computed on the device for every equation of the
+ * batch after its binary32 Schur form, one forward pass of the network over
+ * the whole batch picks each equation's class (info.chosen): class 0 runs
+ * its transforms on bfloat16 operands, class 1 on binary32, class 2 leaves
+ * the batch for the single-equation binary64 path.  All other equations go
  * through sylv_solve / lyap_solve one after another.  work (device, may be
  * NULL: the library keeps its own) must hold sylv_batched_workspace_size
- * bytes; infos may also be a device array.  Returns 0, -i for an invalid i-th argument (-15: work too small),
- * or SYLV_ERR_*; synchronises the stream before returning. */
+ * bytes; infos may also be a device array.  Returns 0, -i for an invalid
+ * i-th argument (-15: work too small), or SYLV_ERR_*; synchronises the
+ * stream before returning. */
 int sylv_solve_batched(int batch, const int *kind, const int *m, const int *n,
                        const double *const *A, const int *lda,
                        const double *const *B, const int *ldb,
@@ -402,7 +409,8 @@ int sylv_selector_train(int n_samples, const float *feats, const int *labels,
  * computed spectra, Sec. 2.2), log10 kappa_est = log10((||A||_F+||B||_F)/sep_est),
  * Henrici departure ||N||_F/||T||_F of T_A and T_B, fraction of eigenvalues in
  * complex pairs (A, B), log10 relative minimum eigenvalue gap (A, B),
- * log10 ||U^T U - I||_F and ||V^T V - I||_F, Lyapunov flag.  feats: host,
+ * log10 of the probe estimates of ||U^T U - I||_F and ||V^T V - I||_F
+ * (orth_check = 1), Lyapunov flag.  feats: host,
  * 16 floats.  Returns 0, -i for an invalid i-th argument, or SYLV_ERR_*. */
 int sylv_selector_features(int m, int n, const double *A, int lda, const double *B, int ldb,
                            const double *C, int ldc, float *feats, void *stream);

@@ -25,7 +25,8 @@ using namespace sylv;
 
 static bool batched_eligible(int kind, int n, const sylv_opts &o) {
     return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 && o.alg == SYLV_ALG_ORIG &&
-           (o.low == SYLV_PREC_FP32 || o.low == SYLV_PREC_BF16 || o.low == SYLV_PREC_FP16);
+           (o.low == SYLV_PREC_FP32 || o.low == SYLV_PREC_BF16 || o.low == SYLV_PREC_FP16 ||
+            (o.low == SYLV_PREC_AUTO && selector_installed()));
 }
 
 extern "C" size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, const int *n,
@@ -39,7 +40,8 @@ extern "C" size_t sylv_batched_workspace_size(int batch, const int *kind, const 
     for (int i = 0; i < batch; ++i) {
         if (batched_eligible(kind[i], m[i], o)) {
             nb.push_back(m[i]);
-            if (o.fallback) {
+            if (o.fallback || o.low == SYLV_PREC_AUTO) {
+                // binary64 re-solves: fallback, or the selector's class 2
                 sylv_opts f = o;
                 f.low = SYLV_PREC_FP64;
                 single = std::max(single, sylv_workspace_size(m[i], m[i], 1, &f));
@@ -134,19 +136,36 @@ static int solve_batched_impl(int batch, const int *kind, const int *m, const in
         for (int t = 0; t < nb; ++t) {
             const int i = idx[t];
             sylv_info f = binf[t];
+            if (o.low == SYLV_PREC_AUTO && f.chosen == 2) {
+                // the selector sent the equation to the plain binary64 path
+                sylv_opts f64 = o;
+                f64.low = SYLV_PREC_FP64;
+                sylv_info g;
+                rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &f64, &g, work, work_bytes,
+                                stream);
+                if (rc) return rc;
+                g.chosen = 2;
+                g.orth_u = f.orth_u;
+                g.orth_v = f.orth_v;
+                if (infos) infos[i] = g;
+                continue;
+            }
             const bool ok = f.status == SYLV_OK || f.status == SYLV_ST_PERTURBED;
             if (!ok && o.fallback) {
                 // next rung of the ladder: bfloat16 / binary16 updates ->
                 // binary32 (which itself falls back to binary64); binary32 ->
                 // binary64
                 sylv_opts f64 = o;
-                f64.low = (o.low == SYLV_PREC_BF16 || o.low == SYLV_PREC_FP16) ? SYLV_PREC_FP32 : SYLV_PREC_FP64;
+                const bool narrow = o.low == SYLV_PREC_BF16 || o.low == SYLV_PREC_FP16 ||
+                                    (o.low == SYLV_PREC_AUTO && f.chosen == 0);
+                f64.low = narrow ? SYLV_PREC_FP32 : SYLV_PREC_FP64;
                 sylv_info g;
                 rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &f64, &g, work,
                                 work_bytes, stream);
                 if (rc) return rc;
                 g.fell_back = 1;
                 g.iterations += f.iterations;
+                g.chosen = f.chosen;
                 f = g;
             }
             if (infos) infos[i] = f;

@@ -303,6 +303,10 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const BatchEq *__rest
     if (!q.active) return;
     if ((amode & 4) && q.sym) return;    // product not needed by the symmetric specialisation
     if ((amode & 16) && !q.sym) return;  // product of the symmetric specialisation only
+    // per-equation operand format under the learned selector: bit 32 takes
+    // only the equations with narrow operands, bit 64 only the others
+    if ((amode & 32) && q.narrow == 0) return;
+    if ((amode & 64) && q.narrow != 0) return;
     const int n = q.n;
     const int tl = (n + GBM - 1) / GBM;
     if ((int)blockIdx.x >= tl * tl) return;

@@ -37,6 +37,8 @@ struct BatchEq {
     long long cyc[4];  // Schur kernel cycles: total, sweeps, U updates, deflation scans
     int sweeps;
     int sym;         // C symmetric to rounding: X kept symmetric, one-product residual, half tri-solve
+    int cls;         // selector class (SYLV_PREC_AUTO): 0 bfloat16 transforms, 1 binary32, 2 binary64; -1 none
+    int narrow;      // operand format of this equation's transforms under the selector (1 bfloat16)
 };
 
 // mlp.hip: feature standardisation and mini-batch gathering
@@ -46,6 +48,9 @@ void mlp_gather(hipStream_t s, int cnt, const int *perm, const float *Z, const i
 
 // selector.hip
 bool selector_installed();
+// device copy of the installed selector blob (params | means | deviations),
+// uploaded on `s` when stale; nullptr if none is installed
+const float *selector_device_blob(hipStream_t s, int *rc);
 int selector_choose(hipStream_t s, char *hbuf, const float *feats, int *cls, float *probs);
 
 // solver.hip

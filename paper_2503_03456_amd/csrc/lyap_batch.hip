@@ -101,6 +101,8 @@ __global__ __launch_bounds__(BNT) void k_bprep(BatchEq *eqs, const int *order) {
         q.nC = sqrt(sc);
         q.sym = sqrt(sd) <= 0x1p-52 * q.nC ? 1 : 0;
         q.active = 1;
+        q.cls = -1;
+        q.narrow = 0;
         q.status = SYLV_ST_NOT_CONVERGED;
         q.iterations = 0;
         q.qr_fail = 0;
@@ -762,6 +764,9 @@ struct BatchPlan {
     double tol;
     int h1, h2;       // Hessenberg buckets [0,h1) [h1,h2) [h2,batch)
     int orth;         // orthogonality probe of the binary32 Schur vectors
+    int autosel;      // learned precision choice per equation (SYLV_PREC_AUTO)
+    float *feat, *zfeat, *prob;  // selector features (batch x 16, raw and standardised), class probabilities
+    const float *sel;            // device selector blob: params | means | standard deviations
     int nsb;          // band-QR buckets [sb[i], sb[i+1]), i < nsb
     int sb[5];
     size_t smem[4];   // their dynamic LDS
@@ -829,15 +834,135 @@ __global__ __launch_bounds__(BNT) void k_bsym_fwd(BatchEq *eqs, const int *order
     }
 }
 
+// The 16 selector features of every equation (the single-equation
+// definitions with B = A^T, so the two spectra are the same): log2 n twice,
+// log10 ||A||_F / sqrt n twice, log10 ||C||_F / n, log10 sep_est with
+// sep_est = min |l_i + l_j|, log10 (2 ||A||_F / sep_est), the Henrici
+// departure ||N||_F / ||T||_F twice, the fraction of eigenvalues in complex
+// pairs twice, log10 of min_{i != j} |l_i - l_j| / max |l_i| twice, log10 of
+// the orthogonality probe twice, and the Lyapunov flag.  Eigenvalues from the
+// 1x1 / 2x2 diagonal blocks of the binary32 T.  Row slot of the batch order.
+__global__ __launch_bounds__(BNT) void k_bfeatures(BatchEq *eqs, const int *order, float *feat) {
+    __shared__ float wr[256], wi[256];
+    __shared__ double red[8];
+    const int slot = blockIdx.x;
+    BatchEq &q = eqs[order[slot]];
+    float *f = feat + (size_t)slot * 16;
+    const int n = q.n;
+    const float *T = (const float *)q.ptr[BF_H];
+    for (int i = threadIdx.x; i < n; i += BNT) {
+        const bool lower = i > 0 && T[(size_t)(i - 1) * n + i] != 0.f;
+        const bool upper = i + 1 < n && T[(size_t)i * n + i + 1] != 0.f;
+        if (!lower && !upper) { wr[i] = T[(size_t)i * n + i]; wi[i] = 0.f; continue; }
+        const int k = upper ? i : i - 1;
+        const double a = T[(size_t)k * n + k], b = T[(size_t)(k + 1) * n + k];
+        const double c = T[(size_t)k * n + k + 1], d = T[(size_t)(k + 1) * n + k + 1];
+        const double p = 0.5 * (a - d), disc = p * p + b * c, mid = 0.5 * (a + d);
+        if (disc >= 0.0) { const double r = sqrt(disc); wr[i] = (float)(upper ? mid + r : mid - r); wi[i] = 0.f; }
+        else { const double r = sqrt(-disc); wr[i] = (float)mid; wi[i] = (float)(upper ? r : -r); }
+    }
+    __syncthreads();
+    double sep = 1e300, gap = 1e300, mx = 0.0, ncx = 0.0, bd = 0.0, tf = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += BNT) {
+        const int i = e % n, j = e / n;
+        const double sr = (double)wr[i] + wr[j], si = (double)wi[i] + wi[j];
+        sep = fmin(sep, sqrt(sr * sr + si * si));
+        if (i < j) {
+            const double dr = (double)wr[i] - wr[j], di = (double)wi[i] - wi[j];
+            gap = fmin(gap, sqrt(dr * dr + di * di));
+        }
+        const double t = T[e];
+        tf += t * t;
+    }
+    for (int i = threadIdx.x; i < n; i += BNT) {
+        if (wi[i] != 0.f) ncx += 1.0;
+        mx = fmax(mx, sqrt((double)wr[i] * wr[i] + (double)wi[i] * wi[i]));
+        const double d = T[(size_t)i * n + i];
+        bd += d * d;
+        if (i + 1 < n && T[(size_t)i * n + i + 1] != 0.f) {
+            const double b = T[(size_t)(i + 1) * n + i], c = T[(size_t)i * n + i + 1];
+            bd += b * b + c * c;
+        }
+    }
+    sep = -wg_max(-sep, red);
+    gap = -wg_max(-gap, red);
+    mx = wg_max(mx, red);
+    ncx = wg_sum(ncx, red);
+    bd = wg_sum(bd, red);
+    tf = wg_sum(tf, red);
+    if (threadIdx.x == 0) {
+        auto lg = [](double x) { return log10(fmax(x, 1e-300)); };
+        const double s = fmax(sep, 1e-300);
+        const double tfn = sqrt(tf);
+        const double hen = tfn > 0.0 ? sqrt(fmax(tf - bd, 0.0)) / tfn : 0.0;
+        const double rg = n > 1 ? lg(gap / fmax(mx, 1e-300)) : 0.0;
+        f[0] = f[1] = (float)log2((double)n);
+        f[2] = f[3] = (float)lg(q.nA / sqrt((double)n));
+        f[4] = (float)lg(q.nC / (double)n);
+        f[5] = (float)lg(s);
+        f[6] = (float)lg(2.0 * q.nA / s);
+        f[7] = f[8] = (float)hen;
+        f[9] = f[10] = (float)(ncx / n);
+        f[11] = f[12] = (float)rg;
+        f[13] = f[14] = (float)lg(q.orth);
+        f[15] = 1.f;
+    }
+}
+
+// Class of every equation from the network's probabilities: 0 bfloat16-input
+// transforms, 1 binary32, 2 plain binary64 (the equation leaves the batch and
+// is solved by the single-equation binary64 path).
+__global__ void k_bchoose(BatchEq *eqs, const int *order, int batch, const float *prob) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= batch) return;
+    BatchEq &q = eqs[order[slot]];
+    const float *p = prob + (size_t)slot * 3;
+    int c = 0;
+    if (p[1] > p[c]) c = 1;
+    if (p[2] > p[c]) c = 2;
+    q.cls = c;
+    q.narrow = c == 0 ? 1 : 0;
+    if (c == 2) {
+        q.active = 0;
+        q.status = SYLV_ST_NOT_CONVERGED;
+    }
+}
+
+// selector inside the front of the batch: features, standardisation, one
+// forward pass over the batch, class per equation
+static void enqueue_selector(hipStream_t s, const BatchPlan &P) {
+    hipLaunchKernelGGL(k_bfeatures, dim3(P.batch), dim3(BNT), 0, s, P.deq, P.dord, P.feat);
+    mlp_standardize(s, P.batch, P.feat, P.sel + SYLV_MLP_NPARAM, P.sel + SYLV_MLP_NPARAM + SYLV_NFEAT, P.zfeat);
+    sylv_mlp_forward(P.batch, P.zfeat, P.sel, P.prob, s);
+    hipLaunchKernelGGL(k_bchoose, dim3((P.batch + 255) / 256), dim3(256), 0, s, P.deq, P.dord, P.batch, P.prob);
+}
+
+// A transform product of the batch in binary32 arithmetic.  Without the
+// selector every equation takes the precision option's operand format
+// (P.bf16); with the selector (P.autosel) the product runs twice, binary32
+// operands for the equations of class 1 (amode bit 64) and bfloat16 ones for
+// class 0 (bit 32): each launch skips the other equations at once.
+template <typename TA, typename TB, typename TC>
+static void tgemm(hipStream_t s, const BatchPlan &P, int fa, int ta, int fb, int tb, int fc, double alpha,
+                  int amode, float beta) {
+    if (!P.autosel) {
+        gemm_batched<TA, TB, TC, float>(s, P.deq, P.dord, P.batch, P.nmax, fa, ta, fb, tb, fc, alpha, amode, beta,
+                                        P.bf16);
+        return;
+    }
+    gemm_batched<TA, TB, TC, float>(s, P.deq, P.dord, P.batch, P.nmax, fa, ta, fb, tb, fc, alpha, amode | 64, beta,
+                                    0);
+    gemm_batched<TA, TB, TC, float>(s, P.deq, P.dord, P.batch, P.nmax, fa, ta, fb, tb, fc, alpha, amode | 32, beta,
+                                    1);
+}
+
 // second product of the forward transform, W = Y V: in full for general
 // equations; for symmetric ones Y U = U^T R U is symmetric, so only its
 // tiles on or above the diagonal are formed (into the free R buffer) and W
 // is read off their mirror with the column reversal of V = U P
 static void second_forward_product(hipStream_t s, const BatchPlan &P) {
-    gemm_batched<float, float, float, float>(s, P.deq, P.dord, P.batch, P.nmax, BF_Y, 0, BF_V, 0, BF_W, 1.f, 4,
-                                             0.f, P.bf16);
-    gemm_batched<float, float, float, float>(s, P.deq, P.dord, P.batch, P.nmax, BF_Y, 0, BF_U, 0, BF_R, 1.f,
-                                             8 | 16, 0.f, P.bf16);
+    tgemm<float, float, float>(s, P, BF_Y, 0, BF_V, 0, BF_W, 1.0, 4, 0.f);
+    tgemm<float, float, float>(s, P, BF_Y, 0, BF_U, 0, BF_R, 1.0, 8 | 16, 0.f);
     hipLaunchKernelGGL(k_bsym_fwd, dim3(P.batch), dim3(BNT), 0, s, P.deq, P.dord);
 }
 
@@ -863,14 +988,12 @@ static void enqueue_front(hipStream_t s, const BatchPlan &P) {
     hipLaunchKernelGGL(k_bpost, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
     if (P.orth) hipLaunchKernelGGL(k_borth, dim3(batch), dim3(BNT), 0, s, P.deq, P.dord);
     // first iterate: W = U^T (2^-e C) V, Y' solves T Y' + Y' TB = W, X = 2^e U Y' V^T
-    gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_C, 0, BF_Y, 1.f, 1, 0.f,
-                                              P.bf16);
+    if (P.autosel) enqueue_selector(s, P);
+    tgemm<float, double, float>(s, P, BF_U, 1, BF_C, 0, BF_Y, 1.0, 1, 0.f);
     second_forward_product(s, P);
     trsyl_batched(s, P.deq, P.dord, batch, P.nmax);
-    gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f,
-                                             P.bf16);
-    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2 | 8,
-                                              0.f, P.bf16);
+    tgemm<float, float, float>(s, P, BF_U, 0, BF_W, 0, BF_Y, 1.0, 0, 0.f);
+    tgemm<float, float, double>(s, P, BF_Y, 0, BF_V, 1, BF_X, 1.0, 2 | 8, 0.f);
     hipLaunchKernelGGL(k_bmirror_x, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
 }
 
@@ -893,14 +1016,11 @@ static void enqueue_pass(hipStream_t s, const BatchPlan &P, bool) {
 // X += 2^e U Y' V^T
 static void enqueue_correction(hipStream_t s, const BatchPlan &P) {
     const int batch = P.batch;
-    gemm_batched<float, double, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 1, BF_R, 0, BF_Y, 1.f, 1, 0.f,
-                                              P.bf16);
+    tgemm<float, double, float>(s, P, BF_U, 1, BF_R, 0, BF_Y, 1.0, 1, 0.f);
     second_forward_product(s, P);
     trsyl_batched(s, P.deq, P.dord, batch, P.nmax);
-    gemm_batched<float, float, float, float>(s, P.deq, P.dord, batch, P.nmax, BF_U, 0, BF_W, 0, BF_Y, 1.f, 0, 0.f,
-                                             P.bf16);
-    gemm_batched<float, float, double, float>(s, P.deq, P.dord, batch, P.nmax, BF_Y, 0, BF_V, 1, BF_X, 1.f, 2 | 8,
-                                              1.f, P.bf16);
+    tgemm<float, float, float>(s, P, BF_U, 0, BF_W, 0, BF_Y, 1.0, 0, 0.f);
+    tgemm<float, float, double>(s, P, BF_Y, 0, BF_V, 1, BF_X, 1.0, 2 | 8, 1.f);
     hipLaunchKernelGGL(k_bmirror_x, dim3(sym_pairs(P.nmax), batch), dim3(256), 0, s, P.deq, P.dord);
 }
 
@@ -923,7 +1043,7 @@ struct BatchGraph {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     BatchEq *deq = nullptr;
-    int passes = 0, bf16 = 0, max_iter = 0, orth = 0;
+    int passes = 0, bf16 = 0, max_iter = 0, orth = 0, autosel = 0;
     double tol = 0.0;
     std::vector<int> sizes;
     int tune[6] = {0, 0, 0, 0, 0, 0};  // batched tunables the graphs were captured with
@@ -971,7 +1091,7 @@ static int batch_graph_run(hipStream_t s, const BatchPlan &P, const std::vector<
     int tv[6];
     batch_tune_get(tv);
     const bool same = g.deq == P.deq && g.passes == passes && g.bf16 == P.bf16 && g.max_iter == P.max_iter &&
-                      g.tol == P.tol && g.orth == P.orth && g.sizes == sizes &&
+                      g.tol == P.tol && g.orth == P.orth && g.autosel == P.autosel && g.sizes == sizes &&
                       std::equal(tv, tv + 6, g.tune);
     if (!same) {
         for (int k = 0; k < 2; ++k)
@@ -987,6 +1107,7 @@ static int batch_graph_run(hipStream_t s, const BatchPlan &P, const std::vector<
         g.max_iter = P.max_iter;
         g.tol = P.tol;
         g.orth = P.orth;
+        g.autosel = P.autosel;
         g.sizes = std::move(sizes);
         std::copy(tv, tv + 6, g.tune);
     }
@@ -1024,6 +1145,7 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
     const size_t o_cnt = take(64);
     const size_t o_d = take(sizeof(double) * ws_d);
     const size_t o_f = take(sizeof(float) * ws_f);
+    const size_t o_sel = take(sizeof(float) * (size_t)batch * (2 * SYLV_NFEAT + SYLV_NCLASS));
     if (work_bytes < off) return -1;
     char *base = (char *)work;
     std::vector<BatchEq> hq(batch);
@@ -1070,6 +1192,18 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
     P.bf16 = (o.low == SYLV_PREC_BF16) ? 1 : (o.low == SYLV_PREC_FP16) ? 2 : 0;
     P.tol = o.tol; P.max_iter = o.max_iter;
     P.orth = o.orth_check != 0 ? 1 : 0;
+    // learned precision choice: the features need the orthogonality probe
+    P.autosel = (o.low == SYLV_PREC_AUTO) ? 1 : 0;
+    P.feat = (float *)(base + o_sel);
+    P.zfeat = P.feat + (size_t)batch * SYLV_NFEAT;
+    P.prob = P.zfeat + (size_t)batch * SYLV_NFEAT;
+    P.sel = nullptr;
+    if (P.autosel) {
+        P.orth = 1;
+        int src = 0;
+        P.sel = selector_device_blob(s, &src);
+        if (!P.sel) return src ? src : SYLV_ERR_HIP;
+    }
     const BatchTune tu = batch_tune();
     // Hessenberg size buckets (order is longest first): n > hess_hi,
     // hess_lo < n <= hess_hi, n <= hess_lo
@@ -1156,6 +1290,10 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
             f.iterations = q.iterations;
             f.precision_used = o.low;
             f.chosen = -1;
+            if (P.autosel) {
+                f.chosen = q.cls;
+                f.precision_used = q.cls == 0 ? SYLV_PREC_BF16 : q.cls == 1 ? SYLV_PREC_FP32 : SYLV_PREC_FP64;
+            }
             f.status = q.status;
             f.fell_back = 0;
         }
@@ -1205,6 +1343,7 @@ size_t lyap_batched_bytes(int batch, const int *nn) {
     take(64);
     take(sizeof(double) * ws_d);
     take(sizeof(float) * ws_f);
+    take(sizeof(float) * (size_t)batch * (2 * SYLV_NFEAT + SYLV_NCLASS));
     return off + 256;
 }
 

@@ -32,6 +32,41 @@ bool selector_installed() {
     return !g_sel.empty();
 }
 
+// Device buffer of the current device with the installed blob (params |
+// means | deviations) up to date (uploaded on s when stale; caller holds no
+// selector lock).
+static float *selector_sync_device(hipStream_t s, int *rc) {
+    *rc = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { *rc = SYLV_ERR_NOGPU; return nullptr; }
+    SelDev &d = g_seldev[dev];
+    const size_t np = SYLV_MLP_NPARAM;
+    if (!d.buf) {
+        if (hipMalloc((void **)&d.buf, sizeof(float) * (np + 96)) != hipSuccess) { *rc = SYLV_ERR_ALLOC; return nullptr; }
+        d.version = -1;
+    }
+    if (d.version != g_sel_version) {
+        const hipError_t e = hipMemcpyAsync(d.buf, g_sel.data(), sizeof(float) * (np + 2 * SYLV_NFEAT),
+                                            hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) {
+            // the host blob can change after this call returns: finish the copy
+            const hipError_t e2 = hipStreamSynchronize(s);
+            if (e2 != hipSuccess) { *rc = SYLV_ERR_HIP - (int)e2; return nullptr; }
+        } else {
+            *rc = SYLV_ERR_HIP - (int)e;
+            return nullptr;
+        }
+        d.version = g_sel_version;
+    }
+    return d.buf;
+}
+
+const float *selector_device_blob(hipStream_t s, int *rc) {
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    if (g_sel.empty()) { *rc = -1; return nullptr; }
+    return selector_sync_device(s, rc);
+}
+
 int selector_choose(hipStream_t s, char *hbuf, const float *f, int *cls, float *probs) {
     std::lock_guard<std::mutex> lk(g_sel_mu);
     if (g_sel.empty()) return -1;
@@ -40,19 +75,11 @@ int selector_choose(hipStream_t s, char *hbuf, const float *f, int *cls, float *
     SelDev &d = g_seldev[dev];
     const size_t np = SYLV_MLP_NPARAM;
     hipError_t e;
-    if (!d.buf) {
-        if (hipMalloc((void **)&d.buf, sizeof(float) * (np + 96)) != hipSuccess) return SYLV_ERR_ALLOC;
-        d.version = -1;
-    }
+    int rc0 = 0;
+    if (!selector_sync_device(s, &rc0)) return rc0;
     // device buffer: params | mean (16) | std (16) | raw features (16) |
     // standardised features (16) | probabilities (3)
     float *hb = reinterpret_cast<float *>(hbuf);
-    if (d.version != g_sel_version) {
-        if ((e = hipMemcpyAsync(d.buf, g_sel.data(), sizeof(float) * (np + 2 * SYLV_NFEAT), hipMemcpyHostToDevice,
-                                s)) != hipSuccess)
-            return SYLV_ERR_HIP - (int)e;
-        d.version = g_sel_version;
-    }
     float *dmean = d.buf + np, *dstd = dmean + SYLV_NFEAT, *draw = dstd + SYLV_NFEAT, *dz = draw + SYLV_NFEAT;
     float *dprob = dz + SYLV_NFEAT;
     for (int k = 0; k < SYLV_NFEAT; ++k) hb[k] = f[k];

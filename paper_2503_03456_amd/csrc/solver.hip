@@ -751,7 +751,8 @@ __global__ __launch_bounds__(1024) void k_spec_stats(int n, const T *Tm, int ld,
 //  4 log10(||C||_F/sqrt(mn)), 5 log10 sep_est, 6 log10 kappa_est
 //  (= (||A||_F + ||B||_F)/sep_est), 7-8 Henrici departure ||N||_F/||T||_F of
 //  T_A, T_B, 9-10 fraction of eigenvalues in complex pairs, 11-12 log10 of the
-//  relative minimum eigenvalue gap, 13-14 log10 ||U^T U - I||_F, ||V^T V - I||_F,
+//  relative minimum eigenvalue gap, 13-14 log10 of the probe estimates of
+//  ||U^T U - I||_F, ||V^T V - I||_F,
 //  15 Lyapunov flag.
 static int selector_features(hipStream_t s, DevCtx *c, int m, int n, bool lyap, Plan &p,
                              const Norms &nm, float *f) {
@@ -967,7 +968,7 @@ static int run_auto(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
                     const double *B, int ldb, bool lyap, const double *C, int ldc, double *X,
                     int ldx, Plan &p, const Norms &nm, const sylv_opts &o, sylv_info *info) {
     int qa = 0, qb = 0;
-    int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, 0, 2, &qa, &qb);
+    int rc = mixed_forms(s, c, m, n, A, lda, B, ldb, lyap, p, 0, 1, &qa, &qb);
     if (rc) return rc;
     float f[SYLV_NFEAT], pr[SYLV_NCLASS];
     rc = selector_features(s, c, m, n, lyap, p, nm, f);
@@ -976,7 +977,7 @@ static int run_auto(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
     rc = selector_choose(s, c->hbuf, f, &cls, pr);
     if (rc) return rc;
     sylv_opts oo = o;
-    oo.orth_check = 2;
+    oo.orth_check = 1;
     sylv_info tmp;
     sylv_info *inf = info ? info : &tmp;
     int ok = 0, iters = 0, esc = 0;
@@ -1055,7 +1056,7 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
     hipStream_t s = (hipStream_t)stream;
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool need_hi = !mixed || o.fallback || autosel;
-    const int orth = !mixed ? 0 : autosel ? 2 : o.orth_check;
+    const int orth = !mixed ? 0 : autosel ? 1 : o.orth_check;
     const bool alg41 = mixed && !autosel && (o.alg == SYLV_ALG_ORTH || o.alg == SYLV_ALG_INV);
     const size_t need = plan_bytes(m, n, lyap, mixed, need_hi, orth, alg41);
     void *base = work;
@@ -1190,7 +1191,7 @@ size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool autosel = o.low == SYLV_PREC_AUTO;
     return plan_bytes(m, n, lyap != 0, mixed, !mixed || o.fallback || autosel,
-                      !mixed ? 0 : (o.low == SYLV_PREC_AUTO) ? 2 : o.orth_check,
+                      !mixed ? 0 : (o.low == SYLV_PREC_AUTO) ? 1 : o.orth_check,
                       mixed && !autosel && (o.alg == SYLV_ALG_ORTH || o.alg == SYLV_ALG_INV));
 }
 
@@ -1238,11 +1239,11 @@ int sylv_selector_features(int m, int n, const double *A, int lda, const double 
         if (rc) return rc;
         hipStream_t s = (hipStream_t)stream;
         void *base = nullptr;
-        rc = ensure_work(c, plan_bytes(m, n, lyap, true, false, 2), &base);
+        rc = ensure_work(c, plan_bytes(m, n, lyap, true, false, 1), &base);
         if (rc) return rc;
         Arena ar(base);
         Plan p;
-        plan(ar, m, n, lyap, true, false, 2, p);
+        plan(ar, m, n, lyap, true, false, 1, p);
         matnorm<double>(s, m, m, A, lda, p.scal + 40, p.nscr, 0);
         if (!lyap) matnorm<double>(s, n, n, B, ldb, p.scal + 41, p.nscr, 0);
         matnorm<double>(s, m, n, C, ldc, p.scal + 42, p.nscr, 0);

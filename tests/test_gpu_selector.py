@@ -163,3 +163,41 @@ def test_selector_load_file(sel, tmp_path):
         fh.write(b"SYLVSEL0" + b"\0" * 64)
     assert sy.lib().sylv_selector_load(bad.encode()) == -2
     assert sy.lib().sylv_selector_load(str(tmp_path / "missing.bin").encode()) == -1
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_batched_auto_forced_class(sel, k):
+    """sylv_solve_batched with AUTO: one forward pass over the batch; with
+    weights that force class k every equation takes it (0: bfloat16-operand
+    transforms, 1: binary32, 2: the binary64 path) and meets the oracle."""
+    sy = binding()
+    sel.install(*sel.forced_params(k))
+    sizes = [150, 40, 17, 256]
+    its = [workloads.config4_item(2500 + i, n) for i, n in enumerate(sizes)]
+    Xs, infos = sy.solve_batched([(dev(A), dev(C)) for A, C, _ in its], low="auto")
+    torch.cuda.synchronize()
+    for (A, C, eig), X, info in zip(its, Xs, infos):
+        assert info["chosen"] == k, info
+        assert info["rel_res"] <= TOL, info
+        if k == 2:
+            assert info["precision_used"] == "fp64" and info["fell_back"] == 0
+        Xo, st = oracle.lyap_solve(A, C)
+        lam = eig[:, None] + eig[None, :]
+        kap = np.abs(lam).max() / np.abs(lam).min()
+        assert relerr(host(X), Xo) <= 100 * 2.0 ** -53 * kap
+
+
+def test_batched_auto_kappa_rule_uses_device_features(sel):
+    """The kappa_est rule as network weights (feature 6 = log10 kappa_est,
+    computed by the batched feature kernel): a well-separated equation gets
+    class 0 or 1, one with sep 2e-7 (kappa_est ~ 1e8) class 2."""
+    sy = binding()
+    sel.install(*sel.rule_params(lo=2.0, hi=6.0))
+    A1, C1, e1 = workloads.config4_item(2600, 90)
+    A2, C2, e2 = workloads.config4_item(2601, 90)
+    shift = -e2.real.max() - 1e-7
+    A2 = A2 + shift * np.eye(90)
+    _, infos = sy.solve_batched([(dev(A1), dev(C1)), (dev(A2), dev(C2))], low="auto")
+    torch.cuda.synchronize()
+    assert infos[0]["chosen"] in (0, 1) and infos[1]["chosen"] == 2, infos
+    assert all(i["rel_res"] <= TOL for i in infos)
