@@ -178,22 +178,85 @@ def label(eq):
     return lab, times, conv
 
 
+def policy_cost(cls, T, conv, tf):
+    """Time of solving one equation when class `cls` is chosen, from its
+    forced-class times T[3] (each: binary32 forms + features + the class's
+    work), their convergence flags and the time tf of the forms and features
+    alone: a failing class escalates (0 -> 1 -> 2) on the same forms."""
+    if cls == 2:
+        return T[2]
+    if cls == 1:
+        return T[1] if conv[1] else T[1] + (T[2] - tf)
+    if conv[0]:
+        return T[0]
+    c = T[0] + (T[1] - tf)
+    return c if conv[1] else c + (T[2] - tf)
+
+
+def tune_bias(logp, T, conv, tf, grid=np.arange(-4.0, 4.01, 0.25)):
+    """Offsets (d0, d2) added to the network's class-0 and class-2 logits
+    that minimise the total policy time on a labelled validation set (the
+    network is trained on labels; the offsets make its decision weigh what a
+    wrong choice costs: an unneeded binary64 solve against a few stalled
+    refinement steps)."""
+    best = (0.0, 0.0, float("inf"))
+    for d0 in grid:
+        for d2 in grid:
+            z = logp + np.array([d0, 0.0, d2])[None, :]
+            ch = z.argmax(1)
+            tot = sum(policy_cost(int(c), T[i], conv[i], tf[i]) for i, c in enumerate(ch))
+            if tot < best[2]:
+                best = (float(d0), float(d2), tot)
+    return best
+
+
+def with_bias(params, d0, d2):
+    p = np.array(params, np.float32, copy=True)
+    p[-3] += d0
+    p[-1] += d2
+    return p
+
+
+BUCKETS = [(16, 32), (32, 64), (64, 128), (128, 256), (256, 512), (512, 1025)]
+
+
+def bucket_accuracy(meta, y, pred):
+    """Accuracy per size bucket of max(m, n)."""
+    out = []
+    for lo, hi in BUCKETS:
+        idx = [i for i, mt in enumerate(meta) if lo <= max(mt[1], mt[2]) < hi]
+        if idx:
+            out.append({"max_order": [lo, hi - 1], "count": len(idx),
+                        "accuracy": float(np.mean([pred[i] == y[i] for i in idx]))})
+    return out
+
+
 def make_dataset(indices, lo, hi, seed_base, progress=True):
+    """Features, labels, forced-class times T (n x 3), convergence flags
+    (n x 3), forms-and-features times and (index, m, n, delta, lyap) per
+    instance."""
     import workloads
-    F, y, T, meta = [], [], [], []
+    F, y, T, CV, TF, meta = [], [], [], [], [], []
     t0 = time.time()
     for c, i in enumerate(indices):
         d = workloads.selector_instance(int(i), lo, hi, seed_base)
         eq = (_dev(d["A"]), None if d["B"] is None else _dev(d["B"]), _dev(d["C"]))
+        features(*eq)  # warm (workspace of this size)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
         F.append(features(*eq))
+        torch.cuda.synchronize()
+        TF.append(time.perf_counter() - s0)
         lab, times, conv = label(eq)
         y.append(lab)
         T.append(times)
+        CV.append(conv)
         meta.append((int(i), d["C"].shape[0], d["C"].shape[1], d["delta"], d["lyap"]))
         if progress and (c % 25 == 0 or c == len(indices) - 1):
             print(f"[selector data] {c + 1}/{len(indices)} n={d['C'].shape} delta={d['delta']:.1e} "
                   f"label={lab} ({time.time() - t0:.0f} s)", flush=True)
-    return np.array(F, np.float32), np.array(y, np.int32), np.array(T), meta
+    return (np.array(F, np.float32), np.array(y, np.int32), np.array(T), np.array(CV, bool), np.array(TF),
+            meta)
 
 
 def he_init(seed=0):
@@ -267,14 +330,22 @@ POLICIES = {
 # through the same AUTO path.
 
 
-def evaluate(indices, lo, hi, seed_base, weights, progress=True):
-    """Solve every instance under each policy (full solves with fallback);
-    report time, escalations and accuracy of the MLP's class."""
+def evaluate(indices, lo, hi, seed_base, weights, progress=True, with_labels=True):
+    """Solve every held-out instance under each policy (full solves with
+    fallback, after one untimed solve of each equation that sizes the
+    library's cached workspace); report time, escalations, the classes the
+    network chose and, from forced-class labels of the same instances, its
+    accuracy per size bucket."""
     import workloads
-    eqs = []
+    eqs, meta = [], []
     for i in indices:
         d = workloads.selector_instance(int(i), lo, hi, seed_base)
         eqs.append((_dev(d["A"]), None if d["B"] is None else _dev(d["B"]), _dev(d["C"])))
+        meta.append((int(i), d["C"].shape[0], d["C"].shape[1], d["delta"], d["lyap"]))
+    install(*weights)
+    for eq in eqs:
+        _run(eq, low="auto")
+    torch.cuda.synchronize()
     out = {}
     for name, kw in POLICIES.items():
         if name == "mlp":
@@ -292,8 +363,51 @@ def evaluate(indices, lo, hi, seed_base, weights, progress=True):
                      "escalation_rate": esc / len(eqs), "converged": ok, "count": len(eqs)}
         if name in ("mlp", "rule_kappa"):
             out[name]["class_counts"] = [int(np.sum(np.array(chosen) == k)) for k in range(3)]
+        if name == "mlp":
+            mlp_chosen = chosen
         if progress:
             print(f"[selector eval] {name}: {out[name]}", flush=True)
+    if with_labels:
+        y = [label(eq)[0] for eq in eqs]
+        out["mlp"]["accuracy"] = float(np.mean([a == b for a, b in zip(mlp_chosen, y)]))
+        out["mlp"]["bucket_accuracy"] = bucket_accuracy(meta, y, mlp_chosen)
+        out["label_counts"] = [int(np.sum(np.array(y) == k)) for k in range(3)]
+    uninstall()
+    return out
+
+
+def evaluate_batched(count, weights, reps=3, progress=True):
+    """Batched mix (count Lyapunov equations, orders U{16..256}, sep
+    log-uniform in [1e-8, 1e-1]): one sylv_solve_batched call per policy --
+    AUTO with the network (one forward pass over the batch) against binary32
+    + binary64 fallback -- timed as the median of `reps` calls."""
+    import workloads
+    from . import solve_batched, batched_workspace_size
+    items = [workloads.selector_lyap_mix(i) for i in range(count)]
+    eqs = [(_dev(d["A"]), _dev(d["C"])) for d in items]
+    ns = [d["n"] for d in items]
+    Xs = [torch.empty((n, n), dtype=torch.float64, device="cuda").t() for n in ns]
+    out = {}
+    for name, low in (("mlp_batched", "auto"), ("no_selector_fp32_batched", "fp32")):
+        install(*weights)
+        work = torch.empty(batched_workspace_size([1] * count, ns, ns, low=low), dtype=torch.uint8, device="cuda")
+        solve_batched(eqs, Xs=Xs, work=work, low=low)
+        torch.cuda.synchronize()
+        times, infos = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _, infos = solve_batched(eqs, Xs=Xs, work=work, low=low)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t = float(np.median(times))
+        out[name] = {"batch_seconds": t, "solves_per_s": count / t,
+                     "escalations": int(sum(i["fell_back"] for i in infos)),
+                     "converged": int(sum(i["rel_res"] <= TOL for i in infos)), "count": count}
+        if low == "auto":
+            out[name]["class_counts"] = [int(sum(i["chosen"] == k for i in infos)) for k in range(3)]
+        if progress:
+            print(f"[selector eval batched] {name}: {out[name]}", flush=True)
+        del work
     uninstall()
     return out
 
@@ -308,17 +422,35 @@ def main(argv=None):
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--weights", default=WEIGHTS)
     ap.add_argument("--report", default=None, help="JSON file for the evaluation / training summary")
+    ap.add_argument("--data", default=None, help="npz file for the labelled training set")
+    ap.add_argument("--batched-count", type=int, default=0,
+                    help="evaluate: also the batched Lyapunov mix of this many equations")
     a = ap.parse_args(argv)
     if a.cmd == "train":
         idx = np.arange(a.count)
-        F, y, T, meta = make_dataset(idx, a.lo, a.hi, 200000)
-        ntr = int(0.8 * len(y))
+        F, y, T, CV, TF, meta = make_dataset(idx, a.lo, a.hi, 200000)
+        if a.data:
+            np.savez(a.data, F=F, y=y, T=T, CV=CV, TF=TF, meta=np.array(meta, dtype=float))
+        ntr = int(0.85 * len(y))
         params, mean, std, hist = train_device(F[:ntr], y[:ntr], epochs=a.epochs)
         P = predict(params, mean, std, F[ntr:])
+        logp = np.log(np.maximum(P, 1e-30))
         acc = float(np.mean(P.argmax(1) == y[ntr:])) if len(y) > ntr else float("nan")
+        d0, d2, tbest = tune_bias(logp, T[ntr:], CV[ntr:], TF[ntr:])
+        params = with_bias(params, d0, d2)
+        Pb = predict(params, mean, std, F[ntr:])
+        vm = meta[ntr:]
+        costs = {name: float(sum(policy_cost(k(i), T[ntr + i], CV[ntr + i], TF[ntr + i])
+                                 for i in range(len(vm))))
+                 for name, k in (("mlp", lambda i: int(Pb[i].argmax())), ("fp32_then_fp64", lambda i: 1),
+                                 ("labels", lambda i: int(y[ntr + i])))}
         np.savez(a.out, params=params, mean=mean, std=std)
         save_blob(os.path.splitext(a.out)[0] + ".bin", params, mean, std)
         summ = {"instances": int(len(y)), "train": ntr, "val": int(len(y) - ntr), "val_accuracy": acc,
+                "val_accuracy_after_bias": float(np.mean(Pb.argmax(1) == y[ntr:])),
+                "bias": {"class0": d0, "class2": d2},
+                "val_policy_seconds_from_forced_times": costs,
+                "val_bucket_accuracy": bucket_accuracy(vm, y[ntr:], Pb.argmax(1)),
                 "label_counts": [int(np.sum(y == k)) for k in range(3)], "loss_first": hist[0],
                 "loss_last": hist[-1], "sizes": [a.lo, a.hi], "k_steps": K_STEPS}
         print(json.dumps(summ), flush=True)
@@ -329,6 +461,8 @@ def main(argv=None):
         w = load(a.weights)
         idx = np.arange(a.count)
         res = evaluate(idx, a.lo, a.hi, 300000, w)
+        if a.batched_count > 0:
+            res["batched"] = evaluate_batched(a.batched_count, w)
         print(json.dumps(res), flush=True)
         if a.report:
             with open(a.report, "w") as fh:

@@ -220,6 +220,20 @@ def selector_instance(i: int, lo: int = 32, hi: int = 1024, seed_base: int = 200
     return dict(A=A, B=B, C=_f(C), delta=delta, lyap=False, eigA=ea, eigB=eb)
 
 
+def selector_lyap_mix(i: int, lo: int = 16, hi: int = 256, seed_base: int = 400000):
+    """Equation i of the batched evaluation mix: a Lyapunov equation of order
+    n uniform in [lo, hi], sep target delta log-uniform in [1e-8, 1e-1], the
+    Lyapunov construction of selector_instance (Re(eig) in [0.5, 5] with a
+    planted eigenvalue delta/2, C = G + G^T)."""
+    rs = np.random.RandomState(seed_base + i)
+    n = int(rs.randint(lo, hi + 1))
+    delta = float(10.0 ** rs.uniform(-8.0, -1.0))
+    s = seed_base + i
+    A, ea, _, _ = normal_coeff(s + 1, n, 0.5, 5.0, planted=0.5, shift=delta / 2 - 0.5)
+    G = np.random.RandomState(s + 3).standard_normal((n, n))
+    return dict(A=A, C=_f(G + G.T), delta=delta, n=n, eigA=ea)
+
+
 def sym_coeff(seed, n, lo=0.5, hi=5.0, repeated=0, rep_value=None):
     """Symmetric A = Q diag(lam) Q^T, Q Haar, lam ~ U[lo, hi] in random
     order; the first ``repeated`` entries of lam equal ``rep_value`` (default
