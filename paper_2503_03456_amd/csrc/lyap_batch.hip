@@ -57,6 +57,21 @@ SYLV_DEVINL T wg_sum(T v, T *red) {
     return s;
 }
 
+// minimum over the workgroup (any sign)
+template <typename T>
+SYLV_DEVINL T wg_min(T v, T *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T s = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fmin(s, red[w]);
+    __syncthreads();
+    return s;
+}
+
+// maximum over the workgroup of non-negative values
 template <typename T>
 SYLV_DEVINL T wg_max(T v, T *red) {
 #pragma unroll
@@ -884,8 +899,8 @@ __global__ __launch_bounds__(BNT) void k_bfeatures(BatchEq *eqs, const int *orde
             bd += b * b + c * c;
         }
     }
-    sep = -wg_max(-sep, red);
-    gap = -wg_max(-gap, red);
+    sep = wg_min(sep, red);
+    gap = wg_min(gap, red);
     mx = wg_max(mx, red);
     ncx = wg_sum(ncx, red);
     bd = wg_sum(bd, red);
