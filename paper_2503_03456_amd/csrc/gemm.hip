@@ -13,6 +13,7 @@
 // fed swapped (op(B)^T in the A slot, op(A)^T in the B slot) so that each
 // lane's accumulators run down a column of C: stores are 16 consecutive
 // elements of a column per quarter-wave.
+#include <cstdlib>
 #include <type_traits>
 #include "common.hpp"
 #include "kernels.hpp"
@@ -104,6 +105,143 @@ SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int ld
                     // alpha is applied in the precision of C: a binary64 C
                     // takes an un-scaling power of two without binary32
                     // overflow or underflow
+                    TC *p = C + (size_t)j * ldc + i;
+                    const TC v = (TC)alpha * (TC)acc[a][b][r];
+                    if (beta != ACC(0)) *p = v + (TC)beta * (*p);
+                    else *p = v;
+                }
+            }
+}
+
+// ------------------------------------------------------ 128 x 128 tiles
+// Large products (M, N >= 128): a 128 x 128 output tile per 256-thread
+// workgroup, each wave64 a 64 x 64 quadrant (4 x 4 MFMA blocks of 16 x 16),
+// K staged through two LDS buffers 16 at a time (one barrier per K step: a
+// buffer is rewritten only after every wave has passed the barrier that
+// follows its last read).  Global loads move 8 consecutive elements per
+// thread along the contiguous dimension of each operand, as 16-byte vector
+// loads when the operand's base and leading dimension allow it.
+constexpr int LBM = 128, LBK = 16, LPAD = 16, LLD = LBM + LPAD;
+
+// 8 consecutive elements p[0..7] (cnt of them in range), scaled by sc in
+// their storage precision (a power of two applied before the conversion
+// keeps the range), converted to ACC
+template <typename TS, typename ACC>
+SYLV_DEVINL void load8(const TS *p, int cnt, bool vec, TS sc, ACC (&out)[8]) {
+    if (vec && cnt >= 8) {
+        if constexpr (sizeof(TS) == 8) {
+            typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const d2 v = *reinterpret_cast<const d2 *>(p + 2 * h);
+                out[2 * h] = (ACC)(sc * v[0]);
+                out[2 * h + 1] = (ACC)(sc * v[1]);
+            }
+        } else {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f4 v = *reinterpret_cast<const f4 *>(p + 4 * h);
+#pragma unroll
+                for (int z = 0; z < 4; ++z) out[4 * h + z] = (ACC)(sc * v[z]);
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h) out[h] = (h < cnt) ? (ACC)(sc * p[h]) : ACC(0);
+}
+
+template <typename TA, typename TB, typename TC, typename ACC>
+__global__ __launch_bounds__(256) void gemm128_kernel(int M, int N, int K, const TA *__restrict__ A, int lda,
+                                                      int ta, const TB *__restrict__ B, int ldb, int tb,
+                                                      TC *__restrict__ C, int ldc, double alpha, ACC beta,
+                                                      int tiles_m, TB bscale, int upper) {
+    typedef typename mfma16<ACC>::v4 v4;
+    __shared__ ACC As[2][LBK][LLD];
+    __shared__ ACC Bs[2][LBK][LLD];
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+    int tm, tn;
+    if (upper) sym_pair_index(bid, tm, tn);
+    else { tm = bid % tiles_m; tn = bid / tiles_m; }
+    const int row0 = tm * LBM, col0 = tn * LBM;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wm = w & 1, wn = w >> 1;
+    // vector loads need 16-byte aligned columns
+    const bool va = ((reinterpret_cast<size_t>(A) | ((size_t)lda * sizeof(TA))) & 15) == 0;
+    const bool vb = ((reinterpret_cast<size_t>(B) | ((size_t)ldb * sizeof(TB))) & 15) == 0;
+    // slab coordinates of this thread's 8 consecutive elements
+    //   op(A) 128 x 16: !ta -> rows ai..ai+7 of column ak; ta -> k ak..ak+7 of row ai
+    //   op(B) 16 x 128: !tb -> k bk..bk+7 of column bj; tb -> columns bj..bj+7 of row bk
+    const int ai = ta ? (t >> 1) : (t & 15) * 8, ak = ta ? (t & 1) * 8 : (t >> 4);
+    const int bj = tb ? (t & 15) * 8 : (t >> 1), bk = tb ? (t >> 4) : (t & 1) * 8;
+    ACC ra[8], rb[8];
+    auto load = [&](int k0) {
+        if (!ta) {
+            const int gi = row0 + ai, gk = k0 + ak;
+            const int cnt = (gk < K) ? min(8, M - gi) : 0;
+            load8<TA, ACC>(A + (size_t)gk * lda + gi, cnt > 0 ? cnt : 0, va, TA(1), ra);
+        } else {
+            const int gi = row0 + ai, gk = k0 + ak;
+            const int cnt = (gi < M) ? min(8, K - gk) : 0;
+            load8<TA, ACC>(A + (size_t)gi * lda + gk, cnt > 0 ? cnt : 0, va, TA(1), ra);
+        }
+        if (!tb) {
+            const int gj = col0 + bj, gk = k0 + bk;
+            const int cnt = (gj < N) ? min(8, K - gk) : 0;
+            load8<TB, ACC>(B + (size_t)gj * ldb + gk, cnt > 0 ? cnt : 0, vb, bscale, rb);
+        } else {
+            const int gj = col0 + bj, gk = k0 + bk;
+            const int cnt = (gk < K) ? min(8, N - gj) : 0;
+            load8<TB, ACC>(B + (size_t)gk * ldb + gj, cnt > 0 ? cnt : 0, vb, bscale, rb);
+        }
+    };
+    auto store = [&](int st) {
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            if (!ta) As[st][ak][ai + h] = ra[h];
+            else As[st][ak + h][ai] = ra[h];
+            if (!tb) Bs[st][bk + h][bj] = rb[h];
+            else Bs[st][bk][bj + h] = rb[h];
+        }
+    };
+    v4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4{0, 0, 0, 0};
+    const int nk = (K + LBK - 1) / LBK;
+    if (nk > 0) load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        const int st = kt & 1;
+        store(st);
+        __syncthreads();
+        if (kt + 1 < nk) load((kt + 1) * LBK);
+#pragma unroll
+        for (int kk = 0; kk < LBK / 4; ++kk) {
+            const int kr = 4 * kk + (l >> 4);
+            ACC fa[4], fb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) fa[a] = As[st][kr][64 * wm + 16 * a + (l & 15)];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) fb[b] = Bs[st][kr][64 * wn + 16 * b + (l & 15)];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = mfma16<ACC>::op(fb[b], fa[a], acc[a][b]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = row0 + 64 * wm + 16 * a + (l & 15);
+                const int j = col0 + 64 * wn + 16 * b + mfma16<ACC>::orow(l, r);
+                if (i < M && j < N) {
                     TC *p = C + (size_t)j * ldc + i;
                     const TC v = (TC)alpha * (TC)acc[a][b][r];
                     if (beta != ACC(0)) *p = v + (TC)beta * (*p);
@@ -366,6 +504,13 @@ template void gemm_batched<float, float, double, float>(hipStream_t, const Batch
                                                         int, int, int, int, int, int, double, int, float,
                                                         int);
 
+// 128 x 128 tiles for large products (SYLV_GEMM128=0 in the environment
+// keeps every product on the 64 x 64 kernel)
+static const bool g_gemm128 = [] {
+    const char *v = std::getenv("SYLV_GEMM128");
+    return !(v && v[0] == '0');
+}();
+
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, const TA *A, int lda,
           const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale, int in_bf16, int upper) {
@@ -386,6 +531,14 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, cons
                                A, lda, ta, B, ldb, tb, C, ldc, alpha, (float)beta, tm, bscale, upper);
             return;
         }
+    }
+    if (M >= LBM && N >= LBM && K >= LBK && g_gemm128) {
+        const int tm2 = (M + LBM - 1) / LBM, tn2 = (N + LBM - 1) / LBM;
+        const int up2 = (upper && tm2 == tn2) ? 1 : 0;
+        const int nt2 = up2 ? tm2 * (tm2 + 1) / 2 : tm2 * tn2;
+        hipLaunchKernelGGL((gemm128_kernel<TA, TB, TC, ACC>), dim3(nt2), dim3(256), 0, s, M, N, K, A, lda, ta, B,
+                           ldb, tb, C, ldc, alpha, beta, tm2, bscale, up2);
+        return;
     }
     hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, ACC>), dim3(ntiles), dim3(256), 0, s, M, N, K, A,
                        lda, ta, B, ldb, tb, C, ldc, alpha, beta, tm, bscale, upper);

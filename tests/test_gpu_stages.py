@@ -15,7 +15,9 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("m,n,k,ta,tb", [(1, 1, 1, 0, 0), (17, 33, 5, 0, 0), (64, 64, 64, 1, 0),
                                          (100, 70, 130, 0, 1), (129, 65, 200, 1, 1),
-                                         (300, 257, 19, 0, 0), (1, 300, 77, 1, 1)])
+                                         (300, 257, 19, 0, 0), (1, 300, 77, 1, 1),
+                                         (257, 300, 130, 1, 0), (256, 384, 64, 0, 1), (129, 131, 33, 1, 1),
+                                         (512, 512, 512, 0, 0), (130, 128, 17, 0, 0)])
 def test_gemm_parity(prec, m, n, k, ta, tb):
     sy = binding()
     say("gemm", prec, m, n, k, ta, tb)
@@ -31,6 +33,36 @@ def test_gemm_parity(prec, m, n, k, ta, tb):
     u = U64 if prec == "fp64" else U32
     scale = np.abs(Ah).max() * np.abs(Bh).max() * k + np.abs(Ch).max()
     assert np.abs(host(Cg) - ref).max() <= 4 * k * u * scale
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+def test_gemm_parity_odd_leading_dimensions(prec, ta, tb):
+    """Operands that are column slices of larger arrays with odd leading
+    dimensions (no 16-byte column alignment: the large-tile kernel's scalar
+    load path) against numpy."""
+    sy = binding()
+    m, n, k = 200, 170, 150
+    rs = np.random.RandomState(11 + ta)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ar, ac = (k, m) if ta else (m, k)
+    br, bc = (n, k) if tb else (k, n)
+    Af = dev(rs.standard_normal((ar + 1, ac)), dt)
+    Bf = dev(rs.standard_normal((br + 3, bc)), dt)
+    Cf = dev(rs.standard_normal((m + 1, n)), dt)
+    A, B, C = Af[:ar], Bf[1:br + 1], Cf[:m]
+    assert A.stride(1) % 2 == 1 and B.stride(1) % 2 == 1
+    C0 = host(C).copy()
+    last = host(Cf)[m].copy()
+    Cg = sy.gemm(A, B, C, alpha=1.25, beta=-1.0, ta=bool(ta), tb=bool(tb))
+    torch.cuda.synchronize()
+    Ah, Bh = host(A), host(B)
+    ref = 1.25 * (Ah.T if ta else Ah) @ (Bh.T if tb else Bh) - C0
+    u = U64 if prec == "fp64" else U32
+    scale = np.abs(Ah).max() * np.abs(Bh).max() * k + np.abs(C0).max()
+    assert np.abs(host(Cg) - ref).max() <= 4 * k * u * scale
+    # the row outside the slice is untouched
+    assert np.array_equal(host(Cf)[m], last)
 
 
 # --------------------------------------------------------- tri-solve parity
