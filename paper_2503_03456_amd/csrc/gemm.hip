@@ -114,7 +114,7 @@ SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int ld
 }
 
 // ------------------------------------------------------ 128 x 128 tiles
-// Large products (M, N >= 128): a 128 x 128 output tile per 256-thread
+// Large products (M, N >= 1024-ish, K >= 256): a 128 x 128 output tile per 256-thread
 // workgroup, each wave64 a 64 x 64 quadrant (4 x 4 MFMA blocks of 16 x 16),
 // K staged through two LDS buffers 16 at a time (one barrier per K step: a
 // buffer is rewritten only after every wave has passed the barrier that
@@ -532,7 +532,10 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, cons
             return;
         }
     }
-    if (M >= LBM && N >= LBM && K >= LBK && g_gemm128) {
+    // the 128-wide tile pays off on long contractions over enough tiles to
+    // fill the chip; the Hessenberg's panel-width products (K = 32) run
+    // faster on the 64-wide tile (four times the workgroups)
+    if (M >= LBM && N >= LBM && K >= 256 && (M / LBM) * (N / LBM) >= 64 && g_gemm128) {
         const int tm2 = (M + LBM - 1) / LBM, tn2 = (N + LBM - 1) / LBM;
         const int up2 = (upper && tm2 == tn2) ? 1 : 0;
         const int nt2 = up2 ? tm2 * (tm2 + 1) / 2 : tm2 * tn2;

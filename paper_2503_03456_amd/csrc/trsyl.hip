@@ -40,6 +40,7 @@ constexpr int TS = 64;       // tile capacity
 constexpr int TBASE = 63;    // nominal boundary spacing (adjusted by +1 at 2x2 blocks)
 constexpr int TLD = TS + 1;  // LDS leading dimension of tiles
 constexpr int TBK = 32;      // K slab of the in-tile MFMA update
+constexpr int TRSYL_NT = 256;   // threads of a single-equation tile workgroup (1024 measured no faster)
 
 // Boundary k of a quasi-triangular matrix of order n cut every TBASE rows.
 template <typename T>
@@ -183,7 +184,11 @@ SYLV_DEVINL void tile_gemm(typename mfma16t<T>::v4 (&acc)[2][2], const T *Ap, in
 // solution Y' = Y P of a symmetric Y (persymmetric: Y'(i, j) =
 // Y'(n-1-j, n-1-i)) maps tile (I, J) onto tile (nt-1-J, nt-1-I) of the same
 // anti-diagonal; wmirror also stores that mirror tile.
-template <typename T>
+// NT: threads of the workgroup (256 with the left-looking MFMA updates of
+// the batched form; the single-equation form runs the same count: 1024
+// threads, which spread each block pair's sums over more lanes, left the
+// binary32 tile time unchanged and slowed the binary64 one).
+template <typename T, int NT = 256>
 SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, const T *__restrict__ TB,
                             int ldtb, T *C, int ldc, int I, int J, double maxab, int *flag, int mirror = 0,
                             int wmirror = 0, bool lazy = true) {
@@ -213,30 +218,40 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
 
     // ---- 1. off-diagonal updates on MFMA (left-looking form): acc =
     //         TA(r0:r1, r1:m) Y(r1:m, c0:c1) + Y(r0:r1, 0:c0) TB(0:c0, c0:c1)
-    v4 acc[2][2];
+    if constexpr (NT == 256) {
+        v4 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
-    if (lazy) {
-        tile_gemm<T>(acc, TA + (size_t)r1 * ldta + r0, ldta, C + (size_t)c0 * ldc + r1, ldc, m - r1, p, q, stA, stB);
-        tile_gemm<T>(acc, C + r0, ldc, TB + (size_t)c0 * ldtb, ldtb, c0, p, q, stA, stB);
+            for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+        if (lazy) {
+            tile_gemm<T>(acc, TA + (size_t)r1 * ldta + r0, ldta, C + (size_t)c0 * ldc + r1, ldc, m - r1, p, q, stA,
+                         stB);
+            tile_gemm<T>(acc, C + r0, ldc, TB + (size_t)c0 * ldtb, ldtb, c0, p, q, stA, stB);
+        }
+        // rhs tile: sC(i, j) = C(r0+i, c0+j) - acc
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int i = 32 * wm + 16 * a + (l & 15);
+                    int j = 32 * wn + 16 * b + mfma16t<T>::orow(l, r);
+                    const int ic = i < p ? i : p - 1, jc = j < q ? j : q - 1;
+                    const T cv = C[(size_t)(c0 + jc) * ldc + r0 + ic];
+                    sC[j * TLD + i] = (cv - acc[a][b][r]) * T((i < p && j < q) ? 1 : 0);
+                }
+    } else {
+        // the right-hand side is complete in C (right-looking updates)
+        for (int e = t; e < TS * TS; e += NT) {
+            const int i = e % TS, j = e / TS;
+            const int ic = i < p ? i : p - 1, jc = j < q ? j : q - 1;
+            sC[j * TLD + i] = C[(size_t)(c0 + jc) * ldc + r0 + ic] * T((i < p && j < q) ? 1 : 0);
+        }
     }
-    // rhs tile: sC(i, j) = C(r0+i, c0+j) - acc
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int i = 32 * wm + 16 * a + (l & 15);
-                int j = 32 * wn + 16 * b + mfma16t<T>::orow(l, r);
-                const int ic = i < p ? i : p - 1, jc = j < q ? j : q - 1;
-                const T cv = C[(size_t)(c0 + jc) * ldc + r0 + ic];
-                sC[j * TLD + i] = (cv - acc[a][b][r]) * T((i < p && j < q) ? 1 : 0);
-            }
 #pragma unroll 8
-    for (int e = t; e < TS * TS; e += 256) {
+    for (int e = t; e < TS * TS; e += NT) {
         const int i = e % TS, j = e / TS;
         const T av = CM(TA, r0 + (i < p ? i : p - 1), r0 + (j < p ? j : p - 1), ldta);
         const T bv = CM(TB, c0 + (i < q ? i : q - 1), c0 + (j < q ? j : q - 1), ldtb);
@@ -262,12 +277,15 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
     // ---- 2. wavefront over block pairs: unit (ib, jb), ib counted from the
     // bottom; anti-diagonal e = ib + jb.  A unit's sums over the solved rows
     // below and columns to the left are split over tpu adjacent lanes (the
-    // largest power of two with tpu * units <= 256).
+    // largest power of two with tpu * units <= NT, at most 64).
     for (int e = 0; e <= P + Q - 2; ++e) {
         const int jlo = e - (P - 1) > 0 ? e - (P - 1) : 0;
         const int jhi = e < Q - 1 ? e : Q - 1;
         const int nunits = jhi - jlo + 1;
-        const int tpu = nunits <= 4 ? 64 : nunits <= 8 ? 32 : nunits <= 16 ? 16 : nunits <= 32 ? 8 : 4;
+        // lanes per unit: the largest power of two <= 64 with tpu * nunits <= NT
+        // (at most 64 units: a tile has at most 64 block rows and columns)
+        const int tpu = (NT == 256) ? (nunits <= 4 ? 64 : nunits <= 8 ? 32 : nunits <= 16 ? 16 : nunits <= 32 ? 8 : 4)
+                                    : (nunits <= 16 ? 64 : nunits <= 32 ? 32 : 16);
         const int u = t / tpu, sub = t % tpu;
         T part[4] = {T(0), T(0), T(0), T(0)};
         int ri = 0, pi = 0, cj = 0, qj = 0;
@@ -331,12 +349,12 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
         }
         __syncthreads();
     }
-    for (int e = t; e < p * q; e += 256) {
+    for (int e = t; e < p * q; e += NT) {
         int i = e % p, j = e / p;
         C[(size_t)(c0 + j) * ldc + r0 + i] = sC[j * TLD + i];
     }
     if (wmirror)  // Y'(n-1-j, n-1-i) = Y'(i, j), consecutive threads down a column
-        for (int e = t; e < p * q; e += 256) {
+        for (int e = t; e < p * q; e += NT) {
             int j = e % q, i = e / q;
             C[(size_t)(n - 1 - (r0 + i)) * ldc + (n - 1 - (c0 + j))] = sC[j * TLD + i];
         }
@@ -346,13 +364,14 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
 // mirror: symmetric Lyapunov (see trsyl_tile); the grid then covers only
 // the tiles with 2J <= d
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
+__global__ __launch_bounds__(TRSYL_NT) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
                                                    const T *__restrict__ TB, int ldtb, T *C, int ldc,
                                                    int d, int nI, int jmin, const double *maxab,
                                                    int *flag, int mirror) {
     const int J = jmin + blockIdx.x;
     const int I = nI - 1 - (d - J);
-    trsyl_tile<T>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror, mirror && 2 * J < d, false);
+    trsyl_tile<T, TRSYL_NT>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror, mirror && 2 * J < d,
+                            false);
 }
 
 // Right-looking updates after anti-diagonal d is solved: every tile (I, J)
@@ -457,7 +476,7 @@ void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int 
         int jmax = d < nJ - 1 ? d : nJ - 1;
         if (mirror && jmax > d / 2) jmax = d / 2;
         ProfScope ps(KID_TRSYL, s);
-        hipLaunchKernelGGL((k_trsyl_diag<T>), dim3(jmax - jmin + 1), dim3(256), 0, s, m, n, TA, ldta,
+        hipLaunchKernelGGL((k_trsyl_diag<T>), dim3(jmax - jmin + 1), dim3(TRSYL_NT), 0, s, m, n, TA, ldta,
                            TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror);
         if (d < nI + nJ - 2)
             hipLaunchKernelGGL((k_trsyl_update<T>), dim3(nJ, nI), dim3(256), 0, s, m, n, TA, ldta, TB, ldtb, C,

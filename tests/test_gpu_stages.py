@@ -17,7 +17,9 @@ pytestmark = pytest.mark.gpu
                                          (100, 70, 130, 0, 1), (129, 65, 200, 1, 1),
                                          (300, 257, 19, 0, 0), (1, 300, 77, 1, 1),
                                          (257, 300, 130, 1, 0), (256, 384, 64, 0, 1), (129, 131, 33, 1, 1),
-                                         (512, 512, 512, 0, 0), (130, 128, 17, 0, 0)])
+                                         (512, 512, 512, 0, 0), (130, 128, 17, 0, 0),
+                                         (1024, 1040, 300, 0, 0), (1100, 1024, 260, 1, 1),
+                                         (1030, 1153, 513, 1, 0)])
 def test_gemm_parity(prec, m, n, k, ta, tb):
     sy = binding()
     say("gemm", prec, m, n, k, ta, tb)
@@ -42,7 +44,7 @@ def test_gemm_parity_odd_leading_dimensions(prec, ta, tb):
     dimensions (no 16-byte column alignment: the large-tile kernel's scalar
     load path) against numpy."""
     sy = binding()
-    m, n, k = 200, 170, 150
+    m, n, k = 1030, 1025, 260   # large enough for the 128-wide tile
     rs = np.random.RandomState(11 + ta)
     dt = torch.float64 if prec == "fp64" else torch.float32
     ar, ac = (k, m) if ta else (m, k)
