@@ -15,6 +15,7 @@
 #include <vector>
 #include <cstring>
 #include <mutex>
+#include <thread>
 
 namespace sylv {
 int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A, const int *lda,
@@ -22,6 +23,72 @@ int lyap_batched(hipStream_t s, int batch, const int *nn, const double *const *A
                  const sylv_opts &o, sylv_info *infos, void *work, size_t work_bytes, char *hbuf);
 }
 using namespace sylv;
+
+static size_t pool_slice(size_t bytes) { return (bytes + 4095) & ~(size_t)4095; }
+
+// One single-equation solve of a batched call (a binary64 re-solve, a
+// selector class-2 equation, or an equation outside the batched kernels).
+struct SingleJob {
+    int i;             // equation index
+    sylv_opts o;       // options of this solve
+    sylv_info prev;    // batched result it follows (fell_back / chosen bookkeeping)
+    int kind;          // 0 plain, 1 fallback after the batched pass, 2 selector class 2
+};
+
+// Runs the jobs on the pooled contexts from up to kSolvePool host threads.
+// With a caller workspace of at least kSolvePool slices each thread takes one
+// slice; a smaller caller workspace runs the jobs one after another in it;
+// without one every pooled context keeps its own.
+static int run_single_jobs(const std::vector<SingleJob> &jobs, const int *kind, const int *m, const int *n,
+                           const double *const *A, const int *lda, const double *const *B, const int *ldb,
+                           const double *const *C, const int *ldc, double *const *X, const int *ldx,
+                           sylv_info *infos, void *work, size_t work_bytes) {
+    if (jobs.empty()) return 0;
+    size_t single = 0;
+    for (const SingleJob &j : jobs) {
+        const int lyap = kind[j.i] == SYLV_KIND_LYAP;
+        single = std::max(single, sylv_workspace_size(m[j.i], lyap ? m[j.i] : n[j.i], lyap, &j.o));
+    }
+    const size_t slice = pool_slice(single);
+    int threads = std::min<int>(kSolvePool, (int)jobs.size());
+    if (work && work_bytes < slice * threads) threads = 1;
+    std::vector<int> rcs(threads, 0);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SYLV_ERR_NOGPU;
+    auto worker = [&](int t) {
+        hipSetDevice(dev);
+        void *w = work ? (char *)work + (threads > 1 ? slice * t : 0) : nullptr;
+        const size_t wb = work ? (threads > 1 ? slice : work_bytes) : 0;
+        for (size_t k = t; k < jobs.size(); k += threads) {
+            const SingleJob &j = jobs[k];
+            const int i = j.i;
+            const bool lyap = kind[i] == SYLV_KIND_LYAP;
+            sylv_info g;
+            const int rc = solve_pooled(t, m[i], n[i], A[i], lda[i], lyap ? nullptr : B[i], lyap ? 1 : ldb[i],
+                                        C[i], ldc[i], X[i], ldx[i], &j.o, &g, w, wb);
+            if (rc) { rcs[t] = rc; return; }
+            if (j.kind == 2) {
+                g.chosen = 2;
+                g.orth_u = j.prev.orth_u;
+                g.orth_v = j.prev.orth_v;
+            } else if (j.kind == 1) {
+                g.fell_back = 1;
+                g.iterations += j.prev.iterations;
+                g.chosen = j.prev.chosen;
+            }
+            if (infos) infos[i] = g;
+        }
+    };
+    if (threads == 1) worker(0);
+    else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < threads; ++t) pool.emplace_back(worker, t);
+        for (auto &th : pool) th.join();
+    }
+    for (int rc : rcs)
+        if (rc) return rc;
+    return 0;
+}
 
 static bool batched_eligible(int kind, int n, const sylv_opts &o) {
     return kind == SYLV_KIND_LYAP && n >= 1 && n <= 256 && o.alg == SYLV_ALG_ORIG &&
@@ -52,7 +119,8 @@ extern "C" size_t sylv_batched_workspace_size(int batch, const int *kind, const 
         }
     }
     const size_t b = nb.empty() ? 0 : lyap_batched_bytes((int)nb.size(), nb.data());
-    return std::max(b, single);
+    // single-equation solves run side by side, one workspace slice each
+    return std::max(b, pool_slice(single) * kSolvePool);
 }
 
 static int solve_batched_impl(int batch, const int *kind, const int *m, const int *n,
@@ -98,6 +166,7 @@ static int solve_batched_impl(int batch, const int *kind, const int *m, const in
     hipStream_t s = (hipStream_t)stream;
     if (const int cap = stream_capture_code(s, work == nullptr)) return cap;
 
+    std::vector<SingleJob> jobs;
     // equations for the batched kernels (validated like the single path)
     std::vector<int> idx, bn, blda, bldc, bldx;
     std::vector<const double *> bA, bC;
@@ -135,19 +204,12 @@ static int solve_batched_impl(int batch, const int *kind, const int *m, const in
         if (rc) return rc;
         for (int t = 0; t < nb; ++t) {
             const int i = idx[t];
-            sylv_info f = binf[t];
+            const sylv_info &f = binf[t];
             if (o.low == SYLV_PREC_AUTO && f.chosen == 2) {
                 // the selector sent the equation to the plain binary64 path
                 sylv_opts f64 = o;
                 f64.low = SYLV_PREC_FP64;
-                sylv_info g;
-                rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &f64, &g, work, work_bytes,
-                                stream);
-                if (rc) return rc;
-                g.chosen = 2;
-                g.orth_u = f.orth_u;
-                g.orth_v = f.orth_v;
-                if (infos) infos[i] = g;
+                jobs.push_back({i, f64, f, 2});
                 continue;
             }
             const bool ok = f.status == SYLV_OK || f.status == SYLV_ST_PERTURBED;
@@ -159,31 +221,23 @@ static int solve_batched_impl(int batch, const int *kind, const int *m, const in
                 const bool narrow = o.low == SYLV_PREC_BF16 || o.low == SYLV_PREC_FP16 ||
                                     (o.low == SYLV_PREC_AUTO && f.chosen == 0);
                 f64.low = narrow ? SYLV_PREC_FP32 : SYLV_PREC_FP64;
-                sylv_info g;
-                rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &f64, &g, work,
-                                work_bytes, stream);
-                if (rc) return rc;
-                g.fell_back = 1;
-                g.iterations += f.iterations;
-                g.chosen = f.chosen;
-                f = g;
+                jobs.push_back({i, f64, f, 1});
+                continue;
             }
             if (infos) infos[i] = f;
         }
     }
     for (int i = 0; i < batch; ++i) {
         if (batched_eligible(kind[i], m[i], o)) continue;
-        int rc;
-        sylv_info *inf = infos ? infos + i : nullptr;
-        if (kind[i] == SYLV_KIND_LYAP)
-            rc = lyap_solve(m[i], A[i], lda[i], C[i], ldc[i], X[i], ldx[i], &o, inf, work, work_bytes,
-                            stream);
-        else
-            rc = sylv_solve(m[i], n[i], A[i], lda[i], B[i], ldb[i], C[i], ldc[i], X[i], ldx[i], &o,
-                            inf, work, work_bytes, stream);
-        if (rc) return rc;
+        jobs.push_back({i, o, sylv_info{}, 0});
     }
-    return 0;
+    // the single solves run on the pooled contexts' own streams: finish the
+    // caller's stream first (its earlier work may produce their inputs)
+    if (!jobs.empty()) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return SYLV_ERR_HIP - (int)e;
+    }
+    return run_single_jobs(jobs, kind, m, n, A, lda, B, ldb, C, ldc, X, ldx, infos, work, work_bytes);
 }
 
 extern "C" int sylv_batched_tune(int hess_hi, int hess_lo, int band1, int band2, int band3, int graph_passes) {

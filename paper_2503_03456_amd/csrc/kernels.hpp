@@ -55,6 +55,12 @@ int selector_choose(hipStream_t s, char *hbuf, const float *feats, int *cls, flo
 
 // solver.hip
 std::mutex &lib_mutex();
+// independent solves run side by side on pooled contexts (own stream,
+// staging and lock each); B == nullptr selects the Lyapunov equation
+constexpr int kSolvePool = 8;
+int solve_pooled(int slot, int m, int n, const double *A, int lda, const double *B, int ldb, const double *C,
+                 int ldc, double *X, int ldx, const sylv_opts *opts, sylv_info *info, void *work,
+                 size_t work_bytes);
 int stream_capture_code(hipStream_t s, bool needs_alloc);
 bool is_device_pointer(const void *p);
 // Per-equation results for a caller array that may live in device memory:

@@ -926,15 +926,23 @@ __global__ __launch_bounds__(BNT) void k_bfeatures(BatchEq *eqs, const int *orde
 
 // Class of every equation from the network's probabilities: 0 bfloat16-input
 // transforms, 1 binary32, 2 plain binary64 (the equation leaves the batch and
-// is solved by the single-equation binary64 path).
+// is solved by the single-equation binary64 path).  In a batch a refinement
+// that stalls costs only its share of batch-wide passes (about 0.5 ms per
+// equation at 1024 equations), while a needless binary64 re-solve costs a
+// whole single-equation solve (about 10 ms at these orders), so class 2 is
+// taken only when p2 > 20 p1 (log-score offset -ln 20 = -3).
+constexpr float kBatchClass2Offset = -3.0f;
 __global__ void k_bchoose(BatchEq *eqs, const int *order, int batch, const float *prob) {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= batch) return;
     BatchEq &q = eqs[order[slot]];
     const float *p = prob + (size_t)slot * 3;
+    float sc[3];
+    for (int k = 0; k < 3; ++k) sc[k] = logf(fmaxf(p[k], 1e-30f));
+    sc[2] += kBatchClass2Offset;
     int c = 0;
-    if (p[1] > p[c]) c = 1;
-    if (p[2] > p[c]) c = 2;
+    if (sc[1] > sc[c]) c = 1;
+    if (sc[2] > sc[c]) c = 2;
     q.cls = c;
     q.narrow = c == 0 ? 1 : 0;
     if (c == 2) {

@@ -39,15 +39,15 @@ struct DevCtx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     void *work = nullptr;       // cached internal workspace
     size_t work_bytes = 0;
+    hipStream_t own = nullptr;  // pooled contexts: the stream their solves run on
 };
 
 static std::mutex g_mu;
 static DevCtx g_ctx[64];
 
-static int device_ctx(DevCtx **out) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SYLV_ERR_NOGPU;
-    DevCtx &c = g_ctx[dev];
+// One-time set-up of a context on device dev (own: also a stream of its own
+// for the pooled solves).
+static int init_ctx(DevCtx &c, int dev, bool own) {
     if (!c.checked) {
         c.checked = true;
         hipDeviceProp_t prop;
@@ -56,15 +56,31 @@ static int device_ctx(DevCtx **out) {
         if (hipHostMalloc((void **)&c.hbuf, 65536, hipHostMallocDefault) != hipSuccess) return SYLV_ERR_ALLOC;
         if (hipHostMalloc((void **)&c.hbuf2, 65536, hipHostMallocDefault) != hipSuccess) return SYLV_ERR_ALLOC;
         if (hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking) != hipSuccess) return SYLV_ERR_NOGPU;
+        if (own && hipStreamCreateWithFlags(&c.own, hipStreamNonBlocking) != hipSuccess) return SYLV_ERR_NOGPU;
         if (hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming) != hipSuccess) return SYLV_ERR_NOGPU;
         if (hipEventCreateWithFlags(&c.ev_out, hipEventDisableTiming) != hipSuccess) return SYLV_ERR_NOGPU;
         c.dev = dev;
         c.ok = true;
     }
-    if (!c.ok) return SYLV_ERR_NOGPU;
+    return c.ok ? 0 : SYLV_ERR_NOGPU;
+}
+
+static int device_ctx(DevCtx **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SYLV_ERR_NOGPU;
+    DevCtx &c = g_ctx[dev];
+    const int rc = init_ctx(c, dev, false);
+    if (rc) return rc;
     *out = &c;
     return 0;
 }
+
+// Pool of contexts for independent solves run side by side from several host
+// threads (the binary64 re-solves and single-equation members of a batched
+// call): each has its own stream, pinned staging and workspace cache, and a
+// lock of its own instead of the library lock.
+static DevCtx g_pool[64][kSolvePool];
+static std::mutex g_pool_mu[64][kSolvePool];
 
 static int ensure_work(DevCtx *c, size_t bytes, void **out) {
     if (c->work_bytes < bytes) {
@@ -1004,10 +1020,12 @@ static int run_auto(hipStream_t s, DevCtx *c, int m, int n, const double *A, int
     return 0;
 }
 
+// pc: a pooled context whose lock the caller holds (the library lock is
+// then not taken); nullptr: the device's own context under the library lock.
 static int solve_common_impl(int m, int n, const double *A, int lda, const double *B, int ldb,
                         const double *C, int ldc, double *X, int ldx, bool lyap,
                         const sylv_opts *opts, sylv_info *info, void *work, size_t work_bytes,
-                        void *stream) {
+                        void *stream, DevCtx *pc = nullptr) {
     sylv_opts o;
     sylv_default_opts(&o);
     if (opts) o = *opts;
@@ -1049,10 +1067,14 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
         const int cap = stream_capture_code((hipStream_t)stream, work == nullptr);
         if (cap) return cap;
     }
-    std::lock_guard<std::mutex> lk(g_mu);
-    DevCtx *c = nullptr;
-    int rc = device_ctx(&c);
-    if (rc) return rc;
+    std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
+    DevCtx *c = pc;
+    int rc = 0;
+    if (!c) {
+        lk.lock();
+        rc = device_ctx(&c);
+        if (rc) return rc;
+    }
     hipStream_t s = (hipStream_t)stream;
     const bool mixed = o.low != SYLV_PREC_FP64;
     const bool need_hi = !mixed || o.fallback || autosel;
@@ -1145,15 +1167,37 @@ static int solve_common_impl(int m, int n, const double *A, int lda, const doubl
 static int solve_common(int m, int n, const double *A, int lda, const double *B, int ldb,
                         const double *C, int ldc, double *X, int ldx, bool lyap,
                         const sylv_opts *opts, sylv_info *info, void *work, size_t work_bytes,
-                        void *stream) {
+                        void *stream, DevCtx *pc = nullptr) {
     int rc = solve_common_impl(m, n, A, lda, B, ldb, C, ldc, X, ldx, lyap, opts, info, work,
-                               work_bytes, stream);
+                               work_bytes, stream, pc);
     // invalid sizes and empty problems return before any HIP call
     if (m <= 0 || (!lyap && n <= 0)) return rc;
     hipError_t e = hipGetLastError();
     if (rc == 0 && e != hipSuccess) rc = SYLV_ERR_HIP - (int)e;
     if (rc == -1 && m >= 0) rc = SYLV_ERR_HIP;  // internal launch failure
     return rc;
+}
+
+// A solve on pooled context `slot` of the current device, on that
+// context's own stream (independent of the caller's stream, which must not
+// hold unfinished work the solve depends on).  B == nullptr: Lyapunov.
+int solve_pooled(int slot, int m, int n, const double *A, int lda, const double *B, int ldb, const double *C,
+                 int ldc, double *X, int ldx, const sylv_opts *opts, sylv_info *info, void *work,
+                 size_t work_bytes) {
+    if (slot < 0 || slot >= kSolvePool) return -1;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SYLV_ERR_NOGPU;
+    std::lock_guard<std::mutex> lk(g_pool_mu[dev][slot]);
+    DevCtx &c = g_pool[dev][slot];
+    int rc = init_ctx(c, dev, true);
+    if (rc) return rc;
+    const bool lyap = B == nullptr;
+    try {
+        return solve_common(m, lyap ? m : n, A, lda, B, lyap ? 1 : ldb, C, ldc, X, ldx, lyap, opts, info, work,
+                            work_bytes, (void *)c.own, &c);
+    } catch (const std::bad_alloc &) {
+        return SYLV_ERR_ALLOC;
+    }
 }
 
 // ------------------------------------------------ allocation-free scratch

@@ -460,7 +460,7 @@ def main(argv=None):
     else:
         w = load(a.weights)
         idx = np.arange(a.count)
-        res = evaluate(idx, a.lo, a.hi, 300000, w)
+        res = evaluate(idx, a.lo, a.hi, 300000, w) if a.count > 0 else {}
         if a.batched_count > 0:
             res["batched"] = evaluate_batched(a.batched_count, w)
         print(json.dumps(res), flush=True)

@@ -190,9 +190,11 @@ def test_batched_auto_forced_class(sel, k):
 def test_batched_auto_kappa_rule_uses_device_features(sel):
     """The kappa_est rule as network weights (feature 6 = log10 kappa_est,
     computed by the batched feature kernel): a well-separated equation gets
-    class 0 or 1, one with sep 2e-7 (kappa_est ~ 1e8) class 2."""
+    class 0 or 1, one with sep 2e-7 (kappa_est ~ 1e8.5) class 2."""
     sy = binding()
-    sel.install(*sel.rule_params(lo=2.0, hi=6.0))
+    # hi = 4: the class-2 logit exceeds class 1's by ~4.5 at kappa_est ~ 1e8.5,
+    # above the batched decision's margin of ln 20
+    sel.install(*sel.rule_params(lo=2.0, hi=4.0))
     A1, C1, e1 = workloads.config4_item(2600, 90)
     A2, C2, e2 = workloads.config4_item(2601, 90)
     shift = -e2.real.max() - 1e-7

@@ -49,8 +49,9 @@ def test_gemm_parity_odd_leading_dimensions(prec, ta, tb):
     dt = torch.float64 if prec == "fp64" else torch.float32
     ar, ac = (k, m) if ta else (m, k)
     br, bc = (n, k) if tb else (k, n)
-    Af = dev(rs.standard_normal((ar + 1, ac)), dt)
-    Bf = dev(rs.standard_normal((br + 3, bc)), dt)
+    odd = lambda r: r + 1 if r % 2 == 0 else r + 2   # an odd leading dimension above r
+    Af = dev(rs.standard_normal((odd(ar), ac)), dt)
+    Bf = dev(rs.standard_normal((odd(br + 1), bc)), dt)
     Cf = dev(rs.standard_normal((m + 1, n)), dt)
     A, B, C = Af[:ar], Bf[1:br + 1], Cf[:m]
     assert A.stride(1) % 2 == 1 and B.stride(1) % 2 == 1
