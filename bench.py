@@ -365,13 +365,16 @@ def sweep_c3(args, np, torch, sy):
     def dev(a):
         return torch.from_numpy(np.asfortranarray(a)).t().contiguous().t().cuda()
 
+    from paper_2503_03456_amd import selector
+    selector.install(*selector.load())   # the committed weights, for low = "auto"
     rows = []
     for j in range(args.c3_first, 6):
         cfg = workloads.config3(j)
         A, B, C = dev(cfg["A"]), dev(cfg["B"]), dev(cfg["C"])
         Xe = exact_solution(cfg)
-        row = {"delta": cfg["delta"]}
-        for low in ("fp32", "bf16", "fp64"):
+        row = {"delta": cfg["delta"], "kappa_est": kappa_est(np, cfg),
+               "forward_error_bound": 100 * 2.0 ** -53 * kappa_est(np, cfg)}
+        for low in ("fp32", "bf16", "fp64", "auto"):
             sy.solve(A, B, C, low=low)   # warm
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -381,11 +384,11 @@ def sweep_c3(args, np, torch, sy):
             fe = float(np.linalg.norm(X.cpu().numpy() - Xe) / np.linalg.norm(Xe))
             row[low] = {"seconds": dt, "iterations": info["iterations"], "fell_back": info["fell_back"],
                         "precision_used": info["precision_used"], "rel_res": info["rel_res"],
-                        "forward_error": fe, "sep_est": info["sep_est"]}
+                        "forward_error": fe, "sep_est": info["sep_est"], "chosen": info["chosen"]}
         rows.append(row)
         print(f"[c3] delta={cfg['delta']:.0e} " + " ".join(
             f"{k}:{row[k]['seconds']:.2f}s/it{row[k]['iterations']}/fb{row[k]['fell_back']}"
-            for k in ("fp32", "bf16", "fp64")), file=sys.stderr, flush=True)
+            for k in ("fp32", "bf16", "fp64", "auto")), file=sys.stderr, flush=True)
     print(json.dumps({"workload": "config 3 sweep, sylvester m=4096 n=1024", "rows": rows}), flush=True)
 
 
