@@ -424,6 +424,45 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K,
                                tn * GBN, As, Bs);
 }
 
+// Split-K partial products for short, wide outputs (a panel of nb <= 64 rows
+// times a long contraction: too few 64x64 tiles to fill the chip).  Slice z
+// of the contraction, k in [z kc, min(K, (z + 1) kc)), writes its product
+// op(A) op(B) to P + z M N (ld M); the caller sums the slices in order.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_splitk_kernel(int M, int N, int K, int kc,
+                                                          const T *__restrict__ A, int lda, int ta,
+                                                          const T *__restrict__ B, int ldb, int tb,
+                                                          T *__restrict__ P, int tiles_m) {
+    __shared__ T As[GBK][GBM + GPAD];
+    __shared__ T Bs[GBK][GBN + GPAD];
+    const int z = blockIdx.y, kb = z * kc;
+    const int kl = min(kc, K - kb);
+    const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    const T *Az = ta ? A + kb : A + (size_t)kb * lda;
+    const T *Bz = tb ? B + (size_t)kb * ldb : B + kb;
+    gemm_tile<T, T, T, T>(M, N, kl, Az, lda, ta, Bz, ldb, tb, P + (size_t)z * M * N, M, 1.0, T(0), T(1),
+                          tm * GBM, tn * GBN, As, Bs);
+}
+
+template <typename T>
+int gemm_splitk(hipStream_t s, int ta, int tb, int M, int N, int K, const T *A, int lda, const T *B, int ldb,
+                T *P, int ksplit) {
+    if (M <= 0 || N <= 0 || K <= 0 || ksplit < 1) return 0;
+    const int per = (K + ksplit - 1) / ksplit;
+    const int kc = (per + GBK - 1) / GBK * GBK;
+    const int nz = (K + kc - 1) / kc;   // every slice non-empty
+    const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
+    prof_add_work(KID_GEMM, 2.0 * M * N * K);
+    ProfScope ps(KID_GEMM, s);
+    hipLaunchKernelGGL((gemm_splitk_kernel<T>), dim3(tm * tn, nz), dim3(256), 0, s, M, N, K, kc, A, lda, ta, B,
+                       ldb, tb, P, tm);
+    return nz;
+}
+template int gemm_splitk<float>(hipStream_t, int, int, int, int, int, const float *, int, const float *, int,
+                                float *, int);
+template int gemm_splitk<double>(hipStream_t, int, int, int, int, int, const double *, int, const double *, int,
+                                 double *, int);
+
 // Batched form over the equations of a batch: grid.y = equation slot (in
 // the order given), grid.x = 64x64 tile of that equation's n x n product.
 // Operands are fields of the per-equation descriptor.

@@ -22,6 +22,7 @@
 namespace sylv {
 
 constexpr int HNT = 1024;
+constexpr int HKS = 16;   // most contraction slices of a split panel product
 
 template <typename T>
 SYLV_DEVINL T block_sum(T v, T *red) {
@@ -471,6 +472,60 @@ __global__ __launch_bounds__(256) void k_hess_gemv(int n, const T *A, int lda, c
     if (r < n) Ypart[(size_t)s * n + r] = acc;
 }
 
+// W2 = op(T) * sum_{z < nz} P_z for a panel: P_z (nbp x nt, ld nbp) are the
+// split-K slices of V^T M, T (nbp x nbp, ld ldt) the panel's triangular
+// factor, op(T) = T^T when trans.  One workgroup per 64 columns: the slice
+// sums go to LDS in a fixed order, then each thread forms 8 outputs.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hess_tsum(int nbp, int nt, int nz, const T *__restrict__ P,
+                                                  const T *__restrict__ Tp, int ldt, int trans, T *__restrict__ W2) {
+    __shared__ T S[32][65];
+    __shared__ T Ts[32][33];
+    const int tid = threadIdx.x, j0 = blockIdx.x * 64;
+    for (int e = tid; e < 32 * 32; e += 256) {
+        const int i = e & 31, l = e >> 5;
+        T v = T(0);
+        if (i < nbp && l < nbp) v = trans ? Tp[(size_t)i * ldt + l] : Tp[(size_t)l * ldt + i];
+        Ts[i][l] = v;
+    }
+    const size_t slice = (size_t)nbp * nt;
+    for (int e = tid; e < 32 * 64; e += 256) {
+        const int i = e & 31, jj = e >> 5, j = j0 + jj;
+        T v = T(0);
+        if (i < nbp && j < nt) {
+            const T *p = P + (size_t)j * nbp + i;
+            for (int z = 0; z < nz; ++z) v += p[z * slice];
+        }
+        S[i][jj] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < 32 * 64; e += 256) {
+        const int i = e & 31, jj = e >> 5, j = j0 + jj;
+        if (i < nbp && j < nt) {
+            T acc = T(0);
+            for (int l = 0; l < nbp; ++l) acc += Ts[i][l] * S[l][jj];
+            W2[(size_t)j * nbp + i] = acc;
+        }
+    }
+}
+
+// W2 (nbp x nt) = op(T) (V^T M): V the panel's reflectors (mr x nbp, ld ldv),
+// M (mr x nt, ld ldm).  The contraction over mr runs split over the chip
+// (the output has only nt / 64 tiles); with BF16 inputs the plain GEMMs.
+template <typename T>
+static void panel_vtm(hipStream_t s, int nbp, int nt, int mr, const T *Vp, int ldv, const T *M, int ldm,
+                      const T *Tp, int ldt, int trans, T *W, T *W2, T *Pk, int bf16) {
+    const int tiles = (nt + 63) / 64;
+    if (!bf16 && nbp <= 32 && tiles < 128) {
+        const int ks = std::min(HKS, std::max(1, 512 / tiles));
+        const int nz = gemm_splitk<T>(s, 1, 0, nbp, nt, mr, Vp, ldv, M, ldm, Pk, ks);
+        hipLaunchKernelGGL((k_hess_tsum<T>), dim3(tiles), dim3(256), 0, s, nbp, nt, nz, Pk, Tp, ldt, trans, W2);
+        return;
+    }
+    gemm<T, T, T, T>(s, 1, 0, nbp, nt, mr, T(1), Vp, ldv, M, ldm, T(0), W, nbp, T(1), bf16);
+    gemm<T, T, T, T>(s, trans, 0, nbp, nt, nbp, T(1), Tp, ldt, W, nbp, T(0), W2, nbp);
+}
+
 template <typename T>
 size_t hessenberg_work_elems(int n, int nb, int S) {
     int np = (n + nb - 1) / nb;
@@ -479,7 +534,8 @@ size_t hessenberg_work_elems(int n, int nb, int S) {
            + (size_t)n * nb           // Y
            + (size_t)S * n            // Ypart
            + (size_t)n                // tau
-           + (size_t)2 * nb * n;      // W, W2 for the trailing update
+           + (size_t)2 * nb * n       // W, W2 for the trailing update
+           + (size_t)HKS * nb * n;    // split-K partial products of V^T M
 }
 template size_t hessenberg_work_elems<float>(int, int, int);
 template size_t hessenberg_work_elems<double>(int, int, int);
@@ -517,6 +573,7 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
     T *tau = Ypart + (size_t)S * n;
     T *W = tau + n;
     T *W2 = W + (size_t)nb * n;
+    T *Pk = W2 + (size_t)nb * n;
     hipMemsetAsync(V, 0, sizeof(T) * (size_t)n * n, s);
     hipMemsetAsync(Tall, 0, sizeof(T) * (size_t)((n + nb - 1) / nb) * nb * nb, s);
     const int rb = (n + 255) / 256;
@@ -544,9 +601,8 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
                              A + (size_t)c1 * lda, lda, T(1), bf16);
             // left: A(k0+1:n, c1:n) -= V T^T (V^T A(k0+1:n, c1:n))
             const int mr = n - k0 - 1;
-            gemm<T, T, T, T>(s, 1, 0, nbp, nt, mr, T(1), V + (size_t)k0 * n + k0 + 1, n,
-                             A + (size_t)c1 * lda + k0 + 1, lda, T(0), W, nbp, T(1), bf16);
-            gemm<T, T, T, T>(s, 1, 0, nbp, nt, nbp, T(1), Tp, nb, W, nbp, T(0), W2, nbp);
+            panel_vtm<T>(s, nbp, nt, mr, V + (size_t)k0 * n + k0 + 1, n, A + (size_t)c1 * lda + k0 + 1, lda,
+                         Tp, nb, 1, W, W2, Pk, bf16);
             gemm<T, T, T, T>(s, 0, 0, mr, nt, nbp, T(-1), V + (size_t)k0 * n + k0 + 1, n, W2, nbp,
                              T(1), A + (size_t)c1 * lda + k0 + 1, lda, T(1), bf16);
         }
@@ -558,9 +614,7 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
         T *Tp = Tall + (size_t)p * nb * nb;
         const int mr = n - k0 - 1;
         T *Us = U + (size_t)(k0 + 1) * ldu + k0 + 1;
-        gemm<T, T, T, T>(s, 1, 0, nbp, mr, mr, T(1), V + (size_t)k0 * n + k0 + 1, n, Us, ldu, T(0),
-                         W, nbp, T(1), bf16);
-        gemm<T, T, T, T>(s, 0, 0, nbp, mr, nbp, T(1), Tp, nb, W, nbp, T(0), W2, nbp);
+        panel_vtm<T>(s, nbp, mr, mr, V + (size_t)k0 * n + k0 + 1, n, Us, ldu, Tp, nb, 0, W, W2, Pk, bf16);
         gemm<T, T, T, T>(s, 0, 0, mr, mr, nbp, T(-1), V + (size_t)k0 * n + k0 + 1, n, W2, nbp, T(1),
                          Us, ldu, T(1), bf16);
     }

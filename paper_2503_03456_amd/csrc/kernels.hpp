@@ -92,6 +92,12 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, cons
           const TB *B, int ldb, ACC beta, TC *C, int ldc, TB bscale = TB(1), int in_bf16 = 0,
           int upper = 0);
 
+// split-K partial products op(A) op(B) of the contraction slices into
+// P + z M N (ld M); returns the slice count nz (<= ksplit)
+template <typename T>
+int gemm_splitk(hipStream_t s, int ta, int tb, int M, int N, int K, const T *A, int lda, const T *B, int ldb,
+                T *P, int ksplit);
+
 template <typename TA, typename TB, typename TC, typename ACC>
 void gemm_batched(hipStream_t s, const BatchEq *eqs, const int *order, int batch, int nmax, int fa,
                   int ta, int fb, int tb, int fc, double alpha, int amode, ACC beta, int in_bf16 = 0);

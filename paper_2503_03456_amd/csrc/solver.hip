@@ -172,6 +172,7 @@ struct OrthStage {
 
 // random probe vectors of the orthogonality estimate
 constexpr int kProbes = 8;
+constexpr int kProbeSlices = 32;  // contraction slices of the probe product U Z
 
 // Narrow operand format of the GEMM-shaped updates for a precision option:
 // 0 binary32 inputs, 1 bfloat16, 2 binary16 (the code the GEMM wrappers take)
@@ -241,7 +242,7 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
     }
     p.R = a.take<double>((size_t)m * n);
     if (orth == 2) p.G = a.take<double>((size_t)2 * mx * mx);
-    else if (orth == 1) p.G = a.take<double>((size_t)3 * kProbes * mx);
+    else if (orth == 1) p.G = a.take<double>((size_t)(3 + kProbeSlices) * kProbes * mx);
     p.scal = a.take<double>(64);
     p.nscr = a.take<double>(512);
     p.flag = a.take<int>(64);
@@ -527,19 +528,92 @@ __global__ void k_probe_vectors(int n, unsigned seed, double *Z) {
     }
 }
 
+// Slice z of W = U Z (U: n x n binary32, Z: n x kProbes binary64, both
+// ld n): Wp_z(i, p) = sum_{k in [z kc, (z + 1) kc)} U(i, k) Z(k, p), one
+// thread per row i (coalesced column reads of U), Z staged 128 rows at a time
+__global__ __launch_bounds__(256) void k_probe_uz(int n, int kc, const float *__restrict__ U,
+                                                  const double *__restrict__ Z, double *__restrict__ Wp) {
+    __shared__ double zs[128 * kProbes];
+    const int z = blockIdx.y, kb = z * kc, ke = min(n, kb + kc);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double acc[kProbes];
+#pragma unroll
+    for (int q = 0; q < kProbes; ++q) acc[q] = 0.0;
+    for (int c0 = kb; c0 < ke; c0 += 128) {
+        const int cl = min(128, ke - c0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cl * kProbes; e += 256) {
+            const int k = e / kProbes, q = e % kProbes;
+            zs[e] = Z[(size_t)q * n + c0 + k];
+        }
+        __syncthreads();
+        if (i < n)
+            for (int k = 0; k < cl; ++k) {
+                const double u = (double)U[(size_t)(c0 + k) * n + i];
+#pragma unroll
+                for (int q = 0; q < kProbes; ++q) acc[q] += u * zs[k * kProbes + q];
+            }
+    }
+    if (i < n)
+#pragma unroll
+        for (int q = 0; q < kProbes; ++q) Wp[((size_t)z * kProbes + q) * n + i] = acc[q];
+}
+
+// W = sum_z Wp_z in slice order (n x kProbes, ld n)
+__global__ void k_probe_sum(int n, int nz, const double *__restrict__ Wp, double *__restrict__ W) {
+    const size_t total = (size_t)n * kProbes;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int z = 0; z < nz; ++z) v += Wp[(size_t)z * total + e];
+        W[e] = v;
+    }
+}
+
+// E(j, p) = sum_i U(i, j) W(i, p) - Z(j, p): one wavefront per column j of
+// U (lanes along i, a fixed shuffle tree per probe)
+__global__ __launch_bounds__(256) void k_probe_utw(int n, const float *__restrict__ U, const double *__restrict__ W,
+                                                   const double *__restrict__ Z, double *__restrict__ E) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    if (j >= n) return;
+    double acc[kProbes];
+#pragma unroll
+    for (int q = 0; q < kProbes; ++q) acc[q] = 0.0;
+    const float *uc = U + (size_t)j * n;
+    for (int i = l; i < n; i += 64) {
+        const double u = (double)uc[i];
+#pragma unroll
+        for (int q = 0; q < kProbes; ++q) acc[q] += u * W[(size_t)q * n + i];
+    }
+#pragma unroll
+    for (int q = 0; q < kProbes; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        acc[q] = v;
+    }
+    if (l == 0)
+#pragma unroll
+        for (int q = 0; q < kProbes; ++q) E[(size_t)q * n + j] = acc[q] - Z[(size_t)q * n + j];
+}
+
 // Randomised estimate of ||U^T U - I||_F (Hutchinson's trace estimator of
 // ||E||_F^2 = tr(E^T E) with E = U^T U - I): for independent random sign
 // vectors z, E ||E z||^2 = ||E||_F^2, so with Z = [z_1 .. z_k] / sqrt(k) the
 // value ||U^T (U Z) - Z||_F estimates ||E||_F in O(k n^2) binary64 flops
-// (binary32 U entries are exact in binary64).  G holds 3 kProbes n doubles.
+// (binary32 U entries are exact in binary64).  G holds (3 + kProbeSlices)
+// kProbes n doubles: Z, W, E and the slices of U Z.
 static void orth_probe(hipStream_t s, int n, const float *U, double *G, double *out, double *nscr,
                        unsigned seed) {
     double *Z = G, *W = G + (size_t)kProbes * n, *E = G + (size_t)2 * kProbes * n;
+    double *Wp = G + (size_t)3 * kProbes * n;
     const int nb = (int)std::min<size_t>(1024, ((size_t)n * kProbes + 255) / 256);
     hipLaunchKernelGGL(k_probe_vectors, dim3(nb), dim3(256), 0, s, n, seed, Z);
-    gemm<float, double, double, double>(s, 0, 0, n, kProbes, n, 1.0, U, n, Z, n, 0.0, W, n);
-    cast<double, double>(s, n, kProbes, Z, n, E, n, -1.0);
-    gemm<float, double, double, double>(s, 1, 0, n, kProbes, n, 1.0, U, n, W, n, 1.0, E, n);
+    const int nz = std::min(kProbeSlices, (n + 15) / 16);
+    const int kc = (n + nz - 1) / nz;
+    const int nzs = (n + kc - 1) / kc;   // every slice non-empty
+    hipLaunchKernelGGL(k_probe_uz, dim3((n + 255) / 256, nzs), dim3(256), 0, s, n, kc, U, Z, Wp);
+    hipLaunchKernelGGL(k_probe_sum, dim3(nb), dim3(256), 0, s, n, nzs, Wp, W);
+    hipLaunchKernelGGL(k_probe_utw, dim3((n + 3) / 4), dim3(256), 0, s, n, U, W, Z, E);
     matnorm<double>(s, n, kProbes, E, n, out, nscr, 0);
 }
 
