@@ -239,15 +239,20 @@ size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, con
  *   adv     rows a bulge chain advances per LDS window phase,
  *   nibble  percentage of the window AED must deflate to skip the sweep,
  *   aed_waves    wavefronts of the AED kernel (4 or 7),
- *   chase_waves  wavefronts of the bulge-chase kernel (8 or 16).
+ *   chase_waves  wavefronts of the bulge-chase kernel (8 or 16),
+ *   chains  bulge chains a sweep's nb bulges are split into (1..4): chain g
+ *           enters one window width after chain g-1, and the chains' disjoint
+ *           windows are chased side by side, one workgroup each (in exact
+ *           arithmetic the same QR step: the chains' shift polynomials
+ *           multiply to the sweep's).
  * A value <= 0 (nibble < 0) keeps the current one.  Returns 0, -1 for a bad
  * prec, -2 when the combination exceeds the LDS/workspace bounds
- * (FP32: nsmall, nw <= 140, adv + 3 nb + 1 <= 141; FP64: 98 and 99) or names
- * an unsupported wave count. */
+ * (FP32: nsmall, nw <= 140, nb <= 44, adv + 3 ceil(nb / chains) + 1 <= 141;
+ * FP64: 98, 32 and 99) or names an unsupported wave or chain count. */
 int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, int aed_waves,
-                    int chase_waves);
-/* Current tunables (nsmall, nw, nb, adv, nibble, aed_waves, chase_waves) into
- * vals[7] (host). */
+                    int chase_waves, int chains);
+/* Current tunables (nsmall, nw, nb, adv, nibble, aed_waves, chase_waves,
+ * chains) into vals[8] (host). */
 int sylv_schur_tune_get(int prec, int *vals);
 
 /* Tunables of the batched Lyapunov path (process-wide, next call on; the

@@ -76,7 +76,7 @@ _lib.sylv_mlp_forward.argtypes = [_i, _vp, _vp, _vp, _vp]
 _lib.sylv_mlp_forward.restype = _i
 _lib.sylv_mlp_train_step.argtypes = [_i, _vp, _vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp, _fp, _vp]
 _lib.sylv_mlp_train_step.restype = _i
-_lib.sylv_schur_tune.argtypes = [_i, _i, _i, _i, _i, _i, _i, _i]
+_lib.sylv_schur_tune.argtypes = [_i, _i, _i, _i, _i, _i, _i, _i, _i]
 _lib.sylv_schur_tune.restype = _i
 _lib.sylv_schur_tune_get.argtypes = [_i, _ip]
 _lib.sylv_schur_tune_get.restype = _i

@@ -1,10 +1,11 @@
 """Autotuners of the Schur factorisation's QR-phase parameters and of the
 batched Lyapunov path.
 
-Coordinate search over (aedw, chasew, nw, nb, adv, nsmall, nibble) -- the
-wavefronts of the AED and bulge-chase kernels, the aggressive early
-deflation window, bulges per multishift sweep, rows per bulge-chain window
-phase, the full-window cutoff and the sweep-skip threshold (see
+Coordinate search over (aedw, chasew, chains, nw, nb, adv, nsmall, nibble) --
+the wavefronts of the AED and bulge-chase kernels, the bulge chains chased
+side by side, the aggressive early deflation window, bulges per multishift
+sweep, rows per bulge-chain window phase, the full-window cutoff and the
+sweep-skip threshold (see
 ``sylv_schur_tune`` in include/sylv.h) -- timing ``sylv_schur`` on a matrix
 of the benchmark recipe (normal, Re(eig) in [0.5, 5], 30% complex pairs) drawn
 with a seed the benchmark does not use.  Each candidate is checked for a valid
@@ -38,24 +39,26 @@ from . import lib, _check
 
 PREC = {"fp32": 1, "fp64": 0}
 GRID = {
-    "fp32": dict(nw=[24, 32, 40, 48, 64, 80, 96, 128], nb=[8, 12, 16, 20, 24, 32], adv=[24, 32, 40, 48, 64],
-                 nsmall=[64, 96, 128, 140], nibble=[14, 20, 30, 40, 50, 65], aedw=[4, 7], chasew=[8, 16]),
-    "fp64": dict(nw=[24, 32, 40, 48, 64, 80, 96], nb=[8, 12, 16, 20, 24], adv=[24, 32, 40, 48],
-                 nsmall=[64, 80, 98], nibble=[14, 20, 30, 40, 50, 65], aedw=[4, 7], chasew=[8, 16]),
+    "fp32": dict(nw=[24, 32, 40, 48, 64, 80, 96, 128], nb=[8, 12, 16, 20, 24, 32, 40, 44], adv=[24, 32, 40, 48, 64],
+                 nsmall=[64, 96, 128, 140], nibble=[14, 20, 30, 40, 50, 65], aedw=[4, 7], chasew=[8, 16],
+                 chains=[1, 2, 3, 4]),
+    "fp64": dict(nw=[24, 32, 40, 48, 64, 80, 96], nb=[8, 12, 16, 20, 24, 32], adv=[24, 32, 40, 48],
+                 nsmall=[64, 80, 98], nibble=[14, 20, 30, 40, 50, 65], aedw=[4, 7], chasew=[8, 16],
+                 chains=[1, 2, 3, 4]),
 }
-ORDER = ["aedw", "chasew", "nw", "nb", "adv", "nsmall", "nibble"]
-KEYS = ["nsmall", "nw", "nb", "adv", "nibble", "aedw", "chasew"]
+ORDER = ["chains", "aedw", "chasew", "nw", "nb", "adv", "nsmall", "nibble"]
+KEYS = ["nsmall", "nw", "nb", "adv", "nibble", "aedw", "chasew", "chains"]
 
 
 def get(prec):
-    v = (ctypes.c_int * 7)()
+    v = (ctypes.c_int * 8)()
     _check(lib().sylv_schur_tune_get(PREC[prec], v), "sylv_schur_tune_get")
     return dict(zip(KEYS, list(v)))
 
 
 def set_(prec, t):
     return lib().sylv_schur_tune(PREC[prec], t["nsmall"], t["nw"], t["nb"], t["adv"], t["nibble"], t["aedw"],
-                                 t["chasew"])
+                                 t["chasew"], t["chains"])
 
 
 def _matrix(n, seed):

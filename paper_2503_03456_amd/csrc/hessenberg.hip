@@ -22,7 +22,7 @@
 namespace sylv {
 
 constexpr int HNT = 1024;
-constexpr int HKS = 16;   // most contraction slices of a split panel product
+constexpr int HKS = 16;   // most contraction slices of a split panel product (k_hess_tsum holds 16)
 
 template <typename T>
 SYLV_DEVINL T block_sum(T v, T *red) {
@@ -474,38 +474,38 @@ __global__ __launch_bounds__(256) void k_hess_gemv(int n, const T *A, int lda, c
 
 // W2 = op(T) * sum_{z < nz} P_z for a panel: P_z (nbp x nt, ld nbp) are the
 // split-K slices of V^T M, T (nbp x nbp, ld ldt) the panel's triangular
-// factor, op(T) = T^T when trans.  One workgroup per 64 columns: the slice
-// sums go to LDS in a fixed order, then each thread forms 8 outputs.
+// factor, op(T) = T^T when trans.  One workgroup per 8 columns, one thread
+// per entry: its nz slice values are loaded together and summed in slice
+// order into LDS, then each thread forms its entry of op(T) S.
 template <typename T>
 __global__ __launch_bounds__(256) void k_hess_tsum(int nbp, int nt, int nz, const T *__restrict__ P,
                                                   const T *__restrict__ Tp, int ldt, int trans, T *__restrict__ W2) {
-    __shared__ T S[32][65];
+    __shared__ T S[8][33];
     __shared__ T Ts[32][33];
-    const int tid = threadIdx.x, j0 = blockIdx.x * 64;
+    const int tid = threadIdx.x, i = tid & 31, jj = tid >> 5, j = blockIdx.x * 8 + jj;
     for (int e = tid; e < 32 * 32; e += 256) {
-        const int i = e & 31, l = e >> 5;
+        const int r = e & 31, l = e >> 5;
         T v = T(0);
-        if (i < nbp && l < nbp) v = trans ? Tp[(size_t)i * ldt + l] : Tp[(size_t)l * ldt + i];
-        Ts[i][l] = v;
+        if (r < nbp && l < nbp) v = trans ? Tp[(size_t)r * ldt + l] : Tp[(size_t)l * ldt + r];
+        Ts[r][l] = v;
     }
     const size_t slice = (size_t)nbp * nt;
-    for (int e = tid; e < 32 * 64; e += 256) {
-        const int i = e & 31, jj = e >> 5, j = j0 + jj;
-        T v = T(0);
-        if (i < nbp && j < nt) {
-            const T *p = P + (size_t)j * nbp + i;
-            for (int z = 0; z < nz; ++z) v += p[z * slice];
-        }
-        S[i][jj] = v;
-    }
+    const bool in = i < nbp && j < nt;
+    // clamped address, masked value: every load is issued unconditionally
+    const T *p = P + (size_t)(j < nt ? j : nt - 1) * nbp + (i < nbp ? i : nbp - 1);
+    T v[16];
+#pragma unroll
+    for (int z = 0; z < 16; ++z) v[z] = p[(z < nz ? z : nz - 1) * slice];
+    T sum = T(0);
+#pragma unroll
+    for (int z = 0; z < 16; ++z)
+        if (z < nz) sum += v[z];
+    S[jj][i] = in ? sum : T(0);
     __syncthreads();
-    for (int e = tid; e < 32 * 64; e += 256) {
-        const int i = e & 31, jj = e >> 5, j = j0 + jj;
-        if (i < nbp && j < nt) {
-            T acc = T(0);
-            for (int l = 0; l < nbp; ++l) acc += Ts[i][l] * S[l][jj];
-            W2[(size_t)j * nbp + i] = acc;
-        }
+    if (in) {
+        T acc = T(0);
+        for (int l = 0; l < nbp; ++l) acc += Ts[i][l] * S[jj][l];
+        W2[(size_t)j * nbp + i] = acc;
     }
 }
 
@@ -519,7 +519,8 @@ static void panel_vtm(hipStream_t s, int nbp, int nt, int mr, const T *Vp, int l
     if (!bf16 && nbp <= 32 && tiles < 128) {
         const int ks = std::min(HKS, std::max(1, 512 / tiles));
         const int nz = gemm_splitk<T>(s, 1, 0, nbp, nt, mr, Vp, ldv, M, ldm, Pk, ks);
-        hipLaunchKernelGGL((k_hess_tsum<T>), dim3(tiles), dim3(256), 0, s, nbp, nt, nz, Pk, Tp, ldt, trans, W2);
+        hipLaunchKernelGGL((k_hess_tsum<T>), dim3((nt + 7) / 8), dim3(256), 0, s, nbp, nt, nz, Pk, Tp, ldt, trans,
+                           W2);
         return;
     }
     gemm<T, T, T, T>(s, 1, 0, nbp, nt, mr, T(1), Vp, ldv, M, ldm, T(0), W, nbp, T(1), bf16);

@@ -27,6 +27,7 @@
 #include "kernels.hpp"
 #include "prof.hpp"
 
+#include <algorithm>
 #include <mutex>
 
 namespace sylv {
@@ -630,16 +631,22 @@ template size_t aed_smem<double>(int);
 
 // ------------------------------------------------------------- k_chase
 // One phase of a multishift sweep over the active block [ktop, kbot].
-// Bulge b (0-based, b = 0 introduced first) sits at position p = t - 3b at
-// time t (its reflector acts on rows/cols ktop+p .. ktop+p+2; p = 0 is the
-// introduction, p = N-2 the 2x2 exit step, N = kbot-ktop+1).  The phase runs
-// times t0 .. t0+adv-1 inside the window [ws, ws+W) of H, which is loaded to
-// LDS; Uw (W x W, LDS) accumulates the window's orthogonal factor and is
-// written to global memory for the off-window GEMM updates.
+// Bulge b (0-based, b = 0 introduced first) of a chain sits at position
+// p = t - 3b at the chain's time t (its reflector acts on rows/cols
+// ktop+p .. ktop+p+2; p = 0 is the introduction, p = N-2 the 2x2 exit step,
+// N = kbot-ktop+1).  The phase runs times t0 .. t0+adv-1 inside the window
+// [ws, ws+W) of H, which is loaded to LDS; Uw (W x W, LDS) accumulates the
+// window's orthogonal factor and is written to global memory for the
+// off-window GEMM updates.  A sweep's bulges may form several chains, each
+// introduced one window width after the one below it (two QR steps whose
+// shift sets multiply to the sweep's shift polynomial): their windows are
+// disjoint, and workgroup g chases chain window g of the launch.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot, int ws, int W,
-                                             int t0, int adv, int nbulge, const T *trd,
-                                             T *Uw_out) {
+__global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot, ChaseSet<T> set, int adv) {
+    const ChaseWin<T> cw = set.w[blockIdx.x];
+    const int ws = cw.ws, W = cw.W, t0 = cw.t0, nbulge = cw.nbulge;
+    const T *trd = cw.trd;
+    T *Uw_out = cw.Uw;
     extern __shared__ unsigned char smem_raw[];
     const int L = W | 1;  // odd leading dimension: conflict-free row-wise access
     T *Hw = reinterpret_cast<T *>(smem_raw);
@@ -702,7 +709,7 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
     __syncthreads();
     for (int t = t0; t < t0 + adv; ++t) {
         const int buf = t & 1;
-        if (t > t0 && t % 3 == 0 && t / 3 < nbulge) {
+        if (t > t0 && t >= 0 && t % 3 == 0 && t / 3 < nbulge) {
             if (tid == 0) form(t / 3, t, buf);
             __syncthreads();
         }
@@ -811,11 +818,16 @@ size_t chase_smem(int W, int nbulge) {
 }
 
 template <typename T>
-int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W, int t0, int adv,
-                 int nbulge, const T *trd, T *Uw, int waves) {
-    size_t sm = chase_smem<T>(W, nbulge);
+int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, const ChaseSet<T> &set, int nwin, int adv,
+                 int waves) {
+    if (nwin < 1 || nwin > kChaseMaxWin) return -1;
+    size_t sm = 0;
+    for (int g = 0; g < nwin; ++g) {
+        const int nbulge = set.w[g].nbulge;
+        if (nbulge < 1 || nbulge > 64 || (64 * waves - 64) / nbulge < 1) return -1;  // one lead lane per bulge
+        sm = std::max(sm, chase_smem<T>(set.w[g].W, nbulge));
+    }
     if (sm > 160 * 1024) return -1;
-    if (nbulge > 64 || (64 * waves - 64) / nbulge < 1) return -1;  // one lead lane per bulge in wavefront 0
     static std::mutex mu;
     static size_t attr8 = 0, attr16 = 0;
     auto k8 = k_chase<T, 512>;
@@ -827,34 +839,34 @@ int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W
         // reflector to one row or column (length 3: 12 flops, length 2: 8),
         // left (window columns right of the bulge), right (window rows up to
         // the bulge) and on the window's orthogonal factor
-        const int N = kbot - ktop + 1, kb = kbot - ws;
+        const int N = kbot - ktop + 1;
         double fl = 0.0;
-        for (int t = t0; t < t0 + adv; ++t)
-            for (int b = 0; b < nbulge; ++b) {
-                int p = t - 3 * b;
-                if (p < 0 || p > N - 2) continue;
-                int q = ktop + p - ws, len = (p <= N - 3) ? 3 : 2;
-                int rmax = q + 3 < kb ? q + 3 : kb;
-                if (rmax > W - 1) rmax = W - 1;
-                fl += (len == 3 ? 12.0 : 8.0) * ((W - q) + (rmax + 1) + W);
-            }
+        for (int g = 0; g < nwin; ++g) {
+            const ChaseWin<T> &cw = set.w[g];
+            const int kb = kbot - cw.ws, W = cw.W;
+            for (int t = cw.t0; t < cw.t0 + adv; ++t)
+                for (int b = 0; b < cw.nbulge; ++b) {
+                    int p = t - 3 * b;
+                    if (p < 0 || p > N - 2) continue;
+                    int q = ktop + p - cw.ws, len = (p <= N - 3) ? 3 : 2;
+                    int rmax = q + 3 < kb ? q + 3 : kb;
+                    if (rmax > W - 1) rmax = W - 1;
+                    fl += (len == 3 ? 12.0 : 8.0) * ((W - q) + (rmax + 1) + W);
+                }
+        }
         prof_add_work(KID_CHASE, fl);
     }
     {
         ProfScope ps(KID_CHASE, s);
         if (waves == 8)
-            hipLaunchKernelGGL(k8, dim3(1), dim3(512), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge, trd,
-                               Uw);
+            hipLaunchKernelGGL(k8, dim3(nwin), dim3(512), sm, s, H, ldh, ktop, kbot, set, adv);
         else
-            hipLaunchKernelGGL(k16, dim3(1), dim3(1024), sm, s, H, ldh, ktop, kbot, ws, W, t0, adv, nbulge,
-                               trd, Uw);
+            hipLaunchKernelGGL(k16, dim3(nwin), dim3(1024), sm, s, H, ldh, ktop, kbot, set, adv);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-template int chase_launch<float>(hipStream_t, float *, int, int, int, int, int, int, int, int,
-                                 const float *, float *, int);
-template int chase_launch<double>(hipStream_t, double *, int, int, int, int, int, int, int, int,
-                                  const double *, double *, int);
+template int chase_launch<float>(hipStream_t, float *, int, int, int, const ChaseSet<float> &, int, int, int);
+template int chase_launch<double>(hipStream_t, double *, int, int, int, const ChaseSet<double> &, int, int, int);
 template size_t chase_smem<float>(int, int);
 template size_t chase_smem<double>(int, int);
 

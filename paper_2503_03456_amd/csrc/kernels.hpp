@@ -137,9 +137,25 @@ int aed_launch(hipStream_t s, int nw, T *H, int ldh, int kwtop, int spike_on, T 
                T *wi, int waves = 7);
 template <typename T>
 size_t chase_smem(int W, int nbulge);
+// One bulge-chain window of a chase phase: rows/cols [ws, ws + W) of H,
+// the chain's time t0 at the phase start (negative before its first
+// bulge enters), its bulge count and shifts (3 values per bulge), and the
+// W x W output of the window's orthogonal factor.
 template <typename T>
-int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, int ws, int W, int t0, int adv,
-                 int nbulge, const T *trd, T *Uw, int waves = 16);
+struct ChaseWin {
+    int ws, W, t0, nbulge;
+    const T *trd;
+    T *Uw;
+};
+constexpr int kChaseMaxWin = 4;
+template <typename T>
+struct ChaseSet {
+    ChaseWin<T> w[kChaseMaxWin];
+};
+// nwin disjoint windows chased side by side (one workgroup each), adv steps
+template <typename T>
+int chase_launch(hipStream_t s, T *H, int ldh, int ktop, int kbot, const ChaseSet<T> &set, int nwin, int adv,
+                 int waves = 16);
 template <typename T>
 void find_ktop(hipStream_t s, T *H, int ldh, int klo, int kbot, int *out);
 template <typename T>

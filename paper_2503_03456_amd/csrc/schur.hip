@@ -37,9 +37,10 @@ static bool g_tune_set[2] = {false, false};
 static SchurTune g_tune[2];
 static SchurTune tune_default(bool fp32) {
     // selected by paper_2503_03456_amd.autotune (n = 2048, normal recipe,
-    // seed 7), last run after the chase kernel's reflector change: Schur
-    // time 0.258 -> 0.252 s (binary32), 0.407 -> 0.396 s (binary64)
-    return fp32 ? SchurTune{64, 48, 20, 48, 40, 7, 16} : SchurTune{64, 48, 16, 48, 40, 7, 8};
+    // seed 7) after the bulge chains were added: Schur time 0.250 -> 0.217 s
+    // (binary32: 3 chains over 40 bulges, AED window 64), 0.368 -> 0.340 s
+    // (binary64: 2 chains over 24 bulges)
+    return fp32 ? SchurTune{64, 64, 40, 48, 50, 7, 8, 3} : SchurTune{64, 64, 24, 48, 40, 7, 16, 2};
 }
 template <typename T>
 SchurTune schur_tune() {
@@ -52,13 +53,15 @@ int schur_tune_set(const SchurTune &t) {
     typedef SchurCaps<T> K;
     if (t.nsmall < 16 || t.nsmall > K::NSMALL) return -1;
     if (t.nw < 8 || t.nw > K::NSMALL) return -1;
+    if (t.chains < 1 || t.chains > kChaseMaxWin) return -1;
     if (t.nb < 1 || t.nb > K::NBMAX) return -1;
-    if (t.adv < 4 || t.adv + 3 * t.nb + 1 > K::WMAX) return -1;
+    const int nbc = (t.nb + t.chains - 1) / t.chains;   // bulges of the largest chain
+    if (t.adv < 4 || t.adv + 3 * nbc + 1 > K::WMAX) return -1;
     if (t.nibble < 0 || t.nibble > 100) return -1;
     if (t.aedw != 4 && t.aedw != 7) return -1;
     if (t.chasew != 8 && t.chasew != 16) return -1;
     if (aed_smem<T>(t.nw) > 160 * 1024) return -1;
-    if (chase_smem<T>(t.adv + 3 * t.nb + 1, t.nb) > 160 * 1024) return -1;
+    if (chase_smem<T>(t.adv + 3 * nbc + 1, nbc) > 160 * 1024) return -1;
     const int f = sizeof(T) == 4 ? 1 : 0;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[f] = t;
@@ -76,7 +79,7 @@ size_t schur_work_bytes(int n) {
     const int wmax = K::WMAX;
     const int wide = std::max(wmax, K::NSMALL);
     size_t e = hessenberg_work_elems<T>(n, K::HNB, K::HS) + (size_t)K::NSMALL * K::NSMALL +
-               (size_t)wmax * wmax + (size_t)wide * n + 3 * K::NBMAX + 64;
+               (size_t)kChaseMaxWin * wmax * wmax + (size_t)wide * n + 3 * K::NBMAX + 64;
     return e * sizeof(T) + 1024;
 }
 template size_t schur_work_bytes<float>(int);
@@ -106,7 +109,7 @@ void carve(Ctx<T> &c, char *ws) {
     T *p = reinterpret_cast<T *>(ws);
     c.hw = p; p += hessenberg_work_elems<T>(n, K::HNB, K::HS);
     c.Zw = p; p += (size_t)K::NSMALL * K::NSMALL;
-    c.Uw = p; p += (size_t)wmax * wmax;
+    c.Uw = p; p += (size_t)kChaseMaxWin * wmax * wmax;
     c.tmp = p; p += (size_t)wide * n;
     c.trd = p; p += 3 * K::NBMAX + 64;
 }
@@ -143,10 +146,36 @@ struct WinLds {
     static constexpr size_t bytes = sizeof(T) * ((size_t)SZ + (size_t)WP * LDZ);
 };
 
+// Window transforms of one launch: window g (rows/cols [w0[g], w0[g] + w[g]),
+// factor Z[g]) has nl[g] left strips, nr[g] strips of H rows above it and
+// nu[g] strips of U rows.  mode 0: every part of every window; mode 1: the
+// left and U parts; mode 2: the right parts.  (Windows on disjoint rows and
+// columns conflict only in H(window g', window g) for g' above g, which
+// takes Z_g'^T from the left and Z_g from the right: mode 1 then mode 2.)
 template <typename T>
-__global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, int ldu, int w0, int w,
-                                                   const T *__restrict__ Z, int nl, int nr) {
+struct WinSet {
+    int w0[kChaseMaxWin], w[kChaseMaxWin], nl[kChaseMaxWin], nr[kChaseMaxWin], nu[kChaseMaxWin];
+    const T *Z[kChaseMaxWin];
+    int nwin, mode;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, int ldu, WinSet<T> set) {
     typedef typename mfma16<T>::v4 v4;
+    // this workgroup's window g and part: b < nl left, then right strips of
+    // H, then strips of U (mode 1 skips the right strips, mode 2 has only them)
+    int b = blockIdx.x, g = 0;
+    for (;; ++g) {
+        const int cnt = set.mode == 0 ? set.nl[g] + set.nr[g] + set.nu[g]
+                        : set.mode == 1 ? set.nl[g] + set.nu[g] : set.nr[g];
+        if (b < cnt || g == set.nwin - 1) break;
+        b -= cnt;
+    }
+    const int w0 = set.w0[g], w = set.w[g];
+    const T *__restrict__ Z = set.Z[g];
+    int nl = set.nl[g], nr = set.nr[g];
+    if (set.mode == 1) nr = 0;                   // b >= nl: U strips
+    else if (set.mode == 2) b += nl;             // past the left range: right strip b - nl
     typedef WinLds<T> L;
     constexpr int WP = L::WP, SS = L::SS, LDK = L::LDK, LDI = L::LDI, LDZ = L::LDZ;
     constexpr int RB = SS / 16;   // 16x16 output blocks across the strip
@@ -166,7 +195,6 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
     // only outputs that are not stored.
     constexpr int UL = sizeof(T) == 4 ? 12 : 14, UZ = sizeof(T) == 4 ? 9 : 7;
     static_assert((SS * WP) % (256 * UL) == 0 && (WP * WP) % (256 * UZ) == 0, "staging trip counts");
-    int b = blockIdx.x;
     const bool left = b < nl;
     T *M;
     int ldm, r0, c0, ext;   // strip origin in M and its extent (columns for left, rows for right)
@@ -192,7 +220,7 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
     } else {
         b -= nl;
         int rows;
-        if (b < nr) { M = H; ldm = ldh; rows = w0; }
+        if (set.mode == 2 || b < nr) { M = H; ldm = ldh; rows = w0; }
         else { b -= nr; M = U; ldm = ldu; rows = n; }
         r0 = SS * b;
         c0 = w0;
@@ -287,6 +315,51 @@ bool win_lds_ready() {
     return ok;
 }
 
+// strip counts of window slot g of a launch
+template <typename T>
+void win_counts(const Ctx<T> &c, WinSet<T> &set, int g, int w0, int w, const T *Z) {
+    constexpr int SS = WinLds<T>::SS;
+    const int nc = c.n - (w0 + w);
+    set.w0[g] = w0;
+    set.w[g] = w;
+    set.Z[g] = Z;
+    set.nl[g] = nc > 0 ? (nc + SS - 1) / SS : 0;
+    set.nr[g] = (w0 + SS - 1) / SS;
+    set.nu[g] = (c.n + SS - 1) / SS;
+}
+
+template <typename T>
+void apply_window(Ctx<T> &c, int w0, int w, const T *Z);
+
+// The transforms of several disjoint chain windows: left and U parts of
+// all windows in one launch, then the right parts in a second.
+template <typename T>
+void apply_windows(Ctx<T> &c, const ChaseSet<T> &cs, int nwin) {
+    bool fused = !c.bf16 && nwin > 1 && win_lds_ready<T>();
+    for (int g = 0; g < nwin && fused; ++g) fused = cs.w[g].W <= SchurCaps<T>::WMAX;
+    if (!fused) {
+        for (int g = 0; g < nwin; ++g) apply_window(c, cs.w[g].ws, cs.w[g].W, cs.w[g].Uw);
+        return;
+    }
+    WinSet<T> set;
+    int nlu = 0, nr = 0;
+    for (int g = 0; g < nwin; ++g) {
+        win_counts(c, set, g, cs.w[g].ws, cs.w[g].W, cs.w[g].Uw);
+        nlu += set.nl[g] + set.nu[g];
+        nr += set.nr[g];
+    }
+    set.nwin = nwin;
+    ProfScope ps(KID_WIN, c.s);
+    set.mode = 1;
+    hipLaunchKernelGGL((k_win_update<T>), dim3(nlu), dim3(256), WinLds<T>::bytes, c.s, c.n, c.H, c.ldh, c.U, c.ldu,
+                       set);
+    if (nr > 0) {
+        set.mode = 2;
+        hipLaunchKernelGGL((k_win_update<T>), dim3(nr), dim3(256), WinLds<T>::bytes, c.s, c.n, c.H, c.ldh, c.U,
+                           c.ldu, set);
+    }
+}
+
 // Apply a window transform Z (w x w, ld w) acting on rows/cols [w0, w0+w):
 // H(w0:w0+w, w0+w:n) <- Z^T H(...), H(0:w0, w0:w0+w) <- H(...) Z,
 // U(:, w0:w0+w) <- U(...) Z.  Binary32/binary64: the fused in-place kernel;
@@ -296,13 +369,13 @@ void apply_window(Ctx<T> &c, int w0, int w, const T *Z) {
     const int n = c.n;
     const int nc = n - (w0 + w);
     if (!c.bf16 && w <= SchurCaps<T>::WMAX && win_lds_ready<T>()) {
-        constexpr int SS = WinLds<T>::SS;
-        const int nl = nc > 0 ? (nc + SS - 1) / SS : 0;
-        const int nr = (w0 + SS - 1) / SS;
-        const int nu = (n + SS - 1) / SS;
+        WinSet<T> set;
+        win_counts(c, set, 0, w0, w, Z);
+        set.nwin = 1;
+        set.mode = 0;
         ProfScope ps(KID_WIN, c.s);
-        hipLaunchKernelGGL((k_win_update<T>), dim3(nl + nr + nu), dim3(256), WinLds<T>::bytes, c.s, n, c.H,
-                           c.ldh, c.U, c.ldu, w0, w, Z, nl, nr);
+        hipLaunchKernelGGL((k_win_update<T>), dim3(set.nl[0] + set.nr[0] + set.nu[0]), dim3(256),
+                           WinLds<T>::bytes, c.s, n, c.H, c.ldh, c.U, c.ldu, set);
         return;
     }
     if (nc > 0) {
@@ -456,20 +529,42 @@ int schur_run(hipStream_t s, int n, T *H, int ldh, T *U, int ldu, char *ws, char
         T *htrd = reinterpret_cast<T *>(c.hbuf + HB_TRD);
         for (size_t q = 0; q < trd.size(); ++q) htrd[q] = trd[q];
         hipMemcpyAsync(c.trd, htrd, sizeof(T) * trd.size(), hipMemcpyHostToDevice, s);
-        // multishift sweep over [ktop, kbot]
-        const int ttot = (N2 - 2) + 3 * (nb - 1) + 1;
+        // multishift sweep over [ktop, kbot]: the nb bulges form G chains
+        // (the first chain, introduced first, carries the first shifts);
+        // chain g enters D[g] steps after the sweep starts, one window width
+        // of the chain below it later, so the chains' windows never overlap
+        const int G = std::max(1, std::min(P.chains, nb));
+        int cnb[kChaseMaxWin], cfb[kChaseMaxWin], D[kChaseMaxWin];
+        for (int g = 0, f = 0; g < G; ++g) {
+            cnb[g] = nb / G + (g < nb % G ? 1 : 0);
+            cfb[g] = f;
+            f += cnb[g];
+            D[g] = g == 0 ? 0 : D[g - 1] + P.adv + 3 * cnb[g - 1] + 1;
+        }
+        const int ttot = D[G - 1] + (N2 - 2) + 3 * (cnb[G - 1] - 1) + 1;
         ++st_sweeps;
+        const size_t wsq = (size_t)K::WMAX * K::WMAX;
         for (int t0 = 0; t0 < ttot; t0 += P.adv) {
             const int t1 = std::min(t0 + P.adv, ttot);
-            const int pmin = std::max(0, t0 - 3 * (nb - 1));
-            const int pmax = std::min(N2 - 2, t1 - 1);
-            if (pmax < pmin) continue;
-            const int ws_ = ktop + std::max(0, pmin - 1);
-            const int we_ = ktop + std::min(N2, pmax + 4);
-            const int W = we_ - ws_;
-            if (chase_launch<T>(s, H, ldh, ktop, kbot, ws_, W, t0, t1 - t0, nb, c.trd, c.Uw, P.chasew)) return -1;
+            ChaseSet<T> set;
+            int nwin = 0;
+            for (int g = 0; g < G; ++g) {
+                const int r0 = t0 - D[g], r1 = t1 - D[g];   // chain time
+                const int pmin = std::max(0, r0 - 3 * (cnb[g] - 1));
+                const int pmax = std::min(N2 - 2, r1 - 1);
+                if (pmax < pmin) continue;
+                const int ws_ = ktop + std::max(0, pmin - 1);
+                const int we_ = ktop + std::min(N2, pmax + 4);
+                set.w[nwin] = ChaseWin<T>{ws_, we_ - ws_, r0, cnb[g], c.trd + 3 * cfb[g], c.Uw + nwin * wsq};
+                ++nwin;
+            }
+            if (nwin == 0) continue;
+            if (chase_launch<T>(s, H, ldh, ktop, kbot, set, nwin, t1 - t0, P.chasew)) return -1;
             ++st_chase;
-            apply_window(c, ws_, W, c.Uw);
+            // the windows' updates commute (disjoint rows and columns except
+            // H(window g', window g) for a window g' above g, which takes
+            // Z_g'^T from the left and Z_g from the right): one after another
+            apply_windows(c, set, nwin);
         }
         // no synchronisation here: the staged shifts are next rewritten after
         // the next find_ktop synchronisation, which follows their upload

@@ -13,9 +13,11 @@ namespace sylv {
 //           window is <= adv + 3 nb + 1 rows);
 //   nibble: skip the sweep when AED deflated more than nibble% of the window;
 //   aedw:   waves of the AED kernel (4 or 7);
-//   chasew: waves of the bulge-chase kernel (8 or 16).
+//   chasew: waves of the bulge-chase kernel (8 or 16);
+//   chains: bulge chains a sweep's bulges are split into (1..4), chased in
+//           disjoint windows by one workgroup each.
 struct SchurTune {
-    int nsmall, nw, nb, adv, nibble, aedw, chasew;
+    int nsmall, nw, nb, adv, nibble, aedw, chasew, chains;
 };
 // Compile-time bounds that size the workspace and keep every LDS window
 // within 160 KiB: two nsmall^2 matrices, a phase window of <= WMAX rows.

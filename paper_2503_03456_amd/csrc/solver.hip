@@ -1314,7 +1314,7 @@ size_t sylv_workspace_size(int m, int n, int lyap, const sylv_opts *opts) {
 }
 
 int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, int aed_waves,
-                    int chase_waves) {
+                    int chase_waves, int chains) {
     if (prec != SYLV_PREC_FP64 && prec != SYLV_PREC_FP32) return -1;
     const bool f = prec == SYLV_PREC_FP32;
     SchurTune t = f ? schur_tune<float>() : schur_tune<double>();
@@ -1325,6 +1325,7 @@ int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, i
     if (nibble >= 0) t.nibble = nibble;
     if (aed_waves > 0) t.aedw = aed_waves;
     if (chase_waves > 0) t.chasew = chase_waves;
+    if (chains > 0) t.chains = chains;
     std::lock_guard<std::mutex> lk(g_mu);
     return (f ? schur_tune_set<float>(t) : schur_tune_set<double>(t)) ? -2 : 0;
 }
@@ -1334,7 +1335,7 @@ int sylv_schur_tune_get(int prec, int *vals) {
     if (!vals) return -2;
     const SchurTune t = prec == SYLV_PREC_FP32 ? schur_tune<float>() : schur_tune<double>();
     vals[0] = t.nsmall; vals[1] = t.nw; vals[2] = t.nb; vals[3] = t.adv; vals[4] = t.nibble;
-    vals[5] = t.aedw; vals[6] = t.chasew;
+    vals[5] = t.aedw; vals[6] = t.chasew; vals[7] = t.chains;
     return 0;
 }
 

@@ -184,6 +184,46 @@ def test_schur_constructed_spectrum_700(prec):
         assert np.min(np.abs(ev - z)) <= 10 * 700 * u * nrm
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("chains,n", [(2, 700), (3, 1300), (4, 700), (4, 2100)])
+def test_schur_bulge_chains(prec, chains, n):
+    """A sweep's bulges split into 2..4 chains chased side by side in
+    disjoint windows: the Schur form stays valid and the constructed
+    spectrum is recovered (the same QR step in exact arithmetic)."""
+    from paper_2503_03456_amd import autotune
+    sy = binding()
+    say("schur chains", prec, chains, n)
+    saved = autotune.get(prec)
+    assert autotune.set_(prec, dict(saved, chains=chains)) == 0
+    try:
+        A, eig, _, _ = workloads.normal_coeff(40 + chains, n, 0.5, 5.0)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        T, Uq, st = sy.schur(dev(A, dt))
+        torch.cuda.synchronize()
+    finally:
+        assert autotune.set_(prec, saved) == 0
+    assert st == 0
+    u = U64 if prec == "fp64" else U32
+    check_schur(host(dev(A, dt)), host(T), host(Uq), u)
+    ev = oracle.quasi_eigs(host(T))
+    nrm = np.linalg.norm(A, 2)
+    for z in eig:
+        assert np.min(np.abs(ev - z)) <= 10 * n * u * nrm
+
+
+def test_schur_tune_chains_bounds():
+    """The chain count is validated (1..4) and read back."""
+    from paper_2503_03456_amd import autotune
+    binding()
+    saved = autotune.get("fp32")
+    try:
+        assert autotune.set_("fp32", dict(saved, chains=5)) != 0
+        assert autotune.set_("fp32", dict(saved, chains=3)) == 0
+        assert autotune.get("fp32")["chains"] == 3
+    finally:
+        assert autotune.set_("fp32", saved) == 0
+
+
 # ------------------------------------------------------------- residual
 @pytest.mark.parametrize("lyap", [False, True])
 def test_residual_parity(lyap):
