@@ -137,14 +137,25 @@ hipError_t sync_host(Ctx<T> &c) {
 // (dynamic shared memory: 121 KiB binary32, 131 KiB binary64, one workgroup
 // per CU); the four wavefronts then take the 16x16 output blocks in turn
 // with no further barrier.
-template <typename T>
+// largest divisor of x that is <= cap
+constexpr int div_le(int x, int cap) { return (x % cap == 0) ? cap : div_le(x, cap - 1); }
+
+// LDS geometry for windows up to WPX wide (WPX a multiple of 16): the
+// narrow form serves the chain, AED and small-block windows (<= 96),
+// the wide one the rest (<= WMAX rounded up to 16).
+template <typename T, int WPX>
 struct WinLds {
-    static constexpr int WP = ((SchurCaps<T>::WMAX + 15) / 16) * 16;
+    static constexpr int WP = WPX;
     static constexpr int SS = sizeof(T) == 4 ? 64 : 32;
     static constexpr int LDK = WP + 1, LDI = SS + 1, LDZ = WP + 1;
     static constexpr int SZ = (SS * LDK > WP * LDI) ? SS * LDK : WP * LDI;
     static constexpr size_t bytes = sizeof(T) * ((size_t)SZ + (size_t)WP * LDZ);
+    // loads in flight per thread in the strip and Z staging (exact trip counts)
+    static constexpr int UL = div_le(SS * WP / 256, 14), UZ = div_le(WP * WP / 256, 9);
 };
+template <typename T>
+constexpr int win_wide() { return ((SchurCaps<T>::WMAX + 15) / 16) * 16; }
+constexpr int kWinNarrow = 96;
 
 // Window transforms of one launch: window g (rows/cols [w0[g], w0[g] + w[g]),
 // factor Z[g]) has nl[g] left strips, nr[g] strips of H rows above it and
@@ -159,7 +170,7 @@ struct WinSet {
     int nwin, mode;
 };
 
-template <typename T>
+template <typename T, int WPX>
 __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, int ldu, WinSet<T> set) {
     typedef typename mfma16<T>::v4 v4;
     // this workgroup's window g and part: b < nl left, then right strips of
@@ -176,7 +187,7 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
     int nl = set.nl[g], nr = set.nr[g];
     if (set.mode == 1) nr = 0;                   // b >= nl: U strips
     else if (set.mode == 2) b += nl;             // past the left range: right strip b - nl
-    typedef WinLds<T> L;
+    typedef WinLds<T, WPX> L;
     constexpr int WP = L::WP, SS = L::SS, LDK = L::LDK, LDI = L::LDI, LDZ = L::LDZ;
     constexpr int RB = SS / 16;   // 16x16 output blocks across the strip
     extern __shared__ __align__(16) unsigned char win_smem[];
@@ -193,7 +204,7 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
     // and one wait per load.  Only Zs needs zeros outside w (rows k >= w, by
     // a 0/1 factor; Z is finite): with those, the strip's padding reaches
     // only outputs that are not stored.
-    constexpr int UL = sizeof(T) == 4 ? 12 : 14, UZ = sizeof(T) == 4 ? 9 : 7;
+    constexpr int UL = L::UL, UZ = L::UZ;
     static_assert((SS * WP) % (256 * UL) == 0 && (WP * WP) % (256 * UZ) == 0, "staging trip counts");
     const bool left = b < nl;
     T *M;
@@ -302,23 +313,43 @@ __global__ __launch_bounds__(256) void k_win_update(int n, T *H, int ldh, T *U, 
     }
 }
 
-// raises k_win_update's dynamic-LDS limit once per element type
+// raises k_win_update's dynamic-LDS limits once per element type
 template <typename T>
 bool win_lds_ready() {
     static std::once_flag once;
     static bool ok = false;
     std::call_once(once, [] {
-        ok = hipFuncSetAttribute((const void *)k_win_update<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)WinLds<T>::bytes) == hipSuccess;
+        ok = hipFuncSetAttribute((const void *)k_win_update<T, win_wide<T>()>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)WinLds<T, win_wide<T>()>::bytes) == hipSuccess &&
+             hipFuncSetAttribute((const void *)k_win_update<T, kWinNarrow>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)WinLds<T, kWinNarrow>::bytes) == hipSuccess;
         if (!ok) (void)hipGetLastError();
     });
     return ok;
 }
 
+// one launch of k_win_update over set: the narrow LDS form when every
+// window of the set fits it
+template <typename T>
+void win_launch(Ctx<T> &c, const WinSet<T> &set, int grid) {
+    if (grid <= 0) return;
+    int wmax = 0;
+    for (int g = 0; g < set.nwin; ++g) wmax = std::max(wmax, set.w[g]);
+    constexpr size_t nb = WinLds<T, kWinNarrow>::bytes, wb = WinLds<T, win_wide<T>()>::bytes;
+    if (wmax <= kWinNarrow)
+        hipLaunchKernelGGL((k_win_update<T, kWinNarrow>), dim3(grid), dim3(256), nb, c.s, c.n, c.H, c.ldh, c.U,
+                           c.ldu, set);
+    else
+        hipLaunchKernelGGL((k_win_update<T, win_wide<T>()>), dim3(grid), dim3(256), wb, c.s, c.n, c.H, c.ldh, c.U,
+                           c.ldu, set);
+}
+
 // strip counts of window slot g of a launch
 template <typename T>
 void win_counts(const Ctx<T> &c, WinSet<T> &set, int g, int w0, int w, const T *Z) {
-    constexpr int SS = WinLds<T>::SS;
+    constexpr int SS = WinLds<T, kWinNarrow>::SS;
     const int nc = c.n - (w0 + w);
     set.w0[g] = w0;
     set.w[g] = w;
@@ -351,13 +382,9 @@ void apply_windows(Ctx<T> &c, const ChaseSet<T> &cs, int nwin) {
     set.nwin = nwin;
     ProfScope ps(KID_WIN, c.s);
     set.mode = 1;
-    hipLaunchKernelGGL((k_win_update<T>), dim3(nlu), dim3(256), WinLds<T>::bytes, c.s, c.n, c.H, c.ldh, c.U, c.ldu,
-                       set);
-    if (nr > 0) {
-        set.mode = 2;
-        hipLaunchKernelGGL((k_win_update<T>), dim3(nr), dim3(256), WinLds<T>::bytes, c.s, c.n, c.H, c.ldh, c.U,
-                           c.ldu, set);
-    }
+    win_launch(c, set, nlu);
+    set.mode = 2;
+    win_launch(c, set, nr);
 }
 
 // Apply a window transform Z (w x w, ld w) acting on rows/cols [w0, w0+w):
@@ -374,8 +401,7 @@ void apply_window(Ctx<T> &c, int w0, int w, const T *Z) {
         set.nwin = 1;
         set.mode = 0;
         ProfScope ps(KID_WIN, c.s);
-        hipLaunchKernelGGL((k_win_update<T>), dim3(set.nl[0] + set.nr[0] + set.nu[0]), dim3(256),
-                           WinLds<T>::bytes, c.s, n, c.H, c.ldh, c.U, c.ldu, set);
+        win_launch(c, set, set.nl[0] + set.nr[0] + set.nu[0]);
         return;
     }
     if (nc > 0) {
