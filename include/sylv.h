@@ -214,7 +214,7 @@ int sylv_init(void);
  * static device array of SYLV_NOALLOC_SCRATCH_BYTES per GPU instead of a
  * `work` argument.  Requires a prior sylv_init() on the current device
  * (else SYLV_ERR_NOINIT).  Sizes whose sylv_workspace_size exceeds the
- * scratch return SYLV_ERR_SCRATCH (with the defaults: m = n up to about 490;
+ * scratch return SYLV_ERR_SCRATCH (with the defaults: m = n up to about 430;
  * Lyapunov problems call it with B = A^T).  low = SYLV_PREC_AUTO returns -11
  * (the selector's device copy of its weights is made on first use).  Every
  * call on a GPU reuses that GPU's scratch, which keeps the last call's

@@ -190,8 +190,15 @@ void cholqr2(hipStream_t s, int n, double *Q, int ldq, double *G, double *R1, in
 // trsyl.hip
 // mirror: symmetric Lyapunov (m = n, TB = P TA^T P, C persymmetric up to
 // rounding): one tile of each mirror pair is solved and stores the other
+// Pinv, pflag (binary32 only, both or neither): the block-pair inverse rows
+// and their perturbation flag from trsyl_prep for the same TA, TB and mirror
 template <typename T>
 void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, T *C, int ldc,
-           const double *maxab, int *flag, int mirror = 0);
+           const double *maxab, int *flag, int mirror = 0, const T *Pinv = nullptr, const int *pflag = nullptr);
+// Pinv (4 m n elements, 16-byte aligned) <- the rows of the inverse of every
+// block pair's embedded system, for repeated solves with the same TA, TB
+template <typename T>
+void trsyl_prep(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, const double *maxab,
+                int *pflag, T *Pinv, int mirror = 0);
 
 }  // namespace sylv

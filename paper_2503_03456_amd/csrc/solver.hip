@@ -160,6 +160,8 @@ struct Stage {  // buffers of one precision's Bartels-Stewart pipeline
     char *schur_ws2;  // Schur workspace for B (the two run concurrently)
     int diag;         // symmetric coefficients: TA, TB diagonal (eigen-decompositions)
     int lsym;         // Lyapunov with symmetric C: symmetric iterate, half tri-solve
+    T *Pinv;          // binary32: block-pair inverse rows of the tri-solve (4 m n), set by mixed_forms
+    int *pflag;       // their pivot-perturbation flag
 };
 
 // Alg. 4.1 buffers (binary64): orthonormalised factors, the triangular-basis
@@ -224,6 +226,8 @@ static void plan(Arena &a, int m, int n, bool lyap, bool need_lo, bool need_hi, 
         p.lo.W1 = a.take<float>((size_t)m * n);
         p.lo.Y = a.take<float>((size_t)m * n);
         if (lyap) p.lo.W2 = a.take<float>((size_t)m * n);
+        p.lo.Pinv = a.take<float>((size_t)4 * m * n);
+        p.lo.pflag = a.take<int>(64);
         p.lo.schur_ws = a.take<char>(std::max(schur_work_bytes<float>(m), sym_eig_work_bytes<float>(m)));
         if (!lyap)
             p.lo.schur_ws2 = a.take<char>(std::max(schur_work_bytes<float>(n), sym_eig_work_bytes<float>(n)));
@@ -435,7 +439,7 @@ void correction<float>(hipStream_t s, int m, int n, Stage<float> &st, const doub
         gemm<float, float, float, float>(s, 0, 0, m, n, n, 1.0, st.W1, m, st.UB, n, 0.0f, st.Y, m, 1.0f, nf);
     }
     if (st.diag) diag_solve<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag);
-    else trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag, st.lsym);
+    else trsyl<float>(s, m, n, st.TA, m, st.TB, n, st.Y, m, maxab, flag, st.lsym, st.Pinv, st.pflag);
     double ys = 1.0;
     if (nf == 2 && yscr && nscr && hbuf) {
         matnorm<float>(s, m, n, st.Y, m, yscr, nscr, 1);
@@ -690,6 +694,9 @@ static int mixed_forms(hipStream_t s, DevCtx *c, int m, int n, const double *A, 
     matnorm<float>(s, n, n, p.lo.TB, n, p.scal + 11, p.nscr, 1);
     matnorm<double>(s, 2, 1, p.scal + 10, 2, p.scal + 12, p.nscr, 1);
     sep_estimate<float>(s, m, n, p.lo.TA, p.lo.TB, p.eig, p.scal + 13, p.nscr);
+    // every binary32 tri-solve with these forms reuses the block-pair inverses
+    if (!p.lo.diag && p.lo.Pinv)
+        trsyl_prep<float>(s, m, n, p.lo.TA, m, p.lo.TB, n, p.scal + 12, p.lo.pflag, p.lo.Pinv, p.lo.lsym);
     return 0;
 }
 
@@ -984,7 +991,7 @@ static int run_alg41(hipStream_t s, DevCtx *c, int m, int n, const double *A, in
     // Y0: low-precision solve of T_A Y + Y T_B = F
     hipMemsetAsync(p.flag, 0, sizeof(int), s);
     cast<double, float>(s, m, n, q.F, m, p.lo.Y, m, 1.0);
-    trsyl<float>(s, m, n, p.lo.TA, m, p.lo.TB, n, p.lo.Y, m, p.scal + 12, p.flag);
+    trsyl<float>(s, m, n, p.lo.TA, m, p.lo.TB, n, p.lo.Y, m, p.scal + 12, p.flag, 0, p.lo.Pinv, p.lo.pflag);
     cast<float, double>(s, m, n, p.lo.Y, m, q.Y, m, 1.0f);
     // Alg. 3.1 in the triangular basis
     double hsep[2];
@@ -1621,8 +1628,10 @@ int sylv_trsyl(int m, int n, const void *TA, int ldta, const void *TB, int ldtb,
     hipStream_t s = (hipStream_t)stream;
     const bool f = prec == SYLV_PREC_FP32;
     const size_t es = f ? sizeof(float) : sizeof(double);
-    // scratch: reversed TB (trans_b), reversed C, scalars
-    size_t bytes = (size_t)n * n * es + (size_t)m * n * es + 8192;
+    // scratch: reversed TB (trans_b), reversed C, scalars, and in binary32
+    // the block-pair inverse rows (4 m n)
+    const size_t pinv_bytes = f ? (((size_t)4 * m * n * sizeof(float) + 255) & ~(size_t)255) : 0;
+    size_t bytes = (size_t)n * n * es + (size_t)m * n * es + 8192 + pinv_bytes + 512;
     void *base;
     rc = ensure_work(c, bytes, &base);
     if (rc) return rc;
@@ -1631,17 +1640,22 @@ int sylv_trsyl(int m, int n, const void *TA, int ldta, const void *TB, int ldtb,
     double *scal = (double *)(Cr + (((size_t)m * n * es + 255) & ~(size_t)255));
     double *nscr = scal + 8;
     int *flag = (int *)(nscr + 256);
+    int *pflag = flag + 16;
+    float *Pinv = f ? (float *)((char *)scal + 8192) : nullptr;
     hipMemsetAsync(flag, 0, sizeof(int), s);
     if (f) {
         const float *ta = (const float *)TA, *tb = (const float *)TB;
         matnorm<float>(s, m, m, ta, ldta, scal + 0, nscr, 1);
         matnorm<float>(s, n, n, tb, ldtb, scal + 1, nscr, 1);
         matnorm<double>(s, 2, 1, scal, 2, scal + 2, nscr, 1);
-        if (!trans_b) trsyl<float>(s, m, n, ta, ldta, tb, ldtb, (float *)Cp, ldc, scal + 2, flag);
-        else {
+        if (!trans_b) {
+            trsyl_prep<float>(s, m, n, ta, ldta, tb, ldtb, scal + 2, pflag, Pinv);
+            trsyl<float>(s, m, n, ta, ldta, tb, ldtb, (float *)Cp, ldc, scal + 2, flag, 0, Pinv, pflag);
+        } else {
             transpose<float>(s, n, n, tb, ldtb, (float *)TBr, n, 1);
             revcols<float, float>(s, m, n, (const float *)Cp, ldc, (float *)Cr, m, 1.0f);
-            trsyl<float>(s, m, n, ta, ldta, (const float *)TBr, n, (float *)Cr, m, scal + 2, flag);
+            trsyl_prep<float>(s, m, n, ta, ldta, (const float *)TBr, n, scal + 2, pflag, Pinv);
+            trsyl<float>(s, m, n, ta, ldta, (const float *)TBr, n, (float *)Cr, m, scal + 2, flag, 0, Pinv, pflag);
             revcols<float, float>(s, m, n, (const float *)Cr, m, (float *)Cp, ldc, 1.0f);
         }
     } else {

@@ -122,6 +122,75 @@ SYLV_DEVINL int pair_solve(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T 
     return flag;
 }
 
+// Inverse of the embedded 4 x 4 block-pair matrix of pair_solve (same
+// pivoting and s_min rule): Minv[k][l], rows and columns in the unknown order
+// (y00, y10, y01, y11).  The embedding keeps real and dummy unknowns
+// uncoupled, so the real rows of Minv vanish in the dummy columns.
+template <typename T>
+SYLV_DEVINL int pair_inverse(bool P, bool Q, T a00, T a01, T a10, T a11, T b00, T b01, T b10, T b11,
+                             T Minv[4][4], T smin) {
+    T m[4][4], r[4][4];
+    const T zp = P ? T(1) : T(0), zq = Q ? T(1) : T(0), zpq = zp * zq;
+    m[0][0] = a00 + b00;       m[0][1] = a01 * zp;        m[0][2] = b10 * zq;        m[0][3] = T(0);
+    m[1][0] = a10 * zp;        m[1][1] = P ? a11 + b00 : T(1); m[1][2] = T(0);      m[1][3] = b10 * zpq;
+    m[2][0] = b01 * zq;        m[2][1] = T(0);            m[2][2] = Q ? a00 + b11 : T(1); m[2][3] = a01 * zpq;
+    m[3][0] = T(0);            m[3][1] = b01 * zpq;       m[3][2] = a10 * zpq;       m[3][3] = (P && Q) ? a11 + b11 : T(1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[i][k] = (i == k) ? T(1) : T(0);
+    int flag = 0;
+    T inv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int pr = c;
+        T pv = fabs(m[c][c]);
+#pragma unroll
+        for (int rr = c + 1; rr < 4; ++rr) {
+            T v = fabs(m[rr][c]);
+            if (v > pv) { pv = v; pr = rr; }
+        }
+#pragma unroll
+        for (int rr = c + 1; rr < 4; ++rr) {
+            const bool sw = (pr == rr);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                T x = m[c][k], y = m[rr][k];
+                m[c][k] = sw ? y : x;
+                m[rr][k] = sw ? x : y;
+                T u = r[c][k], v = r[rr][k];
+                r[c][k] = sw ? v : u;
+                r[rr][k] = sw ? u : v;
+            }
+        }
+        T piv = m[c][c];
+        if (fabs(piv) < smin) {
+            piv = (piv >= T(0)) ? smin : -smin;
+            m[c][c] = piv;
+            flag = 1;
+        }
+        inv[c] = T(1) / piv;
+#pragma unroll
+        for (int rr = c + 1; rr < 4; ++rr) {
+            const T f = m[rr][c] * inv[c];
+#pragma unroll
+            for (int k = c + 1; k < 4; ++k) m[rr][k] -= f * m[c][k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r[rr][k] -= f * r[c][k];
+        }
+    }
+#pragma unroll
+    for (int col = 0; col < 4; ++col)
+#pragma unroll
+        for (int c = 3; c >= 0; --c) {
+            T acc = r[c][col];
+#pragma unroll
+            for (int k = c + 1; k < 4; ++k) acc -= m[c][k] * Minv[k][col];
+            Minv[c][col] = acc * inv[c];
+        }
+    return flag;
+}
+
 // acc += A B on MFMA for one output tile (p x q <= TS x TS): A is p x K
 // (leading dimension lda_), B is K x q (ldb_).  The four wavefronts take a
 // 2 x 2 grid of 32 x 32 output blocks; stA / stB are the LDS slabs.  All
@@ -188,13 +257,19 @@ SYLV_DEVINL void tile_gemm(typename mfma16t<T>::v4 (&acc)[2][2], const T *Ap, in
 // the batched form; the single-equation form runs the same count: 1024
 // threads, which spread each block pair's sums over more lanes, left the
 // binary32 tile time unchanged and slowed the binary64 one).
-template <typename T, int NT = 256>
+// PRE: Pinv holds, for every element (i, j) of Y (at 4 ((size_t) j m + i)),
+// the row of the inverse block-pair matrix for its unknown (k_trsyl_prep);
+// the tile stages its part in LDS and each block pair's solve becomes a
+// 4 x 4 matrix-vector product.
+template <typename T, int NT = 256, bool PRE = false>
 SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, const T *__restrict__ TB,
                             int ldtb, T *C, int ldc, int I, int J, double maxab, int *flag, int mirror = 0,
-                            int wmirror = 0, bool lazy = true) {
+                            int wmirror = 0, bool lazy = true, const T *__restrict__ Pinv = nullptr) {
     __shared__ T sA[TS * TLD];   // TA diagonal tile, later reused
     __shared__ T sB[TS * TLD];   // TB diagonal tile
     __shared__ T sC[TS * TLD];   // rhs -> Y tile
+    typedef T t4 __attribute__((ext_vector_type(4)));
+    __shared__ t4 sI[PRE ? TS * TS : 1];   // PRE: inverse rows, element (i, j) at j * TS + i
     __shared__ T stA[TBK][TS + 16];
     __shared__ T stB[TBK][TS + 16];
     __shared__ int rstart[TS + 1], cstart[TS + 1];
@@ -248,6 +323,15 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
             const int i = e % TS, j = e / TS;
             const int ic = i < p ? i : p - 1, jc = j < q ? j : q - 1;
             sC[j * TLD + i] = C[(size_t)(c0 + jc) * ldc + r0 + ic] * T((i < p && j < q) ? 1 : 0);
+        }
+    }
+    if constexpr (PRE) {
+        // the tile's inverse rows: 16-byte loads, consecutive threads down a column
+#pragma unroll 4
+        for (int e = t; e < TS * TS; e += NT) {
+            const int i = e % TS, j = e / TS;
+            const int ic = i < p ? i : p - 1, jc = j < q ? j : q - 1;
+            sI[j * TS + i] = *reinterpret_cast<const t4 *>(Pinv + 4 * ((size_t)(c0 + jc) * m + r0 + ic));
         }
     }
 #pragma unroll 8
@@ -323,7 +407,24 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
 #pragma unroll
             for (int z = 0; z < 4; ++z) part[z] += __shfl_xor(part[z], o);
         }
-        if (active && sub == 0) {
+        if (PRE && active && sub == 0) {
+            // y = Minv r with the staged rows of the pair's unknowns
+            const bool P2 = (pi == 2), Q2 = (qj == 2);
+            T r[4];
+            r[0] = sC[cj * TLD + ri] - part[0];
+            r[1] = P2 ? sC[cj * TLD + ri + 1] - part[1] : T(0);
+            r[2] = Q2 ? sC[(cj + 1) * TLD + ri] - part[2] : T(0);
+            r[3] = (P2 && Q2) ? sC[(cj + 1) * TLD + ri + 1] - part[3] : T(0);
+            const t4 m0 = sI[cj * TS + ri];
+            const t4 m1 = sI[cj * TS + ri + (P2 ? 1 : 0)];
+            const t4 m2 = sI[(cj + (Q2 ? 1 : 0)) * TS + ri];
+            const t4 m3 = sI[(cj + (Q2 ? 1 : 0)) * TS + ri + (P2 ? 1 : 0)];
+            sC[cj * TLD + ri] = m0[0] * r[0] + m0[1] * r[1] + m0[2] * r[2] + m0[3] * r[3];
+            if (P2) sC[cj * TLD + ri + 1] = m1[0] * r[0] + m1[1] * r[1] + m1[2] * r[2] + m1[3] * r[3];
+            if (Q2) sC[(cj + 1) * TLD + ri] = m2[0] * r[0] + m2[1] * r[1] + m2[2] * r[2] + m2[3] * r[3];
+            if (P2 && Q2)
+                sC[(cj + 1) * TLD + ri + 1] = m3[0] * r[0] + m3[1] * r[1] + m3[2] * r[2] + m3[3] * r[3];
+        } else if (active && sub == 0) {
             // every block pair through the 4 x 4 embedding (order-1 blocks
             // as identity rows): one code path for all shapes
             const bool P2 = (pi == 2), Q2 = (qj == 2);
@@ -363,15 +464,84 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
 
 // mirror: symmetric Lyapunov (see trsyl_tile); the grid then covers only
 // the tiles with 2J <= d
-template <typename T>
+template <typename T, bool PRE>
 __global__ __launch_bounds__(TRSYL_NT) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
                                                    const T *__restrict__ TB, int ldtb, T *C, int ldc,
                                                    int d, int nI, int jmin, const double *maxab,
-                                                   int *flag, int mirror) {
+                                                   int *flag, int mirror, const T *__restrict__ Pinv,
+                                                   const int *pflag) {
     const int J = jmin + blockIdx.x;
     const int I = nI - 1 - (d - J);
-    trsyl_tile<T, TRSYL_NT>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror, mirror && 2 * J < d,
-                            false);
+    trsyl_tile<T, TRSYL_NT, PRE>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror,
+                                 mirror && 2 * J < d, false, Pinv);
+    // the pivots perturbed when the inverses were formed count for every solve
+    if (PRE && d == 0 && threadIdx.x == 0 && *pflag) atomicOr(flag, 1);
+}
+
+// Inverse rows of every block pair (one workgroup per tile, the tile's own
+// block partition as trsyl_tile scans it): for the pair at (ri, cj) of tile
+// (I, J), row k of its inverse embedded matrix goes to the element of
+// unknown k, Pinv[4 ((size_t) j m + i) + l].  *pflag = 1 when a pivot below
+// s_min was replaced.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsyl_prep(int m, int n, const T *__restrict__ TA, int ldta,
+                                                    const T *__restrict__ TB, int ldtb, const double *maxab,
+                                                    int *pflag, T *Pinv, int mirror) {
+    __shared__ int rstart[TS + 1], cstart[TS + 1];
+    __shared__ int nrb_s, ncb_s;
+    const int I = blockIdx.y, J = blockIdx.x;
+    const int r0 = tile_bound(TA, ldta, m, I), r1 = tile_bound(TA, ldta, m, I + 1);
+    int c0, c1;
+    if (mirror) {
+        const int nt = (m + TBASE - 1) / TBASE;
+        c0 = n - tile_bound(TA, ldta, m, nt - J);
+        c1 = n - tile_bound(TA, ldta, m, nt - 1 - J);
+    } else {
+        c0 = tile_bound(TB, ldtb, n, J);
+        c1 = tile_bound(TB, ldtb, n, J + 1);
+    }
+    const int p = r1 - r0, q = c1 - c0;
+    if (p <= 0 || q <= 0) return;
+    if (threadIdx.x == 0) {
+        int nb = 0, i = 0;
+        while (i < p) { rstart[nb++] = i; i += (i + 1 < p && CM(TA, r0 + i + 1, r0 + i, ldta) != T(0)) ? 2 : 1; }
+        rstart[nb] = p;
+        nrb_s = nb;
+        nb = 0; i = 0;
+        while (i < q) { cstart[nb++] = i; i += (i + 1 < q && CM(TB, c0 + i + 1, c0 + i, ldtb) != T(0)) ? 2 : 1; }
+        cstart[nb] = q;
+        ncb_s = nb;
+    }
+    __syncthreads();
+    const int P = nrb_s, Q = ncb_s;
+    const T smin = (T)fmax((double)num<T>::ulp * *maxab, (double)num<T>::safmin);
+    int myflag = 0;
+    for (int u = threadIdx.x; u < P * Q; u += 256) {
+        const int ib = u % P, jb = u / P;
+        const int ri = r0 + rstart[ib], pi = rstart[ib + 1] - rstart[ib];
+        const int cj = c0 + cstart[jb], qj = cstart[jb + 1] - cstart[jb];
+        const bool P2 = pi == 2, Q2 = qj == 2;
+        const T a00 = CM(TA, ri, ri, ldta);
+        const T a01 = P2 ? CM(TA, ri, ri + 1, ldta) : T(0);
+        const T a10 = P2 ? CM(TA, ri + 1, ri, ldta) : T(0);
+        const T a11 = P2 ? CM(TA, ri + 1, ri + 1, ldta) : T(0);
+        const T b00 = CM(TB, cj, cj, ldtb);
+        const T b01 = Q2 ? CM(TB, cj, cj + 1, ldtb) : T(0);
+        const T b10 = Q2 ? CM(TB, cj + 1, cj, ldtb) : T(0);
+        const T b11 = Q2 ? CM(TB, cj + 1, cj + 1, ldtb) : T(0);
+        T Mi[4][4];
+        myflag |= pair_inverse<T>(P2, Q2, a00, a01, a10, a11, b00, b01, b10, b11, Mi, smin);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool valid = (k == 0) || (k == 1 && P2) || (k == 2 && Q2) || (k == 3 && P2 && Q2);
+            if (valid) {
+                T *dst = Pinv + 4 * ((size_t)(cj + (k >> 1)) * m + ri + (k & 1));
+#pragma unroll
+                for (int l = 0; l < 4; ++l) dst[l] = Mi[k][l];
+            }
+        }
+    }
+    if (myflag) atomicOr(pflag, 1);
 }
 
 // Right-looking updates after anti-diagonal d is solved: every tile (I, J)
@@ -466,8 +636,21 @@ void trsyl_batched(hipStream_t s, BatchEq *eqs, const int *order, int batch, int
 }
 
 template <typename T>
+void trsyl_prep(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, const double *maxab,
+                int *pflag, T *Pinv, int mirror) {
+    if (m <= 0 || n <= 0) return;
+    if (m != n) mirror = 0;
+    const int nI = (m + TBASE - 1) / TBASE, nJ = (n + TBASE - 1) / TBASE;
+    hipMemsetAsync(pflag, 0, sizeof(int), s);
+    hipLaunchKernelGGL((k_trsyl_prep<T>), dim3(nJ, nI), dim3(256), 0, s, m, n, TA, ldta, TB, ldtb, maxab, pflag,
+                       Pinv, mirror);
+}
+template void trsyl_prep<float>(hipStream_t, int, int, const float *, int, const float *, int, const double *,
+                                int *, float *, int);
+
+template <typename T>
 void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int ldtb, T *C, int ldc,
-           const double *maxab, int *flag, int mirror) {
+           const double *maxab, int *flag, int mirror, const T *Pinv, const int *pflag) {
     if (m <= 0 || n <= 0) return;
     if (m != n) mirror = 0;
     const int nI = (m + TBASE - 1) / TBASE, nJ = (n + TBASE - 1) / TBASE;
@@ -476,16 +659,25 @@ void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int 
         int jmax = d < nJ - 1 ? d : nJ - 1;
         if (mirror && jmax > d / 2) jmax = d / 2;
         ProfScope ps(KID_TRSYL, s);
-        hipLaunchKernelGGL((k_trsyl_diag<T>), dim3(jmax - jmin + 1), dim3(TRSYL_NT), 0, s, m, n, TA, ldta,
-                           TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror);
+        bool pre = false;
+        if constexpr (sizeof(T) == 4) {   // the staged inverse rows fit LDS in binary32 only
+            if (Pinv && pflag) {
+                hipLaunchKernelGGL((k_trsyl_diag<T, true>), dim3(jmax - jmin + 1), dim3(TRSYL_NT), 0, s, m, n,
+                                   TA, ldta, TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror, Pinv, pflag);
+                pre = true;
+            }
+        }
+        if (!pre)
+            hipLaunchKernelGGL((k_trsyl_diag<T, false>), dim3(jmax - jmin + 1), dim3(TRSYL_NT), 0, s, m, n, TA,
+                               ldta, TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror, Pinv, pflag);
         if (d < nI + nJ - 2)
             hipLaunchKernelGGL((k_trsyl_update<T>), dim3(nJ, nI), dim3(256), 0, s, m, n, TA, ldta, TB, ldtb, C,
                                ldc, d, nI, nJ, mirror);
     }
 }
 template void trsyl<float>(hipStream_t, int, int, const float *, int, const float *, int, float *, int,
-                           const double *, int *, int);
+                           const double *, int *, int, const float *, const int *);
 template void trsyl<double>(hipStream_t, int, int, const double *, int, const double *, int, double *,
-                            int, const double *, int *, int);
+                            int, const double *, int *, int, const double *, const int *);
 
 }  // namespace sylv
