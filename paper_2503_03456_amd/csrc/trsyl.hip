@@ -40,7 +40,9 @@ constexpr int TS = 64;       // tile capacity
 constexpr int TBASE = 63;    // nominal boundary spacing (adjusted by +1 at 2x2 blocks)
 constexpr int TLD = TS + 1;  // LDS leading dimension of tiles
 constexpr int TBK = 32;      // K slab of the in-tile MFMA update
-constexpr int TRSYL_NT = 256;   // threads of a single-equation tile workgroup (1024 measured no faster)
+// threads of a single-equation tile workgroup: 512 with the staged inverses
+// (binary32), 256 with the in-place eliminations (measured best of 256/512/1024)
+constexpr int TRSYL_NT_PRE = 512, TRSYL_NT = 256;
 
 // Boundary k of a quasi-triangular matrix of order n cut every TBASE rows.
 template <typename T>
@@ -368,8 +370,8 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
         const int nunits = jhi - jlo + 1;
         // lanes per unit: the largest power of two <= 64 with tpu * nunits <= NT
         // (at most 64 units: a tile has at most 64 block rows and columns)
-        const int tpu = (NT == 256) ? (nunits <= 4 ? 64 : nunits <= 8 ? 32 : nunits <= 16 ? 16 : nunits <= 32 ? 8 : 4)
-                                    : (nunits <= 16 ? 64 : nunits <= 32 ? 32 : 16);
+        int tpu = 64;
+        while (tpu > 1 && tpu * nunits > NT) tpu >>= 1;
         const int u = t / tpu, sub = t % tpu;
         T part[4] = {T(0), T(0), T(0), T(0)};
         int ri = 0, pi = 0, cj = 0, qj = 0;
@@ -464,15 +466,15 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
 
 // mirror: symmetric Lyapunov (see trsyl_tile); the grid then covers only
 // the tiles with 2J <= d
-template <typename T, bool PRE>
-__global__ __launch_bounds__(TRSYL_NT) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
+template <typename T, bool PRE, int NT>
+__global__ __launch_bounds__(NT) void k_trsyl_diag(int m, int n, const T *__restrict__ TA, int ldta,
                                                    const T *__restrict__ TB, int ldtb, T *C, int ldc,
                                                    int d, int nI, int jmin, const double *maxab,
                                                    int *flag, int mirror, const T *__restrict__ Pinv,
                                                    const int *pflag) {
     const int J = jmin + blockIdx.x;
     const int I = nI - 1 - (d - J);
-    trsyl_tile<T, TRSYL_NT, PRE>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror,
+    trsyl_tile<T, NT, PRE>(m, n, TA, ldta, TB, ldtb, C, ldc, I, J, *maxab, flag, mirror,
                                  mirror && 2 * J < d, false, Pinv);
     // the pivots perturbed when the inverses were formed count for every solve
     if (PRE && d == 0 && threadIdx.x == 0 && *pflag) atomicOr(flag, 1);
@@ -662,13 +664,14 @@ void trsyl(hipStream_t s, int m, int n, const T *TA, int ldta, const T *TB, int 
         bool pre = false;
         if constexpr (sizeof(T) == 4) {   // the staged inverse rows fit LDS in binary32 only
             if (Pinv && pflag) {
-                hipLaunchKernelGGL((k_trsyl_diag<T, true>), dim3(jmax - jmin + 1), dim3(TRSYL_NT), 0, s, m, n,
-                                   TA, ldta, TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror, Pinv, pflag);
+                hipLaunchKernelGGL((k_trsyl_diag<T, true, TRSYL_NT_PRE>), dim3(jmax - jmin + 1), dim3(TRSYL_NT_PRE),
+                                   0, s, m, n, TA, ldta, TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror, Pinv,
+                                   pflag);
                 pre = true;
             }
         }
         if (!pre)
-            hipLaunchKernelGGL((k_trsyl_diag<T, false>), dim3(jmax - jmin + 1), dim3(TRSYL_NT), 0, s, m, n, TA,
+            hipLaunchKernelGGL((k_trsyl_diag<T, false, TRSYL_NT>), dim3(jmax - jmin + 1), dim3(TRSYL_NT), 0, s, m, n, TA,
                                ldta, TB, ldtb, C, ldc, d, nI, jmin, maxab, flag, mirror, Pinv, pflag);
         if (d < nI + nJ - 2)
             hipLaunchKernelGGL((k_trsyl_update<T>), dim3(nJ, nI), dim3(256), 0, s, m, n, TA, ldta, TB, ldtb, C,
