@@ -255,6 +255,17 @@ SYLV_DEVINL void wave_order() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// v of lane src (uniform) broadcast to the wavefront, through scalar registers
+SYLV_DEVINL float wave_bcast(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+SYLV_DEVINL double wave_bcast(double v, int src) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+
 template <typename T>
 SYLV_DEVINL int francis_wave(int n, T *H, int ldh, T *Z, int ldz, int nz, int *nsweep, int *nstep) {
     const int lane = threadIdx.x & 63;
@@ -342,11 +353,8 @@ SYLV_DEVINL int francis_wave(int n, T *H, int ldh, T *Z, int ldz, int nz, int *n
         for (int k = l; k <= ihi - 1; ++k) {
             const int len = (k <= ihi - 2) ? 3 : 2;
             const int k2 = (len == 3) ? k + 2 : k + 1;   // clamped third index
-            if (k > l) {
-                x = CM(H, k, k - 1, ldh);
-                y = CM(H, k + 1, k - 1, ldh);
-                z = CM(H, k2, k - 1, ldh);
-            }
+            // (x, y, z) for k > l: rows k..k2 of column k-1, broadcast from
+            // the lanes that formed them in the previous right update
             T v1, v2, tau, beta;
             reflector3(len, x, y, z, v1, v2, tau, beta);
             wave_order();
@@ -364,11 +372,20 @@ SYLV_DEVINL int francis_wave(int n, T *H, int ldh, T *Z, int ldz, int nz, int *n
             wave_order();
             // right: columns k..k2, rows 0..min(k+3, ihi)
             const int rmax = (k + 3 < ihi) ? k + 3 : ihi;
+            T col_k = T(0);   // this lane's new H(lane, k)
             if (lane <= rmax) {
                 const int i = lane;
                 T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh), a2 = CM(H, i, k2, ldh);
                 refl_apply(len, v1, v2, tau, a0, a1, a2);
                 CM(H, i, k2, ldh) = a2; CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
+                col_k = a0;
+            }
+            if (k + 1 <= ihi - 1) {
+                // next step's column: rows k+1 .. k+1+len'-1 of column k (lanes <= rmax)
+                const int kn2 = (k + 1 <= ihi - 2) ? k + 3 : k + 2;
+                x = wave_bcast(col_k, k + 1);
+                y = wave_bcast(col_k, k + 2);
+                z = wave_bcast(col_k, kn2);
             }
             if (lane < nz) {
                 const int i = lane;

@@ -36,6 +36,52 @@ template <> struct mfma16t<double> {
     static SYLV_DEVINL int orow(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
+// DPP lane move (CTRL a gfx9 DPP control: row_shr:k = 0x110 + k, row_bcast:15
+// = 0x142, row_bcast:31 = 0x143); lanes without a source read 0
+template <int CTRL>
+SYLV_DEVINL float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+SYLV_DEVINL double dpp_move(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+
+// Sums of x over aligned groups of g lanes (g a power of two <= 64, uniform):
+// the last lane of each group ends with its group's sum (other lanes hold
+// partial sums).  Doubling row shifts within rows of 16, then the row
+// broadcasts for groups of 32 and 64.
+template <typename T>
+SYLV_DEVINL void group_sum4(T (&x)[4], int g) {
+    if (g > 1) {
+#pragma unroll
+        for (int z = 0; z < 4; ++z) x[z] += dpp_move<0x111>(x[z]);
+    }
+    if (g > 2) {
+#pragma unroll
+        for (int z = 0; z < 4; ++z) x[z] += dpp_move<0x112>(x[z]);
+    }
+    if (g > 4) {
+#pragma unroll
+        for (int z = 0; z < 4; ++z) x[z] += dpp_move<0x114>(x[z]);
+    }
+    if (g > 8) {
+#pragma unroll
+        for (int z = 0; z < 4; ++z) x[z] += dpp_move<0x118>(x[z]);
+    }
+    if (g > 16) {
+#pragma unroll
+        for (int z = 0; z < 4; ++z) x[z] += dpp_move<0x142>(x[z]);
+    }
+    if (g > 32) {
+#pragma unroll
+        for (int z = 0; z < 4; ++z) x[z] += dpp_move<0x143>(x[z]);
+    }
+}
+
 constexpr int TS = 64;       // tile capacity
 constexpr int TBASE = 63;    // nominal boundary spacing (adjusted by +1 at 2x2 blocks)
 constexpr int TLD = TS + 1;  // LDS leading dimension of tiles
@@ -370,9 +416,9 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
         const int nunits = jhi - jlo + 1;
         // lanes per unit: the largest power of two <= 64 with tpu * nunits <= NT
         // (at most 64 units: a tile has at most 64 block rows and columns)
-        int tpu = 64;
-        while (tpu > 1 && tpu * nunits > NT) tpu >>= 1;
-        const int u = t / tpu, sub = t % tpu;
+        int tpu = 64, lg = 6;
+        while (tpu > 1 && tpu * nunits > NT) { tpu >>= 1; --lg; }
+        const int u = t >> lg, sub = t & (tpu - 1);
         T part[4] = {T(0), T(0), T(0), T(0)};
         int ri = 0, pi = 0, cj = 0, qj = 0;
         const bool active = u < nunits;
@@ -405,11 +451,10 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
                 part[2] += y0 * b1; part[3] += y1 * b1;
             }
         }
-        for (int o = 1; o < tpu; o <<= 1) {
-#pragma unroll
-            for (int z = 0; z < 4; ++z) part[z] += __shfl_xor(part[z], o);
-        }
-        if (PRE && active && sub == 0) {
+        // the unit's sums land in its last lane, which solves the pair
+        group_sum4<T>(part, tpu);
+        const bool solver = active && sub == tpu - 1;
+        if (PRE && solver) {
             // y = Minv r with the staged rows of the pair's unknowns
             const bool P2 = (pi == 2), Q2 = (qj == 2);
             T r[4];
@@ -426,7 +471,7 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
             if (Q2) sC[(cj + 1) * TLD + ri] = m2[0] * r[0] + m2[1] * r[1] + m2[2] * r[2] + m2[3] * r[3];
             if (P2 && Q2)
                 sC[(cj + 1) * TLD + ri + 1] = m3[0] * r[0] + m3[1] * r[1] + m3[2] * r[2] + m3[3] * r[3];
-        } else if (active && sub == 0) {
+        } else if (solver) {
             // every block pair through the 4 x 4 embedding (order-1 blocks
             // as identity rows): one code path for all shapes
             const bool P2 = (pi == 2), Q2 = (qj == 2);
