@@ -431,41 +431,51 @@ SYLV_DEVINL void trsyl_tile(int m, int n, const T *__restrict__ TA, int ldta, co
             // One loop for every block shape (an order-1 block masks its
             // second row or column), so units of different shapes sharing
             // a wavefront do not split it.
-            const bool P2 = (pi == 2), Q2 = (qj == 2);
-#pragma unroll 2
-            for (int rp = ri + pi + sub; rp < p; rp += tpu) {
-                const T a0 = sA[rp * TLD + ri];
-                const T a1 = P2 ? sA[rp * TLD + ri + 1] : T(0);
-                const T y0 = sC[cj * TLD + rp];
-                const T y1 = Q2 ? sC[(cj + 1) * TLD + rp] : T(0);
-                part[0] += a0 * y0; part[1] += a1 * y0;
-                part[2] += a0 * y1; part[3] += a1 * y1;
+            // Both sums in one loop, k < nr the rows below (u = TA(ri.., r'),
+            // w = Y(r', cj..)), then the columns to the left (u = Y(ri.., c'),
+            // w = TB(c', cj..)): part += (u0 w0, u1 w0, u0 w1, u1 w1).  The
+            // second row / column of an order-1 block is read at the first
+            // one's index and masked, so the loads carry no condition.
+            const T zp = (pi == 2) ? T(1) : T(0), zq = (qj == 2) ? T(1) : T(0);
+            const int ri1 = ri + (pi == 2 ? 1 : 0), cj1 = cj + (qj == 2 ? 1 : 0);
+            const int nr = p - ri - pi, ntot = nr + cj;
+#pragma unroll 16
+            for (int k = sub; k < ntot; k += tpu) {
+                const bool rows = k < nr;
+                const int x = rows ? ri + pi + k : k - nr;
+                const T *Ub = rows ? sA : sC;
+                const T *Wb = rows ? sC : sB;
+                const T u0 = Ub[x * TLD + ri], u1 = Ub[x * TLD + ri1] * zp;
+                const T w0 = Wb[cj * TLD + x], w1 = Wb[cj1 * TLD + x] * zq;
+                part[0] += u0 * w0; part[1] += u1 * w0;
+                part[2] += u0 * w1; part[3] += u1 * w1;
             }
-#pragma unroll 2
-            for (int cp = sub; cp < cj; cp += tpu) {
-                const T b0 = sB[cj * TLD + cp];
-                const T b1 = Q2 ? sB[(cj + 1) * TLD + cp] : T(0);
-                const T y0 = sC[cp * TLD + ri];
-                const T y1 = P2 ? sC[cp * TLD + ri + 1] : T(0);
-                part[0] += y0 * b0; part[1] += y1 * b0;
-                part[2] += y0 * b1; part[3] += y1 * b1;
-            }
+        }
+        const bool solver = active && sub == tpu - 1;
+        // the solver's right-hand side and inverse rows (written by no other
+        // unit) are loaded while the group sums run
+        T rhs[4];
+        t4 m0, m1, m2, m3;
+        if (PRE) {
+            const int ri1 = ri + (pi == 2 ? 1 : 0), cj1 = cj + (qj == 2 ? 1 : 0);
+            const T zp = (pi == 2) ? T(1) : T(0), zq = (qj == 2) ? T(1) : T(0);
+            rhs[0] = sC[cj * TLD + ri];
+            rhs[1] = sC[cj * TLD + ri1] * zp;
+            rhs[2] = sC[cj1 * TLD + ri] * zq;
+            rhs[3] = sC[cj1 * TLD + ri1] * (zp * zq);
+            m0 = sI[cj * TS + ri];
+            m1 = sI[cj * TS + ri1];
+            m2 = sI[cj1 * TS + ri];
+            m3 = sI[cj1 * TS + ri1];
         }
         // the unit's sums land in its last lane, which solves the pair
         group_sum4<T>(part, tpu);
-        const bool solver = active && sub == tpu - 1;
         if (PRE && solver) {
             // y = Minv r with the staged rows of the pair's unknowns
             const bool P2 = (pi == 2), Q2 = (qj == 2);
             T r[4];
-            r[0] = sC[cj * TLD + ri] - part[0];
-            r[1] = P2 ? sC[cj * TLD + ri + 1] - part[1] : T(0);
-            r[2] = Q2 ? sC[(cj + 1) * TLD + ri] - part[2] : T(0);
-            r[3] = (P2 && Q2) ? sC[(cj + 1) * TLD + ri + 1] - part[3] : T(0);
-            const t4 m0 = sI[cj * TS + ri];
-            const t4 m1 = sI[cj * TS + ri + (P2 ? 1 : 0)];
-            const t4 m2 = sI[(cj + (Q2 ? 1 : 0)) * TS + ri];
-            const t4 m3 = sI[(cj + (Q2 ? 1 : 0)) * TS + ri + (P2 ? 1 : 0)];
+#pragma unroll
+            for (int z = 0; z < 4; ++z) r[z] = rhs[z] - part[z];
             sC[cj * TLD + ri] = m0[0] * r[0] + m0[1] * r[1] + m0[2] * r[2] + m0[3] * r[3];
             if (P2) sC[cj * TLD + ri + 1] = m1[0] * r[0] + m1[1] * r[1] + m1[2] * r[2] + m1[3] * r[3];
             if (Q2) sC[(cj + 1) * TLD + ri] = m2[0] * r[0] + m2[1] * r[1] + m2[2] * r[2] + m2[3] * r[3];
