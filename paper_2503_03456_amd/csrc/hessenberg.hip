@@ -261,7 +261,7 @@ SYLV_DEVINL void panel_dots(int n, int r0, const T *V, int ldv, int k0, int cnt,
 template <typename T, int NQ>
 __global__ __launch_bounds__(HNT) void k_hess_col_r(int n, T *A, int lda, T *V, T *Tp, int nb, T *Y,
                                                    const T *Ypart, int S, T *tau, int k0, int i,
-                                                   int finalize_only) {
+                                                   int finalize_only, const T *wT) {
     constexpr int NWV = HNT / 64;
     __shared__ T xs[NQ * HNT];
     __shared__ T tps[32 * 32];  // panel T, column c at tps[32 c]
@@ -274,25 +274,20 @@ __global__ __launch_bounds__(HNT) void k_hess_col_r(int n, T *A, int lda, T *V, 
     const int col = k0 + i;
     const bool upd = !finalize_only;
     // stage: finished columns of T, the row V(col, k0:k0+i) (right update
-    // coefficients, zero beyond), and for i > 0 the vector v_{i-1}
+    // coefficients, zero beyond), and for i > 0 the products
+    // w = V(:, k0:k0+i-1)^T v_{i-1} that the previous column's GEMV launch
+    // formed beside its product (wT)
     for (int e = tid; e < 32 * 32; e += HNT) {
         const int c = e >> 5, r = e & 31;
         tps[e] = (c < i - 1 && r < nb) ? Tp[c * nb + r] : T(0);
     }
     if (tid < 32) cm[tid] = (upd && tid < i) ? CM(V, col, k0 + tid, ldv) : T(0);
+    if (tid < 32) wv[tid] = (tid < i - 1) ? wT[tid] : T(0);
     const int cp = k0 + i - 1;
-    if (i > 0) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int r = tid + q * HNT;
-            if (r < n) xs[r] = CM(V, r, cp, ldv);
-        }
-    }
     __syncthreads();
     T yfix = T(0);
     if (i > 0) {
-        // w = V(:, k0:k0+i-1)^T v_{i-1}; T(0:i-1, i-1) = -tau T(0:i-1, 0:i-1) w
-        panel_dots(n, cp + 1, V, ldv, k0, i - 1, xs, part, wv);
+        // T(0:i-1, i-1) = -tau T(0:i-1, 0:i-1) w
         const T tp = tau[cp];
         if (tid < 32) {
             T acc = T(0);
@@ -446,10 +441,24 @@ __global__ __launch_bounds__(HNT) void k_hess_col_r(int n, T *A, int lda, T *V, 
     if (tid == 0) tau[col] = tc;
 }
 
-// Ypart[s][r] = sum_{c in slice s} A(r, c) v(c), c in [col+1, n)
+// Ypart[s][r] = sum_{c in slice s} A(r, c) v(c), c in [col+1, n).  The
+// workgroups of row block gridDim.x - 1 instead form the next column step's
+// panel products wT[j] = sum_{r > col} V(r, k0 + j) v(r), j < col - k0 (one
+// wavefront each), so that step starts from them.
 template <typename T>
 __global__ __launch_bounds__(256) void k_hess_gemv(int n, const T *A, int lda, const T *V, int col,
-                                                  T *Ypart, int S) {
+                                                  T *Ypart, int S, int k0, T *wT) {
+    if ((int)blockIdx.x == (int)gridDim.x - 1) {
+        const int j = blockIdx.y * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+        if (j >= col - k0) return;
+        const T *vj = V + (size_t)(k0 + j) * n, *vc = V + (size_t)col * n;
+        T acc = T(0);
+#pragma unroll 8
+        for (int r = col + 1 + lane; r < n; r += 64) acc += vj[r] * vc[r];
+        acc = wave_sum(acc);
+        if (lane == 0) wT[j] = acc;
+        return;
+    }
     __shared__ T vs[512];
     const int r = blockIdx.x * 256 + threadIdx.x;
     const int s = blockIdx.y;
@@ -536,7 +545,8 @@ size_t hessenberg_work_elems(int n, int nb, int S) {
            + (size_t)S * n            // Ypart
            + (size_t)n                // tau
            + (size_t)2 * nb * n       // W, W2 for the trailing update
-           + (size_t)HKS * nb * n;    // split-K partial products of V^T M
+           + (size_t)HKS * nb * n     // split-K partial products of V^T M
+           + 64;                      // wT: the next column step's panel products
 }
 template size_t hessenberg_work_elems<float>(int, int, int);
 template size_t hessenberg_work_elems<double>(int, int, int);
@@ -545,16 +555,16 @@ template size_t hessenberg_work_elems<double>(int, int, int);
 // (n <= 4 HNT, nb <= 32), else the general one.
 template <typename T>
 static void hess_col(hipStream_t s, int n, T *A, int lda, T *V, T *Tp, int nb, T *Y, const T *Ypart, int S,
-                     T *tau, int k0, int i, int fin) {
+                     T *tau, int k0, int i, int fin, const T *wT) {
     if (nb <= 32 && n <= HNT)
         hipLaunchKernelGGL((k_hess_col_r<T, 1>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart, S,
-                           tau, k0, i, fin);
+                           tau, k0, i, fin, wT);
     else if (nb <= 32 && n <= 2 * HNT)
         hipLaunchKernelGGL((k_hess_col_r<T, 2>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart, S,
-                           tau, k0, i, fin);
+                           tau, k0, i, fin, wT);
     else if (nb <= 32 && n <= 4 * HNT)
         hipLaunchKernelGGL((k_hess_col_r<T, 4>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart, S,
-                           tau, k0, i, fin);
+                           tau, k0, i, fin, wT);
     else
         hipLaunchKernelGGL((k_hess_col<T>), dim3(1), dim3(HNT), 0, s, n, A, lda, V, Tp, nb, Y, Ypart, S, tau,
                            k0, i, fin);
@@ -575,6 +585,7 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
     T *W = tau + n;
     T *W2 = W + (size_t)nb * n;
     T *Pk = W2 + (size_t)nb * n;
+    T *wT = Pk + (size_t)HKS * nb * n;
     hipMemsetAsync(V, 0, sizeof(T) * (size_t)n * n, s);
     hipMemsetAsync(Tall, 0, sizeof(T) * (size_t)((n + nb - 1) / nb) * nb * nb, s);
     const int rb = (n + 255) / 256;
@@ -585,15 +596,15 @@ void hessenberg(hipStream_t s, int n, T *A, int lda, T *U, int ldu, T *work, int
         for (int i = 0; i < nbp; ++i) {
             {
                 ProfScope ps(KID_HESS_COL, s);
-                hess_col<T>(s, n, A, lda, V, Tp, nb, Y, Ypart, S, tau, k0, i, 0);
+                hess_col<T>(s, n, A, lda, V, Tp, nb, Y, Ypart, S, tau, k0, i, 0, wT);
             }
             {
                 ProfScope ps(KID_HESS_GEMV, s);
-                hipLaunchKernelGGL((k_hess_gemv<T>), dim3(rb, S), dim3(256), 0, s, n, A, lda, V, k0 + i,
-                                   Ypart, S);
+                hipLaunchKernelGGL((k_hess_gemv<T>), dim3(rb + 1, S), dim3(256), 0, s, n, A, lda, V, k0 + i,
+                                   Ypart, S, k0, wT);
             }
         }
-        hess_col<T>(s, n, A, lda, V, Tp, nb, Y, Ypart, S, tau, k0, nbp, 1);
+        hess_col<T>(s, n, A, lda, V, Tp, nb, Y, Ypart, S, tau, k0, nbp, 1, wT);
         const int c1 = k0 + nbp;  // first trailing column
         const int nt = n - c1;
         if (nt > 0) {
