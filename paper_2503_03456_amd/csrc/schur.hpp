@@ -23,10 +23,10 @@ struct SchurTune {
 // within 160 KiB: two nsmall^2 matrices, a phase window of <= WMAX rows.
 template <typename T> struct SchurCaps;
 template <> struct SchurCaps<float> {
-    static constexpr int NSMALL = 140, WMAX = 141, NBMAX = 44, HNB = 32, HS = 32;
+    static constexpr int NSMALL = 140, WMAX = 141, NBMAX = 44, HNB = 32, HS = 16;
 };
 template <> struct SchurCaps<double> {
-    static constexpr int NSMALL = 98, WMAX = 99, NBMAX = 32, HNB = 32, HS = 32;
+    static constexpr int NSMALL = 98, WMAX = 99, NBMAX = 32, HNB = 32, HS = 16;
 };
 template <typename T> SchurTune schur_tune();
 // Validates against the bounds; returns 0 or -1.
