@@ -74,6 +74,20 @@ SYLV_DEVINL void reflector3(int len, T x, T y, T z, T &v1, T &v2, T &tau, T &bet
     beta = bs * mm;
 }
 
+// DPP lane move (CTRL a gfx9 DPP control: row_shr:k = 0x110 + k, row_bcast:15
+// = 0x142, row_bcast:31 = 0x143); lanes without a source read 0
+template <int CTRL>
+SYLV_DEVINL float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+SYLV_DEVINL double dpp_move(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+
 // 16x16x4 MFMA in the precision T (binary32 or binary64 accumulate).  With
 // the operands fed swapped (op(B)^T in the A slot, op(A)^T in the B slot),
 // lane l ends up holding C(l & 15, orow(l, r)) in accumulator r, i.e. each

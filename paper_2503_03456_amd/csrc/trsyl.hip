@@ -36,20 +36,6 @@ template <> struct mfma16t<double> {
     static SYLV_DEVINL int orow(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
-// DPP lane move (CTRL a gfx9 DPP control: row_shr:k = 0x110 + k, row_bcast:15
-// = 0x142, row_bcast:31 = 0x143); lanes without a source read 0
-template <int CTRL>
-SYLV_DEVINL float dpp_move(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
-}
-template <int CTRL>
-SYLV_DEVINL double dpp_move(double v) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
-}
-
 // Sums of x over aligned groups of g lanes (g a power of two <= 64, uniform):
 // the last lane of each group ends with its group's sum (other lanes hold
 // partial sums).  Doubling row shifts within rows of 16, then the row
