@@ -556,36 +556,48 @@ __global__ __launch_bounds__(NT) void k_aed(int nw, T *H, int ldh, int kwtop, in
             __syncthreads();
         }
         // Householder reduction of Tw(0:ns, 0:ns) back to Hessenberg form;
-        // the left reflectors also act on columns ns..nw-1.
+        // the left reflectors also act on columns ns..nw-1.  Per column: the
+        // reflector on wavefront 0; then the left update of the columns to
+        // the right and the update of Z side by side, then the right update
+        // of rows 0..ns-1; each dot product split over an aligned group of
+        // RG lanes (strided over the vector) and summed by shuffles.
+        constexpr int RG = 8, NG = NT / RG;
         T *v = sp;  // reuse
+        const int grp = tid / RG, sub = tid % RG;
         for (int c = 0; c + 2 < ns; ++c) {
             const int len = ns - c - 1;  // rows c+1..ns-1
             if (tid < 64) house_wave<T>(len, Tw + c * L + c + 1, v, &sh_tau, &sh_beta);
             __syncthreads();
             const T tau = sh_tau;
+            // column c becomes (beta, 0, ..., 0) below its diagonal (no update
+            // of this column reads it)
+            for (int i = tid; i < len; i += NT) Tw[c * L + c + 1 + i] = (i == 0) ? sh_beta : T(0);
             if (tau != T(0)) {
-                for (int j = c + 1 + tid; j < nw; j += NT) {
+                const int ncol = nw - c - 1;
+                for (int gi = grp; gi < ncol + nw; gi += NG) {
+                    const bool lft = gi < ncol;
+                    // left: column j = c+1+gi, entries Tw(c+1+i, j); Z: row zi, entries Zl(zi, c+1+i)
+                    T *base = lft ? Tw + (size_t)(c + 1 + gi) * L + c + 1 : Zl + (size_t)(c + 1) * L + (gi - ncol);
+                    const int step = lft ? 1 : L;
                     T acc = T(0);
-                    for (int i = 0; i < len; ++i) acc += v[i] * Tw[j * L + c + 1 + i];
+                    for (int i = sub; i < len; i += RG) acc += v[i] * base[i * step];
+#pragma unroll
+                    for (int o = 1; o < RG; o <<= 1) acc += __shfl_xor(acc, o);
                     acc *= tau;
-                    for (int i = 0; i < len; ++i) Tw[j * L + c + 1 + i] -= acc * v[i];
+                    for (int i = sub; i < len; i += RG) base[i * step] -= acc * v[i];
                 }
                 __syncthreads();
-                for (int i = tid; i < ns; i += NT) {
+                for (int gi = grp; gi < ns; gi += NG) {
+                    // right: row gi, entries Tw(gi, c+1+j)
+                    T *base = Tw + (size_t)(c + 1) * L + gi;
                     T acc = T(0);
-                    for (int j = 0; j < len; ++j) acc += Tw[(c + 1 + j) * L + i] * v[j];
+                    for (int j = sub; j < len; j += RG) acc += base[(size_t)j * L] * v[j];
+#pragma unroll
+                    for (int o = 1; o < RG; o <<= 1) acc += __shfl_xor(acc, o);
                     acc *= tau;
-                    for (int j = 0; j < len; ++j) Tw[(c + 1 + j) * L + i] -= acc * v[j];
-                }
-                for (int i = tid; i < nw; i += NT) {
-                    T acc = T(0);
-                    for (int j = 0; j < len; ++j) acc += Zl[(c + 1 + j) * L + i] * v[j];
-                    acc *= tau;
-                    for (int j = 0; j < len; ++j) Zl[(c + 1 + j) * L + i] -= acc * v[j];
+                    for (int j = sub; j < len; j += RG) base[(size_t)j * L] -= acc * v[j];
                 }
             }
-            __syncthreads();
-            for (int i = tid; i < len; i += NT) Tw[c * L + c + 1 + i] = (i == 0) ? sh_beta : T(0);
             __syncthreads();
         }
     }
