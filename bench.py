@@ -31,7 +31,7 @@ PEAKS = {  # MI355X published dense peaks
 # x1.0 for WRITE_SIZE.  Valid for the kernel version the counters were taken
 # on (profiles/hbm_traffic_sylvester_2048.md, profiles/hbm_traffic_symmetric_2048.md);
 # None once the kernel changes.
-TRAFFIC_BYTES = {"k_chase": (116.0 + 105.3) * 1024, "k_jac_pairs": (588.4 + 468.8) * 1024}
+TRAFFIC_BYTES = {"k_chase": (116.1 + 105.0) * 1024, "k_jac_pairs": (588.4 + 468.8) * 1024}
 
 KERNEL_IDS = {"gemm_kernel": 1, "k_hess_col": 2, "k_hess_gemv": 3, "k_aed": 4, "k_chase": 5,
               "k_trsyl_diag": 6, "k_find_ktop": 7, "k_cast": 8, "k_sumsq_partial": 9,

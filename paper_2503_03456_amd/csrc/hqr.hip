@@ -372,26 +372,23 @@ SYLV_DEVINL int francis_wave(int n, T *H, int ldh, T *Z, int ldz, int nz, int *n
             wave_order();
             // right: columns k..k2, rows 0..min(k+3, ihi)
             const int rmax = (k + 3 < ihi) ? k + 3 : ihi;
-            T col_k = T(0);   // this lane's new H(lane, k)
-            if (lane <= rmax) {
-                const int i = lane;
-                T a0 = CM(H, i, k, ldh), a1 = CM(H, i, k + 1, ldh), a2 = CM(H, i, k2, ldh);
-                refl_apply(len, v1, v2, tau, a0, a1, a2);
-                CM(H, i, k2, ldh) = a2; CM(H, i, k, ldh) = a0; CM(H, i, k + 1, ldh) = a1;
-                col_k = a0;
-            }
+            // H rows 0..rmax and Z rows 0..nz-1: both rows' loads first (rows
+            // clamped into range, stores only for real rows), then the updates
+            const bool hrow = lane <= rmax, zrow = lane < nz;
+            const int ih = hrow ? lane : 0, iz = zrow ? lane : 0;
+            T a0 = CM(H, ih, k, ldh), a1 = CM(H, ih, k + 1, ldh), a2 = CM(H, ih, k2, ldh);
+            T b0 = CM(Z, iz, k, ldz), b1 = CM(Z, iz, k + 1, ldz), b2 = CM(Z, iz, k2, ldz);
+            refl_apply(len, v1, v2, tau, a0, a1, a2);
+            refl_apply(len, v1, v2, tau, b0, b1, b2);
+            if (hrow) { CM(H, ih, k2, ldh) = a2; CM(H, ih, k, ldh) = a0; CM(H, ih, k + 1, ldh) = a1; }
+            if (zrow) { CM(Z, iz, k2, ldz) = b2; CM(Z, iz, k, ldz) = b0; CM(Z, iz, k + 1, ldz) = b1; }
+            const T col_k = hrow ? a0 : T(0);   // this lane's new H(lane, k)
             if (k + 1 <= ihi - 1) {
                 // next step's column: rows k+1 .. k+1+len'-1 of column k (lanes <= rmax)
                 const int kn2 = (k + 1 <= ihi - 2) ? k + 3 : k + 2;
                 x = wave_bcast(col_k, k + 1);
                 y = wave_bcast(col_k, k + 2);
                 z = wave_bcast(col_k, kn2);
-            }
-            if (lane < nz) {
-                const int i = lane;
-                T a0 = CM(Z, i, k, ldz), a1 = CM(Z, i, k + 1, ldz), a2 = CM(Z, i, k2, ldz);
-                refl_apply(len, v1, v2, tau, a0, a1, a2);
-                CM(Z, i, k2, ldz) = a2; CM(Z, i, k, ldz) = a0; CM(Z, i, k + 1, ldz) = a1;
             }
             wave_order();
         }
@@ -791,15 +788,26 @@ __global__ __launch_bounds__(NT) void k_chase(T *H, int ldh, int ktop, int kbot,
                     int rmax = q + 3 < kb ? q + 3 : kb;
                     if (rmax > W - 1) rmax = W - 1;
                     const int q2 = (len == 3) ? q + 2 : q + 1;
-                    T nx = T(0), ny = T(0), nz = T(0);
-                    for (int i = q + 1; i <= rmax; ++i) {
-                        T a0 = Hw[q * L + i], a1 = Hw[(q + 1) * L + i], a2 = Hw[q2 * L + i];
-                        refl_apply(len, v1, v2, tau, a0, a1, a2);
-                        Hw[q2 * L + i] = a2; Hw[q * L + i] = a0; Hw[(q + 1) * L + i] = a1;
-                        if (i == q + 1) nx = a0;
-                        else if (i == q + 2) ny = a0;
-                        else nz = a0;
+                    // rows q+1..rmax (1..3 of them): all loads first (a
+                    // missing third row repeats the last one, stored once),
+                    // then the updates, then the stores
+                    const int nrow = rmax - q;
+                    T r0[3], r1[3], r2[3];
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const int i = q + 1 + (u < nrow ? u : nrow - 1);
+                        r0[u] = Hw[q * L + i]; r1[u] = Hw[(q + 1) * L + i]; r2[u] = Hw[q2 * L + i];
                     }
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) refl_apply(len, v1, v2, tau, r0[u], r1[u], r2[u]);
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        if (u < nrow) {
+                            const int i = q + 1 + u;
+                            Hw[q2 * L + i] = r2[u]; Hw[q * L + i] = r0[u]; Hw[(q + 1) * L + i] = r1[u];
+                        }
+                    }
+                    const T nx = r0[0], ny = nrow >= 2 ? r0[1] : T(0), nz = nrow >= 3 ? r0[2] : T(0);
                     const int pn = t + 1 - 3 * b;
                     if (t + 1 < t0 + adv && pn <= N - 2)
                         commit(b, buf ^ 1, q + 1, (pn <= N - 3) ? 3 : 2, nx, ny, nz);
