@@ -116,12 +116,12 @@ SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int ld
 // ------------------------------------------------------ 128 x 128 tiles
 // Large products (M, N >= 1024-ish, K >= 256): a 128 x 128 output tile per 256-thread
 // workgroup, each wave64 a 64 x 64 quadrant (4 x 4 MFMA blocks of 16 x 16),
-// K staged through two LDS buffers 16 at a time (one barrier per K step: a
+// K staged through two LDS buffers 32 at a time (one barrier per K step: a
 // buffer is rewritten only after every wave has passed the barrier that
 // follows its last read).  Global loads move 8 consecutive elements per
 // thread along the contiguous dimension of each operand, as 16-byte vector
 // loads when the operand's base and leading dimension allow it.
-constexpr int LBM = 128, LBK = 16, LPAD = 16, LLD = LBM + LPAD;
+constexpr int LBM = 128, LBK = 32, LPAD = 16, LLD = LBM + LPAD;
 
 // 8 consecutive elements p[0..7] (cnt of them in range), scaled by sc in
 // their storage precision (a power of two applied before the conversion
@@ -177,35 +177,42 @@ __global__ __launch_bounds__(256) void gemm128_kernel(int M, int N, int K, const
     //   op(B) 16 x 128: !tb -> k bk..bk+7 of column bj; tb -> columns bj..bj+7 of row bk
     const int ai = ta ? (t >> 1) : (t & 15) * 8, ak = ta ? (t & 1) * 8 : (t >> 4);
     const int bj = tb ? (t & 15) * 8 : (t >> 1), bk = tb ? (t >> 4) : (t & 1) * 8;
-    ACC ra[8], rb[8];
+    constexpr int KH = LBK / 16;   // 16-deep halves of the slab per thread
+    ACC ra[KH][8], rb[KH][8];
     auto load = [&](int k0) {
-        if (!ta) {
-            const int gi = row0 + ai, gk = k0 + ak;
-            const int cnt = (gk < K) ? min(8, M - gi) : 0;
-            load8<TA, ACC>(A + (size_t)gk * lda + gi, cnt > 0 ? cnt : 0, va, TA(1), ra);
-        } else {
-            const int gi = row0 + ai, gk = k0 + ak;
-            const int cnt = (gi < M) ? min(8, K - gk) : 0;
-            load8<TA, ACC>(A + (size_t)gi * lda + gk, cnt > 0 ? cnt : 0, va, TA(1), ra);
-        }
-        if (!tb) {
-            const int gj = col0 + bj, gk = k0 + bk;
-            const int cnt = (gj < N) ? min(8, K - gk) : 0;
-            load8<TB, ACC>(B + (size_t)gj * ldb + gk, cnt > 0 ? cnt : 0, vb, bscale, rb);
-        } else {
-            const int gj = col0 + bj, gk = k0 + bk;
-            const int cnt = (gk < K) ? min(8, N - gj) : 0;
-            load8<TB, ACC>(B + (size_t)gk * ldb + gj, cnt > 0 ? cnt : 0, vb, bscale, rb);
+#pragma unroll
+        for (int hh = 0; hh < KH; ++hh) {
+            const int kb = k0 + 16 * hh;
+            if (!ta) {
+                const int gi = row0 + ai, gk = kb + ak;
+                const int cnt = (gk < K) ? min(8, M - gi) : 0;
+                load8<TA, ACC>(A + (size_t)gk * lda + gi, cnt > 0 ? cnt : 0, va, TA(1), ra[hh]);
+            } else {
+                const int gi = row0 + ai, gk = kb + ak;
+                const int cnt = (gi < M) ? min(8, K - gk) : 0;
+                load8<TA, ACC>(A + (size_t)gi * lda + gk, cnt > 0 ? cnt : 0, va, TA(1), ra[hh]);
+            }
+            if (!tb) {
+                const int gj = col0 + bj, gk = kb + bk;
+                const int cnt = (gj < N) ? min(8, K - gk) : 0;
+                load8<TB, ACC>(B + (size_t)gj * ldb + gk, cnt > 0 ? cnt : 0, vb, bscale, rb[hh]);
+            } else {
+                const int gj = col0 + bj, gk = kb + bk;
+                const int cnt = (gk < K) ? min(8, N - gj) : 0;
+                load8<TB, ACC>(B + (size_t)gk * ldb + gj, cnt > 0 ? cnt : 0, vb, bscale, rb[hh]);
+            }
         }
     };
     auto store = [&](int st) {
 #pragma unroll
-        for (int h = 0; h < 8; ++h) {
-            if (!ta) As[st][ak][ai + h] = ra[h];
-            else As[st][ak + h][ai] = ra[h];
-            if (!tb) Bs[st][bk + h][bj] = rb[h];
-            else Bs[st][bk][bj + h] = rb[h];
-        }
+        for (int hh = 0; hh < KH; ++hh)
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                if (!ta) As[st][16 * hh + ak][ai + h] = ra[hh][h];
+                else As[st][16 * hh + ak + h][ai] = ra[hh][h];
+                if (!tb) Bs[st][16 * hh + bk + h][bj] = rb[hh][h];
+                else Bs[st][16 * hh + bk][bj + h] = rb[hh][h];
+            }
     };
     v4 acc[4][4];
 #pragma unroll
