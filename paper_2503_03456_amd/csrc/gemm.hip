@@ -40,22 +40,26 @@ SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int ld
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
-    ACC ra[4], rb[4];
+    // the next slab is held in registers in its storage format and scaled
+    // and converted only when written to LDS: nothing waits on the loads
+    // until the MFMAs of the current slab have been issued
+    TA ra[4];
+    TB rb[4];
     auto load = [&](int k0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int i, k;
             if (!ta) { i = l; k = (t >> 6) + 4 * r; } else { k = t & 15; i = (t >> 4) + 16 * r; }
             int gi = row0 + i, gk = k0 + k;
-            ACC v = ACC(0);
-            if (gi < M && gk < K) v = (ACC)(ta ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi]);
+            TA v = TA(0);
+            if (gi < M && gk < K) v = ta ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi];
             ra[r] = v;
             int j;
             if (!tb) { k = t & 15; j = (t >> 4) + 16 * r; } else { j = l; k = (t >> 6) + 4 * r; }
             int gj = col0 + j;
             gk = k0 + k;
-            ACC u = ACC(0);
-            if (gj < N && gk < K) u = (ACC)(bscale * (tb ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk]));
+            TB u = TB(0);
+            if (gj < N && gk < K) u = tb ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk];
             rb[r] = u;
         }
     };
@@ -64,10 +68,12 @@ SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int ld
         for (int r = 0; r < 4; ++r) {
             int i, k;
             if (!ta) { i = l; k = (t >> 6) + 4 * r; } else { k = t & 15; i = (t >> 4) + 16 * r; }
-            As[k][i] = ra[r];
+            As[k][i] = (ACC)ra[r];
             int j;
             if (!tb) { k = t & 15; j = (t >> 4) + 16 * r; } else { j = l; k = (t >> 6) + 4 * r; }
-            Bs[k][j] = rb[r];
+            // the scale (a power of two) is applied in the storage precision
+            // before the conversion, which keeps the range
+            Bs[k][j] = (ACC)(bscale * rb[r]);
         }
     };
 
@@ -123,19 +129,20 @@ SYLV_DEVINL void gemm_tile(int M, int N, int K, const TA *__restrict__ A, int ld
 // loads when the operand's base and leading dimension allow it.
 constexpr int LBM = 128, LBK = 32, LPAD = 16, LLD = LBM + LPAD;
 
-// 8 consecutive elements p[0..7] (cnt of them in range), scaled by sc in
-// their storage precision (a power of two applied before the conversion
-// keeps the range), converted to ACC
-template <typename TS, typename ACC>
-SYLV_DEVINL void load8(const TS *p, int cnt, bool vec, TS sc, ACC (&out)[8]) {
+// 8 consecutive elements p[0..7] (cnt of them in range, zeros after) in
+// their storage format; the caller scales and converts them when it writes
+// the slab to LDS, so the loads stay in flight across the current slab's
+// MFMAs
+template <typename TS>
+SYLV_DEVINL void load8(const TS *p, int cnt, bool vec, TS (&out)[8]) {
     if (vec && cnt >= 8) {
         if constexpr (sizeof(TS) == 8) {
             typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 const d2 v = *reinterpret_cast<const d2 *>(p + 2 * h);
-                out[2 * h] = (ACC)(sc * v[0]);
-                out[2 * h + 1] = (ACC)(sc * v[1]);
+                out[2 * h] = v[0];
+                out[2 * h + 1] = v[1];
             }
         } else {
             typedef float f4 __attribute__((ext_vector_type(4)));
@@ -143,20 +150,20 @@ SYLV_DEVINL void load8(const TS *p, int cnt, bool vec, TS sc, ACC (&out)[8]) {
             for (int h = 0; h < 2; ++h) {
                 const f4 v = *reinterpret_cast<const f4 *>(p + 4 * h);
 #pragma unroll
-                for (int z = 0; z < 4; ++z) out[4 * h + z] = (ACC)(sc * v[z]);
+                for (int z = 0; z < 4; ++z) out[4 * h + z] = v[z];
             }
         }
         return;
     }
 #pragma unroll
-    for (int h = 0; h < 8; ++h) out[h] = (h < cnt) ? (ACC)(sc * p[h]) : ACC(0);
+    for (int h = 0; h < 8; ++h) out[h] = (h < cnt) ? p[h] : TS(0);
 }
 
-template <typename TA, typename TB, typename TC, typename ACC>
+template <typename TA, typename TB, typename TC, typename ACC, int ta, int tb>
 __global__ __launch_bounds__(256) void gemm128_kernel(int M, int N, int K, const TA *__restrict__ A, int lda,
-                                                      int ta, const TB *__restrict__ B, int ldb, int tb,
-                                                      TC *__restrict__ C, int ldc, double alpha, ACC beta,
-                                                      int tiles_m, TB bscale, int upper) {
+                                                      const TB *__restrict__ B, int ldb, TC *__restrict__ C,
+                                                      int ldc, double alpha, ACC beta, int tiles_m, TB bscale,
+                                                      int upper) {
     typedef typename mfma16<ACC>::v4 v4;
     __shared__ ACC As[2][LBK][LLD];
     __shared__ ACC Bs[2][LBK][LLD];
@@ -178,28 +185,29 @@ __global__ __launch_bounds__(256) void gemm128_kernel(int M, int N, int K, const
     const int ai = ta ? (t >> 1) : (t & 15) * 8, ak = ta ? (t & 1) * 8 : (t >> 4);
     const int bj = tb ? (t & 15) * 8 : (t >> 1), bk = tb ? (t >> 4) : (t & 1) * 8;
     constexpr int KH = LBK / 16;   // 16-deep halves of the slab per thread
-    ACC ra[KH][8], rb[KH][8];
+    TA ra[KH][8];
+    TB rb[KH][8];
     auto load = [&](int k0) {
 #pragma unroll
         for (int hh = 0; hh < KH; ++hh) {
             const int kb = k0 + 16 * hh;
-            if (!ta) {
+            if constexpr (!ta) {
                 const int gi = row0 + ai, gk = kb + ak;
                 const int cnt = (gk < K) ? min(8, M - gi) : 0;
-                load8<TA, ACC>(A + (size_t)gk * lda + gi, cnt > 0 ? cnt : 0, va, TA(1), ra[hh]);
+                load8<TA>(A + (size_t)gk * lda + gi, cnt > 0 ? cnt : 0, va, ra[hh]);
             } else {
                 const int gi = row0 + ai, gk = kb + ak;
                 const int cnt = (gi < M) ? min(8, K - gk) : 0;
-                load8<TA, ACC>(A + (size_t)gi * lda + gk, cnt > 0 ? cnt : 0, va, TA(1), ra[hh]);
+                load8<TA>(A + (size_t)gi * lda + gk, cnt > 0 ? cnt : 0, va, ra[hh]);
             }
-            if (!tb) {
+            if constexpr (!tb) {
                 const int gj = col0 + bj, gk = kb + bk;
                 const int cnt = (gj < N) ? min(8, K - gk) : 0;
-                load8<TB, ACC>(B + (size_t)gj * ldb + gk, cnt > 0 ? cnt : 0, vb, bscale, rb[hh]);
+                load8<TB>(B + (size_t)gj * ldb + gk, cnt > 0 ? cnt : 0, vb, rb[hh]);
             } else {
                 const int gj = col0 + bj, gk = kb + bk;
                 const int cnt = (gk < K) ? min(8, N - gj) : 0;
-                load8<TB, ACC>(B + (size_t)gk * ldb + gj, cnt > 0 ? cnt : 0, vb, bscale, rb[hh]);
+                load8<TB>(B + (size_t)gk * ldb + gj, cnt > 0 ? cnt : 0, vb, rb[hh]);
             }
         }
     };
@@ -208,10 +216,13 @@ __global__ __launch_bounds__(256) void gemm128_kernel(int M, int N, int K, const
         for (int hh = 0; hh < KH; ++hh)
 #pragma unroll
             for (int h = 0; h < 8; ++h) {
-                if (!ta) As[st][16 * hh + ak][ai + h] = ra[hh][h];
-                else As[st][16 * hh + ak + h][ai] = ra[hh][h];
-                if (!tb) Bs[st][16 * hh + bk + h][bj] = rb[hh][h];
-                else Bs[st][16 * hh + bk][bj + h] = rb[hh][h];
+                // B's scale (a power of two) in its storage precision, then
+                // the conversion
+                const ACC av = (ACC)ra[hh][h], bv = (ACC)(bscale * rb[hh][h]);
+                if constexpr (!ta) As[st][16 * hh + ak][ai + h] = av;
+                else As[st][16 * hh + ak + h][ai] = av;
+                if constexpr (!tb) Bs[st][16 * hh + bk + h][bj] = bv;
+                else Bs[st][16 * hh + bk][bj + h] = bv;
             }
     };
     v4 acc[4][4];
@@ -314,7 +325,9 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    unsigned short ra[8], rb[8];
+    // raw operands; rounded to the narrow format when the slab goes to LDS
+    TA ra[8];
+    TB rb[8];
     // slab element r of this thread: A (i, k) and B (k, j) with coalesced global reads
     auto aidx = [&](int r, int &i, int &k) {
         if (!ta) { i = t & 63; k = (t >> 6) + 4 * r; } else { k = t & 31; i = (t >> 5) + 8 * r; }
@@ -328,15 +341,15 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
             int i, k;
             aidx(r, i, k);
             const int gi = row0 + i, gk = k0 + k;
-            float v = 0.f;
-            if (gi < M && gk < K) v = (float)(ta ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi]);
-            ra[r] = narrow_rne<FMT>(v);
+            TA v = TA(0);
+            if (gi < M && gk < K) v = ta ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi];
+            ra[r] = v;
             int j;
             bidx(r, k, j);
             const int gj = col0 + j, gk2 = k0 + k;
-            float u = 0.f;
-            if (gj < N && gk2 < K) u = (float)(bscale * (tb ? B[(size_t)gk2 * ldb + gj] : B[(size_t)gj * ldb + gk2]));
-            rb[r] = narrow_rne<FMT>(u);
+            TB u = TB(0);
+            if (gj < N && gk2 < K) u = tb ? B[(size_t)gk2 * ldb + gj] : B[(size_t)gj * ldb + gk2];
+            rb[r] = u;
         }
     };
     auto store = [&]() {
@@ -344,9 +357,9 @@ SYLV_DEVINL void gemm_bf16_tile(int M, int N, int K, const TA *__restrict__ A, i
         for (int r = 0; r < 8; ++r) {
             int i, k, j;
             aidx(r, i, k);
-            As[i][k] = ra[r];
+            As[i][k] = narrow_rne<FMT>((float)ra[r]);
             bidx(r, k, j);
-            Bs[j][k] = rb[r];
+            Bs[j][k] = narrow_rne<FMT>((float)(bscale * rb[r]));
         }
     };
     const int nk = (K + HBK - 1) / HBK;
@@ -585,8 +598,16 @@ void gemm(hipStream_t s, int ta, int tb, int M, int N, int K, double alpha, cons
         const int tm2 = (M + LBM - 1) / LBM, tn2 = (N + LBM - 1) / LBM;
         const int up2 = (upper && tm2 == tn2) ? 1 : 0;
         const int nt2 = up2 ? tm2 * (tm2 + 1) / 2 : tm2 * tn2;
-        hipLaunchKernelGGL((gemm128_kernel<TA, TB, TC, ACC>), dim3(nt2), dim3(256), 0, s, M, N, K, A, lda, ta, B,
-                           ldb, tb, C, ldc, alpha, beta, tm2, bscale, up2);
+        // the transposes are template arguments: the LDS stores and global
+        // loads of each operand layout compile without per-element branches
+#define SYLV_G128(TAT, TBT)                                                                                     \
+    hipLaunchKernelGGL((gemm128_kernel<TA, TB, TC, ACC, TAT, TBT>), dim3(nt2), dim3(256), 0, s, M, N, K, A, lda, B, \
+                       ldb, C, ldc, alpha, beta, tm2, bscale, up2)
+        if (!ta && !tb) SYLV_G128(0, 0);
+        else if (ta && !tb) SYLV_G128(1, 0);
+        else if (!ta) SYLV_G128(0, 1);
+        else SYLV_G128(1, 1);
+#undef SYLV_G128
         return;
     }
     hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, ACC>), dim3(ntiles), dim3(256), 0, s, M, N, K, A,
