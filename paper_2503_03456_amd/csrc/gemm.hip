@@ -172,7 +172,17 @@ __global__ __launch_bounds__(256) void gemm128_kernel(int M, int N, int K, const
     if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
     int tm, tn;
     if (upper) sym_pair_index(bid, tm, tn);
-    else { tm = bid % tiles_m; tn = bid / tiles_m; }
+    else {
+        // tiles in groups of G tile rows, column by column inside a group:
+        // each XCD's consecutive run of tiles (above) is then a block about
+        // G rows tall rather than whole tile columns, so its L2 sees fewer
+        // distinct rows of op(A) for the same columns of op(B)
+        constexpr int G = 4;
+        const int tiles_n = nblk / tiles_m, per = G * tiles_n;
+        const int grp = bid / per, m0 = grp * G, gs = min(G, tiles_m - m0), r = bid - grp * per;
+        tm = m0 + r % gs;
+        tn = r / gs;
+    }
     const int row0 = tm * LBM, col0 = tn * LBM;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = w & 1, wn = w >> 1;
