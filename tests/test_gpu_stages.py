@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
                                          (257, 300, 130, 1, 0), (256, 384, 64, 0, 1), (129, 131, 33, 1, 1),
                                          (512, 512, 512, 0, 0), (130, 128, 17, 0, 0),
                                          (1024, 1040, 300, 0, 0), (1100, 1024, 260, 1, 1),
-                                         (1030, 1153, 513, 1, 0)])
+                                         (1030, 1153, 513, 1, 0), (1090, 1030, 270, 0, 1)])
 def test_gemm_parity(prec, m, n, k, ta, tb):
     sy = binding()
     say("gemm", prec, m, n, k, ta, tb)
@@ -38,14 +38,14 @@ def test_gemm_parity(prec, m, n, k, ta, tb):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_parity_odd_leading_dimensions(prec, ta, tb):
     """Operands that are column slices of larger arrays with odd leading
     dimensions (no 16-byte column alignment: the large-tile kernel's scalar
     load path) against numpy."""
     sy = binding()
     m, n, k = 1030, 1025, 260   # large enough for the 128-wide tile
-    rs = np.random.RandomState(11 + ta)
+    rs = np.random.RandomState(11 + ta + 2 * tb)
     dt = torch.float64 if prec == "fp64" else torch.float32
     ar, ac = (k, m) if ta else (m, k)
     br, bc = (n, k) if tb else (k, n)
