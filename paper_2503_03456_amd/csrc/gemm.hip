@@ -169,14 +169,16 @@ __global__ __launch_bounds__(256) void gemm128_kernel(int M, int N, int K, const
     __shared__ ACC Bs[2][LBK][LLD];
     const int nblk = gridDim.x;
     int bid = blockIdx.x;
+    // workgroups are dealt to the 8 XCDs round-robin: renumber so that each
+    // XCD takes a consecutive run of nblk / 8 tiles
     if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
     int tm, tn;
     if (upper) sym_pair_index(bid, tm, tn);
     else {
         // tiles in groups of G tile rows, column by column inside a group:
-        // each XCD's consecutive run of tiles (above) is then a block about
-        // G rows tall rather than whole tile columns, so its L2 sees fewer
-        // distinct rows of op(A) for the same columns of op(B)
+        // each XCD's run of tiles is then a block about G rows tall rather
+        // than whole tile columns, so its L2 sees fewer distinct rows of
+        // op(A) for the same columns of op(B)
         constexpr int G = 4;
         const int tiles_n = nblk / tiles_m, per = G * tiles_n;
         const int grp = bid / per, m0 = grp * G, gs = min(G, tiles_m - m0), r = bid - grp * per;
@@ -189,7 +191,8 @@ __global__ __launch_bounds__(256) void gemm128_kernel(int M, int N, int K, const
     // vector loads need 16-byte aligned columns
     const bool va = ((reinterpret_cast<size_t>(A) | ((size_t)lda * sizeof(TA))) & 15) == 0;
     const bool vb = ((reinterpret_cast<size_t>(B) | ((size_t)ldb * sizeof(TB))) & 15) == 0;
-    // slab coordinates of this thread's 8 consecutive elements
+    // coordinates of this thread's 8 consecutive elements in each 16-deep
+    // half of the slab
     //   op(A) 128 x 16: !ta -> rows ai..ai+7 of column ak; ta -> k ak..ak+7 of row ai
     //   op(B) 16 x 128: !tb -> k bk..bk+7 of column bj; tb -> columns bj..bj+7 of row bk
     const int ai = ta ? (t >> 1) : (t & 15) * 8, ak = ta ? (t & 1) * 8 : (t >> 4);
