@@ -248,7 +248,8 @@ size_t sylv_batched_workspace_size(int batch, const int *kind, const int *m, con
  * A value <= 0 (nibble < 0) keeps the current one.  Returns 0, -1 for a bad
  * prec, -2 when the combination exceeds the LDS/workspace bounds
  * (FP32: nsmall, nw <= 140, nb <= 44, adv + 3 ceil(nb / chains) + 1 <= 141;
- * FP64: 98, 32 and 99) or names an unsupported wave or chain count. */
+ * FP64: 98, 32 and 99; nsmall >= 16, nw >= 8, adv >= 4, nibble <= 100) or
+ * names an unsupported wave or chain count. */
 int sylv_schur_tune(int prec, int nsmall, int nw, int nb, int adv, int nibble, int aed_waves,
                     int chase_waves, int chains);
 /* Current tunables (nsmall, nw, nb, adv, nibble, aed_waves, chase_waves,

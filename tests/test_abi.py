@@ -114,3 +114,44 @@ def test_batched_tune_validation(lib):
     assert lib.sylv_batched_tune(128, 64, 180, 128, 0, 0) == -4
     assert lib.sylv_batched_tune_get(v) == 0 and list(v) == before
     assert lib.sylv_batched_tune(*before) == 0
+
+
+def test_schur_tune_bounds_as_documented(lib):
+    """sylv_schur_tune validates on the host against the bounds the header
+    states (FP32: nsmall, nw <= 140, nb <= 44, window adv + 3 ceil(nb /
+    chains) + 1 <= 141; FP64: 98, 32 and 99; adv >= 4; 1..4 chains; nibble
+    0..100; 4 or 7 AED waves, 8 or 16 chase waves), at each edge, and a
+    rejected call keeps the current values."""
+    caps = {1: (140, 44, 141), 0: (98, 32, 99)}   # prec -> (nsmall/nw cap, nb cap, window cap)
+    for prec, (ns, nbmax, wmax) in caps.items():
+        v = (ctypes.c_int * 8)()
+        assert lib.sylv_schur_tune_get(prec, v) == 0
+        before = list(v)
+        # (nsmall, nw, nb, adv, nibble, aed_waves, chase_waves, chains)
+        base = [64, 48, 8, 16, 50, 7, 8, 2]
+        ok = [
+            dict(nsmall=ns), dict(nw=ns), dict(nb=nbmax, chains=4, adv=wmax - 3 * (nbmax // 4) - 1),
+            dict(nb=nbmax, chains=2, adv=wmax - 3 * ((nbmax + 1) // 2) - 1), dict(adv=4), dict(aedw=4),
+            dict(chasew=16), dict(chains=1), dict(nibble=0), dict(nibble=100),
+        ]
+        bad = [
+            dict(nsmall=ns + 1), dict(nw=ns + 1), dict(nb=nbmax + 1, chains=4, adv=8),
+            dict(nb=nbmax, chains=2, adv=wmax - 3 * ((nbmax + 1) // 2)), dict(adv=3), dict(chains=5),
+            dict(aedw=5), dict(chasew=12), dict(nibble=101),
+        ]
+        keys = ["nsmall", "nw", "nb", "adv", "nibble", "aedw", "chasew", "chains"]
+        for case in ok:
+            args = [case.get(k, base[i]) for i, k in enumerate(keys)]
+            assert lib.sylv_schur_tune(prec, *args) == 0, (prec, case)
+            assert lib.sylv_schur_tune_get(prec, v) == 0 and list(v) == args, (prec, case)
+        for case in bad:
+            args = [case.get(k, base[i]) for i, k in enumerate(keys)]
+            assert lib.sylv_schur_tune(prec, *[base[i] for i in range(8)]) == 0
+            assert lib.sylv_schur_tune(prec, *args) == -2, (prec, case)
+            assert lib.sylv_schur_tune_get(prec, v) == 0 and list(v) == base, (prec, case)
+        # zeros keep the current values; a bad precision is refused
+        assert lib.sylv_schur_tune(prec, 0, 0, 0, 0, -1, 0, 0, 0) == 0
+        assert lib.sylv_schur_tune_get(prec, v) == 0 and list(v) == base
+        assert lib.sylv_schur_tune(2, *base) == -1
+        assert lib.sylv_schur_tune(prec, *before) == 0
+        assert lib.sylv_schur_tune_get(prec, v) == 0 and list(v) == before
