@@ -155,3 +155,31 @@ def test_schur_tune_bounds_as_documented(lib):
         assert lib.sylv_schur_tune(2, *base) == -1
         assert lib.sylv_schur_tune(prec, *before) == 0
         assert lib.sylv_schur_tune_get(prec, v) == 0 and list(v) == before
+
+
+def test_batched_workspace_size(lib):
+    """sylv_batched_workspace_size (host only): 0 for invalid arguments; a
+    batch of Lyapunov equations of order <= 256 needs at least the per-equation
+    buffers the batched path carves (one binary64 and six binary32 n x n
+    arrays, 32 n^2 bytes); a Sylvester equation or an order above 256 goes to
+    the single-equation path, 8 pooled slices of its workspace; adding
+    equations never shrinks it."""
+    lib.sylv_batched_workspace_size.restype = ctypes.c_size_t
+    lib.sylv_workspace_size.restype = ctypes.c_size_t
+    arr = lambda v: (ctypes.c_int * len(v))(*v)
+
+    def size(kinds, ms, ns):
+        return lib.sylv_batched_workspace_size(len(kinds), arr(kinds), arr(ms), arr(ns), None)
+
+    assert lib.sylv_batched_workspace_size(-1, None, None, None, None) == 0
+    assert lib.sylv_batched_workspace_size(2, None, arr([8, 8]), arr([8, 8]), None) == 0
+    ns = [16, 40, 100, 256, 17, 200]
+    s = size([1] * len(ns), ns, ns)
+    assert s >= 32 * sum(n * n for n in ns)
+    grow = [size([1] * k, ns[:k], ns[:k]) for k in range(1, len(ns) + 1)]
+    assert all(b >= a for a, b in zip(grow, grow[1:]))
+    # outside the batched kernels: one Sylvester equation, one order-300 Lyapunov
+    big = lib.sylv_workspace_size(300, 300, 1, None)
+    assert size([1], [300], [300]) >= 8 * big
+    sylv = lib.sylv_workspace_size(120, 90, 0, None)
+    assert size([0], [120], [90]) >= 8 * sylv
